@@ -1,0 +1,251 @@
+/*
+ * kp.h -- C ABI of the MI355X (gfx950) Kronecker sparse-multiply library.
+ *
+ * Multiplies sparse multivariate Laurent polynomials and Poisson series the
+ * way Biscani (ISSAC 2010) describes: generalised Kronecker substitution
+ * turns every multi-index into one integer code (Section 2, Tables 1-2,
+ * c(e) = c.e - chi), the schoolbook method forms every term-by-term product
+ * (Section 3), and the products are accumulated by code either in a dense
+ * code-indexed array (Section 3.1, "moderately sparse") or in a hash table
+ * keyed by code (Section 3.2, "highly sparse").  Poisson series split each
+ * trigonometric product into cos/sin of the sum and of the difference of the
+ * arguments (Section 2, eq. werner, with the factor 1/2 the printed formulas
+ * leave out).
+ *
+ * Conventions common to every entry point
+ *  - All functions are extern "C", never throw, and return a kp_status.
+ *  - Pointers documented as "device" point to HIP device memory owned by the
+ *    caller (for example torch tensors); "host" pointers are ordinary memory.
+ *    The library never allocates or frees caller-visible device memory: the
+ *    only device allocation it makes is a 256-byte status block per context.
+ *  - Every launch is ordered on the given hipStream_t (0 = null stream).
+ *  - Without KP_FLAG_ASYNC a call synchronises its stream once and reports
+ *    device-detected errors (range, capacity) in its return value.  With it,
+ *    the call returns after queuing; device errors are latched in the
+ *    context's status block (read by kp_ctx_check) and, for multiplies, the
+ *    device count *out_n is set to -(status) instead of the term count.
+ *  - Host-detectable errors (bad arguments, layout overflow, workspace too
+ *    small) return before anything is queued.
+ *  - Exponent arrays are row-major int32 [n][nvars].
+ */
+#ifndef KP_H
+#define KP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KP_MAX_VARS 16
+
+typedef enum kp_status {
+  KP_OK = 0,
+  KP_E_ARG = 1,           /* invalid argument (null pointer, bad size, bad enum)      */
+  KP_E_RANGE = 2,         /* an exponent or multiplier lies outside the layout's box   */
+  KP_E_CODE_OVERFLOW = 3, /* the product box needs 2^62 codes or more (Section 2:
+                             a code is unique only if the multi-index is representable) */
+  KP_E_NONCANONICAL = 4,  /* Poisson input whose first nonzero multiplier is negative,
+                             or a sine with the zero multiplier vector                  */
+  KP_E_CAPACITY = 5,      /* out_cap smaller than the number of result terms, or a
+                             forced hash capacity too small for the result              */
+  KP_E_WORKSPACE = 6,     /* workspace smaller than kp_mul_bound asked for             */
+  KP_E_DEVICE = 7,        /* the HIP runtime reported an error                         */
+  KP_E_DTYPE = 8,         /* coefficient type not supported by this operation          */
+  KP_E_MODE = 9           /* KP_DENSE requested for a box too large for dense mode     */
+} kp_status;
+
+typedef enum kp_dtype { KP_I64 = 0, KP_F64 = 1 } kp_dtype;
+
+/* Accumulator choice (Section 3: dense array for moderately sparse products,
+   hash table for highly sparse ones; the paper leaves the criterion to "an
+   analysis of the densities").  KP_AUTO applies the context's rule. */
+typedef enum kp_mode { KP_AUTO = 0, KP_DENSE = 1, KP_HASH = 2 } kp_mode;
+
+enum { KP_FLAG_ASYNC = 1 };
+
+/*
+ * kp_layout: the coding vectors of one product (Section 2, Table 2).
+ *
+ * Polynomial (Laurent) variables x_0..x_{nx-1}: each factor term's exponent
+ * e_k must lie in its factor's box [amin_k, amax_k] (factor A) or
+ * [bmin_k, bmax_k] (factor B).  The product box is [amin_k+bmin_k,
+ * amax_k+bmax_k] with width xw_k; x_0 is the least significant digit:
+ * xc_0 = 1, xc_k = xc_{k-1} * xw_{k-1}, Wx = prod xw_k.  A factor term is
+ * coded relative to its own factor's minimum, kx = sum_k xc_k (e_k - min_k),
+ * so the code of a product term is simply kx_a + kx_b (that is, c.e - chi
+ * with chi = c . e_min of the product box).
+ *
+ * Trigonometric multipliers y_0..y_{ny-1} (Poisson series only): factor
+ * half-widths ha_k = max |ja_k|, hb_k = max |jb_k|; the product's balanced
+ * box has yh_k = ha_k + hb_k and width 2*yh_k + 1, with y_0 the MOST
+ * significant digit (yc_{ny-1} = 1).  ky = sum_k yc_k j_k is signed; adding
+ * and subtracting codes adds and subtracts multiplier vectors (the extension
+ * of the coding vector Section 2 calls for), and sign(ky) is the sign of the
+ * first nonzero multiplier, so the canonical form is |ky| with a sign flip
+ * of sines.  Hy = (prod(2 yh_k + 1) - 1) / 2 is the largest |ky|.
+ *
+ * nkeys: size of the product's key space.  Laurent: Wx.  Poisson:
+ * 2 * Wx * (Hy + 1), a key being 2 * (kx + Wx * |ky|) + is_sin.
+ */
+typedef struct kp_layout {
+  int32_t nx, ny;
+  int32_t amin[KP_MAX_VARS], amax[KP_MAX_VARS];
+  int32_t bmin[KP_MAX_VARS], bmax[KP_MAX_VARS];
+  int32_t ha[KP_MAX_VARS], hb[KP_MAX_VARS];
+  int64_t xmin[KP_MAX_VARS]; /* product box minimum amin_k + bmin_k             */
+  int64_t xw[KP_MAX_VARS];   /* product widths                                  */
+  int64_t xc[KP_MAX_VARS];   /* strides, x_0 least significant                  */
+  int64_t Wx;                /* prod xw_k                                       */
+  int64_t yh[KP_MAX_VARS];   /* balanced half-widths ha_k + hb_k                */
+  int64_t yc[KP_MAX_VARS];   /* strides, y_0 most significant                   */
+  int64_t Hy;                /* largest |ky|                                    */
+  int64_t nkeys;             /* key-space size, < 2^62                          */
+} kp_layout;
+
+/* Tuning knobs (the paper leaves block size, table size and the density
+   criterion unspecified).  None of them changes a result. */
+typedef struct kp_tune {
+  int32_t window;           /* dense: output codes per workgroup window (<= 20480)   */
+  int32_t block;            /* dense: threads per workgroup (256, 512 or 1024)       */
+  int32_t tasks_per_cu;     /* dense: target work items per compute unit             */
+  double hash_load;         /* hash: target load factor (0.05 .. 0.9)                */
+  int64_t hash_capacity;    /* hash: forced slot count (0 = from the bound)          */
+  int64_t dense_max_keys;   /* auto mode: dense only if nkeys <= this                */
+  double dense_keys_per_pair; /* auto mode: dense only if nkeys <= this * na * nb    */
+  int32_t hash_rows;        /* hash: factor-A rows per thread                        */
+} kp_tune;
+
+typedef struct kp_ctx kp_ctx;
+
+/* Context: device id, tuning, last error text, a 256-byte device status
+   block.  One context per host thread; not thread-safe.  device < 0 makes a
+   host-only context (no device touched) that serves kp_mul_bound and the
+   tuning calls; the launching entry points reject it with KP_E_ARG. */
+kp_status kp_ctx_create(int device, kp_ctx** out);
+kp_status kp_ctx_destroy(kp_ctx* ctx);
+kp_status kp_ctx_get_tune(const kp_ctx* ctx, kp_tune* out);
+kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* tune);
+/* Synchronise `stream`, return and clear the latched device status. */
+kp_status kp_ctx_check(kp_ctx* ctx, hipStream_t stream);
+const char* kp_status_str(kp_status s);
+const char* kp_last_error(const kp_ctx* ctx);
+
+/* Instrumentation.  While enabled, every multiply records a pair of HIP
+   events on its stream around its accumulation kernel (the dense window
+   kernel or the hash insert kernel).  kp_ctx_timing_read waits for those
+   events, returns the summed kernel time in milliseconds and the number of
+   timed launches, and clears the record.  Disabled by default. */
+kp_status kp_ctx_timing(kp_ctx* ctx, int enable);
+kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches);
+
+/*
+ * Per-variable minimum and maximum of an int32 [n][nvars] device array, into
+ * the device array out[2*nvars] = {min_0..min_{nvars-1}, max_0..max_{nvars-1}}.
+ * With n == 0 the result is min = 0, max = -1 for every variable (an empty
+ * box, which kp_layout_product turns into an empty product).  Used to
+ * derive the factor boxes of a layout (Section 2, e_min / e_max).
+ */
+kp_status kp_minmax(kp_ctx* ctx, int64_t n, int32_t nvars, const int32_t* vals, int32_t* out,
+                    unsigned flags, hipStream_t stream);
+
+/*
+ * Host only.  Builds the product layout from the factors' boxes (Section 2,
+ * the definitions of w_k, c and chi).  amin..bmax: host int32[nx];
+ * ha, hb: host int32[ny] (maximum |multiplier| per trig variable; may be null
+ * when ny == 0).  An empty factor is passed as min > max and makes the
+ * product empty (nkeys = 0).  Returns KP_E_CODE_OVERFLOW when the key space
+ * reaches 2^62.
+ */
+kp_status kp_layout_product(int32_t nx, int32_t ny, const int32_t* amin, const int32_t* amax,
+                            const int32_t* bmin, const int32_t* bmax, const int32_t* ha,
+                            const int32_t* hb, kp_layout* out);
+
+/*
+ * Kronecker encode of one factor (Section 2, c(e) = c.e - chi; which = 0 for
+ * factor A, 1 for factor B).  Device in: x_exps int32[n][nx]; for Poisson
+ * (ny > 0) also y_mult int32[n][ny] and is_sin uint8[n] (may be null when
+ * ny == 0).  Device out: xcodes int64[n]; for Poisson ycodes int64[n]
+ * (signed balanced code).  A term outside the factor box latches KP_E_RANGE;
+ * a non-canonical Poisson term latches KP_E_NONCANONICAL.
+ */
+kp_status kp_encode(kp_ctx* ctx, const kp_layout* layout, int which, int64_t n,
+                    const int32_t* x_exps, const int32_t* y_mult, const uint8_t* is_sin,
+                    int64_t* xcodes, int64_t* ycodes, unsigned flags, hipStream_t stream);
+
+/*
+ * Host only.  Sizes the caller must provide for a multiply: the resolved
+ * accumulator mode, an upper bound on the number of result terms
+ * (min(na*nb*(poisson ? 2 : 1), nkeys)) and the workspace bytes.
+ * KP_E_MODE if KP_DENSE is asked for a key space too large for dense mode;
+ * KP_E_DTYPE for an integer Poisson product.
+ */
+kp_status kp_mul_bound(kp_ctx* ctx, const kp_layout* layout, int poisson, kp_dtype dtype,
+                       kp_mode mode, int64_t na, int64_t nb, kp_mode* resolved,
+                       int64_t* max_out_terms, size_t* workspace_bytes);
+
+/*
+ * Product of two Laurent polynomials given as Kronecker-coded sparse vectors
+ * (Section 3: the univariate schoolbook product of the coded factors).
+ * Device in: a_codes int64[na], a_coef (int64 or double)[na], same for B;
+ * unsorted input and repeated codes are accepted (the product is bilinear).
+ * Device out: out_codes int64[out_cap] (product codes in [0, nkeys)),
+ * out_coef[out_cap], out_n int64[1] = number of terms written.  Terms whose
+ * coefficient is exactly zero are dropped.  Dense mode writes ascending
+ * codes; hash mode's order is unspecified.  int64 arithmetic wraps modulo
+ * 2^64.  workspace: device, >= the kp_mul_bound figure, caller-owned,
+ * contents undefined afterwards.
+ */
+kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                         unsigned flags, const int64_t* a_codes, const void* a_coef, int64_t na,
+                         const int64_t* b_codes, const void* b_coef, int64_t nb,
+                         int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Product of two Poisson series (Section 1, eq. ps_def) in canonical form.
+ * Device in per factor: x codes int64[n], signed trig codes int64[n],
+ * is_sin uint8[n], coefficients double[n].  Every pair contributes
+ * 1/2 * ca * cb to cos/sin of the difference and of the sum of its arguments
+ * (eq. werner with the factor 1/2), folded to canonical form; a sine of the
+ * zero vector is dropped.  Device out: keys int64 (2*(kx + Wx*|ky|) + is_sin),
+ * coefficients double, out_n as for kp_mul_laurent.  fp64 only.
+ */
+kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
+                         const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
+                         const double* a_coef, int64_t na, const int64_t* b_x,
+                         const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                         int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
+                         int64_t* out_n, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream);
+
+/*
+ * Decode product codes back to multi-indices (the inverse of the code map of
+ * Section 2).  Device in: codes int64[n] (Laurent product codes, or Poisson
+ * keys when poisson != 0).  Device out: x_exps int32[n][nx]; for Poisson
+ * y_mult int32[n][ny] (canonical) and is_sin uint8[n].  A code outside
+ * [0, nkeys) latches KP_E_RANGE.
+ */
+kp_status kp_decode(kp_ctx* ctx, const kp_layout* layout, int poisson, int64_t n,
+                    const int64_t* codes, int32_t* x_exps, int32_t* y_mult, uint8_t* is_sin,
+                    unsigned flags, hipStream_t stream);
+
+/*
+ * Host-memory twins of kp_encode / kp_decode, running the same per-term code
+ * map on the CPU (for callers without a device and for checking tables).
+ * Errors are returned directly.
+ */
+kp_status kp_encode_host(const kp_layout* layout, int which, int64_t n, const int32_t* x_exps,
+                         const int32_t* y_mult, const uint8_t* is_sin, int64_t* xcodes,
+                         int64_t* ycodes);
+kp_status kp_decode_host(const kp_layout* layout, int poisson, int64_t n, const int64_t* codes,
+                         int32_t* x_exps, int32_t* y_mult, uint8_t* is_sin);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KP_H */

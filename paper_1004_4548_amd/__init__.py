@@ -1,0 +1,462 @@
+"""MI355X (gfx950) multiplication of sparse Laurent polynomials and Poisson series.
+
+Thin Python binding over the C ABI in ``include/kp.h`` (``libkp.so``, built
+in-tree by ``build.py``).  This module only marshals arguments: torch tensors
+provide device memory and the current HIP stream, and every step of a product
+-- min/max of the exponents, Kronecker encoding, sorting, the multiply with
+dense or hash accumulation, compaction and decoding -- runs in the library's
+HIP kernels.  There is no CPU fallback: without the built library every call
+raises.
+
+Method: Biscani, "Multiplication of sparse Laurent polynomials and Poisson
+series on modern hardware architectures" (ISSAC 2010) -- Kronecker
+substitution (Section 2), schoolbook products accumulated by code in a dense
+array or a hash table (Section 3), Poisson split by eq. werner with the
+factor 1/2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkp.so")
+MAX_VARS = 16
+
+KP_OK, KP_E_ARG, KP_E_RANGE, KP_E_CODE_OVERFLOW, KP_E_NONCANONICAL = 0, 1, 2, 3, 4
+KP_E_CAPACITY, KP_E_WORKSPACE, KP_E_DEVICE, KP_E_DTYPE, KP_E_MODE = 5, 6, 7, 8, 9
+KP_I64, KP_F64 = 0, 1
+KP_AUTO, KP_DENSE, KP_HASH = 0, 1, 2
+KP_FLAG_ASYNC = 1
+MODES = {"auto": KP_AUTO, "dense": KP_DENSE, "hash": KP_HASH}
+MODE_NAMES = {v: k for k, v in MODES.items()}
+
+EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tune",
+            "kp_ctx_check", "kp_status_str", "kp_last_error", "kp_ctx_timing",
+            "kp_ctx_timing_read", "kp_minmax", "kp_layout_product",
+            "kp_encode", "kp_mul_bound", "kp_mul_laurent", "kp_mul_poisson", "kp_decode",
+            "kp_encode_host", "kp_decode_host"]
+
+
+class KPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"kp status {status}: {msg}")
+        self.status = status
+
+
+class Layout(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("amin", C.c_int32 * MAX_VARS), ("amax", C.c_int32 * MAX_VARS),
+                ("bmin", C.c_int32 * MAX_VARS), ("bmax", C.c_int32 * MAX_VARS),
+                ("ha", C.c_int32 * MAX_VARS), ("hb", C.c_int32 * MAX_VARS),
+                ("xmin", C.c_int64 * MAX_VARS), ("xw", C.c_int64 * MAX_VARS),
+                ("xc", C.c_int64 * MAX_VARS), ("Wx", C.c_int64),
+                ("yh", C.c_int64 * MAX_VARS), ("yc", C.c_int64 * MAX_VARS),
+                ("Hy", C.c_int64), ("nkeys", C.c_int64)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("window", C.c_int32), ("block", C.c_int32), ("tasks_per_cu", C.c_int32),
+                ("hash_load", C.c_double), ("hash_capacity", C.c_int64),
+                ("dense_max_keys", C.c_int64), ("dense_keys_per_pair", C.c_double),
+                ("hash_rows", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libkp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1004_4548_amd/build.py "
+                           "(or __graft_entry__.build()) first")
+    L = C.CDLL(LIB_PATH)
+    p, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint, C.c_size_t
+    sig = {
+        "kp_ctx_create": (i32, [i32, C.POINTER(p)]),
+        "kp_ctx_destroy": (i32, [p]),
+        "kp_ctx_get_tune": (i32, [p, C.POINTER(Tune)]),
+        "kp_ctx_set_tune": (i32, [p, C.POINTER(Tune)]),
+        "kp_ctx_check": (i32, [p, p]),
+        "kp_status_str": (C.c_char_p, [i32]),
+        "kp_last_error": (C.c_char_p, [p]),
+        "kp_ctx_timing": (i32, [p, i32]),
+        "kp_ctx_timing_read": (i32, [p, C.POINTER(C.c_double), C.POINTER(i64)]),
+        "kp_minmax": (i32, [p, i64, i32, p, p, u32, p]),
+        "kp_layout_product": (i32, [i32, i32, p, p, p, p, p, p, C.POINTER(Layout)]),
+        "kp_encode": (i32, [p, C.POINTER(Layout), i32, i64, p, p, p, p, p, u32, p]),
+        "kp_mul_bound": (i32, [p, C.POINTER(Layout), i32, i32, i32, i64, i64, C.POINTER(i32),
+                               C.POINTER(i64), C.POINTER(sz)]),
+        "kp_mul_laurent": (i32, [p, C.POINTER(Layout), i32, i32, u32, p, p, i64, p, p, i64, p,
+                                 p, i64, p, p, sz, p]),
+        "kp_mul_poisson": (i32, [p, C.POINTER(Layout), i32, u32, p, p, p, p, i64, p, p, p, p,
+                                 i64, p, p, i64, p, p, sz, p]),
+        "kp_decode": (i32, [p, C.POINTER(Layout), i32, i64, p, p, p, p, u32, p]),
+        "kp_encode_host": (i32, [C.POINTER(Layout), i32, i64, p, p, p, p, p]),
+        "kp_decode_host": (i32, [C.POINTER(Layout), i32, i64, p, p, p, p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_str(s):
+    return lib().kp_status_str(s).decode()
+
+
+# ------------------------------------------------------------------ host-only
+def layout_product(nx, ny, amin, amax, bmin, bmax, ha=None, hb=None) -> Layout:
+    """kp_layout_product: the product's coding vectors from the factor boxes."""
+    arr = C.c_int32 * MAX_VARS
+    def a(v, n):
+        v = [] if v is None else [int(x) for x in v]
+        assert len(v) == n
+        return arr(*v)
+    out = Layout()
+    st = lib().kp_layout_product(nx, ny, a(amin, nx), a(amax, nx), a(bmin, nx), a(bmax, nx),
+                                 a(ha, ny), a(hb, ny), C.byref(out))
+    if st != KP_OK:
+        raise KPError(st, status_str(st))
+    return out
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def encode_host(layout: Layout, which, x, y=None, t=None):
+    """kp_encode_host on numpy arrays (same per-term map as the kernel)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.int32).reshape(-1, max(layout.nx, 1))
+    n = x.shape[0]
+    kx = np.zeros(n, dtype=np.int64)
+    ky = np.zeros(n, dtype=np.int64) if layout.ny else None
+    if layout.ny:
+        y = np.ascontiguousarray(y, dtype=np.int32).reshape(n, layout.ny)
+        t = np.ascontiguousarray(t, dtype=np.uint8).reshape(n)
+    st = lib().kp_encode_host(C.byref(layout), which, n, _np_ptr(x), _np_ptr(y), _np_ptr(t),
+                              _np_ptr(kx), _np_ptr(ky))
+    if st != KP_OK:
+        raise KPError(st, status_str(st))
+    return kx, ky
+
+
+def decode_host(layout: Layout, codes, poisson=False):
+    import numpy as np
+    codes = np.ascontiguousarray(codes, dtype=np.int64).reshape(-1)
+    n = codes.shape[0]
+    x = np.zeros((n, layout.nx), dtype=np.int32)
+    y = np.zeros((n, layout.ny), dtype=np.int32) if poisson else None
+    t = np.zeros(n, dtype=np.uint8) if poisson else None
+    st = lib().kp_decode_host(C.byref(layout), 1 if poisson else 0, n, _np_ptr(codes),
+                              _np_ptr(x), _np_ptr(y), _np_ptr(t))
+    if st != KP_OK:
+        raise KPError(st, status_str(st))
+    return (x, y, t) if poisson else x
+
+
+# ------------------------------------------------------------------ device
+class Context:
+    """A kp_ctx on one device (tuning knobs, device status block)."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = C.c_void_p()
+        st = lib().kp_ctx_create(device, C.byref(h))
+        if st != KP_OK:
+            raise KPError(st, "kp_ctx_create failed")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.kp_ctx_destroy(h)
+            self.h = None
+
+    def check(self, st):
+        if st != KP_OK:
+            raise KPError(st, f"{status_str(st)}: {lib().kp_last_error(self.h).decode()}")
+
+    @property
+    def tune(self) -> Tune:
+        t = Tune()
+        self.check(lib().kp_ctx_get_tune(self.h, C.byref(t)))
+        return t
+
+    def set_tune(self, **kw):
+        t = self.tune
+        for k, v in kw.items():
+            setattr(t, k, v)
+        self.check(lib().kp_ctx_set_tune(self.h, C.byref(t)))
+
+    def timing(self, enable=True):
+        """Record HIP events around every accumulation kernel launch."""
+        self.check(lib().kp_ctx_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        """(summed accumulation-kernel milliseconds, launches) since the last read."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self.check(lib().kp_ctx_timing_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def sync_check(self, stream=None):
+        self.check(lib().kp_ctx_check(self.h, _stream(stream)))
+
+
+_contexts = {}
+
+
+def context(device=None) -> Context:
+    import torch
+    d = torch.cuda.current_device() if device is None else device
+    if d not in _contexts:
+        _contexts[d] = Context(d)
+    return _contexts[d]
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_check(t, dtype, name):
+    import torch
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def minmax(vals, ctx=None, flags=0):
+    """kp_minmax: per-column (min, max) of an int32 [n, nv] device tensor."""
+    import torch
+    ctx = ctx or context()
+    _dev_check(vals, torch.int32, "vals")
+    n, nv = vals.shape
+    out = torch.empty(2 * nv, dtype=torch.int32, device=vals.device)
+    ctx.check(lib().kp_minmax(ctx.h, n, nv, _ptr(vals), _ptr(out), flags, _stream()))
+    return out
+
+
+def encode(layout, which, x, y=None, t=None, ctx=None, flags=0):
+    """kp_encode: Kronecker codes of one factor (device tensors)."""
+    import torch
+    ctx = ctx or context()
+    _dev_check(x, torch.int32, "x")
+    n = x.shape[0]
+    kx = torch.empty(n, dtype=torch.int64, device=x.device)
+    ky = None
+    if layout.ny:
+        _dev_check(y, torch.int32, "y")
+        _dev_check(t, torch.uint8, "is_sin")
+        ky = torch.empty(n, dtype=torch.int64, device=x.device)
+    ctx.check(lib().kp_encode(ctx.h, C.byref(layout), which, n, _ptr(x), _ptr(y), _ptr(t),
+                              _ptr(kx), _ptr(ky), flags, _stream()))
+    return kx, ky
+
+
+def decode(layout, codes, poisson=False, ctx=None, flags=0):
+    """kp_decode: product codes (or Poisson keys) back to exponents."""
+    import torch
+    ctx = ctx or context()
+    _dev_check(codes, torch.int64, "codes")
+    n = codes.shape[0]
+    x = torch.empty((n, layout.nx), dtype=torch.int32, device=codes.device)
+    y = t = None
+    if poisson:
+        y = torch.empty((n, layout.ny), dtype=torch.int32, device=codes.device)
+        t = torch.empty(n, dtype=torch.uint8, device=codes.device)
+    ctx.check(lib().kp_decode(ctx.h, C.byref(layout), 1 if poisson else 0, n, _ptr(codes),
+                              _ptr(x), _ptr(y), _ptr(t), flags, _stream()))
+    return (x, y, t) if poisson else x
+
+
+def mul_bound(layout, poisson, dtype, mode, na, nb, ctx=None):
+    """kp_mul_bound -> (resolved mode name, max result terms, workspace bytes)."""
+    ctx = ctx or context()
+    m = C.c_int32()
+    mo = C.c_int64()
+    ws = C.c_size_t()
+    ctx.check(lib().kp_mul_bound(ctx.h, C.byref(layout), 1 if poisson else 0, dtype,
+                                 MODES[mode] if isinstance(mode, str) else mode, na, nb,
+                                 C.byref(m), C.byref(mo), C.byref(ws)))
+    return MODE_NAMES[m.value], mo.value, ws.value
+
+
+class Workspace:
+    """Grow-only device scratch for repeated multiplies (torch-owned)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def _dt(t):
+    import torch
+    if t.dtype == torch.int64:
+        return KP_I64
+    if t.dtype == torch.float64:
+        return KP_F64
+    raise ValueError(f"coefficients must be int64 or float64, got {t.dtype}")
+
+
+def mul_laurent_codes(layout, a_codes, a_coef, b_codes, b_coef, mode="auto", ctx=None,
+                      workspace=None, out=None, flags=0):
+    """kp_mul_laurent on coded factors.
+
+    Returns (codes, coef, count_tensor).  Without KP_FLAG_ASYNC the outputs
+    are trimmed to the result size (one host read of the count).
+    """
+    import torch
+    ctx = ctx or context()
+    dev = a_codes.device
+    dt = _dt(a_coef)
+    for t, nm in ((a_codes, "a_codes"), (b_codes, "b_codes")):
+        _dev_check(t, torch.int64, nm)
+    _dev_check(a_coef, a_coef.dtype, "a_coef")
+    _dev_check(b_coef, a_coef.dtype, "b_coef")
+    na, nb = a_codes.shape[0], b_codes.shape[0]
+    _, max_out, ws = mul_bound(layout, False, dt, mode, na, nb, ctx)
+    if out is None:
+        oc = torch.empty(max(max_out, 1), dtype=torch.int64, device=dev)
+        ov = torch.empty(max(max_out, 1), dtype=a_coef.dtype, device=dev)
+        on = torch.empty(1, dtype=torch.int64, device=dev)
+    else:
+        oc, ov, on = out
+    wbuf = (workspace or Workspace()).get(ws, dev)
+    st = lib().kp_mul_laurent(ctx.h, C.byref(layout), dt, MODES[mode] if isinstance(mode, str)
+                              else mode, flags, _ptr(a_codes), _ptr(a_coef), na, _ptr(b_codes),
+                              _ptr(b_coef), nb, _ptr(oc), _ptr(ov), oc.shape[0], _ptr(on),
+                              _ptr(wbuf), wbuf.numel(), _stream())
+    ctx.check(st)
+    if flags & KP_FLAG_ASYNC:
+        return oc, ov, on
+    n = int(on.item())
+    return oc[:n], ov[:n], on
+
+
+def mul_poisson_codes(layout, a, b, mode="auto", ctx=None, workspace=None, out=None, flags=0):
+    """kp_mul_poisson on coded series a = (x_codes, y_codes, is_sin, coef)."""
+    import torch
+    ctx = ctx or context()
+    ax, ay, at, ac = a
+    bx, by, bt, bc = b
+    dev = ax.device
+    for t, nm in ((ax, "a_x"), (ay, "a_y"), (bx, "b_x"), (by, "b_y")):
+        _dev_check(t, torch.int64, nm)
+    _dev_check(at, torch.uint8, "a_sin")
+    _dev_check(bt, torch.uint8, "b_sin")
+    _dev_check(ac, torch.float64, "a_coef")
+    _dev_check(bc, torch.float64, "b_coef")
+    na, nb = ac.shape[0], bc.shape[0]
+    _, max_out, ws = mul_bound(layout, True, KP_F64, mode, na, nb, ctx)
+    if out is None:
+        ok = torch.empty(max(max_out, 1), dtype=torch.int64, device=dev)
+        ov = torch.empty(max(max_out, 1), dtype=torch.float64, device=dev)
+        on = torch.empty(1, dtype=torch.int64, device=dev)
+    else:
+        ok, ov, on = out
+    wbuf = (workspace or Workspace()).get(ws, dev)
+    st = lib().kp_mul_poisson(ctx.h, C.byref(layout), MODES[mode] if isinstance(mode, str)
+                              else mode, flags, _ptr(ax), _ptr(ay), _ptr(at), _ptr(ac), na,
+                              _ptr(bx), _ptr(by), _ptr(bt), _ptr(bc), nb, _ptr(ok), _ptr(ov),
+                              ok.shape[0], _ptr(on), _ptr(wbuf), wbuf.numel(), _stream())
+    ctx.check(st)
+    if flags & KP_FLAG_ASYNC:
+        return ok, ov, on
+    n = int(on.item())
+    return ok[:n], ov[:n], on
+
+
+# ------------------------------------------------------------------ high level
+@dataclass
+class Poly:
+    """Sparse Laurent polynomial: exps int32 [n, nv], coef int64 or float64 [n]."""
+    exps: "object"
+    coef: "object"
+
+    @property
+    def nv(self):
+        return self.exps.shape[1]
+
+
+@dataclass
+class PoissonSeries:
+    """Sparse Poisson series in canonical form: x int32 [n, nx], y int32 [n, ny],
+    is_sin uint8 [n], coef float64 [n]."""
+    x: "object"
+    y: "object"
+    is_sin: "object"
+    coef: "object"
+
+
+def _boxes(vals, ctx):
+    mm = minmax(vals, ctx).cpu().tolist()
+    nv = vals.shape[1]
+    return mm[:nv], mm[nv:]
+
+
+def laurent_layout(a: Poly, b: Poly, ctx=None) -> Layout:
+    ctx = ctx or context()
+    nv = a.nv
+    amin, amax = _boxes(a.exps, ctx)
+    bmin, bmax = _boxes(b.exps, ctx)
+    return layout_product(nv, 0, amin, amax, bmin, bmax)
+
+
+def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
+    """A * B for device-resident Laurent polynomials; returns (Poly, Layout)."""
+    ctx = ctx or context()
+    if a.nv != b.nv:
+        raise ValueError("factors must have the same number of variables")
+    lay = laurent_layout(a, b, ctx)
+    ka, _ = encode(lay, 0, a.exps, ctx=ctx)
+    kb, _ = encode(lay, 1, b.exps, ctx=ctx)
+    codes, coef, _ = mul_laurent_codes(lay, ka, a.coef, kb, b.coef, mode, ctx, workspace)
+    return Poly(decode(lay, codes, ctx=ctx), coef), lay
+
+
+def poisson_layout(a: PoissonSeries, b: PoissonSeries, ctx=None) -> Layout:
+    ctx = ctx or context()
+    nx, ny = a.x.shape[1], a.y.shape[1]
+    amin, amax = _boxes(a.x, ctx)
+    bmin, bmax = _boxes(b.x, ctx)
+    ya, yb = _boxes(a.y, ctx), _boxes(b.y, ctx)
+    ha = [max(-lo, hi, 0) for lo, hi in zip(*ya)]
+    hb = [max(-lo, hi, 0) for lo, hi in zip(*yb)]
+    return layout_product(nx, ny, amin, amax, bmin, bmax, ha, hb)
+
+
+def mul_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, workspace=None):
+    """A * B for device-resident canonical Poisson series; returns (series, Layout)."""
+    ctx = ctx or context()
+    lay = poisson_layout(a, b, ctx)
+    kxa, kya = encode(lay, 0, a.x, a.y, a.is_sin, ctx=ctx)
+    kxb, kyb = encode(lay, 1, b.x, b.y, b.is_sin, ctx=ctx)
+    keys, coef, _ = mul_poisson_codes(lay, (kxa, kya, a.is_sin, a.coef),
+                                      (kxb, kyb, b.is_sin, b.coef), mode, ctx, workspace)
+    x, y, t = decode(lay, keys, poisson=True, ctx=ctx)
+    return PoissonSeries(x, y, t, coef), lay

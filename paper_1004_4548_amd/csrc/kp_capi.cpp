@@ -1,0 +1,665 @@
+// kp_capi.cpp -- the extern "C" boundary: argument checks, layout and
+// workspace planning, mode choice, and the launch sequences of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kp_internal.h"
+
+struct kp_ctx {
+  int device = 0;
+  int num_cu = 256;
+  kp_tune tune{};
+  kp::CtxStatus* status = nullptr;   // device
+  std::string err;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // pool
+  size_t events_used = 0;
+};
+
+namespace kp {
+
+namespace {
+
+constexpr int64_t CODE_LIMIT = (int64_t)1 << 62;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+kp_status fail(kp_ctx* ctx, kp_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+kp_status fail(kp_ctx* ctx, kp_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+kp_status hip_fail(kp_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, KP_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Saturating product of non-negative values.
+int64_t sat_mul(int64_t a, int64_t b) {
+  int64_t r;
+  if (__builtin_mul_overflow(a, b, &r)) return INT64_MAX;
+  return r;
+}
+
+uint32_t log2_ceil(uint64_t x) {
+  uint32_t l = 0;
+  while (l < 63 && (1ull << l) < x) ++l;
+  return l;
+}
+
+// Synchronise, read and clear the context's latched device status.
+kp_status sync_status(kp_ctx* ctx, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  uint32_t bits = 0;
+  e = hipMemcpy(&bits, &ctx->status->err, sizeof bits, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(status)");
+  if (bits) {
+    uint32_t zero = 0;
+    e = hipMemcpy(&ctx->status->err, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(status clear)");
+    kp_status st = (kp_status)first_error(bits);
+    return fail(ctx, st, "device reported %s (bits 0x%x)", kp_status_str(st), bits);
+  }
+  return KP_OK;
+}
+
+// Next event pair for timing the accumulation kernel (null when disabled).
+std::pair<hipEvent_t, hipEvent_t> timing_pair(kp_ctx* ctx) {
+  if (!ctx->timing) return {nullptr, nullptr};
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return {nullptr, nullptr};
+    ctx->events.emplace_back(a, b);
+  }
+  return ctx->events[ctx->events_used++];
+}
+
+kp_status finish(kp_ctx* ctx, unsigned flags, hipStream_t s, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
+  if (flags & KP_FLAG_ASYNC) return KP_OK;
+  return sync_status(ctx, s);
+}
+
+// ------------------------------------------------------------ planning
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    size_t o = off;
+    off = align_up(off + count * sizeof(T));
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+struct Plan {
+  kp_mode mode = KP_HASH;
+  int64_t max_out = 0;
+  size_t ws = 0;
+  // dense
+  DensePlan dp{};
+  // hash
+  int64_t cap_log2 = 6;
+};
+
+bool dense_feasible(const kp_ctx* ctx, const kp_layout* L, int64_t na, int64_t nb, int64_t* nwin,
+                    int64_t* ntiles) {
+  const int64_t S = ctx->tune.window;
+  *nwin = (L->nkeys + S - 1) / S;
+  *ntiles = (nb + 63) / 64;
+  if (L->nkeys > ctx->tune.dense_max_keys) return false;
+  if (sat_mul(*nwin, *ntiles) > ((int64_t)1 << 27)) return false;
+  (void)na;
+  return true;
+}
+
+template <bool CARVE>
+void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B,
+                 int64_t** a_tmpk, int32_t** a_tmpi, int64_t** b_tmpk, int32_t** b_tmpi) {
+  const int64_t nwin = p.dp.nwin, S = p.dp.S;
+  Meta* meta = c.take<Meta>(1);
+  int64_t* ak = c.take<int64_t>(na);
+  int64_t* apairs = c.take<int64_t>(2 * na + 8);    // the row loop's tail group reads up to 3 pairs past the end
+  int64_t* bk = c.take<int64_t>(nb);
+  int64_t* bc = c.take<int64_t>(nb);
+  *a_tmpk = na > SORT_CHUNK ? c.take<int64_t>(na) : nullptr;
+  *a_tmpi = na > SORT_CHUNK ? c.take<int32_t>(na) : nullptr;
+  *b_tmpk = nb > SORT_CHUNK ? c.take<int64_t>(nb) : nullptr;
+  *b_tmpi = nb > SORT_CHUNK ? c.take<int32_t>(nb) : nullptr;
+  int64_t* wt = c.take<int64_t>(nwin * p.dp.ntiles);
+  int64_t* task_off = c.take<int64_t>(nwin + 1);
+  int32_t* pending = c.take<int32_t>(nwin);
+  int64_t* wcount = c.take<int64_t>(nwin);
+  int64_t* woff = c.take<int64_t>(nwin);
+  int64_t* dense = c.take<int64_t>(nwin * S);
+  int64_t* stage_k = c.take<int64_t>(nwin * S);
+  int64_t* stage_c = c.take<int64_t>(nwin * S);
+  if (CARVE) {
+    B->meta = meta;
+    B->ak = ak;
+    B->apairs = apairs;
+    B->bk = bk;
+    B->bc = bc;
+    B->na = na;
+    B->nb = nb;
+    B->wt = wt;
+    B->task_off = task_off;
+    B->pending = pending;
+    B->wcount = wcount;
+    B->woff = woff;
+    B->dense = dense;
+    B->stage_k = stage_k;
+    B->stage_c = stage_c;
+  }
+}
+
+struct HashCarve {
+  Meta* meta;
+  uint64_t* table;
+  PoissonPrep pp;
+};
+
+void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, HashCarve* h) {
+  h->meta = c.take<Meta>(1);
+  h->table = c.take<uint64_t>((size_t)2 << p.cap_log2);
+  h->pp = PoissonPrep{};
+  if (poisson) {
+    h->pp.ap = c.take<int64_t>(na);
+    h->pp.akx = c.take<int64_t>(na);
+    h->pp.at = c.take<uint8_t>(na);
+    h->pp.bp = c.take<int64_t>(nb);
+    h->pp.bm = c.take<int64_t>(nb);
+    h->pp.bkx = c.take<int64_t>(nb);
+    h->pp.bt = c.take<uint8_t>(nb);
+  }
+}
+
+kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, kp_mode mode,
+                    int64_t na, int64_t nb, Plan* p) {
+  if (!L) return fail(ctx, KP_E_ARG, "null layout");
+  if (na < 0 || nb < 0) return fail(ctx, KP_E_ARG, "negative factor size");
+  if (dt != KP_I64 && dt != KP_F64) return fail(ctx, KP_E_ARG, "bad dtype %d", (int)dt);
+  if (poisson && dt != KP_F64)
+    return fail(ctx, KP_E_DTYPE, "Poisson products carry a factor 1/2 and need fp64 coefficients");
+  if (mode != KP_AUTO && mode != KP_DENSE && mode != KP_HASH)
+    return fail(ctx, KP_E_ARG, "bad mode %d", (int)mode);
+  if (L->nkeys < 0 || L->nkeys >= CODE_LIMIT) return fail(ctx, KP_E_CODE_OVERFLOW, "key space");
+  int64_t pairs = sat_mul(na, nb);
+  int64_t contrib = poisson ? sat_mul(pairs, 2) : pairs;
+  p->max_out = std::min(contrib, L->nkeys);
+  int64_t nwin = 0, ntiles = 0;
+  bool dense_ok = !poisson && dense_feasible(ctx, L, na, nb, &nwin, &ntiles);
+  kp_mode m = mode;
+  if (m == KP_AUTO) {
+    double budget = ctx->tune.dense_keys_per_pair * (double)pairs;
+    m = (dense_ok && (double)L->nkeys <= budget) ? KP_DENSE : KP_HASH;
+  }
+  if (m == KP_DENSE && !dense_ok)
+    return fail(ctx, KP_E_MODE, "dense mode needs a Laurent product with at most %lld codes",
+                (long long)ctx->tune.dense_max_keys);
+  p->mode = m;
+  Carver c;
+  if (m == KP_DENSE) {
+    p->dp.S = ctx->tune.window;
+    p->dp.nwin = nwin;
+    p->dp.ntiles = ntiles;
+    p->dp.block = ctx->tune.block;
+    p->dp.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
+    p->dp.max_tasks = p->dp.target_tasks + nwin;
+    int64_t *a1, *b1;
+    int32_t *a2, *b2;
+    carve_dense<false>(c, *p, na, nb, nullptr, &a1, &a2, &b1, &b2);
+  } else {
+    int64_t want;
+    if (ctx->tune.hash_capacity > 0) {
+      want = ctx->tune.hash_capacity;
+    } else {
+      double w = (double)std::max<int64_t>(p->max_out, 1) / ctx->tune.hash_load;
+      want = w > 4.0e18 ? INT64_MAX : (int64_t)w + 1;
+    }
+    p->cap_log2 = std::max<uint32_t>(6, log2_ceil((uint64_t)want));
+    if (p->cap_log2 > 40) return fail(ctx, KP_E_CAPACITY, "hash table would need 2^%lld slots",
+                                     (long long)p->cap_log2);
+    HashCarve h;
+    carve_hash(c, *p, poisson, na, nb, &h);
+  }
+  p->ws = c.off;
+  return KP_OK;
+}
+
+}  // namespace
+
+DevLayout make_dev_layout(const kp_layout& L, int which) {
+  DevLayout d{};
+  d.nx = L.nx;
+  d.ny = L.ny;
+  d.Wx = L.Wx;
+  d.Hy = L.Hy;
+  d.nkeys = L.nkeys;
+  for (int v = 0; v < L.nx; ++v) {
+    d.fmin[v] = which ? L.bmin[v] : L.amin[v];
+    d.fmax[v] = which ? L.bmax[v] : L.amax[v];
+    d.xc[v] = L.xc[v];
+    d.xmin[v] = L.xmin[v];
+    d.dx[v] = make_fastdiv((uint64_t)L.xw[v]);
+  }
+  for (int v = 0; v < L.ny; ++v) {
+    d.fh[v] = which ? L.hb[v] : L.ha[v];
+    d.yc[v] = L.yc[v];
+    d.yh[v] = L.yh[v];
+    d.dy[v] = make_fastdiv((uint64_t)(2 * L.yh[v] + 1));
+  }
+  d.dWx = make_fastdiv((uint64_t)std::max<int64_t>(L.Wx, 1));
+  return d;
+}
+
+}  // namespace kp
+
+using namespace kp;
+
+extern "C" {
+
+const char* kp_status_str(kp_status s) {
+  switch (s) {
+    case KP_OK: return "ok";
+    case KP_E_ARG: return "invalid argument";
+    case KP_E_RANGE: return "exponent outside the layout box";
+    case KP_E_CODE_OVERFLOW: return "product box exceeds the 62-bit code space";
+    case KP_E_NONCANONICAL: return "Poisson term not in canonical form";
+    case KP_E_CAPACITY: return "output or table capacity too small";
+    case KP_E_WORKSPACE: return "workspace too small";
+    case KP_E_DEVICE: return "HIP runtime error";
+    case KP_E_DTYPE: return "coefficient type not supported";
+    case KP_E_MODE: return "accumulator mode not possible for this layout";
+  }
+  return "unknown status";
+}
+
+const char* kp_last_error(const kp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+kp_status kp_ctx_create(int device, kp_ctx** out) {
+  if (!out) return KP_E_ARG;
+  *out = nullptr;
+  auto* ctx = new kp_ctx;
+  ctx->device = device;
+  ctx->tune.window = 16384;
+  ctx->tune.block = 1024;
+  ctx->tune.tasks_per_cu = 4;
+  ctx->tune.hash_load = 0.5;
+  ctx->tune.hash_capacity = 0;
+  ctx->tune.dense_max_keys = (int64_t)1 << 28;
+  ctx->tune.dense_keys_per_pair = 64.0;
+  ctx->tune.hash_rows = 64;
+  if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
+    *out = ctx;
+    return KP_OK;
+  }
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return KP_E_DEVICE;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    ctx->num_cu = cus;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->status), sizeof(CtxStatus));
+  if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(CtxStatus));
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    delete ctx;
+    return KP_E_DEVICE;
+  }
+  *out = ctx;
+  return KP_OK;
+}
+
+kp_status kp_ctx_timing(kp_ctx* ctx, int enable) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  ctx->timing = enable != 0;
+  return KP_OK;
+}
+
+kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return KP_E_ARG;
+  double tot = 0;
+  for (size_t i = 0; i < ctx->events_used; ++i) {
+    hipError_t e = hipEventSynchronize(ctx->events[i].second);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second);
+    if (e != hipSuccess) {
+      ctx->events_used = 0;
+      return hip_fail(ctx, e, "kp_ctx_timing_read");
+    }
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)ctx->events_used;
+  ctx->events_used = 0;
+  return KP_OK;
+}
+
+kp_status kp_ctx_destroy(kp_ctx* ctx) {
+  if (!ctx) return KP_E_ARG;
+  for (auto& pr : ctx->events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  if (ctx->status) (void)hipFree(ctx->status);
+  delete ctx;
+  return KP_OK;
+}
+
+kp_status kp_ctx_get_tune(const kp_ctx* ctx, kp_tune* out) {
+  if (!ctx || !out) return KP_E_ARG;
+  *out = ctx->tune;
+  return KP_OK;
+}
+
+kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
+  if (!ctx || !t) return KP_E_ARG;
+  if (t->block != 256 && t->block != 512 && t->block != 1024)
+    return fail(ctx, KP_E_ARG, "block must be 256, 512 or 1024");
+  if (t->window < t->block || t->window % t->block != 0 ||
+      (int64_t)t->window * 8 + 1024 > 160 * 1024)
+    return fail(ctx, KP_E_ARG, "window must be a multiple of block and fit 159 KB of LDS");
+  if (t->tasks_per_cu < 1) return fail(ctx, KP_E_ARG, "tasks_per_cu must be >= 1");
+  if (!(t->hash_load >= 0.05 && t->hash_load <= 0.9))
+    return fail(ctx, KP_E_ARG, "hash_load must lie in [0.05, 0.9]");
+  if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
+      t->hash_rows < 1)
+    return fail(ctx, KP_E_ARG, "negative tuning value");
+  ctx->tune = *t;
+  return KP_OK;
+}
+
+kp_status kp_ctx_check(kp_ctx* ctx, hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  return sync_status(ctx, stream);
+}
+
+kp_status kp_minmax(kp_ctx* ctx, int64_t n, int32_t nvars, const int32_t* vals, int32_t* out,
+                    unsigned flags, hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (n < 0 || nvars < 1 || nvars > KP_MAX_VARS || !out || (n > 0 && !vals))
+    return fail(ctx, KP_E_ARG, "kp_minmax: bad arguments");
+  hipError_t e = launch_minmax(n, nvars, vals, out, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_minmax");
+  return finish(ctx, flags, stream, "kp_minmax");
+}
+
+kp_status kp_layout_product(int32_t nx, int32_t ny, const int32_t* amin, const int32_t* amax,
+                            const int32_t* bmin, const int32_t* bmax, const int32_t* ha,
+                            const int32_t* hb, kp_layout* out) {
+  if (!out || nx < 0 || nx > KP_MAX_VARS || ny < 0 || ny > KP_MAX_VARS) return KP_E_ARG;
+  if (nx > 0 && (!amin || !amax || !bmin || !bmax)) return KP_E_ARG;
+  if (ny > 0 && (!ha || !hb)) return KP_E_ARG;
+  kp_layout L;
+  std::memset(&L, 0, sizeof L);
+  L.nx = nx;
+  L.ny = ny;
+  bool empty = false;
+  int64_t W = 1;
+  for (int v = 0; v < nx; ++v) {
+    L.amin[v] = amin[v];
+    L.amax[v] = amax[v];
+    L.bmin[v] = bmin[v];
+    L.bmax[v] = bmax[v];
+    if (amin[v] > amax[v] || bmin[v] > bmax[v]) {
+      empty = true;
+      continue;
+    }
+    L.xmin[v] = (int64_t)amin[v] + bmin[v];
+    L.xw[v] = (int64_t)amax[v] + bmax[v] - L.xmin[v] + 1;
+    L.xc[v] = W;
+    if (__builtin_mul_overflow(W, L.xw[v], &W) || W >= CODE_LIMIT) return KP_E_CODE_OVERFLOW;
+  }
+  int64_t Wy = 1;
+  for (int v = 0; v < ny; ++v) {
+    L.ha[v] = ha[v];
+    L.hb[v] = hb[v];
+    if (ha[v] < 0 || hb[v] < 0) {
+      empty = true;
+      continue;
+    }
+    L.yh[v] = (int64_t)ha[v] + hb[v];
+  }
+  for (int v = ny - 1; v >= 0; --v) {   // y_0 most significant
+    if (L.yh[v] < 0) continue;
+    L.yc[v] = Wy;
+    if (__builtin_mul_overflow(Wy, 2 * L.yh[v] + 1, &Wy) || Wy >= CODE_LIMIT)
+      return KP_E_CODE_OVERFLOW;
+  }
+  L.Wx = W;
+  L.Hy = (Wy - 1) / 2;
+  if (ny == 0) {
+    L.nkeys = W;
+  } else {
+    int64_t k;
+    if (__builtin_mul_overflow(W, L.Hy + 1, &k) || __builtin_mul_overflow(k, (int64_t)2, &k) ||
+        k >= CODE_LIMIT)
+      return KP_E_CODE_OVERFLOW;
+    L.nkeys = k;
+  }
+  if (empty) L.nkeys = 0;
+  *out = L;
+  return KP_OK;
+}
+
+kp_status kp_encode(kp_ctx* ctx, const kp_layout* layout, int which, int64_t n,
+                    const int32_t* x_exps, const int32_t* y_mult, const uint8_t* is_sin,
+                    int64_t* xcodes, int64_t* ycodes, unsigned flags, hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (!layout || (which != 0 && which != 1) || n < 0)
+    return fail(ctx, KP_E_ARG, "kp_encode: bad arguments");
+  if (n > 0 && ((layout->nx > 0 && !x_exps) || !xcodes ||
+                (layout->ny > 0 && (!y_mult || !is_sin || !ycodes))))
+    return fail(ctx, KP_E_ARG, "kp_encode: null array");
+  DevLayout d = make_dev_layout(*layout, which);
+  hipError_t e = launch_encode(d, n, x_exps, y_mult, is_sin, xcodes, ycodes, &ctx->status->err,
+                               stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_encode");
+  return finish(ctx, flags, stream, "kp_encode");
+}
+
+kp_status kp_decode(kp_ctx* ctx, const kp_layout* layout, int poisson, int64_t n,
+                    const int64_t* codes, int32_t* x_exps, int32_t* y_mult, uint8_t* is_sin,
+                    unsigned flags, hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (!layout || n < 0) return fail(ctx, KP_E_ARG, "kp_decode: bad arguments");
+  if (poisson && layout->ny == 0) return fail(ctx, KP_E_ARG, "kp_decode: layout has no trig part");
+  if (n > 0 && (!codes || (layout->nx > 0 && !x_exps) || (poisson && (!y_mult || !is_sin))))
+    return fail(ctx, KP_E_ARG, "kp_decode: null array");
+  DevLayout d = make_dev_layout(*layout, 0);
+  hipError_t e = launch_decode(d, poisson, n, codes, x_exps, y_mult, is_sin, &ctx->status->err,
+                               stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_decode");
+  return finish(ctx, flags, stream, "kp_decode");
+}
+
+kp_status kp_mul_bound(kp_ctx* ctx, const kp_layout* layout, int poisson, kp_dtype dtype,
+                       kp_mode mode, int64_t na, int64_t nb, kp_mode* resolved,
+                       int64_t* max_out_terms, size_t* workspace_bytes) {
+  if (!ctx) return KP_E_ARG;
+  Plan p;
+  kp_status st = make_plan(ctx, layout, poisson, dtype, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  if (resolved) *resolved = p.mode;
+  if (max_out_terms) *max_out_terms = p.max_out;
+  if (workspace_bytes) *workspace_bytes = p.ws;
+  return KP_OK;
+}
+
+kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                         unsigned flags, const int64_t* a_codes, const void* a_coef, int64_t na,
+                         const int64_t* b_codes, const void* b_coef, int64_t nb,
+                         int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  Plan p;
+  kp_status st = make_plan(ctx, layout, 0, dtype, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  if (!out_n || out_cap < 0 || (na > 0 && (!a_codes || !a_coef)) ||
+      (nb > 0 && (!b_codes || !b_coef)) || (out_cap > 0 && (!out_codes || !out_coef)))
+    return fail(ctx, KP_E_ARG, "kp_mul_laurent: null array or negative capacity");
+  if (workspace_bytes < p.ws || (p.ws > 0 && !workspace))
+    return fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, p.ws);
+  Carver c;
+  c.base = static_cast<char*>(workspace);
+  hipError_t e = hipSuccess;
+  const bool empty = na == 0 || nb == 0 || layout->nkeys == 0;
+  if (p.mode == KP_DENSE) {
+    DenseBufs B{};
+    int64_t *atk, *btk;
+    int32_t *ati, *bti;
+    carve_dense<true>(c, p, na, nb, &B, &atk, &ati, &btk, &bti);
+    B.out_k = out_codes;
+    B.out_c = out_coef;
+    B.out_cap = out_cap;
+    if (!empty) std::tie(B.ev0, B.ev1) = timing_pair(ctx);
+    e = launch_meta_init(B.meta, stream);
+    if (!empty) {
+      if (e == hipSuccess && dtype == KP_I64)
+        e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, B.meta,
+                              stream);
+      SortSeg sa{a_codes, (const int64_t*)a_coef, na, B.ak, nullptr, B.apairs, atk, ati};
+      SortSeg sb{b_codes, (const int64_t*)b_coef, nb, B.bk, B.bc, nullptr,
+                 btk, bti};
+      if (e == hipSuccess) e = launch_sort2(sa, sb, stream);
+      if (e == hipSuccess) e = launch_dense_laurent(p.dp, B, dtype, stream);
+    }
+    if (e == hipSuccess) e = launch_finalize(B.meta, out_cap, out_n, &ctx->status->err, stream);
+  } else {
+    HashCarve h;
+    carve_hash(c, p, 0, na, nb, &h);
+    HashBufs H{h.meta, h.table, p.cap_log2, (int64_t)1 << p.cap_log2, out_codes, out_coef, out_cap,
+               nullptr, nullptr};
+    if (!empty) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    e = launch_meta_init(h.meta, stream);
+    if (!empty) {
+      if (e == hipSuccess && dtype == KP_I64)
+        e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
+                              stream);
+      if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 << p.cap_log2, stream);
+      if (e == hipSuccess)
+        e = launch_hash_laurent(H, dtype, a_codes, a_coef, na, b_codes, b_coef, nb,
+                                ctx->tune.hash_rows, stream);
+      if (e == hipSuccess) e = launch_hash_compact(H, dtype, stream);
+    }
+    if (e == hipSuccess) e = launch_finalize(h.meta, out_cap, out_n, &ctx->status->err, stream);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent launch");
+  return finish(ctx, flags, stream, "kp_mul_laurent");
+}
+
+kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
+                         const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
+                         const double* a_coef, int64_t na, const int64_t* b_x,
+                         const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                         int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
+                         int64_t* out_n, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (layout && layout->ny == 0) return fail(ctx, KP_E_ARG, "kp_mul_poisson: layout has ny == 0");
+  Plan p;
+  kp_status st = make_plan(ctx, layout, 1, KP_F64, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  if (!out_n || out_cap < 0 || (na > 0 && (!a_x || !a_y || !a_sin || !a_coef)) ||
+      (nb > 0 && (!b_x || !b_y || !b_sin || !b_coef)) || (out_cap > 0 && (!out_keys || !out_coef)))
+    return fail(ctx, KP_E_ARG, "kp_mul_poisson: null array or negative capacity");
+  if (workspace_bytes < p.ws || (p.ws > 0 && !workspace))
+    return fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, p.ws);
+  Carver c;
+  c.base = static_cast<char*>(workspace);
+  HashCarve h;
+  carve_hash(c, p, 1, na, nb, &h);
+  HashBufs H{h.meta, h.table, p.cap_log2, (int64_t)1 << p.cap_log2, out_keys, out_coef, out_cap,
+             nullptr, nullptr};
+  hipError_t e = launch_meta_init(h.meta, stream);
+  if (na > 0 && nb > 0 && layout->nkeys > 0) {
+    std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 << p.cap_log2, stream);
+    if (e == hipSuccess)
+      e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream);
+    if (e == hipSuccess)
+      e = launch_hash_poisson(H, layout->Wx, h.pp, a_coef, na, b_coef, nb, ctx->tune.hash_rows,
+                              stream);
+    if (e == hipSuccess) e = launch_hash_compact(H, KP_F64, stream);
+  }
+  if (e == hipSuccess) e = launch_finalize(h.meta, out_cap, out_n, &ctx->status->err, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson launch");
+  return finish(ctx, flags, stream, "kp_mul_poisson");
+}
+
+kp_status kp_encode_host(const kp_layout* layout, int which, int64_t n, const int32_t* x_exps,
+                         const int32_t* y_mult, const uint8_t* is_sin, int64_t* xcodes,
+                         int64_t* ycodes) {
+  if (!layout || (which != 0 && which != 1) || n < 0) return KP_E_ARG;
+  if (n > 0 && ((layout->nx > 0 && !x_exps) || !xcodes ||
+                (layout->ny > 0 && (!y_mult || !is_sin || !ycodes))))
+    return KP_E_ARG;
+  DevLayout d = make_dev_layout(*layout, which);
+  uint32_t err = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t kx = 0, ky = 0;
+    err |= encode_term(d, x_exps + i * d.nx, d.ny ? y_mult + i * d.ny : nullptr,
+                       d.ny ? is_sin[i] : 0, &kx, &ky);
+    xcodes[i] = kx;
+    if (d.ny) ycodes[i] = ky;
+  }
+  return (kp_status)first_error(err);
+}
+
+kp_status kp_decode_host(const kp_layout* layout, int poisson, int64_t n, const int64_t* codes,
+                         int32_t* x_exps, int32_t* y_mult, uint8_t* is_sin) {
+  if (!layout || n < 0) return KP_E_ARG;
+  if (poisson && layout->ny == 0) return KP_E_ARG;
+  if (n > 0 && (!codes || (layout->nx > 0 && !x_exps) || (poisson && (!y_mult || !is_sin))))
+    return KP_E_ARG;
+  DevLayout d = make_dev_layout(*layout, 0);
+  uint32_t err = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c = codes[i];
+    if (c < 0 || c >= d.nkeys) {
+      err |= ERR_RANGE;
+      c = 0;
+    }
+    uint64_t q = (uint64_t)c;
+    if (poisson) {
+      is_sin[i] = (uint8_t)(q & 1);
+      q >>= 1;
+      uint64_t u = fdiv(q, d.dWx);
+      decode_x(d, q - u * (uint64_t)d.Wx, x_exps + i * d.nx);
+      decode_y(d, u, y_mult + i * d.ny);
+    } else {
+      decode_x(d, q, x_exps + i * d.nx);
+    }
+  }
+  return (kp_status)first_error(err);
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+// kp_codec.hip -- per-variable min/max, Kronecker encode and decode kernels,
+// plus the small bookkeeping kernels shared by the multiply paths.
+//
+// Encode and decode apply the generalised Kronecker map of Section 2
+// (c(e) = c.e - chi with per-variable widths and negative offsets); the
+// per-term arithmetic is in kp_internal.h so the host twins run the same map.
+#include <climits>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+namespace {
+
+constexpr int CODEC_BLOCK = 256;
+
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_minmax_init(int32_t nv, int32_t* out, int empty) {
+  int v = threadIdx.x;
+  if (v < nv) {
+    out[v] = empty ? 0 : INT_MAX;
+    out[nv + v] = empty ? -1 : INT_MIN;
+  }
+}
+
+// Each thread folds a strided set of rows into per-variable registers, then
+// the block reduces through LDS and folds into `out` with atomics.
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_minmax(int64_t n, int32_t nv, const int32_t* __restrict__ vals, int32_t* out) {
+  __shared__ int32_t smin[KP_MAX_VARS][CODEC_BLOCK / 64];
+  __shared__ int32_t smax[KP_MAX_VARS][CODEC_BLOCK / 64];
+  int32_t lo[KP_MAX_VARS], hi[KP_MAX_VARS];
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    lo[v] = INT_MAX;
+    hi[v] = INT_MIN;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int v = 0; v < KP_MAX_VARS; ++v) {
+      if (v < nv) {
+        int32_t x = vals[i * nv + v];
+        lo[v] = min(lo[v], x);
+        hi[v] = max(hi[v], x);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    if (v >= nv) break;
+    int32_t a = lo[v], b = hi[v];
+    for (int off = 32; off > 0; off >>= 1) {
+      a = min(a, __shfl_xor(a, off));
+      b = max(b, __shfl_xor(b, off));
+    }
+    if (lane == 0) {
+      smin[v][wave] = a;
+      smax[v][wave] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    int v = threadIdx.x;
+    int32_t a = INT_MAX, b = INT_MIN;
+    for (int w = 0; w < CODEC_BLOCK / 64; ++w) {
+      a = min(a, smin[v][w]);
+      b = max(b, smax[v][w]);
+    }
+    atomicMin(&out[v], a);
+    atomicMax(&out[nv + v], b);
+  }
+}
+
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_encode(DevLayout L, int64_t n, const int32_t* __restrict__ x, const int32_t* __restrict__ y,
+         const uint8_t* __restrict__ t, int64_t* __restrict__ kx, int64_t* __restrict__ ky,
+         uint32_t* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t e = 0;
+  if (i < n) {
+    int32_t ex[KP_MAX_VARS], jy[KP_MAX_VARS];
+    for (int v = 0; v < L.nx; ++v) ex[v] = x[i * L.nx + v];
+    for (int v = 0; v < L.ny; ++v) jy[v] = y[i * L.ny + v];
+    int64_t a = 0, b = 0;
+    e = encode_term(L, ex, jy, L.ny > 0 ? t[i] : 0, &a, &b);
+    kx[i] = a;
+    if (L.ny > 0) ky[i] = b;
+  }
+  // one atomic per wave that saw an error
+  uint32_t any = wave_or(e);
+  if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
+}
+
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_decode(DevLayout L, int poisson, int64_t n, const int64_t* __restrict__ codes,
+         int32_t* __restrict__ x, int32_t* __restrict__ y, uint8_t* __restrict__ t,
+         uint32_t* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t e = 0;
+  if (i < n) {
+    int64_t c = codes[i];
+    int32_t ex[KP_MAX_VARS], jy[KP_MAX_VARS];
+    if (c < 0 || c >= L.nkeys) {
+      e = ERR_RANGE;
+      c = 0;
+    }
+    uint64_t q = (uint64_t)c;
+    if (poisson) {
+      t[i] = (uint8_t)(q & 1);
+      q >>= 1;
+      uint64_t u = fdiv(q, L.dWx);
+      uint64_t kx = q - u * (uint64_t)L.Wx;
+      decode_x(L, kx, ex);
+      decode_y(L, u, jy);
+      for (int v = 0; v < L.ny; ++v) y[i * L.ny + v] = jy[v];
+    } else {
+      decode_x(L, q, ex);
+    }
+    for (int v = 0; v < L.nx; ++v) x[i * L.nx + v] = ex[v];
+  }
+  uint32_t any = wave_or(e);
+  if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
+}
+
+__global__ void k_meta_init(Meta* m) {
+  if (threadIdx.x == 0) {
+    m->err = 0;
+    m->narrow = 3u;
+    m->ntasks = 0;
+    m->out_count = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void k_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint32_t* ctx_err) {
+  if (threadIdx.x != 0) return;
+  uint32_t e = m->err;
+  int64_t cnt = m->out_count;
+  if (cnt > out_cap) e |= ERR_CAPACITY;
+  if (e) {
+    atomicOr(ctx_err, e);
+    *out_n = -(int64_t)first_error(e);
+  } else {
+    *out_n = cnt;
+  }
+}
+
+// Range flags of int64 coefficients: bit0 all fit int32, bit1 all fit in a
+// signed 24-bit value (so a product needs only the 24-bit multipliers).
+__global__ void __launch_bounds__(256)
+k_coef_range(const int64_t* __restrict__ a, int64_t na, const int64_t* __restrict__ b, int64_t nb,
+             Meta* m) {
+  uint32_t ok = 3u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+    int64_t c = i < na ? a[i] : b[i - na];
+    if (c < INT_MIN || c > INT_MAX) ok &= ~1u;
+    if (c < -(1 << 23) || c >= (1 << 23)) ok &= ~2u;
+  }
+  uint32_t all = wave_and(ok);
+  if ((threadIdx.x & 63) == 0 && all != 3u) atomicAnd(&m->narrow, all);
+}
+
+int grid_for(int64_t n, int block, int cap = 1 << 20) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(64), 0, s, nv, out, n == 0 ? 1 : 0);
+  if (n > 0) {
+    int g = grid_for(n, CODEC_BLOCK, 2048);
+    hipLaunchKernelGGL(k_minmax, dim3(g), dim3(CODEC_BLOCK), 0, s, n, nv, vals, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const DevLayout& L, int64_t n, const int32_t* x, const int32_t* y,
+                         const uint8_t* t, int64_t* kx, int64_t* ky, uint32_t* err, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encode, dim3(grid_for(n, CODEC_BLOCK, INT_MAX)), dim3(CODEC_BLOCK), 0, s, L,
+                     n, x, y, t, kx, ky, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const DevLayout& L, int poisson, int64_t n, const int64_t* codes,
+                         int32_t* x, int32_t* y, uint8_t* t, uint32_t* err, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode, dim3(grid_for(n, CODEC_BLOCK, INT_MAX)), dim3(CODEC_BLOCK), 0, s, L,
+                     poisson, n, codes, x, y, t, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_meta_init(Meta* m, hipStream_t s) {
+  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(64), 0, s, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  size_t n16 = bytes / 16, tail = bytes % 16;
+  int g = grid_for((int64_t)n16, 256, 8192);
+  hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, s, (uint4*)p, n16, (uint8_t*)p + n16 * 16,
+                     tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint32_t* ctx_err,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, m, out_cap, out_n, ctx_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_range(const int64_t* a, int64_t na, const int64_t* b, int64_t nb, Meta* m,
+                             hipStream_t s) {
+  if (na + nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coef_range, dim3(grid_for(na + nb, 256, 1024)), dim3(256), 0, s, a, na, b,
+                     nb, m);
+  return hipGetLastError();
+}
+
+}  // namespace kp

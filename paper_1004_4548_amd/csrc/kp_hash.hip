@@ -1,0 +1,287 @@
+// kp_hash.hip -- hash-table accumulation for highly sparse products, and the
+// Poisson split.
+//
+// Section 3.2 replaces the dense coefficient array with a hash table keyed by
+// the product's code: a product whose code is already present adds its
+// coefficient, otherwise it is inserted.  The paper's table is a bucketed,
+// cache-blocked CPU design and mentions linear probing as an alternative; on
+// gfx950 the table is one open-addressing array of 16-byte slots in HBM
+// {code + 1, coefficient} (0 marks an empty slot), probed linearly from a
+// multiplicative hash of the code.  A slot is claimed with a device-scope
+// 64-bit compare-and-swap on the key and the coefficient is accumulated with a
+// 64-bit atomic add (integer, or fp64 add), so concurrent insertions of the
+// same code from any compute unit combine without locks.  Compaction reads
+// the table once, selects non-empty slots with a nonzero coefficient by
+// wavefront ballot and writes them contiguously.
+//
+// Poisson series (Section 2, eq. werner with the factor 1/2): every pair
+// contributes +-1/2 ca cb to the term of the difference and of the sum of the
+// trigonometric arguments.  With the product's balanced trig code ky and the
+// polynomial code kx in [0, Wx), the combined code K = kx + Wx * ky of a
+// piece is kx_a + kx_b + Wx (ky_a +- ky_b); K < 0 exactly when ky < 0, and
+// then the canonical form (first multiplier positive) is kx + Wx |ky|
+// = 2 kx - K with the sign of a sine flipped.  A sine with ky = 0
+// (0 <= K < Wx) is dropped.
+#include <climits>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+namespace {
+
+constexpr int HASH_BLOCK = 256;
+constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;   // 2^64 / golden ratio (Fibonacci hashing)
+
+__device__ inline void slot_add(uint64_t* c, int64_t v) {
+  atomicAdd((unsigned long long*)c, (unsigned long long)v);
+}
+__device__ inline void slot_add(uint64_t* c, double v) {
+  unsafeAtomicAdd(reinterpret_cast<double*>(c), v);
+}
+
+// Insert-or-accumulate.  Linear probing from the hash of `code`; at most
+// max_probe slots are visited before the table is declared full.
+template <typename T>
+__device__ inline void table_insert(uint64_t* __restrict__ table, uint64_t mask, int shift,
+                                    int64_t max_probe, int64_t code, T v, uint32_t* err) {
+  const uint64_t key = (uint64_t)code + 1;
+  uint64_t s = ((uint64_t)code * GOLDEN) >> shift;
+  for (int64_t p = 0; p < max_probe; ++p) {
+    uint64_t* ks = table + 2 * s;
+    uint64_t cur = __hip_atomic_load(ks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == 0) {
+      cur = atomicCAS((unsigned long long*)ks, 0ull, (unsigned long long)key);
+      if (cur == 0) cur = key;
+    }
+    if (cur == key) {
+      slot_add(ks + 1, v);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+  atomicOr(err, ERR_CAPACITY);
+}
+
+template <typename T>
+__device__ inline T mul_coef(T a, T b, uint32_t narrow);
+template <>
+__device__ inline int64_t mul_coef<int64_t>(int64_t a, int64_t b, uint32_t narrow) {
+  if (narrow & 2u) {
+    int32_t x = ((int32_t)a << 8) >> 8, y = ((int32_t)b << 8) >> 8;
+    return (int64_t)x * (int64_t)y;
+  }
+  if (narrow & 1u) return (int64_t)(int32_t)a * (int64_t)(int32_t)b;
+  return (int64_t)((uint64_t)a * (uint64_t)b);
+}
+template <>
+__device__ inline double mul_coef<double>(double a, double b, uint32_t) {
+  return a * b;
+}
+
+// Thread = one term of B (in registers); loops over a slice of A's rows,
+// whose code and coefficient are wavefront-uniform (scalar loads).
+template <typename T>
+__global__ void __launch_bounds__(HASH_BLOCK)
+k_hash_laurent(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t max_probe,
+               Meta* meta, const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
+               const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows) {
+  const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * rows;
+  const int64_t i1 = min(i0 + rows, na);
+  const uint32_t narrow = meta->narrow;
+  if (j >= nb) return;
+  const int64_t bj = bk[j];
+  const T cb = bc[j];
+  for (int64_t i = i0; i < i1; ++i) {
+    const T v = mul_coef<T>(ac[i], cb, narrow);
+    if (v != T(0)) table_insert<T>(table, mask, shift, max_probe, ak[i] + bj, v, &meta->err);
+  }
+}
+
+__global__ void __launch_bounds__(HASH_BLOCK)
+k_poisson_prep(int64_t Wx, const int64_t* __restrict__ ax, const int64_t* __restrict__ ay,
+               const uint8_t* __restrict__ as, int64_t na, const int64_t* __restrict__ bx,
+               const int64_t* __restrict__ by, const uint8_t* __restrict__ bs, int64_t nb,
+               PoissonPrep P) {
+  const int64_t g = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+  if (g < na) {
+    P.ap[g] = ax[g] + Wx * ay[g];
+    P.akx[g] = ax[g];
+    P.at[g] = as[g];
+  } else if (g < na + nb) {
+    const int64_t j = g - na;
+    P.bp[j] = bx[j] + Wx * by[j];
+    P.bm[j] = bx[j] - Wx * by[j];
+    P.bkx[j] = bx[j];
+    P.bt[j] = bs[j];
+  }
+}
+
+__device__ inline void poisson_piece(uint64_t* table, uint64_t mask, int shift, int64_t max_probe,
+                                     int64_t Wx, int64_t K, int64_t kx, int t, double v,
+                                     uint32_t* err) {
+  int64_t pos = K;
+  if (K < 0) {                 // ky < 0: fold to |ky|, sin(-a) = -sin(a)
+    pos = 2 * kx - K;
+    if (t) v = -v;
+  } else if (t && K < Wx) {    // sin of the zero multiplier vector vanishes
+    return;
+  }
+  table_insert<double>(table, mask, shift, max_probe, 2 * pos + t, v, err);
+}
+
+// Thread = one term of B; every pair yields the difference piece (sign -1 for
+// cos*sin) and the sum piece (sign -1 for sin*sin), each 1/2 ca cb.
+__global__ void __launch_bounds__(HASH_BLOCK)
+k_hash_poisson(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t max_probe,
+               Meta* meta, int64_t Wx, const int64_t* __restrict__ ap,
+               const int64_t* __restrict__ akx, const uint8_t* __restrict__ at,
+               const double* __restrict__ ac, int64_t na, const int64_t* __restrict__ bp,
+               const int64_t* __restrict__ bm, const int64_t* __restrict__ bkx,
+               const uint8_t* __restrict__ bt, const double* __restrict__ bc, int64_t nb,
+               int rows) {
+  const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * rows;
+  const int64_t i1 = min(i0 + rows, na);
+  if (j >= nb) return;
+  const int64_t Bp = bp[j], Bm = bm[j], kxb = bkx[j];
+  const int tb = bt[j];
+  const double cb = bc[j];
+  for (int64_t i = i0; i < i1; ++i) {
+    const int ta = at[i];
+    const double h = 0.5 * (ac[i] * cb);
+    if (h == 0.0) continue;
+    const int64_t kx = akx[i] + kxb;
+    const int t = ta ^ tb;
+    const double sm = (!ta && tb) ? -h : h;   // cos a sin b: -1/2 sin(a - b)
+    const double sp = (ta && tb) ? -h : h;    // sin a sin b: -1/2 cos(a + b)
+    poisson_piece(table, mask, shift, max_probe, Wx, ap[i] + Bm, kx, t, sm, &meta->err);
+    poisson_piece(table, mask, shift, max_probe, Wx, ap[i] + Bp, kx, t, sp, &meta->err);
+  }
+}
+
+// ------------------------------------------------------------ compaction
+constexpr int COMPACT_PER = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(HASH_BLOCK)
+k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
+               int64_t* __restrict__ out_k, T* __restrict__ out_c, int64_t out_cap) {
+  __shared__ int64_t s_wave[HASH_BLOCK / 64];
+  __shared__ int64_t s_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t chunk = (int64_t)HASH_BLOCK * COMPACT_PER;
+  for (int64_t base = (int64_t)blockIdx.x * chunk; base < cap; base += (int64_t)gridDim.x * chunk) {
+    uint64_t key[COMPACT_PER], val[COMPACT_PER];
+    uint64_t ball[COMPACT_PER];
+    int64_t wave_cnt = 0;
+#pragma unroll
+    for (int r = 0; r < COMPACT_PER; ++r) {
+      const int64_t s = base + r * HASH_BLOCK + threadIdx.x;
+      bool f = false;
+      key[r] = 0;
+      val[r] = 0;
+      if (s < cap) {
+        const uint4 slot = reinterpret_cast<const uint4*>(table)[s];
+        key[r] = ((uint64_t)slot.y << 32) | slot.x;
+        val[r] = ((uint64_t)slot.w << 32) | slot.z;
+        T c;
+        __builtin_memcpy(&c, &val[r], sizeof(T));
+        f = key[r] != 0 && c != T(0);
+      }
+      ball[r] = __ballot(f);
+      wave_cnt += __popcll(ball[r]);
+    }
+    if (lane == 0) s_wave[wave] = wave_cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int w = 0; w < HASH_BLOCK / 64; ++w) tot += s_wave[w];
+      s_base = tot ? (int64_t)atomicAdd((unsigned long long*)&meta->out_count,
+                                        (unsigned long long)tot)
+                   : 0;
+    }
+    __syncthreads();
+    int64_t pos = s_base;
+    for (int w = 0; w < wave; ++w) pos += s_wave[w];
+    const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+    for (int r = 0; r < COMPACT_PER; ++r) {
+      if (ball[r] & (1ull << lane)) {
+        const int64_t p = pos + __popcll(ball[r] & lt);
+        if (p < out_cap) {
+          out_k[p] = (int64_t)(key[r] - 1);
+          T c;
+          __builtin_memcpy(&c, &val[r], sizeof(T));
+          out_c[p] = c;
+        }
+      }
+      pos += __popcll(ball[r]);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
+                               int64_t na, const int64_t* bk, const void* bc, int64_t nb,
+                               int rows, hipStream_t s) {
+  if (rows < 1) rows = 1;
+  const uint64_t mask = (1ull << H.cap_log2) - 1;
+  const int shift = 64 - (int)H.cap_log2;
+  dim3 grid((unsigned)((nb + HASH_BLOCK - 1) / HASH_BLOCK), (unsigned)((na + rows - 1) / rows));
+  if (H.ev0) (void)hipEventRecord(H.ev0, s);
+  if (dt == KP_F64)
+    hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
+                       H.max_probe, H.meta, ak, (const double*)ac, na, bk, (const double*)bc, nb,
+                       rows);
+  else
+    hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
+                       H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk, (const int64_t*)bc,
+                       nb, rows);
+  if (H.ev1) (void)hipEventRecord(H.ev1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay, const uint8_t* as,
+                               int64_t na, const int64_t* bx, const int64_t* by,
+                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s) {
+  const int64_t n = na + nb;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_poisson_prep, dim3((unsigned)((n + HASH_BLOCK - 1) / HASH_BLOCK)),
+                     dim3(HASH_BLOCK), 0, s, Wx, ax, ay, as, na, bx, by, bs, nb, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep& P,
+                               const double* ac, int64_t na, const double* bc, int64_t nb,
+                               int rows, hipStream_t s) {
+  if (rows < 1) rows = 1;
+  const uint64_t mask = (1ull << H.cap_log2) - 1;
+  const int shift = 64 - (int)H.cap_log2;
+  dim3 grid((unsigned)((nb + HASH_BLOCK - 1) / HASH_BLOCK), (unsigned)((na + rows - 1) / rows));
+  if (H.ev0) (void)hipEventRecord(H.ev0, s);
+  hipLaunchKernelGGL(k_hash_poisson, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
+                     H.max_probe, H.meta, Wx, P.ap, P.akx, P.at, ac, na, P.bp, P.bm, P.bkx, P.bt,
+                     bc, nb, rows);
+  if (H.ev1) (void)hipEventRecord(H.ev1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s) {
+  const int64_t cap = 1ll << H.cap_log2;
+  const int64_t chunk = (int64_t)HASH_BLOCK * COMPACT_PER;
+  int64_t blocks = (cap + chunk - 1) / chunk;
+  if (blocks > 8192) blocks = 8192;
+  if (dt == KP_F64)
+    hipLaunchKernelGGL(k_hash_compact<double>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
+                       H.table, cap, H.meta, H.out_k, (double*)H.out_c, H.out_cap);
+  else
+    hipLaunchKernelGGL(k_hash_compact<int64_t>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
+                       H.table, cap, H.meta, H.out_k, (int64_t*)H.out_c, H.out_cap);
+  return hipGetLastError();
+}
+
+}  // namespace kp

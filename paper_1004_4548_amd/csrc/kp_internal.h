@@ -1,0 +1,240 @@
+// kp_internal.h -- shared definitions of the HIP path (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/kp.h"
+
+namespace kp {
+
+// ------------------------------------------------------------------ errors
+// Device-detected errors are latched as bits (1 << status) in a 32-bit word.
+enum : uint32_t {
+  ERR_RANGE = 1u << KP_E_RANGE,
+  ERR_NONCANONICAL = 1u << KP_E_NONCANONICAL,
+  ERR_CAPACITY = 1u << KP_E_CAPACITY,
+};
+
+__host__ __device__ inline int first_error(uint32_t bits) {
+  if (bits & ERR_RANGE) return KP_E_RANGE;
+  if (bits & ERR_NONCANONICAL) return KP_E_NONCANONICAL;
+  if (bits & ERR_CAPACITY) return KP_E_CAPACITY;
+  return bits ? KP_E_DEVICE : KP_OK;
+}
+
+// -------------------------------------------------- invariant-divisor division
+// Unsigned division of a 64-bit n by a fixed d >= 1 with one high multiply
+// (Granlund & Montgomery 1994, the round-up method for N-bit operands):
+//   l = ceil(log2 d),  m = floor(2^64 (2^l - d) / d) + 1,
+//   t = mulhi(m, n),   n / d = (t + ((n - t) >> min(l,1))) >> max(l-1,0).
+struct FastDiv {
+  uint64_t m;
+  uint64_t d;
+  uint32_t s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint64_t d) {
+  FastDiv f{};
+  f.d = d ? d : 1;
+  uint32_t l = 0;
+  while (l < 64 && (1ull << l) < f.d) ++l;
+  unsigned __int128 num = ((unsigned __int128)(((l == 64) ? 0 : (1ull << l)) - f.d)) << 64;
+  f.m = (uint64_t)(num / f.d) + 1;
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 0 ? l - 1 : 0;
+  return f;
+}
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline uint64_t fdiv(uint64_t n, const FastDiv& f) {
+  uint64_t t = mulhi64(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// ------------------------------------------------------------ device layout
+// What the kernels need of a kp_layout, for one factor (encode) or for the
+// product (decode), passed by value as a kernel argument.
+struct DevLayout {
+  int32_t nx, ny;
+  int64_t Wx, Hy, nkeys;
+  int32_t fmin[KP_MAX_VARS], fmax[KP_MAX_VARS];  // factor box (encode)
+  int32_t fh[KP_MAX_VARS];                       // factor trig half-width (encode)
+  int64_t xc[KP_MAX_VARS];
+  int64_t xmin[KP_MAX_VARS];                     // product box minimum (decode)
+  int64_t yc[KP_MAX_VARS];
+  int64_t yh[KP_MAX_VARS];
+  FastDiv dx[KP_MAX_VARS];                       // divide by product width xw_k
+  FastDiv dy[KP_MAX_VARS];                       // divide by 2 yh_k + 1
+  FastDiv dWx;
+};
+
+DevLayout make_dev_layout(const kp_layout& L, int which);
+
+// Per-term code map.  Returns an error bit (0 when fine).
+__host__ __device__ inline uint32_t encode_term(const DevLayout& L, const int32_t* e,
+                                                const int32_t* j, int is_sin, int64_t* kx,
+                                                int64_t* ky) {
+  uint32_t err = 0;
+  int64_t x = 0;
+  for (int v = 0; v < L.nx; ++v) {
+    int32_t ev = e[v];
+    if (ev < L.fmin[v] || ev > L.fmax[v]) err |= ERR_RANGE;
+    x += L.xc[v] * (int64_t)(ev - L.fmin[v]);
+  }
+  *kx = x;
+  if (L.ny > 0) {
+    int64_t y = 0;
+    for (int v = 0; v < L.ny; ++v) {
+      int32_t jv = j[v];
+      if (jv < -L.fh[v] || jv > L.fh[v]) err |= ERR_RANGE;
+      y += L.yc[v] * (int64_t)jv;
+    }
+    // canonical: first nonzero multiplier positive (<=> y > 0), no sin(0)
+    if (y < 0 || (y == 0 && is_sin)) err |= ERR_NONCANONICAL;
+    *ky = y;
+  }
+  return err;
+}
+
+// Laurent product code -> exponents.
+__host__ __device__ inline void decode_x(const DevLayout& L, uint64_t q, int32_t* e) {
+  for (int v = 0; v < L.nx; ++v) {
+    uint64_t qq = fdiv(q, L.dx[v]);
+    e[v] = (int32_t)((int64_t)(q - qq * L.dx[v].d) + L.xmin[v]);
+    q = qq;
+  }
+}
+
+// |ky| -> canonical balanced digits, y_0 most significant.
+__host__ __device__ inline void decode_y(const DevLayout& L, uint64_t u, int32_t* j) {
+  for (int v = L.ny - 1; v >= 0; --v) {
+    uint64_t w = L.dy[v].d;
+    uint64_t h = (uint64_t)L.yh[v];
+    uint64_t s = u + h;
+    uint64_t qq = fdiv(s, L.dy[v]);
+    int64_t d = (int64_t)(s - qq * w) - (int64_t)h;
+    j[v] = (int32_t)d;
+    u = qq;  // (u - d) / w == floor((u + h) / w)
+  }
+}
+
+// ------------------------------------------------------------ wave helpers
+#if defined(__HIPCC__)
+__device__ inline uint32_t wave_or(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off);
+  return v;
+}
+__device__ inline uint32_t wave_and(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v &= (uint32_t)__shfl_xor((int)v, off);
+  return v;
+}
+#endif
+
+// ------------------------------------------------------------ workspace meta
+struct Meta {
+  uint32_t err;         // latched error bits of this call
+  uint32_t narrow;      // bit0: all int64 coefficients fit int32; bit1: fit 24-bit signed
+  int64_t ntasks;       // dense: number of work items
+  int64_t out_count;    // number of result terms (before the capacity check)
+  int64_t pad[5];
+};
+
+// Status block owned by a context (device memory, 256 bytes).
+struct CtxStatus {
+  uint32_t err;
+  uint32_t pad[63];
+};
+
+// ------------------------------------------------------------ launchers
+// codec
+hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* out, hipStream_t s);
+hipError_t launch_encode(const DevLayout& L, int64_t n, const int32_t* x, const int32_t* y,
+                         const uint8_t* t, int64_t* kx, int64_t* ky, uint32_t* err, hipStream_t s);
+hipError_t launch_decode(const DevLayout& L, int poisson, int64_t n, const int64_t* codes,
+                         int32_t* x, int32_t* y, uint8_t* t, uint32_t* err, hipStream_t s);
+
+// misc
+hipError_t launch_meta_init(Meta* m, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint32_t* ctx_err,
+                           hipStream_t s);
+hipError_t launch_coef_range(const int64_t* a, int64_t na, const int64_t* b, int64_t nb, Meta* m,
+                             hipStream_t s);
+
+// sort: ascending by key, stable; two independent segments in one launch
+struct SortSeg {
+  const int64_t* keys;
+  const int64_t* vals;   // 8-byte payload (int64 or double bits)
+  int64_t n;
+  int64_t* out_keys;
+  int64_t* out_vals;
+  int64_t* out_pairs;    // optional AoS (key, val) output, may be null
+  int64_t* tmp_keys;     // n entries, used when n > one chunk
+  int32_t* tmp_idx;      // n entries
+};
+constexpr int SORT_CHUNK = 4096;
+size_t sort_tmp_bytes(int64_t n);
+hipError_t launch_sort2(const SortSeg& a, const SortSeg& b, hipStream_t s);
+
+// dense Laurent
+struct DensePlan {
+  int64_t S;             // window size (codes)
+  int64_t nwin;
+  int64_t ntiles;        // ceil(nb / 64)
+  int64_t max_tasks;
+  int64_t target_tasks;
+  int32_t block;
+};
+struct DenseBufs {
+  Meta* meta;
+  int64_t* ak; int64_t* apairs;   // sorted A: keys, (key, coef) pairs
+  int64_t* bk; int64_t* bc;       // sorted B: keys, coefs
+  int64_t na, nb;
+  int64_t* wt;           // [nwin * ntiles] inclusive work prefix per window
+  int64_t* task_off;     // [nwin + 1]
+  int32_t* pending;      // [nwin]
+  int64_t* wcount;       // [nwin] terms per window
+  int64_t* woff;         // [nwin] output offset per window
+  int64_t* dense;        // [nwin * S] accumulator for windows shared by several tasks
+  int64_t* stage_k;      // [nwin * S]
+  int64_t* stage_c;      // [nwin * S]
+  int64_t* out_k; void* out_c; int64_t out_cap;
+  hipEvent_t ev0, ev1;   // optional: recorded around the window kernel
+};
+hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s);
+
+// hash Laurent / Poisson
+struct HashBufs {
+  Meta* meta;
+  uint64_t* table;       // capacity * 2 words: (key + 1, coef bits)
+  int64_t cap_log2;
+  int64_t max_probe;
+  int64_t* out_k; void* out_c; int64_t out_cap;
+  hipEvent_t ev0, ev1;   // optional: recorded around the insert kernel
+};
+hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
+                               int64_t na, const int64_t* bk, const void* bc, int64_t nb,
+                               int rows, hipStream_t s);
+struct PoissonPrep {
+  int64_t* ap; int64_t* akx; uint8_t* at;     // A: kx + Wx ky, kx, is_sin
+  int64_t* bp; int64_t* bm; int64_t* bkx; uint8_t* bt;  // B: kx + Wx ky, kx - Wx ky, kx, is_sin
+};
+hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay, const uint8_t* as,
+                               int64_t na, const int64_t* bx, const int64_t* by,
+                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s);
+hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep& P,
+                               const double* ac, int64_t na, const double* bc, int64_t nb,
+                               int rows, hipStream_t s);
+hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
+
+}  // namespace kp

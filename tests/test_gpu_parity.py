@@ -1,0 +1,414 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+int64 results must be bit-exact; fp64 results must satisfy
+|gpu - oracle| <= 1e-13 * sum|contributions| per term.  Each case prints what
+it runs before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1004_4548_amd as kp
+from paper_1004_4548_amd import inputs as I
+from tests.helpers import assert_exact, assert_tolerance
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-13
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_laurent(a, b, mode="auto", ctx=None):
+    ctx = ctx or kp.context()
+    pa = kp.Poly(dev(np.asarray(a[0], np.int32)), dev(a[1]))
+    pb = kp.Poly(dev(np.asarray(b[0], np.int32)), dev(b[1]))
+    r, lay = kp.mul_laurent(pa, pb, mode=mode, ctx=ctx)
+    return r.exps.cpu().numpy(), r.coef.cpu().numpy(), lay
+
+
+def gpu_poisson(a, b, mode="auto", ctx=None):
+    ctx = ctx or kp.context()
+    sa = kp.PoissonSeries(dev(np.asarray(a[0], np.int32)), dev(np.asarray(a[1], np.int32)),
+                          dev(np.asarray(a[2], np.uint8)), dev(np.asarray(a[3], np.float64)))
+    sb = kp.PoissonSeries(dev(np.asarray(b[0], np.int32)), dev(np.asarray(b[1], np.int32)),
+                          dev(np.asarray(b[2], np.uint8)), dev(np.asarray(b[3], np.float64)))
+    r, lay = kp.mul_poisson(sa, sb, mode=mode, ctx=ctx)
+    return (r.x.cpu().numpy(), r.y.cpu().numpy(), r.is_sin.cpu().numpy(),
+            r.coef.cpu().numpy(), lay)
+
+
+def check_laurent(a, b, mode, what, ctx=None):
+    say(what, mode, len(a[1]), "x", len(b[1]), a[1].dtype)
+    ge, gc, lay = gpu_laurent(a, b, mode, ctx)
+    oe, oc, oab = O.laurent_mul(a[0], a[1], b[0], b[1], threads=4)
+    if np.asarray(a[1]).dtype == np.float64:
+        assert_tolerance([ge], gc, [oe], oc, oab, TOL, what)
+    else:
+        assert_exact([ge], gc, [oe], oc, what)
+    return ge, gc, lay
+
+
+@pytest.fixture(autouse=True)
+def _fresh_ctx():
+    ctx = kp.context()
+    saved = ctx.tune
+    yield
+    ctx.set_tune(**{f: getattr(saved, f) for f, _ in kp.Tune._fields_})
+
+
+# ------------------------------------------------------------------ codec
+def test_minmax_encode_decode_on_device():
+    torch = _torch()
+    (ea, ca), (eb, cb) = I.config(1)
+    mm = kp.minmax(dev(ea)).cpu().numpy()
+    np.testing.assert_array_equal(mm, np.concatenate([ea.min(0), ea.max(0)]))
+    lay = kp.layout_product(3, 0, ea.min(0), ea.max(0), eb.min(0), eb.max(0))
+    ka, _ = kp.encode(lay, 0, dev(ea))
+    kb, _ = kp.encode(lay, 1, dev(eb))
+    np.testing.assert_array_equal(ka.cpu().numpy(), kp.encode_host(lay, 0, ea)[0])
+    np.testing.assert_array_equal(kb.cpu().numpy(), kp.encode_host(lay, 1, eb)[0])
+    s = (ka[:100] + kb[:100]).contiguous()
+    np.testing.assert_array_equal(kp.decode(lay, s).cpu().numpy(), ea[:100] + eb[:100])
+    # Table 1 codes on the device
+    l1 = kp.layout_product(3, 0, [0, 0, 0], [3, 3, 3], [0, 0, 0], [0, 0, 0])
+    e = np.array([[0, 0, 0], [1, 0, 0], [3, 0, 0], [0, 1, 0], [0, 2, 0], [3, 3, 3]], np.int32)
+    np.testing.assert_array_equal(kp.encode(l1, 0, dev(e))[0].cpu().numpy(), [0, 1, 3, 4, 8, 63])
+    # empty input
+    mm0 = kp.minmax(torch.zeros((0, 2), dtype=torch.int32, device="cuda")).cpu().numpy()
+    assert mm0.tolist() == [0, 0, -1, -1]
+
+
+def test_device_range_and_canonical_errors():
+    lay = kp.layout_product(2, 0, [0, 0], [3, 3], [0, 0], [3, 3])
+    with pytest.raises(kp.KPError) as e:
+        kp.encode(lay, 0, dev(np.array([[1, 1], [4, 0]], np.int32)))
+    assert e.value.status == kp.KP_E_RANGE
+    lp = kp.layout_product(1, 2, [0], [1], [0], [1], [2, 2], [2, 2])
+    with pytest.raises(kp.KPError) as e:
+        kp.encode(lp, 0, dev(np.array([[0]], np.int32)), dev(np.array([[-1, 1]], np.int32)),
+                  dev(np.array([0], np.uint8)))
+    assert e.value.status == kp.KP_E_NONCANONICAL
+    # the context recovers after an error
+    kx, _ = kp.encode(lay, 0, dev(np.array([[1, 1]], np.int32)))
+    assert kx.cpu().tolist() == [1 + 7 * 1]      # product widths are 7
+
+
+def test_poisson_decode_round_trip_on_device():
+    lay = kp.layout_product(2, 3, [-2, 0], [2, 3], [-1, 0], [1, 1], [2, 1, 3], [1, 2, 0])
+    rng = np.random.default_rng(3)
+    keys = rng.integers(0, lay.nkeys, size=5000, dtype=np.int64)
+    x, y, t = kp.decode(lay, dev(keys), poisson=True)
+    hx, hy, ht = kp.decode_host(lay, keys, poisson=True)
+    np.testing.assert_array_equal(x.cpu().numpy(), hx)
+    np.testing.assert_array_equal(y.cpu().numpy(), hy)
+    np.testing.assert_array_equal(t.cpu().numpy(), ht)
+
+
+# ------------------------------------------------------------------ Laurent
+@pytest.mark.parametrize("mode", ["dense", "hash", "auto"])
+def test_laurent_500x500_box(mode):
+    a, b = I.config(1)
+    check_laurent(a, b, mode, "3 vars [-5,5], 500 x 500")
+
+
+@pytest.mark.parametrize("mode", ["dense", "hash"])
+def test_laurent_simplex_2000(mode):
+    a, b = I.config(2, scale=0.2)
+    check_laurent(a, b, mode, "4-var simplex deg 20, 2000 x 2000")
+
+
+def test_laurent_sparse_3000():
+    a, b = I.config(3, scale=0.1)
+    check_laurent(a, b, "auto", "6 vars [0,80], 3000 x 3000 (hash)")
+    with pytest.raises(kp.KPError) as e:       # 161^6 codes: too many for dense mode
+        gpu_laurent(a, b, "dense")
+    assert e.value.status == kp.KP_E_MODE
+
+
+@pytest.mark.parametrize("mode", ["dense", "hash"])
+def test_laurent_fp64(mode):
+    (ea, _), (eb, _) = I.config(1)
+    rng = np.random.default_rng(12)
+    a = (ea, rng.standard_normal(len(ea)))
+    b = (eb, rng.standard_normal(len(eb)))
+    check_laurent(a, b, mode, "fp64 N(0,1) 500 x 500")
+    # dyadic coefficients: every sum is exact, so the result is bit-exact
+    a = (ea, rng.integers(-999, 1000, len(ea)) / 64.0)
+    b = (eb, rng.integers(-999, 1000, len(eb)) / 8.0)
+    say("fp64 dyadic", mode)
+    ge, gc, _ = gpu_laurent(a, b, mode)
+    oe, oc, _ = O.laurent_mul(a[0], a[1], b[0], b[1])
+    nz = oc != 0
+    assert_exact([ge], gc, [oe[nz]], oc[nz], "dyadic fp64")
+
+
+@pytest.mark.parametrize("mode", ["dense", "hash"])
+def test_laurent_coefficient_widths(mode):
+    # 24-bit, 32-bit and full 64-bit (wrapping) coefficient paths
+    (ea, _), (eb, _) = I.config(1, scale=0.4)
+    rng = np.random.default_rng(5)
+    for lo, hi in ((-(2**23), 2**23 - 1), (-(2**31), 2**31 - 1), (-(2**62), 2**62)):
+        a = (ea, rng.integers(lo, hi, len(ea), dtype=np.int64))
+        b = (eb, rng.integers(lo, hi, len(eb), dtype=np.int64))
+        check_laurent(a, b, mode, f"coefficients in [{lo},{hi}]")
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (1, 700), (63, 65), (4095, 4097), (8193, 130)])
+def test_laurent_ragged_sizes(na, nb):
+    rng = np.random.default_rng(na * 7 + nb)
+    a = (rng.integers(-6, 7, (na, 3)).astype(np.int32), rng.integers(-50, 50, na))
+    b = (rng.integers(-4, 9, (nb, 3)).astype(np.int32), rng.integers(-50, 50, nb))
+    for mode in ("dense", "hash"):
+        check_laurent(a, b, mode, f"ragged {na} x {nb} (duplicates allowed)")
+
+
+def test_laurent_many_windows_and_shared_windows():
+    # small windows and many tasks per CU force several windows per product
+    # and windows split across workgroups (combined through HBM atomics)
+    ctx = kp.context()
+    a, b = I.config(2, scale=0.3)
+    for window, block, tpc in ((1024, 256, 64), (2048, 512, 16), (19456, 1024, 8)):
+        ctx.set_tune(window=window, block=block, tasks_per_cu=tpc)
+        check_laurent(a, b, "dense", f"window {window} block {block} tasks/CU {tpc}")
+        a64 = (a[0], a[1].astype(np.float64) / 4)
+        b64 = (b[0], b[1].astype(np.float64))
+        check_laurent(a64, b64, "dense", f"fp64 window {window}")
+
+
+def test_laurent_univariate_long_range():
+    # one variable, codes spanning many windows with sparse hits
+    rng = np.random.default_rng(9)
+    ea = np.unique(rng.integers(-200000, 200000, 3000)).reshape(-1, 1).astype(np.int32)
+    eb = np.unique(rng.integers(0, 300000, 2000)).reshape(-1, 1).astype(np.int32)
+    a = (ea, rng.integers(-9, 10, len(ea)))
+    b = (eb, rng.integers(-9, 10, len(eb)))
+    for mode in ("dense", "hash"):
+        check_laurent(a, b, mode, "univariate, 700k codes")
+
+
+def test_laurent_empty_and_cancelling():
+    torch = _torch()
+    ctx = kp.context()
+    a = kp.Poly(torch.zeros((0, 2), dtype=torch.int32, device="cuda"),
+                torch.zeros(0, dtype=torch.int64, device="cuda"))
+    b = kp.Poly(dev(np.array([[1, 2]], np.int32)), dev(np.array([3], np.int64)))
+    for mode in ("dense", "hash", "auto"):
+        r, _ = kp.mul_laurent(a, b, mode=mode)
+        assert r.coef.shape[0] == 0
+        r, _ = kp.mul_laurent(b, a, mode=mode)
+        assert r.coef.shape[0] == 0
+    # (1 + x)(1 - x): the x term cancels and is dropped
+    p = (np.array([[0], [1]], np.int32), np.array([1, 1], np.int64))
+    q = (np.array([[0], [1]], np.int32), np.array([1, -1], np.int64))
+    for mode in ("dense", "hash"):
+        ge, gc, _ = gpu_laurent(p, q, mode)
+        order = np.argsort(ge[:, 0])
+        assert ge[order, 0].tolist() == [0, 2] and gc[order].tolist() == [1, -1]
+
+
+def test_capacity_errors():
+    ctx = kp.context()
+    a, b = I.config(1, scale=0.4)
+    lay = kp.layout_product(3, 0, a[0].min(0), a[0].max(0), b[0].min(0), b[0].max(0))
+    ka, _ = kp.encode(lay, 0, dev(a[0]))
+    kb, _ = kp.encode(lay, 1, dev(b[0]))
+    torch = _torch()
+    for mode in ("dense", "hash"):
+        small = (torch.empty(10, dtype=torch.int64, device="cuda"),
+                 torch.empty(10, dtype=torch.int64, device="cuda"),
+                 torch.empty(1, dtype=torch.int64, device="cuda"))
+        with pytest.raises(kp.KPError) as e:
+            kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), mode, out=small)
+        assert e.value.status == kp.KP_E_CAPACITY
+    # a forced hash table smaller than the result fills up: reported, not hung
+    ctx.set_tune(hash_capacity=64)
+    with pytest.raises(kp.KPError) as e:
+        kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), "hash")
+    assert e.value.status == kp.KP_E_CAPACITY
+    # async: the count carries -(status)
+    on = kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), "hash",
+                              flags=kp.KP_FLAG_ASYNC)[2]
+    assert int(on.item()) == -kp.KP_E_CAPACITY
+    with pytest.raises(kp.KPError):
+        ctx.sync_check()
+    ctx.set_tune(hash_capacity=0)
+    check_laurent(a, b, "hash", "after recovery")
+
+
+def test_repeat_runs_bit_identical():
+    a, b = I.config(2, scale=0.2)
+    r1 = gpu_laurent(a, b, "hash")
+    r2 = gpu_laurent(a, b, "hash")
+    assert_exact([r1[0]], r1[1], [r2[0]], r2[1], "hash repeat")
+    d1 = gpu_laurent(a, b, "dense")
+    assert_exact([d1[0]], d1[1], [r1[0]], r1[1], "dense vs hash")
+    # dense output is ascending in code
+    lay = d1[2]
+    codes = sum((d1[0][:, v].astype(np.int64) - lay.xmin[v]) * lay.xc[v] for v in range(4))
+    assert (np.diff(codes) > 0).all()
+
+
+# ------------------------------------------------------------------ Poisson
+def _pkeys(x, y, t):
+    return [x, y, np.asarray(t).reshape(-1, 1)]
+
+
+def check_poisson(a, b, what, nx=3, ny=6, mode="auto"):
+    say(what, len(a[3]), "x", len(b[3]))
+    gx, gy, gt, gc, lay = gpu_poisson(a, b, mode)
+    ox, oy, ot, oc, oab = O.poisson_mul(a, b, nx, ny, threads=4)
+    assert_tolerance(_pkeys(gx, gy, gt), gc, _pkeys(ox, oy, ot), oc, oab, TOL, what)
+    return gx, gy, gt, gc
+
+
+def test_poisson_identities_on_device():
+    one = lambda x, j, t, c: (np.array([[x]], np.int32), np.array([j], np.int32),
+                              np.array([t], np.uint8), np.array([c], np.float64))
+    cy, sy = one(0, [1, 0], 0, 1.0), one(0, [1, 0], 1, 1.0)
+    gx, gy, gt, gc, _ = gpu_poisson(cy, cy)
+    got = {(tuple(y), int(t)): c for y, t, c in zip(gy.tolist(), gt, gc)}
+    assert got == {((0, 0), 0): 0.5, ((2, 0), 0): 0.5}
+    gx, gy, gt, gc, _ = gpu_poisson(sy, sy)
+    got = {(tuple(y), int(t)): c for y, t, c in zip(gy.tolist(), gt, gc)}
+    assert got == {((0, 0), 0): 0.5, ((2, 0), 0): -0.5}
+    gx, gy, gt, gc, _ = gpu_poisson(sy, cy)                    # sin 0 dropped
+    got = {(tuple(y), int(t)): c for y, t, c in zip(gy.tolist(), gt, gc)}
+    assert got == {((2, 0), 1): 0.5}
+    c1, s2 = one(0, [1, 0], 0, 1.0), one(0, [0, 1], 1, 1.0)
+    gx, gy, gt, gc, _ = gpu_poisson(s2, c1)
+    got = {(tuple(y), int(t)): c for y, t, c in zip(gy.tolist(), gt, gc)}
+    assert got == {((1, 1), 1): 0.5, ((1, -1), 1): -0.5}
+
+
+def test_poisson_400():
+    a, b = I.config(4, scale=0.08)
+    check_poisson(a, b, "Poisson 3+6 vars, 400 x 400")
+
+
+def test_poisson_exact_fp2_and_tiny():
+    nx, ny = 2, 3
+    a = I.poisson_random(nx=nx, ny=ny, n=300, xlo=-2, xhi=2, jmax=3, coef="f64int", cfg=91,
+                         factor=0)
+    b = I.poisson_random(nx=nx, ny=ny, n=257, xlo=-1, xhi=3, jmax=2, coef="f64int", cfg=91,
+                         factor=1)
+    gx, gy, gt, gc = check_poisson(a, b, "Poisson integer coefficients", nx, ny)
+    P = O.P61
+    rng = np.random.default_rng(1)
+    xp = [int(v) for v in rng.integers(2, P - 1, nx)]
+    zp = [tuple(int(v) for v in rng.integers(1, P - 1, 2)) for _ in range(ny)]
+    lhs = O.poisson_eval_fp2((gx, gy, gt, gc), nx, ny, xp, zp)
+    rhs = O.fp2_mul(O.poisson_eval_fp2(a, nx, ny, xp, zp), O.poisson_eval_fp2(b, nx, ny, xp, zp))
+    assert lhs == rhs
+    check_poisson(a, (b[0][:1], b[1][:1], b[2][:1], b[3][:1]), "Poisson n x 1", nx, ny)
+
+
+# ------------------------------------------------------------------ full sizes
+def test_full_moderately_sparse_10000():
+    """The 4-variable simplex product at full size (1e8 pairs), dense mode,
+    bit-exact against the oracle's full product."""
+    a, b = I.config(2)
+    ge, gc, lay = check_laurent(a, b, "auto", "4-var simplex, 10000 x 10000 (full)")
+    assert len(gc) > 130000
+
+
+def test_full_highly_sparse_sampled():
+    """The 6-variable sparse product at full size (9e8 pairs), hash mode: keys
+    unique and in the box, every coefficient sum over sign patterns of the
+    variables equal to the product of the factors' (mod 2^64), and sampled
+    terms equal to the oracle's one-by-one coefficients."""
+    torch = _torch()
+    a, b = I.config(3)
+    say("6 vars [0,80], 30000 x 30000 (full)")
+    pa = kp.Poly(dev(a[0]), dev(a[1]))
+    pb = kp.Poly(dev(b[0]), dev(b[1]))
+    lay = kp.laurent_layout(pa, pb)
+    ka, _ = kp.encode(lay, 0, pa.exps)
+    kb, _ = kp.encode(lay, 1, pb.exps)
+    codes, coef, _ = kp.mul_laurent_codes(lay, ka, pa.coef, kb, pb.coef, "hash")
+    n = codes.shape[0]
+    assert 8.9e8 < n <= 9e8
+    assert int(torch.unique(codes).shape[0]) == n
+    assert int(codes.min()) >= 0 and int(codes.max()) < lay.nkeys
+    assert bool((coef != 0).all())
+    # sign patterns: sum_t c_t prod_k s_k^e_tk = A(s) B(s)  (mod 2^64), s in {+1,-1}^6
+    par = torch.zeros(n, dtype=torch.int64, device="cuda")
+    q = codes.clone()
+    for v in range(6):
+        w = int(lay.xw[v])
+        e = q % w
+        q = q // w
+        par |= ((e + int(lay.xmin[v])) & 1) << v
+        del e
+    sums = torch.zeros(64, dtype=torch.int64, device="cuda")
+    sums.index_add_(0, par, coef)
+    sums = [int(s) for s in sums.cpu().tolist()]
+    M = 2**64
+    ea, ca, eb, cb = a[0], a[1], b[0], b[1]
+    for s in range(64):
+        sign = np.array([-1 if (s >> v) & 1 else 1 for v in range(6)])
+        pa_ = (ea & 1) @ ((sign < 0).astype(np.int64))
+        pb_ = (eb & 1) @ ((sign < 0).astype(np.int64))
+        va = int(np.where(pa_ % 2 == 1, -ca, ca).sum())
+        vb = int(np.where(pb_ % 2 == 1, -cb, cb).sum())
+        got = sum(sums[m] * (-1 if bin(m & s).count("1") % 2 else 1) for m in range(64))
+        assert got % M == (va * vb) % M, f"sign pattern {s}"
+    # sampled terms against the oracle's one-by-one coefficients
+    rng = np.random.default_rng(77)
+    idx = torch.from_numpy(rng.integers(0, n, 150)).cuda()
+    qe = kp.decode(lay, codes[idx].contiguous()).cpu().numpy()
+    want, _, _ = O.laurent_coeff_at(a[0], a[1], b[0], b[1], qe)
+    np.testing.assert_array_equal(coef[idx].cpu().numpy(), want)
+    # a few codes absent from the result have oracle coefficient 0
+    cand = torch.from_numpy(rng.integers(0, lay.nkeys, 4000)).cuda()
+    absent = cand[~torch.isin(cand, codes)][:20].contiguous()
+    qe = kp.decode(lay, absent).cpu().numpy()
+    want, _, _ = O.laurent_coeff_at(a[0], a[1], b[0], b[1], qe)
+    assert (want == 0).all()
+
+
+def test_full_poisson_sampled():
+    """The Poisson product at full size (2.5e7 pairs), hash mode: keys unique
+    and canonical, numeric evaluation at random angles, sampled terms equal to
+    the oracle's one-by-one coefficients within the tolerance."""
+    torch = _torch()
+    a, b = I.config(4)
+    say("Poisson 3+6 vars, 5000 x 5000 (full)")
+    gx, gy, gt, gc, lay = gpu_poisson(a, b)
+    n = len(gc)
+    assert 4.9e7 < n <= 5e7
+    key = np.concatenate([gx.astype(np.int64), gy.astype(np.int64), gt.reshape(-1, 1)], 1)
+    nz = np.argmax(gy != 0, axis=1)
+    first = gy[np.arange(n), nz]
+    assert ((first > 0) | ((gy == 0).all(1) & (gt == 0))).all()
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        xs = rng.uniform(0.8, 1.2, 3)
+        ys = rng.uniform(-np.pi, np.pi, 6)
+        def ev(x, y, t, c):
+            xv = np.prod(xs[None, :] ** x, axis=1)
+            ang = y @ ys
+            tr = np.where(t.astype(bool), np.sin(ang), np.cos(ang))
+            terms = c * xv * tr
+            return terms.sum(), np.abs(terms).sum()
+        va, sa = ev(*a)
+        vb, sb = ev(*b)
+        vp, sp = ev(gx, gy, gt, gc)
+        assert abs(vp - va * vb) <= 1e-11 * sa * sb
+    sel = rng.integers(0, n, 120)
+    want, wab, _ = O.poisson_coeff_at(a, b, 3, 6, gx[sel], gy[sel], gt[sel])
+    assert np.all(np.abs(gc[sel] - want) <= TOL * wab)
+    assert len(np.unique(key[sel], axis=0)) == len(np.unique(sel))

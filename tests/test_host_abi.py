@@ -1,0 +1,236 @@
+"""CPU tests of the C ABI's host side: exports, layout, codec and planning.
+
+The Kronecker codec is pinned by the codes printed in the paper (Tables 1 and
+2, eq. c_01 of Section 2, fixtures under tests/golden/), by exhaustive round
+trips and by the homomorphism property; the Poisson coding by the sign
+property of balanced digits.  No GPU is needed: these calls never launch.
+"""
+import ctypes as C
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1004_4548_amd as kp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.split() for l in f if l.strip() and not l.startswith("#")]
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(os.path.join(ROOT, "include", "kp.h")).read()
+    declared = set(re.findall(r"\b(kp_[a-z_0-9]+)\s*\(", text))
+    assert declared == set(kp.EXPORTED)
+    lib = C.CDLL(kp.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for s in range(10):
+        assert kp.status_str(s)
+
+
+def _layout_laurent(amin, amax, bmin=None, bmax=None):
+    nv = len(amin)
+    bmin = [0] * nv if bmin is None else bmin
+    bmax = [0] * nv if bmax is None else bmax
+    return kp.layout_product(nv, 0, amin, amax, bmin, bmax)
+
+
+def test_table1_codes():
+    # factor A spans the table's box, factor B is the constant 1: the product
+    # box is the table's box and A's codes are the printed ones
+    lay = _layout_laurent([0, 0, 0], [3, 3, 3])
+    assert list(lay.xc[:3]) == [1, 4, 16] and lay.nkeys == 64
+    for z, y, x, code in _rows("table1_codes.txt"):
+        kx, _ = kp.encode_host(lay, 0, [[int(x), int(y), int(z)]])
+        assert kx[0] == int(code)
+        assert kp.decode_host(lay, [int(code)]).tolist() == [[int(x), int(y), int(z)]]
+
+
+def test_eq_c01_homomorphism():
+    lay = _layout_laurent([0, 0, 0], [3, 3, 3])
+    for r in _rows("eq_c01.txt"):
+        z1, y1, x1, z2, y2, x2, want = map(int, r)
+        c1, _ = kp.encode_host(lay, 0, [[x1, y1, z1]])
+        c2, _ = kp.encode_host(lay, 0, [[x2, y2, z2]])
+        c12, _ = kp.encode_host(lay, 0, [[x1 + x2, y1 + y2, z1 + z2]])
+        assert c1[0] + c2[0] == want == c12[0]
+
+
+@pytest.mark.parametrize("emin,emax", [((-2, -5, 3), (4, 1, 7)), ((0, 0, 0), (9, 2, 1)),
+                                       ((-7, 3, -1), (-3, 8, 0))])
+def test_table2_generalised_codes(emin, emax):
+    lay = _layout_laurent(list(emin), list(emax))
+    w0 = 1 + emax[0] - emin[0]
+    assert list(lay.xc[:3]) == [1, w0, w0 * (1 + emax[1] - emin[1])]
+    for d1, x0, code in _rows("table2_rows.txt"):
+        base, off = x0[:3], int(x0[4:])
+        e0 = emin[0] + off if base == "min" else emax[0] - off
+        e = [e0, emin[1] + int(d1), emin[2]]
+        want = eval(code, {"w0": w0})          # the fixture's printed expression
+        kx, _ = kp.encode_host(lay, 0, [e])
+        assert kx[0] == want
+        # c(e) = c . e - chi with chi = c . e_min
+        chi = sum(int(lay.xc[v]) * emin[v] for v in range(3))
+        assert kx[0] == sum(int(lay.xc[v]) * e[v] for v in range(3)) - chi
+
+
+def test_product_codes_add():
+    rng = np.random.default_rng(1)
+    amin, amax, bmin, bmax = [-3, 0, 2], [2, 4, 5], [-1, -6, 0], [3, 1, 0]
+    lay = kp.layout_product(3, 0, amin, amax, bmin, bmax)
+    ea = np.stack([rng.integers(amin[v], amax[v] + 1, 200) for v in range(3)], 1)
+    eb = np.stack([rng.integers(bmin[v], bmax[v] + 1, 200) for v in range(3)], 1)
+    ka, _ = kp.encode_host(lay, 0, ea)
+    kb, _ = kp.encode_host(lay, 1, eb)
+    np.testing.assert_array_equal(kp.decode_host(lay, ka + kb), ea + eb)
+    assert ((ka + kb) >= 0).all() and ((ka + kb) < lay.nkeys).all()
+
+
+def test_exhaustive_round_trip():
+    lay = kp.layout_product(3, 0, [-2, 0, -1], [1, 3, 0], [0, -2, 0], [2, 0, 2])
+    codes = np.arange(lay.nkeys)
+    ex = kp.decode_host(lay, codes)
+    assert len({tuple(r) for r in ex.tolist()}) == lay.nkeys
+    lo = np.array([lay.xmin[v] for v in range(3)])
+    w = np.array([lay.xw[v] for v in range(3)])
+    assert ((ex >= lo) & (ex < lo + w)).all()
+    # re-encode against the product box itself (factor A = product box, B = 0)
+    lay2 = _layout_laurent(list(lo), list(lo + w - 1))
+    kx, _ = kp.encode_host(lay2, 0, ex)
+    np.testing.assert_array_equal(kx, codes)
+
+
+def test_large_widths_decode():
+    # widths near 2^31 exercise the invariant-divisor division
+    lay = kp.layout_product(2, 0, [-(2**30), 0], [2**30 - 1, 2**20], [0, -5], [2**29, 2**20])
+    rng = np.random.default_rng(2)
+    codes = rng.integers(0, lay.nkeys, size=20000, dtype=np.int64)
+    codes[:3] = [0, lay.nkeys - 1, lay.xw[0] - 1]
+    ex = kp.decode_host(lay, codes)
+    back = sum((ex[:, v].astype(object) - int(lay.xmin[v])) * int(lay.xc[v]) for v in range(2))
+    assert [int(b) for b in back] == codes.tolist()
+
+
+def test_code_overflow_boundary():
+    # 2^31 * 2^31 = 2^62 codes is rejected; 2^31 * (2^31 - 1) is accepted
+    with pytest.raises(kp.KPError) as e:
+        kp.layout_product(2, 0, [0, 0], [2**31 - 1, 2**31 - 1], [0, 0], [0, 0])
+    assert e.value.status == kp.KP_E_CODE_OVERFLOW
+    lay = kp.layout_product(2, 0, [0, 0], [2**31 - 1, 2**31 - 2], [0, 0], [0, 0])
+    assert lay.nkeys == 2**31 * (2**31 - 1)
+
+
+def test_range_check():
+    lay = _layout_laurent([0, 0], [3, 3])
+    with pytest.raises(kp.KPError) as e:
+        kp.encode_host(lay, 0, [[4, 0]])
+    assert e.value.status == kp.KP_E_RANGE
+    with pytest.raises(kp.KPError):
+        kp.decode_host(lay, [lay.nkeys])
+
+
+def test_empty_factor_layout():
+    lay = kp.layout_product(2, 0, [0, -1], [-1, 1], [0, 0], [3, 3])
+    assert lay.nkeys == 0
+
+
+# ---------------------------------------------------------------- Poisson codes
+def test_balanced_trig_codes_sign_property():
+    # every multiplier vector of a small balanced box: sign(ky) is the sign of
+    # the first nonzero multiplier, and ky(a) +- ky(b) = ky(a +- b)
+    ha, hb = [1, 2, 1], [1, 0, 2]
+    lay = kp.layout_product(1, 3, [0], [0], [0], [0], ha, hb)
+    box = [range(-(a + b), a + b + 1) for a, b in zip(ha, hb)]
+    js = np.array(list(itertools.product(*box)), dtype=np.int32)
+    n = len(js)
+    ky = np.array([sum(int(lay.yc[v]) * int(j[v]) for v in range(3)) for j in js])
+    for j, k in zip(js, ky):
+        nz = np.flatnonzero(j)
+        assert np.sign(k) == (0 if len(nz) == 0 else np.sign(j[nz[0]]))
+    assert len(set(ky.tolist())) == n and ky.max() == lay.Hy
+    # canonical decode of |ky| returns the canonical multiplier vector
+    Wx = lay.Wx
+    for j, k in zip(js, ky):
+        if k < 0:
+            continue
+        x, y, t = kp.decode_host(lay, [2 * (Wx * k) + 0], poisson=True)
+        assert y[0].tolist() == j.tolist()
+
+
+def test_poisson_encode_checks_canonical_form():
+    lay = kp.layout_product(1, 2, [0], [2], [0], [2], [3, 3], [3, 3])
+    kx, ky = kp.encode_host(lay, 0, [[1]], [[2, -3]], [1])
+    assert ky[0] > 0
+    for y, t in (([-1, 2], 0), ([0, -1], 1), ([0, 0], 1)):
+        with pytest.raises(kp.KPError) as e:
+            kp.encode_host(lay, 0, [[1]], [y], [t])
+        assert e.value.status == kp.KP_E_NONCANONICAL
+    kx, ky = kp.encode_host(lay, 0, [[1]], [[0, 0]], [0])       # cos(0) is canonical
+    assert ky[0] == 0
+
+
+def test_poisson_key_space():
+    lay = kp.layout_product(3, 6, [-4] * 3, [4] * 3, [-4] * 3, [4] * 3, [8] * 6, [8] * 6)
+    assert lay.Wx == 17**3 and lay.Hy == (33**6 - 1) // 2
+    assert lay.nkeys == 2 * lay.Wx * (lay.Hy + 1)
+
+
+# ---------------------------------------------------------------- planning
+def _host_ctx():
+    return kp.Context(-1)
+
+
+def test_mode_selection_for_the_workloads():
+    ctx = _host_ctx()
+    l1 = kp.layout_product(3, 0, [-5] * 3, [5] * 3, [-5] * 3, [5] * 3)
+    assert kp.mul_bound(l1, False, kp.KP_I64, "auto", 500, 500, ctx)[0] == "dense"
+    l2 = kp.layout_product(4, 0, [0] * 4, [20] * 4, [0] * 4, [20] * 4)
+    m, mo, ws = kp.mul_bound(l2, False, kp.KP_I64, "auto", 10000, 10000, ctx)
+    assert m == "dense" and mo == 41**4
+    l3 = kp.layout_product(6, 0, [0] * 6, [80] * 6, [0] * 6, [80] * 6)
+    m, mo, ws = kp.mul_bound(l3, False, kp.KP_I64, "auto", 30000, 30000, ctx)
+    assert m == "hash" and mo == 9 * 10**8
+    l4 = kp.layout_product(3, 6, [-4] * 3, [4] * 3, [-4] * 3, [4] * 3, [8] * 6, [8] * 6)
+    m, mo, ws = kp.mul_bound(l4, True, kp.KP_F64, "auto", 5000, 5000, ctx)
+    assert m == "hash" and mo == 5 * 10**7
+
+
+def test_planning_errors():
+    ctx = _host_ctx()
+    l3 = kp.layout_product(6, 0, [0] * 6, [80] * 6, [0] * 6, [80] * 6)
+    with pytest.raises(kp.KPError) as e:
+        kp.mul_bound(l3, False, kp.KP_I64, "dense", 30000, 30000, ctx)
+    assert e.value.status == kp.KP_E_MODE
+    l4 = kp.layout_product(1, 1, [0], [1], [0], [1], [1], [1])
+    with pytest.raises(kp.KPError) as e:
+        kp.mul_bound(l4, True, kp.KP_I64, "auto", 5, 5, ctx)
+    assert e.value.status == kp.KP_E_DTYPE
+
+
+def test_tune_validation():
+    ctx = _host_ctx()
+    t = ctx.tune
+    assert t.window == 16384 and t.block == 1024
+    ctx.set_tune(window=2048, block=512)
+    assert ctx.tune.window == 2048
+    for bad in (dict(window=20480 + 1024), dict(block=100), dict(hash_load=0.95),
+                dict(window=1000, block=256)):
+        with pytest.raises(kp.KPError):
+            ctx.set_tune(**bad)
+
+
+def test_host_context_rejects_launches():
+    ctx = _host_ctx()
+    lay = _layout_laurent([0], [3])
+    st = kp.lib().kp_encode(ctx.h, C.byref(lay), 0, 0, None, None, None, None, None, 0, None)
+    assert st == kp.KP_E_ARG
