@@ -119,54 +119,61 @@ struct Plan {
   int64_t cap_log2 = 6;
 };
 
-bool dense_feasible(const kp_ctx* ctx, const kp_layout* L, int64_t na, int64_t nb, int64_t* nwin,
-                    int64_t* ntiles) {
+int64_t factor_maxcode(const kp_layout* L, int which) {
+  int64_t m = 0;
+  for (int v = 0; v < L->nx; ++v)
+    m += L->xc[v] * (int64_t)(which ? L->bmax[v] - L->bmin[v] : L->amax[v] - L->amin[v]);
+  return m;
+}
+
+bool dense_feasible(const kp_ctx* ctx, const kp_layout* L, int64_t na, int64_t nb) {
   const int64_t S = ctx->tune.window;
-  *nwin = (L->nkeys + S - 1) / S;
-  *ntiles = (nb + 63) / 64;
   if (L->nkeys > ctx->tune.dense_max_keys) return false;
-  if (sat_mul(*nwin, *ntiles) > ((int64_t)1 << 27)) return false;
-  (void)na;
+  if (sat_mul((L->nkeys + S - 1) / S, (nb + 63) / 64) > ((int64_t)1 << 26)) return false;
+  if (na >= ((int64_t)1 << 31) || nb >= ((int64_t)1 << 31)) return false;
   return true;
 }
 
 template <bool CARVE>
-void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B,
-                 int64_t** a_tmpk, int32_t** a_tmpi, int64_t** b_tmpk, int32_t** b_tmpi) {
-  const int64_t nwin = p.dp.nwin, S = p.dp.S;
+void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B) {
+  const DensePlan& d = p.dp;
   Meta* meta = c.take<Meta>(1);
   int64_t* ak = c.take<int64_t>(na);
-  int64_t* apairs = c.take<int64_t>(2 * na + 8);    // the row loop's tail group reads up to 3 pairs past the end
+  int64_t* ac = c.take<int64_t>(na);
   int64_t* bk = c.take<int64_t>(nb);
   int64_t* bc = c.take<int64_t>(nb);
-  *a_tmpk = na > SORT_CHUNK ? c.take<int64_t>(na) : nullptr;
-  *a_tmpi = na > SORT_CHUNK ? c.take<int32_t>(na) : nullptr;
-  *b_tmpk = nb > SORT_CHUNK ? c.take<int64_t>(nb) : nullptr;
-  *b_tmpi = nb > SORT_CHUNK ? c.take<int32_t>(nb) : nullptr;
-  int64_t* wt = c.take<int64_t>(nwin * p.dp.ntiles);
-  int64_t* task_off = c.take<int64_t>(nwin + 1);
-  int32_t* pending = c.take<int32_t>(nwin);
-  int64_t* wcount = c.take<int64_t>(nwin);
-  int64_t* woff = c.take<int64_t>(nwin);
-  int64_t* dense = c.take<int64_t>(nwin * S);
-  int64_t* stage_k = c.take<int64_t>(nwin * S);
-  int64_t* stage_c = c.take<int64_t>(nwin * S);
+  int32_t* rank_a = c.take<int32_t>(na);
+  int32_t* rank_b = c.take<int32_t>(nb);
+  int32_t* bstart = c.take<int32_t>(d.nbkA + 1);
+  int64_t* tmin = c.take<int64_t>(d.ntiles);
+  int64_t* tmax = c.take<int64_t>(d.ntiles);
+  int64_t* wt = c.take<int64_t>(d.nwin * d.ntiles);
+  int64_t* task_off = c.take<int64_t>(d.nwin + 1);
+  int64_t* dense = c.take<int64_t>(d.nwin * d.S);
+  int64_t* stage_k = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
+  int64_t* stage_c = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
+  int64_t* ccount = c.take<int64_t>(d.nchunk);
+  int64_t* coff = c.take<int64_t>(d.nchunk);
   if (CARVE) {
     B->meta = meta;
     B->ak = ak;
-    B->apairs = apairs;
+    B->ac = ac;
     B->bk = bk;
     B->bc = bc;
-    B->na = na;
-    B->nb = nb;
+    B->rank_a = rank_a;
+    B->rank_b = rank_b;
+    B->bstart = bstart;
+    B->tmin = tmin;
+    B->tmax = tmax;
     B->wt = wt;
     B->task_off = task_off;
-    B->pending = pending;
-    B->wcount = wcount;
-    B->woff = woff;
     B->dense = dense;
     B->stage_k = stage_k;
     B->stage_c = stage_c;
+    B->ccount = ccount;
+    B->coff = coff;
+    B->na = na;
+    B->nb = nb;
   }
 }
 
@@ -204,8 +211,7 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   int64_t pairs = sat_mul(na, nb);
   int64_t contrib = poisson ? sat_mul(pairs, 2) : pairs;
   p->max_out = std::min(contrib, L->nkeys);
-  int64_t nwin = 0, ntiles = 0;
-  bool dense_ok = !poisson && dense_feasible(ctx, L, na, nb, &nwin, &ntiles);
+  bool dense_ok = !poisson && dense_feasible(ctx, L, na, nb);
   kp_mode m = mode;
   if (m == KP_AUTO) {
     double budget = ctx->tune.dense_keys_per_pair * (double)pairs;
@@ -217,15 +223,23 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   p->mode = m;
   Carver c;
   if (m == KP_DENSE) {
-    p->dp.S = ctx->tune.window;
-    p->dp.nwin = nwin;
-    p->dp.ntiles = ntiles;
-    p->dp.block = ctx->tune.block;
-    p->dp.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
-    p->dp.max_tasks = p->dp.target_tasks + nwin;
-    int64_t *a1, *b1;
-    int32_t *a2, *b2;
-    carve_dense<false>(c, *p, na, nb, nullptr, &a1, &a2, &b1, &b2);
+    DensePlan& d = p->dp;
+    d.S = ctx->tune.window;
+    d.nkeys = L->nkeys;
+    d.nwin = std::max<int64_t>(1, (L->nkeys + d.S - 1) / d.S);
+    d.nchunk = std::max<int64_t>(1, (L->nkeys + DENSE_CHUNK - 1) / DENSE_CHUNK);
+    d.ntiles = std::max<int64_t>(1, (nb + 63) / 64);
+    d.block = ctx->tune.block;
+    d.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
+    d.max_tasks = d.target_tasks + d.nwin;
+    d.min_work = 512;
+    d.maxcodeA = factor_maxcode(L, 0);
+    d.maxcodeB = factor_maxcode(L, 1);
+    d.shiftA = dense_bucket_shift(d.maxcodeA);
+    d.shiftB = dense_bucket_shift(d.maxcodeB);
+    d.nbkA = (d.maxcodeA >> d.shiftA) + 1;
+    d.nbkB = (d.maxcodeB >> d.shiftB) + 1;
+    carve_dense<false>(c, *p, na, nb, nullptr);
   } else {
     int64_t want;
     if (ctx->tune.hash_capacity > 0) {
@@ -301,10 +315,10 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->device = device;
   ctx->tune.window = 16384;
   ctx->tune.block = 1024;
-  ctx->tune.tasks_per_cu = 4;
+  ctx->tune.tasks_per_cu = 2;
   ctx->tune.hash_load = 0.5;
   ctx->tune.hash_capacity = 0;
-  ctx->tune.dense_max_keys = (int64_t)1 << 28;
+  ctx->tune.dense_max_keys = (int64_t)1 << 27;
   ctx->tune.dense_keys_per_pair = 64.0;
   ctx->tune.hash_rows = 64;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
@@ -378,9 +392,9 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
   if (!ctx || !t) return KP_E_ARG;
   if (t->block != 256 && t->block != 512 && t->block != 1024)
     return fail(ctx, KP_E_ARG, "block must be 256, 512 or 1024");
-  if (t->window < t->block || t->window % t->block != 0 ||
-      (int64_t)t->window * 8 + 1024 > 160 * 1024)
-    return fail(ctx, KP_E_ARG, "window must be a multiple of block and fit 159 KB of LDS");
+  if (t->window < DENSE_CHUNK || t->window % DENSE_CHUNK != 0 || t->window > DENSE_MAX_WINDOW)
+    return fail(ctx, KP_E_ARG, "window must be a multiple of %lld in [%lld, %lld]",
+                (long long)DENSE_CHUNK, (long long)DENSE_CHUNK, (long long)DENSE_MAX_WINDOW);
   if (t->tasks_per_cu < 1) return fail(ctx, KP_E_ARG, "tasks_per_cu must be >= 1");
   if (!(t->hash_load >= 0.05 && t->hash_load <= 0.9))
     return fail(ctx, KP_E_ARG, "hash_load must lie in [0.05, 0.9]");
@@ -533,25 +547,23 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
   const bool empty = na == 0 || nb == 0 || layout->nkeys == 0;
   if (p.mode == KP_DENSE) {
     DenseBufs B{};
-    int64_t *atk, *btk;
-    int32_t *ati, *bti;
-    carve_dense<true>(c, p, na, nb, &B, &atk, &ati, &btk, &bti);
+    carve_dense<true>(c, p, na, nb, &B);
+    B.a_keys_in = a_codes;
+    B.a_coef_in = (const int64_t*)a_coef;
+    B.b_keys_in = b_codes;
+    B.b_coef_in = (const int64_t*)b_coef;
     B.out_k = out_codes;
     B.out_c = out_coef;
     B.out_cap = out_cap;
-    if (!empty) std::tie(B.ev0, B.ev1) = timing_pair(ctx);
-    e = launch_meta_init(B.meta, stream);
+    B.out_n = out_n;
+    B.ctx_err = &ctx->status->err;
     if (!empty) {
-      if (e == hipSuccess && dtype == KP_I64)
-        e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, B.meta,
-                              stream);
-      SortSeg sa{a_codes, (const int64_t*)a_coef, na, B.ak, nullptr, B.apairs, atk, ati};
-      SortSeg sb{b_codes, (const int64_t*)b_coef, nb, B.bk, B.bc, nullptr,
-                 btk, bti};
-      if (e == hipSuccess) e = launch_sort2(sa, sb, stream);
-      if (e == hipSuccess) e = launch_dense_laurent(p.dp, B, dtype, stream);
+      std::tie(B.ev0, B.ev1) = timing_pair(ctx);
+      e = launch_dense_laurent(p.dp, B, dtype, stream);
+    } else {
+      e = launch_meta_init(B.meta, stream);
+      if (e == hipSuccess) e = launch_finalize(B.meta, out_cap, out_n, &ctx->status->err, stream);
     }
-    if (e == hipSuccess) e = launch_finalize(B.meta, out_cap, out_n, &ctx->status->err, stream);
   } else {
     HashCarve h;
     carve_hash(c, p, 0, na, nb, &h);

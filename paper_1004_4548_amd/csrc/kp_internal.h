@@ -142,11 +142,15 @@ __device__ inline uint32_t wave_and(uint32_t v) {
 
 // ------------------------------------------------------------ workspace meta
 struct Meta {
-  uint32_t err;         // latched error bits of this call
-  uint32_t narrow;      // bit0: all int64 coefficients fit int32; bit1: fit 24-bit signed
-  int64_t ntasks;       // dense: number of work items
-  int64_t out_count;    // number of result terms (before the capacity check)
-  int64_t pad[5];
+  uint32_t err;           // latched error bits of this call
+  uint32_t narrow;        // bit0: all int64 coefficients fit int32; bit1: fit 24-bit signed
+  int64_t ntasks;         // dense: number of windows
+  int64_t out_count;      // number of result terms (before the capacity check)
+  uint32_t seg_flags[2];  // dense: coefficient-range flags of factor A / B
+  uint32_t seg_err[2];    // dense: error bits found while sorting factor A / B
+  uint32_t plan_done;     // dense: planning workgroups finished
+  uint32_t pad32;
+  int64_t pad[2];
 };
 
 // Status block owned by a context (device memory, 256 bytes).
@@ -171,44 +175,46 @@ hipError_t launch_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint3
 hipError_t launch_coef_range(const int64_t* a, int64_t na, const int64_t* b, int64_t nb, Meta* m,
                              hipStream_t s);
 
-// sort: ascending by key, stable; two independent segments in one launch
-struct SortSeg {
-  const int64_t* keys;
-  const int64_t* vals;   // 8-byte payload (int64 or double bits)
-  int64_t n;
-  int64_t* out_keys;
-  int64_t* out_vals;
-  int64_t* out_pairs;    // optional AoS (key, val) output, may be null
-  int64_t* tmp_keys;     // n entries, used when n > one chunk
-  int32_t* tmp_idx;      // n entries
-};
-constexpr int SORT_CHUNK = 4096;
-size_t sort_tmp_bytes(int64_t n);
-hipError_t launch_sort2(const SortSeg& a, const SortSeg& b, hipStream_t s);
-
 // dense Laurent
+constexpr int64_t DENSE_MAX_BUCKETS = 32768;   // bucket-sort histogram slots (LDS)
+constexpr int DENSE_MAX_TILES_LDS = 1024;      // per-task tile list held in LDS
+constexpr int64_t DENSE_CHUNK = 2048;          // output segment (codes)
+constexpr int64_t DENSE_MAX_WINDOW = 16384;    // LDS slots of one window (8 bytes each)
+constexpr size_t DENSE_LDS_BYTES = DENSE_MAX_WINDOW * 8;
+int dense_bucket_shift(int64_t maxcode);
+
 struct DensePlan {
-  int64_t S;             // window size (codes)
-  int64_t nwin;
+  int64_t S;             // window (codes), a multiple of DENSE_CHUNK
+  int64_t nwin;          // ceil(nkeys / S)
   int64_t ntiles;        // ceil(nb / 64)
-  int64_t max_tasks;
-  int64_t target_tasks;
+  int64_t nkeys;
+  int64_t nchunk;        // ceil(nkeys / DENSE_CHUNK)
+  int64_t target_tasks;  // tasks wanted (compute units x tasks per unit)
+  int64_t max_tasks;     // upper bound on tasks: target + nwin
+  int64_t min_work;      // row visits below which a window is not split
+  int shiftA, shiftB;    // bucket widths 2^shift of the factor sorts
+  int64_t nbkA, nbkB;    // buckets
+  int64_t maxcodeA, maxcodeB;   // largest code of each factor's box
   int32_t block;
 };
 struct DenseBufs {
   Meta* meta;
-  int64_t* ak; int64_t* apairs;   // sorted A: keys, (key, coef) pairs
-  int64_t* bk; int64_t* bc;       // sorted B: keys, coefs
+  const int64_t* a_keys_in; const int64_t* a_coef_in;
+  const int64_t* b_keys_in; const int64_t* b_coef_in;
   int64_t na, nb;
-  int64_t* wt;           // [nwin * ntiles] inclusive work prefix per window
-  int64_t* task_off;     // [nwin + 1]
-  int32_t* pending;      // [nwin]
-  int64_t* wcount;       // [nwin] terms per window
-  int64_t* woff;         // [nwin] output offset per window
-  int64_t* dense;        // [nwin * S] accumulator for windows shared by several tasks
-  int64_t* stage_k;      // [nwin * S]
-  int64_t* stage_c;      // [nwin * S]
-  int64_t* out_k; void* out_c; int64_t out_cap;
+  int64_t* ak; int64_t* ac;     // A bucket-sorted
+  int64_t* bk; int64_t* bc;     // B bucket-sorted
+  int32_t* rank_a; int32_t* rank_b;
+  int32_t* bstart;              // [nbkA + 1] first row of each bucket of A
+  int64_t* tmin; int64_t* tmax; // [ntiles] code range of each tile of B
+  int64_t* wt;                  // [nwin * ntiles] inclusive row-visit prefix per window
+  int64_t* task_off;            // [nwin + 1] first task of each window
+  int64_t* dense;               // [nwin * S] accumulator of windows split across tasks
+  int64_t* stage_k; int64_t* stage_c;   // [nchunk * DENSE_CHUNK] compacted chunks
+  int64_t* ccount;              // [nchunk] terms per chunk
+  int64_t* coff;                // [nchunk] output offset per chunk
+  int64_t* out_k; void* out_c; int64_t out_cap; int64_t* out_n;
+  uint32_t* ctx_err;
   hipEvent_t ev0, ev1;   // optional: recorded around the window kernel
 };
 hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s);

@@ -176,12 +176,13 @@ def test_laurent_ragged_sizes(na, nb):
         check_laurent(a, b, mode, f"ragged {na} x {nb} (duplicates allowed)")
 
 
-def test_laurent_many_windows_and_shared_windows():
-    # small windows and many tasks per CU force several windows per product
-    # and windows split across workgroups (combined through HBM atomics)
+def test_laurent_many_windows_and_split_windows():
+    # small windows and many tasks per CU: many windows per product, busy
+    # windows split into several tasks whose partial windows are combined
     ctx = kp.context()
     a, b = I.config(2, scale=0.3)
-    for window, block, tpc in ((1024, 256, 64), (2048, 512, 16), (19456, 1024, 8)):
+    for window, block, tpc in ((2048, 256, 64), (4096, 512, 16), (16384, 1024, 8),
+                               (16384, 1024, 1)):
         ctx.set_tune(window=window, block=block, tasks_per_cu=tpc)
         check_laurent(a, b, "dense", f"window {window} block {block} tasks/CU {tpc}")
         a64 = (a[0], a[1].astype(np.float64) / 4)
