@@ -32,6 +32,28 @@ HBM_PEAK_GBS = 8000.0
 LDS_ATOMIC_PEAK = CUS * 16 * CLOCK_HZ          # pair accumulations per second
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_dense_mul_moderately_sparse_10k.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dense window kernel from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None once the kernel source differs
+    from the one the counters were taken on."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PROFILE):
+            if " = " in line:
+                k, v = line.strip().split(" = ", 1)
+                kv[k] = v
+        src = open(os.path.join(ROOT, kv["kernel_source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != kv["kernel_source_sha256"]:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +63,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (sparse, Poisson, small)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run device-to-device copies of 256 MiB (a plain copy kernel of "
+                         "known size, used to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -153,7 +178,8 @@ def main():
     roof = {"bound": "alu", "kernel": "k_dense_mul (LDS window accumulation)",
             "achieved": kernel_rate / 1e12, "peak": LDS_ATOMIC_PEAK / 1e12,
             "unit": "Tacc/s (one 64-bit LDS accumulate per term product)",
-            "frac": kernel_rate / LDS_ATOMIC_PEAK, "traffic": None,
+            "frac": kernel_rate / LDS_ATOMIC_PEAK, "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel_ms": r["kernel_s"] * 1e3, "units_per_launch": pairs}
     out = {
         "metric": "term-products/sec", "value": value, "unit": "term-products/s",
@@ -193,6 +219,14 @@ def main():
                                       "result_terms": r4["n_out"],
                                       "insert_kernel_ms": r4["kernel_s"] * 1e3}
         out["other_workloads"] = extra
+    if args.calibrate_copy:
+        n = 256 << 20
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_seconds)
     print(json.dumps(out), flush=True)

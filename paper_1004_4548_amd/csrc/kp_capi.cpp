@@ -56,12 +56,6 @@ int64_t sat_mul(int64_t a, int64_t b) {
   return r;
 }
 
-uint32_t log2_ceil(uint64_t x) {
-  uint32_t l = 0;
-  while (l < 63 && (1ull << l) < x) ++l;
-  return l;
-}
-
 // Synchronise, read and clear the context's latched device status.
 kp_status sync_status(kp_ctx* ctx, hipStream_t s) {
   hipError_t e = hipStreamSynchronize(s);
@@ -116,7 +110,7 @@ struct Plan {
   // dense
   DensePlan dp{};
   // hash
-  int64_t cap_log2 = 6;
+  int64_t cap = 64;
 };
 
 int64_t factor_maxcode(const kp_layout* L, int which) {
@@ -185,7 +179,7 @@ struct HashCarve {
 
 void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, HashCarve* h) {
   h->meta = c.take<Meta>(1);
-  h->table = c.take<uint64_t>((size_t)2 << p.cap_log2);
+  h->table = c.take<uint64_t>((size_t)2 * p.cap);
   h->pp = PoissonPrep{};
   if (poisson) {
     h->pp.ap = c.take<int64_t>(na);
@@ -248,9 +242,9 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
       double w = (double)std::max<int64_t>(p->max_out, 1) / ctx->tune.hash_load;
       want = w > 4.0e18 ? INT64_MAX : (int64_t)w + 1;
     }
-    p->cap_log2 = std::max<uint32_t>(6, log2_ceil((uint64_t)want));
-    if (p->cap_log2 > 40) return fail(ctx, KP_E_CAPACITY, "hash table would need 2^%lld slots",
-                                     (long long)p->cap_log2);
+    p->cap = std::max<int64_t>(64, want);
+    if (p->cap > ((int64_t)1 << 40))
+      return fail(ctx, KP_E_CAPACITY, "hash table would need %lld slots", (long long)p->cap);
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
   }
@@ -567,7 +561,7 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
   } else {
     HashCarve h;
     carve_hash(c, p, 0, na, nb, &h);
-    HashBufs H{h.meta, h.table, p.cap_log2, (int64_t)1 << p.cap_log2, out_codes, out_coef, out_cap,
+    HashBufs H{h.meta, h.table, p.cap, p.cap, out_codes, out_coef, out_cap,
                nullptr, nullptr};
     if (!empty) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
@@ -575,7 +569,7 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
                               stream);
-      if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 << p.cap_log2, stream);
+      if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * p.cap, stream);
       if (e == hipSuccess)
         e = launch_hash_laurent(H, dtype, a_codes, a_coef, na, b_codes, b_coef, nb,
                                 ctx->tune.hash_rows, stream);
@@ -609,12 +603,12 @@ kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, uns
   c.base = static_cast<char*>(workspace);
   HashCarve h;
   carve_hash(c, p, 1, na, nb, &h);
-  HashBufs H{h.meta, h.table, p.cap_log2, (int64_t)1 << p.cap_log2, out_keys, out_coef, out_cap,
+  HashBufs H{h.meta, h.table, p.cap, p.cap, out_keys, out_coef, out_cap,
              nullptr, nullptr};
   hipError_t e = launch_meta_init(h.meta, stream);
   if (na > 0 && nb > 0 && layout->nkeys > 0) {
     std::tie(H.ev0, H.ev1) = timing_pair(ctx);
-    if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 << p.cap_log2, stream);
+    if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * p.cap, stream);
     if (e == hipSuccess)
       e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream);
     if (e == hipSuccess)

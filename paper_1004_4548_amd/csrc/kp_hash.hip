@@ -33,23 +33,33 @@ namespace {
 constexpr int HASH_BLOCK = 256;
 constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;   // 2^64 / golden ratio (Fibonacci hashing)
 
-__device__ inline void slot_add(uint64_t* c, int64_t v) {
+__device__ __forceinline__ void slot_add(uint64_t* c, int64_t v) {
   atomicAdd((unsigned long long*)c, (unsigned long long)v);
 }
-__device__ inline void slot_add(uint64_t* c, double v) {
+__device__ __forceinline__ void slot_add(uint64_t* c, double v) {
   unsafeAtomicAdd(reinterpret_cast<double*>(c), v);
 }
 
-// Insert-or-accumulate.  Linear probing from the hash of `code`; at most
-// max_probe slots are visited before the table is declared full.
+__device__ __forceinline__ uint64_t home_slot(int64_t code, uint64_t cap) {
+  // multiplicative hash, then mapped onto [0, cap) by a high multiply
+  return __umul64hi((uint64_t)code * GOLDEN, cap);
+}
+
+__device__ __forceinline__ uint64_t key_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Probe from slot s (whose key word read `cur`) until the key is found or
+// claimed; at most max_probe slots are visited before the table is declared
+// full.  An occupied slot is skipped after a plain (atomic) load; only an
+// empty slot costs a compare-and-swap.
 template <typename T>
-__device__ inline void table_insert(uint64_t* __restrict__ table, uint64_t mask, int shift,
-                                    int64_t max_probe, int64_t code, T v, uint32_t* err) {
-  const uint64_t key = (uint64_t)code + 1;
-  uint64_t s = ((uint64_t)code * GOLDEN) >> shift;
+__device__ __noinline__ void table_probe(uint64_t* __restrict__ table, uint64_t cap,
+                                         int64_t max_probe, uint64_t s, uint64_t cur, uint64_t key,
+                                         T v, uint32_t* err) {
   for (int64_t p = 0; p < max_probe; ++p) {
     uint64_t* ks = table + 2 * s;
-    uint64_t cur = __hip_atomic_load(ks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p > 0) cur = key_load(ks);
     if (cur == 0) {
       cur = atomicCAS((unsigned long long*)ks, 0ull, (unsigned long long)key);
       if (cur == 0) cur = key;
@@ -58,9 +68,37 @@ __device__ inline void table_insert(uint64_t* __restrict__ table, uint64_t mask,
       slot_add(ks + 1, v);
       return;
     }
-    s = (s + 1) & mask;
+    s = s + 1 == cap ? 0 : s + 1;
   }
   atomicOr(err, ERR_CAPACITY);
+}
+
+// Insert-or-accumulate of NB independent contributions.  The key words of
+// their home slots are read first, all NB loads in flight together; a slot
+// holding the key gets the coefficient added atomically, an empty one is
+// claimed by compare-and-swap (0 = empty, otherwise code + 1), anything
+// else continues probing linearly.  Concurrent insertions of one code
+// combine in any order because the coefficient word only ever receives
+// atomic adds.
+template <typename T, int NB>
+__device__ __forceinline__ void table_insert_n(uint64_t* __restrict__ table, uint64_t cap,
+                                               int64_t max_probe, const int64_t* code,
+                                               const T* v, const bool* on, uint32_t* err) {
+  uint64_t s[NB], cur[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    s[u] = home_slot(code[u], cap);
+    cur[u] = on[u] ? key_load(table + 2 * s[u]) : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if (!on[u]) continue;
+    const uint64_t key = (uint64_t)code[u] + 1;
+    if (cur[u] == key)
+      slot_add(table + 2 * s[u] + 1, v[u]);
+    else
+      table_probe<T>(table, cap, max_probe, s[u], cur[u], key, v[u], err);
+  }
 }
 
 template <typename T>
@@ -80,12 +118,14 @@ __device__ inline double mul_coef<double>(double a, double b, uint32_t) {
 }
 
 // Thread = one term of B (in registers); loops over a slice of A's rows,
-// whose code and coefficient are wavefront-uniform (scalar loads).
+// whose code and coefficient are wavefront-uniform (scalar loads), four rows
+// per round so that four insertions are in flight.
 template <typename T>
 __global__ void __launch_bounds__(HASH_BLOCK)
-k_hash_laurent(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t max_probe,
-               Meta* meta, const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
+k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Meta* meta,
+               const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
                const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows) {
+  constexpr int NB = 4;
   const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows;
   const int64_t i1 = min(i0 + rows, na);
@@ -93,9 +133,19 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t m
   if (j >= nb) return;
   const int64_t bj = bk[j];
   const T cb = bc[j];
-  for (int64_t i = i0; i < i1; ++i) {
-    const T v = mul_coef<T>(ac[i], cb, narrow);
-    if (v != T(0)) table_insert<T>(table, mask, shift, max_probe, ak[i] + bj, v, &meta->err);
+  for (int64_t i = i0; i < i1; i += NB) {
+    int64_t code[NB];
+    T v[NB];
+    bool on[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const bool in = i + u < i1;
+      const int64_t r = in ? i + u : i;
+      v[u] = mul_coef<T>(ac[r], cb, narrow);
+      code[u] = ak[r] + bj;
+      on[u] = in && v[u] != T(0);
+    }
+    table_insert_n<T, NB>(table, cap, max_probe, code, v, on, &meta->err);
   }
 }
 
@@ -118,29 +168,31 @@ k_poisson_prep(int64_t Wx, const int64_t* __restrict__ ax, const int64_t* __rest
   }
 }
 
-__device__ inline void poisson_piece(uint64_t* table, uint64_t mask, int shift, int64_t max_probe,
-                                     int64_t Wx, int64_t K, int64_t kx, int t, double v,
-                                     uint32_t* err) {
+// Key and signed value of one piece; false when the piece vanishes.
+__device__ __forceinline__ bool poisson_piece(int64_t Wx, int64_t K, int64_t kx, int t, double v,
+                                              int64_t* key, double* val) {
   int64_t pos = K;
   if (K < 0) {                 // ky < 0: fold to |ky|, sin(-a) = -sin(a)
     pos = 2 * kx - K;
     if (t) v = -v;
   } else if (t && K < Wx) {    // sin of the zero multiplier vector vanishes
-    return;
+    return false;
   }
-  table_insert<double>(table, mask, shift, max_probe, 2 * pos + t, v, err);
+  *key = 2 * pos + t;
+  *val = v;
+  return true;
 }
 
 // Thread = one term of B; every pair yields the difference piece (sign -1 for
-// cos*sin) and the sum piece (sign -1 for sin*sin), each 1/2 ca cb.
+// cos*sin) and the sum piece (sign -1 for sin*sin), each 1/2 ca cb.  Two
+// pairs per round: four insertions in flight.
 __global__ void __launch_bounds__(HASH_BLOCK)
-k_hash_poisson(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t max_probe,
-               Meta* meta, int64_t Wx, const int64_t* __restrict__ ap,
-               const int64_t* __restrict__ akx, const uint8_t* __restrict__ at,
-               const double* __restrict__ ac, int64_t na, const int64_t* __restrict__ bp,
-               const int64_t* __restrict__ bm, const int64_t* __restrict__ bkx,
-               const uint8_t* __restrict__ bt, const double* __restrict__ bc, int64_t nb,
-               int rows) {
+k_hash_poisson(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Meta* meta,
+               int64_t Wx, const int64_t* __restrict__ ap, const int64_t* __restrict__ akx,
+               const uint8_t* __restrict__ at, const double* __restrict__ ac, int64_t na,
+               const int64_t* __restrict__ bp, const int64_t* __restrict__ bm,
+               const int64_t* __restrict__ bkx, const uint8_t* __restrict__ bt,
+               const double* __restrict__ bc, int64_t nb, int rows) {
   const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows;
   const int64_t i1 = min(i0 + rows, na);
@@ -148,16 +200,27 @@ k_hash_poisson(uint64_t* __restrict__ table, uint64_t mask, int shift, int64_t m
   const int64_t Bp = bp[j], Bm = bm[j], kxb = bkx[j];
   const int tb = bt[j];
   const double cb = bc[j];
-  for (int64_t i = i0; i < i1; ++i) {
-    const int ta = at[i];
-    const double h = 0.5 * (ac[i] * cb);
-    if (h == 0.0) continue;
-    const int64_t kx = akx[i] + kxb;
-    const int t = ta ^ tb;
-    const double sm = (!ta && tb) ? -h : h;   // cos a sin b: -1/2 sin(a - b)
-    const double sp = (ta && tb) ? -h : h;    // sin a sin b: -1/2 cos(a + b)
-    poisson_piece(table, mask, shift, max_probe, Wx, ap[i] + Bm, kx, t, sm, &meta->err);
-    poisson_piece(table, mask, shift, max_probe, Wx, ap[i] + Bp, kx, t, sp, &meta->err);
+  for (int64_t i = i0; i < i1; i += 2) {
+    int64_t code[4];
+    double v[4];
+    bool on[4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool in = i + u < i1;
+      const int64_t r = in ? i + u : i;
+      const int ta = at[r];
+      const double h = 0.5 * (ac[r] * cb);
+      const int64_t kx = akx[r] + kxb;
+      const int t = ta ^ tb;
+      const double sm = (!ta && tb) ? -h : h;   // cos a sin b: -1/2 sin(a - b)
+      const double sp = (ta && tb) ? -h : h;    // sin a sin b: -1/2 cos(a + b)
+      on[2 * u] = in && h != 0.0 && poisson_piece(Wx, ap[r] + Bm, kx, t, sm, &code[2 * u], &v[2 * u]);
+      on[2 * u + 1] =
+          in && h != 0.0 && poisson_piece(Wx, ap[r] + Bp, kx, t, sp, &code[2 * u + 1], &v[2 * u + 1]);
+      if (!on[2 * u]) code[2 * u] = 0;
+      if (!on[2 * u + 1]) code[2 * u + 1] = 0;
+    }
+    table_insert_n<double, 4>(table, cap, max_probe, code, v, on, &meta->err);
   }
 }
 
@@ -229,18 +292,16 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
                                int64_t na, const int64_t* bk, const void* bc, int64_t nb,
                                int rows, hipStream_t s) {
   if (rows < 1) rows = 1;
-  const uint64_t mask = (1ull << H.cap_log2) - 1;
-  const int shift = 64 - (int)H.cap_log2;
   dim3 grid((unsigned)((nb + HASH_BLOCK - 1) / HASH_BLOCK), (unsigned)((na + rows - 1) / rows));
   if (H.ev0) (void)hipEventRecord(H.ev0, s);
   if (dt == KP_F64)
-    hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
-                       H.max_probe, H.meta, ak, (const double*)ac, na, bk, (const double*)bc, nb,
-                       rows);
+    hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table,
+                       (uint64_t)H.cap, H.max_probe, H.meta, ak, (const double*)ac, na, bk,
+                       (const double*)bc, nb, rows);
   else
-    hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
-                       H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk, (const int64_t*)bc,
-                       nb, rows);
+    hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table,
+                       (uint64_t)H.cap, H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk,
+                       (const int64_t*)bc, nb, rows);
   if (H.ev1) (void)hipEventRecord(H.ev1, s);
   return hipGetLastError();
 }
@@ -259,11 +320,9 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
                                const double* ac, int64_t na, const double* bc, int64_t nb,
                                int rows, hipStream_t s) {
   if (rows < 1) rows = 1;
-  const uint64_t mask = (1ull << H.cap_log2) - 1;
-  const int shift = 64 - (int)H.cap_log2;
   dim3 grid((unsigned)((nb + HASH_BLOCK - 1) / HASH_BLOCK), (unsigned)((na + rows - 1) / rows));
   if (H.ev0) (void)hipEventRecord(H.ev0, s);
-  hipLaunchKernelGGL(k_hash_poisson, grid, dim3(HASH_BLOCK), 0, s, H.table, mask, shift,
+  hipLaunchKernelGGL(k_hash_poisson, grid, dim3(HASH_BLOCK), 0, s, H.table, (uint64_t)H.cap,
                      H.max_probe, H.meta, Wx, P.ap, P.akx, P.at, ac, na, P.bp, P.bm, P.bkx, P.bt,
                      bc, nb, rows);
   if (H.ev1) (void)hipEventRecord(H.ev1, s);
@@ -271,7 +330,7 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
 }
 
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s) {
-  const int64_t cap = 1ll << H.cap_log2;
+  const int64_t cap = H.cap;
   const int64_t chunk = (int64_t)HASH_BLOCK * COMPACT_PER;
   int64_t blocks = (cap + chunk - 1) / chunk;
   if (blocks > 8192) blocks = 8192;

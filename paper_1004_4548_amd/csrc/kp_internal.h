@@ -222,8 +222,8 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
 // hash Laurent / Poisson
 struct HashBufs {
   Meta* meta;
-  uint64_t* table;       // capacity * 2 words: (key + 1, coef bits)
-  int64_t cap_log2;
+  uint64_t* table;       // cap * 2 words: (key + 1, coef bits)
+  int64_t cap;           // slots (>= 64)
   int64_t max_probe;
   int64_t* out_k; void* out_c; int64_t out_cap;
   hipEvent_t ev0, ev1;   // optional: recorded around the insert kernel
