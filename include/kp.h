@@ -22,8 +22,12 @@
  *  - Without KP_FLAG_ASYNC a call synchronises its stream once and reports
  *    device-detected errors (range, capacity) in its return value.  With it,
  *    the call returns after queuing; device errors are latched in the
- *    context's status block (read by kp_ctx_check) and, for multiplies, the
- *    device count *out_n is set to -(status) instead of the term count.
+ *    context's status block (read and cleared by kp_ctx_check) and, for
+ *    multiplies, the device count *out_n is set to -(status) instead of the
+ *    term count.  A multiply also reports, through *out_n, an error that an
+ *    earlier asynchronous call on the same context latched and that has not
+ *    been cleared (for example an exponent outside the box in kp_encode), so
+ *    encode + multiply can be queued with one synchronisation at the end.
  *  - Host-detectable errors (bad arguments, layout overflow, workspace too
  *    small) return before anything is queued.
  *  - Exponent arrays are row-major int32 [n][nvars].
@@ -109,12 +113,13 @@ typedef struct kp_layout {
 /* Tuning knobs (the paper leaves block size, table size and the density
    criterion unspecified).  None of them changes a result. */
 typedef struct kp_tune {
-  int32_t window;           /* dense: output codes per workgroup window (<= 20480)   */
+  int32_t window;           /* dense: output codes per LDS window, a multiple of 2048
+                               up to 18432 (default 18432)                           */
   int32_t block;            /* dense: threads per workgroup (256, 512 or 1024)       */
-  int32_t tasks_per_cu;     /* dense: target work items per compute unit             */
+  int32_t tasks_per_cu;     /* dense: equal-cost tasks per compute unit (default 1)  */
   double hash_load;         /* hash: target load factor (0.05 .. 0.9)                */
   int64_t hash_capacity;    /* hash: forced slot count (0 = from the bound)          */
-  int64_t dense_max_keys;   /* auto mode: dense only if nkeys <= this                */
+  int64_t dense_max_keys;   /* dense only if nkeys <= this (at most 2^27)            */
   double dense_keys_per_pair; /* auto mode: dense only if nkeys <= this * na * nb    */
   int32_t hash_rows;        /* hash: factor-A rows per thread                        */
 } kp_tune;

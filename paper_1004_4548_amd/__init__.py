@@ -244,13 +244,15 @@ def _dev_check(t, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def minmax(vals, ctx=None, flags=0):
-    """kp_minmax: per-column (min, max) of an int32 [n, nv] device tensor."""
+def minmax(vals, ctx=None, flags=0, out=None):
+    """kp_minmax: per-column (min, max) of an int32 [n, nv] device tensor
+    (into `out`, 2 * nv int32, when given)."""
     import torch
     ctx = ctx or context()
     _dev_check(vals, torch.int32, "vals")
     n, nv = vals.shape
-    out = torch.empty(2 * nv, dtype=torch.int32, device=vals.device)
+    if out is None:
+        out = torch.empty(2 * nv, dtype=torch.int32, device=vals.device)
     ctx.check(lib().kp_minmax(ctx.h, n, nv, _ptr(vals), _ptr(out), flags, _stream()))
     return out
 
@@ -348,14 +350,25 @@ def mul_laurent_codes(layout, a_codes, a_coef, b_codes, b_coef, mode="auto", ctx
         oc, ov, on = out
     wbuf = (workspace or Workspace()).get(ws, dev)
     st = lib().kp_mul_laurent(ctx.h, C.byref(layout), dt, MODES[mode] if isinstance(mode, str)
-                              else mode, flags, _ptr(a_codes), _ptr(a_coef), na, _ptr(b_codes),
-                              _ptr(b_coef), nb, _ptr(oc), _ptr(ov), oc.shape[0], _ptr(on),
-                              _ptr(wbuf), wbuf.numel(), _stream())
+                              else mode, flags | KP_FLAG_ASYNC, _ptr(a_codes), _ptr(a_coef), na,
+                              _ptr(b_codes), _ptr(b_coef), nb, _ptr(oc), _ptr(ov), oc.shape[0],
+                              _ptr(on), _ptr(wbuf), wbuf.numel(), _stream())
     ctx.check(st)
     if flags & KP_FLAG_ASYNC:
         return oc, ov, on
-    n = int(on.item())
+    n = _count(ctx, on)
     return oc[:n], ov[:n], on
+
+
+def _count(ctx, on):
+    """Result count of an asynchronous multiply: one synchronising read.  A
+    negative count is -(status); the context's latched error is then read
+    (and cleared) for the message."""
+    n = int(on.item())
+    if n < 0:
+        ctx.sync_check()
+        raise KPError(-n, status_str(-n))
+    return n
 
 
 def mul_poisson_codes(layout, a, b, mode="auto", ctx=None, workspace=None, out=None, flags=0):
@@ -381,13 +394,13 @@ def mul_poisson_codes(layout, a, b, mode="auto", ctx=None, workspace=None, out=N
         ok, ov, on = out
     wbuf = (workspace or Workspace()).get(ws, dev)
     st = lib().kp_mul_poisson(ctx.h, C.byref(layout), MODES[mode] if isinstance(mode, str)
-                              else mode, flags, _ptr(ax), _ptr(ay), _ptr(at), _ptr(ac), na,
+                              else mode, flags | KP_FLAG_ASYNC, _ptr(ax), _ptr(ay), _ptr(at), _ptr(ac), na,
                               _ptr(bx), _ptr(by), _ptr(bt), _ptr(bc), nb, _ptr(ok), _ptr(ov),
                               ok.shape[0], _ptr(on), _ptr(wbuf), wbuf.numel(), _stream())
     ctx.check(st)
     if flags & KP_FLAG_ASYNC:
         return ok, ov, on
-    n = int(on.item())
+    n = _count(ctx, on)
     return ok[:n], ov[:n], on
 
 
@@ -413,18 +426,27 @@ class PoissonSeries:
     coef: "object"
 
 
-def _boxes(vals, ctx):
-    mm = minmax(vals, ctx).cpu().tolist()
-    nv = vals.shape[1]
-    return mm[:nv], mm[nv:]
+def _boxes(ctx, *vals):
+    """(min, max) lists of every int32 [n, nv] tensor, with one host read."""
+    import torch
+    widths = [v.shape[1] for v in vals]
+    out = torch.empty(max(1, 2 * sum(widths)), dtype=torch.int32, device=vals[0].device)
+    off = 0
+    for v, nv in zip(vals, widths):
+        minmax(v, ctx, KP_FLAG_ASYNC, out[off:off + 2 * nv])
+        off += 2 * nv
+    mm = out.cpu().tolist()
+    res, off = [], 0
+    for nv in widths:
+        res.append((mm[off:off + nv], mm[off + nv:off + 2 * nv]))
+        off += 2 * nv
+    return res
 
 
 def laurent_layout(a: Poly, b: Poly, ctx=None) -> Layout:
     ctx = ctx or context()
-    nv = a.nv
-    amin, amax = _boxes(a.exps, ctx)
-    bmin, bmax = _boxes(b.exps, ctx)
-    return layout_product(nv, 0, amin, amax, bmin, bmax)
+    (amin, amax), (bmin, bmax) = _boxes(ctx, a.exps, b.exps)
+    return layout_product(a.nv, 0, amin, amax, bmin, bmax)
 
 
 def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
@@ -433,18 +455,17 @@ def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
     if a.nv != b.nv:
         raise ValueError("factors must have the same number of variables")
     lay = laurent_layout(a, b, ctx)
-    ka, _ = encode(lay, 0, a.exps, ctx=ctx)
-    kb, _ = encode(lay, 1, b.exps, ctx=ctx)
+    # encode errors latch on the context and surface in the multiply's count
+    ka, _ = encode(lay, 0, a.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
+    kb, _ = encode(lay, 1, b.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
     codes, coef, _ = mul_laurent_codes(lay, ka, a.coef, kb, b.coef, mode, ctx, workspace)
-    return Poly(decode(lay, codes, ctx=ctx), coef), lay
+    return Poly(decode(lay, codes, ctx=ctx, flags=KP_FLAG_ASYNC), coef), lay
 
 
 def poisson_layout(a: PoissonSeries, b: PoissonSeries, ctx=None) -> Layout:
     ctx = ctx or context()
     nx, ny = a.x.shape[1], a.y.shape[1]
-    amin, amax = _boxes(a.x, ctx)
-    bmin, bmax = _boxes(b.x, ctx)
-    ya, yb = _boxes(a.y, ctx), _boxes(b.y, ctx)
+    (amin, amax), (bmin, bmax), ya, yb = _boxes(ctx, a.x, b.x, a.y, b.y)
     ha = [max(-lo, hi, 0) for lo, hi in zip(*ya)]
     hb = [max(-lo, hi, 0) for lo, hi in zip(*yb)]
     return layout_product(nx, ny, amin, amax, bmin, bmax, ha, hb)
@@ -454,9 +475,9 @@ def mul_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, works
     """A * B for device-resident canonical Poisson series; returns (series, Layout)."""
     ctx = ctx or context()
     lay = poisson_layout(a, b, ctx)
-    kxa, kya = encode(lay, 0, a.x, a.y, a.is_sin, ctx=ctx)
-    kxb, kyb = encode(lay, 1, b.x, b.y, b.is_sin, ctx=ctx)
+    kxa, kya = encode(lay, 0, a.x, a.y, a.is_sin, ctx=ctx, flags=KP_FLAG_ASYNC)
+    kxb, kyb = encode(lay, 1, b.x, b.y, b.is_sin, ctx=ctx, flags=KP_FLAG_ASYNC)
     keys, coef, _ = mul_poisson_codes(lay, (kxa, kya, a.is_sin, a.coef),
                                       (kxb, kyb, b.is_sin, b.coef), mode, ctx, workspace)
-    x, y, t = decode(lay, keys, poisson=True, ctx=ctx)
+    x, y, t = decode(lay, keys, poisson=True, ctx=ctx, flags=KP_FLAG_ASYNC)
     return PoissonSeries(x, y, t, coef), lay

@@ -120,11 +120,27 @@ int64_t factor_maxcode(const kp_layout* L, int which) {
   return m;
 }
 
+// Work items of a dense product are at most ceil(rows / 64) + 3 per
+// (window, tile) pair.  A row of A is visited by a tile in the windows that
+// meet an interval of (bucket width of A + tile span + S) codes, at most
+// (bwA + span) / S + 2 of them, and the tiles' spans add up to at most
+// (buckets of B + tiles) * bucket width of B, B being sorted by bucket.
+double dense_items_bound(const DensePlan& d, int64_t na) {
+  const double bwA = (double)((int64_t)1 << d.shiftA), bwB = (double)((int64_t)1 << d.shiftB);
+  const double nt = (double)d.ntiles, S = (double)d.S;
+  double rows = (double)na * ((nt * bwA + ((double)d.nbkB + nt) * bwB) / S + 2.0 * nt);
+  rows = std::min(rows, (double)na * nt * (double)d.nwin);
+  const double pairs = std::min((double)d.nwin * nt, nt * (((double)d.maxcodeA + bwA) / S + 2.0) +
+                                                         ((double)d.nbkB + nt) * bwB / S);
+  return rows / DENSE_ITEM_ROWS + 3.0 * pairs + 64.0;
+}
+
 bool dense_feasible(const kp_ctx* ctx, const kp_layout* L, int64_t na, int64_t nb) {
   const int64_t S = ctx->tune.window;
-  if (L->nkeys > ctx->tune.dense_max_keys) return false;
-  if (sat_mul((L->nkeys + S - 1) / S, (nb + 63) / 64) > ((int64_t)1 << 26)) return false;
-  if (na >= ((int64_t)1 << 31) || nb >= ((int64_t)1 << 31)) return false;
+  if (L->nkeys > ctx->tune.dense_max_keys || L->nkeys > DENSE_MAX_CODES) return false;
+  if (sat_mul((L->nkeys + S - 1) / S, (nb + DENSE_TILE - 1) / DENSE_TILE) > ((int64_t)1 << 24))
+    return false;
+  if (na >= ((int64_t)1 << 31) || nb >= ((int64_t)1 << 29)) return false;
   return true;
 }
 
@@ -132,17 +148,21 @@ template <bool CARVE>
 void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B) {
   const DensePlan& d = p.dp;
   Meta* meta = c.take<Meta>(1);
-  int64_t* ak = c.take<int64_t>(na);
-  int64_t* ac = c.take<int64_t>(na);
-  int64_t* bk = c.take<int64_t>(nb);
-  int64_t* bc = c.take<int64_t>(nb);
+  uint64_t* apk = c.take<uint64_t>(na);
+  uint64_t* ac = c.take<uint64_t>(na);
+  uint64_t* bpk = c.take<uint64_t>(nb);
+  uint64_t* bc = c.take<uint64_t>(nb);
   int32_t* rank_a = c.take<int32_t>(na);
   int32_t* rank_b = c.take<int32_t>(nb);
   int32_t* bstart = c.take<int32_t>(d.nbkA + 1);
+  int32_t* bstartB = c.take<int32_t>(d.nbkB + 1);
   int64_t* tmin = c.take<int64_t>(d.ntiles);
   int64_t* tmax = c.take<int64_t>(d.ntiles);
-  int64_t* wt = c.take<int64_t>(d.nwin * d.ntiles);
-  int64_t* task_off = c.take<int64_t>(d.nwin + 1);
+  int64_t* win = c.take<int64_t>(5 * (d.nwin + 1));
+  int4* recs = c.take<int4>(d.nwin * d.ntiles);
+  uint64_t* items = c.take<uint64_t>(d.items_cap);
+  int32_t* task_w = c.take<int32_t>(d.max_tasks);
+  int32_t* task_begin = c.take<int32_t>(d.max_tasks + 1);
   int64_t* dense = c.take<int64_t>(d.nwin * d.S);
   int64_t* stage_k = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
   int64_t* stage_c = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
@@ -150,17 +170,21 @@ void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B)
   int64_t* coff = c.take<int64_t>(d.nchunk);
   if (CARVE) {
     B->meta = meta;
-    B->ak = ak;
+    B->apk = apk;
     B->ac = ac;
-    B->bk = bk;
+    B->bpk = bpk;
     B->bc = bc;
     B->rank_a = rank_a;
     B->rank_b = rank_b;
     B->bstart = bstart;
+    B->bstartB = bstartB;
     B->tmin = tmin;
     B->tmax = tmax;
-    B->wt = wt;
-    B->task_off = task_off;
+    B->win = win;
+    B->recs = recs;
+    B->items = items;
+    B->task_w = task_w;
+    B->task_begin = task_begin;
     B->dense = dense;
     B->stage_k = stage_k;
     B->stage_c = stage_c;
@@ -206,33 +230,40 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   int64_t contrib = poisson ? sat_mul(pairs, 2) : pairs;
   p->max_out = std::min(contrib, L->nkeys);
   bool dense_ok = !poisson && dense_feasible(ctx, L, na, nb);
+  if (dense_ok) {
+    DensePlan& d = p->dp;
+    d.S = ctx->tune.window;
+    d.nkeys = L->nkeys;
+    d.nwin = std::max<int64_t>(1, (L->nkeys + d.S - 1) / d.S);
+    d.nchunk = std::max<int64_t>(1, (L->nkeys + DENSE_CHUNK - 1) / DENSE_CHUNK);
+    d.ntiles = std::max<int64_t>(1, (nb + DENSE_TILE - 1) / DENSE_TILE);
+    d.block = ctx->tune.block;
+    d.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
+    d.max_tasks = d.target_tasks;
+    d.min_work = 512;
+    d.maxcodeA = factor_maxcode(L, 0);
+    d.maxcodeB = factor_maxcode(L, 1);
+    d.shiftA = dense_bucket_shift(d.maxcodeA, na);
+    d.shiftB = dense_bucket_shift(d.maxcodeB, nb);
+    d.nbkA = (d.maxcodeA >> d.shiftA) + 1;
+    d.nbkB = (d.maxcodeB >> d.shiftB) + 1;
+    const double items = dense_items_bound(d, na);
+    dense_ok = items <= (double)((int64_t)1 << 31);
+    d.items_cap = dense_ok ? (int64_t)items : 0;
+  }
   kp_mode m = mode;
   if (m == KP_AUTO) {
     double budget = ctx->tune.dense_keys_per_pair * (double)pairs;
     m = (dense_ok && (double)L->nkeys <= budget) ? KP_DENSE : KP_HASH;
   }
   if (m == KP_DENSE && !dense_ok)
-    return fail(ctx, KP_E_MODE, "dense mode needs a Laurent product with at most %lld codes",
-                (long long)ctx->tune.dense_max_keys);
+    return fail(ctx, KP_E_MODE,
+                "dense mode needs a Laurent product with at most %lld codes and a bounded "
+                "number of work items",
+                (long long)std::min<int64_t>(ctx->tune.dense_max_keys, DENSE_MAX_CODES));
   p->mode = m;
   Carver c;
   if (m == KP_DENSE) {
-    DensePlan& d = p->dp;
-    d.S = ctx->tune.window;
-    d.nkeys = L->nkeys;
-    d.nwin = std::max<int64_t>(1, (L->nkeys + d.S - 1) / d.S);
-    d.nchunk = std::max<int64_t>(1, (L->nkeys + DENSE_CHUNK - 1) / DENSE_CHUNK);
-    d.ntiles = std::max<int64_t>(1, (nb + 63) / 64);
-    d.block = ctx->tune.block;
-    d.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
-    d.max_tasks = d.target_tasks + d.nwin;
-    d.min_work = 512;
-    d.maxcodeA = factor_maxcode(L, 0);
-    d.maxcodeB = factor_maxcode(L, 1);
-    d.shiftA = dense_bucket_shift(d.maxcodeA);
-    d.shiftB = dense_bucket_shift(d.maxcodeB);
-    d.nbkA = (d.maxcodeA >> d.shiftA) + 1;
-    d.nbkB = (d.maxcodeB >> d.shiftB) + 1;
     carve_dense<false>(c, *p, na, nb, nullptr);
   } else {
     int64_t want;
@@ -307,9 +338,9 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   *out = nullptr;
   auto* ctx = new kp_ctx;
   ctx->device = device;
-  ctx->tune.window = 16384;
+  ctx->tune.window = 18432;
   ctx->tune.block = 1024;
-  ctx->tune.tasks_per_cu = 2;
+  ctx->tune.tasks_per_cu = 1;
   ctx->tune.hash_load = 0.5;
   ctx->tune.hash_capacity = 0;
   ctx->tune.dense_max_keys = (int64_t)1 << 27;
@@ -392,6 +423,8 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
   if (t->tasks_per_cu < 1) return fail(ctx, KP_E_ARG, "tasks_per_cu must be >= 1");
   if (!(t->hash_load >= 0.05 && t->hash_load <= 0.9))
     return fail(ctx, KP_E_ARG, "hash_load must lie in [0.05, 0.9]");
+  if (t->dense_max_keys > DENSE_MAX_CODES)
+    return fail(ctx, KP_E_ARG, "dense_max_keys must be at most %lld", (long long)DENSE_MAX_CODES);
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");

@@ -142,7 +142,9 @@ __global__ void __launch_bounds__(256) k_zero(uint4* p, size_t n16, uint8_t* tai
 
 __global__ void k_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint32_t* ctx_err) {
   if (threadIdx.x != 0) return;
-  uint32_t e = m->err;
+  // errors of this call, and any latched on the context by an earlier
+  // asynchronous call (an encode that found an exponent out of range)
+  uint32_t e = m->err | *ctx_err;
   int64_t cnt = m->out_count;
   if (cnt > out_cap) e |= ERR_CAPACITY;
   if (e) {

@@ -10,34 +10,50 @@
 // atomics (ds_add_u64 / ds_add_f64) and compacts the nonzero slots in code
 // order.
 //
+// Work decomposition.  Factor B is cut into tiles of 16 consecutive sorted
+// terms, one per lane of a 16-lane DPP row.  For a window [L, L+S) and a tile
+// with codes in [bmin, bmax], the rows of A that can land in the window have
+// codes in [L - bmax, L + S - bmin): a run of A's buckets, read off the bucket
+// start table in O(1).  Rows whose bucket lies inside [L - bmin, L + S - bmax)
+// land for every lane ("core" rows); the others ("edge" rows) need a range
+// test.  The rows of every (window, tile) pair are cut into work items of at
+// most 64 rows, edge and core rows in separate items.  A wavefront handles an
+// item as 16 instructions of 64 pairs: lane 16g + v pairs term v of the tile
+// with row 16g + u of the item in instruction u, the row's code and
+// coefficient being broadcast inside each 16-lane row by DPP row_newbcast:u,
+// which folds into the add and the 24-bit multiplies.  The four rows of an
+// instruction lie 16 rows apart, so their slots rarely coincide.  The edge test is one
+// unsigned min that sends an out-of-window pair to a per-lane discard slot.
+//
 // Launches (one stream):
-//  1. prep    -- two workgroups, one per factor: bucket sort by code (buckets
-//                of 2^shift codes: LDS histogram, scan, scatter), A's bucket
-//                start table, B's per-tile code min/max, coefficient-range
-//                flags.
-//  2. plan    -- one workgroup per window counts the row visits of every tile
-//                of B; the last one to finish gives every window a number of
-//                tasks proportional to its work.
-//  3. mul     -- one workgroup per task.  Factor B is cut into tiles of 64
-//                consecutive terms (one per lane); for a window [L, L+S) and a
-//                tile with codes in [bmin, bmax] the rows of A that can land
-//                in the window are those with codes in [L - bmax, L + S - bmin),
-//                a run of buckets of A read off the bucket table in O(1); rows
-//                with codes in [L - bmin, L + S - bmax) land in the window for
-//                every lane and skip the range test.  A task takes a slice of
-//                the window's tiles (equal work); wavefronts load 64 rows of A
-//                at a time (the next 64 requested before the current ones are
-//                used) and broadcast each row's code and coefficient to all
-//                lanes with v_readlane.  A window with one task compacts its
-//                nonzero slots straight from LDS; a window split into several
-//                tasks writes each task's partial window to HBM.
-//  4. combine -- one workgroup per chunk of a split window: sums the partial
-//                windows and compacts the chunk.
-//  5. scan    -- one workgroup: output offset of every chunk, result count.
-//  6. copy    -- one workgroup per chunk: moves the chunk to its offset.
+//  1. prep    -- two workgroups, one per factor: bucket histogram of the codes
+//                in LDS (buckets of 2^shift codes) with each term's rank in
+//                its bucket, scan to bucket starts, coefficient-range flags.
+//  2. scatter -- one thread per term: writes the bucket-sorted packed
+//                {code, low coefficient word} arrays and each tile's code
+//                min/max (tiles of 16 consecutive sorted terms of B).
+//  3. count   -- one workgroup per window: row ranges of every tile (kept),
+//                the window's rows and items; the last workgroup to finish
+//                lays out items over all windows and cuts the rows into
+//                equal tasks.
+//  4. items   -- one workgroup per window: writes the window's work items in
+//                (tile, row) order, spread evenly over the threads, and the
+//                first item (and window) of every task that starts in it.
+//  5. mul     -- one workgroup per task: a task is a run of items of equal
+//                rows that may cross windows; for each window it meets it
+//                clears the LDS window, wavefronts take the items round-robin
+//                with the next item's rows and terms loaded while the current
+//                one is accumulated, and the window is flushed: compacted
+//                straight from LDS when the task holds all of it, otherwise
+//                added into an HBM accumulator with device-scope atomics.
+//  6. combine -- one workgroup per chunk of a window split across tasks:
+//                compacts the accumulated chunk.
+//  7. scan    -- one workgroup: output offset of every chunk, result count.
+//  8. copy    -- one workgroup per chunk: moves the chunk to its offset.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
+#include <utility>
 
 #include "kp_internal.h"
 
@@ -47,12 +63,53 @@ namespace {
 
 constexpr int PREP_BLOCK = 1024;
 constexpr int PLAN_BLOCK = 256;
+constexpr int64_t ITEMS_LDS_BYTES = 144 * 1024;   // tile rows and item map of the items kernel
 constexpr int PREP_UNROLL = 8;
+// Byte offsets that can never fall inside a window (codes are below 2^27, so
+// a window offset times 8 stays within +-2^30): a missing row of A, and a
+// missing term of B in the last tile.  Their sum is also out of range.
+constexpr uint32_t ROW_SENTINEL = 0x80000000u;
+constexpr uint32_t LANE_SENTINEL = 0x40000000u;
 
-__device__ __forceinline__ int64_t readfirst64(int64_t v) {
-  int32_t lo = __builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
-  int32_t hi = __builtin_amdgcn_readfirstlane((int32_t)((uint64_t)v >> 32));
+// Per-window planning records, stored as five arrays of nwin + 1 entries.
+enum { W_ITEMS = 0, W_ROWS = 1, W_SPLIT = 2, W_IBASE = 3, W_CBASE = 4 };
+// Cost of a window to a task, in work items, beyond its items: clearing the
+// LDS window, the first loads and the flush.
+constexpr int64_t WINDOW_COST = 64;
+
+__device__ __forceinline__ int64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// DPP move of a 64-bit value; lanes without a source keep `fill`.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp64(int64_t v, int64_t fill) {
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)fill, (int)(uint32_t)v, CTRL, 0xF,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)((uint64_t)fill >> 32),
+                                             (int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xF, 0xF,
+                                             false);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Inclusive wavefront scan without LDS traffic: Hillis-Steele steps inside
+// each 16-lane row (DPP row_shr:1,2,4,8), then the row totals by readlane.
+// All 64 lanes must be active.
+template <bool MAX>
+__device__ __forceinline__ int64_t wave_inclusive(int64_t v, int64_t ident) {
+  auto op = [](int64_t a, int64_t b) { return MAX ? (a > b ? a : b) : a + b; };
+  v = op(v, dpp64<0x111>(v, ident));
+  v = op(v, dpp64<0x112>(v, ident));
+  v = op(v, dpp64<0x114>(v, ident));
+  v = op(v, dpp64<0x118>(v, ident));
+  const int row = (threadIdx.x & 63) >> 4;
+  const int64_t r0 = readlane64(v, 15), r1 = readlane64(v, 31), r2 = readlane64(v, 47);
+  v = op(v, row >= 1 ? r0 : ident);
+  v = op(v, row >= 2 ? r1 : ident);
+  v = op(v, row >= 3 ? r2 : ident);
+  return v;
 }
 
 // Block-wide exclusive scan of one int64 per thread; returns the exclusive
@@ -60,11 +117,7 @@ __device__ __forceinline__ int64_t readfirst64(int64_t v) {
 template <int BS>
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* s_wave, int64_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t inc = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    int64_t u = __shfl_up(inc, off);
-    if (lane >= off) inc += u;
-  }
+  const int64_t inc = wave_inclusive<false>(v, 0);
   if (lane == 63) s_wave[wave] = inc;
   __syncthreads();
   int64_t before = 0, all = 0;
@@ -79,10 +132,32 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* s_wa
   return before + inc - v;
 }
 
+// Block-wide exclusive max-scan (identity `lowest`); writes the block maximum.
+template <int BS>
+__device__ __forceinline__ int64_t block_exclusive_max(int64_t v, int64_t lowest, int64_t* s_wave,
+                                                       int64_t* all_max) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t inc = wave_inclusive<true>(v, lowest);
+  int64_t ex = __shfl_up(inc, 1);
+  if (lane == 0) ex = lowest;
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  int64_t before = lowest, all = lowest;
+#pragma unroll
+  for (int w = 0; w < BS / 64; ++w) {
+    int64_t x = s_wave[w];
+    if (w < wave) before = max(before, x);
+    all = max(all, x);
+  }
+  __syncthreads();
+  *all_max = all;
+  return max(before, ex);
+}
+
 // Rows of A (bucket b holds codes [b << shift, (b+1) << shift)) that may hold
 // codes in [lo, hi): the union of the buckets covering that interval.
 __device__ __forceinline__ void rows_for(const int32_t* __restrict__ bstart, int shift, int64_t nbk,
-                                int64_t lo, int64_t hi, int64_t* i0, int64_t* i1) {
+                                         int64_t lo, int64_t hi, int64_t* i0, int64_t* i1) {
   const int64_t maxcode = (nbk << shift) - 1;
   if (hi <= 0 || lo > maxcode || hi <= lo) {
     *i0 = *i1 = 0;
@@ -102,11 +177,11 @@ struct PrepSeg {
   int shift;
   int64_t nbk;            // buckets (<= DENSE_MAX_BUCKETS)
   int64_t maxcode;        // largest code of the factor's box
-  int64_t* out_keys;
-  int64_t* out_coef;
-  int32_t* rank;          // scratch [n]
-  int32_t* bstart;        // [nbk + 1] (factor A only, else null)
-  int64_t* tmin;          // [ceil(n/64)] (factor B only, else null)
+  uint64_t* out_pk;       // {code, low coefficient word}
+  uint64_t* out_coef;     // coefficient bits
+  int32_t* rank;          // [n] rank of each term in its bucket
+  int32_t* bstart;        // [nbk + 1] first sorted position of each bucket
+  int64_t* tmin;          // [ceil(n/16)] (factor B only, else null)
   int64_t* tmax;
   int64_t* zero;          // array cleared by this workgroup (chunk counts), may be null
   int64_t nzero;
@@ -117,15 +192,23 @@ struct PrepArgs {
   int is_i64;
 };
 
+// Bucket of a code (codes outside the factor's box are flagged by the caller
+// and clamped into the first or last bucket).
+__device__ __forceinline__ int64_t bucket_of(int64_t k, int shift, int64_t maxb) {
+  const int64_t b = k >> shift;
+  return k < 0 ? 0 : (b > maxb ? maxb : b);
+}
+
 __global__ void __launch_bounds__(PREP_BLOCK) k_dense_prep(PrepArgs args) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int32_t* hist = reinterpret_cast<int32_t*>(smem_raw);
   __shared__ int64_t s_wave[PREP_BLOCK / 64];
   __shared__ uint32_t s_flags[PREP_BLOCK / 64];
   __shared__ uint32_t s_err[PREP_BLOCK / 64];
+  constexpr int NW = PREP_BLOCK / 64;
   const int which = blockIdx.x;
   const PrepSeg sg = args.seg[which];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t nbk = sg.nbk;
   const int64_t maxb = nbk - 1;
 
@@ -135,8 +218,15 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_dense_prep(PrepArgs args) {
   }
   for (int64_t b = tid; b < nbk; b += PREP_BLOCK) hist[b] = 0;
   for (int64_t i = tid; i < sg.nzero; i += PREP_BLOCK) sg.zero[i] = 0;
+  if (sg.tmin) {
+    const int64_t ntiles = (sg.n + DENSE_TILE - 1) / DENSE_TILE;
+    for (int64_t t = tid; t < ntiles; t += PREP_BLOCK) {
+      sg.tmin[t] = LLONG_MAX;
+      sg.tmax[t] = LLONG_MIN;
+    }
+  }
   __syncthreads();
-  uint32_t flags = 3u;   // bit0 fits int32, bit1 fits signed 24 bits
+  uint32_t flags = 7u;   // bit0 fits int32, bit1 fits signed 24 bits, bit2 in [0, 2^16)
   uint32_t err = 0;
   // PREP_UNROLL elements per thread per round: all loads first, then the atomics
   for (int64_t base = 0; base < sg.n; base += PREP_BLOCK * PREP_UNROLL) {
@@ -152,338 +242,516 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_dense_prep(PrepArgs args) {
       const int64_t i = base + u * PREP_BLOCK + tid;
       if (i >= sg.n) continue;
       const int64_t k = kk[u];
-      int64_t b = k >> sg.shift;
-      if (k < 0 || k > sg.maxcode) {   // a code outside the factor's box: flagged
-        err |= ERR_RANGE;
-        b = k < 0 ? 0 : min(b, maxb);
-      }
-      sg.rank[i] = atomicAdd(&hist[b], 1);
+      if (k < 0 || k > sg.maxcode) err |= ERR_RANGE;   // a code outside the factor's box
+      sg.rank[i] = atomicAdd(&hist[bucket_of(k, sg.shift, maxb)], 1);
       const int64_t c = cc[u];
       if (c < INT_MIN || c > INT_MAX) flags &= ~1u;
       if (c < -(1 << 23) || c >= (1 << 23)) flags &= ~2u;
+      if (c < 0 || c >= (1 << 16)) flags &= ~4u;
     }
   }
   __syncthreads();
-  // exclusive scan of the histogram: each thread owns a contiguous run
-  const int64_t per = (nbk + PREP_BLOCK - 1) / PREP_BLOCK;
-  const int64_t b0 = min(nbk, tid * per), b1 = min(b0 + per, nbk);
-  int64_t local = 0;
-  for (int64_t b = b0; b < b1; ++b) local += hist[b];
-  int64_t total;
-  int64_t run = block_exclusive_scan<PREP_BLOCK>(local, s_wave, &total);
-  for (int64_t b = b0; b < b1; ++b) {
-    const int32_t c = hist[b];
-    hist[b] = (int32_t)run;
-    if (sg.bstart) sg.bstart[b] = (int32_t)run;
-    run += c;
-  }
-  if (sg.bstart && tid == 0) sg.bstart[nbk] = (int32_t)sg.n;
+  // Exclusive scan of the histogram.  Wave w owns a contiguous run of
+  // buckets and reads it 64 consecutive buckets at a time (no bank
+  // conflicts): first the run's total, then the scan with a running carry.
+  const int64_t per = (nbk + NW * 64 - 1) / (NW * 64) * 64;
+  const int64_t r0 = min(nbk, wave * per), r1 = min(nbk, r0 + per);
+  int64_t part = 0;
+  for (int64_t b = r0 + lane; b < r1; b += 64) part += hist[b];
+  part = readlane64(wave_inclusive<false>(part, 0), 63);
+  if (lane == 0) s_wave[wave] = part;
   __syncthreads();
-  for (int64_t base = 0; base < sg.n; base += PREP_BLOCK * PREP_UNROLL) {
-    int64_t kk[PREP_UNROLL], cc[PREP_UNROLL];
-    int32_t rr[PREP_UNROLL];
-#pragma unroll
-    for (int u = 0; u < PREP_UNROLL; ++u) {
-      const int64_t i = base + u * PREP_BLOCK + tid;
-      kk[u] = i < sg.n ? sg.keys[i] : 0;
-      cc[u] = i < sg.n ? sg.coef[i] : 0;
-      rr[u] = i < sg.n ? sg.rank[i] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < PREP_UNROLL; ++u) {
-      const int64_t i = base + u * PREP_BLOCK + tid;
-      if (i >= sg.n) continue;
-      const int64_t k = kk[u];
-      int64_t b = k >> sg.shift;
-      b = k < 0 ? 0 : (b > maxb ? maxb : b);
-      const int64_t pos = hist[b] + rr[u];
-      sg.out_keys[pos] = k;
-      sg.out_coef[pos] = cc[u];
-    }
+  int64_t carry = 0;
+  for (int w = 0; w < wave; ++w) carry += s_wave[w];
+  for (int64_t b0 = r0; b0 < r1; b0 += 64) {
+    const int64_t b = b0 + lane;
+    const int64_t v = b < r1 ? hist[b] : 0;
+    const int64_t inc = wave_inclusive<false>(v, 0);
+    if (b < r1) sg.bstart[b] = (int32_t)(carry + inc - v);
+    carry += readlane64(inc, 63);
   }
+  if (tid == 0) sg.bstart[nbk] = (int32_t)sg.n;
+  if (!args.is_i64) flags = 0;
   const uint32_t wf = wave_and(flags), we = wave_or(err);
-  if ((tid & 63) == 0) {
-    s_flags[tid >> 6] = wf;
-    s_err[tid >> 6] = we;
+  if (lane == 0) {
+    s_flags[wave] = wf;
+    s_err[wave] = we;
   }
-  __syncthreads();   // also orders the scattered keys before the tile pass
+  __syncthreads();
   if (tid == 0) {
-    uint32_t f = 3u, e = 0;
-    for (int w = 0; w < PREP_BLOCK / 64; ++w) {
+    uint32_t f = 7u, e = 0;
+    for (int w = 0; w < NW; ++w) {
       f &= s_flags[w];
       e |= s_err[w];
     }
     args.meta->seg_flags[which] = f;
     args.meta->seg_err[which] = e;
   }
-  if (sg.tmin) {   // code range of every tile of 64 consecutive sorted terms
-    const int lane = tid & 63, wave = tid >> 6;
-    const int64_t ntiles = (sg.n + 63) / 64;
-    constexpr int NWP = PREP_BLOCK / 64;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += NWP * PREP_UNROLL) {
-      int64_t kk[PREP_UNROLL];
-#pragma unroll
-      for (int u = 0; u < PREP_UNROLL; ++u) {
-        const int64_t j = (t0 + u * NWP + wave) * 64 + lane;
-        kk[u] = j < sg.n ? sg.out_keys[j] : LLONG_MAX;
-      }
-#pragma unroll
-      for (int u = 0; u < PREP_UNROLL; ++u) {
-        const int64_t t = t0 + u * NWP + wave;
-        const int64_t j = t * 64 + lane;
-        int64_t lo = kk[u], hi = j < sg.n ? kk[u] : LLONG_MIN;
-        for (int off = 32; off > 0; off >>= 1) {
-          lo = min(lo, __shfl_xor(lo, off));
-          hi = max(hi, __shfl_xor(hi, off));
-        }
-        if (lane == 0 && t < ntiles) {
-          sg.tmin[t] = lo;
-          sg.tmax[t] = hi;
-        }
-      }
-    }
+}
+
+constexpr int SCATTER_BLOCK = 256;
+
+// Writes every term at its bucket-sorted position; for factor B also the
+// code range of each tile of 16 consecutive sorted terms.
+__global__ void __launch_bounds__(SCATTER_BLOCK) k_dense_scatter(PrepArgs args, int64_t blocksA) {
+  const bool isB = blockIdx.x >= blocksA;
+  const PrepSeg& sg = isB ? args.seg[1] : args.seg[0];
+  const int64_t i = (int64_t)(isB ? blockIdx.x - blocksA : blockIdx.x) * SCATTER_BLOCK + threadIdx.x;
+  if (i >= sg.n) return;
+  const int64_t k = sg.keys[i], c = sg.coef[i];
+  const int64_t pos = sg.bstart[bucket_of(k, sg.shift, sg.nbk - 1)] + sg.rank[i];
+  sg.out_pk[pos] = (uint64_t)(uint32_t)k | ((uint64_t)(uint32_t)c << 32);
+  sg.out_coef[pos] = (uint64_t)c;
+  if (isB) {
+    const int64_t t = pos / DENSE_TILE, code = (int64_t)(uint32_t)k;
+    __hip_atomic_fetch_min(&sg.tmin[t], code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&sg.tmax[t], code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 // ------------------------------------------------------------------ plan
 struct PlanArgs {
-  int64_t S, nwin, ntiles, nkeys, target, min_work;
+  int64_t S, nwin, ntiles, nkeys, nb, target, min_work, items_cap;
+  int64_t items_lds;     // dynamic LDS bytes of the items kernel
   const int32_t* bstart;
   int shiftA;
   int64_t nbkA;
   const int64_t* tmin;
   const int64_t* tmax;
-  int64_t* wt;
-  int64_t* task_off;
-  int64_t* dense;     // [nwin * S] accumulator of windows split across tasks
+  int64_t* win;          // [5 * (nwin + 1)]
+  int4* recs;            // [nwin * ntiles] rows of every (window, tile)
+  uint64_t* items;
+  int32_t* task_w;
+  int32_t* task_begin;
+  int64_t* dense;        // [nwin * S] accumulator of windows split across tasks
   Meta* meta;
 };
 
-__global__ void __launch_bounds__(PLAN_BLOCK) k_dense_plan(PlanArgs P) {
+// Rows of A visited by tile t in the window [L, L + Sw): edge rows [i0, c0),
+// core rows [c0, c1) (every lane lands), edge rows [c1, i1).
+struct TileRows {
+  int64_t i0, c0, c1, i1;
+};
+
+__device__ __forceinline__ TileRows tile_rows(const PlanArgs& P, int64_t L, int64_t Sw, int64_t t) {
+  TileRows g{0, 0, 0, 0};
+  if (t >= P.ntiles) return g;
+  const int64_t lo = P.tmin[t], hi = P.tmax[t];
+  rows_for(P.bstart, P.shiftA, P.nbkA, L - hi, L + Sw - lo, &g.i0, &g.i1);
+  g.c0 = g.c1 = g.i0;
+  const bool full = (t + 1) * DENSE_TILE <= P.nb;
+  const int64_t clo = max(L - lo, (int64_t)0), chi = L + Sw - hi;
+  if (full && g.i1 > g.i0 && chi > clo) {
+    const int64_t bw = (int64_t)1 << P.shiftA;
+    const int64_t b0 = (clo + bw - 1) >> P.shiftA;
+    const int64_t b1 = min(chi >> P.shiftA, P.nbkA);
+    if (b1 > b0) {
+      g.c0 = min(g.i1, max(g.i0, (int64_t)P.bstart[b0]));
+      g.c1 = min(g.i1, max(g.c0, (int64_t)P.bstart[b1]));
+    }
+  }
+  return g;
+}
+
+__device__ __forceinline__ int64_t chunks(int64_t n) {
+  return (n + DENSE_ITEM_ROWS - 1) / DENSE_ITEM_ROWS;
+}
+
+__device__ __forceinline__ uint64_t pack_item(int64_t r0, int64_t t, int64_t n, bool core) {
+  const uint32_t hi = (uint32_t)t | ((uint32_t)(n - 1) << 25) | (core ? 0x80000000u : 0u);
+  return (uint64_t)(uint32_t)r0 | ((uint64_t)hi << 32);
+}
+
+// Tiles [t0, t1) of this thread: a contiguous run, so that one block scan
+// orders all of a window's items.
+__device__ __forceinline__ void thread_tiles(int64_t ntiles, int64_t* t0, int64_t* t1) {
+  const int64_t m = (ntiles + PLAN_BLOCK - 1) / PLAN_BLOCK;
+  *t0 = min(ntiles, (int64_t)threadIdx.x * m);
+  *t1 = min(ntiles, *t0 + m);
+}
+
+__device__ __forceinline__ int64_t items_of(const int4& r) {
+  return chunks(r.y - r.x) + chunks(r.z - r.y) + chunks(r.w - r.z);
+}
+
+// Item k of a tile with rows {i0, c0, c1, i1}: first row, rows, core flag.
+__device__ __forceinline__ void item_rows(const int4& r, int64_t k, int64_t* r0, int64_t* n,
+                                          bool* core) {
+  const int64_t e1 = chunks(r.y - r.x), ec = chunks(r.z - r.y);
+  int64_t hi;
+  if (k < e1) {
+    *r0 = r.x + k * DENSE_ITEM_ROWS;
+    hi = r.y;
+    *core = false;
+  } else if (k < e1 + ec) {
+    *r0 = r.y + (k - e1) * DENSE_ITEM_ROWS;
+    hi = r.z;
+    *core = true;
+  } else {
+    *r0 = r.z + (k - e1 - ec) * DENSE_ITEM_ROWS;
+    hi = r.w;
+    *core = false;
+  }
+  *n = min(DENSE_ITEM_ROWS, hi - *r0);
+  *core = *core && *n == DENSE_ITEM_ROWS;
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   __shared__ int64_t s_wave[PLAN_BLOCK / 64];
   __shared__ int s_last;
   const int tid = threadIdx.x;
   const int64_t w = blockIdx.x;
   const int64_t L = w * P.S;
   const int64_t Sw = min(P.S, P.nkeys - L);
-  int64_t running = 0;
-  for (int64_t base = 0; base < P.ntiles; base += PLAN_BLOCK) {
-    const int64_t t = base + tid;
-    int64_t v = 0;
-    if (t < P.ntiles) {
-      int64_t i0, i1;
-      rows_for(P.bstart, P.shiftA, P.nbkA, L - P.tmax[t], L + Sw - P.tmin[t], &i0, &i1);
-      v = i1 - i0;
-    }
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan<PLAN_BLOCK>(v, s_wave, &tot);
-    if (t < P.ntiles) P.wt[w * P.ntiles + t] = running + ex + v;
-    running += tot;
+  const int64_t W1 = P.nwin + 1;
+  int4* rec = P.recs + w * P.ntiles;
+  int64_t t0, t1;
+  thread_tiles(P.ntiles, &t0, &t1);
+  int64_t nit = 0, rows = 0;
+  constexpr int BATCH = 4;   // tiles whose loads are issued together
+  for (int64_t t = t0; t < t1; t += BATCH) {
+    TileRows g[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) g[u] = tile_rows(P, L, Sw, min(t + u, t1 - 1));
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u)
+      if (t + u < t1) {
+        const int4 r = make_int4((int)g[u].i0, (int)g[u].c0, (int)g[u].c1, (int)g[u].i1);
+        rec[t + u] = r;
+        nit += items_of(r);
+        rows += g[u].i1 - g[u].i0;
+      }
   }
-  // a window with more than min_work row visits may be split: clear its
-  // HBM accumulator now (tasks of a split window add into it)
-  if (running > P.min_work) {
-    int64_t* d = P.dense + L;
-    for (int64_t i = tid; i < Sw; i += PLAN_BLOCK) d[i] = 0;
-  }
+  int64_t tot_items, tot_rows;
+  block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tot_items);
+  block_exclusive_scan<PLAN_BLOCK>(rows, s_wave, &tot_rows);
   if (tid == 0) {
+    P.win[W_ITEMS * W1 + w] = tot_items;
+    P.win[W_ROWS * W1 + w] = tot_rows;
     __threadfence();
     s_last = atomicAdd(&P.meta->plan_done, 1u) == (uint32_t)(P.nwin - 1);
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // last workgroup: tasks per window proportional to its work
+  // last workgroup: item and row offsets of every window, equal tasks
+  auto ld = [&](int k, int64_t u) {
+    return __hip_atomic_load(&P.win[k * W1 + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
   const int64_t per = (P.nwin + PLAN_BLOCK - 1) / PLAN_BLOCK;
   const int64_t w0 = min(P.nwin, tid * per), w1 = min(w0 + per, P.nwin);
-  auto work_of = [&](int64_t u) {
-    return __hip_atomic_load(&P.wt[u * P.ntiles + P.ntiles - 1], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-  };
-  int64_t local = 0;
-  for (int64_t u = w0; u < w1; ++u) local += work_of(u);
-  int64_t total;
-  block_exclusive_scan<PLAN_BLOCK>(local, s_wave, &total);
-  int64_t T = (total + P.target - 1) / P.target;
-  if (T < P.min_work) T = P.min_work;
-  // windows at or below min_work are never split (their accumulator was not cleared)
-  auto tasks_of = [&](int64_t u) {
-    const int64_t wk = work_of(u);
-    return wk <= P.min_work ? (wk > 0 ? (int64_t)1 : (int64_t)0) : (wk + T - 1) / T;
-  };
-  int64_t ntask = 0;
-  for (int64_t u = w0; u < w1; ++u) ntask += tasks_of(u);
-  int64_t all;
-  int64_t off = block_exclusive_scan<PLAN_BLOCK>(ntask, s_wave, &all);
+  int64_t li = 0;
+  for (int64_t u = w0; u < w1; ++u) li += ld(W_ITEMS, u);
+  // cost of a window: its items plus WINDOW_COST when it has any
+  int64_t lc = 0;
   for (int64_t u = w0; u < w1; ++u) {
-    P.task_off[u] = off;
-    off += tasks_of(u);
+    const int64_t it = ld(W_ITEMS, u);
+    lc += it > 0 ? it + WINDOW_COST : 0;
   }
+  int64_t all_items, all_cost;
+  int64_t ibase = block_exclusive_scan<PLAN_BLOCK>(li, s_wave, &all_items);
+  int64_t cbase = block_exclusive_scan<PLAN_BLOCK>(lc, s_wave, &all_cost);
+  for (int64_t u = w0; u < w1; ++u) {
+    const int64_t it = ld(W_ITEMS, u);
+    P.win[W_IBASE * W1 + u] = ibase;
+    P.win[W_CBASE * W1 + u] = cbase;
+    ibase += it;
+    cbase += it > 0 ? it + WINDOW_COST : 0;
+  }
+  // No work after a factor code outside its box (reported by the scan
+  // kernel), or past the planned item bound (which cannot happen).
+  const uint32_t bad = P.meta->seg_err[0] | P.meta->seg_err[1];
   if (tid == 0) {
-    P.task_off[P.nwin] = all;
-    P.meta->ntasks = all;
+    P.win[W_IBASE * W1 + P.nwin] = all_items;
+    P.win[W_CBASE * W1 + P.nwin] = all_cost;
+    // tasks of equal cost T (more than one window's overhead plus an item):
+    // task p starts at the item whose cost interval holds p * T
+    int64_t T = (all_cost + P.target - 1) / P.target;
+    if (T < WINDOW_COST + 1) T = WINDOW_COST + 1;
+    int64_t nt = all_cost > 0 ? (all_cost + T - 1) / T : 0;
+    if (bad || all_items > P.items_cap) {
+      if (!bad) P.meta->err |= ERR_CAPACITY;
+      nt = 0;
+    }
+    P.meta->task_rows = T;
+    P.meta->ntasks = nt;
+    P.task_begin[nt] = (int32_t)all_items;
   }
+}
+
+// Item k of window w: its descriptor, and the first item (and window) of the
+// task that starts at it, if any.  Item k covers the cost interval
+// [cb + WINDOW_COST + k, +1) (the first item also covers the window's
+// overhead [cb, cb + WINDOW_COST)); task p starts at the item whose interval
+// holds p * T.
+__device__ __forceinline__ void put_item(const PlanArgs& P, int64_t w, int64_t ib, int64_t k,
+                                         int64_t cb, int64_t r0, int64_t t, int64_t n, bool core,
+                                         int64_t T, double rT, int* s_split) {
+  P.items[ib + k] = pack_item(r0, t, n, core);
+  const int64_t lo = k == 0 ? cb : cb + WINDOW_COST + k, hi = cb + WINDOW_COST + k + 1;
+  // smallest p with p * T >= lo (the quotient is exact in double below 2^52)
+  int64_t p = (int64_t)ceil((double)lo * rT);
+  while (p > 0 && (p - 1) * T >= lo) --p;
+  while (p * T < lo) ++p;
+  if (p * T < hi) {
+    P.task_begin[p] = (int32_t)(ib + k);
+    P.task_w[p] = (int32_t)w;
+    if (k > 0) *s_split = 1;   // a task starts inside the window
+  }
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_wave[PLAN_BLOCK / 64];
+  __shared__ int s_split;
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int64_t W1 = P.nwin + 1;
+  const int64_t nit_w = P.win[W_ITEMS * W1 + w];
+  if (tid == 0) s_split = 0;
+  if (P.meta->ntasks == 0 || nit_w == 0) {
+    if (tid == 0) P.win[W_SPLIT * W1 + w] = 0;
+    return;
+  }
+  const int64_t ib = P.win[W_IBASE * W1 + w], cb = P.win[W_CBASE * W1 + w];
+  const int64_t T = P.meta->task_rows;
+  const double rT = 1.0 / (double)T;
+  const int4* rec = P.recs + w * P.ntiles;
+  const int64_t nt = P.ntiles;
+  // LDS: the window's tile rows, per-tile item prefix, tile of every item
+  int4* s_rec = reinterpret_cast<int4*>(smem_raw);
+  int32_t* s_ip = reinterpret_cast<int32_t*>(s_rec + nt);
+  int32_t* s_of = s_ip + nt + 1;
+  const bool in_lds = (size_t)nt * 20 + 4 + (size_t)nit_w * 4 <= (size_t)P.items_lds;
+  int64_t t0, t1;
+  thread_tiles(nt, &t0, &t1);
+  if (in_lds) {
+    for (int64_t t = tid; t < nt; t += PLAN_BLOCK) s_rec[t] = rec[t];
+    __syncthreads();
+    int64_t nit = 0;
+    for (int64_t t = t0; t < t1; ++t) nit += items_of(s_rec[t]);
+    int64_t tq;
+    int64_t q = block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tq);
+    for (int64_t k = tid; k < nit_w; k += PLAN_BLOCK) s_of[k] = -1;
+    __syncthreads();
+    // each non-empty tile marks its first item; a max-scan over the items
+    // then gives every item its tile
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t c = items_of(s_rec[t]);
+      s_ip[t] = (int32_t)q;
+      if (c > 0) s_of[q] = (int32_t)t;
+      q += c;
+    }
+    __syncthreads();
+    const int64_t per = (nit_w + PLAN_BLOCK - 1) / PLAN_BLOCK;
+    const int64_t k0 = min(nit_w, tid * per), k1 = min(nit_w, k0 + per);
+    int64_t run = -1;
+    for (int64_t k = k0; k < k1; ++k) run = max(run, (int64_t)s_of[k]);
+    int64_t all_max;
+    run = block_exclusive_max<PLAN_BLOCK>(run, -1, s_wave, &all_max);
+    for (int64_t k = k0; k < k1; ++k) {
+      run = max(run, (int64_t)s_of[k]);
+      s_of[k] = (int32_t)run;
+    }
+    __syncthreads();
+    for (int64_t k = tid; k < nit_w; k += PLAN_BLOCK) {
+      const int64_t t = s_of[k];
+      int64_t r0, n;
+      bool core;
+      item_rows(s_rec[t], k - s_ip[t], &r0, &n, &core);
+      put_item(P, w, ib, k, cb, r0, t, n, core, T, rT, &s_split);
+    }
+  } else {
+    // too large for LDS: each thread writes the items of its own tiles
+    int64_t nit = 0;
+    for (int64_t t = t0; t < t1; ++t) nit += items_of(rec[t]);
+    int64_t tq;
+    int64_t q = block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tq);
+    for (int64_t t = t0; t < t1; ++t) {
+      const int4 r = rec[t];
+      const int64_t cnt = items_of(r);
+      for (int64_t k = 0; k < cnt; ++k) {
+        int64_t r0, n;
+        bool core;
+        item_rows(r, k, &r0, &n, &core);
+        put_item(P, w, ib, q + k, cb, r0, t, n, core, T, rT, &s_split);
+      }
+      q += cnt;
+    }
+  }
+  __syncthreads();
+  if (s_split) {   // tasks of a split window add into the HBM accumulator
+    const int64_t L = w * P.S;
+    const int64_t Sw = min(P.S, P.nkeys - L);
+    int64_t* d = P.dense + L;
+    for (int64_t i = tid; i < Sw; i += PLAN_BLOCK) d[i] = 0;
+  }
+  if (tid == 0) P.win[W_SPLIT * W1 + w] = s_split;
 }
 
 // ------------------------------------------------------------------ multiply
-// Coefficient product.  MUL: 2 = both factors fit signed 24 bits (two
-// full-rate 24-bit multiplies), 1 = both fit int32 (one 32x32->64 multiply),
-// 0 = general int64 (wraps modulo 2^64), 3 = fp64.
-template <typename T, int MUL>
-__device__ __forceinline__ T coef_mul_fixed(T a, T b) {
-  if constexpr (MUL == 3) {
-    return a * b;
-  } else if constexpr (MUL == 2) {
-    int32_t x = ((int32_t)a << 8) >> 8, y = ((int32_t)b << 8) >> 8;
-    return (int64_t)x * (int64_t)y;
-  } else if constexpr (MUL == 1) {
-    return (int64_t)(int32_t)a * (int64_t)(int32_t)b;
-  } else {
-    return (int64_t)((uint64_t)a * (uint64_t)b);
-  }
-}
-
-__device__ __forceinline__ void lds_add(int64_t* p, int64_t v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-__device__ __forceinline__ uint32_t rl(uint32_t v, int lane) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
-}
-
-template <typename T, int MUL>
-__device__ __forceinline__ T coef_of(uint32_t clo, uint32_t chi) {
-  if constexpr (MUL == 1 || MUL == 2) {
-    (void)chi;
-    return (T)(int32_t)clo;
-  } else {
-    const uint64_t bits = ((uint64_t)chi << 32) | clo;
-    T c;
-    __builtin_memcpy(&c, &bits, sizeof(T));
-    return c;
-  }
-}
-
-// Row kinds: MODE 0 = every lane lands in the window (no test); 1 = byte
-// offset test on 32 bits (|slot| < 2^28); 2 = full 64-bit test.
-template <typename T, int MUL, int MODE>
-__device__ __forceinline__ void add_row(T* win, uint32_t alo, uint32_t ahi, uint32_t clo,
-                                        uint32_t chi, int64_t cj, uint32_t off8, uint32_t S8,
-                                        bool valid, T cb) {
-  char* base = reinterpret_cast<char*>(win);
-  if constexpr (MODE == 0) {
-    (void)ahi; (void)cj; (void)S8; (void)valid;
-    const uint32_t rel = (alo << 3) + off8;
-    lds_add(reinterpret_cast<T*>(base + rel), coef_mul_fixed<T, MUL>(coef_of<T, MUL>(clo, chi), cb));
-  } else if constexpr (MODE == 1) {
-    (void)ahi; (void)cj;
-    const uint32_t rel = (alo << 3) + off8;
-    if (valid && rel < S8)
-      lds_add(reinterpret_cast<T*>(base + rel),
-              coef_mul_fixed<T, MUL>(coef_of<T, MUL>(clo, chi), cb));
-  } else {
-    (void)off8;
-    const int64_t a = (int64_t)(((uint64_t)ahi << 32) | alo);
-    const int64_t d = a - cj;
-    if (valid && (uint64_t)d < (uint64_t)(S8 >> 3))
-      lds_add(&win[d], coef_mul_fixed<T, MUL>(coef_of<T, MUL>(clo, chi), cb));
-  }
-}
-
-// Rows [i0, i1) of A against one tile of B (i0 < i1, wavefront-uniform).
-// Lane l holds row base + l; the next 64 rows are requested before the
-// current 64 are used.  Loads are unconditional (row indices are clamped to
-// the last row) so that the wait before the broadcasts covers only the
-// current rows.
-template <typename T, int MUL, int MODE>
-__device__ __forceinline__ void rows_loop(T* win, const int64_t* __restrict__ ak,
-                                          const uint64_t* __restrict__ ac, int64_t i0, int64_t i1,
-                                          int64_t cj, uint32_t off8, uint32_t S8, bool valid,
-                                          T cb) {
-  constexpr bool NARROW = MUL == 1 || MUL == 2;
-  const int lane = threadIdx.x & 63;
-  const int64_t last = i1 - 1;
-  int64_t r = min(i0 + lane, last);
-  uint64_t ka = (uint64_t)ak[r];
-  uint64_t kc = ac[r];
-  for (int64_t base = i0; base < i1; base += 64) {
-    const int64_t rn = min(base + 64 + lane, last);
-    const uint64_t nka = (uint64_t)ak[rn];
-    const uint64_t nkc = ac[rn];
-    const uint32_t alo = (uint32_t)ka, ahi = (uint32_t)(ka >> 32);
-    const uint32_t clo = (uint32_t)kc, chi = (uint32_t)(kc >> 32);
-    const int64_t cnt = i1 - base;
-    if (cnt >= 64) {
-#pragma unroll
-      for (int u = 0; u < 64; ++u)
-        add_row<T, MUL, MODE>(win, rl(alo, u), MODE == 2 ? rl(ahi, u) : 0u, rl(clo, u),
-                              NARROW ? 0u : rl(chi, u), cj, off8, S8, valid, cb);
-    } else {
-      for (int u = 0; u < (int)cnt; ++u)
-        add_row<T, MUL, MODE>(win, rl(alo, u), MODE == 2 ? rl(ahi, u) : 0u, rl(clo, u),
-                              NARROW ? 0u : rl(chi, u), cj, off8, S8, valid, cb);
-    }
-    ka = nka;
-    kc = nkc;
-  }
-}
-
-// One tile: rows [i0, c0) and [c1, i1) with the range test, [c0, c1) without.
-template <typename T, int MUL>
-__device__ __forceinline__ void tile_mul(T* win, const int64_t* ak, const uint64_t* ac,
-                                         int64_t i0, int64_t c0, int64_t c1, int64_t i1, bool wide,
-                                         int64_t cj, uint32_t off8, uint32_t S8, bool valid,
-                                         T cb) {
-  if (wide) {
-    rows_loop<T, MUL, 2>(win, ak, ac, i0, i1, cj, off8, S8, valid, cb);
-    return;
-  }
-  if (c0 > i0) rows_loop<T, MUL, 1>(win, ak, ac, i0, c0, cj, off8, S8, valid, cb);
-  if (c1 > c0) rows_loop<T, MUL, 0>(win, ak, ac, c0, c1, cj, off8, S8, valid, cb);
-  if (i1 > c1) rows_loop<T, MUL, 1>(win, ak, ac, c1, i1, cj, off8, S8, valid, cb);
-}
-
 struct MulArgs {
   const Meta* meta;
-  const int64_t* ak;
-  const uint64_t* ac;     // A coefficients (8-byte words)
-  const int32_t* bstart;
-  int shiftA;
-  int64_t nbkA;
-  const int64_t* bk;
-  const int64_t* bc;
-  int64_t nb, ntiles, S, nwin, nkeys;
-  const int64_t* tmin;
-  const int64_t* tmax;
-  const int64_t* wt;
-  const int64_t* task_off;
+  const uint64_t* apk;    // A: {code, low coefficient word}
+  const uint64_t* ac;     // A: coefficient bits
+  const uint64_t* bpk;
+  const uint64_t* bc;
+  int64_t nb, S, nwin, nkeys;
+  const uint64_t* items;
+  const int32_t* task_w;
+  const int32_t* task_begin;
+  const int64_t* win_ibase;   // [nwin + 1] first item of each window
   int64_t* dense;
   int64_t* stage_k;
   int64_t* stage_c;
   int64_t* ccount;
 };
 
-// first index in a[0, n) whose value is > key (a non-decreasing)
-__device__ __forceinline__ int64_t upper_bound(const int64_t* __restrict__ a, int64_t n,
-                                               int64_t key) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= key) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+template <int U>
+__device__ __forceinline__ uint32_t bcast16(uint32_t v) {
+  // row_newbcast:U -- every lane of a 16-lane row reads lane U of that row
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + U, 0xF, 0xF, false);
 }
 
-// window of a task: last w with task_off[w] <= task
-__device__ __forceinline__ int64_t window_of(const int64_t* __restrict__ task_off, int64_t nwin,
-                                             int64_t task) {
-  int64_t lo = 0, hi = nwin;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (task_off[mid] <= task) lo = mid; else hi = mid;
+__device__ __forceinline__ void lds_add(uint32_t addr, int64_t v) {
+  typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+  __hip_atomic_fetch_add(reinterpret_cast<lds_u64*>((size_t)addr), (unsigned long long)v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(uint32_t addr, double v) {
+  typedef __attribute__((address_space(3))) double lds_f64;
+  __hip_atomic_fetch_add(reinterpret_cast<lds_f64*>((size_t)addr), v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Coefficient kinds.  MUL: 4 = both factors in [0, 2^16) (one 24-bit
+// multiply, the product's high word is zero), 2 = both fit signed 24 bits
+// (two 24-bit multiplies), 1 = both fit int32 (one 32x32->64 multiply),
+// 0 = general int64 (wraps modulo 2^64), 3 = fp64.
+template <typename T, int MUL>
+struct Coef {
+  uint32_t lo, hi;   // this lane's row of A (broadcast per instruction)
+  int32_t bn;        // this lane's term of B, narrow kinds
+  T bw;              // this lane's term of B, wide kinds
+};
+
+// One instruction of an item: row 4U + g of the item against this lane's term.
+// Window byte offsets are relative to the window's LDS base, which is added
+// last (it folds into the instruction's offset field).
+template <typename T, int MUL, bool EDGE, int U>
+__device__ __forceinline__ void pair_step(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
+                                          const Coef<T, MUL>& c) {
+  uint32_t rel = bcast16<U>(a8) + off8;
+  if (EDGE) rel = min(rel, lim);
+  rel += base;
+  T v;
+  if constexpr (MUL == 4) {
+    const uint32_t x = bcast16<U>(c.lo) & 0xFFFFFFu;
+    v = (T)(uint64_t)(x * ((uint32_t)c.bn & 0xFFFFFFu));
+  } else if constexpr (MUL == 2) {
+    const int32_t x = (int32_t)bcast16<U>(c.lo);
+    v = (T)((int64_t)((x << 8) >> 8) * (int64_t)c.bn);
+  } else if constexpr (MUL == 1) {
+    v = (T)((int64_t)(int32_t)bcast16<U>(c.lo) * (int64_t)c.bn);
+  } else if constexpr (MUL == 0) {
+    const uint64_t x = ((uint64_t)bcast16<U>(c.hi) << 32) | bcast16<U>(c.lo);
+    v = (T)(x * (uint64_t)c.bw);
+  } else {
+    const uint64_t bits = ((uint64_t)bcast16<U>(c.hi) << 32) | bcast16<U>(c.lo);
+    double x;
+    __builtin_memcpy(&x, &bits, 8);
+    v = (T)(x * (double)c.bw);
   }
-  return lo;
+  lds_add(rel, v);
+}
+
+template <typename T, int MUL, bool EDGE, int... U>
+__device__ __forceinline__ void item_steps(std::integer_sequence<int, U...>, uint32_t a8,
+                                           uint32_t off8, uint32_t lim, uint32_t base,
+                                           const Coef<T, MUL>& c) {
+  (pair_step<T, MUL, EDGE, U>(a8, off8, lim, base, c), ...);
+}
+
+struct ItemRegs {
+  int64_t r0, t, n;
+  bool core;
+  uint64_t a, b;     // packed rows / terms
+  uint64_t ac, bc;   // coefficient words (wide kinds)
+};
+
+template <bool WIDE>
+__device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane, int rowlane,
+                                           ItemRegs& x) {
+  const uint32_t lo = (uint32_t)d, hi = (uint32_t)((uint64_t)d >> 32);
+  x.r0 = (int64_t)lo;
+  x.t = (int64_t)(hi & 0x1FFFFFFu);
+  x.n = (int64_t)((hi >> 25) & 63u) + 1;
+  x.core = (hi >> 31) != 0;
+  const int64_t j = min(x.t * DENSE_TILE + (lane & 15), M.nb - 1);
+  const int64_t r = x.r0 + min((int64_t)rowlane, x.n - 1);
+  x.b = M.bpk[j];
+  x.a = M.apk[r];
+  if (WIDE) {
+    x.bc = M.bc[j];
+    x.ac = M.ac[r];
+  }
+}
+
+template <typename T, int MUL>
+__device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t lim, int lane,
+                                         int rowlane, int64_t nb, uint32_t base) {
+  const bool vb = x.t * DENSE_TILE + (lane & 15) < nb;
+  const uint32_t off8 =
+      vb ? (uint32_t)(((int32_t)(uint32_t)x.b - (int32_t)L) * 8) : LANE_SENTINEL;
+  const uint32_t a8 = rowlane < x.n ? ((uint32_t)x.a << 3) : ROW_SENTINEL;
+  Coef<T, MUL> c;
+  if constexpr (MUL == 1 || MUL == 2 || MUL == 4) {
+    c.lo = (uint32_t)(x.a >> 32);
+    c.hi = 0;
+    c.bn = (int32_t)(uint32_t)(x.b >> 32);
+    if constexpr (MUL == 2) c.bn = (c.bn << 8) >> 8;
+    c.bw = T(0);
+  } else {
+    c.lo = (uint32_t)x.ac;
+    c.hi = (uint32_t)(x.ac >> 32);
+    c.bn = 0;
+    __builtin_memcpy(&c.bw, &x.bc, 8);
+  }
+  if (x.core)
+    item_steps<T, MUL, false>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c);
+  else
+    item_steps<T, MUL, true>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c);
+}
+
+// Items [ib, ie) of the task, wavefront w taking ib + w, ib + w + NW, ...;
+// the next item's rows and terms are loaded while the current one runs.
+template <typename T, int MUL, int BS>
+__device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t ie, int64_t L,
+                                          uint32_t S8, uint32_t base) {
+  constexpr int NW = BS / 64;
+  constexpr bool WIDE = MUL == 0 || MUL == 3;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int rowlane = lane;   // lane 16g + u holds row 16g + u of the item
+  // out-of-window pairs go to this lane's discard slot (or, within 64 slots
+  // past the window, to some discard slot)
+  const uint32_t lim = S8 + (uint32_t)lane * 8;
+  for (int64_t e0 = ib + wave; e0 < ie; e0 += (int64_t)NW * 64) {
+    const int64_t mine = e0 + (int64_t)NW * lane;
+    const uint64_t dv = mine < ie ? M.items[mine] : 0;
+    const int cnt = (int)min((int64_t)64, (ie - e0 + NW - 1) / NW);
+    // two register sets in turn, so that no load result is copied (a copy
+    // would wait for the load)
+    ItemRegs x0, x1;
+    fetch_item<WIDE>(M, readlane64(dv, 0), lane, rowlane, x0);
+    for (int k = 0; k + 1 < cnt; k += 2) {
+      fetch_item<WIDE>(M, readlane64(dv, k + 1), lane, rowlane, x1);
+      run_item<T, MUL>(x0, L, lim, lane, rowlane, M.nb, base);
+      fetch_item<WIDE>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, rowlane, x0);
+      run_item<T, MUL>(x1, L, lim, lane, rowlane, M.nb, base);
+    }
+    if (cnt & 1) run_item<T, MUL>(x0, L, lim, lane, rowlane, M.nb, base);
+  }
 }
 
 __device__ __forceinline__ void global_add(int64_t* p, int64_t v) {
@@ -491,123 +759,13 @@ __device__ __forceinline__ void global_add(int64_t* p, int64_t v) {
 }
 __device__ __forceinline__ void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-constexpr int64_t ITEM_ROWS = 128;   // rows of A per work item
-
-// A task owns the row visits [lo, hi) of its window, in the order (tile,
-// row).  They are cut into items of at most ITEM_ROWS rows of one tile,
-// listed in LDS and taken by wavefronts one at a time.
+// Flush of one window piece: compaction straight from LDS when the task
+// holds the whole window, else an add of its nonzero slots into HBM.
 template <typename T, int BS>
-__global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* win = reinterpret_cast<T*>(smem_raw);
-  __shared__ int32_t s_tile[DENSE_MAX_TILES_LDS];
-  __shared__ int32_t s_r0[DENSE_MAX_TILES_LDS];
-  __shared__ int32_t s_r1[DENSE_MAX_TILES_LDS];
-  __shared__ int64_t s_wave[BS / 64];
-  __shared__ int s_next;
-
-  const int64_t task = blockIdx.x;
-  if (task >= M.meta->ntasks) return;
-  const int64_t w = window_of(M.task_off, M.nwin, task);
-  const int64_t k = M.task_off[w + 1] - M.task_off[w];
-  const int64_t p = task - M.task_off[w];
-  const int64_t L = w * M.S;
-  const int64_t Sw = min(M.S, M.nkeys - L);
-  const int64_t* wtw = M.wt + w * M.ntiles;
-  const int64_t W = wtw[M.ntiles - 1];
-  const int64_t lo = W * p / k, hi = W * (p + 1) / k;
-  // tiles overlapping [lo, hi): tile t covers [wtw[t-1], wtw[t])
-  const int64_t t_begin = upper_bound(wtw, M.ntiles, lo);
-  const int64_t t_end = min(M.ntiles, upper_bound(wtw, M.ntiles, hi - 1) + 1);
-  const uint32_t narrow = M.meta->seg_flags[0] & M.meta->seg_flags[1];
+__device__ __forceinline__ void flush_window(const MulArgs& M, const T* win, int64_t L, int64_t Sw,
+                                             bool whole) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const T* bc = reinterpret_cast<const T*>(M.bc);
-  const uint32_t S8 = (uint32_t)(Sw * 8);
-  const int64_t bw = (int64_t)1 << M.shiftA;
-
-  for (int64_t i = tid; i < Sw; i += BS) win[i] = T(0);
-  int64_t t0 = t_begin;
-  while (t0 < t_end) {
-    // list items of tiles [t0, t1) until the LDS list would overflow
-    const int64_t t1 = min(t_end, t0 + BS);
-    const int64_t t = t0 + tid;
-    int64_t r0 = 0, r1 = 0;
-    if (t < t1) {
-      int64_t i0, i1;
-      rows_for(M.bstart, M.shiftA, M.nbkA, L - M.tmax[t], L + Sw - M.tmin[t], &i0, &i1);
-      const int64_t s0 = t == 0 ? 0 : wtw[t - 1];
-      r0 = i0 + max((int64_t)0, lo - s0);
-      r1 = i0 + min(i1 - i0, hi - s0);
-      if (r1 < r0) r1 = r0;
-    }
-    // at most 256 items per tile (longer tiles get longer items), so the
-    // first tile of a round always fits the list
-    const int64_t irows = max(ITEM_ROWS, (r1 - r0 + 255) / 256);
-    const int64_t nit = (r1 - r0 + irows - 1) / irows;
-    int64_t total;
-    const int64_t pos = block_exclusive_scan<BS>(nit, s_wave, &total);
-    // tiles whose items fit the list form a prefix of [t0, t1)
-    const bool fits = t < t1 && pos + nit <= DENSE_MAX_TILES_LDS;
-    if (fits)
-      for (int64_t q = 0; q < nit; ++q) {
-        s_tile[pos + q] = (int32_t)t;
-        s_r0[pos + q] = (int32_t)(r0 + q * irows);
-        s_r1[pos + q] = (int32_t)min(r1, r0 + (q + 1) * irows);
-      }
-    int64_t nitems;
-    block_exclusive_scan<BS>(fits ? nit : 0, s_wave, &nitems);
-    const uint64_t bal = __ballot(!fits && t < t1);
-    if (lane == 0) s_wave[wave] = bal ? (int64_t)(wave * 64 + __ffsll((long long)bal) - 1) : BS;
-    if (tid == 0) s_next = 0;
-    __syncthreads();
-    int64_t nlisted = BS;   // tiles listed this round
-    for (int u = 0; u < BS / 64; ++u) nlisted = min(nlisted, s_wave[u]);
-    // items: wavefronts take them dynamically
-    while (true) {
-      int e = 0;
-      if (lane == 0) e = atomicAdd(&s_next, 1);
-      e = __builtin_amdgcn_readfirstlane(__shfl(e, 0));
-      if (e >= nitems) break;
-      const int64_t tt = __builtin_amdgcn_readfirstlane(s_tile[e]);
-      const int64_t a0 = __builtin_amdgcn_readfirstlane(s_r0[e]);
-      const int64_t a1 = __builtin_amdgcn_readfirstlane(s_r1[e]);
-      const int64_t j = tt * 64 + lane;
-      const bool full = tt * 64 + 63 < M.nb;
-      const bool valid = j < M.nb;
-      const int64_t bj = valid ? M.bk[j] : 0;
-      const T cb = valid ? bc[j] : T(0);
-      const int64_t bmin = readfirst64(M.tmin[tt]), bmax = readfirst64(M.tmax[tt]);
-      const int64_t cj = L - bj;
-      const uint32_t off8 = (uint32_t)((uint64_t)(bj - L) << 3);
-      // rows whose bucket lies inside [L - bmin, L + Sw - bmax) hit for every lane
-      int64_t c0 = a0, c1 = a0;
-      const int64_t clo = L - bmin, chi = L + Sw - bmax;
-      if (full && chi > clo) {
-        const int64_t b0 = (max(clo, (int64_t)0) + bw - 1) >> M.shiftA;
-        const int64_t b1 = min(chi >> M.shiftA, M.nbkA);
-        if (b1 > b0) {
-          c0 = min(a1, max(a0, (int64_t)M.bstart[b0]));
-          c1 = max(c0, min(a1, (int64_t)M.bstart[b1]));
-        }
-      }
-      // byte offsets of the range test fit 32 bits while |slot| < 2^28
-      const bool wide = (bmax - bmin) + Sw + bw >= ((int64_t)1 << 28);
-      if constexpr (std::is_same<T, double>::value) {
-        tile_mul<T, 3>(win, M.ak, M.ac, a0, c0, c1, a1, wide, cj, off8, S8, valid, cb);
-      } else {
-        if (narrow & 2u)
-          tile_mul<T, 2>(win, M.ak, M.ac, a0, c0, c1, a1, wide, cj, off8, S8, valid, cb);
-        else if (narrow & 1u)
-          tile_mul<T, 1>(win, M.ak, M.ac, a0, c0, c1, a1, wide, cj, off8, S8, valid, cb);
-        else
-          tile_mul<T, 0>(win, M.ak, M.ac, a0, c0, c1, a1, wide, cj, off8, S8, valid, cb);
-      }
-    }
-    __syncthreads();
-    t0 += nlisted;
-  }
-
-  if (k > 1) {   // split window: add this task's nonzero slots into HBM
+  if (!whole) {
     T* d = reinterpret_cast<T*>(M.dense) + L;
     for (int64_t i = tid; i < Sw; i += BS) {
       const T v = win[i];
@@ -641,10 +799,48 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
   }
 }
 
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t task = blockIdx.x;
+  if (task >= M.meta->ntasks) return;
+  const int64_t ib = M.task_begin[task], ie = M.task_begin[task + 1];
+  const int tid = threadIdx.x;
+  T* win = reinterpret_cast<T*>(smem_raw);
+  // The kernel has no static LDS, so the window starts at LDS address 0 and
+  // the per-pair address arithmetic carries no base.
+  constexpr uint32_t base = 0;
+  const uint32_t narrow = M.meta->seg_flags[0] & M.meta->seg_flags[1];
+  const int64_t* ibase = M.win_ibase;
+  for (int64_t w = M.task_w[task]; w < M.nwin; ++w) {
+    const int64_t wb = ibase[w], we = ibase[w + 1];
+    if (wb >= ie) break;
+    const int64_t pb = max(ib, wb), pe = min(ie, we);
+    if (pe <= pb) continue;
+    const int64_t L = w * M.S;
+    const int64_t Sw = min(M.S, M.nkeys - L);
+    uint4* z = reinterpret_cast<uint4*>(smem_raw);
+    const int nz = (int)((Sw + DENSE_DUMMY) * 8 / 16);
+    __syncthreads();   // the previous piece's flush has read the window
+    for (int i = tid; i < nz; i += BS) z[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    const uint32_t S8 = (uint32_t)(Sw * 8);
+    if constexpr (std::is_same<T, double>::value) {
+      run_items<T, 3, BS>(M, pb, pe, L, S8, base);
+    } else {
+      if (narrow & 4u) run_items<T, 4, BS>(M, pb, pe, L, S8, base);
+      else if (narrow & 2u) run_items<T, 2, BS>(M, pb, pe, L, S8, base);
+      else if (narrow & 1u) run_items<T, 1, BS>(M, pb, pe, L, S8, base);
+      else run_items<T, 0, BS>(M, pb, pe, L, S8, base);
+    }
+    __syncthreads();
+    flush_window<T, BS>(M, win, L, Sw, pb == wb && pe == we);
+  }
+}
+
 // ------------------------------------------------------------------ split windows
 struct CombineArgs {
-  const Meta* meta;
-  const int64_t* task_off;
+  const int64_t* win_split;
   int64_t nwin, S, nkeys;
   const int64_t* dense;
   int64_t* stage_k;
@@ -662,7 +858,7 @@ __global__ void __launch_bounds__(COMBINE_BLOCK) k_dense_combine(CombineArgs C) 
   __shared__ int64_t s_wave[COMBINE_BLOCK / 64];
   const int64_t cpw = C.S / DENSE_CHUNK;
   const int64_t w = blockIdx.x / cpw, c = blockIdx.x - w * cpw;
-  if (C.task_off[w + 1] - C.task_off[w] < 2) return;
+  if (!C.win_split[w]) return;
   const int64_t L = w * C.S;
   const int64_t Sw = min(C.S, C.nkeys - L);
   const int64_t s0 = c * DENSE_CHUNK;
@@ -731,7 +927,9 @@ __global__ void __launch_bounds__(1024) k_dense_scan(ScanArgs A) {
     run += A.ccount[c];
   }
   if (threadIdx.x == 0) {
-    uint32_t e = A.meta->err | A.meta->seg_err[0] | A.meta->seg_err[1];
+    // errors of this call, and any latched on the context by an earlier
+    // asynchronous call (an encode that found an exponent out of range)
+    uint32_t e = A.meta->err | A.meta->seg_err[0] | A.meta->seg_err[1] | *A.ctx_err;
     if (total > A.out_cap) e |= ERR_CAPACITY;
     if (e) {
       atomicOr(A.ctx_err, e);
@@ -766,17 +964,26 @@ __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
   }
 }
 
+// Raises the window kernel's dynamic LDS limit and checks that it has no
+// static LDS (its window must start at LDS address 0).
 template <typename T, int BS>
 hipError_t set_lds_limit() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_mul<T, BS>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)DENSE_LDS_BYTES);
+  const void* f = reinterpret_cast<const void*>(&k_dense_mul<T, BS>);
+  hipFuncAttributes at{};
+  hipError_t e = hipFuncGetAttributes(&at, f);
+  if (e != hipSuccess) return e;
+  if (at.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DENSE_LDS_BYTES);
 }
 
 }  // namespace
 
-int dense_bucket_shift(int64_t maxcode) {
+int dense_bucket_shift(int64_t maxcode, int64_t n) {
+  // about two buckets per term (at least 4096, at most DENSE_MAX_BUCKETS):
+  // fine enough for the row ranges, small enough for a quick scan
+  const int64_t want = std::min(DENSE_MAX_BUCKETS, std::max((int64_t)4096, 2 * n));
   int s = 0;
-  while (((maxcode >> s) + 1) > DENSE_MAX_BUCKETS) ++s;
+  while (((maxcode >> s) + 1) > want) ++s;
   return s;
 }
 
@@ -786,6 +993,9 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_prep),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(DENSE_MAX_BUCKETS * 4));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_items),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ITEMS_LDS_BYTES);
     if (e == hipSuccess) e = set_lds_limit<int64_t, 256>();
     if (e == hipSuccess) e = set_lds_limit<int64_t, 512>();
     if (e == hipSuccess) e = set_lds_limit<int64_t, 1024>();
@@ -796,23 +1006,31 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
     attrs = true;
   }
   PrepArgs pa{};
-  pa.seg[0] = PrepSeg{B.a_keys_in, B.a_coef_in, B.na, P.shiftA, P.nbkA, P.maxcodeA, B.ak, B.ac,
+  pa.seg[0] = PrepSeg{B.a_keys_in, B.a_coef_in, B.na, P.shiftA, P.nbkA, P.maxcodeA, B.apk, B.ac,
                       B.rank_a, B.bstart, nullptr, nullptr, nullptr, 0};
-  pa.seg[1] = PrepSeg{B.b_keys_in, B.b_coef_in, B.nb, P.shiftB, P.nbkB, P.maxcodeB, B.bk, B.bc,
-                      B.rank_b, nullptr, B.tmin, B.tmax, B.ccount, P.nchunk};
+  pa.seg[1] = PrepSeg{B.b_keys_in, B.b_coef_in, B.nb, P.shiftB, P.nbkB, P.maxcodeB, B.bpk, B.bc,
+                      B.rank_b, B.bstartB, B.tmin, B.tmax, B.ccount, P.nchunk};
   pa.meta = B.meta;
   pa.is_i64 = dt == KP_I64;
   const size_t hist_bytes = (size_t)std::max(P.nbkA, P.nbkB) * 4;
   hipLaunchKernelGGL(k_dense_prep, dim3(2), dim3(PREP_BLOCK), hist_bytes, s, pa);
+  const int64_t blocksA = (B.na + SCATTER_BLOCK - 1) / SCATTER_BLOCK;
+  const int64_t blocksB = (B.nb + SCATTER_BLOCK - 1) / SCATTER_BLOCK;
+  hipLaunchKernelGGL(k_dense_scatter, dim3((unsigned)(blocksA + blocksB)), dim3(SCATTER_BLOCK), 0,
+                     s, pa, blocksA);
 
-  PlanArgs pl{P.S, P.nwin, P.ntiles, P.nkeys, P.target_tasks, P.min_work, B.bstart, P.shiftA,
-              P.nbkA, B.tmin, B.tmax, B.wt, B.task_off, B.dense, B.meta};
-  hipLaunchKernelGGL(k_dense_plan, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK), 0, s, pl);
+  PlanArgs pl{P.S, P.nwin, P.ntiles, P.nkeys, B.nb, P.target_tasks, P.min_work, P.items_cap,
+              ITEMS_LDS_BYTES,
+              B.bstart, P.shiftA, P.nbkA, B.tmin, B.tmax, B.win, B.recs, B.items, B.task_w,
+              B.task_begin, B.dense, B.meta};
+  hipLaunchKernelGGL(k_dense_count, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK), 0, s, pl);
+  hipLaunchKernelGGL(k_dense_items, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK),
+                     (size_t)ITEMS_LDS_BYTES, s, pl);
 
-  MulArgs ma{B.meta, B.ak, reinterpret_cast<const uint64_t*>(B.ac), B.bstart, P.shiftA, P.nbkA,
-             B.bk, B.bc, B.nb, P.ntiles, P.S, P.nwin, P.nkeys, B.tmin, B.tmax, B.wt, B.task_off,
-             B.dense, B.stage_k, B.stage_c, B.ccount};
-  const size_t lds = (size_t)P.S * 8;
+  const int64_t W1 = P.nwin + 1;
+  MulArgs ma{B.meta, B.apk, B.ac, B.bpk, B.bc, B.nb, P.S, P.nwin, P.nkeys, B.items, B.task_w,
+             B.task_begin, B.win + W_IBASE * W1, B.dense, B.stage_k, B.stage_c, B.ccount};
+  const size_t lds = (size_t)(P.S + DENSE_DUMMY) * 8;
   const unsigned grid = (unsigned)P.max_tasks;
   if (B.ev0) (void)hipEventRecord(B.ev0, s);
 #define KP_DENSE_LAUNCH(TT, BSZ) \
@@ -829,7 +1047,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
 #undef KP_DENSE_LAUNCH
   if (B.ev1) (void)hipEventRecord(B.ev1, s);
 
-  CombineArgs cb{B.meta, B.task_off, P.nwin, P.S, P.nkeys, B.dense, B.stage_k, B.stage_c,
+  CombineArgs cb{B.win + W_SPLIT * W1, P.nwin, P.S, P.nkeys, B.dense, B.stage_k, B.stage_c,
                  B.ccount};
   const unsigned cgrid = (unsigned)(P.nwin * (P.S / DENSE_CHUNK));
   if (dt == KP_F64)

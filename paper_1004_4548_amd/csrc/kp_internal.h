@@ -150,7 +150,8 @@ struct Meta {
   uint32_t seg_err[2];    // dense: error bits found while sorting factor A / B
   uint32_t plan_done;     // dense: planning workgroups finished
   uint32_t pad32;
-  int64_t pad[2];
+  int64_t task_rows;      // dense: cost of a task (work items plus window overheads)
+  int64_t pad;
 };
 
 // Status block owned by a context (device memory, 256 bytes).
@@ -177,21 +178,25 @@ hipError_t launch_coef_range(const int64_t* a, int64_t na, const int64_t* b, int
 
 // dense Laurent
 constexpr int64_t DENSE_MAX_BUCKETS = 32768;   // bucket-sort histogram slots (LDS)
-constexpr int DENSE_MAX_TILES_LDS = 1024;      // per-task tile list held in LDS
 constexpr int64_t DENSE_CHUNK = 2048;          // output segment (codes)
-constexpr int64_t DENSE_MAX_WINDOW = 16384;    // LDS slots of one window (8 bytes each)
-constexpr size_t DENSE_LDS_BYTES = DENSE_MAX_WINDOW * 8;
-int dense_bucket_shift(int64_t maxcode);
+constexpr int64_t DENSE_MAX_WINDOW = 18432;    // LDS slots of one window (8 bytes each)
+constexpr int64_t DENSE_DUMMY = 64;            // per-lane discard slots after the window
+constexpr size_t DENSE_LDS_BYTES = (DENSE_MAX_WINDOW + DENSE_DUMMY) * 8;
+constexpr int64_t DENSE_TILE = 16;             // terms of B per tile (one 16-lane row)
+constexpr int64_t DENSE_ITEM_ROWS = 64;        // rows of A per work item
+constexpr int64_t DENSE_MAX_CODES = (int64_t)1 << 27;   // codes of a dense key space
+int dense_bucket_shift(int64_t maxcode, int64_t n);
 
 struct DensePlan {
   int64_t S;             // window (codes), a multiple of DENSE_CHUNK
   int64_t nwin;          // ceil(nkeys / S)
-  int64_t ntiles;        // ceil(nb / 64)
+  int64_t ntiles;        // ceil(nb / DENSE_TILE)
   int64_t nkeys;
   int64_t nchunk;        // ceil(nkeys / DENSE_CHUNK)
   int64_t target_tasks;  // tasks wanted (compute units x tasks per unit)
-  int64_t max_tasks;     // upper bound on tasks: target + nwin
+  int64_t max_tasks;     // upper bound on tasks (= target)
   int64_t min_work;      // row visits below which a window is not split
+  int64_t items_cap;     // bound on work items (see dense_items_bound)
   int shiftA, shiftB;    // bucket widths 2^shift of the factor sorts
   int64_t nbkA, nbkB;    // buckets
   int64_t maxcodeA, maxcodeB;   // largest code of each factor's box
@@ -202,13 +207,17 @@ struct DenseBufs {
   const int64_t* a_keys_in; const int64_t* a_coef_in;
   const int64_t* b_keys_in; const int64_t* b_coef_in;
   int64_t na, nb;
-  int64_t* ak; int64_t* ac;     // A bucket-sorted
-  int64_t* bk; int64_t* bc;     // B bucket-sorted
+  uint64_t* apk; uint64_t* ac;  // A bucket-sorted: {code, low coefficient word}, coefficient
+  uint64_t* bpk; uint64_t* bc;  // B bucket-sorted, same layout
   int32_t* rank_a; int32_t* rank_b;
   int32_t* bstart;              // [nbkA + 1] first row of each bucket of A
+  int32_t* bstartB;             // [nbkB + 1] first term of each bucket of B
   int64_t* tmin; int64_t* tmax; // [ntiles] code range of each tile of B
-  int64_t* wt;                  // [nwin * ntiles] inclusive row-visit prefix per window
-  int64_t* task_off;            // [nwin + 1] first task of each window
+  int64_t* win;                 // [5 * (nwin + 1)]: items, rows, split flag, item base, cost base
+  int4* recs;                   // [nwin * ntiles] rows of A visited by each (window, tile)
+  uint64_t* items;              // [items_cap] work items
+  int32_t* task_w;              // [max_tasks] window of each task
+  int32_t* task_begin;          // [max_tasks + 1] first item of each task
   int64_t* dense;               // [nwin * S] accumulator of windows split across tasks
   int64_t* stage_k; int64_t* stage_c;   // [nchunk * DENSE_CHUNK] compacted chunks
   int64_t* ccount;              // [nchunk] terms per chunk

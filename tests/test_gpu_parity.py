@@ -182,7 +182,7 @@ def test_laurent_many_windows_and_split_windows():
     ctx = kp.context()
     a, b = I.config(2, scale=0.3)
     for window, block, tpc in ((2048, 256, 64), (4096, 512, 16), (16384, 1024, 8),
-                               (16384, 1024, 1)):
+                               (18432, 1024, 1)):
         ctx.set_tune(window=window, block=block, tasks_per_cu=tpc)
         check_laurent(a, b, "dense", f"window {window} block {block} tasks/CU {tpc}")
         a64 = (a[0], a[1].astype(np.float64) / 4)

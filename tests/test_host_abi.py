@@ -220,11 +220,11 @@ def test_planning_errors():
 def test_tune_validation():
     ctx = _host_ctx()
     t = ctx.tune
-    assert t.window == 16384 and t.block == 1024
+    assert t.window == 18432 and t.block == 1024 and t.tasks_per_cu == 1
     ctx.set_tune(window=2048, block=512)
     assert ctx.tune.window == 2048
-    for bad in (dict(window=20480 + 1024), dict(block=100), dict(hash_load=0.95),
-                dict(window=1000, block=256)):
+    for bad in (dict(window=18432 + 2048), dict(block=100), dict(hash_load=0.95),
+                dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
 
