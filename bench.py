@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (sparse, Poisson, small)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--requests", type=int, default=300,
+                    help="requests of the mixed stream for the serving measurement (0: skip)")
+    ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run device-to-device copies of 256 MiB (a plain copy kernel of "
                          "known size, used to scale HBM byte counters)")
@@ -141,6 +144,40 @@ def measure_poisson(kp, ctx, a, b, mode, steps, warmup):
     kms, launches = ctx.timing_read()
     ctx.timing(False)
     return dict(sec=sec, kernel_s=kms / 1e3 / max(launches, 1), n_out=n_out)
+
+
+def measure_serving(kp, n_requests, max_batch):
+    """The mixed request stream: per-call vs batched throughput (closed loop,
+    all requests available), then continuous batching under Poisson arrivals
+    at 0.8 x the batched capacity, with p50/p99 latency."""
+    import torch
+    from paper_1004_4548_amd import inputs as I
+    from paper_1004_4548_amd import serve
+    reqs = [I.request(r) for r in range(n_requests)]
+    st = serve.stage(reqs)
+    pairs = sum(s.pairs for s in st)
+    serve.run_per_call(st[:4])
+    serve.run_batch(st[:4])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, lat_pc = serve.run_per_call(st)
+    per_call_s = time.perf_counter() - t
+    batched_s = serve.closed_loop(st, max_batch=max_batch)
+    rate = 0.8 * n_requests / batched_s
+    lat, wall = serve.open_loop(st, rate, max_batch=max_batch)
+    kinds = {t: sum(1 for q in reqs if q["type"] == t) for t in (1, 2, 3)}
+    return {
+        "requests": n_requests, "term_products": pairs, "types": kinds,
+        "per_call": {"term_products_per_s": pairs / per_call_s, "seconds": per_call_s,
+                     **serve.percentiles(np.array(lat_pc))},
+        "batched": {"term_products_per_s": pairs / batched_s, "seconds": batched_s,
+                    "max_batch": max_batch},
+        "batched_over_per_call": per_call_s / batched_s,
+        "serving": {"arrival_rate_per_s": rate, "term_products_per_s": pairs / wall,
+                    "seconds": wall, **serve.percentiles(lat)},
+        "workload": "mixed request stream (types 1-3, 2-6 variables, sizes log-uniform in "
+                    "[50, 20000], int64 or fp64), first requests of the seeded stream",
+    }
 
 
 def cpu_baseline(a, b, seconds):
@@ -223,6 +260,8 @@ def main():
                                       "result_terms": r4["n_out"],
                                       "insert_kernel_ms": r4["kernel_s"] * 1e3}
         out["other_workloads"] = extra
+    if args.requests > 0:
+        out["stream"] = measure_serving(kp, args.requests, args.max_batch)
     if args.calibrate_copy:
         n = 256 << 20
         x = torch.ones(n, dtype=torch.uint8, device="cuda")

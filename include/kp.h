@@ -239,6 +239,58 @@ kp_status kp_decode(kp_ctx* ctx, const kp_layout* layout, int poisson, int64_t n
                     unsigned flags, hipStream_t stream);
 
 /*
+ * Batches: many products queued by one call (a systems pattern; it does not
+ * change what any product computes).  A batch holds up to max_tasks
+ * descriptors, each the arguments of one kp_mul_laurent or kp_mul_poisson
+ * call, copied in by kp_batch_add (the layout by value; the arrays stay owned
+ * by the caller and must stay valid while the batch is used).  kp_batch_add
+ * runs every host check of the single call and reports its errors at once.
+ *
+ * kp_batch_launch queues all tasks in order on `stream` and returns without
+ * synchronising; each task's out_n receives its term count or -(status).
+ * With KP_BATCH_GRAPH the first launch captures the queued kernels into a
+ * HIP graph and later launches replay it: the same tasks on the same arrays
+ * (their contents may change between launches); capture needs a stream other
+ * than the null stream.  kp_batch_add and
+ * kp_batch_clear drop the graph.  kp_batch_status synchronises the stream of
+ * the last launch and returns one task's count (status = its error, if any).
+ * Tasks of one batch must not share workspace or output arrays.
+ */
+typedef enum { KP_KIND_LAURENT = 0, KP_KIND_POISSON = 1 } kp_kind;
+enum { KP_BATCH_GRAPH = 2 };
+
+typedef struct kp_mul_desc {
+  kp_kind kind;
+  kp_layout layout;            /* product layout (kp_layout_product)                */
+  kp_dtype dtype;              /* Laurent coefficient type; Poisson is fp64         */
+  kp_mode mode;
+  const int64_t* a_codes;      /* device: Laurent codes, or Poisson x codes [na]    */
+  const int64_t* a_y;          /* device: Poisson trig codes [na] (else null)       */
+  const uint8_t* a_sin;        /* device: Poisson sine flags [na] (else null)       */
+  const void* a_coef;          /* device: coefficients [na]                         */
+  int64_t na;
+  const int64_t* b_codes;
+  const int64_t* b_y;
+  const uint8_t* b_sin;
+  const void* b_coef;
+  int64_t nb;
+  int64_t* out_codes;          /* device: result codes / keys [out_cap]             */
+  void* out_coef;              /* device: result coefficients [out_cap]             */
+  int64_t out_cap;
+  int64_t* out_n;              /* device: int64[1]                                  */
+  void* workspace;             /* device: kp_mul_bound's workspace_bytes            */
+  size_t workspace_bytes;
+} kp_mul_desc;
+
+typedef struct kp_batch kp_batch;
+kp_status kp_batch_create(kp_ctx* ctx, int64_t max_tasks, kp_batch** out);
+kp_status kp_batch_destroy(kp_batch* batch);
+kp_status kp_batch_add(kp_batch* batch, const kp_mul_desc* desc, int64_t* task_id);
+kp_status kp_batch_clear(kp_batch* batch);
+kp_status kp_batch_launch(kp_batch* batch, unsigned flags, hipStream_t stream);
+kp_status kp_batch_status(kp_batch* batch, int64_t task_id, int64_t* n_out);
+
+/*
  * Host-memory twins of kp_encode / kp_decode, running the same per-term code
  * map on the CPU (for callers without a device and for checking tables).
  * Errors are returned directly.

@@ -29,6 +29,8 @@ KP_E_CAPACITY, KP_E_WORKSPACE, KP_E_DEVICE, KP_E_DTYPE, KP_E_MODE = 5, 6, 7, 8, 
 KP_I64, KP_F64 = 0, 1
 KP_AUTO, KP_DENSE, KP_HASH = 0, 1, 2
 KP_FLAG_ASYNC = 1
+KP_BATCH_GRAPH = 2
+KP_KIND_LAURENT, KP_KIND_POISSON = 0, 1
 MODES = {"auto": KP_AUTO, "dense": KP_DENSE, "hash": KP_HASH}
 MODE_NAMES = {v: k for k, v in MODES.items()}
 
@@ -36,7 +38,8 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_ctx_check", "kp_status_str", "kp_last_error", "kp_ctx_timing",
             "kp_ctx_timing_read", "kp_minmax", "kp_layout_product",
             "kp_encode", "kp_mul_bound", "kp_mul_laurent", "kp_mul_poisson", "kp_decode",
-            "kp_encode_host", "kp_decode_host"]
+            "kp_encode_host", "kp_decode_host", "kp_batch_create", "kp_batch_destroy",
+            "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status"]
 
 
 class KPError(RuntimeError):
@@ -61,6 +64,16 @@ class Tune(C.Structure):
                 ("hash_load", C.c_double), ("hash_capacity", C.c_int64),
                 ("dense_max_keys", C.c_int64), ("dense_keys_per_pair", C.c_double),
                 ("hash_rows", C.c_int32)]
+
+
+class MulDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("layout", Layout), ("dtype", C.c_int32),
+                ("mode", C.c_int32), ("a_codes", C.c_void_p), ("a_y", C.c_void_p),
+                ("a_sin", C.c_void_p), ("a_coef", C.c_void_p), ("na", C.c_int64),
+                ("b_codes", C.c_void_p), ("b_y", C.c_void_p), ("b_sin", C.c_void_p),
+                ("b_coef", C.c_void_p), ("nb", C.c_int64), ("out_codes", C.c_void_p),
+                ("out_coef", C.c_void_p), ("out_cap", C.c_int64), ("out_n", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -98,6 +111,12 @@ def lib():
         "kp_decode": (i32, [p, C.POINTER(Layout), i32, i64, p, p, p, p, u32, p]),
         "kp_encode_host": (i32, [C.POINTER(Layout), i32, i64, p, p, p, p, p]),
         "kp_decode_host": (i32, [C.POINTER(Layout), i32, i64, p, p, p, p]),
+        "kp_batch_create": (i32, [p, i64, C.POINTER(p)]),
+        "kp_batch_destroy": (i32, [p]),
+        "kp_batch_add": (i32, [p, C.POINTER(MulDesc), C.POINTER(i64)]),
+        "kp_batch_clear": (i32, [p]),
+        "kp_batch_launch": (i32, [p, u32, p]),
+        "kp_batch_status": (i32, [p, i64, C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -481,3 +500,80 @@ def mul_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, works
                                       (kxb, kyb, b.is_sin, b.coef), mode, ctx, workspace)
     x, y, t = decode(lay, keys, poisson=True, ctx=ctx, flags=KP_FLAG_ASYNC)
     return PoissonSeries(x, y, t, coef), lay
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """kp_batch: many products queued by one call, optionally captured once
+    into a HIP graph and replayed.  Descriptors reference the caller's
+    tensors, which this object keeps alive until clear()."""
+
+    def __init__(self, max_tasks, ctx=None):
+        self.ctx = ctx or context()
+        h = C.c_void_p()
+        self.ctx.check(lib().kp_batch_create(self.ctx.h, max_tasks, C.byref(h)))
+        self.h = h
+        self._keep = []
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.kp_batch_destroy(self.h)
+            self.h = None
+
+    def _add(self, d, tensors):
+        tid = C.c_int64()
+        self.ctx.check(lib().kp_batch_add(self.h, C.byref(d), C.byref(tid)))
+        self._keep.append(tensors)
+        return tid.value
+
+    def add_laurent(self, layout, a_codes, a_coef, b_codes, b_coef, out, workspace, mode="auto"):
+        """Queue a Laurent product; `out` = (codes, coef, count) device tensors,
+        `workspace` a uint8 device tensor of kp_mul_bound's size."""
+        oc, ov, on = out
+        d = MulDesc(kind=KP_KIND_LAURENT, layout=layout, dtype=_dt(a_coef),
+                    mode=MODES[mode] if isinstance(mode, str) else mode,
+                    a_codes=a_codes.data_ptr(), a_coef=a_coef.data_ptr(), na=a_codes.shape[0],
+                    b_codes=b_codes.data_ptr(), b_coef=b_coef.data_ptr(), nb=b_codes.shape[0],
+                    out_codes=oc.data_ptr(), out_coef=ov.data_ptr(), out_cap=oc.shape[0],
+                    out_n=on.data_ptr(), workspace=workspace.data_ptr(),
+                    workspace_bytes=workspace.numel())
+        return self._add(d, (a_codes, a_coef, b_codes, b_coef, oc, ov, on, workspace))
+
+    def add_poisson(self, layout, a, b, out, workspace, mode="auto"):
+        """Queue a Poisson product of coded series a, b = (x, y, is_sin, coef)."""
+        ok, ov, on = out
+        d = MulDesc(kind=KP_KIND_POISSON, layout=layout, dtype=KP_F64,
+                    mode=MODES[mode] if isinstance(mode, str) else mode,
+                    a_codes=a[0].data_ptr(), a_y=a[1].data_ptr(), a_sin=a[2].data_ptr(),
+                    a_coef=a[3].data_ptr(), na=a[0].shape[0], b_codes=b[0].data_ptr(),
+                    b_y=b[1].data_ptr(), b_sin=b[2].data_ptr(), b_coef=b[3].data_ptr(),
+                    nb=b[0].shape[0], out_codes=ok.data_ptr(), out_coef=ov.data_ptr(),
+                    out_cap=ok.shape[0], out_n=on.data_ptr(), workspace=workspace.data_ptr(),
+                    workspace_bytes=workspace.numel())
+        return self._add(d, (*a, *b, ok, ov, on, workspace))
+
+    def launch(self, graph=False, stream=None):
+        """Queue every task (replaying the captured graph when `graph`).  A
+        graph is captured on a side stream of this batch, ordered after and
+        before the current stream's work."""
+        import torch
+        cur = torch.cuda.current_stream() if stream is None else stream
+        if not graph:
+            self.ctx.check(lib().kp_batch_launch(self.h, 0, _stream(cur)))
+            return
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream()
+        self._side.wait_stream(cur)
+        self.ctx.check(lib().kp_batch_launch(self.h, KP_BATCH_GRAPH, _stream(self._side)))
+        cur.wait_stream(self._side)
+
+    def status(self, task):
+        n = C.c_int64()
+        st = lib().kp_batch_status(self.h, task, C.byref(n))
+        if st != KP_OK:
+            raise KPError(st, status_str(st))
+        return n.value
+
+    def clear(self):
+        self.ctx.check(lib().kp_batch_clear(self.h))
+        self._keep = []

@@ -361,6 +361,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
     ctx->num_cu = cus;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->status), sizeof(CtxStatus));
   if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(CtxStatus));
+  if (e == hipSuccess) e = dense_setup();
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     delete ctx;
@@ -553,11 +554,17 @@ kp_status kp_mul_bound(kp_ctx* ctx, const kp_layout* layout, int poisson, kp_dty
   return KP_OK;
 }
 
-kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
-                         unsigned flags, const int64_t* a_codes, const void* a_coef, int64_t na,
-                         const int64_t* b_codes, const void* b_coef, int64_t nb,
-                         int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
-                         void* workspace, size_t workspace_bytes, hipStream_t stream) {
+namespace kp {
+namespace {
+
+// Queues one Laurent product (no synchronisation).  `timed`: record the
+// context's timing events around the accumulation kernel when enabled.
+kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                          const int64_t* a_codes, const void* a_coef, int64_t na,
+                          const int64_t* b_codes, const void* b_coef, int64_t nb,
+                          int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream,
+                          bool timed) {
   if (!ctx) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   Plan p;
@@ -585,7 +592,7 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
     B.out_n = out_n;
     B.ctx_err = &ctx->status->err;
     if (!empty) {
-      std::tie(B.ev0, B.ev1) = timing_pair(ctx);
+      if (timed) std::tie(B.ev0, B.ev1) = timing_pair(ctx);
       e = launch_dense_laurent(p.dp, B, dtype, stream);
     } else {
       e = launch_meta_init(B.meta, stream);
@@ -596,7 +603,7 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
     carve_hash(c, p, 0, na, nb, &h);
     HashBufs H{h.meta, h.table, p.cap, p.cap, out_codes, out_coef, out_cap,
                nullptr, nullptr};
-    if (!empty) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    if (!empty && timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
     if (!empty) {
       if (e == hipSuccess && dtype == KP_I64)
@@ -611,16 +618,16 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
     if (e == hipSuccess) e = launch_finalize(h.meta, out_cap, out_n, &ctx->status->err, stream);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent launch");
-  return finish(ctx, flags, stream, "kp_mul_laurent");
+  return KP_OK;
 }
 
-kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
-                         const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
-                         const double* a_coef, int64_t na, const int64_t* b_x,
-                         const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
-                         int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
-                         int64_t* out_n, void* workspace, size_t workspace_bytes,
-                         hipStream_t stream) {
+kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
+                          const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
+                          const double* a_coef, int64_t na, const int64_t* b_x,
+                          const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                          int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
+                          int64_t* out_n, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream, bool timed) {
   if (!ctx) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   if (layout && layout->ny == 0) return fail(ctx, KP_E_ARG, "kp_mul_poisson: layout has ny == 0");
@@ -640,7 +647,7 @@ kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, uns
              nullptr, nullptr};
   hipError_t e = launch_meta_init(h.meta, stream);
   if (na > 0 && nb > 0 && layout->nkeys > 0) {
-    std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * p.cap, stream);
     if (e == hipSuccess)
       e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream);
@@ -651,7 +658,173 @@ kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, uns
   }
   if (e == hipSuccess) e = launch_finalize(h.meta, out_cap, out_n, &ctx->status->err, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson launch");
-  return finish(ctx, flags, stream, "kp_mul_poisson");
+  return KP_OK;
+}
+
+kp_status enqueue_desc(kp_ctx* ctx, const kp_mul_desc& d, hipStream_t stream) {
+  if (d.kind == KP_KIND_POISSON)
+    return enqueue_poisson(ctx, &d.layout, d.mode, d.a_codes, d.a_y, d.a_sin,
+                           (const double*)d.a_coef, d.na, d.b_codes, d.b_y, d.b_sin,
+                           (const double*)d.b_coef, d.nb, d.out_codes, (double*)d.out_coef,
+                           d.out_cap, d.out_n, d.workspace, d.workspace_bytes, stream, false);
+  return enqueue_laurent(ctx, &d.layout, d.dtype, d.mode, d.a_codes, d.a_coef, d.na, d.b_codes,
+                         d.b_coef, d.nb, d.out_codes, d.out_coef, d.out_cap, d.out_n, d.workspace,
+                         d.workspace_bytes, stream, false);
+}
+
+}  // namespace
+}  // namespace kp
+
+kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                         unsigned flags, const int64_t* a_codes, const void* a_coef, int64_t na,
+                         const int64_t* b_codes, const void* b_coef, int64_t nb,
+                         int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  kp_status st = kp::enqueue_laurent(ctx, layout, dtype, mode, a_codes, a_coef, na, b_codes,
+                                     b_coef, nb, out_codes, out_coef, out_cap, out_n, workspace,
+                                     workspace_bytes, stream, true);
+  if (st != KP_OK) return st;
+  return kp::finish(ctx, flags, stream, "kp_mul_laurent");
+}
+
+kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
+                         const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
+                         const double* a_coef, int64_t na, const int64_t* b_x,
+                         const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                         int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
+                         int64_t* out_n, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  kp_status st = kp::enqueue_poisson(ctx, layout, mode, a_x, a_y, a_sin, a_coef, na, b_x, b_y,
+                                     b_sin, b_coef, nb, out_keys, out_coef, out_cap, out_n,
+                                     workspace, workspace_bytes, stream, true);
+  if (st != KP_OK) return st;
+  return kp::finish(ctx, flags, stream, "kp_mul_poisson");
+}
+
+// ------------------------------------------------------------ batches
+struct kp_batch {
+  kp_ctx* ctx = nullptr;
+  int64_t max_tasks = 0;
+  std::vector<kp_mul_desc> tasks;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+};
+
+namespace {
+void drop_graph(kp_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+}  // namespace
+
+kp_status kp_batch_create(kp_ctx* ctx, int64_t max_tasks, kp_batch** out) {
+  if (!ctx || !out || max_tasks < 1) return KP_E_ARG;
+  if (!ctx->status) return kp::fail(ctx, KP_E_ARG, "host-only context");
+  kp_batch* b = new (std::nothrow) kp_batch;
+  if (!b) return kp::fail(ctx, KP_E_DEVICE, "out of host memory");
+  b->ctx = ctx;
+  b->max_tasks = max_tasks;
+  b->tasks.reserve((size_t)max_tasks);
+  *out = b;
+  return KP_OK;
+}
+
+kp_status kp_batch_destroy(kp_batch* b) {
+  if (!b) return KP_E_ARG;
+  drop_graph(b);
+  delete b;
+  return KP_OK;
+}
+
+kp_status kp_batch_clear(kp_batch* b) {
+  if (!b) return KP_E_ARG;
+  drop_graph(b);
+  b->tasks.clear();
+  return KP_OK;
+}
+
+kp_status kp_batch_add(kp_batch* b, const kp_mul_desc* d, int64_t* task_id) {
+  if (!b || !d) return KP_E_ARG;
+  kp_ctx* ctx = b->ctx;
+  if ((int64_t)b->tasks.size() >= b->max_tasks)
+    return kp::fail(ctx, KP_E_ARG, "batch holds %lld tasks already", (long long)b->max_tasks);
+  if (d->kind != KP_KIND_LAURENT && d->kind != KP_KIND_POISSON)
+    return kp::fail(ctx, KP_E_ARG, "bad task kind %d", (int)d->kind);
+  // host checks now, so that a launch queues only valid work
+  kp::Plan p;
+  kp_status st = kp::make_plan(ctx, &d->layout, d->kind == KP_KIND_POISSON,
+                               d->kind == KP_KIND_POISSON ? KP_F64 : d->dtype, d->mode, d->na,
+                               d->nb, &p);
+  if (st != KP_OK) return st;
+  if (!d->out_n || d->out_cap < 0 || (d->out_cap > 0 && (!d->out_codes || !d->out_coef)) ||
+      (d->na > 0 && (!d->a_codes || !d->a_coef)) || (d->nb > 0 && (!d->b_codes || !d->b_coef)))
+    return kp::fail(ctx, KP_E_ARG, "kp_batch_add: null array or negative capacity");
+  if (d->kind == KP_KIND_POISSON && ((d->na > 0 && (!d->a_y || !d->a_sin)) ||
+                                     (d->nb > 0 && (!d->b_y || !d->b_sin))))
+    return kp::fail(ctx, KP_E_ARG, "kp_batch_add: null trigonometric array");
+  if (d->workspace_bytes < p.ws || (p.ws > 0 && !d->workspace))
+    return kp::fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed",
+                    d->workspace_bytes, p.ws);
+  drop_graph(b);
+  b->tasks.push_back(*d);
+  if (task_id) *task_id = (int64_t)b->tasks.size() - 1;
+  return KP_OK;
+}
+
+kp_status kp_batch_launch(kp_batch* b, unsigned flags, hipStream_t stream) {
+  if (!b) return KP_E_ARG;
+  kp_ctx* ctx = b->ctx;
+  hipError_t e = hipSuccess;
+  if (flags & KP_BATCH_GRAPH) {
+    if (!stream)
+      return kp::fail(ctx, KP_E_ARG, "graph capture needs a stream other than the null stream");
+    if (!b->exec) {
+      // capture the queued work once; later launches replay it
+      e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return kp::hip_fail(ctx, e, "hipStreamBeginCapture");
+      kp_status st = KP_OK;
+      for (const kp_mul_desc& d : b->tasks) {
+        st = kp::enqueue_desc(ctx, d, stream);
+        if (st != KP_OK) break;
+      }
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(stream, &g);
+      if (st != KP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return kp::hip_fail(ctx, e, "hipStreamEndCapture");
+      b->graph = g;
+      e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        drop_graph(b);
+        return kp::hip_fail(ctx, e, "hipGraphInstantiate");
+      }
+    }
+    e = hipGraphLaunch(b->exec, stream);
+    if (e != hipSuccess) return kp::hip_fail(ctx, e, "hipGraphLaunch");
+  } else {
+    for (const kp_mul_desc& d : b->tasks) {
+      kp_status st = kp::enqueue_desc(ctx, d, stream);
+      if (st != KP_OK) return st;
+    }
+  }
+  b->last = stream;
+  return kp::finish(ctx, KP_FLAG_ASYNC, stream, "kp_batch_launch");
+}
+
+kp_status kp_batch_status(kp_batch* b, int64_t task_id, int64_t* n_out) {
+  if (!b || !n_out) return KP_E_ARG;
+  if (task_id < 0 || task_id >= (int64_t)b->tasks.size())
+    return kp::fail(b->ctx, KP_E_ARG, "no task %lld", (long long)task_id);
+  hipError_t e = hipStreamSynchronize(b->last);
+  if (e == hipSuccess)
+    e = hipMemcpy(n_out, b->tasks[(size_t)task_id].out_n, sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return kp::hip_fail(b->ctx, e, "kp_batch_status");
+  return *n_out < 0 ? (kp_status)(-*n_out) : KP_OK;
 }
 
 kp_status kp_encode_host(const kp_layout* layout, int which, int64_t n, const int32_t* x_exps,

@@ -987,7 +987,9 @@ int dense_bucket_shift(int64_t maxcode, int64_t n) {
   return s;
 }
 
-hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s) {
+// Kernel attributes (dynamic LDS limits), set once per process before any
+// launch, so that no launch (or graph capture) has to set them.
+hipError_t dense_setup() {
   static bool attrs = false;
   if (!attrs) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_prep),
@@ -1005,6 +1007,12 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
     if (e != hipSuccess) return e;
     attrs = true;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s) {
+  hipError_t e0 = dense_setup();
+  if (e0 != hipSuccess) return e0;
   PrepArgs pa{};
   pa.seg[0] = PrepSeg{B.a_keys_in, B.a_coef_in, B.na, P.shiftA, P.nbkA, P.maxcodeA, B.apk, B.ac,
                       B.rank_a, B.bstart, nullptr, nullptr, nullptr, 0};

@@ -226,6 +226,7 @@ struct DenseBufs {
   uint32_t* ctx_err;
   hipEvent_t ev0, ev1;   // optional: recorded around the window kernel
 };
+hipError_t dense_setup();
 hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s);
 
 // hash Laurent / Poisson

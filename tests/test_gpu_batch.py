@@ -1,0 +1,146 @@
+"""GPU: batched execution (kp_batch, eager and replayed HIP graph) and the
+serving paths give the same products as single calls and as the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1004_4548_amd as kp
+from paper_1004_4548_amd import inputs as I
+from paper_1004_4548_amd import serve
+from tests.helpers import assert_exact, assert_tolerance
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-13
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _oracle_check(a, b, exps, coef, what):
+    oe, oc, oab = O.laurent_mul(a[0], a[1], b[0], b[1], threads=4)
+    if np.asarray(a[1]).dtype == np.float64:
+        assert_tolerance([exps], coef, [oe], oc, oab, TOL, what)
+    else:
+        assert_exact([exps], coef, [oe], oc, what)
+
+
+def _cases():
+    """Small products of every kind: dense and hash, int64 and fp64."""
+    out = []
+    a, b = I.config(1, scale=0.4)
+    out.append(("box int64", a, b))
+    a, b = I.config(2, scale=0.1)
+    out.append(("simplex int64", a, b))
+    out.append(("simplex fp64", (a[0], a[1].astype(np.float64) / 8), (b[0], b[1].astype(np.float64))))
+    a, b = I.config(3, scale=0.05)
+    out.append(("sparse int64", a, b))
+    return out
+
+
+def _queue(bt, cases, ctx):
+    import torch
+    outs = []
+    for what, a, b in cases:
+        pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+        lay = kp.laurent_layout(pa, pb, ctx)
+        ka, _ = kp.encode(lay, 0, pa.exps, ctx=ctx)
+        kb, _ = kp.encode(lay, 1, pb.exps, ctx=ctx)
+        mode, cap, ws = kp.mul_bound(lay, False, kp._dt(pa.coef), "auto", len(a[1]), len(b[1]),
+                                     ctx)
+        out = (torch.empty(max(cap, 1), dtype=torch.int64, device="cuda"),
+               torch.empty(max(cap, 1), dtype=pa.coef.dtype, device="cuda"),
+               torch.empty(1, dtype=torch.int64, device="cuda"))
+        wbuf = torch.empty(max(ws, 256), dtype=torch.uint8, device="cuda")
+        tid = bt.add_laurent(lay, ka, pa.coef, kb, pb.coef, out, wbuf)
+        outs.append((what, a, b, lay, out, tid, mode))
+    return outs
+
+
+def _collect(bt, outs, ctx):
+    res = []
+    for what, a, b, lay, (oc, ov, on), tid, mode in outs:
+        n = bt.status(tid)
+        assert n == int(on.item())
+        e = kp.decode(lay, oc[:n], ctx=ctx).cpu().numpy()
+        res.append((e, ov[:n].cpu().numpy()))
+    return res
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(graph):
+    ctx = kp.context()
+    cases = _cases()
+    say("batch of", len(cases), "graph" if graph else "eager")
+    bt = kp.Batch(len(cases), ctx)
+    outs = _queue(bt, cases, ctx)
+    for rep in range(3 if graph else 1):
+        for _, _, _, _, (oc, ov, on), _, _ in outs:   # eager work between replays
+            on.fill_(-99)
+            ov.zero_()
+        bt.launch(graph=graph)
+        got = _collect(bt, outs, ctx)
+        for (what, a, b, *_), (e, c) in zip(outs, got):
+            _oracle_check(a, b, e, c, f"{what} (launch {rep})")
+
+
+def test_batch_rejects_bad_tasks():
+    import torch
+    ctx = kp.context()
+    bt = kp.Batch(1, ctx)
+    a, b = I.config(1, scale=0.2)
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    lay = kp.laurent_layout(pa, pb, ctx)
+    ka, _ = kp.encode(lay, 0, pa.exps, ctx=ctx)
+    kb, _ = kp.encode(lay, 1, pb.exps, ctx=ctx)
+    _, cap, ws = kp.mul_bound(lay, False, kp.KP_I64, "auto", len(a[1]), len(b[1]), ctx)
+    out = (torch.empty(cap, dtype=torch.int64, device="cuda"),
+           torch.empty(cap, dtype=torch.int64, device="cuda"),
+           torch.empty(1, dtype=torch.int64, device="cuda"))
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(kp.KPError) as e:
+        bt.add_laurent(lay, ka, pa.coef, kb, pb.coef, out, small)
+    assert e.value.status == kp.KP_E_WORKSPACE
+    wbuf = torch.empty(max(ws, 256), dtype=torch.uint8, device="cuda")
+    bt.add_laurent(lay, ka, pa.coef, kb, pb.coef, out, wbuf)
+    with pytest.raises(kp.KPError):   # full
+        bt.add_laurent(lay, ka, pa.coef, kb, pb.coef, out, wbuf)
+
+
+def test_served_alone_equals_in_a_mix():
+    # requests of the mixed stream, shrunk: alone (per call) and batched
+    reqs = [_shrink(I.request(r)) for r in range(12)]
+    say("stream requests", [(q["type"], q["nv"], len(q["a"][1]), len(q["b"][1])) for q in reqs])
+    st = serve.stage(reqs)
+    alone, _ = serve.run_per_call(st)
+    mixed = serve.run_batch(st)
+    for q, x, y in zip(reqs, alone, mixed):
+        ex, cx = x.exps.cpu().numpy(), x.coef.cpu().numpy()
+        ey, cy = y.exps.cpu().numpy(), y.coef.cpu().numpy()
+        ox, oy = np.lexsort(ex.T[::-1]), np.lexsort(ey.T[::-1])
+        assert np.array_equal(ex[ox], ey[oy]), q["id"]
+        if q["dtype"] == "i64":
+            assert np.array_equal(cx[ox], cy[oy]), q["id"]
+        _oracle_check(q["a"], q["b"], ey, cy, f"request {q['id']}")
+
+
+def test_open_loop_serves_every_request():
+    reqs = [_shrink(I.request(r)) for r in range(20, 36)]
+    st = serve.stage(reqs)
+    lat, wall = serve.open_loop(st, rate=2000.0, max_batch=4)
+    assert len(lat) == len(reqs) and np.all(lat > 0) and wall > 0
+    p = serve.percentiles(lat)
+    assert p["p50_ms"] <= p["p99_ms"]
+
+
+def _shrink(q, n=400):
+    """A request with at most n terms per factor (the oracle stays quick)."""
+    q = dict(q)
+    q["a"] = (q["a"][0][:n], q["a"][1][:n])
+    q["b"] = (q["b"][0][:n], q["b"][1][:n])
+    return q
