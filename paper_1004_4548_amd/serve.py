@@ -9,10 +9,13 @@ min/max pass for all factors, encodes queued back to back, all products
 queued through one kp_batch launch, one read of all counts, decodes queued,
 one synchronisation at the end.  Both orders compute the same products.
 
-Continuous batching: requests arrive at the times of a Poisson process; the
-server repeatedly takes every request that has arrived (up to a batch size
-and a memory budget), runs them as one batch and completes them together.
-The latency of a request is its completion time minus its arrival time.
+Continuous batching: requests arrive at the times of a Poisson process.
+Whenever a stream slot is free, the server admits the requests that have
+arrived (up to a batch size, and as far as the device memory budget allows,
+estimated from each product's output bound and workspace) as one batch on
+that slot's stream, without waiting for the batches already on the device:
+up to `slots` batches overlap.  A batch completes when its decodes are done;
+the latency of a request is its completion time minus its arrival time.
 """
 from __future__ import annotations
 
@@ -138,46 +141,142 @@ def groups(staged, plans, max_batch, max_bytes):
     return out
 
 
-def closed_loop(staged, ctx=None, max_batch=16, max_bytes=48 << 30):
-    """Batched throughput with every request available at once: seconds."""
-    import torch
-    ctx = ctx or context()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    plans = plan_batch(staged, ctx)
-    for g, p in groups(staged, plans, max_batch, max_bytes):
-        run_batch(g, ctx, p)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t
+class InFlight:
+    """A batch on its own stream: multiplies queued, counts on their way to
+    pinned host memory; then decodes queued; then done."""
+
+    def __init__(self, staged, plans, stream, ctx):
+        import torch
+        self.staged, self.stream, self.ctx = staged, stream, ctx
+        self.bytes = batch_bytes(staged, plans)
+        self.results = None
+        dev = staged[0].a.exps.device
+        with torch.cuda.stream(stream):
+            counts = torch.empty(len(staged), dtype=torch.int64, device=dev)
+            self.batch = Batch(len(staged), ctx)
+            self.outs = []
+            for i, (s, (lay, mode, cap, ws)) in enumerate(zip(staged, plans)):
+                ka, _ = encode(lay, 0, s.a.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
+                kb, _ = encode(lay, 1, s.b.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
+                oc = torch.empty(cap, dtype=torch.int64, device=dev)
+                ov = torch.empty(cap, dtype=s.a.coef.dtype, device=dev)
+                wbuf = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+                self.batch.add_laurent(lay, ka, s.a.coef, kb, s.b.coef,
+                                       (oc, ov, counts[i:i + 1]), wbuf)
+                self.outs.append((lay, oc, ov))
+            self.batch.launch()
+            self.counts = torch.empty(len(staged), dtype=torch.int64, pin_memory=True)
+            self.counts.copy_(counts, non_blocking=True)
+            self.ev = torch.cuda.Event()
+            self.ev.record(stream)
+        self.phase = 0
+
+    def advance(self):
+        """Moves the batch on when its stream has caught up; True when done."""
+        import torch
+        if not self.ev.query():
+            return False
+        if self.phase == 0:
+            n = self.counts.tolist()
+            res = []
+            with torch.cuda.stream(self.stream):
+                for (lay, oc, ov), k in zip(self.outs, n):
+                    if k < 0:
+                        self.ctx.sync_check()
+                        raise RuntimeError(f"request failed with status {-k}")
+                    res.append(Poly(decode(lay, oc[:k], ctx=self.ctx, flags=KP_FLAG_ASYNC),
+                                    ov[:k]))
+                self.ev = torch.cuda.Event()
+                self.ev.record(self.stream)
+            self.results = res
+            self.batch = None
+            self.phase = 1
+            return False
+        return True
 
 
-def open_loop(staged, rate, ctx=None, max_batch=16, max_bytes=48 << 30, seed=10044548):
-    """Continuous batching under Poisson arrivals at `rate` requests/s.
-    Returns per-request latencies (s) and the wall time."""
+def _plan_on(staged, ctx, stream):
+    import torch
+    with torch.cuda.stream(stream):
+        return plan_batch(staged, ctx)
+
+
+def serve_stream(staged, arrivals, ctx=None, max_batch=16, max_bytes=48 << 30, slots=3):
+    """Continuous batching: requests arriving at `arrivals` (seconds from
+    start) are admitted as soon as a stream slot and memory allow, while
+    earlier batches are still running; up to `slots` batches overlap on the
+    device.  Returns (latencies, completion order, results, wall time)."""
     import torch
     ctx = ctx or context()
-    rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(staged)))
+    streams = [torch.cuda.Stream() for _ in range(slots)]
+    free = list(range(slots))
+    inflight = []   # (InFlight, slot, first, last)
     lat = np.zeros(len(staged))
+    results = [None] * len(staged)
+    used = 0
+    nxt = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nxt = 0
-    while nxt < len(staged):
+    while nxt < len(staged) or inflight:
         now = time.perf_counter() - t0
-        if arrivals[nxt] > now:   # idle until the next arrival
-            time.sleep(min(arrivals[nxt] - now, 0.001))
-            continue
-        end = nxt
-        while end < len(staged) and end - nxt < max_batch and arrivals[end] <= now:
-            end += 1
-        grp = staged[nxt:end]
-        plans = plan_batch(grp, ctx)
-        for g, p in groups(grp, plans, max_batch, max_bytes):
-            run_batch(g, ctx, p)
-        done = time.perf_counter() - t0
-        lat[nxt:end] = done - arrivals[nxt:end]
-        nxt = end
-    return lat, time.perf_counter() - t0
+        for item in list(inflight):
+            f, slot, i0, i1 = item
+            if f.advance():
+                done = time.perf_counter() - t0
+                lat[i0:i1] = done - arrivals[i0:i1]
+                results[i0:i1] = f.results
+                used -= f.bytes
+                free.append(slot)
+                inflight.remove(item)
+        admitted = False
+        if free and nxt < len(staged) and arrivals[nxt] <= now:
+            end = nxt
+            while end < len(staged) and end - nxt < max_batch and arrivals[end] <= now:
+                end += 1
+            slot = free[0]
+            plans = _plan_on(staged[nxt:end], ctx, streams[slot])
+            # admit the longest prefix that fits the memory left (at least one
+            # request when nothing else is in flight)
+            take, need = 0, 0
+            for s, p in zip(staged[nxt:end], plans):
+                b = batch_bytes([s], [p])
+                if take and used + need + b > max_bytes:
+                    break
+                if not take and inflight and used + b > max_bytes:
+                    break
+                take += 1
+                need += b
+            if take:
+                free.pop(0)
+                f = InFlight(staged[nxt:nxt + take], plans[:take], streams[slot], ctx)
+                used += f.bytes
+                inflight.append((f, slot, nxt, nxt + take))
+                nxt += take
+                admitted = True
+        if not admitted and inflight:
+            time.sleep(0)   # let the device catch up
+        elif not admitted and nxt < len(staged):
+            wait = arrivals[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.0005))
+    torch.cuda.synchronize()
+    return lat, results, time.perf_counter() - t0
+
+
+def closed_loop(staged, ctx=None, max_batch=16, max_bytes=48 << 30, slots=3):
+    """Batched capacity: every request available at once; seconds."""
+    _, _, wall = serve_stream(staged, np.zeros(len(staged)), ctx, max_batch, max_bytes, slots)
+    return wall
+
+
+def open_loop(staged, rate, ctx=None, max_batch=16, max_bytes=48 << 30, slots=3,
+              seed=10044548):
+    """Continuous batching under Poisson arrivals at `rate` requests/s.
+    Returns per-request latencies (s) and the wall time."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(staged)))
+    lat, _, wall = serve_stream(staged, arrivals, ctx, max_batch, max_bytes, slots)
+    return lat, wall
 
 
 def percentiles(lat):

@@ -1,0 +1,140 @@
+"""Autotuner for the knobs the paper leaves open (Sections 3.1, 3.2): the
+dense window size, workgroup size and tasks per compute unit, the hash
+table's load factor and rows per thread, and the density threshold of the
+dense/hash choice.  None of them changes a result; each is picked by timing
+the library's own multiplies on seeded products of the benchmark shapes.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+
+import numpy as np
+
+from . import (KP_FLAG_ASYNC, Poly, Workspace, context, encode, laurent_layout, mul_bound,
+               mul_laurent_codes, _dt)
+from . import inputs as I
+
+DENSE_GRID = [dict(window=w, block=b, tasks_per_cu=t)
+              for w, b, t in itertools.product((8192, 16384, 18432), (512, 1024), (1, 2))]
+HASH_GRID = [dict(hash_load=l, hash_rows=r)
+             for l, r in itertools.product((0.35, 0.5, 0.7), (32, 64, 128))]
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+class _Product:
+    """A product staged for repeated timing: codes, bounds, buffers."""
+
+    def __init__(self, ctx, a, b):
+        import torch
+        self.ctx = ctx
+        self.pa, self.pb = Poly(_dev(a[0]), _dev(a[1])), Poly(_dev(b[0]), _dev(b[1]))
+        self.lay = laurent_layout(self.pa, self.pb, ctx)
+        self.ka, _ = encode(self.lay, 0, self.pa.exps, ctx=ctx)
+        self.kb, _ = encode(self.lay, 1, self.pb.exps, ctx=ctx)
+        self.pairs = len(a[1]) * len(b[1])
+        self.ws = Workspace()
+        self.out = {}
+
+    def feasible(self, mode):
+        from . import KPError
+        try:
+            mul_bound(self.lay, False, _dt(self.pa.coef), mode, self.pa.coef.shape[0],
+                      self.pb.coef.shape[0], self.ctx)
+            return True
+        except KPError:
+            return False
+
+    def seconds(self, mode, reps=5):
+        import torch
+        _, cap, _ = mul_bound(self.lay, False, _dt(self.pa.coef), mode, self.pa.coef.shape[0],
+                              self.pb.coef.shape[0], self.ctx)
+        if self.out.get(mode) is None or self.out[mode][0].shape[0] < cap:
+            self.out[mode] = (torch.empty(max(cap, 1), dtype=torch.int64, device="cuda"),
+                              torch.empty(max(cap, 1), dtype=self.pa.coef.dtype, device="cuda"),
+                              torch.empty(1, dtype=torch.int64, device="cuda"))
+        f = lambda: mul_laurent_codes(self.lay, self.ka, self.pa.coef, self.kb, self.pb.coef,
+                                      mode, self.ctx, self.ws, self.out[mode],
+                                      flags=KP_FLAG_ASYNC)
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+
+def _search(ctx, prod, mode, grid, reps):
+    saved = ctx.tune
+    base = {f: getattr(saved, f) for f, _ in type(saved)._fields_}
+    table = []
+    try:
+        for cand in grid:
+            ctx.set_tune(**{**base, **cand})
+            table.append((prod.seconds(mode, reps), cand))
+    finally:
+        ctx.set_tune(**base)
+    table.sort(key=lambda x: x[0])
+    return table[0][1], table
+
+
+def tune_dense(ctx, scale=1.0, reps=5):
+    """Window, workgroup and tasks per CU on the 4-variable simplex product."""
+    a, b = I.config(2, scale=scale)
+    return _search(ctx, _Product(ctx, a, b), "dense", DENSE_GRID, reps)
+
+
+def tune_hash(ctx, scale=0.2, reps=3):
+    """Load factor and rows per thread on the 6-variable sparse product."""
+    a, b = I.config(3, scale=scale)
+    return _search(ctx, _Product(ctx, a, b), "hash", HASH_GRID, reps)
+
+
+def tune_threshold(ctx, n=2000, reps=3):
+    """The dense/hash switch: products of n x n terms in 3-variable boxes of
+    growing width; the threshold on codes per term product lies between the
+    sparsest box where dense mode still wins and the densest where hash wins."""
+    rows = []
+    for h in (5, 7, 9, 12, 16, 22, 30, 40, 55, 70, 90):
+        if (2 * h + 1) ** 3 < n:
+            continue
+        a = I.laurent_box(n=n, cfg=7, factor=0, lo=-h, hi=h)
+        b = I.laurent_box(n=n, cfg=7, factor=1, lo=-h, hi=h)
+        prod = _Product(ctx, a, b)
+        if not (prod.feasible("dense") and prod.feasible("hash")):
+            continue
+        td, th = prod.seconds("dense", reps), prod.seconds("hash", reps)
+        rows.append((prod.lay.nkeys / prod.pairs, td, th))
+    dense_wins = [r for r, td, th in rows if td <= th]
+    hash_wins = [r for r, td, th in rows if td > th]
+    lo = max(dense_wins) if dense_wins else None
+    hi = min([r for r in hash_wins if lo is None or r > lo], default=None)
+    if lo is None:
+        thr = 0.0
+    elif hi is None:
+        thr = max(ctx.tune.dense_keys_per_pair, lo)
+    else:
+        thr = float(np.sqrt(lo * hi))
+    return thr, rows
+
+
+def autotune(ctx=None, apply=True, quick=True):
+    """Tunes every knob and (when `apply`) sets the context to the result.
+    Returns the chosen settings and the timing tables."""
+    ctx = ctx or context()
+    dense, dt = tune_dense(ctx, scale=0.5 if quick else 1.0)
+    hashed, ht = tune_hash(ctx, scale=0.1 if quick else 0.3)
+    thr, rows = tune_threshold(ctx, n=1000 if quick else 2000)
+    chosen = {**dense, **hashed, "dense_keys_per_pair": thr}
+    if apply:
+        ctx.set_tune(**chosen)
+    return {"chosen": chosen,
+            "dense_ms": [(round(t * 1e3, 4), c) for t, c in dt],
+            "hash_ms": [(round(t * 1e3, 4), c) for t, c in ht],
+            "threshold_rows": [(round(r, 3), round(a * 1e3, 4), round(b * 1e3, 4))
+                               for r, a, b in rows]}

@@ -119,6 +119,17 @@ def test_served_alone_equals_in_a_mix():
     st = serve.stage(reqs)
     alone, _ = serve.run_per_call(st)
     mixed = serve.run_batch(st)
+    # continuous batching: batches of 3 on 3 streams, overlapping on the device
+    _, served, _ = serve.serve_stream(st, np.zeros(len(st)), max_batch=3, slots=3)
+    for q, x, y in zip(reqs, alone, served):
+        ex, cx = x.exps.cpu().numpy(), x.coef.cpu().numpy()
+        ey, cy = y.exps.cpu().numpy(), y.coef.cpu().numpy()
+        ox, oy = np.lexsort(ex.T[::-1]), np.lexsort(ey.T[::-1])
+        assert np.array_equal(ex[ox], ey[oy]), q["id"]
+        if q["dtype"] == "i64":
+            assert np.array_equal(cx[ox], cy[oy]), q["id"]
+        else:   # fp64 sums in another order: each within the tolerance
+            _oracle_check(q["a"], q["b"], ey, cy, f"served request {q['id']}")
     for q, x, y in zip(reqs, alone, mixed):
         ex, cx = x.exps.cpu().numpy(), x.coef.cpu().numpy()
         ey, cy = y.exps.cpu().numpy(), y.coef.cpu().numpy()
@@ -144,3 +155,20 @@ def _shrink(q, n=400):
     q["a"] = (q["a"][0][:n], q["a"][1][:n])
     q["b"] = (q["b"][0][:n], q["b"][1][:n])
     return q
+
+
+def test_autotuner_keeps_results():
+    """The autotuner only moves knobs that do not change a product."""
+    from paper_1004_4548_amd import tune
+    ctx = kp.context()
+    a, b = I.config(2, scale=0.2)
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    before, _ = kp.mul_laurent(pa, pb, ctx=ctx)
+    best, table = tune.tune_dense(ctx, scale=0.2, reps=2)
+    assert len(table) == len(tune.DENSE_GRID) and best in tune.DENSE_GRID
+    thr, rows = tune.tune_threshold(ctx, n=400, reps=1)
+    assert thr >= 0 and rows
+    ctx.set_tune(**best)
+    after, _ = kp.mul_laurent(pa, pb, ctx=ctx)
+    assert np.array_equal(before.exps.cpu().numpy(), after.exps.cpu().numpy())
+    assert np.array_equal(before.coef.cpu().numpy(), after.coef.cpu().numpy())

@@ -413,3 +413,72 @@ def test_full_poisson_sampled():
     want, wab, _ = O.poisson_coeff_at(a, b, 3, 6, gx[sel], gy[sel], gt[sel])
     assert np.all(np.abs(gc[sel] - want) <= TOL * wab)
     assert len(np.unique(key[sel], axis=0)) == len(np.unique(sel))
+
+
+# ------------------------------------------------------------------ the paper's benchmarks
+def _fateman_closed_form(exps, k):
+    """Coefficients of f * (f + 1) = f^2 + f for f = (1 + x + y + z + t)^k, by
+    the multinomial theorem, modulo 2^64 as signed int64."""
+    fact = [math.factorial(i) for i in range(2 * k + 1)]
+    out = np.empty(len(exps), dtype=np.int64)
+    for i, p in enumerate(exps.tolist()):
+        s = sum(p)
+        c = fact[2 * k] // (fact[2 * k - s] * fact[p[0]] * fact[p[1]] * fact[p[2]] * fact[p[3]])
+        if s <= k:
+            c += fact[k] // (fact[k - s] * fact[p[0]] * fact[p[1]] * fact[p[2]] * fact[p[3]])
+        c %= 2**64
+        out[i] = c - 2**64 if c >= 2**63 else c
+    return out
+
+
+def test_fateman_benchmark_closed_form():
+    """Fateman's benchmark (Section 5): f = (1+x+y+z+t)^30 times f + 1, 46376 x
+    46376 terms, dense mode; every one of the C(64,4) result terms equals the
+    closed form modulo 2^64 (the coefficients exceed 2^63)."""
+    f = I.fateman(30)
+    g = I.fateman(30, plus_one=True)
+    say("Fateman k=30", len(f[1]), "x", len(g[1]))
+    ge, gc, lay = gpu_laurent(f, g, "auto")
+    assert len(gc) == math.comb(64, 4)
+    assert len(np.unique(ge, axis=0)) == len(gc)
+    assert ge.min() >= 0 and ge.sum(1).max() == 60
+    np.testing.assert_array_equal(gc, _fateman_closed_form(ge, 30))
+
+
+def _eval_mod2_64(exps, coef, pt):
+    """sum_t c_t prod_k pt_k^e_tk in the ring of integers modulo 2^64 (numpy
+    uint64 arithmetic wraps), for non-negative exponents."""
+    acc = np.asarray(coef).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        for v, x in enumerate(pt):
+            top = int(exps[:, v].max())
+            pw = np.ones(top + 1, dtype=np.uint64)
+            for i in range(1, top + 1):
+                pw[i] = pw[i - 1] * np.uint64(x)
+            acc = acc * pw[exps[:, v]]
+        return int(acc.sum(dtype=np.uint64))
+
+
+def test_mp_sparse_benchmark():
+    """Monagan-Pearce's sparse benchmark (Section 5): f = (1+x+y+2z^2+3t^3+5u^5)^12
+    times g (variables reversed), 6188 x 6188 terms, hash mode: 5,821,335 terms.
+    The coefficients outgrow int64, so the product is the one modulo 2^64: its
+    value at random odd points modulo 2^64 equals f(pt) g(pt) from the closed
+    form, and sampled terms equal the oracle's (which also wraps)."""
+    f = I.mp_sparse(12, "f")
+    g = I.mp_sparse(12, "g")
+    say("MP-sparse k=12", len(f[1]), "x", len(g[1]))
+    ge, gc, lay = gpu_laurent(f, g, "auto")
+    assert len(gc) == 5821335
+    M = 2**64
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        pt = [int(v) | 1 for v in rng.integers(3, 2**62, 5)]
+        x, y, z, t, u = pt
+        fb = (1 + x + y + 2 * z**2 + 3 * t**3 + 5 * u**5) % M
+        gb = (1 + u + t + 2 * z**2 + 3 * y**3 + 5 * x**5) % M
+        want = pow(fb, 12, M) * pow(gb, 12, M) % M
+        assert _eval_mod2_64(ge, gc, pt) == want
+    sel = rng.integers(0, len(gc), 200)
+    w, _, _ = O.laurent_coeff_at(f[0], f[1], g[0], g[1], ge[sel])
+    np.testing.assert_array_equal(gc[sel], w)
