@@ -135,13 +135,39 @@ double dense_items_bound(const DensePlan& d, int64_t na) {
   return rows / DENSE_ITEM_ROWS + 3.0 * pairs + 64.0;
 }
 
-bool dense_feasible(const kp_ctx* ctx, const kp_layout* L, int64_t na, int64_t nb) {
+bool dense_feasible(const kp_ctx* ctx, int64_t nkeys, int64_t na, int64_t nb) {
   const int64_t S = ctx->tune.window;
-  if (L->nkeys > ctx->tune.dense_max_keys || L->nkeys > DENSE_MAX_CODES) return false;
-  if (sat_mul((L->nkeys + S - 1) / S, (nb + DENSE_TILE - 1) / DENSE_TILE) > ((int64_t)1 << 24))
+  if (nkeys > ctx->tune.dense_max_keys || nkeys > DENSE_MAX_CODES) return false;
+  if (sat_mul((nkeys + S - 1) / S, (nb + DENSE_TILE - 1) / DENSE_TILE) > ((int64_t)1 << 24))
     return false;
   if (na >= ((int64_t)1 << 31) || nb >= ((int64_t)1 << 29)) return false;
   return true;
+}
+
+// Poisson products in dense mode: codes U + s N of the unfolded product in
+// eight segments s (piece, type of A, type of B), N = Wx (2 Hy + 1).
+struct PoissonDense {
+  int64_t N, Hya, Hyb, nkeys, maxA, maxB;
+};
+PoissonDense poisson_dense_codes(const kp_layout* L) {
+  PoissonDense q{};
+  int64_t hya = 0, hyb = 0;
+  for (int k = 0; k < L->ny; ++k) {
+    hya += L->yc[k] * L->ha[k];
+    hyb += L->yc[k] * L->hb[k];
+  }
+  q.Hya = hya;
+  q.Hyb = hyb;
+  const double N = (double)L->Wx * (2.0 * (double)L->Hy + 1.0);
+  if (N * 8.0 > (double)DENSE_MAX_CODES) {
+    q.nkeys = INT64_MAX;
+    return q;
+  }
+  q.N = L->Wx * (2 * L->Hy + 1);
+  q.nkeys = 8 * q.N;
+  q.maxA = 2 * q.N + L->Wx * (2 * hya + 1) - 1;
+  q.maxB = 5 * q.N + L->Wx * (2 * hyb + 1) - 1;
+  return q;
 }
 
 template <bool CARVE>
@@ -195,6 +221,22 @@ void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B)
   }
 }
 
+struct PoissonDenseBufs {
+  int64_t* a_codes;
+  double* a_coef;
+  int64_t* b_codes;
+  double* b_coef;
+};
+
+template <bool CARVE>
+void carve_poisson_dense(Carver& c, int64_t na, int64_t nb, PoissonDenseBufs* q) {
+  int64_t* ak = c.take<int64_t>(na);
+  double* ac = c.take<double>(na);
+  int64_t* bk = c.take<int64_t>(2 * nb);
+  double* bc = c.take<double>(2 * nb);
+  if (CARVE) *q = PoissonDenseBufs{ak, ac, bk, bc};
+}
+
 struct HashCarve {
   Meta* meta;
   uint64_t* table;
@@ -229,22 +271,28 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   int64_t pairs = sat_mul(na, nb);
   int64_t contrib = poisson ? sat_mul(pairs, 2) : pairs;
   p->max_out = std::min(contrib, L->nkeys);
-  bool dense_ok = !poisson && dense_feasible(ctx, L, na, nb);
+  // dense mode works on (na, nbd) terms in a space of dn codes; a Poisson
+  // product's B appears twice (difference and sum pieces)
+  const PoissonDense pq = poisson ? poisson_dense_codes(L) : PoissonDense{};
+  const int64_t dn = poisson ? pq.nkeys : L->nkeys;
+  const int64_t nbd = poisson ? sat_mul(nb, 2) : nb;
+  bool dense_ok = dense_feasible(ctx, dn, na, nbd);
   if (dense_ok) {
     DensePlan& d = p->dp;
     d.S = ctx->tune.window;
-    d.nkeys = L->nkeys;
-    d.nwin = std::max<int64_t>(1, (L->nkeys + d.S - 1) / d.S);
-    d.nchunk = std::max<int64_t>(1, (L->nkeys + DENSE_CHUNK - 1) / DENSE_CHUNK);
-    d.ntiles = std::max<int64_t>(1, (nb + DENSE_TILE - 1) / DENSE_TILE);
+    d.nkeys = dn;
+    d.nwin = std::max<int64_t>(1, (dn + d.S - 1) / d.S);
+    d.nchunk = std::max<int64_t>(1, (dn + DENSE_CHUNK - 1) / DENSE_CHUNK);
+    d.ntiles = std::max<int64_t>(1, (nbd + DENSE_TILE - 1) / DENSE_TILE);
     d.block = ctx->tune.block;
     d.target_tasks = std::max<int64_t>(1, (int64_t)ctx->num_cu * ctx->tune.tasks_per_cu);
     d.max_tasks = d.target_tasks;
     d.min_work = 512;
-    d.maxcodeA = factor_maxcode(L, 0);
-    d.maxcodeB = factor_maxcode(L, 1);
+    d.maxcodeA = poisson ? pq.maxA : factor_maxcode(L, 0);
+    d.maxcodeB = poisson ? pq.maxB : factor_maxcode(L, 1);
+    d.accumulate = poisson ? 1 : 0;
     d.shiftA = dense_bucket_shift(d.maxcodeA, na);
-    d.shiftB = dense_bucket_shift(d.maxcodeB, nb);
+    d.shiftB = dense_bucket_shift(d.maxcodeB, nbd);
     d.nbkA = (d.maxcodeA >> d.shiftA) + 1;
     d.nbkB = (d.maxcodeB >> d.shiftB) + 1;
     const double items = dense_items_bound(d, na);
@@ -253,18 +301,19 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   }
   kp_mode m = mode;
   if (m == KP_AUTO) {
-    double budget = ctx->tune.dense_keys_per_pair * (double)pairs;
-    m = (dense_ok && (double)L->nkeys <= budget) ? KP_DENSE : KP_HASH;
+    double budget = ctx->tune.dense_keys_per_pair * (double)contrib;
+    m = (dense_ok && (double)dn <= budget) ? KP_DENSE : KP_HASH;
   }
   if (m == KP_DENSE && !dense_ok)
     return fail(ctx, KP_E_MODE,
-                "dense mode needs a Laurent product with at most %lld codes and a bounded "
+                "dense mode needs a product with at most %lld codes and a bounded "
                 "number of work items",
                 (long long)std::min<int64_t>(ctx->tune.dense_max_keys, DENSE_MAX_CODES));
   p->mode = m;
   Carver c;
   if (m == KP_DENSE) {
-    carve_dense<false>(c, *p, na, nb, nullptr);
+    carve_dense<false>(c, *p, na, nbd, nullptr);
+    if (poisson) carve_poisson_dense<false>(c, na, nb, nullptr);
   } else {
     int64_t want;
     if (ctx->tune.hash_capacity > 0) {
@@ -641,6 +690,34 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
     return fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, p.ws);
   Carver c;
   c.base = static_cast<char*>(workspace);
+  if (p.mode == KP_DENSE) {
+    DenseBufs B{};
+    carve_dense<true>(c, p, na, 2 * nb, &B);
+    PoissonDenseBufs q{};
+    carve_poisson_dense<true>(c, na, nb, &q);
+    const PoissonDense pq = poisson_dense_codes(layout);
+    B.a_keys_in = q.a_codes;
+    B.a_coef_in = reinterpret_cast<const int64_t*>(q.a_coef);
+    B.b_keys_in = q.b_codes;
+    B.b_coef_in = reinterpret_cast<const int64_t*>(q.b_coef);
+    B.ctx_err = &ctx->status->err;
+    hipError_t e = launch_meta_init(B.meta, stream);
+    if (na > 0 && nb > 0 && layout->nkeys > 0) {
+      if (timed) std::tie(B.ev0, B.ev1) = timing_pair(ctx);
+      if (e == hipSuccess)
+        e = launch_poisson_dense_prep(layout->Wx, pq.N, pq.Hya, pq.Hyb, a_x, a_y, a_sin, a_coef,
+                                      na, b_x, b_y, b_sin, b_coef, nb, q.a_codes, q.a_coef,
+                                      q.b_codes, q.b_coef, stream);
+      if (e == hipSuccess) e = launch_zero(B.dense, (size_t)8 * p.dp.nwin * p.dp.S, stream);
+      if (e == hipSuccess) e = launch_dense_laurent(p.dp, B, KP_F64, stream);
+      if (e == hipSuccess)
+        e = launch_poisson_fold(layout->Wx, layout->Hy, pq.N, reinterpret_cast<const double*>(B.dense),
+                                B.meta, out_keys, out_coef, out_cap, stream);
+    }
+    if (e == hipSuccess) e = launch_finalize(B.meta, out_cap, out_n, &ctx->status->err, stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson launch");
+    return KP_OK;
+  }
   HashCarve h;
   carve_hash(c, p, 1, na, nb, &h);
   HashBufs H{h.meta, h.table, p.cap, p.cap, out_keys, out_coef, out_cap,

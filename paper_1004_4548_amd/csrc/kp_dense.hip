@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(SCATTER_BLOCK) k_dense_scatter(PrepArgs args, 
 struct PlanArgs {
   int64_t S, nwin, ntiles, nkeys, nb, target, min_work, items_cap;
   int64_t items_lds;     // dynamic LDS bytes of the items kernel
+  int accumulate;        // the HBM accumulator was cleared beforehand
   const int32_t* bstart;
   int shiftA;
   int64_t nbkA;
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
     if (T < WINDOW_COST + 1) T = WINDOW_COST + 1;
     int64_t nt = all_cost > 0 ? (all_cost + T - 1) / T : 0;
     if (bad || all_items > P.items_cap) {
-      if (!bad) P.meta->err |= ERR_CAPACITY;
+      P.meta->err |= bad ? bad : ERR_CAPACITY;
       nt = 0;
     }
     P.meta->task_rows = T;
@@ -580,7 +581,7 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
     }
   }
   __syncthreads();
-  if (s_split) {   // tasks of a split window add into the HBM accumulator
+  if (s_split && !P.accumulate) {   // tasks of a split window add into the HBM accumulator
     const int64_t L = w * P.S;
     const int64_t Sw = min(P.S, P.nkeys - L);
     int64_t* d = P.dense + L;
@@ -601,6 +602,7 @@ struct MulArgs {
   const int32_t* task_w;
   const int32_t* task_begin;
   const int64_t* win_ibase;   // [nwin + 1] first item of each window
+  int accumulate;             // every window adds into the HBM accumulator
   int64_t* dense;
   int64_t* stage_k;
   int64_t* stage_c;
@@ -834,7 +836,7 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
       else run_items<T, 0, BS>(M, pb, pe, L, S8, base);
     }
     __syncthreads();
-    flush_window<T, BS>(M, win, L, Sw, pb == wb && pe == we);
+    flush_window<T, BS>(M, win, L, Sw, !M.accumulate && pb == wb && pe == we);
   }
 }
 
@@ -1028,7 +1030,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
                      s, pa, blocksA);
 
   PlanArgs pl{P.S, P.nwin, P.ntiles, P.nkeys, B.nb, P.target_tasks, P.min_work, P.items_cap,
-              ITEMS_LDS_BYTES,
+              ITEMS_LDS_BYTES, P.accumulate,
               B.bstart, P.shiftA, P.nbkA, B.tmin, B.tmax, B.win, B.recs, B.items, B.task_w,
               B.task_begin, B.dense, B.meta};
   hipLaunchKernelGGL(k_dense_count, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK), 0, s, pl);
@@ -1037,7 +1039,8 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
 
   const int64_t W1 = P.nwin + 1;
   MulArgs ma{B.meta, B.apk, B.ac, B.bpk, B.bc, B.nb, P.S, P.nwin, P.nkeys, B.items, B.task_w,
-             B.task_begin, B.win + W_IBASE * W1, B.dense, B.stage_k, B.stage_c, B.ccount};
+             B.task_begin, B.win + W_IBASE * W1, P.accumulate, B.dense, B.stage_k, B.stage_c,
+             B.ccount};
   const size_t lds = (size_t)(P.S + DENSE_DUMMY) * 8;
   const unsigned grid = (unsigned)P.max_tasks;
   if (B.ev0) (void)hipEventRecord(B.ev0, s);
@@ -1054,6 +1057,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   }
 #undef KP_DENSE_LAUNCH
   if (B.ev1) (void)hipEventRecord(B.ev1, s);
+  if (P.accumulate) return hipGetLastError();   // the caller reads the accumulator
 
   CombineArgs cb{B.win + W_SPLIT * W1, P.nwin, P.S, P.nkeys, B.dense, B.stage_k, B.stage_c,
                  B.ccount};

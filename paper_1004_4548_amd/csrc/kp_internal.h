@@ -197,6 +197,7 @@ struct DensePlan {
   int64_t max_tasks;     // upper bound on tasks (= target)
   int64_t min_work;      // row visits below which a window is not split
   int64_t items_cap;     // bound on work items (see dense_items_bound)
+  int accumulate;        // 1: every window adds into the HBM accumulator, no compaction
   int shiftA, shiftB;    // bucket widths 2^shift of the factor sorts
   int64_t nbkA, nbkB;    // buckets
   int64_t maxcodeA, maxcodeB;   // largest code of each factor's box
@@ -252,5 +253,15 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
                                const double* ac, int64_t na, const double* bc, int64_t nb,
                                int rows, hipStream_t s);
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
+
+// dense Poisson (kp_poisson.hip)
+hipError_t launch_poisson_dense_prep(int64_t Wx, int64_t N, int64_t Hya, int64_t Hyb,
+                                     const int64_t* ax, const int64_t* ay, const uint8_t* as,
+                                     const double* ac, int64_t na, const int64_t* bx,
+                                     const int64_t* by, const uint8_t* bs, const double* bc,
+                                     int64_t nb, int64_t* a_codes, double* a_coef,
+                                     int64_t* b_codes, double* b_coef, hipStream_t s);
+hipError_t launch_poisson_fold(int64_t Wx, int64_t Hy, int64_t N, const double* acc, Meta* meta,
+                               int64_t* out_k, double* out_c, int64_t out_cap, hipStream_t s);
 
 }  // namespace kp

@@ -295,6 +295,37 @@ def test_poisson_identities_on_device():
     assert got == {((1, 1), 1): 0.5, ((1, -1), 1): -0.5}
 
 
+@pytest.mark.parametrize("mode", ["dense", "hash"])
+def test_poisson_identities_both_modes(mode):
+    one = lambda x, j, t, c: (np.array([[x]], np.int32), np.array([j], np.int32),
+                              np.array([t], np.uint8), np.array([c], np.float64))
+    cy, sy = one(0, [1, 0], 0, 1.0), one(0, [1, 0], 1, 1.0)
+    c1, s2 = one(1, [1, 0], 0, 2.0), one(-1, [0, 1], 1, 1.0)
+    for a, b, want in ((cy, cy, {((0, 0), 0): 0.5, ((2, 0), 0): 0.5}),
+                       (sy, sy, {((0, 0), 0): 0.5, ((2, 0), 0): -0.5}),
+                       (sy, cy, {((2, 0), 1): 0.5}),
+                       (cy, sy, {((2, 0), 1): 0.5}),
+                       (s2, c1, {((1, 1), 1): 1.0, ((1, -1), 1): -1.0})):
+        gx, gy, gt, gc, _ = gpu_poisson(a, b, mode)
+        got = {(tuple(y), int(t)): c for y, t, c in zip(gy.tolist(), gt, gc)}
+        assert got == want, (mode, got)
+
+
+@pytest.mark.parametrize("jmax", [2, 5])
+def test_poisson_dense_matches_oracle_and_hash(jmax):
+    """Dense-mode Poisson products (segmented codes, fold to canonical keys)
+    against the oracle and against hash mode."""
+    a = I.poisson_random(nx=2, ny=2, n=700, xlo=-3, xhi=3, jmax=jmax, cfg=92, factor=0)
+    b = I.poisson_random(nx=2, ny=2, n=650, xlo=-2, xhi=4, jmax=jmax, cfg=92, factor=1)
+    dx, dy, dt, dc = check_poisson(a, b, f"Poisson dense jmax {jmax}", 2, 2, mode="dense")
+    hx, hy, ht, hc = check_poisson(a, b, f"Poisson hash jmax {jmax}", 2, 2, mode="hash")
+    assert len(dc) == len(hc)
+    ex = np.concatenate([dx, dy, dt.reshape(-1, 1).astype(np.int32)], 1)
+    eh = np.concatenate([hx, hy, ht.reshape(-1, 1).astype(np.int32)], 1)
+    od, oh = np.lexsort(ex.T[::-1]), np.lexsort(eh.T[::-1])
+    assert np.array_equal(ex[od], eh[oh])
+
+
 def test_poisson_400():
     a, b = I.config(4, scale=0.08)
     check_poisson(a, b, "Poisson 3+6 vars, 400 x 400")

@@ -203,6 +203,13 @@ def test_mode_selection_for_the_workloads():
     l4 = kp.layout_product(3, 6, [-4] * 3, [4] * 3, [-4] * 3, [4] * 3, [8] * 6, [8] * 6)
     m, mo, ws = kp.mul_bound(l4, True, kp.KP_F64, "auto", 5000, 5000, ctx)
     assert m == "hash" and mo == 5 * 10**7
+    with pytest.raises(kp.KPError) as e:   # eight segments of 6.3e12 codes: no dense mode
+        kp.mul_bound(l4, True, kp.KP_F64, "dense", 5000, 5000, ctx)
+    assert e.value.status == kp.KP_E_MODE
+    # a small Poisson key space: dense (two trig variables, multipliers up to 5)
+    l5 = kp.layout_product(2, 2, [-3] * 2, [3] * 2, [-2] * 2, [4] * 2, [5] * 2, [5] * 2)
+    m, mo, ws = kp.mul_bound(l5, True, kp.KP_F64, "auto", 700, 650, ctx)
+    assert m == "dense" and mo == min(2 * 700 * 650, l5.nkeys)
 
 
 def test_planning_errors():
