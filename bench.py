@@ -66,10 +66,18 @@ def parse():
     ap.add_argument("--requests", type=int, default=300,
                     help="requests of the mixed stream for the serving measurement (0: skip)")
     ap.add_argument("--max-batch", type=int, default=16)
+    ap.add_argument("--only", choices=sorted(EXTRA), default=None,
+                    help="run this one of the other workloads after the headline (no autotune, "
+                         "no others), e.g. to profile its kernels alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run device-to-device copies of 256 MiB (a plain copy kernel of "
                          "known size, used to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def note(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def to_dev(a):
@@ -143,7 +151,82 @@ def measure_poisson(kp, ctx, a, b, mode, steps, warmup):
     time_steps(lambda: poisson_step(kp, ctx, ws, sa, sb, mode), steps, 0)
     kms, launches = ctx.timing_read()
     ctx.timing(False)
-    return dict(sec=sec, kernel_s=kms / 1e3 / max(launches, 1), n_out=n_out)
+    lay = kp.poisson_layout(sa, sb, ctx)
+    m, _, _ = kp.mul_bound(lay, True, kp.KP_F64, mode, len(a[3]), len(b[3]), ctx)
+    return dict(sec=sec, kernel_s=kms / 1e3 / max(launches, 1), n_out=n_out, mode=m)
+
+
+def hash_probe_stats(kp, ctx, fn):
+    """Insertions and mean extra probe steps of one more call of fn."""
+    import torch
+    torch.cuda.synchronize()
+    ctx.hash_stats_read()
+    ctx.hash_stats(True)
+    fn()
+    ins, extra = ctx.hash_stats_read()
+    ctx.hash_stats(False)
+    return {"inserts": ins, "extra_probes_per_insert": extra / max(ins, 1)}
+
+
+def run_box(kp, ctx, I, args):
+    a1, b1 = I.config(1)
+    r1 = measure_laurent(kp, ctx, a1, b1, "auto", max(args.steps, 20), args.warmup)
+    return {"term_products_per_s": 250000 / r1["sec"], "ms_per_step": r1["sec"] * 1e3,
+            "mode": r1["mode"]}
+
+
+def run_sparse(kp, ctx, I, args):
+    a3, b3 = I.config(3)
+    r3 = measure_laurent(kp, ctx, a3, b3, "auto", 3, 1)
+    alg_bytes = 32 * 9e8 + 16 * r3["n_out"]
+    out = {"term_products_per_s": 9e8 / r3["sec"], "ms_per_step": r3["sec"] * 1e3,
+           "mode": r3["mode"], "result_terms": r3["n_out"],
+           "insert_kernel_ms": r3["kernel_s"] * 1e3,
+           "hbm_frac_of_insert": alg_bytes / r3["kernel_s"] / 1e9 / HBM_PEAK_GBS}
+    if r3["mode"] == "hash":
+        pa = kp.Poly(to_dev(a3[0]), to_dev(a3[1]))
+        pb = kp.Poly(to_dev(b3[0]), to_dev(b3[1]))
+        out["probing"] = hash_probe_stats(
+            kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "auto"))
+    return out
+
+
+def run_fateman(kp, ctx, I, args):
+    f, g = I.fateman(30), I.fateman(30, plus_one=True)
+    rf = measure_laurent(kp, ctx, f, g, "auto", 5, 1)
+    pf = len(f[1]) * len(g[1])
+    return {"term_products_per_s": pf / rf["sec"], "ms_per_step": rf["sec"] * 1e3,
+            "term_products": pf, "mode": rf["mode"], "result_terms": rf["n_out"],
+            "window_kernel_ms": rf["kernel_s"] * 1e3,
+            "paper_cpu_context": "4.29 s on one Core2 Q6600 core, fp64 (5.0e8 pairs/s)"}
+
+
+def run_mp(kp, ctx, I, args):
+    f, g = I.mp_sparse(12, "f"), I.mp_sparse(12, "g")
+    rm = measure_laurent(kp, ctx, f, g, "auto", 5, 1)
+    pm = len(f[1]) * len(g[1])
+    out = {"term_products_per_s": pm / rm["sec"], "ms_per_step": rm["sec"] * 1e3,
+           "term_products": pm, "mode": rm["mode"], "result_terms": rm["n_out"],
+           "insert_kernel_ms": rm["kernel_s"] * 1e3,
+           "paper_cpu_context": "1.71 s on one Core2 Q6600 core, fp64 (2.2e7 pairs/s)"}
+    if rm["mode"] == "hash":
+        pa = kp.Poly(to_dev(f[0]), to_dev(f[1]))
+        pb = kp.Poly(to_dev(g[0]), to_dev(g[1]))
+        out["probing"] = hash_probe_stats(
+            kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "auto"))
+    return out
+
+
+def run_poisson(kp, ctx, I, args):
+    a4, b4 = I.config(4)
+    r4 = measure_poisson(kp, ctx, a4, b4, "auto", 5, 1)
+    return {"term_products_per_s": 2.5e7 / r4["sec"], "ms_per_step": r4["sec"] * 1e3,
+            "result_terms": r4["n_out"], "mode": r4["mode"],
+            "accumulation_kernel_ms": r4["kernel_s"] * 1e3}
+
+
+EXTRA = {"box_500x500": run_box, "sparse_30000x30000": run_sparse, "fateman_30": run_fateman,
+         "mp_sparse_12": run_mp, "poisson_5000x5000": run_poisson}
 
 
 def measure_serving(kp, n_requests, max_batch):
@@ -213,6 +296,7 @@ def main():
     ctx = kp.context(0)
     a, b = I.config(2)
     pairs = len(a[1]) * len(b[1])
+    note("headline", len(a[1]), "x", len(b[1]))
     r = measure_laurent(kp, ctx, a, b, "auto", args.steps, args.warmup)
     value = pairs / r["sec"]
     kernel_rate = pairs / r["kernel_s"]
@@ -237,53 +321,30 @@ def main():
                                     "encoded codes"},
         "roofline": roof,
     }
-    if not args.no_extra:
+    # measured ceilings of the window kernel's accumulator (context for frac)
+    cons, rnd = ctx.probe_lds_atomic(0), ctx.probe_lds_atomic(1)
+    roof["measured_lds_atomic"] = {
+        "consecutive_Tacc_per_s": cons / 1e12, "random_Tacc_per_s": rnd / 1e12,
+        "frac_of_consecutive": kernel_rate / cons,
+        "probe": "ds_add_u64 on every CU, 1024-thread workgroups, 128 KiB LDS counters"}
+    if args.only:
+        out["other_workloads"] = {args.only: EXTRA[args.only](kp, ctx, I, args)}
+    elif not args.no_extra:
         # the autotuner picks the open knobs; the measurements below use them
         from paper_1004_4548_amd import tune
+        note("autotune")
         t = time.perf_counter()
         tuned = tune.autotune(ctx, apply=True, quick=True)
         tuned["seconds"] = time.perf_counter() - t
         out["autotune"] = tuned
         extra = {}
-        a1, b1 = I.config(1)
-        r1 = measure_laurent(kp, ctx, a1, b1, "auto", max(args.steps, 20), args.warmup)
-        extra["box_500x500"] = {"term_products_per_s": 250000 / r1["sec"],
-                                "ms_per_step": r1["sec"] * 1e3, "mode": r1["mode"]}
-        a3, b3 = I.config(3)
-        r3 = measure_laurent(kp, ctx, a3, b3, "auto", 3, 1)
-        alg_bytes = 32 * 9e8 + 16 * r3["n_out"]
-        extra["sparse_30000x30000"] = {
-            "term_products_per_s": 9e8 / r3["sec"], "ms_per_step": r3["sec"] * 1e3,
-            "mode": r3["mode"], "result_terms": r3["n_out"],
-            "insert_kernel_ms": r3["kernel_s"] * 1e3,
-            "hbm_frac_of_insert": alg_bytes / r3["kernel_s"] / 1e9 / HBM_PEAK_GBS}
-        del a3, b3
-        torch.cuda.empty_cache()
-        # the paper's own benchmarks (Section 5), regenerated from their closed forms
-        f, g = I.fateman(30), I.fateman(30, plus_one=True)
-        rf = measure_laurent(kp, ctx, f, g, "auto", 5, 1)
-        pf = len(f[1]) * len(g[1])
-        extra["fateman_30"] = {
-            "term_products_per_s": pf / rf["sec"], "ms_per_step": rf["sec"] * 1e3,
-            "term_products": pf, "mode": rf["mode"], "result_terms": rf["n_out"],
-            "window_kernel_ms": rf["kernel_s"] * 1e3,
-            "paper_cpu_context": "4.29 s on one Core2 Q6600 core, fp64 (5.0e8 pairs/s)"}
-        f, g = I.mp_sparse(12, "f"), I.mp_sparse(12, "g")
-        rm = measure_laurent(kp, ctx, f, g, "auto", 5, 1)
-        pm = len(f[1]) * len(g[1])
-        extra["mp_sparse_12"] = {
-            "term_products_per_s": pm / rm["sec"], "ms_per_step": rm["sec"] * 1e3,
-            "term_products": pm, "mode": rm["mode"], "result_terms": rm["n_out"],
-            "insert_kernel_ms": rm["kernel_s"] * 1e3,
-            "paper_cpu_context": "1.71 s on one Core2 Q6600 core, fp64 (2.2e7 pairs/s)"}
-        a4, b4 = I.config(4)
-        r4 = measure_poisson(kp, ctx, a4, b4, "auto", 5, 1)
-        extra["poisson_5000x5000"] = {"term_products_per_s": 2.5e7 / r4["sec"],
-                                      "ms_per_step": r4["sec"] * 1e3,
-                                      "result_terms": r4["n_out"],
-                                      "insert_kernel_ms": r4["kernel_s"] * 1e3}
+        for name, run in EXTRA.items():
+            note(name)
+            extra[name] = run(kp, ctx, I, args)
+            torch.cuda.empty_cache()
         out["other_workloads"] = extra
     if args.requests > 0:
+        note("stream of", args.requests, "requests")
         out["stream"] = measure_serving(kp, args.requests, args.max_batch)
     if args.calibrate_copy:
         n = 256 << 20
@@ -294,6 +355,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = n
     if not args.no_cpu_baseline:
+        note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -147,6 +147,29 @@ const char* kp_last_error(const kp_ctx* ctx);
 kp_status kp_ctx_timing(kp_ctx* ctx, int enable);
 kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Hash-table statistics (Section 3.2: open addressing with linear probing).
+   While enabled, every hash-mode multiply adds to two device counters in the
+   context's status block: the number of term products inserted (nonzero
+   ones) and the number of slots visited beyond each product's home slot.
+   Their ratio is the mean extra probe length the load factor buys.
+   kp_ctx_hash_stats_read synchronises `stream`, returns both counts and
+   clears them.  Enabling costs one atomic pair per wavefront per launch.
+   Disabled by default. */
+kp_status kp_ctx_hash_stats(kp_ctx* ctx, int enable);
+kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inserts,
+                                 int64_t* extra_probes);
+
+/* Measured denominator of the dense window kernel's roofline (Section 3.1:
+   the dense accumulation is one read-modify-write of a 64-bit counter per
+   term product, held in LDS).  Times 64-bit LDS atomic adds on every
+   compute unit, one 1024-thread workgroup with a 128 KiB array per unit:
+   pattern 0 gives each wavefront 64 consecutive 8-byte counters (no bank
+   conflicts), pattern 1 pseudo-random counters.  Writes the device-wide
+   rate in adds per second to *adds_per_second.  Runs twice (the first run
+   warms up) and synchronises `stream`.  Touches no caller memory. */
+kp_status kp_probe_lds_atomic(kp_ctx* ctx, int pattern, double* adds_per_second,
+                              hipStream_t stream);
+
 /*
  * Per-variable minimum and maximum of an int32 [n][nvars] device array, into
  * the device array out[2*nvars] = {min_0..min_{nvars-1}, max_0..max_{nvars-1}}.

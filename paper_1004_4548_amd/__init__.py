@@ -39,7 +39,8 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_ctx_timing_read", "kp_minmax", "kp_layout_product",
             "kp_encode", "kp_mul_bound", "kp_mul_laurent", "kp_mul_poisson", "kp_decode",
             "kp_encode_host", "kp_decode_host", "kp_batch_create", "kp_batch_destroy",
-            "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status"]
+            "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status",
+            "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic"]
 
 
 class KPError(RuntimeError):
@@ -117,6 +118,9 @@ def lib():
         "kp_batch_clear": (i32, [p]),
         "kp_batch_launch": (i32, [p, u32, p]),
         "kp_batch_status": (i32, [p, i64, C.POINTER(i64)]),
+        "kp_ctx_hash_stats": (i32, [p, i32]),
+        "kp_ctx_hash_stats_read": (i32, [p, p, C.POINTER(i64), C.POINTER(i64)]),
+        "kp_probe_lds_atomic": (i32, [p, i32, C.POINTER(C.c_double), p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -225,6 +229,24 @@ class Context:
         n = C.c_int64()
         self.check(lib().kp_ctx_timing_read(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def hash_stats(self, enable=True):
+        """Count insertions and extra probe steps of every hash-mode multiply."""
+        self.check(lib().kp_ctx_hash_stats(self.h, 1 if enable else 0))
+
+    def hash_stats_read(self, stream=None):
+        """(insertions, slots visited beyond the home slots) since the last read."""
+        n = C.c_int64()
+        x = C.c_int64()
+        self.check(lib().kp_ctx_hash_stats_read(self.h, _stream(stream), C.byref(n), C.byref(x)))
+        return n.value, x.value
+
+    def probe_lds_atomic(self, pattern=0, stream=None):
+        """Device-wide 64-bit LDS atomic adds per second (0: conflict-free
+        consecutive counters, 1: pseudo-random counters)."""
+        r = C.c_double()
+        self.check(lib().kp_probe_lds_atomic(self.h, pattern, C.byref(r), _stream(stream)))
+        return r.value
 
     def sync_check(self, stream=None):
         self.check(lib().kp_ctx_check(self.h, _stream(stream)))

@@ -19,6 +19,7 @@ struct kp_ctx {
   kp::CtxStatus* status = nullptr;   // device
   std::string err;
   bool timing = false;
+  bool hash_stats = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // pool
   size_t events_used = 0;
 };
@@ -82,6 +83,11 @@ std::pair<hipEvent_t, hipEvent_t> timing_pair(kp_ctx* ctx) {
     ctx->events.emplace_back(a, b);
   }
   return ctx->events[ctx->events_used++];
+}
+
+// Device counters {insertions, extra probe steps} when statistics are on.
+unsigned long long* hash_stats_ptr(kp_ctx* ctx) {
+  return ctx->hash_stats ? &ctx->status->inserts : nullptr;
 }
 
 kp_status finish(kp_ctx* ctx, unsigned flags, hipStream_t s, const char* what) {
@@ -446,6 +452,42 @@ kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches) {
   return KP_OK;
 }
 
+kp_status kp_ctx_hash_stats(kp_ctx* ctx, int enable) {
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  ctx->hash_stats = enable != 0;
+  return KP_OK;
+}
+
+kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inserts,
+                                 int64_t* extra_probes) {
+  if (!ctx || !inserts || !extra_probes) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  hipError_t e = hipStreamSynchronize(stream);
+  unsigned long long v[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(v, &ctx->status->inserts, sizeof v, hipMemcpyDeviceToHost);
+  const unsigned long long zero[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(&ctx->status->inserts, zero, sizeof zero, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_ctx_hash_stats_read");
+  *inserts = (int64_t)v[0];
+  *extra_probes = (int64_t)v[1];
+  return KP_OK;
+}
+
+kp_status kp_probe_lds_atomic(kp_ctx* ctx, int pattern, double* adds_per_second,
+                              hipStream_t stream) {
+  if (!ctx || !adds_per_second) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (pattern != 0 && pattern != 1) return fail(ctx, KP_E_ARG, "pattern must be 0 or 1");
+  const int blocks = 2 * ctx->num_cu, iters = 1024;
+  float ms = 0;
+  hipError_t e = probe_lds_atomic(pattern, blocks, iters, ctx->status->sink, &ms, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_probe_lds_atomic");
+  if (!(ms > 0)) return fail(ctx, KP_E_DEVICE, "kp_probe_lds_atomic: no elapsed time");
+  *adds_per_second = (double)blocks * 1024.0 * 16.0 * iters / (ms * 1e-3);
+  return KP_OK;
+}
+
 kp_status kp_ctx_destroy(kp_ctx* ctx) {
   if (!ctx) return KP_E_ARG;
   for (auto& pr : ctx->events) {
@@ -651,7 +693,7 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
     HashCarve h;
     carve_hash(c, p, 0, na, nb, &h);
     HashBufs H{h.meta, h.table, p.cap, p.cap, out_codes, out_coef, out_cap,
-               nullptr, nullptr};
+               nullptr, nullptr, hash_stats_ptr(ctx)};
     if (!empty && timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
     if (!empty) {
@@ -721,7 +763,7 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
   HashCarve h;
   carve_hash(c, p, 1, na, nb, &h);
   HashBufs H{h.meta, h.table, p.cap, p.cap, out_keys, out_coef, out_cap,
-             nullptr, nullptr};
+             nullptr, nullptr, hash_stats_ptr(ctx)};
   hipError_t e = launch_meta_init(h.meta, stream);
   if (na > 0 && nb > 0 && layout->nkeys > 0) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);

@@ -53,10 +53,11 @@ __device__ __forceinline__ uint64_t key_load(const uint64_t* p) {
 // claimed; at most max_probe slots are visited before the table is declared
 // full.  An occupied slot is skipped after a plain (atomic) load; only an
 // empty slot costs a compare-and-swap.
+// Returns the number of slots visited beyond the home slot.
 template <typename T>
-__device__ __noinline__ void table_probe(uint64_t* __restrict__ table, uint64_t cap,
-                                         int64_t max_probe, uint64_t s, uint64_t cur, uint64_t key,
-                                         T v, uint32_t* err) {
+__device__ __noinline__ int64_t table_probe(uint64_t* __restrict__ table, uint64_t cap,
+                                            int64_t max_probe, uint64_t s, uint64_t cur,
+                                            uint64_t key, T v, uint32_t* err) {
   for (int64_t p = 0; p < max_probe; ++p) {
     uint64_t* ks = table + 2 * s;
     if (p > 0) cur = key_load(ks);
@@ -66,11 +67,24 @@ __device__ __noinline__ void table_probe(uint64_t* __restrict__ table, uint64_t 
     }
     if (cur == key) {
       slot_add(ks + 1, v);
-      return;
+      return p;
     }
     s = s + 1 == cap ? 0 : s + 1;
   }
   atomicOr(err, ERR_CAPACITY);
+  return max_probe;
+}
+
+// Adds a thread's counts into the context's statistics (one atomic per wavefront).
+__device__ __forceinline__ void add_stats(unsigned long long* stats, int64_t ins, int64_t probes) {
+  for (int off = 32; off > 0; off >>= 1) {
+    ins += __shfl_xor(ins, off);
+    probes += __shfl_xor(probes, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&stats[0], (unsigned long long)ins);
+    atomicAdd(&stats[1], (unsigned long long)probes);
+  }
 }
 
 // Insert-or-accumulate of NB independent contributions.  The key words of
@@ -81,9 +95,10 @@ __device__ __noinline__ void table_probe(uint64_t* __restrict__ table, uint64_t 
 // combine in any order because the coefficient word only ever receives
 // atomic adds.
 template <typename T, int NB>
-__device__ __forceinline__ void table_insert_n(uint64_t* __restrict__ table, uint64_t cap,
-                                               int64_t max_probe, const int64_t* code,
-                                               const T* v, const bool* on, uint32_t* err) {
+__device__ __forceinline__ int64_t table_insert_n(uint64_t* __restrict__ table, uint64_t cap,
+                                                  int64_t max_probe, const int64_t* code,
+                                                  const T* v, const bool* on, uint32_t* err) {
+  int64_t extra = 0;
   uint64_t s[NB], cur[NB];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
@@ -97,8 +112,9 @@ __device__ __forceinline__ void table_insert_n(uint64_t* __restrict__ table, uin
     if (cur[u] == key)
       slot_add(table + 2 * s[u] + 1, v[u]);
     else
-      table_probe<T>(table, cap, max_probe, s[u], cur[u], key, v[u], err);
+      extra += table_probe<T>(table, cap, max_probe, s[u], cur[u], key, v[u], err);
   }
+  return extra;
 }
 
 template <typename T>
@@ -124,16 +140,19 @@ template <typename T>
 __global__ void __launch_bounds__(HASH_BLOCK)
 k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Meta* meta,
                const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
-               const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows) {
+               const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows,
+               unsigned long long* stats) {
   constexpr int NB = 4;
-  const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows;
   const int64_t i1 = min(i0 + rows, na);
   const uint32_t narrow = meta->narrow;
-  if (j >= nb) return;
+  const bool live = j0 < nb;
+  const int64_t j = live ? j0 : nb - 1;   // idle lanes stay for the statistics reduction
   const int64_t bj = bk[j];
   const T cb = bc[j];
-  for (int64_t i = i0; i < i1; i += NB) {
+  int64_t ins = 0, extra = 0;
+  for (int64_t i = live ? i0 : i1; i < i1; i += NB) {
     int64_t code[NB];
     T v[NB];
     bool on[NB];
@@ -144,9 +163,11 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
       v[u] = mul_coef<T>(ac[r], cb, narrow);
       code[u] = ak[r] + bj;
       on[u] = in && v[u] != T(0);
+      ins += on[u];
     }
-    table_insert_n<T, NB>(table, cap, max_probe, code, v, on, &meta->err);
+    extra += table_insert_n<T, NB>(table, cap, max_probe, code, v, on, &meta->err);
   }
+  if (stats) add_stats(stats, ins, extra);
 }
 
 __global__ void __launch_bounds__(HASH_BLOCK)
@@ -192,15 +213,18 @@ k_hash_poisson(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
                const uint8_t* __restrict__ at, const double* __restrict__ ac, int64_t na,
                const int64_t* __restrict__ bp, const int64_t* __restrict__ bm,
                const int64_t* __restrict__ bkx, const uint8_t* __restrict__ bt,
-               const double* __restrict__ bc, int64_t nb, int rows) {
-  const int64_t j = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+               const double* __restrict__ bc, int64_t nb, int rows,
+               unsigned long long* stats) {
+  const int64_t j0 = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows;
   const int64_t i1 = min(i0 + rows, na);
-  if (j >= nb) return;
+  const bool live = j0 < nb;
+  const int64_t j = live ? j0 : nb - 1;   // idle lanes stay for the statistics reduction
+  int64_t ins = 0, extra = 0;
   const int64_t Bp = bp[j], Bm = bm[j], kxb = bkx[j];
   const int tb = bt[j];
   const double cb = bc[j];
-  for (int64_t i = i0; i < i1; i += 2) {
+  for (int64_t i = live ? i0 : i1; i < i1; i += 2) {
     int64_t code[4];
     double v[4];
     bool on[4];
@@ -219,9 +243,11 @@ k_hash_poisson(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
           in && h != 0.0 && poisson_piece(Wx, ap[r] + Bp, kx, t, sp, &code[2 * u + 1], &v[2 * u + 1]);
       if (!on[2 * u]) code[2 * u] = 0;
       if (!on[2 * u + 1]) code[2 * u + 1] = 0;
+      ins += on[2 * u] + on[2 * u + 1];
     }
-    table_insert_n<double, 4>(table, cap, max_probe, code, v, on, &meta->err);
+    extra += table_insert_n<double, 4>(table, cap, max_probe, code, v, on, &meta->err);
   }
+  if (stats) add_stats(stats, ins, extra);
 }
 
 // ------------------------------------------------------------ compaction
@@ -297,11 +323,11 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
   if (dt == KP_F64)
     hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const double*)ac, na, bk,
-                       (const double*)bc, nb, rows);
+                       (const double*)bc, nb, rows, H.stats);
   else
     hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk,
-                       (const int64_t*)bc, nb, rows);
+                       (const int64_t*)bc, nb, rows, H.stats);
   if (H.ev1) (void)hipEventRecord(H.ev1, s);
   return hipGetLastError();
 }
@@ -324,7 +350,7 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
   if (H.ev0) (void)hipEventRecord(H.ev0, s);
   hipLaunchKernelGGL(k_hash_poisson, grid, dim3(HASH_BLOCK), 0, s, H.table, (uint64_t)H.cap,
                      H.max_probe, H.meta, Wx, P.ap, P.akx, P.at, ac, na, P.bp, P.bm, P.bkx, P.bt,
-                     bc, nb, rows);
+                     bc, nb, rows, H.stats);
   if (H.ev1) (void)hipEventRecord(H.ev1, s);
   return hipGetLastError();
 }

@@ -157,8 +157,13 @@ struct Meta {
 // Status block owned by a context (device memory, 256 bytes).
 struct CtxStatus {
   uint32_t err;
-  uint32_t pad[63];
+  uint32_t pad0;
+  unsigned long long inserts;    // hash insertions counted while statistics are on
+  unsigned long long probes;     // slots visited beyond the home slot
+  unsigned long long sink[16];   // discard area of the LDS atomic probe
+  uint32_t pad[26];
 };
+static_assert(sizeof(CtxStatus) == 256, "status block is 256 bytes");
 
 // ------------------------------------------------------------ launchers
 // codec
@@ -238,6 +243,7 @@ struct HashBufs {
   int64_t max_probe;
   int64_t* out_k; void* out_c; int64_t out_cap;
   hipEvent_t ev0, ev1;   // optional: recorded around the insert kernel
+  unsigned long long* stats;   // optional: {insertions, extra probe steps}
 };
 hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
                                int64_t na, const int64_t* bk, const void* bc, int64_t nb,
@@ -253,6 +259,10 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
                                const double* ac, int64_t na, const double* bc, int64_t nb,
                                int rows, hipStream_t s);
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
+
+// diagnostics (kp_diag.hip)
+hipError_t probe_lds_atomic(int random, int blocks, int iters, unsigned long long* sink,
+                            float* ms, hipStream_t s);
 
 // dense Poisson (kp_poisson.hip)
 hipError_t launch_poisson_dense_prep(int64_t Wx, int64_t N, int64_t Hya, int64_t Hyb,
