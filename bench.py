@@ -322,11 +322,12 @@ def main():
         "roofline": roof,
     }
     # measured ceilings of the window kernel's accumulator (context for frac)
-    cons, rnd = ctx.probe_lds_atomic(0), ctx.probe_lds_atomic(1)
+    rates = [ctx.probe_lds_atomic(p) for p in range(4)]
     roof["measured_lds_atomic"] = {
-        "consecutive_Tacc_per_s": cons / 1e12, "random_Tacc_per_s": rnd / 1e12,
-        "frac_of_consecutive": kernel_rate / cons,
-        "probe": "ds_add_u64 on every CU, 1024-thread workgroups, 128 KiB LDS counters"}
+        "u64_consecutive_Tacc_per_s": rates[0] / 1e12, "u64_random_Tacc_per_s": rates[1] / 1e12,
+        "u32_consecutive_Tacc_per_s": rates[2] / 1e12, "u32_random_Tacc_per_s": rates[3] / 1e12,
+        "frac_of_u64_consecutive": kernel_rate / rates[0],
+        "probe": "LDS atomic adds on every CU, 1024-thread workgroups, 128 KiB of counters"}
     if args.only:
         out["other_workloads"] = {args.only: EXTRA[args.only](kp, ctx, I, args)}
     elif not args.no_extra:

@@ -160,13 +160,14 @@ kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inser
                                  int64_t* extra_probes);
 
 /* Measured denominator of the dense window kernel's roofline (Section 3.1:
-   the dense accumulation is one read-modify-write of a 64-bit counter per
-   term product, held in LDS).  Times 64-bit LDS atomic adds on every
-   compute unit, one 1024-thread workgroup with a 128 KiB array per unit:
-   pattern 0 gives each wavefront 64 consecutive 8-byte counters (no bank
-   conflicts), pattern 1 pseudo-random counters.  Writes the device-wide
-   rate in adds per second to *adds_per_second.  Runs twice (the first run
-   warms up) and synchronises `stream`.  Touches no caller memory. */
+   the dense accumulation is one read-modify-write of a counter per term
+   product, held in LDS).  Times LDS atomic adds on every compute unit, one
+   1024-thread workgroup with a 128 KiB array per unit: pattern 0 gives each
+   wavefront 64 consecutive 8-byte counters (no bank conflicts), pattern 1
+   pseudo-random 8-byte counters, patterns 2 and 3 the same with 4-byte
+   counters.  Writes the device-wide rate in adds per second to
+   *adds_per_second.  Runs twice (the first run warms up) and synchronises
+   `stream`.  Touches no caller memory; KP_E_ARG for another pattern. */
 kp_status kp_probe_lds_atomic(kp_ctx* ctx, int pattern, double* adds_per_second,
                               hipStream_t stream);
 

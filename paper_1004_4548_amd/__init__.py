@@ -242,8 +242,8 @@ class Context:
         return n.value, x.value
 
     def probe_lds_atomic(self, pattern=0, stream=None):
-        """Device-wide 64-bit LDS atomic adds per second (0: conflict-free
-        consecutive counters, 1: pseudo-random counters)."""
+        """Device-wide LDS atomic adds per second: 0/1 = 64-bit counters,
+        consecutive (conflict-free) or pseudo-random; 2/3 = 32-bit counters."""
         r = C.c_double()
         self.check(lib().kp_probe_lds_atomic(self.h, pattern, C.byref(r), _stream(stream)))
         return r.value

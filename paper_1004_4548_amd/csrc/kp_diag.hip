@@ -1,10 +1,10 @@
 // kp_diag.hip -- measurements of the roofline denominators on the device.
 //
-// The dense window kernel is bound by 64-bit LDS atomic adds.  This probe
-// fills every compute unit with one 1024-thread workgroup holding a 128 KiB
-// LDS array and times ds_add_u64 at two address patterns: consecutive
-// 8-byte slots per wavefront (no bank conflicts) and pseudo-random slots
-// (the conflicts of data-dependent addresses).
+// The dense window kernel is bound by LDS atomic adds.  This probe fills
+// every compute unit with one 1024-thread workgroup holding a 128 KiB LDS
+// array and times atomic adds of 64-bit or 32-bit counters at two address
+// patterns: consecutive counters per wavefront (no bank conflicts) and
+// pseudo-random counters (the conflicts of data-dependent addresses).
 #include "kp_internal.h"
 
 namespace kp {
@@ -12,12 +12,13 @@ namespace kp {
 namespace {
 
 constexpr int PROBE_BLOCK = 1024;
-constexpr int PROBE_SLOTS = 16384;   // 128 KiB of 8-byte counters
+constexpr int PROBE_BYTES = 131072;
 constexpr int PROBE_UNROLL = 16;
 
-template <int RANDOM>
+template <typename T, int RANDOM>
 __global__ void __launch_bounds__(PROBE_BLOCK) k_lds_atomic_probe(unsigned long long* out, int iters) {
-  __shared__ unsigned long long buf[PROBE_SLOTS];
+  constexpr int PROBE_SLOTS = PROBE_BYTES / (int)sizeof(T);
+  __shared__ T buf[PROBE_SLOTS];
   const int tid = threadIdx.x;
   for (int i = tid; i < PROBE_SLOTS; i += PROBE_BLOCK) buf[i] = 0;
   __syncthreads();
@@ -38,16 +39,17 @@ __global__ void __launch_bounds__(PROBE_BLOCK) k_lds_atomic_probe(unsigned long 
 #pragma unroll
     for (int u = 0; u < PROBE_UNROLL; ++u) {
       const uint32_t s = RANDOM ? ((slot[u] + (uint32_t)it * 977u) & (PROBE_SLOTS - 1)) : slot[u];
-      atomicAdd(&buf[s], 1ull);
+      atomicAdd(&buf[s], (T)1);
     }
   }
   __syncthreads();
-  if (tid == 0) out[blockIdx.x % 16] = buf[0] + buf[PROBE_SLOTS - 1];   // keeps the adds
+  if (tid == 0) out[blockIdx.x % 16] = (unsigned long long)buf[0] + buf[PROBE_SLOTS - 1];   // keeps the adds
 }
 
 }  // namespace
 
-hipError_t probe_lds_atomic(int random, int blocks, int iters, unsigned long long* sink,
+// pattern: 0/1 = 64-bit consecutive/random, 2/3 = 32-bit consecutive/random.
+hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
                             float* ms, hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
@@ -55,12 +57,24 @@ hipError_t probe_lds_atomic(int random, int blocks, int iters, unsigned long lon
   if (e == hipSuccess) {
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first run warms up
       e = hipEventRecord(a, s);
-      if (random)
-        hipLaunchKernelGGL(k_lds_atomic_probe<1>, dim3(blocks), dim3(PROBE_BLOCK), 0, s, sink,
-                           iters);
-      else
-        hipLaunchKernelGGL(k_lds_atomic_probe<0>, dim3(blocks), dim3(PROBE_BLOCK), 0, s, sink,
-                           iters);
+      switch (pattern) {
+        case 0:
+          hipLaunchKernelGGL((k_lds_atomic_probe<unsigned long long, 0>), dim3(blocks),
+                             dim3(PROBE_BLOCK), 0, s, sink, iters);
+          break;
+        case 1:
+          hipLaunchKernelGGL((k_lds_atomic_probe<unsigned long long, 1>), dim3(blocks),
+                             dim3(PROBE_BLOCK), 0, s, sink, iters);
+          break;
+        case 2:
+          hipLaunchKernelGGL((k_lds_atomic_probe<unsigned int, 0>), dim3(blocks), dim3(PROBE_BLOCK),
+                             0, s, sink, iters);
+          break;
+        default:
+          hipLaunchKernelGGL((k_lds_atomic_probe<unsigned int, 1>), dim3(blocks), dim3(PROBE_BLOCK),
+                             0, s, sink, iters);
+          break;
+      }
       if (e == hipSuccess) e = hipGetLastError();
       if (e == hipSuccess) e = hipEventRecord(b, s);
       if (e == hipSuccess) e = hipEventSynchronize(b);

@@ -261,7 +261,7 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
 
 // diagnostics (kp_diag.hip)
-hipError_t probe_lds_atomic(int random, int blocks, int iters, unsigned long long* sink,
+hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
                             float* ms, hipStream_t s);
 
 // dense Poisson (kp_poisson.hip)

@@ -63,7 +63,7 @@ def test_hash_stats_poisson_counts_both_pieces():
     assert extra >= 0
 
 
-@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("pattern", [0, 1, 2, 3])
 def test_lds_atomic_probe(pattern):
     ctx = kp.context()
     say("lds atomic probe pattern", pattern)
