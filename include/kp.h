@@ -263,6 +263,81 @@ kp_status kp_decode(kp_ctx* ctx, const kp_layout* layout, int poisson, int64_t n
                     unsigned flags, hipStream_t stream);
 
 /*
+ * Whole products from exponents, in two calls (Sections 2 and 3: the code
+ * map from the factors' boxes, then the product of the coded factors, then
+ * the inverse map).  The plan call finds both factors' per-variable boxes in
+ * one kernel launch and waits for them (the kernel hands them over through
+ * a pinned host-coherent mailbox of the context, no stream synchronisation;
+ * serialised per context), then fills the product layout, the resolved
+ * mode, a bound on the result terms and the workspace bytes.  The multiply
+ * call queues encode, multiply and decode on `stream`; the decode reads the
+ * result count on the device.  The result lands in out_exps
+ * int32[out_cap][nvars] and out_coef[out_cap] (int64 or double); *out_n
+ * (device) is the number of terms, or -status on error (as for
+ * kp_mul_laurent, including errors of the encode, e.g. KP_E_RANGE for
+ * exponents outside the planned boxes).  With KP_FLAG_ASYNC the call
+ * returns once the work is queued and n_host is unused; without it the call
+ * waits for the count (through the mailbox), stores it in *n_host (when not
+ * null) and returns any error, read and cleared as by kp_ctx_check.
+ * Terms whose coefficient is exactly zero are dropped; order as for
+ * kp_mul_laurent.  Device in: a_exps int32[na][nvars], a_coef[na], same for
+ * B.  workspace: device, >= the planned bytes, caller-owned, contents
+ * undefined afterwards.  KP_E_WORKSPACE if it is smaller; KP_E_CODE_OVERFLOW
+ * (plan) when the product's codes would not fit in 62 bits.
+ */
+kp_status kp_plan_laurent(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,
+                          const int32_t* a_exps, int64_t na, const int32_t* b_exps, int64_t nb,
+                          kp_layout* layout, kp_mode* resolved, int64_t* max_out_terms,
+                          size_t* workspace_bytes, hipStream_t stream);
+kp_status kp_mul_laurent_exps(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                              unsigned flags, const int32_t* a_exps, const void* a_coef, int64_t na,
+                              const int32_t* b_exps, const void* b_coef, int64_t nb,
+                              int32_t* out_exps, void* out_coef, int64_t out_cap, int64_t* out_n,
+                              int64_t* n_host, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream);
+
+/*
+ * Plan and multiply in one call, for callers that keep buffers across
+ * products of similar size: the plan as kp_plan_laurent (its layout into
+ * *layout), then, when out_cap and workspace_bytes cover it, the multiply as
+ * kp_mul_laurent_exps.  *need_cap and *need_workspace always receive the
+ * sizes this product needs; when the given ones are smaller the call returns
+ * KP_E_WORKSPACE with nothing queued after the plan, and the caller may
+ * continue with kp_mul_laurent_exps and the returned layout.
+ */
+kp_status kp_mul_laurent_auto(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,
+                              unsigned flags, const int32_t* a_exps, const void* a_coef, int64_t na,
+                              const int32_t* b_exps, const void* b_coef, int64_t nb,
+                              int32_t* out_exps, void* out_coef, int64_t out_cap, int64_t* out_n,
+                              int64_t* n_host, void* workspace, size_t workspace_bytes,
+                              kp_layout* layout, int64_t* need_cap, size_t* need_workspace,
+                              hipStream_t stream);
+
+/*
+ * The same two calls for Poisson series in canonical form (Section 1,
+ * eq. ps_def; products by eq. werner as in kp_mul_poisson).  Per factor:
+ * x exponents int32[n][nx] (nx may be 0, then the x arrays may be null),
+ * trigonometric multipliers int32[n][ny] (ny >= 1), is_sin uint8[n],
+ * coefficients double[n].  The trigonometric half-widths of the layout are
+ * the largest |multiplier| per variable of each factor.  Out: out_x
+ * int32[out_cap][nx], out_y int32[out_cap][ny] (canonical: first nonzero
+ * multiplier positive), out_sin uint8[out_cap], out_coef double[out_cap],
+ * *out_n (device), n_host as above.  A non-canonical input term gives
+ * KP_E_NONCANONICAL.
+ */
+kp_status kp_plan_poisson(kp_ctx* ctx, int32_t nx, int32_t ny, kp_mode mode, const int32_t* a_x,
+                          const int32_t* a_y, int64_t na, const int32_t* b_x, const int32_t* b_y,
+                          int64_t nb, kp_layout* layout, kp_mode* resolved,
+                          int64_t* max_out_terms, size_t* workspace_bytes, hipStream_t stream);
+kp_status kp_mul_poisson_exps(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
+                              const int32_t* a_x, const int32_t* a_y, const uint8_t* a_sin,
+                              const double* a_coef, int64_t na, const int32_t* b_x,
+                              const int32_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                              int64_t nb, int32_t* out_x, int32_t* out_y, uint8_t* out_sin,
+                              double* out_coef, int64_t out_cap, int64_t* out_n, int64_t* n_host,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Batches: many products queued by one call (a systems pattern; it does not
  * change what any product computes).  A batch holds up to max_tasks
  * descriptors, each the arguments of one kp_mul_laurent or kp_mul_poisson

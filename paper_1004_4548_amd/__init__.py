@@ -40,7 +40,9 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_encode", "kp_mul_bound", "kp_mul_laurent", "kp_mul_poisson", "kp_decode",
             "kp_encode_host", "kp_decode_host", "kp_batch_create", "kp_batch_destroy",
             "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status",
-            "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic"]
+            "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic",
+            "kp_plan_laurent", "kp_mul_laurent_exps", "kp_plan_poisson", "kp_mul_poisson_exps",
+            "kp_mul_laurent_auto"]
 
 
 class KPError(RuntimeError):
@@ -121,6 +123,17 @@ def lib():
         "kp_ctx_hash_stats": (i32, [p, i32]),
         "kp_ctx_hash_stats_read": (i32, [p, p, C.POINTER(i64), C.POINTER(i64)]),
         "kp_probe_lds_atomic": (i32, [p, i32, C.POINTER(C.c_double), p]),
+        "kp_plan_laurent": (i32, [p, i32, i32, i32, p, i64, p, i64, C.POINTER(Layout),
+                                  C.POINTER(i32), C.POINTER(i64), C.POINTER(sz), p]),
+        "kp_mul_laurent_exps": (i32, [p, C.POINTER(Layout), i32, i32, u32, p, p, i64, p, p, i64,
+                                      p, p, i64, p, C.POINTER(i64), p, sz, p]),
+        "kp_mul_laurent_auto": (i32, [p, i32, i32, i32, u32, p, p, i64, p, p, i64, p, p, i64, p,
+                                      C.POINTER(i64), p, sz, C.POINTER(Layout), C.POINTER(i64),
+                                      C.POINTER(sz), p]),
+        "kp_plan_poisson": (i32, [p, i32, i32, i32, p, p, i64, p, p, i64, C.POINTER(Layout),
+                                  C.POINTER(i32), C.POINTER(i64), C.POINTER(sz), p]),
+        "kp_mul_poisson_exps": (i32, [p, C.POINTER(Layout), i32, u32, p, p, p, p, i64, p, p, p, p,
+                                      i64, p, p, p, p, i64, p, C.POINTER(i64), p, sz, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -267,6 +280,12 @@ def _stream(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+def _raw_stream(device):
+    """Handle of the current stream of `device` (a torch.device), as an int."""
+    import torch
+    return torch._C._cuda_getCurrentRawStream(device.index)
 
 
 def _ptr(t):
@@ -490,17 +509,76 @@ def laurent_layout(a: Poly, b: Poly, ctx=None) -> Layout:
     return layout_product(a.nv, 0, amin, amax, bmin, bmax)
 
 
-def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
-    """A * B for device-resident Laurent polynomials; returns (Poly, Layout)."""
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else mode
+
+
+def plan_laurent(a: Poly, b: Poly, mode="auto", ctx=None, stream=None):
+    """kp_plan_laurent: boxes of both factors (one launch, one wait) ->
+    (Layout, resolved mode name, max result terms, workspace bytes)."""
+    import torch
     ctx = ctx or context()
+    _dev_check(a.exps, torch.int32, "a.exps")
+    _dev_check(b.exps, torch.int32, "b.exps")
     if a.nv != b.nv:
         raise ValueError("factors must have the same number of variables")
-    lay = laurent_layout(a, b, ctx)
-    # encode errors latch on the context and surface in the multiply's count
-    ka, _ = encode(lay, 0, a.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
-    kb, _ = encode(lay, 1, b.exps, ctx=ctx, flags=KP_FLAG_ASYNC)
-    codes, coef, _ = mul_laurent_codes(lay, ka, a.coef, kb, b.coef, mode, ctx, workspace)
-    return Poly(decode(lay, codes, ctx=ctx, flags=KP_FLAG_ASYNC), coef), lay
+    s = _raw_stream(a.exps.device) if stream is None else stream.cuda_stream
+    lay, m, mo, ws = Layout(), C.c_int32(), C.c_int64(), C.c_size_t()
+    ctx.check(lib().kp_plan_laurent(ctx.h, a.nv, _dt(a.coef), _mode(mode), a.exps.data_ptr(),
+                                    a.exps.shape[0], b.exps.data_ptr(), b.exps.shape[0],
+                                    C.byref(lay), C.byref(m), C.byref(mo), C.byref(ws), s))
+    return lay, MODE_NAMES[m.value], mo.value, ws.value
+
+
+_SIZE_HINT = {}   # (na, nb, nvars, dtype, mode) -> (result capacity, workspace bytes)
+
+
+def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
+    """A * B for device-resident Laurent polynomials; returns (Poly, Layout).
+
+    One library call when the sizes of the last product of the same shape
+    still fit (kp_mul_laurent_auto: plan, encode, multiply, decode, wait for
+    the count), else the plan's sizes and a second call.  The device count
+    slot sits after the multiply's workspace."""
+    import torch
+    ctx = ctx or context()
+    _dev_check(a.exps, torch.int32, "a.exps")
+    _dev_check(b.exps, torch.int32, "b.exps")
+    _dev_check(a.coef, a.coef.dtype, "a.coef")
+    _dev_check(b.coef, a.coef.dtype, "b.coef")
+    if a.nv != b.nv:
+        raise ValueError("factors must have the same number of variables")
+    dev = a.exps.device
+    s = _raw_stream(dev)
+    na, nb, nv, dt, md = a.exps.shape[0], b.exps.shape[0], a.nv, _dt(a.coef), _mode(mode)
+    key = (na, nb, nv, dt, md)
+    cap, ws = _SIZE_HINT.get(key, (1, 0))
+    workspace = workspace or Workspace()
+    lay, n, need_cap, need_ws = Layout(), C.c_int64(), C.c_int64(), C.c_size_t()
+    for attempt in range(2):
+        ox = torch.empty((cap, nv), dtype=torch.int32, device=dev)
+        oc = torch.empty(cap, dtype=a.coef.dtype, device=dev)
+        ws_al = (ws + 255) & ~255
+        w = workspace.get(ws_al + 256, dev).data_ptr()
+        if attempt == 0:
+            st = lib().kp_mul_laurent_auto(
+                ctx.h, nv, dt, md, 0, a.exps.data_ptr(), a.coef.data_ptr(), na,
+                b.exps.data_ptr(), b.coef.data_ptr(), nb, ox.data_ptr(), oc.data_ptr(), cap,
+                w + ws_al, C.byref(n), w, ws_al, C.byref(lay), C.byref(need_cap),
+                C.byref(need_ws), s)
+            if st == KP_E_WORKSPACE and (need_cap.value > cap or need_ws.value > ws):
+                cap, ws = need_cap.value, need_ws.value
+                _SIZE_HINT[key] = (cap, ws)
+                continue
+        else:
+            st = lib().kp_mul_laurent_exps(
+                ctx.h, C.byref(lay), dt, md, 0, a.exps.data_ptr(), a.coef.data_ptr(), na,
+                b.exps.data_ptr(), b.coef.data_ptr(), nb, ox.data_ptr(), oc.data_ptr(), cap,
+                w + ws_al, C.byref(n), w, ws_al, s)
+        ctx.check(st)
+        break
+    n = n.value
+    return Poly(ox[:n], oc[:n]), lay
 
 
 def poisson_layout(a: PoissonSeries, b: PoissonSeries, ctx=None) -> Layout:
@@ -512,16 +590,51 @@ def poisson_layout(a: PoissonSeries, b: PoissonSeries, ctx=None) -> Layout:
     return layout_product(nx, ny, amin, amax, bmin, bmax, ha, hb)
 
 
+def plan_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, stream=None):
+    """kp_plan_poisson -> (Layout, resolved mode name, max result terms, workspace bytes)."""
+    import torch
+    ctx = ctx or context()
+    for t, nm in ((a.x, "a.x"), (a.y, "a.y"), (b.x, "b.x"), (b.y, "b.y")):
+        _dev_check(t, torch.int32, nm)
+    nx, ny = a.x.shape[1], a.y.shape[1]
+    if (b.x.shape[1], b.y.shape[1]) != (nx, ny):
+        raise ValueError("factors must have the same numbers of variables")
+    s = _raw_stream(a.y.device) if stream is None else stream.cuda_stream
+    lay, m, mo, ws = Layout(), C.c_int32(), C.c_int64(), C.c_size_t()
+    ctx.check(lib().kp_plan_poisson(ctx.h, nx, ny, _mode(mode), a.x.data_ptr(), a.y.data_ptr(),
+                                    a.y.shape[0], b.x.data_ptr(), b.y.data_ptr(), b.y.shape[0],
+                                    C.byref(lay), C.byref(m), C.byref(mo), C.byref(ws), s))
+    return lay, MODE_NAMES[m.value], mo.value, ws.value
+
+
 def mul_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, workspace=None):
     """A * B for device-resident canonical Poisson series; returns (series, Layout)."""
+    import torch
     ctx = ctx or context()
-    lay = poisson_layout(a, b, ctx)
-    kxa, kya = encode(lay, 0, a.x, a.y, a.is_sin, ctx=ctx, flags=KP_FLAG_ASYNC)
-    kxb, kyb = encode(lay, 1, b.x, b.y, b.is_sin, ctx=ctx, flags=KP_FLAG_ASYNC)
-    keys, coef, _ = mul_poisson_codes(lay, (kxa, kya, a.is_sin, a.coef),
-                                      (kxb, kyb, b.is_sin, b.coef), mode, ctx, workspace)
-    x, y, t = decode(lay, keys, poisson=True, ctx=ctx, flags=KP_FLAG_ASYNC)
-    return PoissonSeries(x, y, t, coef), lay
+    for t, nm in ((a.is_sin, "a.is_sin"), (b.is_sin, "b.is_sin")):
+        _dev_check(t, torch.uint8, nm)
+    for t, nm in ((a.coef, "a.coef"), (b.coef, "b.coef")):
+        _dev_check(t, torch.float64, nm)
+    dev = a.y.device
+    s = _raw_stream(dev)
+    lay, _, max_out, ws = plan_poisson(a, b, mode, ctx)
+    cap = max(max_out, 1)
+    nx, ny = a.x.shape[1], a.y.shape[1]
+    ox = torch.empty((cap, nx), dtype=torch.int32, device=dev)
+    oy = torch.empty((cap, ny), dtype=torch.int32, device=dev)
+    ot = torch.empty(cap, dtype=torch.uint8, device=dev)
+    oc = torch.empty(cap, dtype=torch.float64, device=dev)
+    ws_al = (ws + 255) & ~255
+    wbuf = (workspace or Workspace()).get(ws_al + 256, dev)
+    w = wbuf.data_ptr()
+    n = C.c_int64()
+    ctx.check(lib().kp_mul_poisson_exps(
+        ctx.h, C.byref(lay), _mode(mode), 0, a.x.data_ptr(), a.y.data_ptr(), a.is_sin.data_ptr(),
+        a.coef.data_ptr(), a.y.shape[0], b.x.data_ptr(), b.y.data_ptr(), b.is_sin.data_ptr(),
+        b.coef.data_ptr(), b.y.shape[0], ox.data_ptr(), oy.data_ptr(), ot.data_ptr(),
+        oc.data_ptr(), cap, w + ws_al, C.byref(n), w, ws_al, s))
+    n = n.value
+    return PoissonSeries(ox[:n], oy[:n], ot[:n], oc[:n]), lay
 
 
 # ------------------------------------------------------------------ batches

@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <climits>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -22,6 +24,11 @@ struct kp_ctx {
   bool hash_stats = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // pool
   size_t events_used = 0;
+  int32_t* box_dev = nullptr;         // device: box accumulator and its counter
+  kp::Mailbox* mb = nullptr;          // pinned host-coherent mailbox (host address)
+  kp::Mailbox* mb_dev = nullptr;      // the same, device address
+  uint64_t seq = 0;                   // last sequence number handed to a kernel
+  std::mutex mb_mu;                   // serialises mailbox users
 };
 
 namespace kp {
@@ -88,6 +95,103 @@ std::pair<hipEvent_t, hipEvent_t> timing_pair(kp_ctx* ctx) {
 // Device counters {insertions, extra probe steps} when statistics are on.
 unsigned long long* hash_stats_ptr(kp_ctx* ctx) {
   return ctx->hash_stats ? &ctx->status->inserts : nullptr;
+}
+
+// Layout of kp_ctx::box_dev (int32 words): accumulator of four arrays
+// (mins, then maxes), then the completion counter.
+constexpr int BOX_SET = 2 * KP_MAX_VARS;
+constexpr int BOX_ACC = 0, BOX_DONE = 4 * BOX_SET;
+constexpr int BOX_WORDS = BOX_DONE + 64;
+
+hipError_t box_init(int32_t* dev) {
+  std::vector<int32_t> h(BOX_WORDS, 0);
+  for (int g = 0; g < 4; ++g)
+    for (int v = 0; v < KP_MAX_VARS; ++v) {
+      h[BOX_ACC + g * BOX_SET + v] = INT_MAX;
+      h[BOX_ACC + g * BOX_SET + KP_MAX_VARS + v] = INT_MIN;
+    }
+  return hipMemcpy(dev, h.data(), sizeof(int32_t) * BOX_WORDS, hipMemcpyHostToDevice);
+}
+
+// Spins until the kernel side writes `want` to a mailbox sequence slot.
+// Every few hundred polls the stream is queried, so that a stream that
+// failed, or finished without signalling, ends the wait with an error.
+kp_status wait_seq(kp_ctx* ctx, const uint64_t* slot, uint64_t want, hipStream_t s,
+                   const char* what) {
+  for (uint64_t spins = 1;; ++spins) {
+    if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == want) return KP_OK;
+    __builtin_ia32_pause();
+    if ((spins & 255) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == want) return KP_OK;
+        return fail(ctx, KP_E_DEVICE, "%s: the stream finished without signalling", what);
+      }
+      if (q != hipErrorNotReady) return hip_fail(ctx, q, what);
+    }
+  }
+}
+
+// Blocking end of a from-exponents multiply: the count and the latched
+// status come back through the mailbox; an error is then read and cleared
+// from the status block as by kp_ctx_check.
+kp_status wait_count(kp_ctx* ctx, const int64_t* out_n, int64_t* n_host, hipStream_t s,
+                     const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
+  int64_t n;
+  uint32_t err;
+  {
+    std::lock_guard<std::mutex> guard(ctx->mb_mu);
+    const uint64_t seq = ++ctx->seq;
+    e = launch_post_count(out_n, &ctx->status->err, ctx->mb_dev, seq, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    kp_status st = wait_seq(ctx, &ctx->mb->n_seq, seq, s, what);
+    if (st != KP_OK) return st;
+    n = ctx->mb->n;
+    err = ctx->mb->err;
+  }
+  if (n < 0 || err) {
+    kp_status st = sync_status(ctx, s);
+    return st != KP_OK ? st : fail(ctx, n < 0 ? (kp_status)(-n) : KP_E_DEVICE, "%s", what);
+  }
+  if (n_host) *n_host = n;
+  return KP_OK;
+}
+
+// Per-variable (min, max) of up to four exponent arrays: one launch, the
+// result through the mailbox.  res receives, per array, KP_MAX_VARS mins
+// then KP_MAX_VARS maxes; an empty array gives min 0 and max -1.
+kp_status read_boxes(kp_ctx* ctx, int nseg, const int32_t* const* vals, const int64_t* n,
+                     const int32_t* nv, int32_t* res, hipStream_t s) {
+  std::lock_guard<std::mutex> guard(ctx->mb_mu);
+  BoxArgs A{};
+  A.nseg = nseg;
+  for (int g = 0; g < nseg; ++g) {
+    A.vals[g] = vals[g];
+    A.n[g] = n[g];
+    A.nv[g] = nv[g];
+  }
+  A.acc = ctx->box_dev + BOX_ACC;
+  A.done = reinterpret_cast<unsigned*>(ctx->box_dev + BOX_DONE);
+  A.mb = ctx->mb_dev;
+  A.seq = ++ctx->seq;
+  hipError_t e = launch_boxes(A, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "factor boxes");
+  for (int g = 0; g < nseg; ++g) {
+    kp_status st = wait_seq(ctx, &ctx->mb->box_seq[g], A.seq, s, "factor boxes");
+    if (st != KP_OK) return st;
+  }
+  std::memcpy(res, ctx->mb->box, sizeof(int32_t) * nseg * BOX_SET);
+  return KP_OK;
+}
+
+// Workspace of the from-exponents entry points: the factors' codes, the
+// result's codes, then the multiply's own workspace.
+size_t exps_workspace(int poisson, int64_t na, int64_t nb, int64_t max_out, size_t mul_ws) {
+  const size_t k = poisson ? 2 : 1;
+  return k * align_up(8 * (size_t)na) + k * align_up(8 * (size_t)nb) +
+         align_up(8 * (size_t)std::max<int64_t>(max_out, 1)) + mul_ws;
 }
 
 kp_status finish(kp_ctx* ctx, unsigned flags, hipStream_t s, const char* what) {
@@ -417,9 +521,19 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->status), sizeof(CtxStatus));
   if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(CtxStatus));
   if (e == hipSuccess) e = dense_setup();
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&ctx->box_dev), sizeof(int32_t) * BOX_WORDS);
+  if (e == hipSuccess) e = box_init(ctx->box_dev);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&ctx->mb), sizeof(Mailbox),
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) {
+    std::memset(ctx->mb, 0, sizeof(Mailbox));
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->mb_dev), ctx->mb, 0);
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
-    delete ctx;
+    kp_ctx_destroy(ctx);
     return KP_E_DEVICE;
   }
   *out = ctx;
@@ -495,6 +609,8 @@ kp_status kp_ctx_destroy(kp_ctx* ctx) {
     (void)hipEventDestroy(pr.second);
   }
   if (ctx->status) (void)hipFree(ctx->status);
+  if (ctx->box_dev) (void)hipFree(ctx->box_dev);
+  if (ctx->mb) (void)hipHostFree(ctx->mb);
   delete ctx;
   return KP_OK;
 }
@@ -818,6 +934,189 @@ kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, uns
                                      workspace, workspace_bytes, stream, true);
   if (st != KP_OK) return st;
   return kp::finish(ctx, flags, stream, "kp_mul_poisson");
+}
+
+// ------------------------------------------------------------ from exponents
+kp_status kp_plan_laurent(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,
+                          const int32_t* a_exps, int64_t na, const int32_t* b_exps, int64_t nb,
+                          kp_layout* layout, kp_mode* resolved, int64_t* max_out_terms,
+                          size_t* workspace_bytes, hipStream_t stream) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (nvars < 1 || nvars > KP_MAX_VARS || na < 0 || nb < 0 || (na > 0 && !a_exps) ||
+      (nb > 0 && !b_exps) || !layout || !resolved || !max_out_terms || !workspace_bytes)
+    return fail(ctx, KP_E_ARG, "kp_plan_laurent: bad arguments");
+  const int32_t* vals[2] = {a_exps, b_exps};
+  const int64_t n[2] = {na, nb};
+  const int32_t nv[2] = {nvars, nvars};
+  int32_t r[2 * BOX_SET];
+  kp_status st = read_boxes(ctx, 2, vals, n, nv, r, stream);
+  if (st != KP_OK) return st;
+  st = kp_layout_product(nvars, 0, r, r + KP_MAX_VARS, r + BOX_SET, r + BOX_SET + KP_MAX_VARS,
+                         nullptr, nullptr, layout);
+  if (st != KP_OK) return fail(ctx, st, "kp_plan_laurent: the product's codes overflow");
+  Plan p;
+  st = make_plan(ctx, layout, 0, dtype, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  *resolved = p.mode;
+  *max_out_terms = p.max_out;
+  *workspace_bytes = exps_workspace(0, na, nb, p.max_out, p.ws);
+  return KP_OK;
+}
+
+kp_status kp_mul_laurent_exps(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
+                              unsigned flags, const int32_t* a_exps, const void* a_coef, int64_t na,
+                              const int32_t* b_exps, const void* b_coef, int64_t nb,
+                              int32_t* out_exps, void* out_coef, int64_t out_cap, int64_t* out_n,
+                              int64_t* n_host, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (!layout || layout->ny != 0 || layout->nx < 1)
+    return fail(ctx, KP_E_ARG, "kp_mul_laurent_exps: needs a Laurent layout");
+  if (na < 0 || nb < 0 || out_cap < 0 || !out_n || (na > 0 && (!a_exps || !a_coef)) ||
+      (nb > 0 && (!b_exps || !b_coef)) || (out_cap > 0 && (!out_exps || !out_coef)))
+    return fail(ctx, KP_E_ARG, "kp_mul_laurent_exps: null array or negative size");
+  Plan p;
+  kp_status st = make_plan(ctx, layout, 0, dtype, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  const size_t need = exps_workspace(0, na, nb, p.max_out, p.ws);
+  if (workspace_bytes < need || !workspace)
+    return fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  Carver c;
+  c.base = static_cast<char*>(workspace);
+  int64_t* ka = c.take<int64_t>(na);
+  int64_t* kb = c.take<int64_t>(nb);
+  const int64_t ncodes = std::min<int64_t>(out_cap, std::max<int64_t>(p.max_out, 1));
+  int64_t* oc = c.take<int64_t>(std::max<int64_t>(p.max_out, 1));
+  hipError_t e = hipSuccess;
+  if (layout->nkeys > 0)   // an empty product encodes nothing
+    e = launch_encode2(make_dev_layout(*layout, 0), make_dev_layout(*layout, 1), na, nb, a_exps,
+                       nullptr, nullptr, ka, nullptr, b_exps, nullptr, nullptr, kb, nullptr,
+                       &ctx->status->err, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps encode");
+  st = enqueue_laurent(ctx, layout, dtype, mode, ka, a_coef, na, kb, b_coef, nb, oc, out_coef,
+                       ncodes, out_n, static_cast<char*>(workspace) + c.off,
+                       workspace_bytes - c.off, stream, true);
+  if (st != KP_OK) return st;
+  e = launch_decode_n(make_dev_layout(*layout, 0), 0, out_n, ncodes, oc, out_exps, nullptr,
+                      nullptr, &ctx->status->err, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps decode");
+  if (flags & KP_FLAG_ASYNC) return finish(ctx, flags, stream, "kp_mul_laurent_exps");
+  return wait_count(ctx, out_n, n_host, stream, "kp_mul_laurent_exps");
+}
+
+kp_status kp_mul_laurent_auto(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,
+                              unsigned flags, const int32_t* a_exps, const void* a_coef, int64_t na,
+                              const int32_t* b_exps, const void* b_coef, int64_t nb,
+                              int32_t* out_exps, void* out_coef, int64_t out_cap, int64_t* out_n,
+                              int64_t* n_host, void* workspace, size_t workspace_bytes,
+                              kp_layout* layout, int64_t* need_cap, size_t* need_workspace,
+                              hipStream_t stream) {
+  if (!need_cap || !need_workspace) return kp::fail(ctx, KP_E_ARG, "kp_mul_laurent_auto: null size");
+  kp_mode resolved;
+  int64_t max_out = 0;
+  size_t ws = 0;
+  kp_status st = kp_plan_laurent(ctx, nvars, dtype, mode, a_exps, na, b_exps, nb, layout,
+                                 &resolved, &max_out, &ws, stream);
+  if (st != KP_OK) return st;
+  *need_cap = std::max<int64_t>(max_out, 1);
+  *need_workspace = ws;
+  if (out_cap < *need_cap || workspace_bytes < ws || !workspace) return KP_E_WORKSPACE;
+  return kp_mul_laurent_exps(ctx, layout, dtype, mode, flags, a_exps, a_coef, na, b_exps, b_coef,
+                             nb, out_exps, out_coef, out_cap, out_n, n_host, workspace,
+                             workspace_bytes, stream);
+}
+
+kp_status kp_plan_poisson(kp_ctx* ctx, int32_t nx, int32_t ny, kp_mode mode, const int32_t* a_x,
+                          const int32_t* a_y, int64_t na, const int32_t* b_x, const int32_t* b_y,
+                          int64_t nb, kp_layout* layout, kp_mode* resolved,
+                          int64_t* max_out_terms, size_t* workspace_bytes, hipStream_t stream) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (nx < 0 || nx > KP_MAX_VARS || ny < 1 || ny > KP_MAX_VARS || na < 0 || nb < 0 ||
+      (na > 0 && ((nx > 0 && !a_x) || !a_y)) || (nb > 0 && ((nx > 0 && !b_x) || !b_y)) ||
+      !layout || !resolved || !max_out_terms || !workspace_bytes)
+    return fail(ctx, KP_E_ARG, "kp_plan_poisson: bad arguments");
+  const int32_t* vals[4] = {a_y, b_y, a_x, b_x};
+  const int64_t n[4] = {na, nb, na, nb};
+  const int32_t nv[4] = {ny, ny, nx, nx};
+  int32_t r[4 * BOX_SET];
+  kp_status st = read_boxes(ctx, nx > 0 ? 4 : 2, vals, n, nv, r, stream);
+  if (st != KP_OK) return st;
+  // trigonometric half-widths: the largest |multiplier| per variable
+  int32_t ha[KP_MAX_VARS], hb[KP_MAX_VARS];
+  for (int v = 0; v < ny; ++v) {
+    const int64_t a = std::max<int64_t>({-(int64_t)r[v], r[KP_MAX_VARS + v], 0});
+    const int64_t b = std::max<int64_t>({-(int64_t)r[BOX_SET + v], r[BOX_SET + KP_MAX_VARS + v], 0});
+    if (a > INT32_MAX || b > INT32_MAX)
+      return fail(ctx, KP_E_CODE_OVERFLOW, "kp_plan_poisson: multiplier out of range");
+    ha[v] = (int32_t)a;
+    hb[v] = (int32_t)b;
+  }
+  const int32_t* xa = r + 2 * BOX_SET;
+  const int32_t* xb = r + 3 * BOX_SET;
+  st = kp_layout_product(nx, ny, xa, xa + KP_MAX_VARS, xb, xb + KP_MAX_VARS, ha, hb, layout);
+  if (st != KP_OK) return fail(ctx, st, "kp_plan_poisson: the product's keys overflow");
+  if (na == 0 || nb == 0) layout->nkeys = 0;
+  Plan p;
+  st = make_plan(ctx, layout, 1, KP_F64, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  *resolved = p.mode;
+  *max_out_terms = p.max_out;
+  *workspace_bytes = exps_workspace(1, na, nb, p.max_out, p.ws);
+  return KP_OK;
+}
+
+kp_status kp_mul_poisson_exps(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
+                              const int32_t* a_x, const int32_t* a_y, const uint8_t* a_sin,
+                              const double* a_coef, int64_t na, const int32_t* b_x,
+                              const int32_t* b_y, const uint8_t* b_sin, const double* b_coef,
+                              int64_t nb, int32_t* out_x, int32_t* out_y, uint8_t* out_sin,
+                              double* out_coef, int64_t out_cap, int64_t* out_n, int64_t* n_host,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (!layout || layout->ny < 1)
+    return fail(ctx, KP_E_ARG, "kp_mul_poisson_exps: needs a layout with a trigonometric part");
+  const bool hx = layout->nx > 0;
+  if (na < 0 || nb < 0 || out_cap < 0 || !out_n ||
+      (na > 0 && ((hx && !a_x) || !a_y || !a_sin || !a_coef)) ||
+      (nb > 0 && ((hx && !b_x) || !b_y || !b_sin || !b_coef)) ||
+      (out_cap > 0 && ((hx && !out_x) || !out_y || !out_sin || !out_coef)))
+    return fail(ctx, KP_E_ARG, "kp_mul_poisson_exps: null array or negative size");
+  Plan p;
+  kp_status st = make_plan(ctx, layout, 1, KP_F64, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  const size_t need = exps_workspace(1, na, nb, p.max_out, p.ws);
+  if (workspace_bytes < need || !workspace)
+    return fail(ctx, KP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  Carver c;
+  c.base = static_cast<char*>(workspace);
+  int64_t* kxa = c.take<int64_t>(na);
+  int64_t* kya = c.take<int64_t>(na);
+  int64_t* kxb = c.take<int64_t>(nb);
+  int64_t* kyb = c.take<int64_t>(nb);
+  const int64_t ncodes = std::min<int64_t>(out_cap, std::max<int64_t>(p.max_out, 1));
+  int64_t* ok = c.take<int64_t>(std::max<int64_t>(p.max_out, 1));
+  hipError_t e = hipSuccess;
+  if (layout->nkeys > 0)
+    e = launch_encode2(make_dev_layout(*layout, 0), make_dev_layout(*layout, 1), na, nb, a_x, a_y,
+                       a_sin, kxa, kya, b_x, b_y, b_sin, kxb, kyb, &ctx->status->err, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson_exps encode");
+  st = enqueue_poisson(ctx, layout, mode, kxa, kya, a_sin, a_coef, na, kxb, kyb, b_sin, b_coef,
+                       nb, ok, out_coef, ncodes, out_n, static_cast<char*>(workspace) + c.off,
+                       workspace_bytes - c.off, stream, true);
+  if (st != KP_OK) return st;
+  e = launch_decode_n(make_dev_layout(*layout, 0), 1, out_n, ncodes, ok, out_x, out_y, out_sin,
+                      &ctx->status->err, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson_exps decode");
+  if (flags & KP_FLAG_ASYNC) return finish(ctx, flags, stream, "kp_mul_poisson_exps");
+  return wait_count(ctx, out_n, n_host, stream, "kp_mul_poisson_exps");
 }
 
 // ------------------------------------------------------------ batches

@@ -4,6 +4,7 @@
 // Encode and decode apply the generalised Kronecker map of Section 2
 // (c(e) = c.e - chi with per-variable widths and negative offsets); the
 // per-term arithmetic is in kp_internal.h so the host twins run the same map.
+#include <algorithm>
 #include <climits>
 
 #include "kp_internal.h"
@@ -73,6 +74,204 @@ k_minmax(int64_t n, int32_t nv, const int32_t* __restrict__ vals, int32_t* out) 
   }
 }
 
+// Boxes of several exponent arrays in one launch (blockIdx.y = array).
+// Blocks fold into a persistent accumulator with atomics; the last block to
+// finish (counted on `done`) moves the result to the host mailbox, restores
+// the accumulator and the counter (so the next launch starts clean) and
+// then publishes the sequence number.  An empty array reports min 0 and
+// max -1 per variable.
+// One workgroup per array (arrays of up to BOX_ONE_ROWS rows): no
+// cross-block atomics; each workgroup publishes its own array's box and
+// sequence slot.
+constexpr int BOX_BLOCK = 1024;
+constexpr int64_t BOX_ONE_ROWS = 65536;
+
+__global__ void __launch_bounds__(BOX_BLOCK) k_boxes_one(BoxArgs A) {
+  __shared__ int32_t smin[KP_MAX_VARS][BOX_BLOCK / 64];
+  __shared__ int32_t smax[KP_MAX_VARS][BOX_BLOCK / 64];
+  const int g = blockIdx.x;
+  const int64_t n = A.n[g];
+  const int32_t nv = A.nv[g];
+  const int32_t* __restrict__ vals = A.vals[g];
+  int32_t lo[KP_MAX_VARS], hi[KP_MAX_VARS];
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    lo[v] = INT_MAX;
+    hi[v] = INT_MIN;
+  }
+  // the block's rows as one flat run of n * nv words, BOX_UNROLL loads in
+  // flight per thread; word w belongs to variable w % nv
+  constexpr int BOX_UNROLL = 8;
+  const int64_t words = n * nv;
+  for (int64_t w0 = threadIdx.x; w0 < words; w0 += (int64_t)BOX_BLOCK * BOX_UNROLL) {
+    int32_t x[BOX_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BOX_UNROLL; ++u) {
+      const int64_t w = w0 + (int64_t)u * BOX_BLOCK;
+      x[u] = w < words ? vals[w] : 0;
+    }
+    int v = (int)(w0 % nv);
+    const int step = BOX_BLOCK % nv;
+#pragma unroll
+    for (int u = 0; u < BOX_UNROLL; ++u) {
+      const int64_t w = w0 + (int64_t)u * BOX_BLOCK;
+      if (w < words) {
+#pragma unroll
+        for (int q = 0; q < KP_MAX_VARS; ++q)
+          if (q == v) {
+            lo[q] = min(lo[q], x[u]);
+            hi[q] = max(hi[q], x[u]);
+          }
+      }
+      v += step;
+      if (v >= nv) v -= nv;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    if (v >= nv) break;
+    int32_t a = lo[v], b = hi[v];
+    for (int off = 32; off > 0; off >>= 1) {
+      a = min(a, __shfl_xor(a, off));
+      b = max(b, __shfl_xor(b, off));
+    }
+    if (lane == 0) {
+      smin[v][wave] = a;
+      smax[v][wave] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * KP_MAX_VARS) {
+    const int v = threadIdx.x % KP_MAX_VARS;
+    const bool is_max = threadIdx.x >= KP_MAX_VARS;
+    int32_t r = is_max ? INT_MIN : INT_MAX;
+    if (v < nv)
+      for (int w = 0; w < BOX_BLOCK / 64; ++w) r = is_max ? max(r, smax[v][w]) : min(r, smin[v][w]);
+    A.mb->box[g * 2 * KP_MAX_VARS + threadIdx.x] = n == 0 ? (is_max ? -1 : 0) : r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(&A.mb->box_seq[g], A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+__global__ void __launch_bounds__(CODEC_BLOCK) k_boxes(BoxArgs A) {
+  __shared__ int32_t smin[KP_MAX_VARS][CODEC_BLOCK / 64];
+  __shared__ int32_t smax[KP_MAX_VARS][CODEC_BLOCK / 64];
+  __shared__ int s_last;
+  const int g = blockIdx.y;
+  const int64_t n = A.n[g];
+  const int32_t nv = A.nv[g];
+  const int32_t* __restrict__ vals = A.vals[g];
+  int32_t lo[KP_MAX_VARS], hi[KP_MAX_VARS];
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    lo[v] = INT_MAX;
+    hi[v] = INT_MIN;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int v = 0; v < KP_MAX_VARS; ++v) {
+      if (v < nv) {
+        const int32_t x = vals[i * nv + v];
+        lo[v] = min(lo[v], x);
+        hi[v] = max(hi[v], x);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < KP_MAX_VARS; ++v) {
+    if (v >= nv) break;
+    int32_t a = lo[v], b = hi[v];
+    for (int off = 32; off > 0; off >>= 1) {
+      a = min(a, __shfl_xor(a, off));
+      b = max(b, __shfl_xor(b, off));
+    }
+    if (lane == 0) {
+      smin[v][wave] = a;
+      smax[v][wave] = b;
+    }
+  }
+  __syncthreads();
+  int32_t* acc = A.acc + g * 2 * KP_MAX_VARS;
+  if (threadIdx.x < nv) {
+    const int v = threadIdx.x;
+    int32_t a = INT_MAX, b = INT_MIN;
+    for (int w = 0; w < CODEC_BLOCK / 64; ++w) {
+      a = min(a, smin[v][w]);
+      b = max(b, smax[v][w]);
+    }
+    if (a != INT_MAX) atomicMin(&acc[v], a);
+    if (b != INT_MIN) atomicMax(&acc[KP_MAX_VARS + v], b);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = atomicAdd(A.done, 1u) == gridDim.x * gridDim.y - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int total = A.nseg * 2 * KP_MAX_VARS;
+  for (int k = threadIdx.x; k < total; k += blockDim.x) {
+    const int seg = k / (2 * KP_MAX_VARS), r = k % (2 * KP_MAX_VARS);
+    const bool is_max = r >= KP_MAX_VARS;
+    const int32_t val = atomicExch(&A.acc[k], is_max ? INT_MIN : INT_MAX);
+    A.mb->box[k] = A.n[seg] == 0 ? (is_max ? -1 : 0) : val;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicExch(A.done, 0u);
+    __threadfence_system();
+    for (int k = 0; k < A.nseg; ++k)
+      __hip_atomic_store(&A.mb->box_seq[k], A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+__global__ void k_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
+                             uint64_t seq) {
+  if (threadIdx.x != 0) return;
+  mb->n = *out_n;
+  mb->err = *ctx_err;
+  __threadfence_system();
+  __hip_atomic_store(&mb->n_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ uint32_t encode_row(const DevLayout& L, int64_t r,
+                                               const int32_t* __restrict__ x,
+                                               const int32_t* __restrict__ y,
+                                               const uint8_t* __restrict__ t,
+                                               int64_t* __restrict__ kx, int64_t* __restrict__ ky) {
+  int32_t ex[KP_MAX_VARS], jy[KP_MAX_VARS];
+  for (int v = 0; v < L.nx; ++v) ex[v] = x[r * L.nx + v];
+  for (int v = 0; v < L.ny; ++v) jy[v] = y[r * L.ny + v];
+  int64_t a = 0, b = 0;
+  const uint32_t e = encode_term(L, ex, jy, L.ny > 0 ? t[r] : 0, &a, &b);
+  kx[r] = a;
+  if (L.ny > 0) ky[r] = b;
+  return e;
+}
+
+// Both factors in one launch: rows [0, na) of A, then [na, na + nb) of B.
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_encode2(DevLayout LA, DevLayout LB, int64_t na, int64_t nb, const int32_t* __restrict__ ax,
+          const int32_t* __restrict__ ay, const uint8_t* __restrict__ at,
+          int64_t* __restrict__ akx, int64_t* __restrict__ aky, const int32_t* __restrict__ bx,
+          const int32_t* __restrict__ by, const uint8_t* __restrict__ bt,
+          int64_t* __restrict__ bkx, int64_t* __restrict__ bky, uint32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t e = 0;
+  if (i < na)
+    e = encode_row(LA, i, ax, ay, at, akx, aky);
+  else if (i < na + nb)
+    e = encode_row(LB, i - na, bx, by, bt, bkx, bky);
+  uint32_t any = wave_or(e);
+  if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
+}
+
 __global__ void __launch_bounds__(CODEC_BLOCK)
 k_encode(DevLayout L, int64_t n, const int32_t* __restrict__ x, const int32_t* __restrict__ y,
          const uint8_t* __restrict__ t, int64_t* __restrict__ kx, int64_t* __restrict__ ky,
@@ -93,33 +292,55 @@ k_encode(DevLayout L, int64_t n, const int32_t* __restrict__ x, const int32_t* _
   if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
 }
 
+__device__ __forceinline__ uint32_t decode_one(const DevLayout& L, int poisson, int64_t i,
+                                               const int64_t* __restrict__ codes,
+                                               int32_t* __restrict__ x, int32_t* __restrict__ y,
+                                               uint8_t* __restrict__ t) {
+  uint32_t e = 0;
+  int64_t c = codes[i];
+  int32_t ex[KP_MAX_VARS], jy[KP_MAX_VARS];
+  if (c < 0 || c >= L.nkeys) {
+    e = ERR_RANGE;
+    c = 0;
+  }
+  uint64_t q = (uint64_t)c;
+  if (poisson) {
+    t[i] = (uint8_t)(q & 1);
+    q >>= 1;
+    uint64_t u = fdiv(q, L.dWx);
+    uint64_t kx = q - u * (uint64_t)L.Wx;
+    decode_x(L, kx, ex);
+    decode_y(L, u, jy);
+    for (int v = 0; v < L.ny; ++v) y[i * L.ny + v] = jy[v];
+  } else {
+    decode_x(L, q, ex);
+  }
+  for (int v = 0; v < L.nx; ++v) x[i * L.nx + v] = ex[v];
+  return e;
+}
+
 __global__ void __launch_bounds__(CODEC_BLOCK)
 k_decode(DevLayout L, int poisson, int64_t n, const int64_t* __restrict__ codes,
          int32_t* __restrict__ x, int32_t* __restrict__ y, uint8_t* __restrict__ t,
          uint32_t* err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t e = 0;
-  if (i < n) {
-    int64_t c = codes[i];
-    int32_t ex[KP_MAX_VARS], jy[KP_MAX_VARS];
-    if (c < 0 || c >= L.nkeys) {
-      e = ERR_RANGE;
-      c = 0;
-    }
-    uint64_t q = (uint64_t)c;
-    if (poisson) {
-      t[i] = (uint8_t)(q & 1);
-      q >>= 1;
-      uint64_t u = fdiv(q, L.dWx);
-      uint64_t kx = q - u * (uint64_t)L.Wx;
-      decode_x(L, kx, ex);
-      decode_y(L, u, jy);
-      for (int v = 0; v < L.ny; ++v) y[i * L.ny + v] = jy[v];
-    } else {
-      decode_x(L, q, ex);
-    }
-    for (int v = 0; v < L.nx; ++v) x[i * L.nx + v] = ex[v];
-  }
+  if (i < n) e = decode_one(L, poisson, i, codes, x, y, t);
+  uint32_t any = wave_or(e);
+  if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
+}
+
+// Decode of a result whose size is on the device (a multiply's count, or a
+// negative status, in which case nothing is decoded); at most `cap` terms.
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_decode_n(DevLayout L, int poisson, const int64_t* __restrict__ n_dev, int64_t cap,
+           const int64_t* __restrict__ codes, int32_t* __restrict__ x, int32_t* __restrict__ y,
+           uint8_t* __restrict__ t, uint32_t* err) {
+  const int64_t n = min(*n_dev, cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t e = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    e |= decode_one(L, poisson, i, codes, x, y, t);
   uint32_t any = wave_or(e);
   if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
 }
@@ -189,11 +410,48 @@ hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* ou
   return hipGetLastError();
 }
 
+hipError_t launch_boxes(const BoxArgs& A, hipStream_t s) {
+  int64_t n = 0;
+  for (int g = 0; g < A.nseg; ++g) n = std::max(n, A.n[g]);
+  if (n <= BOX_ONE_ROWS) {
+    hipLaunchKernelGGL(k_boxes_one, dim3(A.nseg), dim3(BOX_BLOCK), 0, s, A);
+  } else {
+    const int gx = grid_for(n, CODEC_BLOCK * 8, 512);   // about 8 rows per thread
+    hipLaunchKernelGGL(k_boxes, dim3(gx, A.nseg), dim3(CODEC_BLOCK), 0, s, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
+                             uint64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_post_count, dim3(1), dim3(64), 0, s, out_n, ctx_err, mb, seq);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_n(const DevLayout& L, int poisson, const int64_t* n_dev, int64_t cap,
+                           const int64_t* codes, int32_t* x, int32_t* y, uint8_t* t, uint32_t* err,
+                           hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode_n, dim3(grid_for(cap, CODEC_BLOCK, 4096)), dim3(CODEC_BLOCK), 0, s,
+                     L, poisson, n_dev, cap, codes, x, y, t, err);
+  return hipGetLastError();
+}
+
 hipError_t launch_encode(const DevLayout& L, int64_t n, const int32_t* x, const int32_t* y,
                          const uint8_t* t, int64_t* kx, int64_t* ky, uint32_t* err, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_encode, dim3(grid_for(n, CODEC_BLOCK, INT_MAX)), dim3(CODEC_BLOCK), 0, s, L,
                      n, x, y, t, kx, ky, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode2(const DevLayout& LA, const DevLayout& LB, int64_t na, int64_t nb,
+                          const int32_t* ax, const int32_t* ay, const uint8_t* at, int64_t* akx,
+                          int64_t* aky, const int32_t* bx, const int32_t* by, const uint8_t* bt,
+                          int64_t* bkx, int64_t* bky, uint32_t* err, hipStream_t s) {
+  if (na + nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encode2, dim3(grid_for(na + nb, CODEC_BLOCK, INT_MAX)), dim3(CODEC_BLOCK),
+                     0, s, LA, LB, na, nb, ax, ay, at, akx, aky, bx, by, bt, bkx, bky, err);
   return hipGetLastError();
 }
 

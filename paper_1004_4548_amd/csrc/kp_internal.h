@@ -168,6 +168,42 @@ static_assert(sizeof(CtxStatus) == 256, "status block is 256 bytes");
 // ------------------------------------------------------------ launchers
 // codec
 hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* out, hipStream_t s);
+
+// Boxes of up to four exponent arrays in one launch; acc (nseg x 2 x
+// KP_MAX_VARS, mins then maxes) and done persist between launches and must
+// hold INT_MAX / INT_MIN and 0 before the first one.
+// Host-coherent pinned block through which kernels hand small results to a
+// host thread that spins on a sequence number (no stream synchronisation).
+struct Mailbox {
+  int32_t box[4 * 2 * KP_MAX_VARS];   // factor boxes: per array mins, then maxes
+  int64_t n;                          // a multiply's result count (or -status)
+  uint32_t err;                       // the context's latched status bits
+  uint32_t pad;
+  uint64_t n_seq;                     // written after n and err
+  uint64_t box_seq[4];                // per array, written after its box
+};
+
+struct BoxArgs {
+  const int32_t* vals[4];
+  int64_t n[4];
+  int32_t nv[4];
+  int nseg;
+  int32_t* acc;
+  unsigned* done;
+  Mailbox* mb;     // device address of the mailbox
+  uint64_t seq;
+};
+hipError_t launch_boxes(const BoxArgs& A, hipStream_t s);
+// Posts *out_n and *ctx_err to the mailbox, then seq to n_seq.
+hipError_t launch_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
+                             uint64_t seq, hipStream_t s);
+hipError_t launch_encode2(const DevLayout& LA, const DevLayout& LB, int64_t na, int64_t nb,
+                          const int32_t* ax, const int32_t* ay, const uint8_t* at, int64_t* akx,
+                          int64_t* aky, const int32_t* bx, const int32_t* by, const uint8_t* bt,
+                          int64_t* bkx, int64_t* bky, uint32_t* err, hipStream_t s);
+hipError_t launch_decode_n(const DevLayout& L, int poisson, const int64_t* n_dev, int64_t cap,
+                           const int64_t* codes, int32_t* x, int32_t* y, uint8_t* t, uint32_t* err,
+                           hipStream_t s);
 hipError_t launch_encode(const DevLayout& L, int64_t n, const int32_t* x, const int32_t* y,
                          const uint8_t* t, int64_t* kx, int64_t* ky, uint32_t* err, hipStream_t s);
 hipError_t launch_decode(const DevLayout& L, int poisson, int64_t n, const int64_t* codes,

@@ -1,0 +1,185 @@
+"""GPU: the from-exponents entry points (kp_plan_* + kp_mul_*_exps).
+
+The plan's fused box kernel must give the same layout as per-factor min/max
+passes; products through the two-call path must equal the oracle; a result
+larger than the given capacity reports KP_E_CAPACITY and decodes nothing;
+the box accumulator restores itself between launches."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1004_4548_amd as kp
+from paper_1004_4548_amd import inputs as I
+from tests.helpers import assert_exact, assert_tolerance
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-13
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _fields(lay):
+    return {f: (list(getattr(lay, f)) if hasattr(getattr(lay, f), "__len__") else getattr(lay, f))
+            for f, _ in Layout_fields}
+
+
+Layout_fields = kp.Layout._fields_
+
+
+def _cases():
+    out = [("box", *I.config(1, scale=0.3)), ("simplex", *I.config(2, scale=0.05)),
+           ("sparse", *I.config(3, scale=0.02))]
+    a, b = I.config(1, scale=0.2)
+    # shifted to negative exponents, and a single-term factor
+    out.append(("negative", (a[0] - 7, a[1]), (b[0][:1] - 30, b[1][:1])))
+    out.append(("empty A", (a[0][:0], a[1][:0]), b))
+    return out
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_plan_layout_equals_per_factor_boxes(k):
+    what, a, b = _cases()[k]
+    say("plan", what, len(a[1]), "x", len(b[1]))
+    ctx = kp.context()
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    lay, mode, max_out, ws = kp.plan_laurent(pa, pb, ctx=ctx)
+    ref = kp.laurent_layout(pa, pb, ctx)
+    assert _fields(lay) == _fields(ref)
+    m2, mo2, ws2 = kp.mul_bound(ref, False, kp._dt(pa.coef), "auto", len(a[1]), len(b[1]), ctx)
+    assert (mode, max_out) == (m2, mo2) and ws >= ws2
+    if len(a[1]):
+        e = np.asarray(a[0])
+        assert list(lay.amin)[:e.shape[1]] == e.min(0).tolist()
+        assert list(lay.amax)[:e.shape[1]] == e.max(0).tolist()
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_two_call_product_matches_oracle(k):
+    what, a, b = _cases()[k]
+    say("two-call product", what, len(a[1]), "x", len(b[1]))
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    r, _ = kp.mul_laurent(pa, pb)
+    oe, oc, _ = O.laurent_mul(a[0], a[1], b[0], b[1], threads=4)
+    if len(oc) == 0:
+        assert r.coef.shape[0] == 0 and r.exps.shape == (0, pa.nv)
+        return
+    assert_exact([r.exps.cpu().numpy()], r.coef.cpu().numpy(), [oe], oc, what)
+
+
+def test_two_call_capacity_error_decodes_nothing():
+    import torch
+    ctx = kp.context()
+    a, b = I.config(1, scale=0.2)
+    say("capacity", len(a[1]), "x", len(b[1]))
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    lay, _, max_out, ws = kp.plan_laurent(pa, pb, ctx=ctx)
+    cap = 5
+    ox = torch.full((cap, pa.nv), -77, dtype=torch.int32, device="cuda")
+    oc = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    on = torch.empty(1, dtype=torch.int64, device="cuda")
+    wbuf = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    st = kp.lib().kp_mul_laurent_exps(
+        ctx.h, C.byref(lay), kp.KP_I64, kp.KP_AUTO, kp.KP_FLAG_ASYNC, kp._ptr(pa.exps),
+        kp._ptr(pa.coef), len(a[1]), kp._ptr(pb.exps), kp._ptr(pb.coef), len(b[1]), kp._ptr(ox),
+        kp._ptr(oc), cap, kp._ptr(on), None, kp._ptr(wbuf), ws, kp._stream())
+    assert st == kp.KP_OK
+    assert int(on.item()) == -kp.KP_E_CAPACITY
+    assert bool((ox == -77).all())
+    with pytest.raises(kp.KPError):   # the latched status, read and cleared
+        ctx.sync_check()
+    # the context is clean again: a product with room succeeds
+    r, _ = kp.mul_laurent(pa, pb, ctx=ctx)
+    assert r.coef.shape[0] > cap
+    # a workspace one byte short is refused before anything is queued
+    st = kp.lib().kp_mul_laurent_exps(
+        ctx.h, C.byref(lay), kp.KP_I64, kp.KP_AUTO, kp.KP_FLAG_ASYNC, kp._ptr(pa.exps),
+        kp._ptr(pa.coef), len(a[1]), kp._ptr(pb.exps), kp._ptr(pb.coef), len(b[1]), kp._ptr(ox),
+        kp._ptr(oc), cap, kp._ptr(on), None, kp._ptr(wbuf), ws - 1, kp._stream())
+    assert st == kp.KP_E_WORKSPACE
+    # blocking form: the capacity error comes back as the call's status and is cleared
+    n = C.c_int64(-1)
+    st = kp.lib().kp_mul_laurent_exps(
+        ctx.h, C.byref(lay), kp.KP_I64, kp.KP_AUTO, 0, kp._ptr(pa.exps), kp._ptr(pa.coef),
+        len(a[1]), kp._ptr(pb.exps), kp._ptr(pb.coef), len(b[1]), kp._ptr(ox), kp._ptr(oc), cap,
+        kp._ptr(on), C.byref(n), kp._ptr(wbuf), ws, kp._stream())
+    assert st == kp.KP_E_CAPACITY and n.value == -1
+    ctx.sync_check()   # nothing left latched
+
+
+def test_box_accumulator_restores_between_launches():
+    ctx = kp.context()
+    rng = np.random.default_rng(10044548)
+    for r in range(6):
+        nv = int(rng.integers(1, 7))
+        na, nb = int(rng.integers(1, 3000)), int(rng.integers(1, 3000))
+        lo, hi = int(rng.integers(-500, 0)), int(rng.integers(1, 500))
+        ea = rng.integers(lo, hi, size=(na, nv)).astype(np.int32)
+        eb = rng.integers(lo // 2, hi // 2 + 1, size=(nb, nv)).astype(np.int32)
+        say("boxes", r, nv, na, nb)
+        pa = kp.Poly(dev(ea), dev(np.ones(na, np.int64)))
+        pb = kp.Poly(dev(eb), dev(np.ones(nb, np.int64)))
+        lay, *_ = kp.plan_laurent(pa, pb, ctx=ctx)
+        assert list(lay.amin)[:nv] == ea.min(0).tolist()
+        assert list(lay.amax)[:nv] == ea.max(0).tolist()
+        assert list(lay.bmin)[:nv] == eb.min(0).tolist()
+        assert list(lay.bmax)[:nv] == eb.max(0).tolist()
+
+
+def test_two_call_poisson_matches_oracle_and_layout():
+    ctx = kp.context()
+    a, b = I.config(4, scale=0.04)
+    say("two-call poisson", len(a[3]), "x", len(b[3]))
+    sa = kp.PoissonSeries(dev(a[0]), dev(a[1]), dev(a[2]), dev(a[3]))
+    sb = kp.PoissonSeries(dev(b[0]), dev(b[1]), dev(b[2]), dev(b[3]))
+    lay, mode, max_out, ws = kp.plan_poisson(sa, sb, ctx=ctx)
+    assert _fields(lay) == _fields(kp.poisson_layout(sa, sb, ctx))
+    r, _ = kp.mul_poisson(sa, sb, ctx=ctx)
+    nx, ny = a[0].shape[1], a[1].shape[1]
+    ox, oy, ot, oc, oab = O.poisson_mul(a, b, nx, ny, threads=4)
+    gk = [r.x.cpu().numpy(), r.y.cpu().numpy(), r.is_sin.cpu().numpy()[:, None]]
+    assert_tolerance(gk, r.coef.cpu().numpy(), [ox, oy, ot[:, None]], oc, oab, TOL, "poisson")
+
+
+def test_two_call_poisson_without_x_variables():
+    """A pure trigonometric series (nx = 0): x arrays are empty."""
+    rng = np.random.default_rng(7)
+    ny = 3
+
+    def series(n):
+        y = rng.integers(-4, 5, size=(n, ny)).astype(np.int32)
+        # canonical: first nonzero multiplier positive, no sine of the zero vector
+        for i in range(n):
+            nz = np.flatnonzero(y[i])
+            if len(nz) and y[i, nz[0]] < 0:
+                y[i] = -y[i]
+        t = rng.integers(0, 2, size=n).astype(np.uint8)
+        t[~y.any(1)] = 0
+        keys = {}
+        for i in range(n):
+            keys[(tuple(y[i]), int(t[i]))] = i
+        idx = sorted(keys.values())
+        y, t = y[idx], t[idx]
+        c = rng.standard_normal(len(idx))
+        return np.zeros((len(idx), 0), np.int32), y, t, c
+
+    a, b = series(200), series(150)
+    say("poisson nx=0", len(a[3]), "x", len(b[3]))
+    sa = kp.PoissonSeries(dev(a[0]), dev(a[1]), dev(a[2]), dev(a[3]))
+    sb = kp.PoissonSeries(dev(b[0]), dev(b[1]), dev(b[2]), dev(b[3]))
+    r, lay = kp.mul_poisson(sa, sb)
+    assert lay.nx == 0
+    # the oracle takes at least one x variable: x^0 on every term is the same series
+    pad = lambda s: (np.zeros((len(s[3]), 1), np.int32),) + tuple(s[1:])
+    ox, oy, ot, oc, oab = O.poisson_mul(pad(a), pad(b), 1, ny, threads=2)
+    assert not ox.any()
+    gk = [r.y.cpu().numpy(), r.is_sin.cpu().numpy()[:, None]]
+    assert_tolerance(gk, r.coef.cpu().numpy(), [oy, ot[:, None]], oc, oab, TOL, "poisson nx=0")
