@@ -167,6 +167,22 @@ def test_laurent_coefficient_widths(mode):
         check_laurent(a, b, mode, f"coefficients in [{lo},{hi}]")
 
 
+def test_dense_narrow_kind_largest_products():
+    """The narrowest coefficient kind (both factors in [0, 2^16), one 24-bit
+    multiply per pair) at its largest products, just below 2^32, whose sums
+    pass 2^32 many times over: in whole windows and in windows split across
+    tasks."""
+    ctx = kp.context()
+    (ea, _), (eb, _) = I.config(1, scale=0.6)
+    rng = np.random.default_rng(65535)
+    cases = [("all 65535", np.full(len(ea), 65535, np.int64), np.full(len(eb), 65535, np.int64)),
+             ("random [0, 65535]", rng.integers(0, 65536, len(ea)), rng.integers(0, 65536, len(eb)))]
+    for window, block, tpc in ((18432, 1024, 1), (2048, 256, 64)):
+        ctx.set_tune(window=window, block=block, tasks_per_cu=tpc)
+        for what, ca, cb in cases:
+            check_laurent((ea, ca), (eb, cb), "dense", f"{what}, window {window} tasks/CU {tpc}")
+
+
 @pytest.mark.parametrize("na,nb", [(1, 1), (1, 700), (63, 65), (4095, 4097), (8193, 130)])
 def test_laurent_ragged_sizes(na, nb):
     rng = np.random.default_rng(na * 7 + nb)
