@@ -121,7 +121,12 @@ typedef struct kp_tune {
   int64_t hash_capacity;    /* hash: forced slot count (0 = from the bound)          */
   int64_t dense_max_keys;   /* dense only if nkeys <= this (at most 2^27)            */
   double dense_keys_per_pair; /* auto mode: dense only if nkeys <= this * na * nb    */
-  int32_t hash_rows;        /* hash: factor-A rows per thread                        */
+  int32_t hash_rows;        /* hash: factor-A rows per thread (global table)         */
+  int32_t hash_partitioned; /* hash: 2 = products grouped by hash bits in two levels
+                               through HBM, each group accumulated in an LDS table
+                               (workspace 32 bytes per product); 0 = one open-addressing
+                               table in HBM; 1 (default) = grouped when the products are
+                               at most 4 times the result bound, else the table          */
 } kp_tune;
 
 typedef struct kp_ctx kp_ctx;

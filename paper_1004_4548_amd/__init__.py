@@ -66,7 +66,7 @@ class Tune(C.Structure):
     _fields_ = [("window", C.c_int32), ("block", C.c_int32), ("tasks_per_cu", C.c_int32),
                 ("hash_load", C.c_double), ("hash_capacity", C.c_int64),
                 ("dense_max_keys", C.c_int64), ("dense_keys_per_pair", C.c_double),
-                ("hash_rows", C.c_int32)]
+                ("hash_rows", C.c_int32), ("hash_partitioned", C.c_int32)]
 
 
 class MulDesc(C.Structure):

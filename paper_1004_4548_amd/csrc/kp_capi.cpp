@@ -221,6 +221,11 @@ struct Plan {
   DensePlan dp{};
   // hash
   int64_t cap = 64;
+  // partitioned hash: rows of A per workgroup, log2 partitions and bins,
+  // count/scatter workgroups, products bound
+  bool radix = false;
+  int rows = 0, l1 = 1, l2 = 0;
+  int64_t nblocks = 0, nprod = 0;
 };
 
 int64_t factor_maxcode(const kp_layout* L, int which) {
@@ -351,11 +356,45 @@ struct HashCarve {
   Meta* meta;
   uint64_t* table;
   PoissonPrep pp;
+  uint32_t* counts;
+  int64_t* pstart;
+  int64_t* bstart;
+  uint4* ent1;
+  uint4* ent2;
 };
+
+// Shape of the partitioned accumulation: about 1024 products per bin (a
+// quarter of the LDS table), at most 2^10 partitions and 2^10 bins each;
+// about 4096 count/scatter workgroups.
+void radix_shape(int64_t na, int64_t nb, int64_t nprod, Plan* p) {
+  int bits = 1;
+  while (bits < 20 && ((int64_t)1024 << bits) < nprod) ++bits;
+  p->l2 = std::min(10, bits / 2);
+  p->l1 = std::max(1, bits - p->l2);
+  const int64_t bx = std::max<int64_t>(1, (nb + 255) / 256);
+  int64_t rows = (na * bx + 4095) / 4096;
+  rows = std::max<int64_t>(rows, (na + 65534) / 65535);   // grid.y limit
+  p->rows = (int)std::max<int64_t>(1, std::min<int64_t>(rows, (int64_t)1 << 30));
+  p->nblocks = bx * std::max<int64_t>(1, (na + p->rows - 1) / p->rows);
+  p->nprod = std::max<int64_t>(nprod, 1);
+}
 
 void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, HashCarve* h) {
   h->meta = c.take<Meta>(1);
-  h->table = c.take<uint64_t>((size_t)2 * p.cap);
+  h->table = nullptr;
+  h->counts = nullptr;
+  h->pstart = h->bstart = nullptr;
+  h->ent1 = h->ent2 = nullptr;
+  if (p.radix) {
+    const int64_t P1 = (int64_t)1 << p.l1, bins = P1 << p.l2;
+    h->counts = c.take<uint32_t>((size_t)(P1 * p.nblocks));
+    h->pstart = c.take<int64_t>((size_t)P1 + 1);
+    h->bstart = c.take<int64_t>((size_t)bins + 1);
+    h->ent1 = c.take<uint4>((size_t)p.nprod);
+    h->ent2 = c.take<uint4>((size_t)p.nprod);
+  } else {
+    h->table = c.take<uint64_t>((size_t)2 * p.cap);
+  }
   h->pp = PoissonPrep{};
   if (poisson) {
     h->pp.ap = c.take<int64_t>(na);
@@ -435,6 +474,18 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     p->cap = std::max<int64_t>(64, want);
     if (p->cap > ((int64_t)1 << 40))
       return fail(ctx, KP_E_CAPACITY, "hash table would need %lld slots", (long long)p->cap);
+    // partitioned when asked for, or (auto) when the products are not many
+    // more than the result bound: its workspace is 32 bytes per product
+    // against 32 per result slot pair of the global table
+    p->radix = ctx->tune.hash_partitioned == 2 ||
+               (ctx->tune.hash_partitioned == 1 &&
+                (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1));
+    if (p->radix) {
+      if (contrib > ((int64_t)1 << 36))
+        return fail(ctx, KP_E_CAPACITY, "%lld products exceed the partitioned table",
+                    (long long)contrib);
+      radix_shape(na, nb, contrib, p);
+    }
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
   }
@@ -505,6 +556,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.dense_max_keys = (int64_t)1 << 27;
   ctx->tune.dense_keys_per_pair = 64.0;
   ctx->tune.hash_rows = 64;
+  ctx->tune.hash_partitioned = 1;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
     *out = ctx;
     return KP_OK;
@@ -633,6 +685,8 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "hash_load must lie in [0.05, 0.9]");
   if (t->dense_max_keys > DENSE_MAX_CODES)
     return fail(ctx, KP_E_ARG, "dense_max_keys must be at most %lld", (long long)DENSE_MAX_CODES);
+  if (t->hash_partitioned < 0 || t->hash_partitioned > 2)
+    return fail(ctx, KP_E_ARG, "hash_partitioned must be 0, 1 or 2");
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");
@@ -812,7 +866,15 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
                nullptr, nullptr, hash_stats_ptr(ctx)};
     if (!empty && timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
-    if (!empty) {
+    if (!empty && p.radix) {
+      if (e == hipSuccess && dtype == KP_I64)
+        e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
+                              stream);
+      RadixArgs R{a_codes, a_coef, na, b_codes, b_coef, nb, 0, PoissonPrep{}, p.rows, p.l1,
+                  p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_codes,
+                  out_coef, out_cap, H.stats, H.ev0, H.ev1};
+      if (e == hipSuccess) e = launch_radix(R, dtype == KP_F64 ? 1 : 0, stream);
+    } else if (!empty) {
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
                               stream);
@@ -881,7 +943,15 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
   HashBufs H{h.meta, h.table, p.cap, p.cap, out_keys, out_coef, out_cap,
              nullptr, nullptr, hash_stats_ptr(ctx)};
   hipError_t e = launch_meta_init(h.meta, stream);
-  if (na > 0 && nb > 0 && layout->nkeys > 0) {
+  if (na > 0 && nb > 0 && layout->nkeys > 0 && p.radix) {
+    if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    if (e == hipSuccess)
+      e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream);
+    RadixArgs R{nullptr, a_coef, na, nullptr, b_coef, nb, layout->Wx, h.pp, p.rows, p.l1,
+                p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_keys,
+                out_coef, out_cap, H.stats, H.ev0, H.ev1};
+    if (e == hipSuccess) e = launch_radix(R, 2, stream);
+  } else if (na > 0 && nb > 0 && layout->nkeys > 0) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * p.cap, stream);
     if (e == hipSuccess)

@@ -84,7 +84,7 @@ k_minmax(int64_t n, int32_t nv, const int32_t* __restrict__ vals, int32_t* out) 
 // cross-block atomics; each workgroup publishes its own array's box and
 // sequence slot.
 constexpr int BOX_BLOCK = 1024;
-constexpr int64_t BOX_ONE_ROWS = 65536;
+constexpr int64_t BOX_ONE_ROWS = 8192;
 
 __global__ void __launch_bounds__(BOX_BLOCK) k_boxes_one(BoxArgs A) {
   __shared__ int32_t smin[KP_MAX_VARS][BOX_BLOCK / 64];

@@ -23,6 +23,7 @@
 // = 2 kx - K with the sign of a sine flipped.  A sine with ky = 0
 // (0 <= K < Wx) is dropped.
 #include <climits>
+#include <type_traits>
 
 #include "kp_internal.h"
 
@@ -312,6 +313,291 @@ k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
   }
 }
 
+
+// ------------------------------------------------------------ partitioned accumulation
+// The same insert-or-accumulate with the table kept on chip.  Every nonzero
+// product {code, value} is written once to HBM, grouped by the top bits of
+// its multiplicative hash (level 1, with exact offsets from per-workgroup
+// histograms, so the scatter needs no global atomics), then regrouped inside
+// each level-1 partition by the next bits (level 2).  A level-2 bin holds
+// about BIN_TARGET products, all of any one code; one workgroup accumulates
+// a bin in an LDS open-addressing table and writes its nonzero terms.  HBM
+// sees sequential runs instead of one random line per insertion.
+constexpr int RADIX_BLOCK = 256;     // count and scatter: threads over terms of B
+constexpr int RADIX_MAX_L = 10;      // at most 1024 partitions per level
+constexpr int SPLIT_BLOCK = 1024;
+constexpr int BIN_BLOCK = 256;
+constexpr int BIN_SLOTS = 4096;      // LDS table of one bin: 4096 x (8 + 8) bytes
+
+__device__ __forceinline__ uint64_t code_hash(int64_t code) { return (uint64_t)code * GOLDEN; }
+__device__ __forceinline__ uint32_t part1(uint64_t h, int l1) { return (uint32_t)(h >> (64 - l1)); }
+__device__ __forceinline__ uint32_t part2(uint64_t h, int l1, int l2) {
+  return (uint32_t)(h >> (64 - l1 - l2)) & ((1u << l2) - 1);
+}
+__device__ __forceinline__ uint32_t bin_slot(uint64_t h, int l1, int l2) {
+  return (uint32_t)(h >> (64 - l1 - l2 - 12)) & (BIN_SLOTS - 1);
+}
+
+// Every nonzero product of this thread: its term j of B against rows
+// [i0, i1) of A.  KIND 0: Laurent int64, 1: Laurent fp64, 2: Poisson (two
+// pieces per pair).  f(code, value bits).
+template <int KIND, typename F>
+__device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow, F&& f) {
+  const int64_t j = (int64_t)blockIdx.x * RADIX_BLOCK + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * R.rows;
+  const int64_t i1 = min(i0 + R.rows, R.na);
+  if (j >= R.nb) return;
+  if constexpr (KIND == 2) {
+    const double* ac = static_cast<const double*>(R.ac);
+    const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
+    const int tb = R.P.bt[j];
+    const double cb = static_cast<const double*>(R.bc)[j];
+    for (int64_t i = i0; i < i1; ++i) {
+      const int ta = R.P.at[i];
+      const double h = 0.5 * (ac[i] * cb);
+      if (h == 0.0) continue;
+      const int64_t kx = R.P.akx[i] + kxb;
+      const int t = ta ^ tb;
+      const double sm = (!ta && tb) ? -h : h;   // cos a sin b: -1/2 sin(a - b)
+      const double sp = (ta && tb) ? -h : h;    // sin a sin b: -1/2 cos(a + b)
+      int64_t key;
+      double v;
+      if (poisson_piece(R.Wx, R.P.ap[i] + Bm, kx, t, sm, &key, &v)) f(key, __double_as_longlong(v));
+      if (poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &key, &v)) f(key, __double_as_longlong(v));
+    }
+  } else {
+    using T = typename std::conditional<KIND == 0, int64_t, double>::type;
+    const T* ac = static_cast<const T*>(R.ac);
+    const int64_t bj = R.bk[j];
+    const T cb = static_cast<const T*>(R.bc)[j];
+    for (int64_t i = i0; i < i1; ++i) {
+      const T v = mul_coef<T>(ac[i], cb, narrow);
+      if (v == T(0)) continue;
+      int64_t bits;
+      __builtin_memcpy(&bits, &v, 8);
+      f(R.ak[i] + bj, bits);
+    }
+  }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(RADIX_BLOCK) k_radix_count(RadixArgs R) {
+  __shared__ uint32_t hist[1 << RADIX_MAX_L];
+  const int P1 = 1 << R.l1;
+  for (int p = threadIdx.x; p < P1; p += RADIX_BLOCK) hist[p] = 0;
+  __syncthreads();
+  const uint32_t narrow = KIND == 0 ? R.meta->narrow : 0u;
+  each_product<KIND>(R, narrow, [&](int64_t code, int64_t) {
+    atomicAdd(&hist[part1(code_hash(code), R.l1)], 1u);
+  });
+  __syncthreads();
+  const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  for (int p = threadIdx.x; p < P1; p += RADIX_BLOCK)
+    R.counts[(int64_t)p * R.nblocks + blk] = hist[p];
+}
+
+// Exclusive scan of n values by one workgroup of BS threads, each taking a
+// contiguous run; returns the total.  In place, 32-bit in-partition offsets
+// (a partition of 2^32 products or more is reported as ERR_CAPACITY).
+template <int BS, typename V>
+__device__ int64_t block_scan_runs(V* a, int64_t n, Meta* meta) {
+  __shared__ int64_t s_part[BS / 64];
+  __shared__ int64_t s_total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t per = (n + BS - 1) / BS;
+  const int64_t r0 = min(n, (int64_t)tid * per), r1 = min(n, r0 + per);
+  int64_t local = 0;
+  for (int64_t r = r0; r < r1; ++r) local += (int64_t)a[r];
+  int64_t incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) s_part[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < BS / 64; ++w) {
+      const int64_t x = s_part[w];
+      s_part[w] = run;
+      run += x;
+    }
+    s_total = run;
+  }
+  __syncthreads();
+  int64_t run = s_part[wave] + incl - local;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t x = (int64_t)a[r];
+    if (run > (int64_t)UINT32_MAX && sizeof(V) == 4) atomicOr(&meta->err, ERR_CAPACITY);
+    a[r] = (V)run;
+    run += x;
+  }
+  const int64_t total = s_total;
+  __syncthreads();
+  return total;
+}
+
+// One workgroup per level-1 partition: workgroup counts -> offsets within the
+// partition, and the partition's total.
+__global__ void __launch_bounds__(256) k_radix_scan_parts(RadixArgs R) {
+  const int64_t p = blockIdx.x;
+  const int64_t total = block_scan_runs<256>(R.counts + p * R.nblocks, R.nblocks, R.meta);
+  if (threadIdx.x == 0) R.pstart[p] = total;
+}
+
+// Partition totals -> partition starts (pstart[P1] = number of products).
+__global__ void __launch_bounds__(1024) k_radix_scan_totals(RadixArgs R) {
+  const int64_t P1 = (int64_t)1 << R.l1;
+  const int64_t total = block_scan_runs<1024>(R.pstart, P1, R.meta);
+  if (threadIdx.x == 0) R.pstart[P1] = total;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
+  __shared__ int64_t base[1 << RADIX_MAX_L];
+  __shared__ uint32_t cur[1 << RADIX_MAX_L];
+  const int P1 = 1 << R.l1;
+  const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  for (int p = threadIdx.x; p < P1; p += RADIX_BLOCK) {
+    base[p] = R.pstart[p] + (int64_t)R.counts[(int64_t)p * R.nblocks + blk];
+    cur[p] = 0;
+  }
+  __syncthreads();
+  const uint32_t narrow = KIND == 0 ? R.meta->narrow : 0u;
+  each_product<KIND>(R, narrow, [&](int64_t code, int64_t bits) {
+    const uint32_t p = part1(code_hash(code), R.l1);
+    const int64_t pos = base[p] + atomicAdd(&cur[p], 1u);
+    R.ent1[pos] = make_uint4((uint32_t)code, (uint32_t)((uint64_t)code >> 32), (uint32_t)bits,
+                             (uint32_t)((uint64_t)bits >> 32));
+  });
+}
+
+// One workgroup per level-1 partition: histogram by the level-2 bits, bin
+// starts, and the regrouped copy.
+__global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
+  __shared__ uint32_t h2[1 << RADIX_MAX_L];
+  __shared__ uint32_t cur[1 << RADIX_MAX_L];
+  const int P2 = 1 << R.l2;
+  const int64_t p = blockIdx.x;
+  const int64_t s = R.pstart[p], e = R.pstart[p + 1];
+  for (int b = threadIdx.x; b < P2; b += SPLIT_BLOCK) {
+    h2[b] = 0;
+    cur[b] = 0;
+  }
+  __syncthreads();
+  for (int64_t k = s + threadIdx.x; k < e; k += SPLIT_BLOCK) {
+    const uint4 en = R.ent1[k];
+    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
+    atomicAdd(&h2[part2(code_hash(code), R.l1, R.l2)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < P2; ++b) {
+      const uint32_t x = h2[b];
+      h2[b] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < P2; b += SPLIT_BLOCK) R.bstart[p * P2 + b] = s + h2[b];
+  if (p == ((int64_t)1 << R.l1) - 1 && threadIdx.x == 0) R.bstart[(p + 1) * P2] = e;
+  for (int64_t k = s + threadIdx.x; k < e; k += SPLIT_BLOCK) {
+    const uint4 en = R.ent1[k];
+    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
+    const uint32_t b = part2(code_hash(code), R.l1, R.l2);
+    R.ent2[s + h2[b] + atomicAdd(&cur[b], 1u)] = en;
+  }
+}
+
+__device__ __forceinline__ void lds_slot_add(int64_t* p, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+__device__ __forceinline__ void lds_slot_add(double* p, double v) { atomicAdd(p, v); }
+
+// One workgroup per level-2 bin: accumulate in an LDS table, then write the
+// nonzero terms at an offset taken from the call's output counter.
+template <typename T>
+__global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
+  __shared__ unsigned long long keys[BIN_SLOTS];
+  __shared__ T vals[BIN_SLOTS];
+  __shared__ int64_t s_wave[BIN_BLOCK / 64];
+  __shared__ int64_t s_base;
+  const int64_t b = blockIdx.x;
+  const int64_t s = R.bstart[b], e = R.bstart[b + 1];
+  if (s == e) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
+    keys[i] = 0;
+    vals[i] = T(0);
+  }
+  __syncthreads();
+  int64_t ins = 0, extra = 0;
+  for (int64_t k = s + tid; k < e; k += BIN_BLOCK) {
+    const uint4 en = R.ent2[k];
+    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
+    const uint64_t bits = ((uint64_t)en.w << 32) | en.z;
+    T v;
+    __builtin_memcpy(&v, &bits, 8);
+    const unsigned long long key = (unsigned long long)code + 1;
+    uint32_t slot = bin_slot(code_hash(code), R.l1, R.l2);
+    int q = 0;
+    for (; q < BIN_SLOTS; ++q) {
+      unsigned long long c = keys[slot];
+      if (c == 0) {
+        c = atomicCAS(&keys[slot], 0ull, key);
+        if (c == 0) c = key;
+      }
+      if (c == key) {
+        lds_slot_add(&vals[slot], v);
+        break;
+      }
+      slot = (slot + 1) & (BIN_SLOTS - 1);
+    }
+    if (q == BIN_SLOTS) atomicOr(&R.meta->err, ERR_CAPACITY);
+    ++ins;
+    extra += q;
+  }
+  __syncthreads();
+  // compaction: thread tid owns slots tid + r * BIN_BLOCK
+  constexpr int PER = BIN_SLOTS / BIN_BLOCK;
+  uint64_t ball[PER];
+  int64_t cnt = 0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int i = r * BIN_BLOCK + tid;
+    ball[r] = __ballot(keys[i] != 0 && vals[i] != T(0));
+    cnt += __popcll(ball[r]);
+  }
+  if (lane == 0) s_wave[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t tot = 0;
+    for (int w = 0; w < BIN_BLOCK / 64; ++w) tot += s_wave[w];
+    s_base = tot ? (int64_t)atomicAdd((unsigned long long*)&R.meta->out_count,
+                                      (unsigned long long)tot)
+                 : 0;
+  }
+  __syncthreads();
+  int64_t pos = s_base;
+  for (int w = 0; w < wave; ++w) pos += s_wave[w];
+  const uint64_t lt = (1ull << lane) - 1;
+  T* out_c = static_cast<T*>(R.out_c);
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if (ball[r] & (1ull << lane)) {
+      const int i = r * BIN_BLOCK + tid;
+      const int64_t q = pos + __popcll(ball[r] & lt);
+      if (q < R.out_cap) {
+        R.out_k[q] = (int64_t)(keys[i] - 1);
+        out_c[q] = vals[i];
+      }
+    }
+    pos += __popcll(ball[r]);
+  }
+  if (R.stats) add_stats(R.stats, ins, extra);
+}
+
 }  // namespace
 
 hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
@@ -366,6 +652,38 @@ hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_hash_compact<int64_t>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
                        H.table, cap, H.meta, H.out_k, (int64_t*)H.out_c, H.out_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
+  RadixArgs R = R0;
+  if (R.na == 0 || R.nb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((R.nb + RADIX_BLOCK - 1) / RADIX_BLOCK),
+                  (unsigned)((R.na + R.rows - 1) / R.rows));
+  R.nblocks = (int64_t)grid.x * grid.y;
+  const unsigned P1 = 1u << R.l1;
+  if (R.ev0) (void)hipEventRecord(R.ev0, s);
+  if (kind == 2)
+    hipLaunchKernelGGL(k_radix_count<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_radix_count<1>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else
+    hipLaunchKernelGGL(k_radix_count<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_radix_scan_parts, dim3(P1), dim3(256), 0, s, R);
+  hipLaunchKernelGGL(k_radix_scan_totals, dim3(1), dim3(1024), 0, s, R);
+  if (kind == 2)
+    hipLaunchKernelGGL(k_radix_scatter<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_radix_scatter<1>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else
+    hipLaunchKernelGGL(k_radix_scatter<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_radix_split, dim3(P1), dim3(SPLIT_BLOCK), 0, s, R);
+  const unsigned bins = P1 << R.l2;
+  if (kind == 0)
+    hipLaunchKernelGGL(k_radix_bins<int64_t>, dim3(bins), dim3(BIN_BLOCK), 0, s, R);
+  else
+    hipLaunchKernelGGL(k_radix_bins<double>, dim3(bins), dim3(BIN_BLOCK), 0, s, R);
+  if (R.ev1) (void)hipEventRecord(R.ev1, s);
   return hipGetLastError();
 }
 

@@ -296,6 +296,28 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
                                int rows, hipStream_t s);
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
 
+// Partitioned hash accumulation: products grouped by hash bits in two
+// levels through HBM, each final bin accumulated in an LDS table.
+struct RadixArgs {
+  const int64_t* ak; const void* ac; int64_t na;   // Laurent: codes, coefficients
+  const int64_t* bk; const void* bc; int64_t nb;   // (Poisson: coefficients only)
+  int64_t Wx; PoissonPrep P;                       // Poisson combined codes
+  int rows;              // rows of A per count / scatter workgroup
+  int l1, l2;            // log2 of the level-1 partitions and level-2 bins per partition
+  int64_t nblocks;       // count / scatter workgroups (set by the launcher)
+  uint32_t* counts;      // [2^l1][nblocks] products per (partition, workgroup), then offsets
+  int64_t* pstart;       // [2^l1 + 1] partition totals, then starts
+  int64_t* bstart;       // [2^(l1+l2) + 1] bin starts
+  uint4* ent1;           // [products] {code, value bits}, grouped by partition
+  uint4* ent2;           // [products] the same, grouped by bin
+  Meta* meta;
+  int64_t* out_k; void* out_c; int64_t out_cap;
+  unsigned long long* stats;
+  hipEvent_t ev0, ev1;   // optional: recorded around the whole accumulation
+};
+// kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
+hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
+
 // diagnostics (kp_diag.hip)
 hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
                             float* ms, hipStream_t s);

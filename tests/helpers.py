@@ -2,9 +2,16 @@
 import numpy as np
 
 
+def _col2d(c):
+    c = np.asarray(c, dtype=np.int64)
+    if c.ndim == 1:
+        return c.reshape(-1, 1)
+    return c.reshape(c.shape[0], int(np.prod(c.shape[1:])))
+
+
 def rows_key(*cols):
     """One int64 key per row of the integer columns (mixed radix over their ranges)."""
-    cols = [np.asarray(c, dtype=np.int64).reshape(len(c), -1) for c in cols]
+    cols = [_col2d(c) for c in cols]
     full = np.concatenate(cols, axis=1) if cols else np.zeros((0, 0), np.int64)
     return full
 

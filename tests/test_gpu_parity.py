@@ -252,7 +252,7 @@ def test_capacity_errors():
             kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), mode, out=small)
         assert e.value.status == kp.KP_E_CAPACITY
     # a forced hash table smaller than the result fills up: reported, not hung
-    ctx.set_tune(hash_capacity=64)
+    ctx.set_tune(hash_capacity=64, hash_partitioned=0)
     with pytest.raises(kp.KPError) as e:
         kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), "hash")
     assert e.value.status == kp.KP_E_CAPACITY
@@ -264,6 +264,44 @@ def test_capacity_errors():
         ctx.sync_check()
     ctx.set_tune(hash_capacity=0)
     check_laurent(a, b, "hash", "after recovery")
+
+
+def _with_partitioning(ctx, mode):
+    ctx.set_tune(hash_partitioned=mode)
+
+
+@pytest.mark.parametrize("part", [0, 2])
+def test_hash_layouts_match_oracle(part):
+    """Both hash layouts (global table, products partitioned through HBM into
+    LDS tables), forced, on sparse, colliding, fp64, ragged and duplicate-heavy
+    products."""
+    ctx = kp.context()
+    _with_partitioning(ctx, part)
+    a, b = I.config(3, scale=0.1)
+    check_laurent(a, b, "hash", f"sparse 3000 (partitioned={part})")
+    a, b = I.config(1)
+    check_laurent(a, b, "hash", f"box 500 x 500, many products per code (partitioned={part})")
+    a, b = I.config(2, scale=0.05)
+    a64 = (a[0], a[1].astype(np.float64) / 8)
+    check_laurent(a64, (b[0], b[1].astype(np.float64)), "hash", f"fp64 simplex (partitioned={part})")
+    rng = np.random.default_rng(31 + part)
+    for na, nb in ((1, 1), (1, 700), (63, 65), (257, 1)):
+        ra = (rng.integers(-40, 40, (na, 2)).astype(np.int32), rng.integers(-9, 10, na))
+        rb = (rng.integers(-40, 40, (nb, 2)).astype(np.int32), rng.integers(-9, 10, nb))
+        check_laurent(ra, rb, "hash", f"ragged {na} x {nb} (partitioned={part})")
+    # three product codes only: every bin but three is empty, each busy bin
+    # holds one code many times
+    da = (rng.integers(0, 2, (600, 1)).astype(np.int32), rng.integers(1, 50, 600))
+    db = (rng.integers(0, 2, (500, 1)).astype(np.int32), rng.integers(1, 50, 500))
+    check_laurent(da, db, "hash", f"3 codes from 3e5 products (partitioned={part})")
+
+
+@pytest.mark.parametrize("part", [0, 2])
+def test_poisson_hash_layouts(part):
+    ctx = kp.context()
+    _with_partitioning(ctx, part)
+    a, b = I.config(4, scale=0.06)
+    check_poisson(a, b, f"poisson hash (partitioned={part})", mode="hash")
 
 
 def test_repeat_runs_bit_identical():

@@ -230,10 +230,33 @@ def test_tune_validation():
     assert t.window == 18432 and t.block == 1024 and t.tasks_per_cu == 1
     ctx.set_tune(window=2048, block=512)
     assert ctx.tune.window == 2048
+    assert t.hash_partitioned == 1
     for bad in (dict(window=18432 + 2048), dict(block=100), dict(hash_load=0.95),
-                dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1)):
+                dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1),
+                dict(hash_partitioned=3), dict(hash_partitioned=-1)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
+
+
+def test_partitioned_hash_workspace():
+    """Partitioned hash mode keeps every product (16 bytes, twice); the
+    global table two 16-byte slots per bounded result term.  Auto takes the
+    partitioned one only when the products are at most 4x the bound."""
+    ctx = _host_ctx()
+    sparse = kp.layout_product(6, 0, [0] * 6, [80] * 6, [0] * 6, [80] * 6)
+    box = kp.layout_product(3, 0, [-5] * 3, [5] * 3, [-5] * 3, [5] * 3)
+    na = nb = 3000
+    _, mo, ws_auto = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+    assert mo == na * nb and ws_auto >= 32 * na * nb
+    ctx.set_tune(hash_partitioned=0)
+    _, _, ws_table = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+    assert 32 * na * nb <= ws_table < 33 * na * nb
+    _, mo_box, ws_box_table = kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)
+    ctx.set_tune(hash_partitioned=1)
+    assert kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)[2] == ws_box_table
+    ctx.set_tune(hash_partitioned=2)
+    _, _, ws_box_part = kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)
+    assert mo_box == 21 ** 3 and ws_box_part >= 32 * 500 * 500 > ws_box_table
 
 
 def test_host_context_rejects_launches():
