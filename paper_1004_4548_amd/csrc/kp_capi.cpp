@@ -363,15 +363,15 @@ struct HashCarve {
   uint4* ent2;
 };
 
-// Shape of the partitioned accumulation: about 1024 products per bin (a
-// quarter of the LDS table), at most 2^10 partitions and 2^10 bins each;
-// about 4096 count/scatter workgroups.
+// Shape of the partitioned accumulation: at most 1024 products per bin on
+// average (half of the LDS table), at most 2^10 partitions and 2^10 bins
+// each; about 4096 count/scatter workgroups.
 void radix_shape(int64_t na, int64_t nb, int64_t nprod, Plan* p) {
   int bits = 1;
   while (bits < 20 && ((int64_t)1024 << bits) < nprod) ++bits;
   p->l2 = std::min(10, bits / 2);
   p->l1 = std::max(1, bits - p->l2);
-  const int64_t bx = std::max<int64_t>(1, (nb + 255) / 256);
+  const int64_t bx = std::max<int64_t>(1, (nb + RADIX_THREADS - 1) / RADIX_THREADS);
   int64_t rows = (na * bx + 4095) / 4096;
   rows = std::max<int64_t>(rows, (na + 65534) / 65535);   // grid.y limit
   p->rows = (int)std::max<int64_t>(1, std::min<int64_t>(rows, (int64_t)1 << 30));

@@ -323,11 +323,12 @@ k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
 // about BIN_TARGET products, all of any one code; one workgroup accumulates
 // a bin in an LDS open-addressing table and writes its nonzero terms.  HBM
 // sees sequential runs instead of one random line per insertion.
-constexpr int RADIX_BLOCK = 256;     // count and scatter: threads over terms of B
+constexpr int RADIX_BLOCK = RADIX_THREADS;   // count and scatter: threads over terms of B
+constexpr int STAGE = 8192;          // entries staged per chunk (8 per thread): 128 KiB of LDS
 constexpr int RADIX_MAX_L = 10;      // at most 1024 partitions per level
 constexpr int SPLIT_BLOCK = 1024;
 constexpr int BIN_BLOCK = 256;
-constexpr int BIN_SLOTS = 4096;      // LDS table of one bin: 4096 x (8 + 8) bytes
+constexpr int BIN_SLOTS = 2048;      // LDS table of one bin: 2048 x (8 + 8) bytes
 
 __device__ __forceinline__ uint64_t code_hash(int64_t code) { return (uint64_t)code * GOLDEN; }
 __device__ __forceinline__ uint32_t part1(uint64_t h, int l1) { return (uint32_t)(h >> (64 - l1)); }
@@ -378,6 +379,87 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
       f(R.ak[i] + bj, bits);
     }
   }
+}
+
+// Rows [r0, r0 + CR) of A against this thread's term j of B (CR = 8 for
+// Laurent, 4 for Poisson, whose pairs give two pieces): up to 8 products in
+// fixed slots, valid where `mask` has the slot's bit.
+template <int KIND>
+__device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t narrow, int64_t j,
+                                                   int64_t r0, int64_t r1, int64_t (&code)[8],
+                                                   int64_t (&bits)[8]) {
+  uint32_t mask = 0;
+  if (j >= R.nb) return 0;
+  if constexpr (KIND == 2) {
+    const double* ac = static_cast<const double*>(R.ac);
+    const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
+    const int tb = R.P.bt[j];
+    const double cb = static_cast<const double*>(R.bc)[j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = r0 + u;
+      if (i >= r1) break;
+      const int ta = R.P.at[i];
+      const double h = 0.5 * (ac[i] * cb);
+      if (h == 0.0) continue;
+      const int64_t kx = R.P.akx[i] + kxb;
+      const int t = ta ^ tb;
+      const double sm = (!ta && tb) ? -h : h;
+      const double sp = (ta && tb) ? -h : h;
+      double v;
+      if (poisson_piece(R.Wx, R.P.ap[i] + Bm, kx, t, sm, &code[2 * u], &v)) {
+        bits[2 * u] = __double_as_longlong(v);
+        mask |= 1u << (2 * u);
+      }
+      if (poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &code[2 * u + 1], &v)) {
+        bits[2 * u + 1] = __double_as_longlong(v);
+        mask |= 1u << (2 * u + 1);
+      }
+    }
+  } else {
+    using T = typename std::conditional<KIND == 0, int64_t, double>::type;
+    const T* ac = static_cast<const T*>(R.ac);
+    const int64_t bj = R.bk[j];
+    const T cb = static_cast<const T*>(R.bc)[j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = r0 + u;
+      if (i >= r1) break;
+      const T v = mul_coef<T>(ac[i], cb, narrow);
+      if (v == T(0)) continue;
+      code[u] = R.ak[i] + bj;
+      __builtin_memcpy(&bits[u], &v, 8);
+      mask |= 1u << u;
+    }
+  }
+  return mask;
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan1(uint32_t v, uint32_t* s_ws, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) s_ws[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      const uint32_t x = s_ws[w];
+      s_ws[w] = run;
+      run += x;
+    }
+    s_ws[NT / 64] = run;
+  }
+  __syncthreads();
+  const uint32_t r = s_ws[wave] + incl - v;
+  *total = s_ws[NT / 64];
+  __syncthreads();
+  return r;
 }
 
 template <int KIND>
@@ -452,61 +534,149 @@ __global__ void __launch_bounds__(1024) k_radix_scan_totals(RadixArgs R) {
   if (threadIdx.x == 0) R.pstart[P1] = total;
 }
 
+// Products in chunks of 8 rows per thread: each chunk is counting-sorted by
+// partition through LDS and written as contiguous runs (about 8 entries, one
+// 128-byte line, per partition and chunk) after this workgroup's earlier
+// runs in each partition.
 template <int KIND>
 __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
+  __shared__ uint4 stage[STAGE];
   __shared__ int64_t base[1 << RADIX_MAX_L];
-  __shared__ uint32_t cur[1 << RADIX_MAX_L];
+  __shared__ uint32_t coff[1 << RADIX_MAX_L];
+  __shared__ uint32_t done[1 << RADIX_MAX_L];
+  __shared__ uint32_t s_ws[RADIX_BLOCK / 64 + 1];
+  constexpr int CR = KIND == 2 ? 4 : 8;
+  const int tid = threadIdx.x;
   const int P1 = 1 << R.l1;
   const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  for (int p = threadIdx.x; p < P1; p += RADIX_BLOCK) {
-    base[p] = R.pstart[p] + (int64_t)R.counts[(int64_t)p * R.nblocks + blk];
-    cur[p] = 0;
+  if (tid < P1) {
+    base[tid] = R.pstart[tid] + (int64_t)R.counts[(int64_t)tid * R.nblocks + blk];
+    coff[tid] = 0;
+    done[tid] = 0;
   }
   __syncthreads();
   const uint32_t narrow = KIND == 0 ? R.meta->narrow : 0u;
-  each_product<KIND>(R, narrow, [&](int64_t code, int64_t bits) {
-    const uint32_t p = part1(code_hash(code), R.l1);
-    const int64_t pos = base[p] + atomicAdd(&cur[p], 1u);
-    R.ent1[pos] = make_uint4((uint32_t)code, (uint32_t)((uint64_t)code >> 32), (uint32_t)bits,
-                             (uint32_t)((uint64_t)bits >> 32));
-  });
+  const int64_t j = (int64_t)blockIdx.x * RADIX_BLOCK + tid;
+  const int64_t i0 = (int64_t)blockIdx.y * R.rows;
+  const int64_t i1 = min(i0 + R.rows, R.na);
+  for (int64_t r0 = i0; r0 < i1; r0 += CR) {
+    int64_t code[8], bits[8];
+    const uint32_t mask = chunk_products<KIND>(R, narrow, j, r0, i1, code, bits);
+    uint32_t part[8], rank[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if ((mask >> u) & 1u) {
+        part[u] = part1(code_hash(code[u]), R.l1);
+        rank[u] = atomicAdd(&coff[part[u]], 1u);
+      }
+    __syncthreads();
+    const uint32_t mine = tid < P1 ? coff[tid] : 0u;
+    uint32_t total;
+    const uint32_t off = block_scan1<RADIX_BLOCK>(mine, s_ws, &total);
+    if (tid < P1) coff[tid] = off;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if ((mask >> u) & 1u)
+        stage[coff[part[u]] + rank[u]] = make_uint4((uint32_t)code[u],
+                                                    (uint32_t)((uint64_t)code[u] >> 32),
+                                                    (uint32_t)bits[u],
+                                                    (uint32_t)((uint64_t)bits[u] >> 32));
+    __syncthreads();
+    for (uint32_t t = tid; t < total; t += RADIX_BLOCK) {
+      const uint4 en = stage[t];
+      const uint32_t p = part1(code_hash((int64_t)(((uint64_t)en.y << 32) | en.x)), R.l1);
+      R.ent1[base[p] + done[p] + (t - coff[p])] = en;
+    }
+    __syncthreads();
+    if (tid < P1) {
+      done[tid] += mine;
+      coff[tid] = 0;
+    }
+    __syncthreads();
+  }
 }
 
 // One workgroup per level-1 partition: histogram by the level-2 bits, bin
-// starts, and the regrouped copy.
+// starts, and the regrouped copy, staged in chunks of STAGE entries like the
+// scatter so that each bin receives contiguous runs.
 __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
+  static_assert(SPLIT_BLOCK * 8 == STAGE, "eight entries per thread and chunk");
+  __shared__ uint4 stage[STAGE];
   __shared__ uint32_t h2[1 << RADIX_MAX_L];
-  __shared__ uint32_t cur[1 << RADIX_MAX_L];
+  __shared__ uint32_t coff[1 << RADIX_MAX_L];
+  __shared__ uint32_t done[1 << RADIX_MAX_L];
+  __shared__ uint32_t s_ws[SPLIT_BLOCK / 64 + 1];
+  const int tid = threadIdx.x;
   const int P2 = 1 << R.l2;
   const int64_t p = blockIdx.x;
   const int64_t s = R.pstart[p], e = R.pstart[p + 1];
-  for (int b = threadIdx.x; b < P2; b += SPLIT_BLOCK) {
-    h2[b] = 0;
-    cur[b] = 0;
+  if (tid < P2) {
+    h2[tid] = 0;
+    coff[tid] = 0;
+    done[tid] = 0;
   }
   __syncthreads();
-  for (int64_t k = s + threadIdx.x; k < e; k += SPLIT_BLOCK) {
-    const uint4 en = R.ent1[k];
-    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
-    atomicAdd(&h2[part2(code_hash(code), R.l1, R.l2)], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = 0; b < P2; ++b) {
-      const uint32_t x = h2[b];
-      h2[b] = run;
-      run += x;
+  constexpr int U = 8;   // loads in flight per thread
+  for (int64_t k0 = s + tid; k0 < e; k0 += (int64_t)SPLIT_BLOCK * U) {
+    uint2 c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = k0 + (int64_t)u * SPLIT_BLOCK;
+      c[u] = k < e ? reinterpret_cast<const uint2*>(R.ent1)[2 * k] : make_uint2(0, 0);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + (int64_t)u * SPLIT_BLOCK < e) {
+        const int64_t code = (int64_t)(((uint64_t)c[u].y << 32) | c[u].x);
+        atomicAdd(&h2[part2(code_hash(code), R.l1, R.l2)], 1u);
+      }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < P2; b += SPLIT_BLOCK) R.bstart[p * P2 + b] = s + h2[b];
-  if (p == ((int64_t)1 << R.l1) - 1 && threadIdx.x == 0) R.bstart[(p + 1) * P2] = e;
-  for (int64_t k = s + threadIdx.x; k < e; k += SPLIT_BLOCK) {
-    const uint4 en = R.ent1[k];
-    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
-    const uint32_t b = part2(code_hash(code), R.l1, R.l2);
-    R.ent2[s + h2[b] + atomicAdd(&cur[b], 1u)] = en;
+  uint32_t all;
+  const uint32_t boff = block_scan1<SPLIT_BLOCK>(tid < P2 ? h2[tid] : 0u, s_ws, &all);
+  if (tid < P2) {
+    h2[tid] = boff;
+    R.bstart[p * P2 + tid] = s + boff;
+  }
+  if (p == ((int64_t)1 << R.l1) - 1 && tid == 0) R.bstart[(p + 1) * P2] = e;
+  __syncthreads();
+  for (int64_t c0 = s; c0 < e; c0 += STAGE) {
+    uint4 en[U];
+    uint32_t bin[U], rank[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = c0 + (int64_t)u * SPLIT_BLOCK + tid;
+      en[u] = k < e ? R.ent1[k] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c0 + (int64_t)u * SPLIT_BLOCK + tid < e) {
+        const int64_t code = (int64_t)(((uint64_t)en[u].y << 32) | en[u].x);
+        bin[u] = part2(code_hash(code), R.l1, R.l2);
+        rank[u] = atomicAdd(&coff[bin[u]], 1u);
+      }
+    __syncthreads();
+    const uint32_t mine = tid < P2 ? coff[tid] : 0u;
+    uint32_t total;
+    const uint32_t off = block_scan1<SPLIT_BLOCK>(mine, s_ws, &total);
+    if (tid < P2) coff[tid] = off;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c0 + (int64_t)u * SPLIT_BLOCK + tid < e) stage[coff[bin[u]] + rank[u]] = en[u];
+    __syncthreads();
+    for (uint32_t t = tid; t < total; t += SPLIT_BLOCK) {
+      const uint4 x = stage[t];
+      const uint32_t b = part2(code_hash((int64_t)(((uint64_t)x.y << 32) | x.x)), R.l1, R.l2);
+      R.ent2[s + h2[b] + done[b] + (t - coff[b])] = x;
+    }
+    __syncthreads();
+    if (tid < P2) {
+      done[tid] += mine;
+      coff[tid] = 0;
+    }
+    __syncthreads();
   }
 }
 

@@ -317,6 +317,9 @@ struct RadixArgs {
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
+// Threads (terms of B) per count / scatter workgroup; the workspace planner
+// sizes the per-workgroup histograms with it.
+constexpr int RADIX_THREADS = 1024;
 
 // diagnostics (kp_diag.hip)
 hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
