@@ -132,20 +132,28 @@ kp_status wait_seq(kp_ctx* ctx, const uint64_t* slot, uint64_t want, hipStream_t
   }
 }
 
+uint64_t next_seq(kp_ctx* ctx) {
+  std::lock_guard<std::mutex> guard(ctx->mb_mu);
+  return ++ctx->seq;
+}
+
 // Blocking end of a from-exponents multiply: the count and the latched
-// status come back through the mailbox; an error is then read and cleared
-// from the status block as by kp_ctx_check.
+// status come back through the mailbox (posted by a kernel already queued
+// under `posted`, or else by a post queued here); an error is then read and
+// cleared from the status block as by kp_ctx_check.
 kp_status wait_count(kp_ctx* ctx, const int64_t* out_n, int64_t* n_host, hipStream_t s,
-                     const char* what) {
+                     const char* what, uint64_t posted = 0) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, what);
   int64_t n;
   uint32_t err;
   {
+    const uint64_t seq = posted ? posted : next_seq(ctx);
     std::lock_guard<std::mutex> guard(ctx->mb_mu);
-    const uint64_t seq = ++ctx->seq;
-    e = launch_post_count(out_n, &ctx->status->err, ctx->mb_dev, seq, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    if (!posted) {
+      e = launch_post_count(out_n, &ctx->status->err, ctx->mb_dev, seq, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, what);
+    }
     kp_status st = wait_seq(ctx, &ctx->mb->n_seq, seq, s, what);
     if (st != KP_OK) return st;
     n = ctx->mb->n;
@@ -820,12 +828,23 @@ namespace {
 
 // Queues one Laurent product (no synchronisation).  `timed`: record the
 // context's timing events around the accumulation kernel when enabled.
+// Dense-mode options of the from-exponents path: the output copy decodes
+// into `exps`, and the output scan posts the count to the mailbox under
+// `seq` (0: no post).  `fused` reports whether they were taken.
+struct ExpsOut {
+  int32_t* exps;
+  DevLayout dec;
+  Mailbox* mb;
+  uint64_t seq;
+  bool fused;
+};
+
 kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
                           const int64_t* a_codes, const void* a_coef, int64_t na,
                           const int64_t* b_codes, const void* b_coef, int64_t nb,
                           int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
                           void* workspace, size_t workspace_bytes, hipStream_t stream,
-                          bool timed) {
+                          bool timed, ExpsOut* xo = nullptr) {
   if (!ctx) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   Plan p;
@@ -851,6 +870,13 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
     B.out_c = out_coef;
     B.out_cap = out_cap;
     B.out_n = out_n;
+    if (xo && !empty) {
+      B.out_exps = xo->exps;
+      B.dec = xo->dec;
+      B.mb = xo->seq ? xo->mb : nullptr;
+      B.seq = xo->seq;
+      xo->fused = true;
+    }
     B.ctx_err = &ctx->status->err;
     if (!empty) {
       if (timed) std::tie(B.ev0, B.ev1) = timing_pair(ctx);
@@ -1067,15 +1093,21 @@ kp_status kp_mul_laurent_exps(kp_ctx* ctx, const kp_layout* layout, kp_dtype dty
                        nullptr, nullptr, ka, nullptr, b_exps, nullptr, nullptr, kb, nullptr,
                        &ctx->status->err, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps encode");
+  // dense mode decodes in its output copy and posts the count from its
+  // output scan, so the host wakes before the copy has run
+  const bool sync = !(flags & KP_FLAG_ASYNC);
+  ExpsOut xo{out_exps, make_dev_layout(*layout, 0), ctx->mb_dev, sync ? next_seq(ctx) : 0, false};
   st = enqueue_laurent(ctx, layout, dtype, mode, ka, a_coef, na, kb, b_coef, nb, oc, out_coef,
                        ncodes, out_n, static_cast<char*>(workspace) + c.off,
-                       workspace_bytes - c.off, stream, true);
+                       workspace_bytes - c.off, stream, true, &xo);
   if (st != KP_OK) return st;
-  e = launch_decode_n(make_dev_layout(*layout, 0), 0, out_n, ncodes, oc, out_exps, nullptr,
-                      nullptr, &ctx->status->err, stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps decode");
-  if (flags & KP_FLAG_ASYNC) return finish(ctx, flags, stream, "kp_mul_laurent_exps");
-  return wait_count(ctx, out_n, n_host, stream, "kp_mul_laurent_exps");
+  if (!xo.fused) {
+    e = launch_decode_n(make_dev_layout(*layout, 0), 0, out_n, ncodes, oc, out_exps, nullptr,
+                        nullptr, &ctx->status->err, stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps decode");
+  }
+  if (!sync) return finish(ctx, flags, stream, "kp_mul_laurent_exps");
+  return wait_count(ctx, out_n, n_host, stream, "kp_mul_laurent_exps", xo.fused ? xo.seq : 0);
 }
 
 kp_status kp_mul_laurent_auto(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,

@@ -914,6 +914,8 @@ struct ScanArgs {
   int64_t* coff;
   int64_t* out_n;
   uint32_t* ctx_err;
+  Mailbox* mb;      // optional: the count is posted here as soon as it is known
+  uint64_t seq;
 };
 
 __global__ void __launch_bounds__(1024) k_dense_scan(ScanArgs A) {
@@ -933,11 +935,14 @@ __global__ void __launch_bounds__(1024) k_dense_scan(ScanArgs A) {
     // asynchronous call (an encode that found an exponent out of range)
     uint32_t e = A.meta->err | A.meta->seg_err[0] | A.meta->seg_err[1] | *A.ctx_err;
     if (total > A.out_cap) e |= ERR_CAPACITY;
-    if (e) {
-      atomicOr(A.ctx_err, e);
-      *A.out_n = -(int64_t)first_error(e);
-    } else {
-      *A.out_n = total;
+    const int64_t n = e ? -(int64_t)first_error(e) : total;
+    if (e) atomicOr(A.ctx_err, e);
+    *A.out_n = n;
+    if (A.mb) {   // the waiting host needs only the count; the copy follows in stream order
+      A.mb->n = n;
+      A.mb->err = e;
+      __threadfence_system();
+      __hip_atomic_store(&A.mb->n_seq, A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -950,9 +955,14 @@ struct CopyArgs {
   const int64_t* stage_c;
   int64_t* out_k;
   int64_t* out_c;
+  int32_t* out_x;   // optional: decoded exponents instead of codes
+  DevLayout L;
+  const int64_t* out_n;   // the scan's count: nothing is written after an error
 };
 
+template <bool DECODE>
 __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
+  if (*C.out_n < 0) return;
   const int64_t c = blockIdx.x;
   const int64_t n = C.ccount[c], off = C.coff[c];
   const int64_t* sk = C.stage_k + c * DENSE_CHUNK;
@@ -960,7 +970,13 @@ __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
   for (int64_t r = threadIdx.x; r < n; r += 256) {
     const int64_t q = off + r;
     if (q < C.out_cap) {
-      C.out_k[q] = sk[r];
+      if constexpr (DECODE) {
+        int32_t ex[KP_MAX_VARS];
+        decode_x(C.L, (uint64_t)sk[r], ex);
+        for (int v = 0; v < C.L.nx; ++v) C.out_x[q * C.L.nx + v] = ex[v];
+      } else {
+        C.out_k[q] = sk[r];
+      }
       C.out_c[q] = sc[r];
     }
   }
@@ -1067,11 +1083,14 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   else
     hipLaunchKernelGGL(k_dense_combine<int64_t>, dim3(cgrid), dim3(COMBINE_BLOCK), 0, s, cb);
 
-  ScanArgs sa{B.meta, P.nchunk, B.out_cap, B.ccount, B.coff, B.out_n, B.ctx_err};
+  ScanArgs sa{B.meta, P.nchunk, B.out_cap, B.ccount, B.coff, B.out_n, B.ctx_err, B.mb, B.seq};
   hipLaunchKernelGGL(k_dense_scan, dim3(1), dim3(1024), 0, s, sa);
   CopyArgs ca{B.out_cap, B.ccount, B.coff, B.stage_k, B.stage_c, B.out_k,
-              reinterpret_cast<int64_t*>(B.out_c)};
-  hipLaunchKernelGGL(k_dense_copy, dim3((unsigned)P.nchunk), dim3(256), 0, s, ca);
+              reinterpret_cast<int64_t*>(B.out_c), B.out_exps, B.dec, B.out_n};
+  if (B.out_exps)
+    hipLaunchKernelGGL(k_dense_copy<true>, dim3((unsigned)P.nchunk), dim3(256), 0, s, ca);
+  else
+    hipLaunchKernelGGL(k_dense_copy<false>, dim3((unsigned)P.nchunk), dim3(256), 0, s, ca);
   return hipGetLastError();
 }
 

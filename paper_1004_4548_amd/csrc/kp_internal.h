@@ -267,6 +267,14 @@ struct DenseBufs {
   int64_t* out_k; void* out_c; int64_t out_cap; int64_t* out_n;
   uint32_t* ctx_err;
   hipEvent_t ev0, ev1;   // optional: recorded around the window kernel
+  // optional: the output scan also posts the count (or -status) and the
+  // status bits to this mailbox, then seq to its n_seq
+  struct Mailbox* mb;
+  uint64_t seq;
+  // optional: the output copy writes decoded exponents (int32[n][dec.nx])
+  // instead of codes
+  int32_t* out_exps;
+  DevLayout dec;
 };
 hipError_t dense_setup();
 hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s);
