@@ -62,7 +62,7 @@ namespace kp {
 namespace {
 
 constexpr int PREP_BLOCK = 1024;
-constexpr int PLAN_BLOCK = 256;
+constexpr int PLAN_BLOCK = 1024;
 constexpr int64_t ITEMS_LDS_BYTES = 144 * 1024;   // tile rows and item map of the items kernel
 constexpr int PREP_UNROLL = 8;
 // Byte offsets that can never fall inside a window (codes are below 2^27, so
@@ -441,19 +441,21 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   };
   const int64_t per = (P.nwin + PLAN_BLOCK - 1) / PLAN_BLOCK;
   const int64_t w0 = min(P.nwin, tid * per), w1 = min(w0 + per, P.nwin);
-  int64_t li = 0;
-  for (int64_t u = w0; u < w1; ++u) li += ld(W_ITEMS, u);
-  // cost of a window: its items plus WINDOW_COST when it has any
-  int64_t lc = 0;
+  // each thread's windows, read once (kept in registers for up to 4)
+  constexpr int KEEP = 4;
+  int64_t kept[KEEP];
+  int64_t li = 0, lc = 0;   // items, and cost: items plus WINDOW_COST when any
   for (int64_t u = w0; u < w1; ++u) {
     const int64_t it = ld(W_ITEMS, u);
+    if (u - w0 < KEEP) kept[u - w0] = it;
+    li += it;
     lc += it > 0 ? it + WINDOW_COST : 0;
   }
   int64_t all_items, all_cost;
   int64_t ibase = block_exclusive_scan<PLAN_BLOCK>(li, s_wave, &all_items);
   int64_t cbase = block_exclusive_scan<PLAN_BLOCK>(lc, s_wave, &all_cost);
   for (int64_t u = w0; u < w1; ++u) {
-    const int64_t it = ld(W_ITEMS, u);
+    const int64_t it = u - w0 < KEEP ? kept[u - w0] : ld(W_ITEMS, u);
     P.win[W_IBASE * W1 + u] = ibase;
     P.win[W_CBASE * W1 + u] = cbase;
     ibase += it;
