@@ -152,6 +152,23 @@ const char* kp_last_error(const kp_ctx* ctx);
 kp_status kp_ctx_timing(kp_ctx* ctx, int enable);
 kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Truncated multiplication (Section 3 names efficient truncation among the
+   requirements of a series multiplier).  While a truncation is set, Laurent
+   products computed with this context (kp_mul_laurent and the from-exponents
+   calls, also inside batches, at the time they are queued) keep only the
+   terms whose weighted degree sum_v weights[v] * e_v is at most max_degree;
+   variables from nvars on have weight 0.  A pair of terms over the limit is
+   never generated in hash mode and is sent to the discard slot in dense mode
+   (the degree is linear, so the pair test deg_a + deg_b <= max_degree is
+   exact).  weights: nvars (1..KP_MAX_VARS) values in [-2^15, 2^15].  Every
+   factor term's weighted degree must lie in [-2^30, 2^30], else the multiply
+   reports KP_E_RANGE.  Poisson products reject a set truncation (KP_E_ARG).
+   kp_ctx_clear_truncation removes it.  Workspace sizes (kp_mul_bound, the
+   plan calls) include the truncation tables while one is set. */
+kp_status kp_ctx_set_truncation(kp_ctx* ctx, int32_t nvars, const int32_t* weights,
+                                int64_t max_degree);
+kp_status kp_ctx_clear_truncation(kp_ctx* ctx);
+
 /* Hash-table statistics (Section 3.2: open addressing with linear probing).
    While enabled, every hash-mode multiply adds to two device counters in the
    context's status block: the number of term products inserted (nonzero

@@ -13,6 +13,8 @@ out of that library.
 Every function here is pinned by ``tests/test_oracle_pins.py``:
   * ``laurent_mul``      -- n-D convolution, Fateman closed form, mod-p
                             evaluation of the Monagan-Pearce benchmark;
+  * ``laurent_mul_truncated`` -- brute force with the degree test on each
+                            pair, a binomial closed form, the limiting cuts;
   * ``poisson_mul``      -- trigonometric identities, numeric evaluation at
                             random angles, exact evaluation over F_{p^2};
   * ``*_coeff_at``       -- against the full product on random inputs, whose
@@ -138,6 +140,19 @@ def laurent_mul(a_exps, a_coef, b_exps, b_coef, row_begin=0, row_end=-1, threads
     finally:
         lib.oracle_laurent_free(h)
     return ex, co, ab
+
+
+def laurent_mul_truncated(a_exps, a_coef, b_exps, b_coef, weights, max_degree, threads=1):
+    """Truncated product (Section 3: a series multiplier should truncate): the
+    terms of A*B whose weighted degree sum_v weights[v] * e_v is at most
+    max_degree.  Definition applied literally: the full product, then the
+    filter (variables past len(weights) have weight 0).  Same return layout
+    as ``laurent_mul``."""
+    ex, co, ab = laurent_mul(a_exps, a_coef, b_exps, b_coef, threads=threads)
+    w = np.zeros(ex.shape[1], dtype=np.int64)
+    w[:min(len(weights), ex.shape[1])] = np.asarray(weights, dtype=np.int64)[:ex.shape[1]]
+    keep = ex.astype(np.int64) @ w <= max_degree
+    return ex[keep], co[keep], (ab[keep] if ab is not None else None)
 
 
 def laurent_coeff_at(a_exps, a_coef, b_exps, b_coef, q_exps):

@@ -42,7 +42,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status",
             "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic",
             "kp_plan_laurent", "kp_mul_laurent_exps", "kp_plan_poisson", "kp_mul_poisson_exps",
-            "kp_mul_laurent_auto"]
+            "kp_mul_laurent_auto", "kp_ctx_set_truncation", "kp_ctx_clear_truncation"]
 
 
 class KPError(RuntimeError):
@@ -130,6 +130,8 @@ def lib():
         "kp_mul_laurent_auto": (i32, [p, i32, i32, i32, u32, p, p, i64, p, p, i64, p, p, i64, p,
                                       C.POINTER(i64), p, sz, C.POINTER(Layout), C.POINTER(i64),
                                       C.POINTER(sz), p]),
+        "kp_ctx_set_truncation": (i32, [p, i32, C.POINTER(i32), i64]),
+        "kp_ctx_clear_truncation": (i32, [p]),
         "kp_plan_poisson": (i32, [p, i32, i32, i32, p, p, i64, p, p, i64, C.POINTER(Layout),
                                   C.POINTER(i32), C.POINTER(i64), C.POINTER(sz), p]),
         "kp_mul_poisson_exps": (i32, [p, C.POINTER(Layout), i32, u32, p, p, p, p, i64, p, p, p, p,
@@ -242,6 +244,28 @@ class Context:
         n = C.c_int64()
         self.check(lib().kp_ctx_timing_read(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_truncation(self, weights, max_degree):
+        """Keep only product terms with sum(w * e) <= max_degree (Laurent)."""
+        w = [int(x) for x in weights]
+        arr = (C.c_int32 * len(w))(*w)
+        self.check(lib().kp_ctx_set_truncation(self.h, len(w), arr, int(max_degree)))
+
+    def clear_truncation(self):
+        self.check(lib().kp_ctx_clear_truncation(self.h))
+
+    def truncation(self, weights, max_degree):
+        """Context manager: a truncation for the products inside the block."""
+        import contextlib
+
+        @contextlib.contextmanager
+        def scope():
+            self.set_truncation(weights, max_degree)
+            try:
+                yield self
+            finally:
+                self.clear_truncation()
+        return scope()
 
     def hash_stats(self, enable=True):
         """Count insertions and extra probe steps of every hash-mode multiply."""

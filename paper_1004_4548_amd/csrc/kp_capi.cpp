@@ -29,6 +29,8 @@ struct kp_ctx {
   kp::Mailbox* mb_dev = nullptr;      // the same, device address
   uint64_t seq = 0;                   // last sequence number handed to a kernel
   std::mutex mb_mu;                   // serialises mailbox users
+  bool trunc_on = false;              // truncation of Laurent products by weighted degree
+  kp::TruncSpec trunc{};
 };
 
 namespace kp {
@@ -234,7 +236,25 @@ struct Plan {
   bool radix = false;
   int rows = 0, l1 = 1, l2 = 0;
   int64_t nblocks = 0, nprod = 0;
+  bool trunc = false;   // truncation tables follow the mode's workspace
 };
+
+// Truncation tables: slack of A's terms and degree of B's (input order),
+// and in dense mode their bucket-sorted copies.
+struct TruncBufs {
+  int32_t* sa; int32_t* tb;
+  int32_t* sa_sorted; int32_t* tb_sorted;
+};
+void carve_trunc(Carver& c, const Plan& p, int64_t na, int64_t nb, TruncBufs* t) {
+  *t = TruncBufs{};
+  if (!p.trunc) return;
+  t->sa = c.take<int32_t>(na);
+  t->tb = c.take<int32_t>(nb);
+  if (p.mode == KP_DENSE) {
+    t->sa_sorted = c.take<int32_t>(na);
+    t->tb_sorted = c.take<int32_t>(nb);
+  }
+}
 
 int64_t factor_maxcode(const kp_layout* L, int which) {
   int64_t m = 0;
@@ -497,6 +517,9 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
   }
+  p->trunc = ctx->trunc_on && !poisson;
+  TruncBufs tb;
+  carve_trunc(c, *p, na, nb, &tb);
   p->ws = c.off;
   return KP_OK;
 }
@@ -623,6 +646,29 @@ kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches) {
   *total_ms = tot;
   *launches = (int64_t)ctx->events_used;
   ctx->events_used = 0;
+  return KP_OK;
+}
+
+kp_status kp_ctx_set_truncation(kp_ctx* ctx, int32_t nvars, const int32_t* weights,
+                                int64_t max_degree) {
+  if (!ctx) return KP_E_ARG;
+  if (nvars < 1 || nvars > KP_MAX_VARS || !weights)
+    return fail(ctx, KP_E_ARG, "kp_ctx_set_truncation: 1..%d weights", KP_MAX_VARS);
+  TruncSpec t{};
+  for (int v = 0; v < nvars; ++v) {
+    if (weights[v] < -(1 << 15) || weights[v] > (1 << 15))
+      return fail(ctx, KP_E_ARG, "kp_ctx_set_truncation: weights must lie in [-2^15, 2^15]");
+    t.w[v] = weights[v];
+  }
+  t.max_degree = max_degree;
+  ctx->trunc = t;
+  ctx->trunc_on = true;
+  return KP_OK;
+}
+
+kp_status kp_ctx_clear_truncation(kp_ctx* ctx) {
+  if (!ctx) return KP_E_ARG;
+  ctx->trunc_on = false;
   return KP_OK;
 }
 
@@ -859,9 +905,29 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
   c.base = static_cast<char*>(workspace);
   hipError_t e = hipSuccess;
   const bool empty = na == 0 || nb == 0 || layout->nkeys == 0;
+  // the truncation tables sit after the mode's workspace (as planned)
+  TruncBufs tr{};
+  {
+    Carver t = c;
+    if (p.mode == KP_DENSE) {
+      carve_dense<false>(t, p, na, nb, nullptr);
+    } else {
+      HashCarve h;
+      carve_hash(t, p, 0, na, nb, &h);
+    }
+    carve_trunc(t, p, na, nb, &tr);
+    if (p.trunc && !empty)
+      e = launch_degrees(make_dev_layout(*layout, 0), make_dev_layout(*layout, 1), ctx->trunc, na,
+                         nb, a_codes, b_codes, tr.sa, tr.tb, &ctx->status->err, stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent truncation tables");
+  }
   if (p.mode == KP_DENSE) {
     DenseBufs B{};
     carve_dense<true>(c, p, na, nb, &B);
+    B.a_sa_in = tr.sa;
+    B.b_tb_in = tr.tb;
+    B.a_sa = tr.sa_sorted;
+    B.b_tb = tr.tb_sorted;
     B.a_keys_in = a_codes;
     B.a_coef_in = (const int64_t*)a_coef;
     B.b_keys_in = b_codes;
@@ -890,6 +956,8 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
     carve_hash(c, p, 0, na, nb, &h);
     HashBufs H{h.meta, h.table, p.cap, p.cap, out_codes, out_coef, out_cap,
                nullptr, nullptr, hash_stats_ptr(ctx)};
+    H.a_sa = tr.sa;
+    H.b_tb = tr.tb;
     if (!empty && timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
     if (!empty && p.radix) {
@@ -899,6 +967,8 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       RadixArgs R{a_codes, a_coef, na, b_codes, b_coef, nb, 0, PoissonPrep{}, p.rows, p.l1,
                   p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_codes,
                   out_coef, out_cap, H.stats, H.ev0, H.ev1};
+      R.a_sa = tr.sa;
+      R.b_tb = tr.tb;
       if (e == hipSuccess) e = launch_radix(R, dtype == KP_F64 ? 1 : 0, stream);
     } else if (!empty) {
       if (e == hipSuccess && dtype == KP_I64)
@@ -926,6 +996,8 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
   if (!ctx) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   if (layout && layout->ny == 0) return fail(ctx, KP_E_ARG, "kp_mul_poisson: layout has ny == 0");
+  if (ctx->trunc_on)
+    return fail(ctx, KP_E_ARG, "truncation by degree applies to Laurent products only");
   Plan p;
   kp_status st = make_plan(ctx, layout, 1, KP_F64, mode, na, nb, &p);
   if (st != KP_OK) return st;

@@ -255,6 +255,42 @@ __device__ __forceinline__ uint32_t encode_row(const DevLayout& L, int64_t r,
   return e;
 }
 
+// Weighted degree sum_v w_v e_v of a factor term from its code (digits over
+// the product widths, offset by the factor's box minimum).
+__device__ __forceinline__ int64_t code_degree(const DevLayout& L, uint64_t q, const int32_t* w) {
+  int64_t deg = 0;
+  for (int v = 0; v < L.nx; ++v) {
+    const uint64_t qq = fdiv(q, L.dx[v]);
+    deg += (int64_t)w[v] * ((int64_t)(q - qq * L.dx[v].d) + L.fmin[v]);
+    q = qq;
+  }
+  return deg;
+}
+
+// Truncation tables: for a term of A its slack D - deg, for a term of B its
+// degree, both as int32 (a pair is kept iff deg_b <= slack_a).  Exact while
+// every |deg| <= 2^30, else ERR_RANGE; slacks outside int32 are clamped
+// (they then decide the same way for every |deg_b| <= 2^30).
+__global__ void __launch_bounds__(CODEC_BLOCK)
+k_degrees(DevLayout LA, DevLayout LB, TruncSpec T, int64_t na, int64_t nb,
+          const int64_t* __restrict__ ak, const int64_t* __restrict__ bk,
+          int32_t* __restrict__ sa, int32_t* __restrict__ tb, uint32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t e = 0;
+  constexpr int64_t LIM = (int64_t)1 << 30;
+  if (i < na) {
+    const int64_t d = code_degree(LA, (uint64_t)ak[i], T.w);
+    if (d > LIM || d < -LIM) e = ERR_RANGE;
+    sa[i] = (int32_t)max((int64_t)INT_MIN, min((int64_t)INT_MAX, T.max_degree - d));
+  } else if (i < na + nb) {
+    const int64_t d = code_degree(LB, (uint64_t)bk[i - na], T.w);
+    if (d > LIM || d < -LIM) e = ERR_RANGE;
+    tb[i - na] = (int32_t)max(-LIM, min(LIM, d));
+  }
+  const uint32_t any = wave_or(e);
+  if (any && (threadIdx.x & 63) == 0) atomicOr(err, any);
+}
+
 // Both factors in one launch: rows [0, na) of A, then [na, na + nb) of B.
 __global__ void __launch_bounds__(CODEC_BLOCK)
 k_encode2(DevLayout LA, DevLayout LB, int64_t na, int64_t nb, const int32_t* __restrict__ ax,
@@ -407,6 +443,15 @@ hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* ou
     int g = grid_for(n, CODEC_BLOCK, 2048);
     hipLaunchKernelGGL(k_minmax, dim3(g), dim3(CODEC_BLOCK), 0, s, n, nv, vals, out);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_degrees(const DevLayout& LA, const DevLayout& LB, const TruncSpec& T, int64_t na,
+                          int64_t nb, const int64_t* ak, const int64_t* bk, int32_t* sa,
+                          int32_t* tb, uint32_t* err, hipStream_t s) {
+  if (na + nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_degrees, dim3(grid_for(na + nb, CODEC_BLOCK, INT_MAX)), dim3(CODEC_BLOCK), 0,
+                     s, LA, LB, T, na, nb, ak, bk, sa, tb, err);
   return hipGetLastError();
 }
 

@@ -185,6 +185,8 @@ struct PrepSeg {
   int64_t* tmax;
   int64_t* zero;          // array cleared by this workgroup (chunk counts), may be null
   int64_t nzero;
+  const int32_t* deg_in;  // optional truncation table (slack of A / degree of B), input order
+  int32_t* deg_out;       // the same in bucket-sorted order
 };
 struct PrepArgs {
   PrepSeg seg[2];
@@ -302,6 +304,7 @@ __global__ void __launch_bounds__(SCATTER_BLOCK) k_dense_scatter(PrepArgs args, 
   const int64_t pos = sg.bstart[bucket_of(k, sg.shift, sg.nbk - 1)] + sg.rank[i];
   sg.out_pk[pos] = (uint64_t)(uint32_t)k | ((uint64_t)(uint32_t)c << 32);
   sg.out_coef[pos] = (uint64_t)c;
+  if (sg.deg_out) sg.deg_out[pos] = sg.deg_in[i];
   if (isB) {
     const int64_t t = pos / DENSE_TILE, code = (int64_t)(uint32_t)k;
     __hip_atomic_fetch_min(&sg.tmin[t], code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -609,6 +612,8 @@ struct MulArgs {
   int64_t* stage_k;
   int64_t* stage_c;
   int64_t* ccount;
+  const int32_t* a_sa;   // optional truncation: slack of each row of A (sorted order)
+  const int32_t* b_tb;   // and degree of each term of B; a pair is kept iff tb <= sa
 };
 
 template <int U>
@@ -642,11 +647,12 @@ struct Coef {
 // One instruction of an item: row 4U + g of the item against this lane's term.
 // Window byte offsets are relative to the window's LDS base, which is added
 // last (it folds into the instruction's offset field).
-template <typename T, int MUL, bool EDGE, int U>
+template <typename T, int MUL, bool EDGE, bool TRUNC, int U>
 __device__ __forceinline__ void pair_step(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
-                                          const Coef<T, MUL>& c) {
+                                          const Coef<T, MUL>& c, uint32_t sa, int32_t tb) {
   uint32_t rel = bcast16<U>(a8) + off8;
   if (EDGE) rel = min(rel, lim);
+  if (TRUNC && (int32_t)bcast16<U>(sa) < tb) rel = lim;   // over the degree limit: discard
   rel += base;
   T v;
   if constexpr (MUL == 4) {
@@ -669,11 +675,11 @@ __device__ __forceinline__ void pair_step(uint32_t a8, uint32_t off8, uint32_t l
   lds_add(rel, v);
 }
 
-template <typename T, int MUL, bool EDGE, int... U>
+template <typename T, int MUL, bool EDGE, bool TRUNC, int... U>
 __device__ __forceinline__ void item_steps(std::integer_sequence<int, U...>, uint32_t a8,
                                            uint32_t off8, uint32_t lim, uint32_t base,
-                                           const Coef<T, MUL>& c) {
-  (pair_step<T, MUL, EDGE, U>(a8, off8, lim, base, c), ...);
+                                           const Coef<T, MUL>& c, uint32_t sa, int32_t tb) {
+  (pair_step<T, MUL, EDGE, TRUNC, U>(a8, off8, lim, base, c, sa, tb), ...);
 }
 
 struct ItemRegs {
@@ -681,9 +687,10 @@ struct ItemRegs {
   bool core;
   uint64_t a, b;     // packed rows / terms
   uint64_t ac, bc;   // coefficient words (wide kinds)
+  int32_t sa, tb;    // truncation: slack of this lane's row, degree of its term
 };
 
-template <bool WIDE>
+template <bool WIDE, bool TRUNC>
 __device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane, int rowlane,
                                            ItemRegs& x) {
   const uint32_t lo = (uint32_t)d, hi = (uint32_t)((uint64_t)d >> 32);
@@ -699,9 +706,13 @@ __device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane
     x.bc = M.bc[j];
     x.ac = M.ac[r];
   }
+  if (TRUNC) {
+    x.sa = M.a_sa[r];
+    x.tb = M.b_tb[j];
+  }
 }
 
-template <typename T, int MUL>
+template <typename T, int MUL, bool TRUNC>
 __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t lim, int lane,
                                          int rowlane, int64_t nb, uint32_t base) {
   const bool vb = x.t * DENSE_TILE + (lane & 15) < nb;
@@ -722,14 +733,16 @@ __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t 
     __builtin_memcpy(&c.bw, &x.bc, 8);
   }
   if (x.core)
-    item_steps<T, MUL, false>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c);
+    item_steps<T, MUL, false, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c,
+                                     (uint32_t)x.sa, x.tb);
   else
-    item_steps<T, MUL, true>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c);
+    item_steps<T, MUL, true, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c,
+                                    (uint32_t)x.sa, x.tb);
 }
 
 // Items [ib, ie) of the task, wavefront w taking ib + w, ib + w + NW, ...;
 // the next item's rows and terms are loaded while the current one runs.
-template <typename T, int MUL, int BS>
+template <typename T, int MUL, int BS, bool TRUNC>
 __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t ie, int64_t L,
                                           uint32_t S8, uint32_t base) {
   constexpr int NW = BS / 64;
@@ -747,14 +760,14 @@ __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t 
     // two register sets in turn, so that no load result is copied (a copy
     // would wait for the load)
     ItemRegs x0, x1;
-    fetch_item<WIDE>(M, readlane64(dv, 0), lane, rowlane, x0);
+    fetch_item<WIDE, TRUNC>(M, readlane64(dv, 0), lane, rowlane, x0);
     for (int k = 0; k + 1 < cnt; k += 2) {
-      fetch_item<WIDE>(M, readlane64(dv, k + 1), lane, rowlane, x1);
-      run_item<T, MUL>(x0, L, lim, lane, rowlane, M.nb, base);
-      fetch_item<WIDE>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, rowlane, x0);
-      run_item<T, MUL>(x1, L, lim, lane, rowlane, M.nb, base);
+      fetch_item<WIDE, TRUNC>(M, readlane64(dv, k + 1), lane, rowlane, x1);
+      run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base);
+      fetch_item<WIDE, TRUNC>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, rowlane, x0);
+      run_item<T, MUL, TRUNC>(x1, L, lim, lane, rowlane, M.nb, base);
     }
-    if (cnt & 1) run_item<T, MUL>(x0, L, lim, lane, rowlane, M.nb, base);
+    if (cnt & 1) run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base);
   }
 }
 
@@ -815,6 +828,7 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
   // the per-pair address arithmetic carries no base.
   constexpr uint32_t base = 0;
   const uint32_t narrow = M.meta->seg_flags[0] & M.meta->seg_flags[1];
+  const bool trunc = M.a_sa != nullptr;
   const int64_t* ibase = M.win_ibase;
   for (int64_t w = M.task_w[task]; w < M.nwin; ++w) {
     const int64_t wb = ibase[w], we = ibase[w + 1];
@@ -830,12 +844,15 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
     __syncthreads();
     const uint32_t S8 = (uint32_t)(Sw * 8);
     if constexpr (std::is_same<T, double>::value) {
-      run_items<T, 3, BS>(M, pb, pe, L, S8, base);
+      if (trunc) run_items<T, 3, BS, true>(M, pb, pe, L, S8, base);
+      else run_items<T, 3, BS, false>(M, pb, pe, L, S8, base);
+    } else if (trunc) {   // truncated products: one (int64) coefficient kind
+      run_items<T, 0, BS, true>(M, pb, pe, L, S8, base);
     } else {
-      if (narrow & 4u) run_items<T, 4, BS>(M, pb, pe, L, S8, base);
-      else if (narrow & 2u) run_items<T, 2, BS>(M, pb, pe, L, S8, base);
-      else if (narrow & 1u) run_items<T, 1, BS>(M, pb, pe, L, S8, base);
-      else run_items<T, 0, BS>(M, pb, pe, L, S8, base);
+      if (narrow & 4u) run_items<T, 4, BS, false>(M, pb, pe, L, S8, base);
+      else if (narrow & 2u) run_items<T, 2, BS, false>(M, pb, pe, L, S8, base);
+      else if (narrow & 1u) run_items<T, 1, BS, false>(M, pb, pe, L, S8, base);
+      else run_items<T, 0, BS, false>(M, pb, pe, L, S8, base);
     }
     __syncthreads();
     flush_window<T, BS>(M, win, L, Sw, !M.accumulate && pb == wb && pe == we);
@@ -1035,9 +1052,9 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   if (e0 != hipSuccess) return e0;
   PrepArgs pa{};
   pa.seg[0] = PrepSeg{B.a_keys_in, B.a_coef_in, B.na, P.shiftA, P.nbkA, P.maxcodeA, B.apk, B.ac,
-                      B.rank_a, B.bstart, nullptr, nullptr, nullptr, 0};
+                      B.rank_a, B.bstart, nullptr, nullptr, nullptr, 0, B.a_sa_in, B.a_sa};
   pa.seg[1] = PrepSeg{B.b_keys_in, B.b_coef_in, B.nb, P.shiftB, P.nbkB, P.maxcodeB, B.bpk, B.bc,
-                      B.rank_b, B.bstartB, B.tmin, B.tmax, B.ccount, P.nchunk};
+                      B.rank_b, B.bstartB, B.tmin, B.tmax, B.ccount, P.nchunk, B.b_tb_in, B.b_tb};
   pa.meta = B.meta;
   pa.is_i64 = dt == KP_I64;
   const size_t hist_bytes = (size_t)std::max(P.nbkA, P.nbkB) * 4;
@@ -1058,7 +1075,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   const int64_t W1 = P.nwin + 1;
   MulArgs ma{B.meta, B.apk, B.ac, B.bpk, B.bc, B.nb, P.S, P.nwin, P.nkeys, B.items, B.task_w,
              B.task_begin, B.win + W_IBASE * W1, P.accumulate, B.dense, B.stage_k, B.stage_c,
-             B.ccount};
+             B.ccount, B.a_sa_in ? B.a_sa : nullptr, B.b_tb_in ? B.b_tb : nullptr};
   const size_t lds = (size_t)(P.S + DENSE_DUMMY) * 8;
   const unsigned grid = (unsigned)P.max_tasks;
   if (B.ev0) (void)hipEventRecord(B.ev0, s);

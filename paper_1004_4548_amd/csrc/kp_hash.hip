@@ -142,7 +142,8 @@ __global__ void __launch_bounds__(HASH_BLOCK)
 k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Meta* meta,
                const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
                const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows,
-               unsigned long long* stats) {
+               unsigned long long* stats, const int32_t* __restrict__ a_sa,
+               const int32_t* __restrict__ b_tb) {
   constexpr int NB = 4;
   const int64_t j0 = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows;
@@ -152,6 +153,7 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
   const int64_t j = live ? j0 : nb - 1;   // idle lanes stay for the statistics reduction
   const int64_t bj = bk[j];
   const T cb = bc[j];
+  const int32_t tb = b_tb ? b_tb[j] : INT_MIN;
   int64_t ins = 0, extra = 0;
   for (int64_t i = live ? i0 : i1; i < i1; i += NB) {
     int64_t code[NB];
@@ -163,7 +165,7 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
       const int64_t r = in ? i + u : i;
       v[u] = mul_coef<T>(ac[r], cb, narrow);
       code[u] = ak[r] + bj;
-      on[u] = in && v[u] != T(0);
+      on[u] = in && v[u] != T(0) && (!a_sa || tb <= a_sa[r]);
       ins += on[u];
     }
     extra += table_insert_n<T, NB>(table, cap, max_probe, code, v, on, &meta->err);
@@ -371,7 +373,9 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
     const T* ac = static_cast<const T*>(R.ac);
     const int64_t bj = R.bk[j];
     const T cb = static_cast<const T*>(R.bc)[j];
+    const int32_t tb = R.a_sa ? R.b_tb[j] : INT_MIN;
     for (int64_t i = i0; i < i1; ++i) {
+      if (R.a_sa && tb > R.a_sa[i]) continue;   // over the degree limit
       const T v = mul_coef<T>(ac[i], cb, narrow);
       if (v == T(0)) continue;
       int64_t bits;
@@ -421,10 +425,12 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
     const T* ac = static_cast<const T*>(R.ac);
     const int64_t bj = R.bk[j];
     const T cb = static_cast<const T*>(R.bc)[j];
+    const int32_t tb = R.a_sa ? R.b_tb[j] : INT_MIN;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t i = r0 + u;
       if (i >= r1) break;
+      if (R.a_sa && tb > R.a_sa[i]) continue;   // over the degree limit
       const T v = mul_coef<T>(ac[i], cb, narrow);
       if (v == T(0)) continue;
       code[u] = R.ak[i] + bj;
@@ -779,11 +785,11 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
   if (dt == KP_F64)
     hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const double*)ac, na, bk,
-                       (const double*)bc, nb, rows, H.stats);
+                       (const double*)bc, nb, rows, H.stats, H.a_sa, H.b_tb);
   else
     hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk,
-                       (const int64_t*)bc, nb, rows, H.stats);
+                       (const int64_t*)bc, nb, rows, H.stats, H.a_sa, H.b_tb);
   if (H.ev1) (void)hipEventRecord(H.ev1, s);
   return hipGetLastError();
 }

@@ -80,6 +80,16 @@ struct DevLayout {
 
 DevLayout make_dev_layout(const kp_layout& L, int which);
 
+// Truncation by weighted degree: keep product terms with
+// sum_v w[v] e[v] <= max_degree.
+struct TruncSpec {
+  int32_t w[KP_MAX_VARS];
+  int64_t max_degree;
+};
+hipError_t launch_degrees(const DevLayout& LA, const DevLayout& LB, const TruncSpec& T, int64_t na,
+                          int64_t nb, const int64_t* ak, const int64_t* bk, int32_t* sa,
+                          int32_t* tb, uint32_t* err, hipStream_t s);
+
 // Per-term code map.  Returns an error bit (0 when fine).
 __host__ __device__ inline uint32_t encode_term(const DevLayout& L, const int32_t* e,
                                                 const int32_t* j, int is_sin, int64_t* kx,
@@ -275,6 +285,9 @@ struct DenseBufs {
   // instead of codes
   int32_t* out_exps;
   DevLayout dec;
+  // optional truncation tables (input order) and their bucket-sorted copies
+  const int32_t* a_sa_in; const int32_t* b_tb_in;
+  int32_t* a_sa; int32_t* b_tb;
 };
 hipError_t dense_setup();
 hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype dt, hipStream_t s);
@@ -288,6 +301,8 @@ struct HashBufs {
   int64_t* out_k; void* out_c; int64_t out_cap;
   hipEvent_t ev0, ev1;   // optional: recorded around the insert kernel
   unsigned long long* stats;   // optional: {insertions, extra probe steps}
+  const int32_t* a_sa;   // optional truncation: slack of A's terms, degree of B's
+  const int32_t* b_tb;
 };
 hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
                                int64_t na, const int64_t* bk, const void* bc, int64_t nb,
@@ -322,6 +337,8 @@ struct RadixArgs {
   int64_t* out_k; void* out_c; int64_t out_cap;
   unsigned long long* stats;
   hipEvent_t ev0, ev1;   // optional: recorded around the whole accumulation
+  const int32_t* a_sa;   // optional truncation (Laurent): a pair is generated iff
+  const int32_t* b_tb;   // b_tb[j] <= a_sa[i]
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);

@@ -67,6 +67,7 @@ def _fresh_ctx():
     ctx = kp.context()
     saved = ctx.tune
     yield
+    ctx.clear_truncation()
     ctx.set_tune(**{f: getattr(saved, f) for f, _ in kp.Tune._fields_})
 
 
@@ -567,3 +568,68 @@ def test_mp_sparse_benchmark():
     sel = rng.integers(0, len(gc), 200)
     w, _, _ = O.laurent_coeff_at(f[0], f[1], g[0], g[1], ge[sel])
     np.testing.assert_array_equal(gc[sel], w)
+
+
+# ------------------------------------------------------------------ truncation
+def _trunc_cases():
+    out = []
+    a, b = I.config(2, scale=0.2)
+    out.append(("simplex, total degree <= 20", a, b, [1, 1, 1, 1], 20))
+    out.append(("simplex fp64, degree in x0, x2 <= 9",
+                (a[0], a[1].astype(np.float64) / 8), (b[0], b[1].astype(np.float64)),
+                [1, 0, 1, 0], 9))
+    a, b = I.config(1, scale=0.6)
+    out.append(("box, weights (2, -1, 1) <= 3", a, b, [2, -1, 1], 3))
+    a, b = I.config(3, scale=0.04)
+    out.append(("sparse, total degree <= 240", a, b, [1] * 6, 240))
+    return out
+
+
+@pytest.mark.parametrize("mode,part", [("dense", 0), ("hash", 0), ("hash", 2)])
+def test_truncated_products_match_oracle(mode, part):
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=part)
+    for what, a, b, w, D in _trunc_cases():
+        if mode == "dense" and "sparse" in what:
+            continue
+        say("truncated", what, mode, part)
+        with ctx.truncation(w, D):
+            ge, gc, _ = gpu_laurent(a, b, mode, ctx)
+        oe, oc, oab = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], w, D, threads=4)
+        assert len(oc) > 0
+        if np.asarray(a[1]).dtype == np.float64:
+            assert_tolerance([ge], gc, [oe], oc, oab, TOL, what)
+        else:
+            assert_exact([ge], gc, [oe], oc, what)
+
+
+def test_truncation_codes_path_and_errors():
+    torch = _torch()
+    ctx = kp.context()
+    a, b = I.config(1, scale=0.4)
+    lay = kp.layout_product(3, 0, a[0].min(0), a[0].max(0), b[0].min(0), b[0].max(0))
+    ka, _ = kp.encode(lay, 0, dev(a[0]))
+    kb, _ = kp.encode(lay, 1, dev(b[0]))
+    say("truncated codes path")
+    with ctx.truncation([1, 1, 1], 0):
+        codes, coef, _ = kp.mul_laurent_codes(lay, ka, dev(a[1]), kb, dev(b[1]), "dense")
+        ex = kp.decode(lay, codes).cpu().numpy()
+    oe, oc, _ = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [1, 1, 1], 0)
+    assert_exact([ex], coef.cpu().numpy(), [oe], oc, "codes path, degree <= 0")
+    # a factor degree past 2^30 is reported, not silently wrong
+    big = (np.array([[40000], [1]], np.int32), np.array([1, 2], np.int64))
+    pa, pb = kp.Poly(dev(big[0]), dev(big[1])), kp.Poly(dev(big[0]), dev(big[1]))
+    with ctx.truncation([1 << 15], 10):
+        with pytest.raises(kp.KPError) as e:
+            kp.mul_laurent(pa, pb, ctx=ctx)
+    assert e.value.status == kp.KP_E_RANGE
+    ctx.sync_check()
+    # Poisson products do not take a degree truncation
+    p4a, p4b = I.config(4, scale=0.01)
+    with ctx.truncation([1, 1, 1], 5):
+        with pytest.raises(kp.KPError) as e:
+            gpu_poisson(p4a, p4b)
+    assert e.value.status == kp.KP_E_ARG
+    # cleared: the full product again
+    r, _ = kp.mul_laurent(kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1])), ctx=ctx)
+    assert r.coef.shape[0] == len(O.laurent_mul(a[0], a[1], b[0], b[1])[1])

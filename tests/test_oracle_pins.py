@@ -9,6 +9,8 @@
   the factor 1/2), Chebyshev's recurrence, numeric evaluation at random angles
   and exact evaluation over F_{p^2}.
 * The evaluators themselves: binomial closed forms and exact field identities.
+* Truncated products (Section 3): brute force that tests every pair against
+  the degree limit before it contributes, a binomial closed form, the limits.
 """
 import math
 
@@ -340,3 +342,62 @@ def test_poisson_coeff_at_matches_full_product():
     # a key that no pair reaches
     got, _, cnt = O.poisson_coeff_at(a, b, 3, 6, [[50, 0, 0]], [[1, 0, 0, 0, 0, 0]], [0])
     assert got[0] == 0 and cnt[0] == 0
+
+
+# ------------------------------------------------------------------ truncation
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_truncated_equals_brute_force_with_pair_test(seed):
+    """Every pair tested against the limit before it contributes (the
+    efficient form a multiplier uses), in Python integers mod 2^64, equals the
+    oracle's product-then-filter."""
+    rng = np.random.default_rng(900 + seed)
+    nv = 3
+    a = (rng.integers(-3, 5, (40, nv)).astype(np.int32), rng.integers(-50, 50, 40))
+    b = (rng.integers(-2, 6, (30, nv)).astype(np.int32), rng.integers(-50, 50, 30))
+    w = [int(x) for x in rng.integers(-2, 4, nv)]
+    D = int(rng.integers(-3, 12))
+    acc = {}
+    for ea, ca in zip(a[0].tolist(), a[1].tolist()):
+        da = sum(x * y for x, y in zip(w, ea))
+        for eb, cb in zip(b[0].tolist(), b[1].tolist()):
+            if da + sum(x * y for x, y in zip(w, eb)) > D:
+                continue
+            k = tuple(x + y for x, y in zip(ea, eb))
+            acc[k] = (acc.get(k, 0) + ca * cb) % (1 << 64)
+    ref = {k: (v - (1 << 64) if v >= (1 << 63) else v) for k, v in acc.items() if v}
+    ex, co, _ = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], w, D)
+    got = {tuple(e): int(c) for e, c in zip(ex.tolist(), co.tolist())}
+    assert got == ref
+
+
+@pytest.mark.parametrize("n,m,D", [(5, 4, 6), (7, 7, 3), (6, 2, 8)])
+def test_truncated_binomial_closed_form(n, m, D):
+    """(1+x+y)^n (1+x+y)^m cut at total degree D: the multinomial coefficients
+    of (1+x+y)^(n+m) of degree <= D."""
+    def poly(k):
+        ex, co = [], []
+        for i in range(k + 1):
+            for j in range(k + 1 - i):
+                ex.append((i, j))
+                co.append(math.comb(k, i) * math.comb(k - i, j))
+        return np.array(ex, np.int32), np.array(co, np.int64)
+    a, b = poly(n), poly(m)
+    ex, co, _ = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [1, 1], D)
+    N = n + m
+    want = {(i, j): math.comb(N, i) * math.comb(N - i, j)
+            for i in range(N + 1) for j in range(N + 1 - i) if i + j <= D}
+    assert {tuple(e): int(c) for e, c in zip(ex.tolist(), co.tolist())} == want
+
+
+def test_truncated_limits():
+    rng = np.random.default_rng(77)
+    a = (rng.integers(0, 5, (25, 2)).astype(np.int32), rng.integers(1, 9, 25))
+    b = (rng.integers(0, 5, (20, 2)).astype(np.int32), rng.integers(1, 9, 20))
+    full = O.laurent_mul(a[0], a[1], b[0], b[1])
+    top = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [1, 1], 16)
+    assert np.array_equal(full[0], top[0]) and np.array_equal(full[1], top[1])
+    none = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [1, 1], -1)
+    assert len(none[1]) == 0
+    # weight 0 on a variable: only the other one is cut
+    part = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [0, 1], 3)
+    assert (part[0][:, 1] <= 3).all() and part[0][:, 0].max() > 3
