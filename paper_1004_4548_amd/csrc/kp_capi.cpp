@@ -874,15 +874,17 @@ namespace {
 
 // Queues one Laurent product (no synchronisation).  `timed`: record the
 // context's timing events around the accumulation kernel when enabled.
-// Dense-mode options of the from-exponents path: the output copy decodes
-// into `exps`, and the output scan posts the count to the mailbox under
-// `seq` (0: no post).  `fused` reports whether they were taken.
+// Options of the from-exponents path: the multiply writes decoded exponents
+// into `exps` (dense: its output copy; partitioned hash: its bins), and the
+// dense output scan posts the count to the mailbox under `seq` (0: no post).
+// `decoded` and `posted` report which were taken.
 struct ExpsOut {
   int32_t* exps;
   DevLayout dec;
   Mailbox* mb;
   uint64_t seq;
-  bool fused;
+  bool decoded;
+  bool posted;
 };
 
 kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, kp_mode mode,
@@ -941,7 +943,8 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       B.dec = xo->dec;
       B.mb = xo->seq ? xo->mb : nullptr;
       B.seq = xo->seq;
-      xo->fused = true;
+      xo->decoded = true;
+      xo->posted = xo->seq != 0;
     }
     B.ctx_err = &ctx->status->err;
     if (!empty) {
@@ -969,6 +972,11 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
                   out_coef, out_cap, H.stats, H.ev0, H.ev1};
       R.a_sa = tr.sa;
       R.b_tb = tr.tb;
+      if (xo) {
+        R.out_x = xo->exps;
+        R.dec = xo->dec;
+        xo->decoded = true;
+      }
       if (e == hipSuccess) e = launch_radix(R, dtype == KP_F64 ? 1 : 0, stream);
     } else if (!empty) {
       if (e == hipSuccess && dtype == KP_I64)
@@ -1168,18 +1176,19 @@ kp_status kp_mul_laurent_exps(kp_ctx* ctx, const kp_layout* layout, kp_dtype dty
   // dense mode decodes in its output copy and posts the count from its
   // output scan, so the host wakes before the copy has run
   const bool sync = !(flags & KP_FLAG_ASYNC);
-  ExpsOut xo{out_exps, make_dev_layout(*layout, 0), ctx->mb_dev, sync ? next_seq(ctx) : 0, false};
+  ExpsOut xo{out_exps, make_dev_layout(*layout, 0), ctx->mb_dev, sync ? next_seq(ctx) : 0, false,
+             false};
   st = enqueue_laurent(ctx, layout, dtype, mode, ka, a_coef, na, kb, b_coef, nb, oc, out_coef,
                        ncodes, out_n, static_cast<char*>(workspace) + c.off,
                        workspace_bytes - c.off, stream, true, &xo);
   if (st != KP_OK) return st;
-  if (!xo.fused) {
+  if (!xo.decoded) {
     e = launch_decode_n(make_dev_layout(*layout, 0), 0, out_n, ncodes, oc, out_exps, nullptr,
                         nullptr, &ctx->status->err, stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_laurent_exps decode");
   }
   if (!sync) return finish(ctx, flags, stream, "kp_mul_laurent_exps");
-  return wait_count(ctx, out_n, n_host, stream, "kp_mul_laurent_exps", xo.fused ? xo.seq : 0);
+  return wait_count(ctx, out_n, n_host, stream, "kp_mul_laurent_exps", xo.posted ? xo.seq : 0);
 }
 
 kp_status kp_mul_laurent_auto(kp_ctx* ctx, int32_t nvars, kp_dtype dtype, kp_mode mode,

@@ -765,7 +765,13 @@ __global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
       const int i = r * BIN_BLOCK + tid;
       const int64_t q = pos + __popcll(ball[r] & lt);
       if (q < R.out_cap) {
-        R.out_k[q] = (int64_t)(keys[i] - 1);
+        if (R.out_x) {
+          int32_t ex[KP_MAX_VARS];
+          decode_x(R.dec, (uint64_t)(keys[i] - 1), ex);
+          for (int v = 0; v < R.dec.nx; ++v) R.out_x[q * R.dec.nx + v] = ex[v];
+        } else {
+          R.out_k[q] = (int64_t)(keys[i] - 1);
+        }
         out_c[q] = vals[i];
       }
     }

@@ -339,6 +339,8 @@ struct RadixArgs {
   hipEvent_t ev0, ev1;   // optional: recorded around the whole accumulation
   const int32_t* a_sa;   // optional truncation (Laurent): a pair is generated iff
   const int32_t* b_tb;   // b_tb[j] <= a_sa[i]
+  int32_t* out_x;        // optional (Laurent): decoded exponents instead of codes
+  DevLayout dec;
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
