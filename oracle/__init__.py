@@ -13,6 +13,8 @@ out of that library.
 Every function here is pinned by ``tests/test_oracle_pins.py``:
   * ``laurent_mul``      -- n-D convolution, Fateman closed form, mod-p
                             evaluation of the Monagan-Pearce benchmark;
+  * ``laurent_mul(..., exact=True)`` -- brute force in Python integers, the
+                            closed form of scaled Fateman-type products;
   * ``laurent_mul_truncated`` -- brute force with the degree test on each
                             pair, a binomial closed form, the limiting cuts;
   * ``poisson_mul``      -- trigonometric identities, numeric evaluation at
@@ -111,13 +113,17 @@ def hardware_threads() -> int:
     return int(_load().oracle_hardware_threads())
 
 
-def laurent_mul(a_exps, a_coef, b_exps, b_coef, row_begin=0, row_end=-1, threads=1):
+def laurent_mul(a_exps, a_coef, b_exps, b_coef, row_begin=0, row_end=-1, threads=1,
+                exact=False):
     """Product of two Laurent polynomials given as (exponents[n, nv], coef[n]).
 
-    Coefficients are int64 (wrapping mod 2^64) or float64.  Returns
-    ``(exps[m, nv] int32, coef[m], abs_sum[m] or None)`` sorted by exponent
-    tuple.  int64 results omit zero terms; float64 results keep every touched
-    key (with its sum of |contributions|).
+    Coefficients are int64 (wrapping mod 2^64) or float64.  With
+    ``exact=True`` (int64 factors) every product and sum is formed in signed
+    128-bit integers and ``coef`` is int64[m, 2]: the low and the high word of
+    each two's complement value (``wide_to_int`` turns them into Python
+    integers).  Returns ``(exps[m, nv] int32, coef, abs_sum[m] or None)``
+    sorted by exponent tuple.  Integer results omit zero terms; float64
+    results keep every touched key (with its sum of |contributions|).
     Only A's rows [row_begin, row_end) take part (for bounded timing samples).
     """
     lib = _load()
@@ -127,6 +133,9 @@ def laurent_mul(a_exps, a_coef, b_exps, b_coef, row_begin=0, row_end=-1, threads
     ac, dt = _coef(a_coef)
     bc, dt2 = _coef(b_coef)
     assert dt == dt2, "both factors need the same coefficient type"
+    if exact:
+        assert dt == 0, "exact products take int64 coefficients"
+        dt = 2
     h = lib.oracle_laurent_mul(nv, dt, ae.shape[0], _ptr(ae), _ptr(ac), be.shape[0], _ptr(be),
                                _ptr(bc), row_begin, row_end, threads)
     if not h:
@@ -134,8 +143,9 @@ def laurent_mul(a_exps, a_coef, b_exps, b_coef, row_begin=0, row_end=-1, threads
     try:
         n = lib.oracle_laurent_len(h)
         ex = np.empty((n, nv), dtype=np.int32)
-        co = np.empty(n, dtype=np.float64 if dt else np.int64)
-        ab = np.empty(n, dtype=np.float64) if dt else None
+        co = (np.empty((n, 2), dtype=np.int64) if dt == 2 else
+              np.empty(n, dtype=np.float64 if dt else np.int64))
+        ab = np.empty(n, dtype=np.float64) if dt == 1 else None
         lib.oracle_laurent_get(h, _ptr(ex), _ptr(co), _ptr(ab))
     finally:
         lib.oracle_laurent_free(h)
@@ -155,10 +165,11 @@ def laurent_mul_truncated(a_exps, a_coef, b_exps, b_coef, weights, max_degree, t
     return ex[keep], co[keep], (ab[keep] if ab is not None else None)
 
 
-def laurent_coeff_at(a_exps, a_coef, b_exps, b_coef, q_exps):
+def laurent_coeff_at(a_exps, a_coef, b_exps, b_coef, q_exps, exact=False):
     """Coefficient of each queried monomial of A*B, computed one by one.
 
-    Returns ``(coef[q], abs_sum[q] or None, n_contributions[q])``.
+    Returns ``(coef[q], abs_sum[q] or None, n_contributions[q])``; with
+    ``exact=True`` coef is int64[q, 2] as in ``laurent_mul``.
     """
     lib = _load()
     ae, be = _exps(a_exps), _exps(b_exps)
@@ -166,13 +177,23 @@ def laurent_coeff_at(a_exps, a_coef, b_exps, b_coef, q_exps):
     qe = _exps(q_exps, nv)
     ac, dt = _coef(a_coef)
     bc, _ = _coef(b_coef)
+    if exact:
+        assert dt == 0, "exact products take int64 coefficients"
+        dt = 2
     nq = qe.shape[0]
-    co = np.empty(nq, dtype=np.float64 if dt else np.int64)
-    ab = np.empty(nq, dtype=np.float64) if dt else None
+    co = (np.empty((nq, 2), dtype=np.int64) if dt == 2 else
+          np.empty(nq, dtype=np.float64 if dt else np.int64))
+    ab = np.empty(nq, dtype=np.float64) if dt == 1 else None
     cnt = np.empty(nq, dtype=np.int64)
     lib.oracle_laurent_coeff_at(nv, dt, ae.shape[0], _ptr(ae), _ptr(ac), be.shape[0], _ptr(be),
                                 _ptr(bc), nq, _ptr(qe), _ptr(co), _ptr(ab), _ptr(cnt))
     return co, ab, cnt
+
+
+def wide_to_int(words):
+    """Python integers of int64[m, 2] (low word, high word) 128-bit values."""
+    w = np.asarray(words, dtype=np.int64).reshape(-1, 2)
+    return [int(lo) % (1 << 64) + (int(hi) << 64) for lo, hi in w]
 
 
 def _series(s, nx, ny):

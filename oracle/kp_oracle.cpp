@@ -19,6 +19,10 @@
 // Arithmetic conventions
 //   int64 coefficients: products and sums wrap modulo 2^64 (computed in
 //     uint64_t, converted back at the end).
+//   exact (dtype 2): int64 coefficients whose products and sums are formed in
+//     signed 128-bit integers (__int128); nothing wraps while the true sum
+//     fits 127 bits.  Coefficients are returned as two int64 words
+//     (low word, then high word, two's complement).
 //   fp64 coefficients: each output term carries a Neumaier-compensated sum and
 //     the sum of the absolute values of its contributions (used by the parity
 //     tolerance |gpu - oracle| <= tol * abs_sum).
@@ -52,6 +56,11 @@ struct AccI64 {
   void add(uint64_t x) { v += x; }
 };
 
+struct AccI128 {
+  __int128 v = 0;
+  void add(__int128 x) { v += x; }
+};
+
 // Neumaier's improvement of Kahan summation; abs is the sum of |contribution|.
 struct AccF64 {
   double s = 0.0, c = 0.0, abs = 0.0;
@@ -80,9 +89,10 @@ using PKey = std::array<int32_t, 2 * MAXV + 1>;     // x exps, trig mults, sin f
 
 struct ResultL {
   int nv = 0;
-  int dtype = 0;  // 0 int64, 1 fp64
+  int dtype = 0;  // 0 int64, 1 fp64, 2 exact (128-bit)
   std::map<LKey, AccI64> mi;
   std::map<LKey, AccF64> mf;
+  std::map<LKey, AccI128> mw;
 };
 
 struct ResultP {
@@ -108,6 +118,8 @@ void laurent_rows(ResultL& r, int64_t r0, int64_t r1, const int32_t* ae, const v
       if (r.dtype == 0) {
         uint64_t x = (uint64_t)((const int64_t*)ac)[i] * (uint64_t)((const int64_t*)bc)[j];
         r.mi[k].add(x);
+      } else if (r.dtype == 2) {
+        r.mw[k].add((__int128)((const int64_t*)ac)[i] * (__int128)((const int64_t*)bc)[j]);
       } else {
         double x = ((const double*)ac)[i] * ((const double*)bc)[j];
         r.mf[k].add(x);
@@ -278,7 +290,7 @@ extern "C" {
 void* oracle_laurent_mul(int nv, int dtype, int64_t na, const int32_t* a_exps, const void* a_coef,
                          int64_t nb, const int32_t* b_exps, const void* b_coef,
                          int64_t row_begin, int64_t row_end, int nthreads) {
-  if (nv < 0 || nv > MAXV || (dtype != 0 && dtype != 1)) return nullptr;
+  if (nv < 0 || nv > MAXV || dtype < 0 || dtype > 2) return nullptr;
   if (row_end < 0 || row_end > na) row_end = na;
   if (row_begin < 0) row_begin = 0;
   if (nthreads < 1) nthreads = 1;
@@ -302,19 +314,31 @@ void* oracle_laurent_mul(int nv, int dtype, int64_t na, const int32_t* a_exps, c
   for (int t = 0; t < nthreads; ++t) {
     if (dtype == 0)
       for (auto& kv : part[t].mi) res->mi[kv.first].add(kv.second.v);
+    else if (dtype == 2)
+      for (auto& kv : part[t].mw) res->mw[kv.first].add(kv.second.v);
     else
       for (auto& kv : part[t].mf) res->mf[kv.first].merge(kv.second);
   }
   return res;
 }
 
-// Number of terms: int64 drops exact zeros, fp64 keeps every key touched.
+// Number of terms: integer results drop exact zeros, fp64 keeps every key touched.
 int64_t oracle_laurent_len(void* h) {
   auto* r = (ResultL*)h;
   if (r->dtype == 1) return (int64_t)r->mf.size();
   int64_t n = 0;
-  for (auto& kv : r->mi) n += kv.second.v != 0;
+  if (r->dtype == 2)
+    for (auto& kv : r->mw) n += kv.second.v != 0;
+  else
+    for (auto& kv : r->mi) n += kv.second.v != 0;
   return n;
+}
+
+// Two int64 words (low, high) of a 128-bit two's complement value.
+void put_i128(__int128 v, int64_t* out) {
+  const unsigned __int128 u = (unsigned __int128)v;
+  out[0] = (int64_t)(uint64_t)u;
+  out[1] = (int64_t)(uint64_t)(u >> 64);
 }
 
 // Key-sorted (lexicographic on exponent 0, 1, ...) result.  abs_sum may be
@@ -328,6 +352,13 @@ void oracle_laurent_get(void* h, int32_t* exps, void* coef, double* abs_sum) {
       if (kv.second.v == 0) continue;
       for (int v = 0; v < nv; ++v) exps[t * nv + v] = kv.first[v];
       ((int64_t*)coef)[t] = (int64_t)kv.second.v;
+      ++t;
+    }
+  } else if (r->dtype == 2) {
+    for (auto& kv : r->mw) {
+      if (kv.second.v == 0) continue;
+      for (int v = 0; v < nv; ++v) exps[t * nv + v] = kv.first[v];
+      put_i128(kv.second.v, (int64_t*)coef + 2 * t);
       ++t;
     }
   } else {
@@ -352,6 +383,7 @@ void oracle_laurent_coeff_at(int nv, int dtype, int64_t na, const int32_t* a_exp
   for (int64_t j = 0; j < nb; ++j) bidx[lkey(b_exps + j * nv, nv)].push_back(j);
   for (int64_t q = 0; q < nq; ++q) {
     AccI64 ai;
+    AccI128 aw;
     AccF64 af;
     int64_t cnt = 0;
     for (int64_t i = 0; i < na; ++i) {
@@ -363,12 +395,16 @@ void oracle_laurent_coeff_at(int nv, int dtype, int64_t na, const int32_t* a_exp
         ++cnt;
         if (dtype == 0)
           ai.add((uint64_t)((const int64_t*)a_coef)[i] * (uint64_t)((const int64_t*)b_coef)[j]);
+        else if (dtype == 2)
+          aw.add((__int128)((const int64_t*)a_coef)[i] * (__int128)((const int64_t*)b_coef)[j]);
         else
           af.add(((const double*)a_coef)[i] * ((const double*)b_coef)[j]);
       }
     }
     if (dtype == 0)
       ((int64_t*)out_coef)[q] = (int64_t)ai.v;
+    else if (dtype == 2)
+      put_i128(aw.v, (int64_t*)out_coef + 2 * q);
     else {
       ((double*)out_coef)[q] = af.value();
       if (out_abs) out_abs[q] = af.abs;

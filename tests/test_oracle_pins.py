@@ -401,3 +401,83 @@ def test_truncated_limits():
     # weight 0 on a variable: only the other one is cut
     part = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [0, 1], 3)
     assert (part[0][:, 1] <= 3).all() and part[0][:, 0].max() > 3
+
+
+# ------------------------------------------------------------ exact (128-bit) products
+def _signed128(v):
+    v %= 1 << 128
+    return v - (1 << 128) if v >= 1 << 127 else v
+
+
+def _brute_int(ae, ac, be, bc):
+    """Schoolbook product in Python integers, reduced to signed 128 bits at
+    the end (the exact value whenever it fits)."""
+    out = {}
+    for e, c in zip(np.asarray(ae).tolist(), np.asarray(ac).tolist()):
+        for f, d in zip(np.asarray(be).tolist(), np.asarray(bc).tolist()):
+            k = tuple(x + y for x, y in zip(e, f))
+            out[k] = out.get(k, 0) + int(c) * int(d)
+    out = {k: _signed128(v) for k, v in out.items()}
+    return {k: v for k, v in out.items() if v != 0}
+
+
+@pytest.mark.parametrize("seed,bits", [(0, 63), (1, 63), (2, 58), (3, 58)])
+def test_exact_equals_python_integers(seed, bits):
+    # Section 5 compares against exact integer arithmetic.  With 63-bit
+    # coefficients every product is near 2^126, so sums carry across the
+    # 64-bit word boundary and some wrap modulo 2^128; with 58-bit ones the
+    # products stay below 2^116 and every sum is the exact integer.
+    rng = np.random.default_rng(40 + seed)
+    na, nb, nv = 60, 45, 3
+    ae = rng.integers(-2, 3, size=(na, nv)).astype(np.int32)
+    be = rng.integers(-2, 3, size=(nb, nv)).astype(np.int32)
+    hi = 2**bits - 1
+    ext = np.array([hi, -hi - 1, -hi, 1, -1, 0], dtype=np.int64)
+    ac = np.concatenate([ext, rng.integers(-hi - 1, hi, size=na - 6, dtype=np.int64)])
+    bc = np.concatenate([ext[:5], rng.integers(-hi - 1, hi, size=nb - 5, dtype=np.int64)])
+    ex, co, ab = O.laurent_mul(ae, ac, be, bc, exact=True)
+    assert ab is None and co.shape == (len(ex), 2)
+    got = dict(zip(map(tuple, ex.tolist()), O.wide_to_int(co)))
+    want = _brute_int(ae, ac, be, bc)
+    assert got == want
+    if bits == 58:
+        assert max(abs(v) for v in want.values()) < 2**127
+
+
+@pytest.mark.parametrize("k,c", [(3, 3**37), (3, -(3**37)), (4, 7**19)])
+def test_exact_scaled_fateman_closed_form(k, c):
+    # f = c (1+x+y+z+t)^k, g = f + 1: f g = c^2 (1+...)^(2k) + c (1+...)^k, so
+    # each coefficient is c^2 multinomial(2k; e) + c [|e| <= k] multinomial(k; e),
+    # with values up to 2^124 (beyond any 64-bit accumulator).
+    fe, fc = I.fateman(k)
+    fc = fc * c
+    gc = fc.copy()
+    gc[np.all(fe == 0, axis=1)] += 1
+    ex, co, _ = O.laurent_mul(fe, fc, fe, gc, exact=True)
+    assert len(ex) == math.comb(2 * k + 4, 4)
+    big = 0
+    for e, v in zip(ex, O.wide_to_int(co)):
+        e = tuple(int(x) for x in e)
+        want = c * c * I.multinomial(2 * k, e) + (c * I.multinomial(k, e) if sum(e) <= k else 0)
+        assert v == want
+        big = max(big, abs(v))
+    assert big > 2**100
+
+
+def test_exact_low_word_and_coeff_at():
+    # The low word of the exact sum is the int64 result modulo 2^64, and the
+    # one-query-at-a-time form agrees with the full product.
+    rng = np.random.default_rng(7)
+    ae = rng.integers(-3, 4, size=(80, 2)).astype(np.int32)
+    be = rng.integers(-3, 4, size=(70, 2)).astype(np.int32)
+    ac = rng.integers(-2**62, 2**62, size=80, dtype=np.int64)
+    bc = rng.integers(-2**62, 2**62, size=70, dtype=np.int64)
+    ex, co, _ = O.laurent_mul(ae, ac, be, bc, exact=True)
+    ex0, co0, _ = O.laurent_mul(ae, ac, be, bc)
+    low = {k: int(v) % 2**64 for k, v in zip(map(tuple, ex0.tolist()), co0)}
+    for k, v in zip(map(tuple, ex.tolist()), O.wide_to_int(co)):
+        assert low.get(k, 0) == v % 2**64
+    q = np.concatenate([ex[::5], np.array([[50, 50]], np.int32)])
+    got, ab, cnt = O.laurent_coeff_at(ae, ac, be, bc, q, exact=True)
+    assert ab is None and cnt[-1] == 0
+    assert O.wide_to_int(got) == O.wide_to_int(co[::5]) + [0]
