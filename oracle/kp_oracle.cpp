@@ -19,10 +19,11 @@
 // Arithmetic conventions
 //   int64 coefficients: products and sums wrap modulo 2^64 (computed in
 //     uint64_t, converted back at the end).
-//   exact (dtype 2): int64 coefficients whose products and sums are formed in
-//     signed 128-bit integers (__int128); nothing wraps while the true sum
-//     fits 127 bits.  Coefficients are returned as two int64 words
-//     (low word, then high word, two's complement).
+//   exact (dtype 2): int64 coefficients whose products are formed exactly in
+//     __int128 and summed modulo 2^128 (in unsigned __int128, where
+//     wrap-around is defined).  Coefficients are returned as two int64 words
+//     (low word, then high word): the exact sum as a two's complement value
+//     while |sum| < 2^127, and as an unsigned value for sums in [0, 2^128).
 //   fp64 coefficients: each output term carries a Neumaier-compensated sum and
 //     the sum of the absolute values of its contributions (used by the parity
 //     tolerance |gpu - oracle| <= tol * abs_sum).
@@ -57,8 +58,9 @@ struct AccI64 {
 };
 
 struct AccI128 {
-  __int128 v = 0;
-  void add(__int128 x) { v += x; }
+  unsigned __int128 v = 0;
+  void add(__int128 x) { v += (unsigned __int128)x; }
+  void add(unsigned __int128 x) { v += x; }
 };
 
 // Neumaier's improvement of Kahan summation; abs is the sum of |contribution|.
@@ -334,9 +336,8 @@ int64_t oracle_laurent_len(void* h) {
   return n;
 }
 
-// Two int64 words (low, high) of a 128-bit two's complement value.
-void put_i128(__int128 v, int64_t* out) {
-  const unsigned __int128 u = (unsigned __int128)v;
+// Two int64 words (low, high) of a 128-bit value.
+void put_i128(unsigned __int128 u, int64_t* out) {
   out[0] = (int64_t)(uint64_t)u;
   out[1] = (int64_t)(uint64_t)(u >> 64);
 }
