@@ -62,7 +62,17 @@ typedef enum kp_status {
   KP_E_MODE = 9           /* KP_DENSE requested for a box too large for dense mode     */
 } kp_status;
 
-typedef enum kp_dtype { KP_I64 = 0, KP_F64 = 1 } kp_dtype;
+/* Coefficient types.  KP_I64: int64 in and out, products and sums wrap
+   modulo 2^64.  KP_F64: double in and out.  KP_I128 (Laurent only): int64
+   coefficients in, every product formed exactly in 128 bits and summed in
+   128-bit accumulators (Section 5: the 64-bit-input, 128-bit-output integer
+   arithmetic the paper's Fateman timings compare against); each output
+   coefficient is 16 bytes, the low then the high 64-bit word of the sum
+   modulo 2^128: exact as a two's complement value while |sum| < 2^127, and
+   as an unsigned value for nonnegative sums below 2^128 (the Fateman product
+   at degree 30 has coefficients between 2^127 and 2^128).  Out-coefficient
+   arrays hold out_cap * 16 bytes. */
+typedef enum kp_dtype { KP_I64 = 0, KP_F64 = 1, KP_I128 = 2 } kp_dtype;
 
 /* Accumulator choice (Section 3: dense array for moderately sparse products,
    hash table for highly sparse ones; the paper leaves the criterion to "an

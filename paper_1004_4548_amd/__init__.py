@@ -26,7 +26,7 @@ MAX_VARS = 16
 
 KP_OK, KP_E_ARG, KP_E_RANGE, KP_E_CODE_OVERFLOW, KP_E_NONCANONICAL = 0, 1, 2, 3, 4
 KP_E_CAPACITY, KP_E_WORKSPACE, KP_E_DEVICE, KP_E_DTYPE, KP_E_MODE = 5, 6, 7, 8, 9
-KP_I64, KP_F64 = 0, 1
+KP_I64, KP_F64, KP_I128 = 0, 1, 2
 KP_AUTO, KP_DENSE, KP_HASH = 0, 1, 2
 KP_FLAG_ASYNC = 1
 KP_BATCH_GRAPH = 2
@@ -400,26 +400,51 @@ class Workspace:
         return self.buf
 
 
-def _dt(t):
+def _dt(t, exact=False):
+    """Library dtype of factor coefficients; `exact` asks for 128-bit sums of
+    int64 products (KP_I128)."""
     import torch
     if t.dtype == torch.int64:
-        return KP_I64
+        return KP_I128 if exact else KP_I64
+    if exact:
+        raise ValueError("exact (128-bit) products take int64 coefficients")
     if t.dtype == torch.float64:
         return KP_F64
     raise ValueError(f"coefficients must be int64 or float64, got {t.dtype}")
 
 
+def _out_coef(n, dt, device):
+    """Result coefficient buffer: [n] of the factor type, or int64 [n, 2]
+    (low word, high word) for 128-bit results."""
+    import torch
+    if dt == KP_I128:
+        return torch.empty((n, 2), dtype=torch.int64, device=device)
+    return torch.empty(n, dtype=torch.float64 if dt == KP_F64 else torch.int64, device=device)
+
+
+def to_pyint(coef, unsigned=False):
+    """Python integers of 128-bit result coefficients (int64 [n, 2] tensor or
+    array: low word, high word).  The sums are exact modulo 2^128: read as
+    two's complement (default) they are exact while |sum| < 2^127, read as
+    unsigned (`unsigned=True`) for nonnegative sums below 2^128."""
+    import numpy as np
+    w = np.asarray(coef.cpu() if hasattr(coef, "cpu") else coef, dtype=np.int64).reshape(-1, 2)
+    out = [(int(lo) & 0xFFFFFFFFFFFFFFFF) | (int(hi) << 64) for lo, hi in w]
+    return [v % (1 << 128) for v in out] if unsigned else out
+
+
 def mul_laurent_codes(layout, a_codes, a_coef, b_codes, b_coef, mode="auto", ctx=None,
-                      workspace=None, out=None, flags=0):
+                      workspace=None, out=None, flags=0, exact=False):
     """kp_mul_laurent on coded factors.
 
     Returns (codes, coef, count_tensor).  Without KP_FLAG_ASYNC the outputs
-    are trimmed to the result size (one host read of the count).
+    are trimmed to the result size (one host read of the count).  With
+    `exact` (int64 factors) coef is int64 [n, 2]: 128-bit sums.
     """
     import torch
     ctx = ctx or context()
     dev = a_codes.device
-    dt = _dt(a_coef)
+    dt = _dt(a_coef, exact)
     for t, nm in ((a_codes, "a_codes"), (b_codes, "b_codes")):
         _dev_check(t, torch.int64, nm)
     _dev_check(a_coef, a_coef.dtype, "a_coef")
@@ -428,7 +453,7 @@ def mul_laurent_codes(layout, a_codes, a_coef, b_codes, b_coef, mode="auto", ctx
     _, max_out, ws = mul_bound(layout, False, dt, mode, na, nb, ctx)
     if out is None:
         oc = torch.empty(max(max_out, 1), dtype=torch.int64, device=dev)
-        ov = torch.empty(max(max_out, 1), dtype=a_coef.dtype, device=dev)
+        ov = _out_coef(max(max_out, 1), dt, dev)
         on = torch.empty(1, dtype=torch.int64, device=dev)
     else:
         oc, ov, on = out
@@ -537,7 +562,7 @@ def _mode(mode):
     return MODES[mode] if isinstance(mode, str) else mode
 
 
-def plan_laurent(a: Poly, b: Poly, mode="auto", ctx=None, stream=None):
+def plan_laurent(a: Poly, b: Poly, mode="auto", ctx=None, stream=None, exact=False):
     """kp_plan_laurent: boxes of both factors (one launch, one wait) ->
     (Layout, resolved mode name, max result terms, workspace bytes)."""
     import torch
@@ -548,7 +573,7 @@ def plan_laurent(a: Poly, b: Poly, mode="auto", ctx=None, stream=None):
         raise ValueError("factors must have the same number of variables")
     s = _raw_stream(a.exps.device) if stream is None else stream.cuda_stream
     lay, m, mo, ws = Layout(), C.c_int32(), C.c_int64(), C.c_size_t()
-    ctx.check(lib().kp_plan_laurent(ctx.h, a.nv, _dt(a.coef), _mode(mode), a.exps.data_ptr(),
+    ctx.check(lib().kp_plan_laurent(ctx.h, a.nv, _dt(a.coef, exact), _mode(mode), a.exps.data_ptr(),
                                     a.exps.shape[0], b.exps.data_ptr(), b.exps.shape[0],
                                     C.byref(lay), C.byref(m), C.byref(mo), C.byref(ws), s))
     return lay, MODE_NAMES[m.value], mo.value, ws.value
@@ -557,13 +582,15 @@ def plan_laurent(a: Poly, b: Poly, mode="auto", ctx=None, stream=None):
 _SIZE_HINT = {}   # (na, nb, nvars, dtype, mode) -> (result capacity, workspace bytes)
 
 
-def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
+def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None, exact=False):
     """A * B for device-resident Laurent polynomials; returns (Poly, Layout).
 
     One library call when the sizes of the last product of the same shape
     still fit (kp_mul_laurent_auto: plan, encode, multiply, decode, wait for
     the count), else the plan's sizes and a second call.  The device count
-    slot sits after the multiply's workspace."""
+    slot sits after the multiply's workspace.  With `exact` (int64 factors)
+    every product and sum is formed in 128 bits and the result's coef is
+    int64 [n, 2] (low word, high word; `to_pyint` converts)."""
     import torch
     ctx = ctx or context()
     _dev_check(a.exps, torch.int32, "a.exps")
@@ -574,14 +601,14 @@ def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None):
         raise ValueError("factors must have the same number of variables")
     dev = a.exps.device
     s = _raw_stream(dev)
-    na, nb, nv, dt, md = a.exps.shape[0], b.exps.shape[0], a.nv, _dt(a.coef), _mode(mode)
+    na, nb, nv, dt, md = a.exps.shape[0], b.exps.shape[0], a.nv, _dt(a.coef, exact), _mode(mode)
     key = (na, nb, nv, dt, md)
     cap, ws = _SIZE_HINT.get(key, (1, 0))
     workspace = workspace or Workspace()
     lay, n, need_cap, need_ws = Layout(), C.c_int64(), C.c_int64(), C.c_size_t()
     for attempt in range(2):
         ox = torch.empty((cap, nv), dtype=torch.int32, device=dev)
-        oc = torch.empty(cap, dtype=a.coef.dtype, device=dev)
+        oc = _out_coef(cap, dt, dev)
         ws_al = (ws + 255) & ~255
         w = workspace.get(ws_al + 256, dev).data_ptr()
         if attempt == 0:
@@ -685,11 +712,13 @@ class Batch:
         self._keep.append(tensors)
         return tid.value
 
-    def add_laurent(self, layout, a_codes, a_coef, b_codes, b_coef, out, workspace, mode="auto"):
+    def add_laurent(self, layout, a_codes, a_coef, b_codes, b_coef, out, workspace, mode="auto",
+                    exact=False):
         """Queue a Laurent product; `out` = (codes, coef, count) device tensors,
-        `workspace` a uint8 device tensor of kp_mul_bound's size."""
+        `workspace` a uint8 device tensor of kp_mul_bound's size; `exact` as
+        in mul_laurent (coef then int64 [cap, 2])."""
         oc, ov, on = out
-        d = MulDesc(kind=KP_KIND_LAURENT, layout=layout, dtype=_dt(a_coef),
+        d = MulDesc(kind=KP_KIND_LAURENT, layout=layout, dtype=_dt(a_coef, exact),
                     mode=MODES[mode] if isinstance(mode, str) else mode,
                     a_codes=a_codes.data_ptr(), a_coef=a_coef.data_ptr(), na=a_codes.shape[0],
                     b_codes=b_codes.data_ptr(), b_coef=b_coef.data_ptr(), nb=b_codes.shape[0],

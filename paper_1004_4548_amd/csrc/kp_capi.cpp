@@ -237,6 +237,7 @@ struct Plan {
   int rows = 0, l1 = 1, l2 = 0;
   int64_t nblocks = 0, nprod = 0;
   bool trunc = false;   // truncation tables follow the mode's workspace
+  int cw = 1;           // 64-bit words per result coefficient (2 for KP_I128)
 };
 
 // Truncation tables: slack of A's terms and degree of B's (input order),
@@ -278,8 +279,15 @@ double dense_items_bound(const DensePlan& d, int64_t na) {
   return rows / DENSE_ITEM_ROWS + 3.0 * pairs + 64.0;
 }
 
-bool dense_feasible(const kp_ctx* ctx, int64_t nkeys, int64_t na, int64_t nb) {
+// Codes per LDS window: the tuned window for 8-byte slots; 128-bit slots
+// take twice the bytes, so half as many codes (a multiple of DENSE_CHUNK).
+int64_t dense_window(const kp_ctx* ctx, kp_dtype dt) {
   const int64_t S = ctx->tune.window;
+  if (dt != KP_I128) return S;
+  return std::max<int64_t>(DENSE_CHUNK, S / 2 / DENSE_CHUNK * DENSE_CHUNK);
+}
+
+bool dense_feasible(const kp_ctx* ctx, int64_t S, int64_t nkeys, int64_t na, int64_t nb) {
   if (nkeys > ctx->tune.dense_max_keys || nkeys > DENSE_MAX_CODES) return false;
   if (sat_mul((nkeys + S - 1) / S, (nb + DENSE_TILE - 1) / DENSE_TILE) > ((int64_t)1 << 24))
     return false;
@@ -332,9 +340,9 @@ void carve_dense(Carver& c, const Plan& p, int64_t na, int64_t nb, DenseBufs* B)
   uint64_t* items = c.take<uint64_t>(d.items_cap);
   int32_t* task_w = c.take<int32_t>(d.max_tasks);
   int32_t* task_begin = c.take<int32_t>(d.max_tasks + 1);
-  int64_t* dense = c.take<int64_t>(d.nwin * d.S);
+  int64_t* dense = c.take<int64_t>(d.nwin * d.S * p.cw);
   int64_t* stage_k = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
-  int64_t* stage_c = c.take<int64_t>(d.nchunk * DENSE_CHUNK);
+  int64_t* stage_c = c.take<int64_t>(d.nchunk * DENSE_CHUNK * p.cw);
   int64_t* ccount = c.take<int64_t>(d.nchunk);
   int64_t* coff = c.take<int64_t>(d.nchunk);
   if (CARVE) {
@@ -421,7 +429,7 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     h->ent1 = c.take<uint4>((size_t)p.nprod);
     h->ent2 = c.take<uint4>((size_t)p.nprod);
   } else {
-    h->table = c.take<uint64_t>((size_t)2 * p.cap);
+    h->table = c.take<uint64_t>((size_t)(p.cw == 2 ? 4 : 2) * p.cap);   // 16- or 32-byte slots
   }
   h->pp = PoissonPrep{};
   if (poisson) {
@@ -439,7 +447,8 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                     int64_t na, int64_t nb, Plan* p) {
   if (!L) return fail(ctx, KP_E_ARG, "null layout");
   if (na < 0 || nb < 0) return fail(ctx, KP_E_ARG, "negative factor size");
-  if (dt != KP_I64 && dt != KP_F64) return fail(ctx, KP_E_ARG, "bad dtype %d", (int)dt);
+  if (dt != KP_I64 && dt != KP_F64 && dt != KP_I128)
+    return fail(ctx, KP_E_ARG, "bad dtype %d", (int)dt);
   if (poisson && dt != KP_F64)
     return fail(ctx, KP_E_DTYPE, "Poisson products carry a factor 1/2 and need fp64 coefficients");
   if (mode != KP_AUTO && mode != KP_DENSE && mode != KP_HASH)
@@ -453,10 +462,12 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   const PoissonDense pq = poisson ? poisson_dense_codes(L) : PoissonDense{};
   const int64_t dn = poisson ? pq.nkeys : L->nkeys;
   const int64_t nbd = poisson ? sat_mul(nb, 2) : nb;
-  bool dense_ok = dense_feasible(ctx, dn, na, nbd);
+  p->cw = coef_words(dt);
+  const int64_t S = dense_window(ctx, dt);
+  bool dense_ok = dense_feasible(ctx, S, dn, na, nbd);
   if (dense_ok) {
     DensePlan& d = p->dp;
-    d.S = ctx->tune.window;
+    d.S = S;
     d.nkeys = dn;
     d.nwin = std::max<int64_t>(1, (dn + d.S - 1) / d.S);
     d.nchunk = std::max<int64_t>(1, (dn + DENSE_CHUNK - 1) / DENSE_CHUNK);
@@ -505,9 +516,11 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     // partitioned when asked for, or (auto) when the products are not many
     // more than the result bound: its workspace is 32 bytes per product
     // against 32 per result slot pair of the global table
-    p->radix = ctx->tune.hash_partitioned == 2 ||
-               (ctx->tune.hash_partitioned == 1 &&
-                (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1));
+    // (128-bit sums always use the global table)
+    p->radix = dt != KP_I128 &&
+               (ctx->tune.hash_partitioned == 2 ||
+                (ctx->tune.hash_partitioned == 1 &&
+                 (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
     if (p->radix) {
       if (contrib > ((int64_t)1 << 36))
         return fail(ctx, KP_E_CAPACITY, "%lld products exceed the partitioned table",
@@ -982,7 +995,7 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
                               stream);
-      if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * p.cap, stream);
+      if (e == hipSuccess) e = launch_zero(h.table, (size_t)(p.cw == 2 ? 32 : 16) * p.cap, stream);
       if (e == hipSuccess)
         e = launch_hash_laurent(H, dtype, a_codes, a_coef, na, b_codes, b_coef, nb,
                                 ctx->tune.hash_rows, stream);

@@ -50,6 +50,14 @@
 //                compacts the accumulated chunk.
 //  7. scan    -- one workgroup: output offset of every chunk, result count.
 //  8. copy    -- one workgroup per chunk: moves the chunk to its offset.
+//
+// 128-bit coefficients (exact int64 products): a window slot is 16 bytes
+// {low word, high word}, so a window holds half as many codes, and every
+// pair adds its exact product with two 64-bit LDS atomics: the add on the
+// low word returns the word's previous value, which gives the carry out of
+// that add, and the high word then receives the product's high word plus the
+// carry.  The sum of a slot is exact in any order of the adds, because each
+// carry out of the low word is counted once, by the add that produced it.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -327,8 +335,9 @@ struct PlanArgs {
   uint64_t* items;
   int32_t* task_w;
   int32_t* task_begin;
-  int64_t* dense;        // [nwin * S] accumulator of windows split across tasks
+  int64_t* dense;        // [nwin * S * cw] accumulator of windows split across tasks
   Meta* meta;
+  int cw;                // words per coefficient (1, or 2 for 128-bit)
 };
 
 // Rows of A visited by tile t in the window [L, L + Sw): edge rows [i0, c0),
@@ -589,8 +598,8 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
   if (s_split && !P.accumulate) {   // tasks of a split window add into the HBM accumulator
     const int64_t L = w * P.S;
     const int64_t Sw = min(P.S, P.nkeys - L);
-    int64_t* d = P.dense + L;
-    for (int64_t i = tid; i < Sw; i += PLAN_BLOCK) d[i] = 0;
+    int64_t* d = P.dense + L * P.cw;
+    for (int64_t i = tid; i < Sw * P.cw; i += PLAN_BLOCK) d[i] = 0;
   }
   if (tid == 0) P.win[W_SPLIT * W1 + w] = s_split;
 }
@@ -627,6 +636,11 @@ __device__ __forceinline__ void lds_add(uint32_t addr, int64_t v) {
   __hip_atomic_fetch_add(reinterpret_cast<lds_u64*>((size_t)addr), (unsigned long long)v,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ uint64_t lds_fetch_add(uint32_t addr, uint64_t v) {
+  typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+  return __hip_atomic_fetch_add(reinterpret_cast<lds_u64*>((size_t)addr), (unsigned long long)v,
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ void lds_add(uint32_t addr, double v) {
   typedef __attribute__((address_space(3))) double lds_f64;
   __hip_atomic_fetch_add(reinterpret_cast<lds_f64*>((size_t)addr), v, __ATOMIC_RELAXED,
@@ -636,7 +650,8 @@ __device__ __forceinline__ void lds_add(uint32_t addr, double v) {
 // Coefficient kinds.  MUL: 4 = both factors in [0, 2^16) (one 24-bit
 // multiply, the product's high word is zero), 2 = both fit signed 24 bits
 // (two 24-bit multiplies), 1 = both fit int32 (one 32x32->64 multiply),
-// 0 = general int64 (wraps modulo 2^64), 3 = fp64.
+// 0 = general int64 (wraps modulo 2^64), 3 = fp64, 5 = int64 factors with
+// exact 128-bit products and sums.
 template <typename T, int MUL>
 struct Coef {
   uint32_t lo, hi;   // this lane's row of A (broadcast per instruction)
@@ -682,6 +697,58 @@ __device__ __forceinline__ void item_steps(std::integer_sequence<int, U...>, uin
   (pair_step<T, MUL, EDGE, TRUNC, U>(a8, off8, lim, base, c, sa, tb), ...);
 }
 
+// 128-bit slots (MUL 5): the slot offset is computed in 8-byte units, as
+// for the other kinds (same edge and discard tests), then doubled.  Issue:
+// the exact product and the low-word add, which returns the old low word.
+template <bool EDGE, bool TRUNC, int U>
+__device__ __forceinline__ void wide_issue(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
+                                           uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
+                                           int32_t tb, uint32_t& addr, uint64_t& plo,
+                                           int64_t& phi, uint64_t& old) {
+  uint32_t rel = bcast16<U>(a8) + off8;
+  if (EDGE) rel = min(rel, lim);
+  if (TRUNC && (int32_t)bcast16<U>(sa) < tb) rel = lim;
+  addr = (rel << 1) + base;
+  const int64_t x = (int64_t)(((uint64_t)bcast16<U>(chi) << 32) | bcast16<U>(clo));
+  plo = (uint64_t)x * (uint64_t)bw;
+  phi = __mul64hi(x, bw);
+  old = lds_fetch_add(addr, plo);
+}
+
+// Finish: the carry out of the low-word add goes into the high word.
+__device__ __forceinline__ void wide_finish(uint32_t addr, uint64_t plo, int64_t phi,
+                                            uint64_t old) {
+  const uint64_t carry = old + plo < old ? 1u : 0u;
+  lds_add(addr + 8, (int64_t)((uint64_t)phi + carry));
+}
+
+// A group of instructions: every low-word add is issued before the first
+// returned value is needed, so their latencies overlap.
+template <bool EDGE, bool TRUNC, int G, int... U>
+__device__ __forceinline__ void wide_group(std::integer_sequence<int, U...>, uint32_t a8,
+                                           uint32_t off8, uint32_t lim, uint32_t base,
+                                           uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
+                                           int32_t tb) {
+  constexpr int N = sizeof...(U);
+  uint32_t addr[N];
+  uint64_t plo[N], old[N];
+  int64_t phi[N];
+  (wide_issue<EDGE, TRUNC, G + U>(a8, off8, lim, base, clo, chi, bw, sa, tb, addr[U], plo[U],
+                                  phi[U], old[U]),
+   ...);
+  (wide_finish(addr[U], plo[U], phi[U], old[U]), ...);
+}
+
+template <bool EDGE, bool TRUNC>
+__device__ __forceinline__ void wide_steps(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
+                                           uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
+                                           int32_t tb) {
+  wide_group<EDGE, TRUNC, 0>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
+                             bw, sa, tb);
+  wide_group<EDGE, TRUNC, 8>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
+                             bw, sa, tb);
+}
+
 struct ItemRegs {
   int64_t r0, t, n;
   bool core;
@@ -719,25 +786,34 @@ __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t 
   const uint32_t off8 =
       vb ? (uint32_t)(((int32_t)(uint32_t)x.b - (int32_t)L) * 8) : LANE_SENTINEL;
   const uint32_t a8 = rowlane < x.n ? ((uint32_t)x.a << 3) : ROW_SENTINEL;
-  Coef<T, MUL> c;
-  if constexpr (MUL == 1 || MUL == 2 || MUL == 4) {
-    c.lo = (uint32_t)(x.a >> 32);
-    c.hi = 0;
-    c.bn = (int32_t)(uint32_t)(x.b >> 32);
-    if constexpr (MUL == 2) c.bn = (c.bn << 8) >> 8;
-    c.bw = T(0);
+  if constexpr (MUL == 5) {
+    const uint32_t clo = (uint32_t)x.ac, chi = (uint32_t)(x.ac >> 32);
+    const int64_t bw = (int64_t)x.bc;
+    if (x.core)
+      wide_steps<false, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb);
+    else
+      wide_steps<true, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb);
   } else {
-    c.lo = (uint32_t)x.ac;
-    c.hi = (uint32_t)(x.ac >> 32);
-    c.bn = 0;
-    __builtin_memcpy(&c.bw, &x.bc, 8);
+    Coef<T, MUL> c;
+    if constexpr (MUL == 1 || MUL == 2 || MUL == 4) {
+      c.lo = (uint32_t)(x.a >> 32);
+      c.hi = 0;
+      c.bn = (int32_t)(uint32_t)(x.b >> 32);
+      if constexpr (MUL == 2) c.bn = (c.bn << 8) >> 8;
+      c.bw = T(0);
+    } else {
+      c.lo = (uint32_t)x.ac;
+      c.hi = (uint32_t)(x.ac >> 32);
+      c.bn = 0;
+      __builtin_memcpy(&c.bw, &x.bc, 8);
+    }
+    if (x.core)
+      item_steps<T, MUL, false, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base,
+                                       c, (uint32_t)x.sa, x.tb);
+    else
+      item_steps<T, MUL, true, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base,
+                                      c, (uint32_t)x.sa, x.tb);
   }
-  if (x.core)
-    item_steps<T, MUL, false, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c,
-                                     (uint32_t)x.sa, x.tb);
-  else
-    item_steps<T, MUL, true, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base, c,
-                                    (uint32_t)x.sa, x.tb);
 }
 
 // Items [ib, ie) of the task, wavefront w taking ib + w, ib + w + NW, ...;
@@ -746,7 +822,7 @@ template <typename T, int MUL, int BS, bool TRUNC>
 __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t ie, int64_t L,
                                           uint32_t S8, uint32_t base) {
   constexpr int NW = BS / 64;
-  constexpr bool WIDE = MUL == 0 || MUL == 3;
+  constexpr bool WIDE = MUL == 0 || MUL == 3 || MUL == 5;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int rowlane = lane;   // lane 16g + u holds row 16g + u of the item
@@ -775,6 +851,12 @@ __device__ __forceinline__ void global_add(int64_t* p, int64_t v) {
   atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
 __device__ __forceinline__ void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void global_add(I128* p, I128 v) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(p);
+  const uint64_t old = atomicAdd(w, (unsigned long long)v.lo);
+  const uint64_t carry = old + v.lo < old ? 1u : 0u;
+  atomicAdd(w + 1, (unsigned long long)((uint64_t)v.hi + carry));
+}
 
 // Flush of one window piece: compaction straight from LDS when the task
 // holds the whole window, else an add of its nonzero slots into HBM.
@@ -838,7 +920,7 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
     const int64_t L = w * M.S;
     const int64_t Sw = min(M.S, M.nkeys - L);
     uint4* z = reinterpret_cast<uint4*>(smem_raw);
-    const int nz = (int)((Sw + DENSE_DUMMY) * 8 / 16);
+    const int nz = (int)((Sw + DENSE_DUMMY) * (int64_t)sizeof(T) / 16);
     __syncthreads();   // the previous piece's flush has read the window
     for (int i = tid; i < nz; i += BS) z[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
@@ -846,6 +928,9 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
     if constexpr (std::is_same<T, double>::value) {
       if (trunc) run_items<T, 3, BS, true>(M, pb, pe, L, S8, base);
       else run_items<T, 3, BS, false>(M, pb, pe, L, S8, base);
+    } else if constexpr (std::is_same<T, I128>::value) {
+      if (trunc) run_items<T, 5, BS, true>(M, pb, pe, L, S8, base);
+      else run_items<T, 5, BS, false>(M, pb, pe, L, S8, base);
     } else if (trunc) {   // truncated products: one (int64) coefficient kind
       run_items<T, 0, BS, true>(M, pb, pe, L, S8, base);
     } else {
@@ -979,13 +1064,14 @@ struct CopyArgs {
   const int64_t* out_n;   // the scan's count: nothing is written after an error
 };
 
-template <bool DECODE>
+template <bool DECODE, typename T>
 __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
   if (*C.out_n < 0) return;
   const int64_t c = blockIdx.x;
   const int64_t n = C.ccount[c], off = C.coff[c];
   const int64_t* sk = C.stage_k + c * DENSE_CHUNK;
-  const int64_t* sc = C.stage_c + c * DENSE_CHUNK;
+  const T* sc = reinterpret_cast<const T*>(C.stage_c) + c * DENSE_CHUNK;
+  T* out_c = reinterpret_cast<T*>(C.out_c);
   for (int64_t r = threadIdx.x; r < n; r += 256) {
     const int64_t q = off + r;
     if (q < C.out_cap) {
@@ -996,7 +1082,7 @@ __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
       } else {
         C.out_k[q] = sk[r];
       }
-      C.out_c[q] = sc[r];
+      out_c[q] = sc[r];
     }
   }
 }
@@ -1041,6 +1127,9 @@ hipError_t dense_setup() {
     if (e == hipSuccess) e = set_lds_limit<double, 256>();
     if (e == hipSuccess) e = set_lds_limit<double, 512>();
     if (e == hipSuccess) e = set_lds_limit<double, 1024>();
+    if (e == hipSuccess) e = set_lds_limit<I128, 256>();
+    if (e == hipSuccess) e = set_lds_limit<I128, 512>();
+    if (e == hipSuccess) e = set_lds_limit<I128, 1024>();
     if (e != hipSuccess) return e;
     attrs = true;
   }
@@ -1056,7 +1145,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   pa.seg[1] = PrepSeg{B.b_keys_in, B.b_coef_in, B.nb, P.shiftB, P.nbkB, P.maxcodeB, B.bpk, B.bc,
                       B.rank_b, B.bstartB, B.tmin, B.tmax, B.ccount, P.nchunk, B.b_tb_in, B.b_tb};
   pa.meta = B.meta;
-  pa.is_i64 = dt == KP_I64;
+  pa.is_i64 = dt != KP_F64;
   const size_t hist_bytes = (size_t)std::max(P.nbkA, P.nbkB) * 4;
   hipLaunchKernelGGL(k_dense_prep, dim3(2), dim3(PREP_BLOCK), hist_bytes, s, pa);
   const int64_t blocksA = (B.na + SCATTER_BLOCK - 1) / SCATTER_BLOCK;
@@ -1067,7 +1156,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   PlanArgs pl{P.S, P.nwin, P.ntiles, P.nkeys, B.nb, P.target_tasks, P.min_work, P.items_cap,
               ITEMS_LDS_BYTES, P.accumulate,
               B.bstart, P.shiftA, P.nbkA, B.tmin, B.tmax, B.win, B.recs, B.items, B.task_w,
-              B.task_begin, B.dense, B.meta};
+              B.task_begin, B.dense, B.meta, coef_words(dt)};
   hipLaunchKernelGGL(k_dense_count, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK), 0, s, pl);
   hipLaunchKernelGGL(k_dense_items, dim3((unsigned)P.nwin), dim3(PLAN_BLOCK),
                      (size_t)ITEMS_LDS_BYTES, s, pl);
@@ -1076,7 +1165,7 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   MulArgs ma{B.meta, B.apk, B.ac, B.bpk, B.bc, B.nb, P.S, P.nwin, P.nkeys, B.items, B.task_w,
              B.task_begin, B.win + W_IBASE * W1, P.accumulate, B.dense, B.stage_k, B.stage_c,
              B.ccount, B.a_sa_in ? B.a_sa : nullptr, B.b_tb_in ? B.b_tb : nullptr};
-  const size_t lds = (size_t)(P.S + DENSE_DUMMY) * 8;
+  const size_t lds = (size_t)(P.S + DENSE_DUMMY) * 8 * coef_words(dt);
   const unsigned grid = (unsigned)P.max_tasks;
   if (B.ev0) (void)hipEventRecord(B.ev0, s);
 #define KP_DENSE_LAUNCH(TT, BSZ) \
@@ -1085,6 +1174,10 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
     if (P.block == 256) KP_DENSE_LAUNCH(double, 256);
     else if (P.block == 512) KP_DENSE_LAUNCH(double, 512);
     else KP_DENSE_LAUNCH(double, 1024);
+  } else if (dt == KP_I128) {
+    if (P.block == 256) KP_DENSE_LAUNCH(I128, 256);
+    else if (P.block == 512) KP_DENSE_LAUNCH(I128, 512);
+    else KP_DENSE_LAUNCH(I128, 1024);
   } else {
     if (P.block == 256) KP_DENSE_LAUNCH(int64_t, 256);
     else if (P.block == 512) KP_DENSE_LAUNCH(int64_t, 512);
@@ -1099,6 +1192,8 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   const unsigned cgrid = (unsigned)(P.nwin * (P.S / DENSE_CHUNK));
   if (dt == KP_F64)
     hipLaunchKernelGGL(k_dense_combine<double>, dim3(cgrid), dim3(COMBINE_BLOCK), 0, s, cb);
+  else if (dt == KP_I128)
+    hipLaunchKernelGGL(k_dense_combine<I128>, dim3(cgrid), dim3(COMBINE_BLOCK), 0, s, cb);
   else
     hipLaunchKernelGGL(k_dense_combine<int64_t>, dim3(cgrid), dim3(COMBINE_BLOCK), 0, s, cb);
 
@@ -1106,10 +1201,14 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   hipLaunchKernelGGL(k_dense_scan, dim3(1), dim3(1024), 0, s, sa);
   CopyArgs ca{B.out_cap, B.ccount, B.coff, B.stage_k, B.stage_c, B.out_k,
               reinterpret_cast<int64_t*>(B.out_c), B.out_exps, B.dec, B.out_n};
-  if (B.out_exps)
-    hipLaunchKernelGGL(k_dense_copy<true>, dim3((unsigned)P.nchunk), dim3(256), 0, s, ca);
-  else
-    hipLaunchKernelGGL(k_dense_copy<false>, dim3((unsigned)P.nchunk), dim3(256), 0, s, ca);
+  const dim3 cg((unsigned)P.nchunk);
+  if (dt == KP_I128) {
+    if (B.out_exps) hipLaunchKernelGGL((k_dense_copy<true, I128>), cg, dim3(256), 0, s, ca);
+    else hipLaunchKernelGGL((k_dense_copy<false, I128>), cg, dim3(256), 0, s, ca);
+  } else {
+    if (B.out_exps) hipLaunchKernelGGL((k_dense_copy<true, int64_t>), cg, dim3(256), 0, s, ca);
+    else hipLaunchKernelGGL((k_dense_copy<false, int64_t>), cg, dim3(256), 0, s, ca);
+  }
   return hipGetLastError();
 }
 

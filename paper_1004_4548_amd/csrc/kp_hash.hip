@@ -12,7 +12,10 @@
 // 64-bit atomic add (integer, or fp64 add), so concurrent insertions of the
 // same code from any compute unit combine without locks.  Compaction reads
 // the table once, selects non-empty slots with a nonzero coefficient by
-// wavefront ballot and writes them contiguously.
+// wavefront ballot and writes them contiguously.  Exact 128-bit sums of
+// int64 products use 32-byte slots {code + 1, low word, high word, unused};
+// the low word's atomic add returns its previous value, and the carry out of
+// that add goes into the high word with the product's high word.
 //
 // Poisson series (Section 2, eq. werner with the factor 1/2): every pair
 // contributes +-1/2 ca cb to the term of the difference and of the sum of the
@@ -40,6 +43,18 @@ __device__ __forceinline__ void slot_add(uint64_t* c, int64_t v) {
 __device__ __forceinline__ void slot_add(uint64_t* c, double v) {
   unsafeAtomicAdd(reinterpret_cast<double*>(c), v);
 }
+__device__ __forceinline__ void slot_add(uint64_t* c, I128 v) {
+  const uint64_t old = atomicAdd((unsigned long long*)c, (unsigned long long)v.lo);
+  const uint64_t carry = old + v.lo < old ? 1u : 0u;
+  atomicAdd((unsigned long long*)(c + 1), (unsigned long long)((uint64_t)v.hi + carry));
+}
+
+// 64-bit words per table slot: the key and one coefficient, padded to a
+// power of two.
+template <typename T>
+constexpr int slot_words() {
+  return sizeof(T) == 16 ? 4 : 2;
+}
 
 __device__ __forceinline__ uint64_t home_slot(int64_t code, uint64_t cap) {
   // multiplicative hash, then mapped onto [0, cap) by a high multiply
@@ -60,7 +75,7 @@ __device__ __noinline__ int64_t table_probe(uint64_t* __restrict__ table, uint64
                                             int64_t max_probe, uint64_t s, uint64_t cur,
                                             uint64_t key, T v, uint32_t* err) {
   for (int64_t p = 0; p < max_probe; ++p) {
-    uint64_t* ks = table + 2 * s;
+    uint64_t* ks = table + slot_words<T>() * s;
     if (p > 0) cur = key_load(ks);
     if (cur == 0) {
       cur = atomicCAS((unsigned long long*)ks, 0ull, (unsigned long long)key);
@@ -104,14 +119,14 @@ __device__ __forceinline__ int64_t table_insert_n(uint64_t* __restrict__ table, 
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     s[u] = home_slot(code[u], cap);
-    cur[u] = on[u] ? key_load(table + 2 * s[u]) : 0;
+    cur[u] = on[u] ? key_load(table + slot_words<T>() * s[u]) : 0;
   }
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     if (!on[u]) continue;
     const uint64_t key = (uint64_t)code[u] + 1;
     if (cur[u] == key)
-      slot_add(table + 2 * s[u] + 1, v[u]);
+      slot_add(table + slot_words<T>() * s[u] + 1, v[u]);
     else
       extra += table_probe<T>(table, cap, max_probe, s[u], cur[u], key, v[u], err);
   }
@@ -134,14 +149,24 @@ __device__ inline double mul_coef<double>(double a, double b, uint32_t) {
   return a * b;
 }
 
+// Factor coefficients of a value type: 128-bit sums take int64 factors.
+template <typename T>
+using factor_t = typename std::conditional<std::is_same<T, I128>::value, int64_t, T>::type;
+
+// Exact product of two int64 coefficients.
+__device__ inline I128 mul_wide(int64_t a, int64_t b) {
+  return I128((uint64_t)a * (uint64_t)b, __mul64hi(a, b));
+}
+
 // Thread = one term of B (in registers); loops over a slice of A's rows,
 // whose code and coefficient are wavefront-uniform (scalar loads), four rows
 // per round so that four insertions are in flight.
 template <typename T>
 __global__ void __launch_bounds__(HASH_BLOCK)
 k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Meta* meta,
-               const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
-               const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb, int rows,
+               const int64_t* __restrict__ ak, const factor_t<T>* __restrict__ ac, int64_t na,
+               const int64_t* __restrict__ bk, const factor_t<T>* __restrict__ bc, int64_t nb,
+               int rows,
                unsigned long long* stats, const int32_t* __restrict__ a_sa,
                const int32_t* __restrict__ b_tb) {
   constexpr int NB = 4;
@@ -152,7 +177,7 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
   const bool live = j0 < nb;
   const int64_t j = live ? j0 : nb - 1;   // idle lanes stay for the statistics reduction
   const int64_t bj = bk[j];
-  const T cb = bc[j];
+  const factor_t<T> cb = bc[j];
   const int32_t tb = b_tb ? b_tb[j] : INT_MIN;
   int64_t ins = 0, extra = 0;
   for (int64_t i = live ? i0 : i1; i < i1; i += NB) {
@@ -163,7 +188,10 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
     for (int u = 0; u < NB; ++u) {
       const bool in = i + u < i1;
       const int64_t r = in ? i + u : i;
-      v[u] = mul_coef<T>(ac[r], cb, narrow);
+      if constexpr (std::is_same<T, I128>::value)
+        v[u] = mul_wide(ac[r], cb);
+      else
+        v[u] = mul_coef<T>(ac[r], cb, narrow);
       code[u] = ak[r] + bj;
       on[u] = in && v[u] != T(0) && (!a_sa || tb <= a_sa[r]);
       ins += on[u];
@@ -265,7 +293,8 @@ k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t chunk = (int64_t)HASH_BLOCK * COMPACT_PER;
   for (int64_t base = (int64_t)blockIdx.x * chunk; base < cap; base += (int64_t)gridDim.x * chunk) {
-    uint64_t key[COMPACT_PER], val[COMPACT_PER];
+    uint64_t key[COMPACT_PER];
+    T val[COMPACT_PER];
     uint64_t ball[COMPACT_PER];
     int64_t wave_cnt = 0;
 #pragma unroll
@@ -273,14 +302,18 @@ k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
       const int64_t s = base + r * HASH_BLOCK + threadIdx.x;
       bool f = false;
       key[r] = 0;
-      val[r] = 0;
+      val[r] = T(0);
       if (s < cap) {
-        const uint4 slot = reinterpret_cast<const uint4*>(table)[s];
-        key[r] = ((uint64_t)slot.y << 32) | slot.x;
-        val[r] = ((uint64_t)slot.w << 32) | slot.z;
-        T c;
-        __builtin_memcpy(&c, &val[r], sizeof(T));
-        f = key[r] != 0 && c != T(0);
+        const uint4* sl = reinterpret_cast<const uint4*>(table) + (slot_words<T>() / 2) * s;
+        const uint4 w0 = sl[0];
+        key[r] = ((uint64_t)w0.y << 32) | w0.x;
+        uint64_t words[2] = {((uint64_t)w0.w << 32) | w0.z, 0};
+        if constexpr (slot_words<T>() == 4) {
+          const uint4 w1 = sl[1];
+          words[1] = ((uint64_t)w1.y << 32) | w1.x;
+        }
+        __builtin_memcpy(&val[r], words, sizeof(T));
+        f = key[r] != 0 && val[r] != T(0);
       }
       ball[r] = __ballot(f);
       wave_cnt += __popcll(ball[r]);
@@ -304,9 +337,7 @@ k_hash_compact(const uint64_t* __restrict__ table, int64_t cap, Meta* meta,
         const int64_t p = pos + __popcll(ball[r] & lt);
         if (p < out_cap) {
           out_k[p] = (int64_t)(key[r] - 1);
-          T c;
-          __builtin_memcpy(&c, &val[r], sizeof(T));
-          out_c[p] = c;
+          out_c[p] = val[r];
         }
       }
       pos += __popcll(ball[r]);
@@ -792,6 +823,10 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
     hipLaunchKernelGGL(k_hash_laurent<double>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const double*)ac, na, bk,
                        (const double*)bc, nb, rows, H.stats, H.a_sa, H.b_tb);
+  else if (dt == KP_I128)
+    hipLaunchKernelGGL(k_hash_laurent<I128>, grid, dim3(HASH_BLOCK), 0, s, H.table,
+                       (uint64_t)H.cap, H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk,
+                       (const int64_t*)bc, nb, rows, H.stats, H.a_sa, H.b_tb);
   else
     hipLaunchKernelGGL(k_hash_laurent<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table,
                        (uint64_t)H.cap, H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk,
@@ -831,6 +866,9 @@ hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s) {
   if (dt == KP_F64)
     hipLaunchKernelGGL(k_hash_compact<double>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
                        H.table, cap, H.meta, H.out_k, (double*)H.out_c, H.out_cap);
+  else if (dt == KP_I128)
+    hipLaunchKernelGGL(k_hash_compact<I128>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
+                       H.table, cap, H.meta, H.out_k, (I128*)H.out_c, H.out_cap);
   else
     hipLaunchKernelGGL(k_hash_compact<int64_t>, dim3((unsigned)blocks), dim3(HASH_BLOCK), 0, s,
                        H.table, cap, H.meta, H.out_k, (int64_t*)H.out_c, H.out_cap);

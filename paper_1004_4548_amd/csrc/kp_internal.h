@@ -227,6 +227,23 @@ hipError_t launch_finalize(const Meta* m, int64_t out_cap, int64_t* out_n, uint3
 hipError_t launch_coef_range(const int64_t* a, int64_t na, const int64_t* b, int64_t nb, Meta* m,
                              hipStream_t s);
 
+// A 128-bit two's complement coefficient: low word, then high word (the
+// output layout of KP_I128).  Sums are formed with a carry out of the low
+// word, so that 64-bit atomic adds can accumulate it.
+struct I128 {
+  uint64_t lo;
+  int64_t hi;
+  __host__ __device__ constexpr I128() : lo(0), hi(0) {}
+  __host__ __device__ constexpr I128(int v) : lo((uint64_t)(int64_t)v), hi(v < 0 ? -1 : 0) {}
+  __host__ __device__ constexpr I128(uint64_t l, int64_t h) : lo(l), hi(h) {}
+  __host__ __device__ constexpr bool operator==(const I128& o) const {
+    return lo == o.lo && hi == o.hi;
+  }
+  __host__ __device__ constexpr bool operator!=(const I128& o) const { return !(*this == o); }
+};
+// Words of one coefficient of a dtype (int64 and fp64: 1, int128: 2).
+inline constexpr int coef_words(kp_dtype dt) { return dt == KP_I128 ? 2 : 1; }
+
 // dense Laurent
 constexpr int64_t DENSE_MAX_BUCKETS = 32768;   // bucket-sort histogram slots (LDS)
 constexpr int64_t DENSE_CHUNK = 2048;          // output segment (codes)
@@ -270,8 +287,8 @@ struct DenseBufs {
   uint64_t* items;              // [items_cap] work items
   int32_t* task_w;              // [max_tasks] window of each task
   int32_t* task_begin;          // [max_tasks + 1] first item of each task
-  int64_t* dense;               // [nwin * S] accumulator of windows split across tasks
-  int64_t* stage_k; int64_t* stage_c;   // [nchunk * DENSE_CHUNK] compacted chunks
+  int64_t* dense;               // [nwin * S * cw] accumulator of windows split across tasks
+  int64_t* stage_k; int64_t* stage_c;   // [nchunk * DENSE_CHUNK (* cw)] compacted chunks
   int64_t* ccount;              // [nchunk] terms per chunk
   int64_t* coff;                // [nchunk] output offset per chunk
   int64_t* out_k; void* out_c; int64_t out_cap; int64_t* out_n;
@@ -295,7 +312,8 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
 // hash Laurent / Poisson
 struct HashBufs {
   Meta* meta;
-  uint64_t* table;       // cap * 2 words: (key + 1, coef bits)
+  uint64_t* table;       // cap * 2 words: (key + 1, coef bits); int128: cap * 4 words
+                         // (key + 1, low word, high word, unused)
   int64_t cap;           // slots (>= 64)
   int64_t max_probe;
   int64_t* out_k; void* out_c; int64_t out_cap;

@@ -264,3 +264,13 @@ def test_host_context_rejects_launches():
     lay = _layout_laurent([0], [3])
     st = kp.lib().kp_encode(ctx.h, C.byref(lay), 0, 0, None, None, None, None, None, 0, None)
     assert st == kp.KP_E_ARG
+
+
+def test_to_pyint_round_trip():
+    # 128-bit result words (low, high) to Python integers, both converters
+    import oracle as O
+    vals = [0, 1, -1, 2**64, -2**64, 2**127 - 1, -2**127, 3**70, -(5**50)]
+    words = np.array([[(v & (2**64 - 1)) - (2**64 if v & (2**63) else 0), v >> 64] for v in vals],
+                     np.int64)
+    assert kp.to_pyint(words) == vals
+    assert O.wide_to_int(words) == vals
