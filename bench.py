@@ -85,8 +85,8 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def laurent_step(kp, ctx, ws, pa, pb, mode):
-    r, lay = kp.mul_laurent(pa, pb, mode=mode, ctx=ctx, workspace=ws)
+def laurent_step(kp, ctx, ws, pa, pb, mode, exact=False):
+    r, lay = kp.mul_laurent(pa, pb, mode=mode, ctx=ctx, workspace=ws, exact=exact)
     return r
 
 
@@ -107,19 +107,20 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def measure_laurent(kp, ctx, a, b, mode, steps, warmup):
+def measure_laurent(kp, ctx, a, b, mode, steps, warmup, exact=False):
     import torch
     ws = kp.Workspace()
     pa = kp.Poly(to_dev(a[0]), to_dev(a[1]))
     pb = kp.Poly(to_dev(b[0]), to_dev(b[1]))
-    res = laurent_step(kp, ctx, ws, pa, pb, mode)
+    step = lambda: laurent_step(kp, ctx, ws, pa, pb, mode, exact)
+    res = step()
     n_out = int(res.coef.shape[0])
-    sec = time_steps(lambda: laurent_step(kp, ctx, ws, pa, pb, mode), steps, warmup)
+    sec = time_steps(step, steps, warmup)
     # the accumulation kernel alone, bracketed by HIP events on the call's
     # stream (a separate pass: the events add a little time to each step)
     ctx.timing_read()
     ctx.timing(True)
-    time_steps(lambda: laurent_step(kp, ctx, ws, pa, pb, mode), steps, 0)
+    time_steps(step, steps, 0)
     kms, launches = ctx.timing_read()
     ctx.timing(False)
     kernel_s = kms / 1e3 / max(launches, 1)
@@ -127,12 +128,13 @@ def measure_laurent(kp, ctx, a, b, mode, steps, warmup):
     lay = kp.laurent_layout(pa, pb, ctx)
     ka, _ = kp.encode(lay, 0, pa.exps, ctx=ctx)
     kb, _ = kp.encode(lay, 1, pb.exps, ctx=ctx)
-    m, max_out, _ = kp.mul_bound(lay, False, kp._dt(pa.coef), mode, len(a[1]), len(b[1]), ctx)
+    dt = kp._dt(pa.coef, exact)
+    m, max_out, _ = kp.mul_bound(lay, False, dt, mode, len(a[1]), len(b[1]), ctx)
     out = (torch.empty(max_out, dtype=torch.int64, device="cuda"),
-           torch.empty(max_out, dtype=pa.coef.dtype, device="cuda"),
+           kp._out_coef(max_out, dt, "cuda"),
            torch.empty(1, dtype=torch.int64, device="cuda"))
     mul = lambda: kp.mul_laurent_codes(lay, ka, pa.coef, kb, pb.coef, mode, ctx, ws, out,
-                                       flags=kp.KP_FLAG_ASYNC)
+                                       flags=kp.KP_FLAG_ASYNC, exact=exact)
     mul_sec = time_steps(mul, steps, warmup)
     assert int(out[2].item()) == n_out
     return dict(sec=sec, kernel_s=kernel_s, launches=launches, mul_sec=mul_sec, n_out=n_out,
@@ -195,9 +197,17 @@ def run_fateman(kp, ctx, I, args):
     f, g = I.fateman(30), I.fateman(30, plus_one=True)
     rf = measure_laurent(kp, ctx, f, g, "auto", 5, 1)
     pf = len(f[1]) * len(g[1])
+    rx = measure_laurent(kp, ctx, f, g, "auto", 5, 1, exact=True)
+    pair_rate = ctx.probe_lds_atomic(4)
     return {"term_products_per_s": pf / rf["sec"], "ms_per_step": rf["sec"] * 1e3,
             "term_products": pf, "mode": rf["mode"], "result_terms": rf["n_out"],
             "window_kernel_ms": rf["kernel_s"] * 1e3,
+            "exact_128": {"term_products_per_s": pf / rx["sec"], "ms_per_step": rx["sec"] * 1e3,
+                          "mode": rx["mode"], "result_terms": rx["n_out"],
+                          "window_kernel_ms": rx["kernel_s"] * 1e3,
+                          "measured_carry_pair_Tacc_per_s": pair_rate / 1e12,
+                          "frac_of_carry_pair_probe": pf / rx["kernel_s"] / pair_rate,
+                          "note": "int64 factors, exact 128-bit products and sums"},
             "paper_cpu_context": "4.29 s on one Core2 Q6600 core, fp64 (5.0e8 pairs/s)"}
 
 
@@ -209,6 +219,11 @@ def run_mp(kp, ctx, I, args):
            "term_products": pm, "mode": rm["mode"], "result_terms": rm["n_out"],
            "insert_kernel_ms": rm["kernel_s"] * 1e3,
            "paper_cpu_context": "1.71 s on one Core2 Q6600 core, fp64 (2.2e7 pairs/s)"}
+    rx = measure_laurent(kp, ctx, f, g, "auto", 5, 1, exact=True)
+    out["exact_128"] = {"term_products_per_s": pm / rx["sec"], "ms_per_step": rx["sec"] * 1e3,
+                        "mode": rx["mode"], "result_terms": rx["n_out"],
+                        "insert_kernel_ms": rx["kernel_s"] * 1e3,
+                        "note": "int64 factors, exact 128-bit sums (global table, 32-byte slots)"}
     if rm["mode"] == "hash":
         pa = kp.Poly(to_dev(f[0]), to_dev(f[1]))
         pb = kp.Poly(to_dev(g[0]), to_dev(g[1]))
@@ -342,10 +357,11 @@ def main():
         "roofline": roof,
     }
     # measured ceilings of the window kernel's accumulator (context for frac)
-    rates = [ctx.probe_lds_atomic(p) for p in range(4)]
+    rates = [ctx.probe_lds_atomic(p) for p in range(5)]
     roof["measured_lds_atomic"] = {
         "u64_consecutive_Tacc_per_s": rates[0] / 1e12, "u64_random_Tacc_per_s": rates[1] / 1e12,
         "u32_consecutive_Tacc_per_s": rates[2] / 1e12, "u32_random_Tacc_per_s": rates[3] / 1e12,
+        "u128_carry_pair_random_Tacc_per_s": rates[4] / 1e12,
         "frac_of_u64_consecutive": kernel_rate / rates[0],
         "probe": "LDS atomic adds on every CU, 1024-thread workgroups, 128 KiB of counters"}
     if args.only:

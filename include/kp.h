@@ -197,8 +197,10 @@ kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inser
    1024-thread workgroup with a 128 KiB array per unit: pattern 0 gives each
    wavefront 64 consecutive 8-byte counters (no bank conflicts), pattern 1
    pseudo-random 8-byte counters, patterns 2 and 3 the same with 4-byte
-   counters.  Writes the device-wide rate in adds per second to
-   *adds_per_second.  Runs twice (the first run warms up) and synchronises
+   counters; pattern 4 times the 128-bit accumulation of KP_I128 at random
+   slots (a returning add on the low word, then the carry into the high
+   word) and counts one such pair as one add.  Writes the device-wide rate in
+   adds per second to *adds_per_second.  Runs twice (the first run warms up) and synchronises
    `stream`.  Touches no caller memory; KP_E_ARG for another pattern. */
 kp_status kp_probe_lds_atomic(kp_ctx* ctx, int pattern, double* adds_per_second,
                               hipStream_t stream);

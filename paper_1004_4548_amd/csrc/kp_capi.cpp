@@ -711,7 +711,7 @@ kp_status kp_probe_lds_atomic(kp_ctx* ctx, int pattern, double* adds_per_second,
                               hipStream_t stream) {
   if (!ctx || !adds_per_second) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
-  if (pattern < 0 || pattern > 3) return fail(ctx, KP_E_ARG, "pattern must be 0, 1, 2 or 3");
+  if (pattern < 0 || pattern > 4) return fail(ctx, KP_E_ARG, "pattern must be 0 to 4");
   const int blocks = 2 * ctx->num_cu, iters = 1024;
   float ms = 0;
   hipError_t e = probe_lds_atomic(pattern, blocks, iters, ctx->status->sink, &ms, stream);

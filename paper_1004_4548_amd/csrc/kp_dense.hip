@@ -51,13 +51,15 @@
 //  7. scan    -- one workgroup: output offset of every chunk, result count.
 //  8. copy    -- one workgroup per chunk: moves the chunk to its offset.
 //
-// 128-bit coefficients (exact int64 products): a window slot is 16 bytes
-// {low word, high word}, so a window holds half as many codes, and every
-// pair adds its exact product with two 64-bit LDS atomics: the add on the
-// low word returns the word's previous value, which gives the carry out of
-// that add, and the high word then receives the product's high word plus the
-// carry.  The sum of a slot is exact in any order of the adds, because each
-// carry out of the low word is counted once, by the add that produced it.
+// 128-bit coefficients (exact int64 products): a window holds half as many
+// codes, as two arrays of 64-bit words, the low words of its slots followed
+// by their high words (two arrays rather than 16-byte slots, so that both
+// kinds of add spread over every LDS bank).  Every pair adds its exact
+// product with two 64-bit LDS atomics: the add on the low word returns the
+// word's previous value, which gives the carry out of that add, and the high
+// word then receives the product's high word plus the carry.  The sum of a
+// slot is exact in any order of the adds, because each carry out of the low
+// word is counted once, by the add that produced it.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -697,9 +699,10 @@ __device__ __forceinline__ void item_steps(std::integer_sequence<int, U...>, uin
   (pair_step<T, MUL, EDGE, TRUNC, U>(a8, off8, lim, base, c, sa, tb), ...);
 }
 
-// 128-bit slots (MUL 5): the slot offset is computed in 8-byte units, as
-// for the other kinds (same edge and discard tests), then doubled.  Issue:
-// the exact product and the low-word add, which returns the old low word.
+// 128-bit slots (MUL 5): the low word's offset is computed as for the other
+// kinds (same edge and discard tests); the high word lies hi8 bytes further.
+// Issue: the exact product and the low-word add, which returns the old low
+// word.
 template <bool EDGE, bool TRUNC, int U>
 __device__ __forceinline__ void wide_issue(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
                                            uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
@@ -708,7 +711,7 @@ __device__ __forceinline__ void wide_issue(uint32_t a8, uint32_t off8, uint32_t 
   uint32_t rel = bcast16<U>(a8) + off8;
   if (EDGE) rel = min(rel, lim);
   if (TRUNC && (int32_t)bcast16<U>(sa) < tb) rel = lim;
-  addr = (rel << 1) + base;
+  addr = rel + base;
   const int64_t x = (int64_t)(((uint64_t)bcast16<U>(chi) << 32) | bcast16<U>(clo));
   plo = (uint64_t)x * (uint64_t)bw;
   phi = __mul64hi(x, bw);
@@ -716,10 +719,10 @@ __device__ __forceinline__ void wide_issue(uint32_t a8, uint32_t off8, uint32_t 
 }
 
 // Finish: the carry out of the low-word add goes into the high word.
-__device__ __forceinline__ void wide_finish(uint32_t addr, uint64_t plo, int64_t phi,
-                                            uint64_t old) {
+__device__ __forceinline__ void wide_finish(uint32_t addr, uint32_t hi8, uint64_t plo,
+                                            int64_t phi, uint64_t old) {
   const uint64_t carry = old + plo < old ? 1u : 0u;
-  lds_add(addr + 8, (int64_t)((uint64_t)phi + carry));
+  lds_add(addr + hi8, (int64_t)((uint64_t)phi + carry));
 }
 
 // A group of instructions: every low-word add is issued before the first
@@ -728,7 +731,7 @@ template <bool EDGE, bool TRUNC, int G, int... U>
 __device__ __forceinline__ void wide_group(std::integer_sequence<int, U...>, uint32_t a8,
                                            uint32_t off8, uint32_t lim, uint32_t base,
                                            uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
-                                           int32_t tb) {
+                                           int32_t tb, uint32_t hi8) {
   constexpr int N = sizeof...(U);
   uint32_t addr[N];
   uint64_t plo[N], old[N];
@@ -736,17 +739,17 @@ __device__ __forceinline__ void wide_group(std::integer_sequence<int, U...>, uin
   (wide_issue<EDGE, TRUNC, G + U>(a8, off8, lim, base, clo, chi, bw, sa, tb, addr[U], plo[U],
                                   phi[U], old[U]),
    ...);
-  (wide_finish(addr[U], plo[U], phi[U], old[U]), ...);
+  (wide_finish(addr[U], hi8, plo[U], phi[U], old[U]), ...);
 }
 
 template <bool EDGE, bool TRUNC>
 __device__ __forceinline__ void wide_steps(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
                                            uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
-                                           int32_t tb) {
+                                           int32_t tb, uint32_t hi8) {
   wide_group<EDGE, TRUNC, 0>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
-                             bw, sa, tb);
+                             bw, sa, tb, hi8);
   wide_group<EDGE, TRUNC, 8>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
-                             bw, sa, tb);
+                             bw, sa, tb, hi8);
 }
 
 struct ItemRegs {
@@ -781,7 +784,7 @@ __device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane
 
 template <typename T, int MUL, bool TRUNC>
 __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t lim, int lane,
-                                         int rowlane, int64_t nb, uint32_t base) {
+                                         int rowlane, int64_t nb, uint32_t base, uint32_t hi8) {
   const bool vb = x.t * DENSE_TILE + (lane & 15) < nb;
   const uint32_t off8 =
       vb ? (uint32_t)(((int32_t)(uint32_t)x.b - (int32_t)L) * 8) : LANE_SENTINEL;
@@ -790,9 +793,9 @@ __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t 
     const uint32_t clo = (uint32_t)x.ac, chi = (uint32_t)(x.ac >> 32);
     const int64_t bw = (int64_t)x.bc;
     if (x.core)
-      wide_steps<false, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb);
+      wide_steps<false, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8);
     else
-      wide_steps<true, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb);
+      wide_steps<true, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8);
   } else {
     Coef<T, MUL> c;
     if constexpr (MUL == 1 || MUL == 2 || MUL == 4) {
@@ -820,7 +823,7 @@ __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t 
 // the next item's rows and terms are loaded while the current one runs.
 template <typename T, int MUL, int BS, bool TRUNC>
 __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t ie, int64_t L,
-                                          uint32_t S8, uint32_t base) {
+                                          uint32_t S8, uint32_t base, uint32_t hi8) {
   constexpr int NW = BS / 64;
   constexpr bool WIDE = MUL == 0 || MUL == 3 || MUL == 5;
   const int lane = threadIdx.x & 63;
@@ -839,11 +842,11 @@ __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t 
     fetch_item<WIDE, TRUNC>(M, readlane64(dv, 0), lane, rowlane, x0);
     for (int k = 0; k + 1 < cnt; k += 2) {
       fetch_item<WIDE, TRUNC>(M, readlane64(dv, k + 1), lane, rowlane, x1);
-      run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base);
+      run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base, hi8);
       fetch_item<WIDE, TRUNC>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, rowlane, x0);
-      run_item<T, MUL, TRUNC>(x1, L, lim, lane, rowlane, M.nb, base);
+      run_item<T, MUL, TRUNC>(x1, L, lim, lane, rowlane, M.nb, base, hi8);
     }
-    if (cnt & 1) run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base);
+    if (cnt & 1) run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base, hi8);
   }
 }
 
@@ -858,16 +861,28 @@ __device__ __forceinline__ void global_add(I128* p, I128 v) {
   atomicAdd(w + 1, (unsigned long long)((uint64_t)v.hi + carry));
 }
 
+// Slot i of the window: one word, or (128-bit) the low word and the high
+// word `hw` words further.
+template <typename T>
+__device__ __forceinline__ T win_load(const unsigned char* win, int64_t i, int64_t hw) {
+  if constexpr (std::is_same<T, I128>::value) {
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(win);
+    return I128(w[i], (int64_t)w[hw + i]);
+  } else {
+    return reinterpret_cast<const T*>(win)[i];
+  }
+}
+
 // Flush of one window piece: compaction straight from LDS when the task
 // holds the whole window, else an add of its nonzero slots into HBM.
 template <typename T, int BS>
-__device__ __forceinline__ void flush_window(const MulArgs& M, const T* win, int64_t L, int64_t Sw,
-                                             bool whole) {
+__device__ __forceinline__ void flush_window(const MulArgs& M, const unsigned char* win, int64_t L,
+                                             int64_t Sw, int64_t hw, bool whole) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (!whole) {
     T* d = reinterpret_cast<T*>(M.dense) + L;
     for (int64_t i = tid; i < Sw; i += BS) {
-      const T v = win[i];
+      const T v = win_load<T>(win, i, hw);
       if (v != T(0)) global_add(&d[i], v);
     }
     return;
@@ -884,7 +899,7 @@ __device__ __forceinline__ void flush_window(const MulArgs& M, const T* win, int
     int64_t off = 0;
     for (int64_t b = s0; b < s1; b += 64) {
       const int64_t i = b + lane;
-      const T v = i < s1 ? win[i] : T(0);
+      const T v = i < s1 ? win_load<T>(win, i, hw) : T(0);
       const bool f = v != T(0);
       const uint64_t m = __ballot(f);
       if (f) {
@@ -905,7 +920,6 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
   if (task >= M.meta->ntasks) return;
   const int64_t ib = M.task_begin[task], ie = M.task_begin[task + 1];
   const int tid = threadIdx.x;
-  T* win = reinterpret_cast<T*>(smem_raw);
   // The kernel has no static LDS, so the window starts at LDS address 0 and
   // the per-pair address arithmetic carries no base.
   constexpr uint32_t base = 0;
@@ -925,22 +939,25 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
     for (int i = tid; i < nz; i += BS) z[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     const uint32_t S8 = (uint32_t)(Sw * 8);
+    // 128-bit: the high words follow the low words (and their discard slots)
+    const int64_t hw = Sw + DENSE_DUMMY;
+    const uint32_t hi8 = (uint32_t)(hw * 8);
     if constexpr (std::is_same<T, double>::value) {
-      if (trunc) run_items<T, 3, BS, true>(M, pb, pe, L, S8, base);
-      else run_items<T, 3, BS, false>(M, pb, pe, L, S8, base);
+      if (trunc) run_items<T, 3, BS, true>(M, pb, pe, L, S8, base, hi8);
+      else run_items<T, 3, BS, false>(M, pb, pe, L, S8, base, hi8);
     } else if constexpr (std::is_same<T, I128>::value) {
-      if (trunc) run_items<T, 5, BS, true>(M, pb, pe, L, S8, base);
-      else run_items<T, 5, BS, false>(M, pb, pe, L, S8, base);
+      if (trunc) run_items<T, 5, BS, true>(M, pb, pe, L, S8, base, hi8);
+      else run_items<T, 5, BS, false>(M, pb, pe, L, S8, base, hi8);
     } else if (trunc) {   // truncated products: one (int64) coefficient kind
-      run_items<T, 0, BS, true>(M, pb, pe, L, S8, base);
+      run_items<T, 0, BS, true>(M, pb, pe, L, S8, base, hi8);
     } else {
-      if (narrow & 4u) run_items<T, 4, BS, false>(M, pb, pe, L, S8, base);
-      else if (narrow & 2u) run_items<T, 2, BS, false>(M, pb, pe, L, S8, base);
-      else if (narrow & 1u) run_items<T, 1, BS, false>(M, pb, pe, L, S8, base);
-      else run_items<T, 0, BS, false>(M, pb, pe, L, S8, base);
+      if (narrow & 4u) run_items<T, 4, BS, false>(M, pb, pe, L, S8, base, hi8);
+      else if (narrow & 2u) run_items<T, 2, BS, false>(M, pb, pe, L, S8, base, hi8);
+      else if (narrow & 1u) run_items<T, 1, BS, false>(M, pb, pe, L, S8, base, hi8);
+      else run_items<T, 0, BS, false>(M, pb, pe, L, S8, base, hi8);
     }
     __syncthreads();
-    flush_window<T, BS>(M, win, L, Sw, !M.accumulate && pb == wb && pe == we);
+    flush_window<T, BS>(M, smem_raw, L, Sw, hw, !M.accumulate && pb == wb && pe == we);
   }
 }
 

@@ -4,7 +4,10 @@
 // every compute unit with one 1024-thread workgroup holding a 128 KiB LDS
 // array and times atomic adds of 64-bit or 32-bit counters at two address
 // patterns: consecutive counters per wavefront (no bank conflicts) and
-// pseudo-random counters (the conflicts of data-dependent addresses).
+// pseudo-random counters (the conflicts of data-dependent addresses).  A
+// fifth pattern times the 128-bit accumulation of exact products: at random
+// slots of two 64 KiB word arrays, a returning add on the low word, then an
+// add of the carry into the high word, eight pairs in flight per lane.
 #include "kp_internal.h"
 
 namespace kp {
@@ -46,9 +49,45 @@ __global__ void __launch_bounds__(PROBE_BLOCK) k_lds_atomic_probe(unsigned long 
   if (tid == 0) out[blockIdx.x % 16] = (unsigned long long)buf[0] + buf[PROBE_SLOTS - 1];   // keeps the adds
 }
 
+constexpr int PAIR_WORDS = PROBE_BYTES / 16;   // slots of each word array
+constexpr int PAIR_UNROLL = 8;
+
+__global__ void __launch_bounds__(PROBE_BLOCK) k_lds_pair_probe(unsigned long long* out, int iters) {
+  __shared__ unsigned long long lo[PAIR_WORDS];
+  __shared__ unsigned long long hi[PAIR_WORDS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < PAIR_WORDS; i += PROBE_BLOCK) lo[i] = hi[i] = 0;
+  __syncthreads();
+  uint32_t slot[PAIR_UNROLL];
+#pragma unroll
+  for (int u = 0; u < PAIR_UNROLL; ++u) {
+    uint32_t h = (uint32_t)(tid * PAIR_UNROLL + u) * 2654435761u + blockIdx.x * 40503u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    slot[u] = h & (PAIR_WORDS - 1);
+  }
+  const unsigned long long v = 0xF0000000F0000000ull + (unsigned long long)tid;
+  for (int it = 0; it < 2 * iters; ++it) {
+    unsigned long long old[PAIR_UNROLL];
+    uint32_t s[PAIR_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PAIR_UNROLL; ++u) {
+      s[u] = (slot[u] + (uint32_t)it * 977u) & (PAIR_WORDS - 1);
+      old[u] = atomicAdd(&lo[s[u]], v);
+    }
+#pragma unroll
+    for (int u = 0; u < PAIR_UNROLL; ++u) atomicAdd(&hi[s[u]], (old[u] + v < old[u]) ? 2ull : 1ull);
+  }
+  __syncthreads();
+  if (tid == 0) out[blockIdx.x % 16] = lo[0] + hi[PAIR_WORDS - 1];   // keeps the adds
+}
+
 }  // namespace
 
-// pattern: 0/1 = 64-bit consecutive/random, 2/3 = 32-bit consecutive/random.
+// pattern: 0/1 = 64-bit consecutive/random, 2/3 = 32-bit consecutive/random,
+// 4 = random 128-bit carry pairs (16 pairs per lane per iteration, as the
+// other patterns make 16 adds).
 hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
                             float* ms, hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
@@ -70,9 +109,12 @@ hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long lo
           hipLaunchKernelGGL((k_lds_atomic_probe<unsigned int, 0>), dim3(blocks), dim3(PROBE_BLOCK),
                              0, s, sink, iters);
           break;
-        default:
+        case 3:
           hipLaunchKernelGGL((k_lds_atomic_probe<unsigned int, 1>), dim3(blocks), dim3(PROBE_BLOCK),
                              0, s, sink, iters);
+          break;
+        default:
+          hipLaunchKernelGGL(k_lds_pair_probe, dim3(blocks), dim3(PROBE_BLOCK), 0, s, sink, iters);
           break;
       }
       if (e == hipSuccess) e = hipGetLastError();

@@ -63,7 +63,7 @@ def test_hash_stats_poisson_counts_both_pieces():
     assert extra >= 0
 
 
-@pytest.mark.parametrize("pattern", [0, 1, 2, 3])
+@pytest.mark.parametrize("pattern", [0, 1, 2, 3, 4])
 def test_lds_atomic_probe(pattern):
     ctx = kp.context()
     say("lds atomic probe pattern", pattern)

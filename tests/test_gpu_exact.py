@@ -215,3 +215,56 @@ def test_exact_codes_path_batch_and_errors():
     ge, gc, _ = gpu_exact((ea[:0], ca[:0]), (eb, cb), "auto")
     assert len(ge) == 0 and gc.shape == (0, 2)
 
+
+
+P31 = (1 << 31) - 1   # prime; residues below 2^31 keep every product within 64 bits
+
+
+def _eval_mod(exps, coef_mod, point):
+    """sum_i c_i prod_v point_v^e_iv modulo P31 (exponents >= 0), vectorised."""
+    acc = np.asarray(coef_mod, np.uint64) % P31
+    for v in range(exps.shape[1]):
+        e = exps[:, v].astype(np.int64)
+        assert e.min() >= 0
+        table = np.ones(int(e.max()) + 1, np.uint64)
+        for k in range(1, len(table)):
+            table[k] = table[k - 1] * np.uint64(point[v]) % P31
+        acc = acc * table[e] % P31
+    return int(acc.sum(dtype=object) % P31)
+
+
+def _words_mod(words):
+    """(hi * 2^64 + lo) mod P31 of int64 [n, 2] words, the sum read unsigned."""
+    lo = words[:, 0].view(np.uint64)
+    hi = words[:, 1].view(np.uint64)
+    t = np.uint64((1 << 64) % P31)
+    return ((hi % P31) * t + lo % P31) % P31
+
+
+def test_exact_mp_sparse_full_size_evaluation():
+    """Section 5's sparse benchmark at full size (3.8e7 pairs, 5.8 million
+    terms, products up to 1.3e22): the exact product evaluated modulo a
+    prime at random points equals f(point) g(point), and its low words are
+    the int64 product."""
+    f, g = I.mp_sparse(12, "f"), I.mp_sparse(12, "g")
+    say("MP-sparse k=12, exact, auto mode")
+    ex, co, _ = gpu_exact(f, g, "auto")
+    say("MP-sparse k=12, int64, auto mode")
+    pa = kp.Poly(dev(f[0]), dev(f[1]))
+    pb = kp.Poly(dev(g[0]), dev(g[1]))
+    r, _ = kp.mul_laurent(pa, pb)
+    e64, c64 = r.exps.cpu().numpy(), r.coef.cpu().numpy()
+    assert len(ex) == 5821335
+    # low words against the int64 product (both orders: sort by code-like key)
+    assert_exact([ex], co[:, 0], [e64], c64, "low words of the exact product")
+    # the values: nonnegative factors, so every sum is nonnegative and the
+    # unsigned reading applies; all fit far below 2^127 here
+    assert (co[:, 1] >= 0).all()
+    rng = np.random.default_rng(1231)
+    cm = _words_mod(co)
+    for _ in range(2):
+        pt = [int(x) for x in rng.integers(2, P31, 5)]
+        lhs = _eval_mod(ex, cm, pt)
+        rhs = _eval_mod(f[0], np.asarray(f[1], np.uint64) % P31, pt) * \
+            _eval_mod(g[0], np.asarray(g[1], np.uint64) % P31, pt) % P31
+        assert lhs == rhs
