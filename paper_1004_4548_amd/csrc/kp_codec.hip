@@ -84,7 +84,7 @@ k_minmax(int64_t n, int32_t nv, const int32_t* __restrict__ vals, int32_t* out) 
 // cross-block atomics; each workgroup publishes its own array's box and
 // sequence slot.
 constexpr int BOX_BLOCK = 1024;
-constexpr int64_t BOX_ONE_ROWS = 8192;
+constexpr int64_t BOX_ONE_ROWS = 2048;
 
 __global__ void __launch_bounds__(BOX_BLOCK) k_boxes_one(BoxArgs A) {
   __shared__ int32_t smin[KP_MAX_VARS][BOX_BLOCK / 64];
@@ -171,15 +171,34 @@ __global__ void __launch_bounds__(CODEC_BLOCK) k_boxes(BoxArgs A) {
     lo[v] = INT_MAX;
     hi[v] = INT_MIN;
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  // the rows as one flat run of n * nv words (word w belongs to variable
+  // w % nv), BOX_UNROLL loads in flight per thread: one round of loads when
+  // the grid is sized for it
+  constexpr int BOX_UNROLL = 8;
+  const int64_t words = n * nv;
+  const int64_t T = (int64_t)gridDim.x * CODEC_BLOCK;
+  const int step = (int)(T % nv);
+  for (int64_t w0 = (int64_t)blockIdx.x * CODEC_BLOCK + threadIdx.x; w0 < words;
+       w0 += T * BOX_UNROLL) {
+    int32_t x[BOX_UNROLL];
 #pragma unroll
-    for (int v = 0; v < KP_MAX_VARS; ++v) {
-      if (v < nv) {
-        const int32_t x = vals[i * nv + v];
-        lo[v] = min(lo[v], x);
-        hi[v] = max(hi[v], x);
+    for (int u = 0; u < BOX_UNROLL; ++u) {
+      const int64_t w = w0 + (int64_t)u * T;
+      x[u] = w < words ? vals[w] : 0;
+    }
+    int v = (int)(w0 % nv);
+#pragma unroll
+    for (int u = 0; u < BOX_UNROLL; ++u) {
+      if (w0 + (int64_t)u * T < words) {
+#pragma unroll
+        for (int q = 0; q < KP_MAX_VARS; ++q)
+          if (q == v) {
+            lo[q] = min(lo[q], x[u]);
+            hi[q] = max(hi[q], x[u]);
+          }
       }
+      v += step;
+      if (v >= nv) v -= nv;
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -456,12 +475,15 @@ hipError_t launch_degrees(const DevLayout& LA, const DevLayout& LB, const TruncS
 }
 
 hipError_t launch_boxes(const BoxArgs& A, hipStream_t s) {
-  int64_t n = 0;
-  for (int g = 0; g < A.nseg; ++g) n = std::max(n, A.n[g]);
+  int64_t n = 0, words = 0;
+  for (int g = 0; g < A.nseg; ++g) {
+    n = std::max(n, A.n[g]);
+    words = std::max(words, A.n[g] * (int64_t)A.nv[g]);
+  }
   if (n <= BOX_ONE_ROWS) {
     hipLaunchKernelGGL(k_boxes_one, dim3(A.nseg), dim3(BOX_BLOCK), 0, s, A);
   } else {
-    const int gx = grid_for(n, CODEC_BLOCK * 8, 512);   // about 8 rows per thread
+    const int gx = grid_for(words, CODEC_BLOCK * 8, 512);   // one round of 8 words per thread
     hipLaunchKernelGGL(k_boxes, dim3(gx, A.nseg), dim3(CODEC_BLOCK), 0, s, A);
   }
   return hipGetLastError();

@@ -22,7 +22,10 @@
 // with row 16g + u of the item in instruction u, the row's code and
 // coefficient being broadcast inside each 16-lane row by DPP row_newbcast:u,
 // which folds into the add and the 24-bit multiplies.  The four rows of an
-// instruction lie 16 rows apart, so their slots rarely coincide.  The edge test is one
+// instruction lie 16 rows apart, so their slots rarely coincide.  An item of
+// n < 64 rows (the last of a range) takes only R = 4 ceil(n / 16)
+// instructions, lane 16g + u then holding row R g + u: at most 15 idle rows
+// per range instead of 63.  The edge test is one
 // unsigned min that sends an out-of-window pair to a per-lane discard slot.
 //
 // Launches (one stream):
@@ -82,10 +85,13 @@ constexpr uint32_t ROW_SENTINEL = 0x80000000u;
 constexpr uint32_t LANE_SENTINEL = 0x40000000u;
 
 // Per-window planning records, stored as five arrays of nwin + 1 entries.
-enum { W_ITEMS = 0, W_ROWS = 1, W_SPLIT = 2, W_IBASE = 3, W_CBASE = 4 };
-// Cost of a window to a task, in work items, beyond its items: clearing the
-// LDS window, the first loads and the flush.
-constexpr int64_t WINDOW_COST = 64;
+enum { W_ITEMS = 0, W_COST = 1, W_SPLIT = 2, W_IBASE = 3, W_CBASE = 4 };
+// Task costs count blocks of four instructions: 4 for an item of 64 rows,
+// ceil(n / 16) for a shorter one (its instructions, over four).  Equal item
+// counts per task left the busiest task 11 % above the median.
+// Cost of a window to a task beyond its items (clearing the LDS window, the
+// first loads and the flush): that of 64 full items.
+constexpr int64_t WINDOW_COST = 64 * 4;
 
 __device__ __forceinline__ int64_t readlane64(uint64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
@@ -389,23 +395,62 @@ __device__ __forceinline__ int64_t items_of(const int4& r) {
   return chunks(r.y - r.x) + chunks(r.z - r.y) + chunks(r.w - r.z);
 }
 
-// Item k of a tile with rows {i0, c0, c1, i1}: first row, rows, core flag.
+// Cost of a run of n rows cut into items (every item but the last is full),
+// of a tile's three runs, of an item of n rows, and of the items of a tile
+// before its item k.
+__device__ __forceinline__ int64_t run_cost(int64_t n) {
+  return 4 * (n / DENSE_ITEM_ROWS) + (n % DENSE_ITEM_ROWS + 15) / 16;
+}
+__device__ __forceinline__ int64_t cost_of(const int4& r) {
+  return run_cost(r.y - r.x) + run_cost(r.z - r.y) + run_cost(r.w - r.z);
+}
+__device__ __forceinline__ int64_t item_cost(int64_t n) { return (n + 15) / 16; }
+// Exclusive block scan of each thread's items and cost.  When every thread
+// holds fewer than 2^21 items the window has fewer than 2^31, and items (high
+// 31 bits) and cost (at most 4 per item, low 33 bits) are scanned as one
+// value; otherwise in two scans.
+constexpr int COST_BITS = 33;
+__device__ __forceinline__ void scan_items_cost(int64_t nit, int64_t cost, int64_t* s_wave,
+                                                int64_t* q, int64_t* qc, int64_t* tot_items,
+                                                int64_t* tot_cost) {
+  if (!__syncthreads_or(nit >= ((int64_t)1 << 21))) {
+    int64_t tot;
+    const uint64_t v = (uint64_t)block_exclusive_scan<PLAN_BLOCK>(
+        (int64_t)(((uint64_t)nit << COST_BITS) | (uint64_t)cost), s_wave, &tot);
+    const uint64_t mask = ((uint64_t)1 << COST_BITS) - 1;
+    *q = (int64_t)(v >> COST_BITS);
+    *qc = (int64_t)(v & mask);
+    *tot_items = (int64_t)((uint64_t)tot >> COST_BITS);
+    *tot_cost = (int64_t)((uint64_t)tot & mask);
+  } else {
+    *q = block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, tot_items);
+    *qc = block_exclusive_scan<PLAN_BLOCK>(cost, s_wave, tot_cost);
+  }
+}
+
+
+// Item k of a tile with rows {i0, c0, c1, i1}: first row, rows, core flag,
+// and the cost of the tile's items before it (every item of a run but the
+// last is full, cost 4).
 __device__ __forceinline__ void item_rows(const int4& r, int64_t k, int64_t* r0, int64_t* n,
-                                          bool* core) {
+                                          bool* core, int64_t* before) {
   const int64_t e1 = chunks(r.y - r.x), ec = chunks(r.z - r.y);
   int64_t hi;
   if (k < e1) {
     *r0 = r.x + k * DENSE_ITEM_ROWS;
     hi = r.y;
     *core = false;
+    *before = 4 * k;
   } else if (k < e1 + ec) {
     *r0 = r.y + (k - e1) * DENSE_ITEM_ROWS;
     hi = r.z;
     *core = true;
+    *before = run_cost(r.y - r.x) + 4 * (k - e1);
   } else {
     *r0 = r.z + (k - e1 - ec) * DENSE_ITEM_ROWS;
     hi = r.w;
     *core = false;
+    *before = run_cost(r.y - r.x) + run_cost(r.z - r.y) + 4 * (k - e1 - ec);
   }
   *n = min(DENSE_ITEM_ROWS, hi - *r0);
   *core = *core && *n == DENSE_ITEM_ROWS;
@@ -422,7 +467,7 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   int4* rec = P.recs + w * P.ntiles;
   int64_t t0, t1;
   thread_tiles(P.ntiles, &t0, &t1);
-  int64_t nit = 0, rows = 0;
+  int64_t nit = 0, cost = 0;
   constexpr int BATCH = 4;   // tiles whose loads are issued together
   for (int64_t t = t0; t < t1; t += BATCH) {
     TileRows g[BATCH];
@@ -434,15 +479,14 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
         const int4 r = make_int4((int)g[u].i0, (int)g[u].c0, (int)g[u].c1, (int)g[u].i1);
         rec[t + u] = r;
         nit += items_of(r);
-        rows += g[u].i1 - g[u].i0;
+        cost += cost_of(r);
       }
   }
-  int64_t tot_items, tot_rows;
-  block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tot_items);
-  block_exclusive_scan<PLAN_BLOCK>(rows, s_wave, &tot_rows);
+  int64_t q, qc, tot_items, tot_cost;
+  scan_items_cost(nit, cost, s_wave, &q, &qc, &tot_items, &tot_cost);
   if (tid == 0) {
     P.win[W_ITEMS * W1 + w] = tot_items;
-    P.win[W_ROWS * W1 + w] = tot_rows;
+    P.win[W_COST * W1 + w] = tot_cost;
     __threadfence();
     s_last = atomicAdd(&P.meta->plan_done, 1u) == (uint32_t)(P.nwin - 1);
   }
@@ -457,23 +501,27 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   const int64_t w0 = min(P.nwin, tid * per), w1 = min(w0 + per, P.nwin);
   // each thread's windows, read once (kept in registers for up to 4)
   constexpr int KEEP = 4;
-  int64_t kept[KEEP];
-  int64_t li = 0, lc = 0;   // items, and cost: items plus WINDOW_COST when any
+  int64_t kept[KEEP], kept_c[KEEP];
+  int64_t li = 0, lc = 0;   // items, and cost: the items' plus WINDOW_COST when any
   for (int64_t u = w0; u < w1; ++u) {
-    const int64_t it = ld(W_ITEMS, u);
-    if (u - w0 < KEEP) kept[u - w0] = it;
+    const int64_t it = ld(W_ITEMS, u), ct = ld(W_COST, u);
+    if (u - w0 < KEEP) {
+      kept[u - w0] = it;
+      kept_c[u - w0] = ct;
+    }
     li += it;
-    lc += it > 0 ? it + WINDOW_COST : 0;
+    lc += it > 0 ? ct + WINDOW_COST : 0;
   }
   int64_t all_items, all_cost;
   int64_t ibase = block_exclusive_scan<PLAN_BLOCK>(li, s_wave, &all_items);
   int64_t cbase = block_exclusive_scan<PLAN_BLOCK>(lc, s_wave, &all_cost);
   for (int64_t u = w0; u < w1; ++u) {
     const int64_t it = u - w0 < KEEP ? kept[u - w0] : ld(W_ITEMS, u);
+    const int64_t ct = u - w0 < KEEP ? kept_c[u - w0] : ld(W_COST, u);
     P.win[W_IBASE * W1 + u] = ibase;
     P.win[W_CBASE * W1 + u] = cbase;
     ibase += it;
-    cbase += it > 0 ? it + WINDOW_COST : 0;
+    cbase += it > 0 ? ct + WINDOW_COST : 0;
   }
   // No work after a factor code outside its box (reported by the scan
   // kernel), or past the planned item bound (which cannot happen).
@@ -481,10 +529,10 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   if (tid == 0) {
     P.win[W_IBASE * W1 + P.nwin] = all_items;
     P.win[W_CBASE * W1 + P.nwin] = all_cost;
-    // tasks of equal cost T (more than one window's overhead plus an item):
+    // tasks of equal cost T (more than one window's overhead plus an item's):
     // task p starts at the item whose cost interval holds p * T
     int64_t T = (all_cost + P.target - 1) / P.target;
-    if (T < WINDOW_COST + 1) T = WINDOW_COST + 1;
+    if (T < WINDOW_COST + 4) T = WINDOW_COST + 4;
     int64_t nt = all_cost > 0 ? (all_cost + T - 1) / T : 0;
     if (bad || all_items > P.items_cap) {
       P.meta->err |= bad ? bad : ERR_CAPACITY;
@@ -498,14 +546,15 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
 
 // Item k of window w: its descriptor, and the first item (and window) of the
 // task that starts at it, if any.  Item k covers the cost interval
-// [cb + WINDOW_COST + k, +1) (the first item also covers the window's
-// overhead [cb, cb + WINDOW_COST)); task p starts at the item whose interval
-// holds p * T.
+// [cb + WINDOW_COST + c, + item_cost(n)), c the cost of the window's items
+// before it (the first item also covers the window's overhead
+// [cb, cb + WINDOW_COST)); task p starts at the item whose interval holds
+// p * T.
 __device__ __forceinline__ void put_item(const PlanArgs& P, int64_t w, int64_t ib, int64_t k,
-                                         int64_t cb, int64_t r0, int64_t t, int64_t n, bool core,
-                                         int64_t T, double rT, int* s_split) {
+                                         int64_t cb, int64_t c, int64_t r0, int64_t t, int64_t n,
+                                         bool core, int64_t T, double rT, int* s_split) {
   P.items[ib + k] = pack_item(r0, t, n, core);
-  const int64_t lo = k == 0 ? cb : cb + WINDOW_COST + k, hi = cb + WINDOW_COST + k + 1;
+  const int64_t lo = k == 0 ? cb : cb + WINDOW_COST + c, hi = cb + WINDOW_COST + c + item_cost(n);
   // smallest p with p * T >= lo (the quotient is exact in double below 2^52)
   int64_t p = (int64_t)ceil((double)lo * rT);
   while (p > 0 && (p - 1) * T >= lo) --p;
@@ -535,20 +584,25 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
   const double rT = 1.0 / (double)T;
   const int4* rec = P.recs + w * P.ntiles;
   const int64_t nt = P.ntiles;
-  // LDS: the window's tile rows, per-tile item prefix, tile of every item
+  // LDS: the window's tile rows, per-tile item and cost prefixes, tile of
+  // every item
   int4* s_rec = reinterpret_cast<int4*>(smem_raw);
   int32_t* s_ip = reinterpret_cast<int32_t*>(s_rec + nt);
-  int32_t* s_of = s_ip + nt + 1;
-  const bool in_lds = (size_t)nt * 20 + 4 + (size_t)nit_w * 4 <= (size_t)P.items_lds;
+  int32_t* s_cp = s_ip + nt + 1;
+  int32_t* s_of = s_cp + nt + 1;
+  const bool in_lds = (size_t)nt * 24 + 8 + (size_t)nit_w * 4 <= (size_t)P.items_lds;
   int64_t t0, t1;
   thread_tiles(nt, &t0, &t1);
   if (in_lds) {
     for (int64_t t = tid; t < nt; t += PLAN_BLOCK) s_rec[t] = rec[t];
     __syncthreads();
-    int64_t nit = 0;
-    for (int64_t t = t0; t < t1; ++t) nit += items_of(s_rec[t]);
-    int64_t tq;
-    int64_t q = block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tq);
+    int64_t nit = 0, ncost = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+      nit += items_of(s_rec[t]);
+      ncost += cost_of(s_rec[t]);
+    }
+    int64_t q, qc, tq, tqc;
+    scan_items_cost(nit, ncost, s_wave, &q, &qc, &tq, &tqc);
     for (int64_t k = tid; k < nit_w; k += PLAN_BLOCK) s_of[k] = -1;
     __syncthreads();
     // each non-empty tile marks its first item; a max-scan over the items
@@ -556,8 +610,10 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
     for (int64_t t = t0; t < t1; ++t) {
       const int64_t c = items_of(s_rec[t]);
       s_ip[t] = (int32_t)q;
+      s_cp[t] = (int32_t)qc;
       if (c > 0) s_of[q] = (int32_t)t;
       q += c;
+      qc += cost_of(s_rec[t]);
     }
     __syncthreads();
     const int64_t per = (nit_w + PLAN_BLOCK - 1) / PLAN_BLOCK;
@@ -573,27 +629,32 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
     __syncthreads();
     for (int64_t k = tid; k < nit_w; k += PLAN_BLOCK) {
       const int64_t t = s_of[k];
-      int64_t r0, n;
+      const int4 r = s_rec[t];
+      int64_t r0, n, before;
       bool core;
-      item_rows(s_rec[t], k - s_ip[t], &r0, &n, &core);
-      put_item(P, w, ib, k, cb, r0, t, n, core, T, rT, &s_split);
+      item_rows(r, k - s_ip[t], &r0, &n, &core, &before);
+      put_item(P, w, ib, k, cb, s_cp[t] + before, r0, t, n, core, T, rT, &s_split);
     }
   } else {
     // too large for LDS: each thread writes the items of its own tiles
-    int64_t nit = 0;
-    for (int64_t t = t0; t < t1; ++t) nit += items_of(rec[t]);
-    int64_t tq;
-    int64_t q = block_exclusive_scan<PLAN_BLOCK>(nit, s_wave, &tq);
+    int64_t nit = 0, ncost = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+      nit += items_of(rec[t]);
+      ncost += cost_of(rec[t]);
+    }
+    int64_t q, qc, tq, tqc;
+    scan_items_cost(nit, ncost, s_wave, &q, &qc, &tq, &tqc);
     for (int64_t t = t0; t < t1; ++t) {
       const int4 r = rec[t];
       const int64_t cnt = items_of(r);
       for (int64_t k = 0; k < cnt; ++k) {
-        int64_t r0, n;
+        int64_t r0, n, before;
         bool core;
-        item_rows(r, k, &r0, &n, &core);
-        put_item(P, w, ib, q + k, cb, r0, t, n, core, T, rT, &s_split);
+        item_rows(r, k, &r0, &n, &core, &before);
+        put_item(P, w, ib, q + k, cb, qc + before, r0, t, n, core, T, rT, &s_split);
       }
       q += cnt;
+      qc += cost_of(r);
     }
   }
   __syncthreads();
@@ -692,11 +753,11 @@ __device__ __forceinline__ void pair_step(uint32_t a8, uint32_t off8, uint32_t l
   lds_add(rel, v);
 }
 
-template <typename T, int MUL, bool EDGE, bool TRUNC, int... U>
+template <typename T, int MUL, bool EDGE, bool TRUNC, int G, int... U>
 __device__ __forceinline__ void item_steps(std::integer_sequence<int, U...>, uint32_t a8,
                                            uint32_t off8, uint32_t lim, uint32_t base,
                                            const Coef<T, MUL>& c, uint32_t sa, int32_t tb) {
-  (pair_step<T, MUL, EDGE, TRUNC, U>(a8, off8, lim, base, c, sa, tb), ...);
+  (pair_step<T, MUL, EDGE, TRUNC, G + U>(a8, off8, lim, base, c, sa, tb), ...);
 }
 
 // 128-bit slots (MUL 5): the low word's offset is computed as for the other
@@ -742,14 +803,33 @@ __device__ __forceinline__ void wide_group(std::integer_sequence<int, U...>, uin
   (wide_finish(addr[U], hi8, plo[U], phi[U], old[U]), ...);
 }
 
+// R instructions (4, 8, 12 or 16), in groups of up to eight.
 template <bool EDGE, bool TRUNC>
 __device__ __forceinline__ void wide_steps(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
                                            uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
-                                           int32_t tb, uint32_t hi8) {
-  wide_group<EDGE, TRUNC, 0>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
-                             bw, sa, tb, hi8);
-  wide_group<EDGE, TRUNC, 8>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo, chi,
-                             bw, sa, tb, hi8);
+                                           int32_t tb, uint32_t hi8, int R) {
+  if (R >= 8)
+    wide_group<EDGE, TRUNC, 0>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo,
+                               chi, bw, sa, tb, hi8);
+  else
+    wide_group<EDGE, TRUNC, 0>(std::make_integer_sequence<int, 4>{}, a8, off8, lim, base, clo,
+                               chi, bw, sa, tb, hi8);
+  if (R == 16)
+    wide_group<EDGE, TRUNC, 8>(std::make_integer_sequence<int, 8>{}, a8, off8, lim, base, clo,
+                               chi, bw, sa, tb, hi8);
+  else if (R == 12)
+    wide_group<EDGE, TRUNC, 8>(std::make_integer_sequence<int, 4>{}, a8, off8, lim, base, clo,
+                               chi, bw, sa, tb, hi8);
+}
+
+// Instructions of an item of n rows: 4, 8, 12 or 16, so that the four
+// 16-lane groups cover the rows in blocks of four instructions (an item of
+// 64 rows, every core item, takes all 16).  Lane 16g + u holds row R g + u
+// of the item for u < R.
+__device__ __forceinline__ int item_instr(int64_t n) { return (int)(((n + 15) >> 4) << 2); }
+__device__ __forceinline__ int item_row(int64_t n, int lane) {
+  const int R = item_instr(n), u = lane & 15;
+  return R * (lane >> 4) + (u < R ? u : R - 1);
 }
 
 struct ItemRegs {
@@ -761,15 +841,14 @@ struct ItemRegs {
 };
 
 template <bool WIDE, bool TRUNC>
-__device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane, int rowlane,
-                                           ItemRegs& x) {
+__device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane, ItemRegs& x) {
   const uint32_t lo = (uint32_t)d, hi = (uint32_t)((uint64_t)d >> 32);
   x.r0 = (int64_t)lo;
   x.t = (int64_t)(hi & 0x1FFFFFFu);
   x.n = (int64_t)((hi >> 25) & 63u) + 1;
   x.core = (hi >> 31) != 0;
   const int64_t j = min(x.t * DENSE_TILE + (lane & 15), M.nb - 1);
-  const int64_t r = x.r0 + min((int64_t)rowlane, x.n - 1);
+  const int64_t r = x.r0 + min((int64_t)item_row(x.n, lane), x.n - 1);
   x.b = M.bpk[j];
   x.a = M.apk[r];
   if (WIDE) {
@@ -784,18 +863,20 @@ __device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane
 
 template <typename T, int MUL, bool TRUNC>
 __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t lim, int lane,
-                                         int rowlane, int64_t nb, uint32_t base, uint32_t hi8) {
+                                         int64_t nb, uint32_t base, uint32_t hi8) {
   const bool vb = x.t * DENSE_TILE + (lane & 15) < nb;
   const uint32_t off8 =
       vb ? (uint32_t)(((int32_t)(uint32_t)x.b - (int32_t)L) * 8) : LANE_SENTINEL;
-  const uint32_t a8 = rowlane < x.n ? ((uint32_t)x.a << 3) : ROW_SENTINEL;
+  const int R = item_instr(x.n);   // wavefront-uniform
+  const uint32_t a8 = (lane & 15) < R && R * (lane >> 4) + (lane & 15) < x.n
+                          ? ((uint32_t)x.a << 3) : ROW_SENTINEL;
   if constexpr (MUL == 5) {
     const uint32_t clo = (uint32_t)x.ac, chi = (uint32_t)(x.ac >> 32);
     const int64_t bw = (int64_t)x.bc;
     if (x.core)
-      wide_steps<false, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8);
+      wide_steps<false, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8, 16);
     else
-      wide_steps<true, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8);
+      wide_steps<true, TRUNC>(a8, off8, lim, base, clo, chi, bw, (uint32_t)x.sa, x.tb, hi8, R);
   } else {
     Coef<T, MUL> c;
     if constexpr (MUL == 1 || MUL == 2 || MUL == 4) {
@@ -810,12 +891,17 @@ __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t 
       c.bn = 0;
       __builtin_memcpy(&c.bw, &x.bc, 8);
     }
-    if (x.core)
-      item_steps<T, MUL, false, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base,
-                                       c, (uint32_t)x.sa, x.tb);
-    else
-      item_steps<T, MUL, true, TRUNC>(std::make_integer_sequence<int, 16>{}, a8, off8, lim, base,
-                                      c, (uint32_t)x.sa, x.tb);
+    if (x.core) {
+      item_steps<T, MUL, false, TRUNC, 0>(std::make_integer_sequence<int, 16>{}, a8, off8, lim,
+                                          base, c, (uint32_t)x.sa, x.tb);
+    } else {   // R instructions, in blocks of four
+      constexpr auto q4 = std::make_integer_sequence<int, 4>{};
+      item_steps<T, MUL, true, TRUNC, 0>(q4, a8, off8, lim, base, c, (uint32_t)x.sa, x.tb);
+      if (R > 4) item_steps<T, MUL, true, TRUNC, 4>(q4, a8, off8, lim, base, c, (uint32_t)x.sa, x.tb);
+      if (R > 8) item_steps<T, MUL, true, TRUNC, 8>(q4, a8, off8, lim, base, c, (uint32_t)x.sa, x.tb);
+      if (R > 12)
+        item_steps<T, MUL, true, TRUNC, 12>(q4, a8, off8, lim, base, c, (uint32_t)x.sa, x.tb);
+    }
   }
 }
 
@@ -828,7 +914,6 @@ __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t 
   constexpr bool WIDE = MUL == 0 || MUL == 3 || MUL == 5;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int rowlane = lane;   // lane 16g + u holds row 16g + u of the item
   // out-of-window pairs go to this lane's discard slot (or, within 64 slots
   // past the window, to some discard slot)
   const uint32_t lim = S8 + (uint32_t)lane * 8;
@@ -839,14 +924,14 @@ __device__ __forceinline__ void run_items(const MulArgs& M, int64_t ib, int64_t 
     // two register sets in turn, so that no load result is copied (a copy
     // would wait for the load)
     ItemRegs x0, x1;
-    fetch_item<WIDE, TRUNC>(M, readlane64(dv, 0), lane, rowlane, x0);
+    fetch_item<WIDE, TRUNC>(M, readlane64(dv, 0), lane, x0);
     for (int k = 0; k + 1 < cnt; k += 2) {
-      fetch_item<WIDE, TRUNC>(M, readlane64(dv, k + 1), lane, rowlane, x1);
-      run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base, hi8);
-      fetch_item<WIDE, TRUNC>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, rowlane, x0);
-      run_item<T, MUL, TRUNC>(x1, L, lim, lane, rowlane, M.nb, base, hi8);
+      fetch_item<WIDE, TRUNC>(M, readlane64(dv, k + 1), lane, x1);
+      run_item<T, MUL, TRUNC>(x0, L, lim, lane, M.nb, base, hi8);
+      fetch_item<WIDE, TRUNC>(M, readlane64(dv, min(k + 2, cnt - 1)), lane, x0);
+      run_item<T, MUL, TRUNC>(x1, L, lim, lane, M.nb, base, hi8);
     }
-    if (cnt & 1) run_item<T, MUL, TRUNC>(x0, L, lim, lane, rowlane, M.nb, base, hi8);
+    if (cnt & 1) run_item<T, MUL, TRUNC>(x0, L, lim, lane, M.nb, base, hi8);
   }
 }
 
@@ -1071,7 +1156,7 @@ __global__ void __launch_bounds__(1024) k_dense_scan(ScanArgs A) {
 struct CopyArgs {
   int64_t out_cap;
   const int64_t* ccount;
-  const int64_t* coff;
+  const int64_t* coff;    // from the scan kernel (not used when the copy scans)
   const int64_t* stage_k;
   const int64_t* stage_c;
   int64_t* out_k;
@@ -1079,13 +1164,63 @@ struct CopyArgs {
   int32_t* out_x;   // optional: decoded exponents instead of codes
   DevLayout L;
   const int64_t* out_n;   // the scan's count: nothing is written after an error
+  // a copy that scans itself: the inputs and outputs of the scan kernel
+  const Meta* meta;
+  int64_t nchunk;
+  int64_t* out_n_w;
+  uint32_t* ctx_err;
+  Mailbox* mb;
+  uint64_t seq;
 };
 
-template <bool DECODE, typename T>
+// Chunks up to which the copy kernel also does the scan's work (each of its
+// workgroups sums the counts of the chunks before its own), saving a launch.
+constexpr int64_t COPY_SCAN_MAX = 4096;
+
+template <bool DECODE, typename T, bool SCAN>
 __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
-  if (*C.out_n < 0) return;
   const int64_t c = blockIdx.x;
-  const int64_t n = C.ccount[c], off = C.coff[c];
+  int64_t off;
+  if constexpr (SCAN) {
+    // this chunk's offset and the total, from the chunk counts
+    __shared__ int64_t s_wave[2][4];
+    int64_t before = 0, all = 0;
+    for (int64_t k = threadIdx.x; k < C.nchunk; k += 256) {
+      const int64_t v = C.ccount[k];
+      all += v;
+      if (k < c) before += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      before += __shfl_xor(before, o);
+      all += __shfl_xor(all, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      s_wave[0][threadIdx.x >> 6] = before;
+      s_wave[1][threadIdx.x >> 6] = all;
+    }
+    __syncthreads();
+    off = s_wave[0][0] + s_wave[0][1] + s_wave[0][2] + s_wave[0][3];
+    const int64_t total = s_wave[1][0] + s_wave[1][1] + s_wave[1][2] + s_wave[1][3];
+    // the scan kernel's checks, taken by every workgroup on the same inputs
+    uint32_t e = C.meta->err | C.meta->seg_err[0] | C.meta->seg_err[1] | *C.ctx_err;
+    if (total > C.out_cap) e |= ERR_CAPACITY;
+    if (c == 0 && threadIdx.x == 0) {
+      const int64_t n = e ? -(int64_t)first_error(e) : total;
+      if (e) atomicOr(C.ctx_err, e);
+      *C.out_n_w = n;
+      if (C.mb) {   // the waiting host needs only the count
+        C.mb->n = n;
+        C.mb->err = e;
+        __threadfence_system();
+        __hip_atomic_store(&C.mb->n_seq, C.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    if (e) return;
+  } else {
+    if (*C.out_n < 0) return;
+    off = C.coff[c];
+  }
+  const int64_t n = C.ccount[c];
   const int64_t* sk = C.stage_k + c * DENSE_CHUNK;
   const T* sc = reinterpret_cast<const T*>(C.stage_c) + c * DENSE_CHUNK;
   T* out_c = reinterpret_cast<T*>(C.out_c);
@@ -1214,18 +1349,28 @@ hipError_t launch_dense_laurent(const DensePlan& P, const DenseBufs& B, kp_dtype
   else
     hipLaunchKernelGGL(k_dense_combine<int64_t>, dim3(cgrid), dim3(COMBINE_BLOCK), 0, s, cb);
 
-  ScanArgs sa{B.meta, P.nchunk, B.out_cap, B.ccount, B.coff, B.out_n, B.ctx_err, B.mb, B.seq};
-  hipLaunchKernelGGL(k_dense_scan, dim3(1), dim3(1024), 0, s, sa);
   CopyArgs ca{B.out_cap, B.ccount, B.coff, B.stage_k, B.stage_c, B.out_k,
-              reinterpret_cast<int64_t*>(B.out_c), B.out_exps, B.dec, B.out_n};
-  const dim3 cg((unsigned)P.nchunk);
-  if (dt == KP_I128) {
-    if (B.out_exps) hipLaunchKernelGGL((k_dense_copy<true, I128>), cg, dim3(256), 0, s, ca);
-    else hipLaunchKernelGGL((k_dense_copy<false, I128>), cg, dim3(256), 0, s, ca);
-  } else {
-    if (B.out_exps) hipLaunchKernelGGL((k_dense_copy<true, int64_t>), cg, dim3(256), 0, s, ca);
-    else hipLaunchKernelGGL((k_dense_copy<false, int64_t>), cg, dim3(256), 0, s, ca);
+              reinterpret_cast<int64_t*>(B.out_c), B.out_exps, B.dec, B.out_n,
+              B.meta, P.nchunk, B.out_n, B.ctx_err, B.mb, B.seq};
+  const bool scan_in_copy = P.nchunk <= COPY_SCAN_MAX;
+  if (!scan_in_copy) {
+    ScanArgs sa{B.meta, P.nchunk, B.out_cap, B.ccount, B.coff, B.out_n, B.ctx_err, B.mb, B.seq};
+    hipLaunchKernelGGL(k_dense_scan, dim3(1), dim3(1024), 0, s, sa);
   }
+  const dim3 cg((unsigned)P.nchunk);
+#define KP_COPY(DEC, TT)                                                                        \
+  do {                                                                                          \
+    if (scan_in_copy) hipLaunchKernelGGL((k_dense_copy<DEC, TT, true>), cg, dim3(256), 0, s, ca); \
+    else hipLaunchKernelGGL((k_dense_copy<DEC, TT, false>), cg, dim3(256), 0, s, ca);           \
+  } while (0)
+  if (dt == KP_I128) {
+    if (B.out_exps) KP_COPY(true, I128);
+    else KP_COPY(false, I128);
+  } else {
+    if (B.out_exps) KP_COPY(true, int64_t);
+    else KP_COPY(false, int64_t);
+  }
+#undef KP_COPY
   return hipGetLastError();
 }
 
