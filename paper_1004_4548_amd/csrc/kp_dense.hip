@@ -51,8 +51,11 @@
 //                added into an HBM accumulator with device-scope atomics.
 //  6. combine -- one workgroup per chunk of a window split across tasks:
 //                compacts the accumulated chunk.
-//  7. scan    -- one workgroup: output offset of every chunk, result count.
-//  8. copy    -- one workgroup per chunk: moves the chunk to its offset.
+//  7. scan    -- one workgroup: output offset of every chunk, result count
+//                (products of more than COPY_SCAN_MAX chunks only).
+//  8. copy    -- one workgroup per chunk: moves the chunk to its offset; for
+//                at most COPY_SCAN_MAX chunks it sums the counts before its
+//                own and the first workgroup publishes the result count.
 //
 // 128-bit coefficients (exact int64 products): a window holds half as many
 // codes, as two arrays of 64-bit words, the low words of its slots followed
