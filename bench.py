@@ -165,9 +165,42 @@ def hash_probe_stats(kp, ctx, fn):
     ctx.hash_stats_read()
     ctx.hash_stats(True)
     fn()
-    ins, extra = ctx.hash_stats_read()
+    ins, extra, ovf = ctx.hash_stats_read()
     ctx.hash_stats(False)
-    return {"inserts": ins, "extra_probes_per_insert": extra / max(ins, 1)}
+    out = {"inserts": ins, "extra_probes_per_insert": extra / max(ins, 1)}
+    if ovf:
+        out["overflow_inserts"] = ovf
+    return out
+
+
+def compare_layouts(kp, ctx, a, b, steps=3):
+    """Section 3.2's bucketed table (8 slots per bucket, code mod N, with and
+    without the term order by code mod N) against open addressing in one HBM
+    table: step time, insert kernel time and probe statistics of each."""
+    saved = ctx.tune
+    base = {f: getattr(saved, f) for f, _ in type(saved)._fields_}
+    pa = kp.Poly(to_dev(a[0]), to_dev(a[1]))
+    pb = kp.Poly(to_dev(b[0]), to_dev(b[1]))
+    ws = kp.Workspace()
+    out = {}
+    layouts = {"open_addressing": dict(hash_partitioned=0, hash_bucket=0),
+               "bucketed_m8_ordered": dict(hash_partitioned=0, hash_bucket=8, hash_order=1),
+               "bucketed_m8_unordered": dict(hash_partitioned=0, hash_bucket=8, hash_order=0)}
+    try:
+        for name, t in layouts.items():
+            ctx.set_tune(**{**base, **t})
+            step = lambda: laurent_step(kp, ctx, ws, pa, pb, "hash")
+            sec = time_steps(step, steps, 1)
+            ctx.timing_read()
+            ctx.timing(True)
+            time_steps(step, steps, 0)
+            kms, launches = ctx.timing_read()
+            ctx.timing(False)
+            out[name] = {"ms_per_step": sec * 1e3, "insert_kernel_ms": kms / max(launches, 1),
+                         **hash_probe_stats(kp, ctx, step)}
+    finally:
+        ctx.set_tune(**base)
+    return out
 
 
 def run_box(kp, ctx, I, args):
@@ -190,6 +223,7 @@ def run_sparse(kp, ctx, I, args):
         pb = kp.Poly(to_dev(b3[0]), to_dev(b3[1]))
         out["probing"] = hash_probe_stats(
             kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "auto"))
+    out["hash_layouts"] = compare_layouts(kp, ctx, a3, b3)
     return out
 
 
@@ -229,6 +263,7 @@ def run_mp(kp, ctx, I, args):
         pb = kp.Poly(to_dev(g[0]), to_dev(g[1]))
         out["probing"] = hash_probe_stats(
             kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "auto"))
+    out["hash_layouts"] = compare_layouts(kp, ctx, f, g, steps=5)
     return out
 
 

@@ -137,6 +137,17 @@ typedef struct kp_tune {
                                (workspace 32 bytes per product); 0 = one open-addressing
                                table in HBM; 1 (default) = grouped when the products are
                                at most 4 times the result bound, else the table          */
+  int32_t hash_bucket;      /* hash, Laurent, int64/fp64: > 0 selects Section 3.2's bucketed
+                               table instead of the above, with this many slots per bucket
+                               (1 .. 16): product code e goes to bucket e mod N, where it is
+                               added to the slot holding e or appended; a full bucket sends
+                               it to an overflow table (open addressing, six times the
+                               codes expected to overflow if the bound's codes spread over
+                               the buckets as a Poisson variable, at least 1024 slots); a
+                               full overflow table is KP_E_CAPACITY.  0 (default) = not
+                               used                                                       */
+  int32_t hash_order;       /* bucketed table: 1 (default) orders both factors' terms by
+                               code mod N first (Section 3.2's term order), 0 keeps them  */
 } kp_tune;
 
 typedef struct kp_ctx kp_ctx;
@@ -184,12 +195,13 @@ kp_status kp_ctx_clear_truncation(kp_ctx* ctx);
    context's status block: the number of term products inserted (nonzero
    ones) and the number of slots visited beyond each product's home slot.
    Their ratio is the mean extra probe length the load factor buys.
-   kp_ctx_hash_stats_read synchronises `stream`, returns both counts and
-   clears them.  Enabling costs one atomic pair per wavefront per launch.
+   kp_ctx_hash_stats_read synchronises `stream`, returns both counts and, for
+   the bucketed table, the products sent to its overflow table (overflows may
+   be null), and clears them.  Enabling costs one atomic pair per wavefront per launch.
    Disabled by default. */
 kp_status kp_ctx_hash_stats(kp_ctx* ctx, int enable);
 kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inserts,
-                                 int64_t* extra_probes);
+                                 int64_t* extra_probes, int64_t* overflows);
 
 /* Measured denominator of the dense window kernel's roofline (Section 3.1:
    the dense accumulation is one read-modify-write of a counter per term

@@ -66,7 +66,8 @@ class Tune(C.Structure):
     _fields_ = [("window", C.c_int32), ("block", C.c_int32), ("tasks_per_cu", C.c_int32),
                 ("hash_load", C.c_double), ("hash_capacity", C.c_int64),
                 ("dense_max_keys", C.c_int64), ("dense_keys_per_pair", C.c_double),
-                ("hash_rows", C.c_int32), ("hash_partitioned", C.c_int32)]
+                ("hash_rows", C.c_int32), ("hash_partitioned", C.c_int32),
+                ("hash_bucket", C.c_int32), ("hash_order", C.c_int32)]
 
 
 class MulDesc(C.Structure):
@@ -121,7 +122,7 @@ def lib():
         "kp_batch_launch": (i32, [p, u32, p]),
         "kp_batch_status": (i32, [p, i64, C.POINTER(i64)]),
         "kp_ctx_hash_stats": (i32, [p, i32]),
-        "kp_ctx_hash_stats_read": (i32, [p, p, C.POINTER(i64), C.POINTER(i64)]),
+        "kp_ctx_hash_stats_read": (i32, [p, p, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "kp_probe_lds_atomic": (i32, [p, i32, C.POINTER(C.c_double), p]),
         "kp_plan_laurent": (i32, [p, i32, i32, i32, p, i64, p, i64, C.POINTER(Layout),
                                   C.POINTER(i32), C.POINTER(i64), C.POINTER(sz), p]),
@@ -272,11 +273,14 @@ class Context:
         self.check(lib().kp_ctx_hash_stats(self.h, 1 if enable else 0))
 
     def hash_stats_read(self, stream=None):
-        """(insertions, slots visited beyond the home slots) since the last read."""
+        """(insertions, slots visited beyond the home slots, insertions sent to
+        the bucketed table's overflow table) since the last read."""
         n = C.c_int64()
         x = C.c_int64()
-        self.check(lib().kp_ctx_hash_stats_read(self.h, _stream(stream), C.byref(n), C.byref(x)))
-        return n.value, x.value
+        o = C.c_int64()
+        self.check(lib().kp_ctx_hash_stats_read(self.h, _stream(stream), C.byref(n), C.byref(x),
+                                                C.byref(o)))
+        return n.value, x.value, o.value
 
     def probe_lds_atomic(self, pattern=0, stream=None):
         """Device-wide LDS atomic adds per second: 0/1 = 64-bit counters,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <climits>
@@ -238,6 +239,11 @@ struct Plan {
   int64_t nblocks = 0, nprod = 0;
   bool trunc = false;   // truncation tables follow the mode's workspace
   int cw = 1;           // 64-bit words per result coefficient (2 for KP_I128)
+  // bucketed table: slots per bucket, buckets, overflow slots, term order
+  bool bucket = false;
+  int bm = 0;
+  int64_t nbuckets = 0, ovcap = 0;
+  bool order = false;
 };
 
 // Truncation tables: slack of A's terms and degree of B's (input order),
@@ -391,6 +397,9 @@ void carve_poisson_dense(Carver& c, int64_t na, int64_t nb, PoissonDenseBufs* q)
 struct HashCarve {
   Meta* meta;
   uint64_t* table;
+  // bucketed table with its term order: both factors reordered, rank scratch
+  int64_t* ord_ak; uint64_t* ord_ac; int64_t* ord_bk; uint64_t* ord_bc;
+  int32_t* ord_rank; int32_t* ord_sa; int32_t* ord_tb;
   PoissonPrep pp;
   uint32_t* counts;
   int64_t* pstart;
@@ -421,6 +430,9 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
   h->counts = nullptr;
   h->pstart = h->bstart = nullptr;
   h->ent1 = h->ent2 = nullptr;
+  h->ord_ak = h->ord_bk = nullptr;
+  h->ord_ac = h->ord_bc = nullptr;
+  h->ord_rank = h->ord_sa = h->ord_tb = nullptr;
   if (p.radix) {
     const int64_t P1 = (int64_t)1 << p.l1, bins = P1 << p.l2;
     h->counts = c.take<uint32_t>((size_t)(P1 * p.nblocks));
@@ -429,7 +441,19 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     h->ent1 = c.take<uint4>((size_t)p.nprod);
     h->ent2 = c.take<uint4>((size_t)p.nprod);
   } else {
-    h->table = c.take<uint64_t>((size_t)(p.cw == 2 ? 4 : 2) * p.cap);   // 16- or 32-byte slots
+    const int64_t slots = p.bucket ? p.nbuckets * p.bm + p.ovcap : p.cap;
+    h->table = c.take<uint64_t>((size_t)(p.cw == 2 ? 4 : 2) * slots);   // 16- or 32-byte slots
+    if (p.bucket && p.order) {
+      h->ord_ak = c.take<int64_t>(na);
+      h->ord_ac = c.take<uint64_t>(na);
+      h->ord_bk = c.take<int64_t>(nb);
+      h->ord_bc = c.take<uint64_t>(nb);
+      h->ord_rank = c.take<int32_t>(na + nb);
+      if (p.trunc) {
+        h->ord_sa = c.take<int32_t>(na);
+        h->ord_tb = c.take<int32_t>(nb);
+      }
+    }
   }
   h->pp = PoissonPrep{};
   if (poisson) {
@@ -498,6 +522,7 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                 "number of work items",
                 (long long)std::min<int64_t>(ctx->tune.dense_max_keys, DENSE_MAX_CODES));
   p->mode = m;
+  p->trunc = ctx->trunc_on && !poisson;
   Carver c;
   if (m == KP_DENSE) {
     carve_dense<false>(c, *p, na, nbd, nullptr);
@@ -516,8 +541,27 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     // partitioned when asked for, or (auto) when the products are not many
     // more than the result bound: its workspace is 32 bytes per product
     // against 32 per result slot pair of the global table
+    // the paper's bucketed table when asked for (Laurent, 8-byte coefficients)
+    p->bucket = ctx->tune.hash_bucket > 0 && !poisson && dt != KP_I128;
+    if (p->bucket) {
+      p->bm = ctx->tune.hash_bucket;
+      p->nbuckets = (p->cap + p->bm - 1) / p->bm;
+      // overflow table: six times the codes expected to overflow when the
+      // bound's codes spread over the buckets as a Poisson variable X of mean
+      // lam, N E[(X - m)+]: the highly sparse benchmark product (m = 8, load
+      // 0.5) overflowed 2.5 times the estimate, which leaves the table 40 % full
+      const double lam = (double)std::max<int64_t>(p->max_out, 1) / (double)p->nbuckets;
+      double pk = std::exp(-lam), below = 0.0;
+      for (int k = 0; k <= p->bm; ++k) {
+        below += (double)(p->bm - k) * pk;
+        pk *= lam / (double)(k + 1);
+      }
+      const double excess = std::max(0.0, lam - (double)p->bm + below);
+      p->ovcap = std::max<int64_t>(1024, (int64_t)std::ceil(6.0 * excess * (double)p->nbuckets));
+      p->order = ctx->tune.hash_order != 0;
+    }
     // (128-bit sums always use the global table)
-    p->radix = dt != KP_I128 &&
+    p->radix = !p->bucket && dt != KP_I128 &&
                (ctx->tune.hash_partitioned == 2 ||
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
@@ -530,7 +574,6 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
   }
-  p->trunc = ctx->trunc_on && !poisson;
   TruncBufs tb;
   carve_trunc(c, *p, na, nb, &tb);
   p->ws = c.off;
@@ -601,6 +644,8 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.dense_keys_per_pair = 64.0;
   ctx->tune.hash_rows = 64;
   ctx->tune.hash_partitioned = 1;
+  ctx->tune.hash_bucket = 0;
+  ctx->tune.hash_order = 1;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
     *out = ctx;
     return KP_OK;
@@ -693,17 +738,18 @@ kp_status kp_ctx_hash_stats(kp_ctx* ctx, int enable) {
 }
 
 kp_status kp_ctx_hash_stats_read(kp_ctx* ctx, hipStream_t stream, int64_t* inserts,
-                                 int64_t* extra_probes) {
+                                 int64_t* extra_probes, int64_t* overflows) {
   if (!ctx || !inserts || !extra_probes) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   hipError_t e = hipStreamSynchronize(stream);
-  unsigned long long v[2] = {0, 0};
+  unsigned long long v[3] = {0, 0, 0};   // inserts, probes, overflows (consecutive)
   if (e == hipSuccess) e = hipMemcpy(v, &ctx->status->inserts, sizeof v, hipMemcpyDeviceToHost);
-  const unsigned long long zero[2] = {0, 0};
+  const unsigned long long zero[3] = {0, 0, 0};
   if (e == hipSuccess) e = hipMemcpy(&ctx->status->inserts, zero, sizeof zero, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "kp_ctx_hash_stats_read");
   *inserts = (int64_t)v[0];
   *extra_probes = (int64_t)v[1];
+  if (overflows) *overflows = (int64_t)v[2];
   return KP_OK;
 }
 
@@ -754,6 +800,10 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "dense_max_keys must be at most %lld", (long long)DENSE_MAX_CODES);
   if (t->hash_partitioned < 0 || t->hash_partitioned > 2)
     return fail(ctx, KP_E_ARG, "hash_partitioned must be 0, 1 or 2");
+  if (t->hash_bucket < 0 || t->hash_bucket > 16)
+    return fail(ctx, KP_E_ARG, "hash_bucket must lie in [0, 16]");
+  if (t->hash_order != 0 && t->hash_order != 1)
+    return fail(ctx, KP_E_ARG, "hash_order must be 0 or 1");
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");
@@ -995,10 +1045,54 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
                               stream);
-      if (e == hipSuccess) e = launch_zero(h.table, (size_t)(p.cw == 2 ? 32 : 16) * p.cap, stream);
-      if (e == hipSuccess)
-        e = launch_hash_laurent(H, dtype, a_codes, a_coef, na, b_codes, b_coef, nb,
-                                ctx->tune.hash_rows, stream);
+      if (p.bucket) {
+        const BucketGeom G{p.bm, (uint64_t)p.nbuckets, make_fastdiv((uint64_t)p.nbuckets),
+                           p.ovcap};
+        const int64_t* ak = a_codes;
+        const int64_t* bk = b_codes;
+        const void* ac = a_coef;
+        const void* bc = b_coef;
+        if (p.order) {   // the terms by code mod N
+          ModOrder O{};
+          O.k_in[0] = a_codes;
+          O.k_in[1] = b_codes;
+          O.c_in[0] = static_cast<const uint64_t*>(a_coef);
+          O.c_in[1] = static_cast<const uint64_t*>(b_coef);
+          O.t_in[0] = p.trunc ? tr.sa : nullptr;
+          O.t_in[1] = p.trunc ? tr.tb : nullptr;
+          O.n[0] = na;
+          O.n[1] = nb;
+          O.k_out[0] = h.ord_ak;
+          O.k_out[1] = h.ord_bk;
+          O.c_out[0] = h.ord_ac;
+          O.c_out[1] = h.ord_bc;
+          O.t_out[0] = h.ord_sa;
+          O.t_out[1] = h.ord_tb;
+          O.rank[0] = h.ord_rank;
+          O.rank[1] = h.ord_rank + na;
+          if (e == hipSuccess) e = launch_mod_order(O, G, stream);
+          ak = h.ord_ak;
+          bk = h.ord_bk;
+          ac = h.ord_ac;
+          bc = h.ord_bc;
+          if (p.trunc) {
+            H.a_sa = h.ord_sa;
+            H.b_tb = h.ord_tb;
+          }
+        }
+        H.cap = p.nbuckets * p.bm + p.ovcap;   // compaction reads buckets and overflow
+        H.max_probe = p.ovcap;
+        if (e == hipSuccess) e = launch_zero(h.table, (size_t)16 * H.cap, stream);
+        if (e == hipSuccess)
+          e = launch_hash_laurent_bucket(H, G, dtype, ak, ac, na, bk, bc, nb,
+                                         ctx->tune.hash_rows, stream);
+      } else {
+        if (e == hipSuccess)
+          e = launch_zero(h.table, (size_t)(p.cw == 2 ? 32 : 16) * p.cap, stream);
+        if (e == hipSuccess)
+          e = launch_hash_laurent(H, dtype, a_codes, a_coef, na, b_codes, b_coef, nb,
+                                  ctx->tune.hash_rows, stream);
+      }
       if (e == hipSuccess) e = launch_hash_compact(H, dtype, stream);
     }
     if (e == hipSuccess) e = launch_finalize(h.meta, out_cap, out_n, &ctx->status->err, stream);

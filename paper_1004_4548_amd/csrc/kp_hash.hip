@@ -811,6 +811,153 @@ __global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
   if (R.stats) add_stats(R.stats, ins, extra);
 }
 
+// ------------------------------------------------------------ bucketed table
+// Section 3.2's table: N buckets of m slots in one array, a product of code
+// e going to bucket e mod N, where it is added to the slot already holding e
+// or appended after the bucket's last term; a full bucket sends it to an
+// overflow area, which is searched whenever a full bucket is met.  On the
+// GPU the bucket's slots are claimed in order by compare-and-swap (a
+// concurrent append), so a code is in at most one slot of its bucket, and a
+// code only reaches the overflow area when every slot of its bucket holds
+// another code for good; the overflow area is an open-addressing table,
+// since many insertions can overflow at a load the GPU table runs at, where
+// the paper's list would be searched linearly.  A full overflow table is
+// reported as a capacity error (the point at which the paper resizes).
+
+__device__ __forceinline__ uint64_t mod_bucket(int64_t code, const BucketGeom& G) {
+  const uint64_t c = (uint64_t)code;
+  return c - fdiv(c, G.fN) * G.nbuckets;
+}
+
+// Slots visited beyond the first (m and the overflow table's probes for an
+// overflowing product), with OVF_BIT set when the product went to the
+// overflow table.
+constexpr int64_t OVF_BIT = (int64_t)1 << 62;
+
+template <typename T>
+__device__ __forceinline__ int64_t bucket_probe(uint64_t* __restrict__ table, int m, uint64_t nbuckets,
+                                             int64_t ovcap, int64_t max_probe, uint64_t base,
+                                             uint64_t cur, uint64_t key, T v, uint32_t* err) {
+  for (int k = 0; k < m; ++k) {
+    uint64_t* ks = table + 2 * (base + (uint64_t)k);
+    if (k > 0) cur = key_load(ks);
+    if (cur == 0) {
+      cur = atomicCAS((unsigned long long*)ks, 0ull, (unsigned long long)key);
+      if (cur == 0) cur = key;
+    }
+    if (cur == key) {
+      slot_add(ks + 1, v);
+      return k;
+    }
+  }
+  uint64_t* ov = table + 2 * nbuckets * (uint64_t)m;
+  const uint64_t h = home_slot((int64_t)(key - 1), (uint64_t)ovcap);
+  return OVF_BIT + m +
+         table_probe<T>(ov, (uint64_t)ovcap, max_probe, h, key_load(ov + 2 * h), key, v, err);
+}
+
+// Thread = one term of B, rows of A wavefront-uniform, NB insertions with
+// their first key loads in flight together (as the open-addressing kernel).
+template <typename T>
+__global__ void __launch_bounds__(HASH_BLOCK)
+k_hash_laurent_bucket(uint64_t* __restrict__ table, BucketGeom G, int64_t max_probe, Meta* meta,
+                      const int64_t* __restrict__ ak, const T* __restrict__ ac, int64_t na,
+                      const int64_t* __restrict__ bk, const T* __restrict__ bc, int64_t nb,
+                      int rows, unsigned long long* stats, const int32_t* __restrict__ a_sa,
+                      const int32_t* __restrict__ b_tb) {
+  constexpr int NB = 4;
+  const int64_t j0 = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * rows;
+  const int64_t i1 = min(i0 + rows, na);
+  const uint32_t narrow = meta->narrow;
+  const bool live = j0 < nb;
+  const int64_t j = live ? j0 : nb - 1;   // idle lanes stay for the statistics reduction
+  const int64_t bj = bk[j];
+  const T cb = bc[j];
+  const int32_t tb = b_tb ? b_tb[j] : INT_MIN;
+  int64_t ins = 0, extra = 0, novf = 0;
+  for (int64_t i = live ? i0 : i1; i < i1; i += NB) {
+    uint64_t base[NB], cur[NB];
+    int64_t code[NB];
+    T v[NB];
+    bool on[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const bool in = i + u < i1;
+      const int64_t r = in ? i + u : i;
+      v[u] = mul_coef<T>(ac[r], cb, narrow);
+      code[u] = ak[r] + bj;
+      on[u] = in && v[u] != T(0) && (!a_sa || tb <= a_sa[r]);
+      ins += on[u];
+      base[u] = mod_bucket(code[u], G) * (uint64_t)G.m;
+      cur[u] = on[u] ? key_load(table + 2 * base[u]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (!on[u]) continue;
+      const uint64_t key = (uint64_t)code[u] + 1;
+      if (cur[u] == key) {
+        slot_add(table + 2 * base[u] + 1, v[u]);
+      } else {
+        const int64_t pr = bucket_probe<T>(table, G.m, G.nbuckets, G.ovcap, max_probe, base[u],
+                                           cur[u], key, v[u], &meta->err);
+        extra += pr & (OVF_BIT - 1);
+        novf += pr >> 62;
+      }
+    }
+  }
+  if (stats) {
+    add_stats(stats, ins, extra);
+    for (int off = 32; off > 0; off >>= 1) novf += __shfl_xor(novf, off);
+    if ((threadIdx.x & 63) == 0 && novf) atomicAdd(&stats[2], (unsigned long long)novf);
+  }
+}
+
+// The paper's term order for the hashed product: each factor's terms by code
+// mod N, so that consecutive products of a row go to consecutive buckets.
+// One workgroup per factor: a counting sort on MOD_BINS bins of the residue
+// (the order within a bin is unspecified), ranks kept in global scratch.
+constexpr int MOD_BLOCK = 1024;
+constexpr int MOD_BINS = 16384;
+
+__global__ void __launch_bounds__(MOD_BLOCK) k_mod_order(ModOrder O, BucketGeom G) {
+  __shared__ int32_t hist[MOD_BINS];
+  __shared__ uint32_t s_ws[MOD_BLOCK / 64 + 1];
+  const int f = blockIdx.x;
+  const int64_t n = O.n[f];
+  const int64_t* __restrict__ kin = O.k_in[f];
+  // bin = floor(MOD_BINS * (code mod N) / N), exact in 64 bits for N < 2^40
+  auto bin_of = [&](int64_t code) -> int {
+    const uint64_t r = mod_bucket(code, G);
+    return (int)fdiv(r * (uint64_t)MOD_BINS, G.fN);
+  };
+  for (int b = threadIdx.x; b < MOD_BINS; b += MOD_BLOCK) hist[b] = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += MOD_BLOCK)
+    O.rank[f][i] = atomicAdd(&hist[bin_of(kin[i])], 1);
+  __syncthreads();
+  // exclusive scan of the bins: MOD_BINS / MOD_BLOCK consecutive bins per thread
+  constexpr int PER = MOD_BINS / MOD_BLOCK;
+  uint32_t part = 0;
+  for (int q = 0; q < PER; ++q) part += (uint32_t)hist[threadIdx.x * PER + q];
+  uint32_t total;
+  uint32_t run = block_scan1<MOD_BLOCK>(part, s_ws, &total);
+  for (int q = 0; q < PER; ++q) {
+    const int b = threadIdx.x * PER + q;
+    const uint32_t c = (uint32_t)hist[b];
+    hist[b] = (int32_t)run;
+    run += c;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += MOD_BLOCK) {
+    const int64_t code = kin[i];
+    const int64_t pos = hist[bin_of(code)] + O.rank[f][i];
+    O.k_out[f][pos] = code;
+    O.c_out[f][pos] = O.c_in[f][i];
+    if (O.t_in[f]) O.t_out[f][pos] = O.t_in[f][i];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak, const void* ac,
@@ -904,6 +1051,31 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_radix_bins<double>, dim3(bins), dim3(BIN_BLOCK), 0, s, R);
   if (R.ev1) (void)hipEventRecord(R.ev1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_laurent_bucket(const HashBufs& H, const BucketGeom& G, kp_dtype dt,
+                                      const int64_t* ak, const void* ac, int64_t na,
+                                      const int64_t* bk, const void* bc, int64_t nb, int rows,
+                                      hipStream_t s) {
+  if (rows < 1) rows = 1;
+  dim3 grid((unsigned)((nb + HASH_BLOCK - 1) / HASH_BLOCK), (unsigned)((na + rows - 1) / rows));
+  if (H.ev0) (void)hipEventRecord(H.ev0, s);
+  if (dt == KP_F64)
+    hipLaunchKernelGGL(k_hash_laurent_bucket<double>, grid, dim3(HASH_BLOCK), 0, s, H.table, G,
+                       H.max_probe, H.meta, ak, (const double*)ac, na, bk, (const double*)bc, nb,
+                       rows, H.stats, H.a_sa, H.b_tb);
+  else
+    hipLaunchKernelGGL(k_hash_laurent_bucket<int64_t>, grid, dim3(HASH_BLOCK), 0, s, H.table, G,
+                       H.max_probe, H.meta, ak, (const int64_t*)ac, na, bk, (const int64_t*)bc, nb,
+                       rows, H.stats, H.a_sa, H.b_tb);
+  if (H.ev1) (void)hipEventRecord(H.ev1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mod_order(const ModOrder& O, const BucketGeom& G, hipStream_t s) {
+  if (O.n[0] + O.n[1] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mod_order, dim3(2), dim3(MOD_BLOCK), 0, s, O, G);
   return hipGetLastError();
 }
 

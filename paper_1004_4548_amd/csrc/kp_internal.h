@@ -170,8 +170,9 @@ struct CtxStatus {
   uint32_t pad0;
   unsigned long long inserts;    // hash insertions counted while statistics are on
   unsigned long long probes;     // slots visited beyond the home slot
+  unsigned long long overflows;  // bucketed table: insertions that went to the overflow table
   unsigned long long sink[16];   // discard area of the LDS atomic probe
-  uint32_t pad[26];
+  uint32_t pad[24];
 };
 static_assert(sizeof(CtxStatus) == 256, "status block is 256 bytes");
 
@@ -336,6 +337,29 @@ hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep&
                                const double* ac, int64_t na, const double* bc, int64_t nb,
                                int rows, hipStream_t s);
 hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s);
+
+// Bucketed table (the paper's layout): nbuckets buckets of m slots at the
+// start of H.table, hashed by code mod nbuckets, followed by an overflow
+// table of ovcap slots (open addressing); H.cap counts both.
+struct BucketGeom {
+  int m;
+  uint64_t nbuckets;
+  FastDiv fN;
+  int64_t ovcap;
+};
+hipError_t launch_hash_laurent_bucket(const HashBufs& H, const BucketGeom& G, kp_dtype dt,
+                                      const int64_t* ak, const void* ac, int64_t na,
+                                      const int64_t* bk, const void* bc, int64_t nb, int rows,
+                                      hipStream_t s);
+// Orders the terms of both factors by code mod nbuckets (bins of the
+// residue, a counting sort per factor): codes, 8-byte coefficients and the
+// optional int32 truncation tables, into the out arrays; rank is scratch of
+// na + nb int32.
+struct ModOrder {
+  const int64_t* k_in[2]; const uint64_t* c_in[2]; const int32_t* t_in[2]; int64_t n[2];
+  int64_t* k_out[2]; uint64_t* c_out[2]; int32_t* t_out[2]; int32_t* rank[2];
+};
+hipError_t launch_mod_order(const ModOrder& O, const BucketGeom& G, hipStream_t s);
 
 // Partitioned hash accumulation: products grouped by hash bits in two
 // levels through HBM, each final bin accumulated in an LDS table.

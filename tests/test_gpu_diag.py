@@ -30,11 +30,11 @@ def test_hash_stats_count_every_insertion():
     pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
     ctx.hash_stats_read()          # start from zero
     kp.mul_laurent(pa, pb, mode="hash", ctx=ctx)
-    assert ctx.hash_stats_read() == (0, 0)   # off by default
+    assert ctx.hash_stats_read() == (0, 0, 0)   # off by default
     ctx.hash_stats(True)
     try:
         r, _ = kp.mul_laurent(pa, pb, mode="hash", ctx=ctx)
-        ins, extra = ctx.hash_stats_read()
+        ins, extra, ovf = ctx.hash_stats_read()
     finally:
         ctx.hash_stats(False)
     # coefficients in [1, 1000]: every term product is nonzero and inserted
@@ -54,7 +54,7 @@ def test_hash_stats_poisson_counts_both_pieces():
     ctx.hash_stats(True)
     try:
         kp.mul_poisson(sa, sb, mode="hash", ctx=ctx)
-        ins, extra = ctx.hash_stats_read()
+        ins, extra, ovf = ctx.hash_stats_read()
     finally:
         ctx.hash_stats(False)
     # each pair gives the difference and the sum term; only sines of the zero

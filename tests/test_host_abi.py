@@ -233,9 +233,11 @@ def test_tune_validation():
     assert t.hash_partitioned == 1
     for bad in (dict(window=18432 + 2048), dict(block=100), dict(hash_load=0.95),
                 dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1),
-                dict(hash_partitioned=3), dict(hash_partitioned=-1)):
+                dict(hash_partitioned=3), dict(hash_partitioned=-1), dict(hash_bucket=-1),
+                dict(hash_bucket=17), dict(hash_order=2)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
+    assert t.hash_bucket == 0 and t.hash_order == 1
 
 
 def test_partitioned_hash_workspace():
@@ -257,6 +259,42 @@ def test_partitioned_hash_workspace():
     ctx.set_tune(hash_partitioned=2)
     _, _, ws_box_part = kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)
     assert mo_box == 21 ** 3 and ws_box_part >= 32 * 500 * 500 > ws_box_table
+
+
+def test_bucketed_hash_workspace():
+    """The bucketed table: ceil(cap / m) buckets of m 16-byte slots and an
+    overflow table of six times N E[(X - m)+] slots, X Poisson with the
+    bound's codes per bucket as mean (at least 1024); with the term order
+    both factors again (16 bytes a term) plus 4 bytes of rank scratch.  It is
+    not used for 128-bit sums."""
+    from scipy.stats import poisson
+    ctx = _host_ctx()
+    sparse = kp.layout_product(6, 0, [0] * 6, [80] * 6, [0] * 6, [80] * 6)
+    na, nb = 3000, 2000
+    ctx.set_tune(hash_partitioned=0)
+    _, mo, ws_table = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+    cap = int(mo / 0.5) + 1
+    for m in (1, 3, 8, 16):
+        nbk = -(-cap // m)
+        lam = mo / nbk
+        k = np.arange(0, m + 200)
+        excess = float(np.sum(np.maximum(k - m, 0) * poisson.pmf(k, lam)))
+        ov = max(1024, int(np.ceil(6 * excess * nbk)))
+        ctx.set_tune(hash_bucket=m, hash_order=0)
+        _, _, ws0 = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+        ctx.set_tune(hash_order=1)
+        _, _, ws1 = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+        # (each workspace buffer starts on a 256-byte boundary; the C side's
+        # Poisson sum may round one slot differently)
+        assert abs((ws0 - ws_table) - 16 * (nbk * m + ov - cap)) < 256 + 32, m
+        assert 20 * (na + nb) <= ws1 - ws0 < 20 * (na + nb) + 5 * 256
+        if m == 1:
+            assert ov > cap // 5   # a fifth of the codes overflow single-slot buckets at load 0.5
+    # 128-bit sums keep the open-addressing table
+    ctx.set_tune(hash_bucket=0)
+    ws128 = kp.mul_bound(sparse, False, kp.KP_I128, "hash", na, nb, ctx)[2]
+    ctx.set_tune(hash_bucket=8)
+    assert kp.mul_bound(sparse, False, kp.KP_I128, "hash", na, nb, ctx)[2] == ws128
 
 
 def test_host_context_rejects_launches():
