@@ -80,7 +80,7 @@ namespace {
 constexpr int PREP_BLOCK = 1024;
 constexpr int PLAN_BLOCK = 1024;
 constexpr int64_t ITEMS_LDS_BYTES = 144 * 1024;   // tile rows and item map of the items kernel
-constexpr int PREP_UNROLL = 8;
+constexpr int PREP_UNROLL = 16;   // one round of loads for factors of up to 16384 terms
 // Byte offsets that can never fall inside a window (codes are below 2^27, so
 // a window offset times 8 stays within +-2^30): a missing row of A, and a
 // missing term of B in the last tile.  Their sum is also out of range.
@@ -272,25 +272,36 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_dense_prep(PrepArgs args) {
     }
   }
   __syncthreads();
-  // Exclusive scan of the histogram.  Wave w owns a contiguous run of
-  // buckets and reads it 64 consecutive buckets at a time (no bank
-  // conflicts): first the run's total, then the scan with a running carry.
-  const int64_t per = (nbk + NW * 64 - 1) / (NW * 64) * 64;
-  const int64_t r0 = min(nbk, wave * per), r1 = min(nbk, r0 + per);
+  // Exclusive scan of the histogram: thread t owns the contiguous buckets
+  // [t per, (t + 1) per), read four at a time (loads in flight) and summed;
+  // the sums are scanned across the workgroup, each thread writes its
+  // buckets' starts back into LDS, and the workgroup copies them out with
+  // consecutive lanes on consecutive buckets.
+  const int64_t per = (nbk + PREP_BLOCK - 1) / PREP_BLOCK;
+  const int64_t r0 = min(nbk, (int64_t)tid * per), r1 = min(nbk, r0 + per);
   int64_t part = 0;
-  for (int64_t b = r0 + lane; b < r1; b += 64) part += hist[b];
-  part = readlane64(wave_inclusive<false>(part, 0), 63);
-  if (lane == 0) s_wave[wave] = part;
-  __syncthreads();
-  int64_t carry = 0;
-  for (int w = 0; w < wave; ++w) carry += s_wave[w];
-  for (int64_t b0 = r0; b0 < r1; b0 += 64) {
-    const int64_t b = b0 + lane;
-    const int64_t v = b < r1 ? hist[b] : 0;
-    const int64_t inc = wave_inclusive<false>(v, 0);
-    if (b < r1) sg.bstart[b] = (int32_t)(carry + inc - v);
-    carry += readlane64(inc, 63);
+  for (int64_t b = r0; b < r1; b += 4) {
+    int32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = b + u < r1 ? hist[b + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part += v[u];
   }
+  int64_t all;
+  int64_t run = block_exclusive_scan<PREP_BLOCK>(part, s_wave, &all);
+  for (int64_t b = r0; b < r1; b += 4) {
+    int32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = b + u < r1 ? hist[b + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b + u < r1) {
+        hist[b + u] = (int32_t)run;
+        run += v[u];
+      }
+  }
+  __syncthreads();
+  for (int64_t b = tid; b < nbk; b += PREP_BLOCK) sg.bstart[b] = hist[b];
   if (tid == 0) sg.bstart[nbk] = (int32_t)sg.n;
   if (!args.is_i64) flags = 0;
   const uint32_t wf = wave_and(flags), we = wave_or(err);
@@ -361,18 +372,20 @@ __device__ __forceinline__ TileRows tile_rows(const PlanArgs& P, int64_t L, int6
   TileRows g{0, 0, 0, 0};
   if (t >= P.ntiles) return g;
   const int64_t lo = P.tmin[t], hi = P.tmax[t];
-  rows_for(P.bstart, P.shiftA, P.nbkA, L - hi, L + Sw - lo, &g.i0, &g.i1);
-  g.c0 = g.c1 = g.i0;
+  // the core-row bounds depend only on the tile's codes: their loads go out
+  // with those of the row range (one round of latency instead of two)
   const bool full = (t + 1) * DENSE_TILE <= P.nb;
   const int64_t clo = max(L - lo, (int64_t)0), chi = L + Sw - hi;
-  if (full && g.i1 > g.i0 && chi > clo) {
-    const int64_t bw = (int64_t)1 << P.shiftA;
-    const int64_t b0 = (clo + bw - 1) >> P.shiftA;
-    const int64_t b1 = min(chi >> P.shiftA, P.nbkA);
-    if (b1 > b0) {
-      g.c0 = min(g.i1, max(g.i0, (int64_t)P.bstart[b0]));
-      g.c1 = min(g.i1, max(g.c0, (int64_t)P.bstart[b1]));
-    }
+  const int64_t bw = (int64_t)1 << P.shiftA;
+  const int64_t b0 = min((clo + bw - 1) >> P.shiftA, P.nbkA);
+  const int64_t b1 = max((int64_t)0, min(chi >> P.shiftA, P.nbkA));
+  const bool core = full && chi > clo && b1 > b0;
+  const int64_t s0 = core ? P.bstart[b0] : 0, s1 = core ? P.bstart[b1] : 0;
+  rows_for(P.bstart, P.shiftA, P.nbkA, L - hi, L + Sw - lo, &g.i0, &g.i1);
+  g.c0 = g.c1 = g.i0;
+  if (core && g.i1 > g.i0) {
+    g.c0 = min(g.i1, max(g.i0, s0));
+    g.c1 = min(g.i1, max(g.c0, s1));
   }
   return g;
 }
@@ -409,14 +422,14 @@ __device__ __forceinline__ int64_t cost_of(const int4& r) {
 }
 __device__ __forceinline__ int64_t item_cost(int64_t n) { return (n + 15) / 16; }
 // Exclusive block scan of each thread's items and cost.  When every thread
-// holds fewer than 2^21 items the window has fewer than 2^31, and items (high
-// 31 bits) and cost (at most 4 per item, low 33 bits) are scanned as one
-// value; otherwise in two scans.
+// holds fewer than 2^21 items and a cost below 2^22, the totals stay below
+// 2^31 and 2^32, and items (high 31 bits) and cost (low 33 bits) are scanned
+// as one value; otherwise in two scans.
 constexpr int COST_BITS = 33;
 __device__ __forceinline__ void scan_items_cost(int64_t nit, int64_t cost, int64_t* s_wave,
                                                 int64_t* q, int64_t* qc, int64_t* tot_items,
                                                 int64_t* tot_cost) {
-  if (!__syncthreads_or(nit >= ((int64_t)1 << 21))) {
+  if (!__syncthreads_or(nit >= ((int64_t)1 << 21) || cost >= ((int64_t)1 << 22))) {
     int64_t tot;
     const uint64_t v = (uint64_t)block_exclusive_scan<PLAN_BLOCK>(
         (int64_t)(((uint64_t)nit << COST_BITS) | (uint64_t)cost), s_wave, &tot);
@@ -459,6 +472,41 @@ __device__ __forceinline__ void item_rows(const int4& r, int64_t k, int64_t* r0,
   *core = *core && *n == DENSE_ITEM_ROWS;
 }
 
+// Products of at most this many windows lay out their tasks in the items
+// kernel (every workgroup sums the records of the windows before its own);
+// larger ones in the last workgroup of the count kernel.
+constexpr int64_t LAYOUT_IN_ITEMS_MAX = 4096;
+
+// Workgroup-wide sums of four values per thread (every thread gets them):
+// DPP wavefront sums, one barrier.  s_red is written once per kernel.
+__device__ __forceinline__ void block_sum4(int64_t (&v)[4], int64_t* s_red) {
+  constexpr int NW = PLAN_BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = readlane64(wave_inclusive<false>(v[k], 0), 63);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_red[k * NW + wave] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int64_t t = 0;
+    for (int u = 0; u < NW; ++u) t += s_red[k * NW + u];
+    v[k] = t;
+  }
+}
+
+// Task size from the total cost: tasks of equal cost T (more than one
+// window's overhead plus an item's); task p starts at the item whose cost
+// interval holds p * T.
+__device__ __forceinline__ void task_shape(const PlanArgs& P, int64_t all_cost, int64_t* T,
+                                           int64_t* nt) {
+  int64_t t = (all_cost + P.target - 1) / P.target;
+  if (t < WINDOW_COST + 4) t = WINDOW_COST + 4;
+  *T = t;
+  *nt = all_cost > 0 ? (all_cost + t - 1) / t : 0;
+}
+
 __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   __shared__ int64_t s_wave[PLAN_BLOCK / 64];
   __shared__ int s_last;
@@ -487,6 +535,13 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   }
   int64_t q, qc, tot_items, tot_cost;
   scan_items_cost(nit, cost, s_wave, &q, &qc, &tot_items, &tot_cost);
+  if (P.nwin <= LAYOUT_IN_ITEMS_MAX) {   // the items kernel lays out the tasks
+    if (tid == 0) {
+      P.win[W_ITEMS * W1 + w] = tot_items;
+      P.win[W_COST * W1 + w] = tot_cost;
+    }
+    return;
+  }
   if (tid == 0) {
     P.win[W_ITEMS * W1 + w] = tot_items;
     P.win[W_COST * W1 + w] = tot_cost;
@@ -515,9 +570,8 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
     li += it;
     lc += it > 0 ? ct + WINDOW_COST : 0;
   }
-  int64_t all_items, all_cost;
-  int64_t ibase = block_exclusive_scan<PLAN_BLOCK>(li, s_wave, &all_items);
-  int64_t cbase = block_exclusive_scan<PLAN_BLOCK>(lc, s_wave, &all_cost);
+  int64_t ibase, cbase, all_items, all_cost;
+  scan_items_cost(li, lc, s_wave, &ibase, &cbase, &all_items, &all_cost);
   for (int64_t u = w0; u < w1; ++u) {
     const int64_t it = u - w0 < KEEP ? kept[u - w0] : ld(W_ITEMS, u);
     const int64_t ct = u - w0 < KEEP ? kept_c[u - w0] : ld(W_COST, u);
@@ -532,11 +586,8 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_count(PlanArgs P) {
   if (tid == 0) {
     P.win[W_IBASE * W1 + P.nwin] = all_items;
     P.win[W_CBASE * W1 + P.nwin] = all_cost;
-    // tasks of equal cost T (more than one window's overhead plus an item's):
-    // task p starts at the item whose cost interval holds p * T
-    int64_t T = (all_cost + P.target - 1) / P.target;
-    if (T < WINDOW_COST + 4) T = WINDOW_COST + 4;
-    int64_t nt = all_cost > 0 ? (all_cost + T - 1) / T : 0;
+    int64_t T, nt;
+    task_shape(P, all_cost, &T, &nt);
     if (bad || all_items > P.items_cap) {
       P.meta->err |= bad ? bad : ERR_CAPACITY;
       nt = 0;
@@ -578,13 +629,6 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
   const int64_t W1 = P.nwin + 1;
   const int64_t nit_w = P.win[W_ITEMS * W1 + w];
   if (tid == 0) s_split = 0;
-  if (P.meta->ntasks == 0 || nit_w == 0) {
-    if (tid == 0) P.win[W_SPLIT * W1 + w] = 0;
-    return;
-  }
-  const int64_t ib = P.win[W_IBASE * W1 + w], cb = P.win[W_CBASE * W1 + w];
-  const int64_t T = P.meta->task_rows;
-  const double rT = 1.0 / (double)T;
   const int4* rec = P.recs + w * P.ntiles;
   const int64_t nt = P.ntiles;
   // LDS: the window's tile rows, per-tile item and cost prefixes, tile of
@@ -594,11 +638,62 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
   int32_t* s_cp = s_ip + nt + 1;
   int32_t* s_of = s_cp + nt + 1;
   const bool in_lds = (size_t)nt * 24 + 8 + (size_t)nit_w * 4 <= (size_t)P.items_lds;
+  // the tile rows go to LDS first, so that their loads overlap the layout's
+  if (in_lds && nit_w > 0)
+    for (int64_t t = tid; t < nt; t += PLAN_BLOCK) s_rec[t] = rec[t];
+  const bool layout_here = P.nwin <= LAYOUT_IN_ITEMS_MAX;
+  int64_t ib, cb, T, ntasks;
+  if (layout_here) {
+    // this window's item and cost offsets, and the task size, from the
+    // windows' records (the count kernel's last workgroup does this for
+    // larger products)
+    __shared__ int64_t s_red[4 * (PLAN_BLOCK / 64)];
+    // (all loads issued together: the error bits, and both records of the
+    // thread's windows)
+    const uint32_t bad = P.meta->seg_err[0] | P.meta->seg_err[1];
+    int64_t v[4] = {0, 0, 0, 0};   // items before w, cost before w, all items, all cost
+    for (int64_t u = tid; u < P.nwin; u += PLAN_BLOCK) {
+      const int64_t it = P.win[W_ITEMS * W1 + u], ct = P.win[W_COST * W1 + u];
+      const int64_t c = it > 0 ? ct + WINDOW_COST : 0;
+      if (u < w) {
+        v[0] += it;
+        v[1] += c;
+      }
+      v[2] += it;
+      v[3] += c;
+    }
+    block_sum4(v, s_red);
+    ib = v[0];
+    cb = v[1];
+    task_shape(P, v[3], &T, &ntasks);
+    // no work after a factor code outside its box (reported by the scan
+    // kernel), or past the planned item bound (which cannot happen)
+    if (bad || v[2] > P.items_cap) ntasks = 0;
+    if (tid == 0) {
+      P.win[W_IBASE * W1 + w] = ib;   // read by the multiply kernel
+      if (w == 0) {
+        P.win[W_IBASE * W1 + P.nwin] = v[2];
+        if (bad || v[2] > P.items_cap) P.meta->err |= bad ? bad : ERR_CAPACITY;
+        P.meta->task_rows = T;
+        P.meta->ntasks = ntasks;
+        P.task_begin[ntasks] = (int32_t)v[2];
+      }
+    }
+  } else {
+    ib = P.win[W_IBASE * W1 + w];
+    cb = P.win[W_CBASE * W1 + w];
+    T = P.meta->task_rows;
+    ntasks = P.meta->ntasks;
+  }
+  if (ntasks == 0 || nit_w == 0) {
+    if (tid == 0) P.win[W_SPLIT * W1 + w] = 0;
+    return;
+  }
+  const double rT = 1.0 / (double)T;
   int64_t t0, t1;
   thread_tiles(nt, &t0, &t1);
   if (in_lds) {
-    for (int64_t t = tid; t < nt; t += PLAN_BLOCK) s_rec[t] = rec[t];
-    __syncthreads();
+    if (!layout_here) __syncthreads();   // the records are in LDS (else the prologue's barrier)
     int64_t nit = 0, ncost = 0;
     for (int64_t t = t0; t < t1; ++t) {
       nit += items_of(s_rec[t]);
@@ -636,7 +731,32 @@ __global__ void __launch_bounds__(PLAN_BLOCK) k_dense_items(PlanArgs P) {
       int64_t r0, n, before;
       bool core;
       item_rows(r, k - s_ip[t], &r0, &n, &core, &before);
-      put_item(P, w, ib, k, cb, s_cp[t] + before, r0, t, n, core, T, rT, &s_split);
+      P.items[ib + k] = pack_item(r0, t, n, core);
+    }
+    // Tasks that start in this window: task p at the item whose cost
+    // interval holds p * T (item 0's interval also covers the window's
+    // overhead), found by one thread each by bisection over the items' cost
+    // starts.  At most one item in 65 starts a task.
+    auto start_of = [&](int64_t k) -> int64_t {   // cost interval start of item k
+      if (k == 0) return cb;
+      const int64_t t = s_of[k];
+      int64_t r0, n, before;
+      bool core;
+      item_rows(s_rec[t], k - s_ip[t], &r0, &n, &core, &before);
+      return cb + WINDOW_COST + s_cp[t] + before;
+    };
+    const int64_t end = cb + WINDOW_COST + tqc;   // past the window's last item
+    for (int64_t p = (cb + T - 1) / T + tid; p * T < end; p += PLAN_BLOCK) {
+      const int64_t x = p * T;
+      int64_t lo = 0, hi = nit_w - 1;   // largest k with start_of(k) <= x
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (start_of(mid) <= x) lo = mid;
+        else hi = mid - 1;
+      }
+      P.task_begin[p] = (int32_t)(ib + lo);
+      P.task_w[p] = (int32_t)w;
+      if (lo > 0) s_split = 1;   // a task starts inside the window
     }
   } else {
     // too large for LDS: each thread writes the items of its own tiles

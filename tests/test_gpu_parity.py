@@ -207,6 +207,21 @@ def test_laurent_many_windows_and_split_windows():
         check_laurent(a64, b64, "dense", f"fp64 window {window}")
 
 
+def test_dense_layout_of_many_windows():
+    """A product of more than 4096 windows lays out its tasks in the count
+    kernel's last workgroup (smaller ones in the items kernel): both paths
+    against the oracle."""
+    ctx = kp.context()
+    rng = np.random.default_rng(4096)
+    ea = np.unique(rng.integers(0, 6_000_000, 2500)).reshape(-1, 1).astype(np.int32)
+    eb = np.unique(rng.integers(0, 6_000_000, 1500)).reshape(-1, 1).astype(np.int32)
+    a = (ea, rng.integers(-9, 10, len(ea)))
+    b = (eb, rng.integers(-9, 10, len(eb)))
+    for window in (2048, 18432):   # about 5900 and 650 windows
+        ctx.set_tune(window=window, block=1024, tasks_per_cu=2)
+        check_laurent(a, b, "dense", f"univariate over 12e6 codes, window {window}")
+
+
 def test_laurent_univariate_long_range():
     # one variable, codes spanning many windows with sparse hits
     rng = np.random.default_rng(9)
