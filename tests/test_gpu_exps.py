@@ -115,6 +115,37 @@ def test_two_call_capacity_error_decodes_nothing():
     ctx.sync_check()   # nothing left latched
 
 
+def test_two_call_exponent_outside_the_layout_is_a_range_error():
+    """An exponent past the layout's box is reported (dense mode checks it in
+    its prep kernel, hash mode in the encode kernel), and the context is
+    clean afterwards."""
+    import torch
+    ctx = kp.context()
+    a, b = I.config(1, scale=0.3)
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    bad = pa.exps.clone()
+    for mode in ("dense", "hash"):
+        lay, m, max_out, ws = kp.plan_laurent(pa, pb, mode=mode, ctx=ctx)
+        assert m == mode
+        bad.copy_(pa.exps)
+        bad[3, 1] = lay.amax[1] + 1
+        ox = torch.empty((max_out, pa.nv), dtype=torch.int32, device="cuda")
+        oc = torch.empty(max_out, dtype=torch.int64, device="cuda")
+        on = torch.empty(1, dtype=torch.int64, device="cuda")
+        wbuf = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        n = C.c_int64(0)
+        say("range error", mode)
+        st = kp.lib().kp_mul_laurent_exps(
+            ctx.h, C.byref(lay), kp.KP_I64, kp.MODES[mode], 0, kp._ptr(bad), kp._ptr(pa.coef),
+            len(a[1]), kp._ptr(pb.exps), kp._ptr(pb.coef), len(b[1]), kp._ptr(ox), kp._ptr(oc),
+            max_out, kp._ptr(on), C.byref(n), kp._ptr(wbuf), ws, kp._stream())
+        assert st == kp.KP_E_RANGE, (mode, st)
+        ctx.sync_check()   # nothing left latched
+        r, _ = kp.mul_laurent(pa, pb, mode=mode, ctx=ctx)
+        oe, oc_, _ = O.laurent_mul(a[0], a[1], b[0], b[1])
+        assert_exact([r.exps.cpu().numpy()], r.coef.cpu().numpy(), [oe], oc_, f"after, {mode}")
+
+
 def test_box_accumulator_restores_between_launches():
     ctx = kp.context()
     rng = np.random.default_rng(10044548)
