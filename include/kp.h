@@ -148,6 +148,9 @@ typedef struct kp_tune {
                                used                                                       */
   int32_t hash_order;       /* bucketed table: 1 (default) orders both factors' terms by
                                code mod N first (Section 3.2's term order), 0 keeps them  */
+  int32_t hash_bin_slots;   /* grouped products: slots of one bin's LDS table, 2048, 4096
+                               (default) or 8192, 16 bytes each; bins are sized for half
+                               a table of products on average                             */
 } kp_tune;
 
 typedef struct kp_ctx kp_ctx;

@@ -235,7 +235,7 @@ struct Plan {
   // partitioned hash: rows of A per workgroup, log2 partitions and bins,
   // count/scatter workgroups, products bound
   bool radix = false;
-  int rows = 0, l1 = 1, l2 = 0;
+  int rows = 0, l1 = 1, l2 = 0, blog = 11;   // blog: log2 of a bin's LDS slots
   int64_t nblocks = 0, nprod = 0;
   bool trunc = false;   // truncation tables follow the mode's workspace
   int cw = 1;           // 64-bit words per result coefficient (2 for KP_I128)
@@ -408,12 +408,13 @@ struct HashCarve {
   uint4* ent2;
 };
 
-// Shape of the partitioned accumulation: at most 1024 products per bin on
-// average (half of the LDS table), at most 2^10 partitions and 2^10 bins
-// each; about 4096 count/scatter workgroups.
-void radix_shape(int64_t na, int64_t nb, int64_t nprod, Plan* p) {
+// Shape of the partitioned accumulation: at most half a bin's LDS table of
+// products per bin on average, at most 2^10 partitions and 2^10 bins each;
+// about 4096 count/scatter workgroups.
+void radix_shape(int64_t na, int64_t nb, int64_t nprod, int bin_slots, Plan* p) {
+  p->blog = bin_slots == 8192 ? 13 : bin_slots == 4096 ? 12 : 11;
   int bits = 1;
-  while (bits < 20 && ((int64_t)1024 << bits) < nprod) ++bits;
+  while (bits < 20 && ((int64_t)bin_slots / 2 << bits) < nprod) ++bits;
   p->l2 = std::min(10, bits / 2);
   p->l1 = std::max(1, bits - p->l2);
   const int64_t bx = std::max<int64_t>(1, (nb + RADIX_THREADS - 1) / RADIX_THREADS);
@@ -569,7 +570,7 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
       if (contrib > ((int64_t)1 << 36))
         return fail(ctx, KP_E_CAPACITY, "%lld products exceed the partitioned table",
                     (long long)contrib);
-      radix_shape(na, nb, contrib, p);
+      radix_shape(na, nb, contrib, ctx->tune.hash_bin_slots, p);
     }
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
@@ -646,6 +647,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.hash_partitioned = 1;
   ctx->tune.hash_bucket = 0;
   ctx->tune.hash_order = 1;
+  ctx->tune.hash_bin_slots = 4096;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
     *out = ctx;
     return KP_OK;
@@ -804,6 +806,8 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "hash_bucket must lie in [0, 16]");
   if (t->hash_order != 0 && t->hash_order != 1)
     return fail(ctx, KP_E_ARG, "hash_order must be 0 or 1");
+  if (t->hash_bin_slots != 2048 && t->hash_bin_slots != 4096 && t->hash_bin_slots != 8192)
+    return fail(ctx, KP_E_ARG, "hash_bin_slots must be 2048, 4096 or 8192");
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");
@@ -1033,6 +1037,7 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       RadixArgs R{a_codes, a_coef, na, b_codes, b_coef, nb, 0, PoissonPrep{}, p.rows, p.l1,
                   p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_codes,
                   out_coef, out_cap, H.stats, H.ev0, H.ev1};
+      R.bin_log = p.blog;
       R.a_sa = tr.sa;
       R.b_tb = tr.tb;
       if (xo) {
@@ -1163,6 +1168,7 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
     RadixArgs R{nullptr, a_coef, na, nullptr, b_coef, nb, layout->Wx, h.pp, p.rows, p.l1,
                 p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_keys,
                 out_coef, out_cap, H.stats, H.ev0, H.ev1};
+    R.bin_log = p.blog;
     if (e == hipSuccess) e = launch_radix(R, 2, stream);
   } else if (na > 0 && nb > 0 && layout->nkeys > 0) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);

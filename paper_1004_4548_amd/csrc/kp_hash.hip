@@ -360,16 +360,18 @@ constexpr int RADIX_BLOCK = RADIX_THREADS;   // count and scatter: threads over 
 constexpr int STAGE = 8192;          // entries staged per chunk (8 per thread): 128 KiB of LDS
 constexpr int RADIX_MAX_L = 10;      // at most 1024 partitions per level
 constexpr int SPLIT_BLOCK = 1024;
-constexpr int BIN_BLOCK = 256;
-constexpr int BIN_SLOTS = 2048;      // LDS table of one bin: 2048 x (8 + 8) bytes
+// A bin's LDS table has 2^LOG slots of 8 + 8 bytes (LOG 11, 12 or 13: 32, 64
+// or 128 KiB, four, two or one workgroup per CU) and 2^LOG / 8 threads.
+constexpr int BIN_PER_THREAD = 8;
 
 __device__ __forceinline__ uint64_t code_hash(int64_t code) { return (uint64_t)code * GOLDEN; }
 __device__ __forceinline__ uint32_t part1(uint64_t h, int l1) { return (uint32_t)(h >> (64 - l1)); }
 __device__ __forceinline__ uint32_t part2(uint64_t h, int l1, int l2) {
   return (uint32_t)(h >> (64 - l1 - l2)) & ((1u << l2) - 1);
 }
+template <int LOG>
 __device__ __forceinline__ uint32_t bin_slot(uint64_t h, int l1, int l2) {
-  return (uint32_t)(h >> (64 - l1 - l2 - 12)) & (BIN_SLOTS - 1);
+  return (uint32_t)(h >> (64 - l1 - l2 - LOG)) & ((1u << LOG) - 1);
 }
 
 // Every nonzero product of this thread: its term j of B against rows
@@ -430,23 +432,36 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
     const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
     const int tb = R.P.bt[j];
     const double cb = static_cast<const double*>(R.bc)[j];
+    // rows of A loaded two at a time (as for Laurent products below)
+    int at[2];
+    double ca[2];
+    int64_t akx[2], ap[2];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t i = r0 + u;
-      if (i >= r1) break;
-      const int ta = R.P.at[i];
-      const double h = 0.5 * (ac[i] * cb);
+      if ((u & 1) == 0) {
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const int64_t i = min(r0 + u + w, r1 - 1);
+          at[w] = R.P.at[i];
+          ca[w] = ac[i];
+          akx[w] = R.P.akx[i];
+          ap[w] = R.P.ap[i];
+        }
+      }
+      if (r0 + u >= r1) break;
+      const int ta = at[u & 1];
+      const double h = 0.5 * (ca[u & 1] * cb);
       if (h == 0.0) continue;
-      const int64_t kx = R.P.akx[i] + kxb;
+      const int64_t kx = akx[u & 1] + kxb;
       const int t = ta ^ tb;
       const double sm = (!ta && tb) ? -h : h;
       const double sp = (ta && tb) ? -h : h;
       double v;
-      if (poisson_piece(R.Wx, R.P.ap[i] + Bm, kx, t, sm, &code[2 * u], &v)) {
+      if (poisson_piece(R.Wx, ap[u & 1] + Bm, kx, t, sm, &code[2 * u], &v)) {
         bits[2 * u] = __double_as_longlong(v);
         mask |= 1u << (2 * u);
       }
-      if (poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &code[2 * u + 1], &v)) {
+      if (poisson_piece(R.Wx, ap[u & 1] + Bp, kx, t, sp, &code[2 * u + 1], &v)) {
         bits[2 * u + 1] = __double_as_longlong(v);
         mask |= 1u << (2 * u + 1);
       }
@@ -457,16 +472,31 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
     const int64_t bj = R.bk[j];
     const T cb = static_cast<const T*>(R.bc)[j];
     const int32_t tb = R.a_sa ? R.b_tb[j] : INT_MIN;
+    // rows of A are loaded four at a time (one wait per four rows, not one
+    // per row); rows past the end repeat the last row and are not used
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = r0 + u;
-      if (i >= r1) break;
-      if (R.a_sa && tb > R.a_sa[i]) continue;   // over the degree limit
-      const T v = mul_coef<T>(ac[i], cb, narrow);
-      if (v == T(0)) continue;
-      code[u] = R.ak[i] + bj;
-      __builtin_memcpy(&bits[u], &v, 8);
-      mask |= 1u << u;
+    for (int h = 0; h < 8; h += 4) {
+      if (r0 + h >= r1) break;
+      int64_t ka[4];
+      T ca[4];
+      int32_t sa[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = min(r0 + h + u, r1 - 1);
+        ka[u] = R.ak[i];
+        ca[u] = ac[i];
+        sa[u] = R.a_sa ? R.a_sa[i] : INT_MAX;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (r0 + h + u >= r1) break;
+        if (tb > sa[u]) continue;   // over the degree limit
+        const T v = mul_coef<T>(ca[u], cb, narrow);
+        if (v == T(0)) continue;
+        code[h + u] = ka[u] + bj;
+        __builtin_memcpy(&bits[h + u], &v, 8);
+        mask |= 1u << (h + u);
+      }
     }
   }
   return mask;
@@ -655,13 +685,13 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
   }
   __syncthreads();
   constexpr int U = 8;   // loads in flight per thread
+  // (indices past the partition repeat its last entry, unused: loads without
+  // a branch each, so that they are all in flight together)
   for (int64_t k0 = s + tid; k0 < e; k0 += (int64_t)SPLIT_BLOCK * U) {
     uint2 c[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = k0 + (int64_t)u * SPLIT_BLOCK;
-      c[u] = k < e ? reinterpret_cast<const uint2*>(R.ent1)[2 * k] : make_uint2(0, 0);
-    }
+    for (int u = 0; u < U; ++u)
+      c[u] = reinterpret_cast<const uint2*>(R.ent1)[2 * min(k0 + (int64_t)u * SPLIT_BLOCK, e - 1)];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (k0 + (int64_t)u * SPLIT_BLOCK < e) {
@@ -678,14 +708,15 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
   }
   if (p == ((int64_t)1 << R.l1) - 1 && tid == 0) R.bstart[(p + 1) * P2] = e;
   __syncthreads();
-  for (int64_t c0 = s; c0 < e; c0 += STAGE) {
-    uint4 en[U];
-    uint32_t bin[U], rank[U];
+  // each chunk's entries are loaded while the previous chunk is written out
+  uint4 en[U];
+  const auto load_chunk = [&](int64_t c0) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = c0 + (int64_t)u * SPLIT_BLOCK + tid;
-      en[u] = k < e ? R.ent1[k] : make_uint4(0, 0, 0, 0);
-    }
+    for (int u = 0; u < U; ++u) en[u] = R.ent1[min(c0 + (int64_t)u * SPLIT_BLOCK + tid, e - 1)];
+  };
+  if (s < e) load_chunk(s);
+  for (int64_t c0 = s; c0 < e; c0 += STAGE) {
+    uint32_t bin[U], rank[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (c0 + (int64_t)u * SPLIT_BLOCK + tid < e) {
@@ -702,6 +733,7 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (c0 + (int64_t)u * SPLIT_BLOCK + tid < e) stage[coff[bin[u]] + rank[u]] = en[u];
+    if (c0 + STAGE < e) load_chunk(c0 + STAGE);
     __syncthreads();
     for (uint32_t t = tid; t < total; t += SPLIT_BLOCK) {
       const uint4 x = stage[t];
@@ -724,8 +756,9 @@ __device__ __forceinline__ void lds_slot_add(double* p, double v) { atomicAdd(p,
 
 // One workgroup per level-2 bin: accumulate in an LDS table, then write the
 // nonzero terms at an offset taken from the call's output counter.
-template <typename T>
-__global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
+template <typename T, int LOG>
+__global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(RadixArgs R) {
+  constexpr int BIN_SLOTS = 1 << LOG, BIN_BLOCK = BIN_SLOTS / BIN_PER_THREAD;
   __shared__ unsigned long long keys[BIN_SLOTS];
   __shared__ T vals[BIN_SLOTS];
   __shared__ int64_t s_wave[BIN_BLOCK / 64];
@@ -734,20 +767,28 @@ __global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
   const int64_t s = R.bstart[b], e = R.bstart[b + 1];
   if (s == e) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The bin's first BIN_PER_THREAD entries per thread (a table's worth) are
+  // loaded at once, before the table is cleared: one memory round trip for
+  // the whole bin instead of one per entry.
+  // (indices past the bin repeat its last entry, unused: loads without a
+  // branch each, so that they are all in flight together)
+  uint4 en[BIN_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < BIN_PER_THREAD; ++u)
+    en[u] = R.ent2[min(s + tid + (int64_t)u * BIN_BLOCK, e - 1)];
   for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
     keys[i] = 0;
     vals[i] = T(0);
   }
   __syncthreads();
   int64_t ins = 0, extra = 0;
-  for (int64_t k = s + tid; k < e; k += BIN_BLOCK) {
-    const uint4 en = R.ent2[k];
-    const int64_t code = (int64_t)(((uint64_t)en.y << 32) | en.x);
-    const uint64_t bits = ((uint64_t)en.w << 32) | en.z;
+  const auto insert = [&](const uint4& x) {
+    const int64_t code = (int64_t)(((uint64_t)x.y << 32) | x.x);
+    const uint64_t bits = ((uint64_t)x.w << 32) | x.z;
     T v;
     __builtin_memcpy(&v, &bits, 8);
     const unsigned long long key = (unsigned long long)code + 1;
-    uint32_t slot = bin_slot(code_hash(code), R.l1, R.l2);
+    uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, R.l2);
     int q = 0;
     for (; q < BIN_SLOTS; ++q) {
       unsigned long long c = keys[slot];
@@ -764,49 +805,74 @@ __global__ void __launch_bounds__(BIN_BLOCK) k_radix_bins(RadixArgs R) {
     if (q == BIN_SLOTS) atomicOr(&R.meta->err, ERR_CAPACITY);
     ++ins;
     extra += q;
-  }
+  };
+#pragma unroll
+  for (int u = 0; u < BIN_PER_THREAD; ++u)
+    if (s + tid + (int64_t)u * BIN_BLOCK < e) insert(en[u]);
+  // bins of many products per code can hold more entries than slots
+  for (int64_t k = s + tid + (int64_t)BIN_PER_THREAD * BIN_BLOCK; k < e; k += BIN_BLOCK)
+    insert(R.ent2[k]);
   __syncthreads();
-  // compaction: thread tid owns slots tid + r * BIN_BLOCK
-  constexpr int PER = BIN_SLOTS / BIN_BLOCK;
+  // Compaction to the front of the table: thread tid owns slots
+  // tid + r * BIN_BLOCK; every slot is read before any is rewritten.
+  constexpr int PER = BIN_PER_THREAD;
+  unsigned long long kk[PER];
+  T vv[PER];
   uint64_t ball[PER];
   int64_t cnt = 0;
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const int i = r * BIN_BLOCK + tid;
-    ball[r] = __ballot(keys[i] != 0 && vals[i] != T(0));
+    kk[r] = keys[i];
+    vv[r] = vals[i];
+    ball[r] = __ballot(kk[r] != 0 && vv[r] != T(0));
     cnt += __popcll(ball[r]);
   }
   if (lane == 0) s_wave[wave] = cnt;
   __syncthreads();
-  if (tid == 0) {
-    int64_t tot = 0;
-    for (int w = 0; w < BIN_BLOCK / 64; ++w) tot += s_wave[w];
+  int64_t tot = 0, pos = 0;
+  for (int w = 0; w < BIN_BLOCK / 64; ++w) {
+    if (w == wave) pos = tot;
+    tot += s_wave[w];
+  }
+  if (tid == 0)
     s_base = tot ? (int64_t)atomicAdd((unsigned long long*)&R.meta->out_count,
                                       (unsigned long long)tot)
                  : 0;
-  }
-  __syncthreads();
-  int64_t pos = s_base;
-  for (int w = 0; w < wave; ++w) pos += s_wave[w];
   const uint64_t lt = (1ull << lane) - 1;
-  T* out_c = static_cast<T*>(R.out_c);
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     if (ball[r] & (1ull << lane)) {
-      const int i = r * BIN_BLOCK + tid;
       const int64_t q = pos + __popcll(ball[r] & lt);
-      if (q < R.out_cap) {
-        if (R.out_x) {
-          int32_t ex[KP_MAX_VARS];
-          decode_x(R.dec, (uint64_t)(keys[i] - 1), ex);
-          for (int v = 0; v < R.dec.nx; ++v) R.out_x[q * R.dec.nx + v] = ex[v];
-        } else {
-          R.out_k[q] = (int64_t)(keys[i] - 1);
-        }
-        out_c[q] = vals[i];
-      }
+      keys[q] = kk[r];
+      vals[q] = vv[r];
     }
     pos += __popcll(ball[r]);
+  }
+  __syncthreads();
+  // the bin's terms, one per thread and all lanes busy, at the offset taken
+  // from the call's output counter
+  const int64_t base = s_base;
+  const int64_t n = min(tot, R.out_cap - base);
+  T* out_c = static_cast<T*>(R.out_c);
+  const int nx = R.dec.nx;
+  const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
+  for (int64_t t = tid; t < n; t += BIN_BLOCK) {
+    const int64_t q = base + t;
+    const uint64_t code = (uint64_t)(keys[t] - 1);
+    if (R.out_x) {
+      int32_t ex[KP_MAX_VARS];
+      decode_x(R.dec, code, ex);
+      if (pairs) {
+        int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
+        for (int v = 0; v < nx; v += 2) o[v >> 1] = make_int2(ex[v], ex[v + 1]);
+      } else {
+        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = ex[v];
+      }
+    } else {
+      R.out_k[q] = (int64_t)code;
+    }
+    out_c[q] = vals[t];
   }
   if (R.stats) add_stats(R.stats, ins, extra);
 }
@@ -1045,11 +1111,17 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_radix_scatter<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_radix_split, dim3(P1), dim3(SPLIT_BLOCK), 0, s, R);
-  const unsigned bins = P1 << R.l2;
-  if (kind == 0)
-    hipLaunchKernelGGL(k_radix_bins<int64_t>, dim3(bins), dim3(BIN_BLOCK), 0, s, R);
-  else
-    hipLaunchKernelGGL(k_radix_bins<double>, dim3(bins), dim3(BIN_BLOCK), 0, s, R);
+  const dim3 bins(P1 << R.l2), block((1u << R.bin_log) / BIN_PER_THREAD);
+  if (R.bin_log == 13) {
+    if (kind == 0) hipLaunchKernelGGL((k_radix_bins<int64_t, 13>), bins, block, 0, s, R);
+    else hipLaunchKernelGGL((k_radix_bins<double, 13>), bins, block, 0, s, R);
+  } else if (R.bin_log == 12) {
+    if (kind == 0) hipLaunchKernelGGL((k_radix_bins<int64_t, 12>), bins, block, 0, s, R);
+    else hipLaunchKernelGGL((k_radix_bins<double, 12>), bins, block, 0, s, R);
+  } else {
+    if (kind == 0) hipLaunchKernelGGL((k_radix_bins<int64_t, 11>), bins, block, 0, s, R);
+    else hipLaunchKernelGGL((k_radix_bins<double, 11>), bins, block, 0, s, R);
+  }
   if (R.ev1) (void)hipEventRecord(R.ev1, s);
   return hipGetLastError();
 }

@@ -383,6 +383,7 @@ struct RadixArgs {
   const int32_t* b_tb;   // b_tb[j] <= a_sa[i]
   int32_t* out_x;        // optional (Laurent): decoded exponents instead of codes
   DevLayout dec;
+  int bin_log = 11;      // log2 of the slots of a bin's LDS table (11, 12 or 13)
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);

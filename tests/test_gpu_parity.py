@@ -320,6 +320,30 @@ def test_poisson_hash_layouts(part):
     check_poisson(a, b, f"poisson hash (partitioned={part})", mode="hash")
 
 
+@pytest.mark.parametrize("slots", [2048, 4096, 8192])
+def test_partitioned_bin_tables(slots):
+    """Every size of a bin's LDS table (bins hold half a table of products on
+    average) on sparse, duplicate-heavy, fp64, truncated and Poisson
+    products."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots)
+    a, b = I.config(3, scale=0.1)
+    check_laurent(a, b, "hash", f"sparse 3000, bins of {slots}")
+    a, b = I.config(1)
+    check_laurent(a, b, "hash", f"box 500 x 500, bins of {slots}")
+    a, b = I.config(2, scale=0.05)
+    a64 = (a[0], a[1].astype(np.float64) / 8)
+    check_laurent(a64, (b[0], b[1].astype(np.float64)), "hash", f"fp64 simplex, bins of {slots}")
+    what, ta, tb, w, D = _trunc_cases()[-1]
+    say("truncated", what, "bins of", slots)
+    with ctx.truncation(w, D):
+        ge, gc, _ = gpu_laurent(ta, tb, "hash", ctx)
+    oe, oc, _ = O.laurent_mul_truncated(ta[0], ta[1], tb[0], tb[1], w, D, threads=4)
+    assert_exact([ge], gc, [oe], oc, what)
+    pa, pb = I.config(4, scale=0.06)
+    check_poisson(pa, pb, f"poisson hash, bins of {slots}", mode="hash")
+
+
 def test_repeat_runs_bit_identical():
     a, b = I.config(2, scale=0.2)
     r1 = gpu_laurent(a, b, "hash")

@@ -234,10 +234,14 @@ def test_tune_validation():
     for bad in (dict(window=18432 + 2048), dict(block=100), dict(hash_load=0.95),
                 dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1),
                 dict(hash_partitioned=3), dict(hash_partitioned=-1), dict(hash_bucket=-1),
-                dict(hash_bucket=17), dict(hash_order=2)):
+                dict(hash_bucket=17), dict(hash_order=2), dict(hash_bin_slots=0),
+                dict(hash_bin_slots=3000), dict(hash_bin_slots=16384)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
-    assert t.hash_bucket == 0 and t.hash_order == 1
+    assert t.hash_bucket == 0 and t.hash_order == 1 and t.hash_bin_slots == 4096
+    for slots in (2048, 4096, 8192):
+        ctx.set_tune(hash_bin_slots=slots)
+        assert ctx.tune.hash_bin_slots == slots
 
 
 def test_partitioned_hash_workspace():
