@@ -134,7 +134,7 @@ typedef struct kp_tune {
   int32_t hash_rows;        /* hash: factor-A rows per thread (global table)         */
   int32_t hash_partitioned; /* hash: 2 = products grouped by hash bits in two levels
                                through HBM, each group accumulated in an LDS table
-                               (workspace 32 bytes per product); 0 = one open-addressing
+                               (workspace 34 bytes per product); 0 = one open-addressing
                                table in HBM; 1 (default) = grouped when the products are
                                at most 4 times the result bound, else the table          */
   int32_t hash_bucket;      /* hash, Laurent, int64/fp64: > 0 selects Section 3.2's bucketed

@@ -406,6 +406,7 @@ struct HashCarve {
   int64_t* bstart;
   uint4* ent1;
   uint4* ent2;
+  uint16_t* bin1;
 };
 
 // Shape of the partitioned accumulation: at most half a bin's LDS table of
@@ -431,6 +432,7 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
   h->counts = nullptr;
   h->pstart = h->bstart = nullptr;
   h->ent1 = h->ent2 = nullptr;
+  h->bin1 = nullptr;
   h->ord_ak = h->ord_bk = nullptr;
   h->ord_ac = h->ord_bc = nullptr;
   h->ord_rank = h->ord_sa = h->ord_tb = nullptr;
@@ -441,6 +443,7 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     h->bstart = c.take<int64_t>((size_t)bins + 1);
     h->ent1 = c.take<uint4>((size_t)p.nprod);
     h->ent2 = c.take<uint4>((size_t)p.nprod);
+    h->bin1 = c.take<uint16_t>((size_t)p.nprod);
   } else {
     const int64_t slots = p.bucket ? p.nbuckets * p.bm + p.ovcap : p.cap;
     h->table = c.take<uint64_t>((size_t)(p.cw == 2 ? 4 : 2) * slots);   // 16- or 32-byte slots
@@ -1038,6 +1041,7 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
                   p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_codes,
                   out_coef, out_cap, H.stats, H.ev0, H.ev1};
       R.bin_log = p.blog;
+      R.bin1 = h.bin1;
       R.a_sa = tr.sa;
       R.b_tb = tr.tb;
       if (xo) {
@@ -1169,6 +1173,7 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
                 p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_keys,
                 out_coef, out_cap, H.stats, H.ev0, H.ev1};
     R.bin_log = p.blog;
+    R.bin1 = h.bin1;
     if (e == hipSuccess) e = launch_radix(R, 2, stream);
   } else if (na > 0 && nb > 0 && layout->nkeys > 0) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);

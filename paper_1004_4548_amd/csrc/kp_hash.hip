@@ -652,8 +652,11 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
     __syncthreads();
     for (uint32_t t = tid; t < total; t += RADIX_BLOCK) {
       const uint4 en = stage[t];
-      const uint32_t p = part1(code_hash((int64_t)(((uint64_t)en.y << 32) | en.x)), R.l1);
-      R.ent1[base[p] + done[p] + (t - coff[p])] = en;
+      const uint64_t h = code_hash((int64_t)(((uint64_t)en.y << 32) | en.x));
+      const uint32_t p = part1(h, R.l1);
+      const int64_t at = base[p] + done[p] + (t - coff[p]);
+      R.ent1[at] = en;
+      R.bin1[at] = (uint16_t)part2(h, R.l1, R.l2);   // for the split's histogram
     }
     __syncthreads();
     if (tid < P1) {
@@ -685,19 +688,17 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
   }
   __syncthreads();
   constexpr int U = 8;   // loads in flight per thread
-  // (indices past the partition repeat its last entry, unused: loads without
-  // a branch each, so that they are all in flight together)
-  for (int64_t k0 = s + tid; k0 < e; k0 += (int64_t)SPLIT_BLOCK * U) {
-    uint2 c[U];
+  // Histogram from the 2-byte bin ids the scatter wrote beside the entries.
+  // (Indices past the partition repeat its last entry, unused: loads without
+  // a branch each, so that they are all in flight together.)
+  constexpr int UB = 16;
+  for (int64_t k0 = s + tid; k0 < e; k0 += (int64_t)SPLIT_BLOCK * UB) {
+    uint32_t c[UB];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      c[u] = reinterpret_cast<const uint2*>(R.ent1)[2 * min(k0 + (int64_t)u * SPLIT_BLOCK, e - 1)];
+    for (int u = 0; u < UB; ++u) c[u] = R.bin1[min(k0 + (int64_t)u * SPLIT_BLOCK, e - 1)];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (k0 + (int64_t)u * SPLIT_BLOCK < e) {
-        const int64_t code = (int64_t)(((uint64_t)c[u].y << 32) | c[u].x);
-        atomicAdd(&h2[part2(code_hash(code), R.l1, R.l2)], 1u);
-      }
+    for (int u = 0; u < UB; ++u)
+      if (k0 + (int64_t)u * SPLIT_BLOCK < e) atomicAdd(&h2[c[u]], 1u);
   }
   __syncthreads();
   uint32_t all;
@@ -860,14 +861,16 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   for (int64_t t = tid; t < n; t += BIN_BLOCK) {
     const int64_t q = base + t;
     const uint64_t code = (uint64_t)(keys[t] - 1);
-    if (R.out_x) {
-      int32_t ex[KP_MAX_VARS];
-      decode_x(R.dec, code, ex);
+    if (R.out_x) {   // decoded exponents, written as they are found
+      uint64_t c = code;
       if (pairs) {
         int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
-        for (int v = 0; v < nx; v += 2) o[v >> 1] = make_int2(ex[v], ex[v + 1]);
+        for (int v = 0; v < nx; v += 2) {
+          const int32_t lo = decode_step(R.dec, v, c);
+          o[v >> 1] = make_int2(lo, decode_step(R.dec, v + 1, c));
+        }
       } else {
-        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = ex[v];
+        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
       }
     } else {
       R.out_k[q] = (int64_t)code;

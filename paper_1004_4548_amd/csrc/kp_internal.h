@@ -117,12 +117,17 @@ __host__ __device__ inline uint32_t encode_term(const DevLayout& L, const int32_
 }
 
 // Laurent product code -> exponents.
+// Exponent v of the code whose quotient by the widths of variables < v is q;
+// q becomes the quotient by the widths up to v.
+__host__ __device__ inline int32_t decode_step(const DevLayout& L, int v, uint64_t& q) {
+  const uint64_t qq = fdiv(q, L.dx[v]);
+  const int32_t e = (int32_t)((int64_t)(q - qq * L.dx[v].d) + L.xmin[v]);
+  q = qq;
+  return e;
+}
+
 __host__ __device__ inline void decode_x(const DevLayout& L, uint64_t q, int32_t* e) {
-  for (int v = 0; v < L.nx; ++v) {
-    uint64_t qq = fdiv(q, L.dx[v]);
-    e[v] = (int32_t)((int64_t)(q - qq * L.dx[v].d) + L.xmin[v]);
-    q = qq;
-  }
+  for (int v = 0; v < L.nx; ++v) e[v] = decode_step(L, v, q);
 }
 
 // |ky| -> canonical balanced digits, y_0 most significant.
@@ -384,6 +389,7 @@ struct RadixArgs {
   int32_t* out_x;        // optional (Laurent): decoded exponents instead of codes
   DevLayout dec;
   int bin_log = 11;      // log2 of the slots of a bin's LDS table (11, 12 or 13)
+  uint16_t* bin1 = nullptr;   // [products] level-2 bin of each entry of ent1
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
