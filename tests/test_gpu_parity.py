@@ -344,6 +344,32 @@ def test_partitioned_bin_tables(slots):
     check_poisson(pa, pb, f"poisson hash, bins of {slots}", mode="hash")
 
 
+@pytest.mark.parametrize("slots", [2048, 4096, 8192])
+def test_partitioned_full_bin_is_a_capacity_error(slots):
+    """Univariate codes whose multiplicative hash (code times the 64-bit
+    golden-ratio constant) has its top three bits zero all fall in bin 0
+    while the product has at most 4 bins; slots + 1000 of them overflow that
+    bin's table: reported as a capacity error, not hung, and the next product
+    is unaffected."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots)
+    rng = np.random.default_rng(slots)
+    e = np.unique(rng.integers(1, 1 << 31, 1 << 20, dtype=np.int64))
+    with np.errstate(over="ignore"):
+        h = e.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    e = e[(h >> np.uint64(61)) == 0][: slots + 999]
+    assert len(e) == slots + 999
+    a = (np.concatenate([[0], e]).astype(np.int32).reshape(-1, 1), np.ones(slots + 1000, np.int64))
+    b = (np.zeros((1, 1), np.int32), np.ones(1, np.int64))
+    say("partitioned capacity error,", slots + 1000, "codes in one bin of", slots, "slots")
+    with pytest.raises(kp.KPError) as err:
+        gpu_laurent(a, b, "hash", ctx)
+    assert err.value.status == kp.KP_E_CAPACITY
+    ctx.sync_check()
+    a2, b2 = I.config(3, scale=0.03)
+    check_laurent(a2, b2, "hash", f"after the capacity error, bins of {slots}", ctx)
+
+
 def test_repeat_runs_bit_identical():
     a, b = I.config(2, scale=0.2)
     r1 = gpu_laurent(a, b, "hash")
