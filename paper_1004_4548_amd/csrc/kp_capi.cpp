@@ -1110,13 +1110,23 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
   return KP_OK;
 }
 
+// Decoded output of a Poisson product: the grouped-products hash path writes
+// it directly (and sets `decoded`), the others write keys.
+struct PoissonOut {
+  int32_t* x;
+  int32_t* y;
+  uint8_t* sin;
+  DevLayout dec;
+  bool decoded;
+};
+
 kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
                           const int64_t* a_x, const int64_t* a_y, const uint8_t* a_sin,
                           const double* a_coef, int64_t na, const int64_t* b_x,
                           const int64_t* b_y, const uint8_t* b_sin, const double* b_coef,
                           int64_t nb, int64_t* out_keys, double* out_coef, int64_t out_cap,
                           int64_t* out_n, void* workspace, size_t workspace_bytes,
-                          hipStream_t stream, bool timed) {
+                          hipStream_t stream, bool timed, PoissonOut* po = nullptr) {
   if (!ctx) return KP_E_ARG;
   if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
   if (layout && layout->ny == 0) return fail(ctx, KP_E_ARG, "kp_mul_poisson: layout has ny == 0");
@@ -1174,6 +1184,13 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
                 out_coef, out_cap, H.stats, H.ev0, H.ev1};
     R.bin_log = p.blog;
     R.bin1 = h.bin1;
+    if (po) {
+      R.out_x = po->x;
+      R.out_y = po->y;
+      R.out_t = po->sin;
+      R.dec = po->dec;
+      po->decoded = true;
+    }
     if (e == hipSuccess) e = launch_radix(R, 2, stream);
   } else if (na > 0 && nb > 0 && layout->nkeys > 0) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
@@ -1409,13 +1426,16 @@ kp_status kp_mul_poisson_exps(kp_ctx* ctx, const kp_layout* layout, kp_mode mode
     e = launch_encode2(make_dev_layout(*layout, 0), make_dev_layout(*layout, 1), na, nb, a_x, a_y,
                        a_sin, kxa, kya, b_x, b_y, b_sin, kxb, kyb, &ctx->status->err, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson_exps encode");
+  PoissonOut po{out_x, out_y, out_sin, make_dev_layout(*layout, 0), false};
   st = enqueue_poisson(ctx, layout, mode, kxa, kya, a_sin, a_coef, na, kxb, kyb, b_sin, b_coef,
                        nb, ok, out_coef, ncodes, out_n, static_cast<char*>(workspace) + c.off,
-                       workspace_bytes - c.off, stream, true);
+                       workspace_bytes - c.off, stream, true, &po);
   if (st != KP_OK) return st;
-  e = launch_decode_n(make_dev_layout(*layout, 0), 1, out_n, ncodes, ok, out_x, out_y, out_sin,
-                      &ctx->status->err, stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson_exps decode");
+  if (!po.decoded) {
+    e = launch_decode_n(make_dev_layout(*layout, 0), 1, out_n, ncodes, ok, out_x, out_y, out_sin,
+                        &ctx->status->err, stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kp_mul_poisson_exps decode");
+  }
   if (flags & KP_FLAG_ASYNC) return finish(ctx, flags, stream, "kp_mul_poisson_exps");
   return wait_count(ctx, out_n, n_host, stream, "kp_mul_poisson_exps");
 }

@@ -861,7 +861,15 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   for (int64_t t = tid; t < n; t += BIN_BLOCK) {
     const int64_t q = base + t;
     const uint64_t code = (uint64_t)(keys[t] - 1);
-    if (R.out_x) {   // decoded exponents, written as they are found
+    if (R.out_t) {   // Poisson key: sin flag, then kx + Wx |ky|, decoded
+      uint64_t c = code >> 1;
+      R.out_t[q] = (uint8_t)(code & 1);
+      uint64_t u = fdiv(c, R.dec.dWx);
+      uint64_t kx = c - u * (uint64_t)R.dec.Wx;
+      for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, kx);
+      const int ny = R.dec.ny;
+      for (int v = ny - 1; v >= 0; --v) R.out_y[q * ny + v] = decode_y_step(R.dec, v, u);
+    } else if (R.out_x) {   // decoded exponents, written as they are found
       uint64_t c = code;
       if (pairs) {
         int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);

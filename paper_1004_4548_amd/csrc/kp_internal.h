@@ -130,17 +130,21 @@ __host__ __device__ inline void decode_x(const DevLayout& L, uint64_t q, int32_t
   for (int v = 0; v < L.nx; ++v) e[v] = decode_step(L, v, q);
 }
 
+// Balanced digit v of |ky| (digits are found from v = ny - 1 down, y_0 most
+// significant); u becomes the quotient for the next digit.
+__host__ __device__ inline int32_t decode_y_step(const DevLayout& L, int v, uint64_t& u) {
+  const uint64_t w = L.dy[v].d;
+  const uint64_t h = (uint64_t)L.yh[v];
+  const uint64_t s = u + h;
+  const uint64_t qq = fdiv(s, L.dy[v]);
+  const int64_t d = (int64_t)(s - qq * w) - (int64_t)h;
+  u = qq;  // (u - d) / w == floor((u + h) / w)
+  return (int32_t)d;
+}
+
 // |ky| -> canonical balanced digits, y_0 most significant.
 __host__ __device__ inline void decode_y(const DevLayout& L, uint64_t u, int32_t* j) {
-  for (int v = L.ny - 1; v >= 0; --v) {
-    uint64_t w = L.dy[v].d;
-    uint64_t h = (uint64_t)L.yh[v];
-    uint64_t s = u + h;
-    uint64_t qq = fdiv(s, L.dy[v]);
-    int64_t d = (int64_t)(s - qq * w) - (int64_t)h;
-    j[v] = (int32_t)d;
-    u = qq;  // (u - d) / w == floor((u + h) / w)
-  }
+  for (int v = L.ny - 1; v >= 0; --v) j[v] = decode_y_step(L, v, u);
 }
 
 // ------------------------------------------------------------ wave helpers
@@ -390,6 +394,8 @@ struct RadixArgs {
   DevLayout dec;
   int bin_log = 11;      // log2 of the slots of a bin's LDS table (11, 12 or 13)
   uint16_t* bin1 = nullptr;   // [products] level-2 bin of each entry of ent1
+  int32_t* out_y = nullptr;   // optional (Poisson, with out_x and out_t): decoded
+  uint8_t* out_t = nullptr;   // trigonometric exponents and sin flags instead of keys
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
