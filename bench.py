@@ -257,7 +257,7 @@ def run_mp(kp, ctx, I, args):
     out["exact_128"] = {"term_products_per_s": pm / rx["sec"], "ms_per_step": rx["sec"] * 1e3,
                         "mode": rx["mode"], "result_terms": rx["n_out"],
                         "insert_kernel_ms": rx["kernel_s"] * 1e3,
-                        "note": "int64 factors, exact 128-bit sums (global table, 32-byte slots)"}
+                        "note": "int64 factors, exact 128-bit sums (products grouped by hash bits, 24-byte LDS slots)"}
     if rm["mode"] == "hash":
         pa = kp.Poly(to_dev(f[0]), to_dev(f[1]))
         pb = kp.Poly(to_dev(g[0]), to_dev(g[1]))

@@ -150,7 +150,10 @@ typedef struct kp_tune {
                                code mod N first (Section 3.2's term order), 0 keeps them  */
   int32_t hash_bin_slots;   /* grouped products: slots of one bin's LDS table, 2048, 4096
                                (default) or 8192, 16 bytes each; bins are sized for half
-                               a table of products on average                             */
+                               a table of products on average.  KP_I128 sums use 24-byte
+                               slots and at most 4096 of them (8192 acts as 4096); their
+                               grouped entries carry the pair's 32-bit term indices, so
+                               factors of 2^32 terms or more keep the global table        */
 } kp_tune;
 
 typedef struct kp_ctx kp_ctx;

@@ -564,8 +564,10 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
       p->ovcap = std::max<int64_t>(1024, (int64_t)std::ceil(6.0 * excess * (double)p->nbuckets));
       p->order = ctx->tune.hash_order != 0;
     }
-    // (128-bit sums always use the global table)
-    p->radix = !p->bucket && dt != KP_I128 &&
+    // (128-bit sums: the grouped entries carry 32-bit term indices, and the
+    // bins' LDS tables of 24-byte slots hold at most 4096)
+    const bool idx32 = na < ((int64_t)1 << 32) && nb < ((int64_t)1 << 32);
+    p->radix = !p->bucket && (dt != KP_I128 || idx32) &&
                (ctx->tune.hash_partitioned == 2 ||
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
@@ -573,7 +575,9 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
       if (contrib > ((int64_t)1 << 36))
         return fail(ctx, KP_E_CAPACITY, "%lld products exceed the partitioned table",
                     (long long)contrib);
-      radix_shape(na, nb, contrib, ctx->tune.hash_bin_slots, p);
+      const int slots = dt == KP_I128 ? std::min(ctx->tune.hash_bin_slots, 4096)
+                                      : ctx->tune.hash_bin_slots;
+      radix_shape(na, nb, contrib, slots, p);
     }
     HashCarve h;
     carve_hash(c, *p, poisson, na, nb, &h);
@@ -1049,7 +1053,8 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
         R.dec = xo->dec;
         xo->decoded = true;
       }
-      if (e == hipSuccess) e = launch_radix(R, dtype == KP_F64 ? 1 : 0, stream);
+      if (e == hipSuccess)
+        e = launch_radix(R, dtype == KP_F64 ? 1 : dtype == KP_I128 ? 3 : 0, stream);
     } else if (!empty) {
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,

@@ -402,18 +402,23 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
       if (poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &key, &v)) f(key, __double_as_longlong(v));
     }
   } else {
-    using T = typename std::conditional<KIND == 0, int64_t, double>::type;
+    using T = typename std::conditional<KIND == 1, double, int64_t>::type;
     const T* ac = static_cast<const T*>(R.ac);
     const int64_t bj = R.bk[j];
     const T cb = static_cast<const T*>(R.bc)[j];
     const int32_t tb = R.a_sa ? R.b_tb[j] : INT_MIN;
     for (int64_t i = i0; i < i1; ++i) {
       if (R.a_sa && tb > R.a_sa[i]) continue;   // over the degree limit
-      const T v = mul_coef<T>(ac[i], cb, narrow);
-      if (v == T(0)) continue;
-      int64_t bits;
-      __builtin_memcpy(&bits, &v, 8);
-      f(R.ak[i] + bj, bits);
+      if constexpr (KIND == 3) {   // exact sums: the pair's indices (the bins multiply)
+        if (ac[i] == 0 || cb == 0) continue;
+        f(R.ak[i] + bj, (int64_t)(((uint64_t)i << 32) | (uint64_t)j));
+      } else {
+        const T v = mul_coef<T>(ac[i], cb, narrow);
+        if (v == T(0)) continue;
+        int64_t bits;
+        __builtin_memcpy(&bits, &v, 8);
+        f(R.ak[i] + bj, bits);
+      }
     }
   }
 }
@@ -467,7 +472,7 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
       }
     }
   } else {
-    using T = typename std::conditional<KIND == 0, int64_t, double>::type;
+    using T = typename std::conditional<KIND == 1, double, int64_t>::type;
     const T* ac = static_cast<const T*>(R.ac);
     const int64_t bj = R.bk[j];
     const T cb = static_cast<const T*>(R.bc)[j];
@@ -491,10 +496,15 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
       for (int u = 0; u < 4; ++u) {
         if (r0 + h + u >= r1) break;
         if (tb > sa[u]) continue;   // over the degree limit
-        const T v = mul_coef<T>(ca[u], cb, narrow);
-        if (v == T(0)) continue;
+        if constexpr (KIND == 3) {   // exact sums: the pair's indices (the bins multiply)
+          if (ca[u] == 0 || cb == 0) continue;
+          bits[h + u] = (int64_t)(((uint64_t)(r0 + h + u) << 32) | (uint64_t)j);
+        } else {
+          const T v = mul_coef<T>(ca[u], cb, narrow);
+          if (v == T(0)) continue;
+          __builtin_memcpy(&bits[h + u], &v, 8);
+        }
         code[h + u] = ka[u] + bj;
-        __builtin_memcpy(&bits[h + u], &v, 8);
         mask |= 1u << (h + u);
       }
     }
@@ -754,6 +764,15 @@ __device__ __forceinline__ void lds_slot_add(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 __device__ __forceinline__ void lds_slot_add(double* p, double v) { atomicAdd(p, v); }
+// 128-bit: the low word's returning add gives its carry, which the high word
+// receives with the product's high word (each carry counted by the add that
+// made it, so the sum is exact in any order)
+__device__ __forceinline__ void lds_slot_add(I128* p, I128 v) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(p);
+  const uint64_t old = atomicAdd(w, (unsigned long long)v.lo);
+  const uint64_t carry = old + v.lo < old ? 1u : 0u;
+  atomicAdd(w + 1, (unsigned long long)((uint64_t)v.hi + carry));
+}
 
 // One workgroup per level-2 bin: accumulate in an LDS table, then write the
 // nonzero terms at an offset taken from the call's output counter.
@@ -761,7 +780,8 @@ template <typename T, int LOG>
 __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(RadixArgs R) {
   constexpr int BIN_SLOTS = 1 << LOG, BIN_BLOCK = BIN_SLOTS / BIN_PER_THREAD;
   __shared__ unsigned long long keys[BIN_SLOTS];
-  __shared__ T vals[BIN_SLOTS];
+  __shared__ uint64_t vals_words[BIN_SLOTS * (sizeof(T) / 8)];   // (T may have a constructor)
+  T* vals = reinterpret_cast<T*>(vals_words);
   __shared__ int64_t s_wave[BIN_BLOCK / 64];
   __shared__ int64_t s_base;
   const int64_t b = blockIdx.x;
@@ -785,9 +805,13 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   int64_t ins = 0, extra = 0;
   const auto insert = [&](const uint4& x) {
     const int64_t code = (int64_t)(((uint64_t)x.y << 32) | x.x);
-    const uint64_t bits = ((uint64_t)x.w << 32) | x.z;
     T v;
-    __builtin_memcpy(&v, &bits, 8);
+    if constexpr (std::is_same<T, I128>::value) {   // exact: the entry holds the pair (i, j)
+      v = mul_wide(static_cast<const int64_t*>(R.ac)[x.w], static_cast<const int64_t*>(R.bc)[x.z]);
+    } else {
+      const uint64_t bits = ((uint64_t)x.w << 32) | x.z;
+      __builtin_memcpy(&v, &bits, 8);
+    }
     const unsigned long long key = (unsigned long long)code + 1;
     uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, R.l2);
     int q = 0;
@@ -1107,7 +1131,9 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
   R.nblocks = (int64_t)grid.x * grid.y;
   const unsigned P1 = 1u << R.l1;
   if (R.ev0) (void)hipEventRecord(R.ev0, s);
-  if (kind == 2)
+  if (kind == 3)
+    hipLaunchKernelGGL(k_radix_count<3>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 2)
     hipLaunchKernelGGL(k_radix_count<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
   else if (kind == 1)
     hipLaunchKernelGGL(k_radix_count<1>, grid, dim3(RADIX_BLOCK), 0, s, R);
@@ -1115,7 +1141,9 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
     hipLaunchKernelGGL(k_radix_count<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_radix_scan_parts, dim3(P1), dim3(256), 0, s, R);
   hipLaunchKernelGGL(k_radix_scan_totals, dim3(1), dim3(1024), 0, s, R);
-  if (kind == 2)
+  if (kind == 3)
+    hipLaunchKernelGGL(k_radix_scatter<3>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 2)
     hipLaunchKernelGGL(k_radix_scatter<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
   else if (kind == 1)
     hipLaunchKernelGGL(k_radix_scatter<1>, grid, dim3(RADIX_BLOCK), 0, s, R);
@@ -1123,7 +1151,12 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
     hipLaunchKernelGGL(k_radix_scatter<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_radix_split, dim3(P1), dim3(SPLIT_BLOCK), 0, s, R);
   const dim3 bins(P1 << R.l2), block((1u << R.bin_log) / BIN_PER_THREAD);
-  if (R.bin_log == 13) {
+  if (kind == 3) {   // 128-bit sums: 24-byte slots, tables of at most 4096 (the planner's cap)
+    if (R.bin_log >= 12)
+      hipLaunchKernelGGL((k_radix_bins<I128, 12>), bins, dim3(4096 / BIN_PER_THREAD), 0, s, R);
+    else
+      hipLaunchKernelGGL((k_radix_bins<I128, 11>), bins, dim3(2048 / BIN_PER_THREAD), 0, s, R);
+  } else if (R.bin_log == 13) {
     if (kind == 0) hipLaunchKernelGGL((k_radix_bins<int64_t, 13>), bins, block, 0, s, R);
     else hipLaunchKernelGGL((k_radix_bins<double, 13>), bins, block, 0, s, R);
   } else if (R.bin_log == 12) {

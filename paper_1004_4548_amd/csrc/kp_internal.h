@@ -397,7 +397,9 @@ struct RadixArgs {
   int32_t* out_y = nullptr;   // optional (Poisson, with out_x and out_t): decoded
   uint8_t* out_t = nullptr;   // trigonometric exponents and sin flags instead of keys
 };
-// kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64).
+// kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64), 3 Laurent int64
+// factors with exact 128-bit sums (entries carry the pair's indices, the bins
+// form the products; the planner caps the tables at 4096 slots).
 hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
 // Threads (terms of B) per count / scatter workgroup; the workspace planner
 // sizes the per-workgroup histograms with it.

@@ -74,6 +74,37 @@ def test_exact_sparse_hash():
     check_exact((ea, _big(rng, len(ea))), (eb, _big(rng, len(eb))), "hash", "6-variable sparse")
 
 
+@pytest.mark.parametrize("part", [0, 2])
+def test_exact_hash_layouts(part):
+    """Both hash layouts with 128-bit sums: one HBM table of 32-byte slots
+    (partitioned=0), and products grouped by hash bits (partitioned=2), whose
+    entries carry the pair's term indices; the bins form each product and add
+    it into 24-byte LDS slots, the carry taken from the low word's returning
+    add.  Every bin table size (8192 slots are capped at 4096 for these)."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=part)
+    rng = np.random.default_rng(40 + part)
+    (ea, _), (eb, _) = I.config(1, scale=0.5)
+    check_exact((ea, _big(rng, len(ea))), (eb, _big(rng, len(eb))), "hash",
+                f"box, 62-bit coefficients (partitioned={part})", ctx)
+    (ea, _), (eb, _) = I.config(3, scale=0.03)
+    ca, cb = _big(rng, len(ea), 63), _big(rng, len(eb), 63)
+    ca[::7] = 0   # zero terms make no products
+    check_exact((ea, ca), (eb, cb), "hash", f"sparse, 63-bit, zero terms (partitioned={part})", ctx)
+    n = 4097   # one code, every add after the first carries out of the low word
+    a = (np.zeros((n, 1), np.int32), np.full(n, 2**32 + 1, np.int64))
+    b = (np.zeros((1, 1), np.int32), np.array([2**32 - 1], np.int64))
+    say("one code,", n, "adds, partitioned", part)
+    ge, gc, _ = gpu_exact(a, b, "hash", ctx)
+    assert O.wide_to_int(gc) == [n * (2**64 - 1)]
+    if part == 2:
+        (ea, _), (eb, _) = I.config(2, scale=0.08)
+        a, b = (ea, _big(rng, len(ea))), (eb, _big(rng, len(eb)))
+        for slots in (2048, 4096, 8192):
+            ctx.set_tune(hash_bin_slots=slots)
+            check_exact(a, b, "hash", f"simplex, bins of {slots} slots", ctx)
+
+
 def test_exact_split_windows_and_small_windows():
     """Windows split across tasks add their 128-bit partial sums into the HBM
     accumulator with a carry between the words."""
