@@ -121,7 +121,7 @@ def test_bucketed_truncated(order):
 
 
 def test_bucketed_not_used_for_poisson_or_exact():
-    """Poisson series and 128-bit sums keep the open-addressing table."""
+    """Poisson series and 128-bit sums ignore hash_bucket and take the other layouts."""
     ctx = kp.context()
     ctx.set_tune(hash_bucket=4)
     pa, pb = I.config(4, scale=0.02)

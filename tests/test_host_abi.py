@@ -294,7 +294,7 @@ def test_bucketed_hash_workspace():
         assert 20 * (na + nb) <= ws1 - ws0 < 20 * (na + nb) + 5 * 256
         if m == 1:
             assert ov > cap // 5   # a fifth of the codes overflow single-slot buckets at load 0.5
-    # 128-bit sums keep the open-addressing table
+    # 128-bit sums ignore hash_bucket
     ctx.set_tune(hash_bucket=0)
     ws128 = kp.mul_bound(sparse, False, kp.KP_I128, "hash", na, nb, ctx)[2]
     ctx.set_tune(hash_bucket=8)
