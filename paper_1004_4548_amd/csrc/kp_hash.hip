@@ -605,10 +605,20 @@ __global__ void __launch_bounds__(256) k_radix_scan_parts(RadixArgs R) {
 }
 
 // Partition totals -> partition starts (pstart[P1] = number of products).
+// Partition starts, and the level-2 bits for the products actually made:
+// bins of at most half a table on average, as planned for all pairs, so that
+// a truncated product (or one with many zero products) does not pay for
+// bins it leaves empty.
 __global__ void __launch_bounds__(1024) k_radix_scan_totals(RadixArgs R) {
   const int64_t P1 = (int64_t)1 << R.l1;
   const int64_t total = block_scan_runs<1024>(R.pstart, P1, R.meta);
-  if (threadIdx.x == 0) R.pstart[P1] = total;
+  if (threadIdx.x == 0) {
+    R.pstart[P1] = total;
+    const int64_t half = ((int64_t)1 << R.bin_log) / 2;
+    int bits = 1;
+    while (bits < R.l1 + R.l2 && (half << bits) < total) ++bits;
+    R.meta->radix_l2 = (uint32_t)max(0, bits - R.l1);
+  }
 }
 
 // Products in chunks of 8 rows per thread: each chunk is counting-sorted by
@@ -633,6 +643,7 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
   }
   __syncthreads();
   const uint32_t narrow = KIND == 0 ? R.meta->narrow : 0u;
+  const int l2 = (int)R.meta->radix_l2;
   const int64_t j = (int64_t)blockIdx.x * RADIX_BLOCK + tid;
   const int64_t i0 = (int64_t)blockIdx.y * R.rows;
   const int64_t i1 = min(i0 + R.rows, R.na);
@@ -666,7 +677,7 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
       const uint32_t p = part1(h, R.l1);
       const int64_t at = base[p] + done[p] + (t - coff[p]);
       R.ent1[at] = en;
-      R.bin1[at] = (uint16_t)part2(h, R.l1, R.l2);   // for the split's histogram
+      R.bin1[at] = (uint16_t)part2(h, R.l1, l2);   // for the split's histogram
     }
     __syncthreads();
     if (tid < P1) {
@@ -688,7 +699,8 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
   __shared__ uint32_t done[1 << RADIX_MAX_L];
   __shared__ uint32_t s_ws[SPLIT_BLOCK / 64 + 1];
   const int tid = threadIdx.x;
-  const int P2 = 1 << R.l2;
+  const int l2 = (int)R.meta->radix_l2;
+  const int P2 = 1 << l2;
   const int64_t p = blockIdx.x;
   const int64_t s = R.pstart[p], e = R.pstart[p + 1];
   if (tid < P2) {
@@ -732,7 +744,7 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
     for (int u = 0; u < U; ++u)
       if (c0 + (int64_t)u * SPLIT_BLOCK + tid < e) {
         const int64_t code = (int64_t)(((uint64_t)en[u].y << 32) | en[u].x);
-        bin[u] = part2(code_hash(code), R.l1, R.l2);
+        bin[u] = part2(code_hash(code), R.l1, l2);
         rank[u] = atomicAdd(&coff[bin[u]], 1u);
       }
     __syncthreads();
@@ -748,7 +760,7 @@ __global__ void __launch_bounds__(SPLIT_BLOCK) k_radix_split(RadixArgs R) {
     __syncthreads();
     for (uint32_t t = tid; t < total; t += SPLIT_BLOCK) {
       const uint4 x = stage[t];
-      const uint32_t b = part2(code_hash((int64_t)(((uint64_t)x.y << 32) | x.x)), R.l1, R.l2);
+      const uint32_t b = part2(code_hash((int64_t)(((uint64_t)x.y << 32) | x.x)), R.l1, l2);
       R.ent2[s + h2[b] + done[b] + (t - coff[b])] = x;
     }
     __syncthreads();
@@ -784,7 +796,11 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   T* vals = reinterpret_cast<T*>(vals_words);
   __shared__ int64_t s_wave[BIN_BLOCK / 64];
   __shared__ int64_t s_base;
+  // the grid covers the planned bins; the bins used are those of the level-2
+  // bits chosen for the products actually made
+  const int l2 = (int)R.meta->radix_l2;
   const int64_t b = blockIdx.x;
+  if (b >= ((int64_t)1 << (R.l1 + l2))) return;
   const int64_t s = R.bstart[b], e = R.bstart[b + 1];
   if (s == e) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -813,7 +829,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
       __builtin_memcpy(&v, &bits, 8);
     }
     const unsigned long long key = (unsigned long long)code + 1;
-    uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, R.l2);
+    uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, l2);
     int q = 0;
     for (; q < BIN_SLOTS; ++q) {
       unsigned long long c = keys[slot];

@@ -168,7 +168,7 @@ struct Meta {
   uint32_t seg_flags[2];  // dense: coefficient-range flags of factor A / B
   uint32_t seg_err[2];    // dense: error bits found while sorting factor A / B
   uint32_t plan_done;     // dense: planning workgroups finished
-  uint32_t pad32;
+  uint32_t radix_l2;      // grouped hash: level-2 bits for the products actually made
   int64_t task_rows;      // dense: cost of a task (work items plus window overheads)
   int64_t pad;
 };
@@ -377,7 +377,8 @@ struct RadixArgs {
   const int64_t* bk; const void* bc; int64_t nb;   // (Poisson: coefficients only)
   int64_t Wx; PoissonPrep P;                       // Poisson combined codes
   int rows;              // rows of A per count / scatter workgroup
-  int l1, l2;            // log2 of the level-1 partitions and level-2 bins per partition
+  int l1, l2;            // log2 of the level-1 partitions and (at most) level-2 bins per
+                         // partition; the bits used are chosen on the device (Meta::radix_l2)
   int64_t nblocks;       // count / scatter workgroups (set by the launcher)
   uint32_t* counts;      // [2^l1][nblocks] products per (partition, workgroup), then offsets
   int64_t* pstart;       // [2^l1 + 1] partition totals, then starts
