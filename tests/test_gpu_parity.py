@@ -668,6 +668,27 @@ def test_truncated_products_match_oracle(mode, part):
             assert_exact([ge], gc, [oe], oc, what)
 
 
+@pytest.mark.parametrize("part", [0, 2])
+def test_truncation_keeps_few_or_no_pairs(part):
+    """A degree limit below every pair's degree gives the empty product; one a
+    little above the smallest keeps a handful of pairs (the grouped layout
+    then chooses its fewest level-2 bins).  Against the oracle's filter."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=part)
+    a, b = I.config(3, scale=0.03)
+    da, db = a[0].sum(1).min(), b[0].sum(1).min()
+    for D, what in ((int(da + db) - 1, "no pair kept"), (int(da + db) + 25, "a few pairs kept")):
+        say("truncated sparse,", what, "partitioned", part)
+        with ctx.truncation([1] * 6, D):
+            ge, gc, _ = gpu_laurent(a, b, "hash", ctx)
+        oe, oc, _ = O.laurent_mul_truncated(a[0], a[1], b[0], b[1], [1] * 6, D, threads=4)
+        if what == "no pair kept":
+            assert len(oc) == 0 and len(gc) == 0
+        else:
+            assert 0 < len(oc) < 1000
+        assert_exact([ge], gc, [oe], oc, what)
+
+
 def test_truncation_codes_path_and_errors():
     torch = _torch()
     ctx = kp.context()
