@@ -130,7 +130,8 @@ typedef struct kp_tune {
   double hash_load;         /* hash: target load factor (0.05 .. 0.9)                */
   int64_t hash_capacity;    /* hash: forced slot count (0 = from the bound)          */
   int64_t dense_max_keys;   /* dense only if nkeys <= this (at most 2^27)            */
-  double dense_keys_per_pair; /* auto mode: dense only if nkeys <= this * na * nb    */
+  double dense_keys_per_pair; /* auto mode: dense only if nkeys <= this * na * nb
+                                 (default 8)                                          */
   int32_t hash_rows;        /* hash: factor-A rows per thread (global table)         */
   int32_t hash_partitioned; /* hash: 2 = products grouped by hash bits in two levels
                                through HBM, each group accumulated in an LDS table

@@ -649,7 +649,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.hash_load = 0.5;
   ctx->tune.hash_capacity = 0;
   ctx->tune.dense_max_keys = (int64_t)1 << 27;
-  ctx->tune.dense_keys_per_pair = 64.0;
+  ctx->tune.dense_keys_per_pair = 8.0;
   ctx->tune.hash_rows = 64;
   ctx->tune.hash_partitioned = 1;
   ctx->tune.hash_bucket = 0;

@@ -1,8 +1,9 @@
 """Autotuner for the knobs the paper leaves open (Sections 3.1, 3.2): the
-dense window size, workgroup size and tasks per compute unit, the hash
-table's load factor and rows per thread, and the density threshold of the
-dense/hash choice.  None of them changes a result; each is picked by timing
-the library's own multiplies on seeded products of the benchmark shapes.
+dense window size, workgroup size and tasks per compute unit, the global
+hash table's load factor and rows per thread, the size of the LDS tables of
+grouped products, and the density threshold of the dense/hash choice.  None
+of them changes a result; each is picked by timing the library's own
+multiplies on seeded products of the benchmark shapes.
 """
 from __future__ import annotations
 
@@ -19,6 +20,7 @@ DENSE_GRID = [dict(window=w, block=b, tasks_per_cu=t)
               for w, b, t in itertools.product((8192, 16384, 18432), (512, 1024), (1, 2))]
 HASH_GRID = [dict(hash_load=l, hash_rows=r)
              for l, r in itertools.product((0.35, 0.5, 0.7), (32, 64, 128))]
+BIN_GRID = [dict(hash_bin_slots=s) for s in (2048, 4096, 8192)]
 
 
 def _dev(x):
@@ -69,13 +71,15 @@ class _Product:
         return (time.perf_counter() - t) / reps
 
 
-def _search(ctx, prod, mode, grid, reps):
+def _search(ctx, prod, mode, grid, reps, fixed=None):
+    """Times every candidate (with `fixed` settings held while timing, not
+    part of the result) and returns the fastest and the table."""
     saved = ctx.tune
     base = {f: getattr(saved, f) for f, _ in type(saved)._fields_}
     table = []
     try:
         for cand in grid:
-            ctx.set_tune(**{**base, **cand})
+            ctx.set_tune(**{**base, **(fixed or {}), **cand})
             table.append((prod.seconds(mode, reps), cand))
     finally:
         ctx.set_tune(**base)
@@ -90,9 +94,20 @@ def tune_dense(ctx, scale=1.0, reps=5):
 
 
 def tune_hash(ctx, scale=0.2, reps=3):
-    """Load factor and rows per thread on the 6-variable sparse product."""
+    """Load factor and rows per thread of the global table (forced while
+    timing) on the 6-variable sparse product."""
     a, b = I.config(3, scale=scale)
-    return _search(ctx, _Product(ctx, a, b), "hash", HASH_GRID, reps)
+    return _search(ctx, _Product(ctx, a, b), "hash", HASH_GRID, reps,
+                   fixed=dict(hash_partitioned=0))
+
+
+def tune_bins(ctx, scale=0.5, reps=3):
+    """Slots of the grouped products' LDS tables (the grouped layout forced
+    while timing) on the 6-variable sparse product; the bins are sized from
+    the product count, so the product should be of the size it is tuned for."""
+    a, b = I.config(3, scale=scale)
+    return _search(ctx, _Product(ctx, a, b), "hash", BIN_GRID, reps,
+                   fixed=dict(hash_partitioned=2))
 
 
 def tune_threshold(ctx, n=2000, reps=3):
@@ -129,12 +144,14 @@ def autotune(ctx=None, apply=True, quick=True):
     ctx = ctx or context()
     dense, dt = tune_dense(ctx, scale=0.5 if quick else 1.0)
     hashed, ht = tune_hash(ctx, scale=0.1 if quick else 0.3)
+    bins, bt = tune_bins(ctx, scale=0.5 if quick else 1.0)
     thr, rows = tune_threshold(ctx, n=1000 if quick else 2000)
-    chosen = {**dense, **hashed, "dense_keys_per_pair": thr}
+    chosen = {**dense, **hashed, **bins, "dense_keys_per_pair": thr}
     if apply:
         ctx.set_tune(**chosen)
     return {"chosen": chosen,
             "dense_ms": [(round(t * 1e3, 4), c) for t, c in dt],
             "hash_ms": [(round(t * 1e3, 4), c) for t, c in ht],
+            "bins_ms": [(round(t * 1e3, 4), c) for t, c in bt],
             "threshold_rows": [(round(r, 3), round(a * 1e3, 4), round(b * 1e3, 4))
                                for r, a, b in rows]}

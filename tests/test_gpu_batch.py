@@ -168,6 +168,11 @@ def test_autotuner_keeps_results():
     assert len(table) == len(tune.DENSE_GRID) and best in tune.DENSE_GRID
     thr, rows = tune.tune_threshold(ctx, n=400, reps=1)
     assert thr >= 0 and rows
+    bins, btable = tune.tune_bins(ctx, scale=0.05, reps=1)
+    assert len(btable) == len(tune.BIN_GRID) and bins in tune.BIN_GRID
+    hashed, htable = tune.tune_hash(ctx, scale=0.03, reps=1)
+    assert hashed in tune.HASH_GRID and "hash_partitioned" not in hashed
+    assert ctx.tune.hash_partitioned == 1   # the knob held while timing is restored
     ctx.set_tune(**best)
     after, _ = kp.mul_laurent(pa, pb, ctx=ctx)
     assert np.array_equal(before.exps.cpu().numpy(), after.exps.cpu().numpy())
