@@ -25,7 +25,6 @@ struct kp_ctx {
   bool hash_stats = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // pool
   size_t events_used = 0;
-  int32_t* box_dev = nullptr;         // device: box accumulator and its counter
   kp::Mailbox* mb = nullptr;          // pinned host-coherent mailbox (host address)
   kp::Mailbox* mb_dev = nullptr;      // the same, device address
   uint64_t seq = 0;                   // last sequence number handed to a kernel
@@ -100,21 +99,8 @@ unsigned long long* hash_stats_ptr(kp_ctx* ctx) {
   return ctx->hash_stats ? &ctx->status->inserts : nullptr;
 }
 
-// Layout of kp_ctx::box_dev (int32 words): accumulator of four arrays
-// (mins, then maxes), then the completion counter.
+// Words of one array's box as returned by read_boxes: mins, then maxes.
 constexpr int BOX_SET = 2 * KP_MAX_VARS;
-constexpr int BOX_ACC = 0, BOX_DONE = 4 * BOX_SET;
-constexpr int BOX_WORDS = BOX_DONE + 64;
-
-hipError_t box_init(int32_t* dev) {
-  std::vector<int32_t> h(BOX_WORDS, 0);
-  for (int g = 0; g < 4; ++g)
-    for (int v = 0; v < KP_MAX_VARS; ++v) {
-      h[BOX_ACC + g * BOX_SET + v] = INT_MAX;
-      h[BOX_ACC + g * BOX_SET + KP_MAX_VARS + v] = INT_MIN;
-    }
-  return hipMemcpy(dev, h.data(), sizeof(int32_t) * BOX_WORDS, hipMemcpyHostToDevice);
-}
 
 // Spins until the kernel side writes `want` to a mailbox sequence slot.
 // Every few hundred polls the stream is queried, so that a stream that
@@ -128,6 +114,23 @@ kp_status wait_seq(kp_ctx* ctx, const uint64_t* slot, uint64_t want, hipStream_t
       const hipError_t q = hipStreamQuery(s);
       if (q == hipSuccess) {
         if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == want) return KP_OK;
+        return fail(ctx, KP_E_DEVICE, "%s: the stream finished without signalling", what);
+      }
+      if (q != hipErrorNotReady) return hip_fail(ctx, q, what);
+    }
+  }
+}
+
+// As wait_seq, for a mailbox word whose high half must equal `tag`.
+kp_status wait_tag(kp_ctx* ctx, const uint64_t* slot, uint64_t tag, hipStream_t s,
+                   const char* what) {
+  for (uint64_t spins = 1;; ++spins) {
+    if ((__atomic_load_n(slot, __ATOMIC_ACQUIRE) >> 32) == tag) return KP_OK;
+    __builtin_ia32_pause();
+    if ((spins & 255) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        if ((__atomic_load_n(slot, __ATOMIC_ACQUIRE) >> 32) == tag) return KP_OK;
         return fail(ctx, KP_E_DEVICE, "%s: the stream finished without signalling", what);
       }
       if (q != hipErrorNotReady) return hip_fail(ctx, q, what);
@@ -183,17 +186,35 @@ kp_status read_boxes(kp_ctx* ctx, int nseg, const int32_t* const* vals, const in
     A.n[g] = n[g];
     A.nv[g] = nv[g];
   }
-  A.acc = ctx->box_dev + BOX_ACC;
-  A.done = reinterpret_cast<unsigned*>(ctx->box_dev + BOX_DONE);
   A.mb = ctx->mb_dev;
   A.seq = ++ctx->seq;
   hipError_t e = launch_boxes(A, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "factor boxes");
+  // every partial word of this call carries the sequence number's low half
+  const uint64_t tag = (uint64_t)(uint32_t)A.seq;
+  const int parts = box_parts(A);
   for (int g = 0; g < nseg; ++g) {
-    kp_status st = wait_seq(ctx, &ctx->mb->box_seq[g], A.seq, s, "factor boxes");
-    if (st != KP_OK) return st;
+    int32_t* r = res + g * BOX_SET;
+    for (int v = 0; v < KP_MAX_VARS; ++v) {
+      r[v] = INT_MAX;
+      r[KP_MAX_VARS + v] = INT_MIN;
+    }
+    for (int k = 0; k < parts; ++k)
+      for (int v = 0; v < nv[g]; ++v)
+        for (int side = 0; side < 2; ++side) {
+          const uint64_t* slot = &ctx->mb->box_part[g][k][side * KP_MAX_VARS + v];
+          kp_status st = wait_tag(ctx, slot, tag, s, "factor boxes");
+          if (st != KP_OK) return st;
+          const int32_t x = (int32_t)(uint32_t)__atomic_load_n(slot, __ATOMIC_ACQUIRE);
+          int32_t& out = r[side * KP_MAX_VARS + v];
+          out = side ? std::max(out, x) : std::min(out, x);
+        }
+    if (n[g] == 0)   // an empty array: min 0, max -1
+      for (int v = 0; v < KP_MAX_VARS; ++v) {
+        r[v] = 0;
+        r[KP_MAX_VARS + v] = -1;
+      }
   }
-  std::memcpy(res, ctx->mb->box, sizeof(int32_t) * nseg * BOX_SET);
   return KP_OK;
 }
 
@@ -672,9 +693,6 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(CtxStatus));
   if (e == hipSuccess) e = dense_setup();
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void**>(&ctx->box_dev), sizeof(int32_t) * BOX_WORDS);
-  if (e == hipSuccess) e = box_init(ctx->box_dev);
-  if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&ctx->mb), sizeof(Mailbox),
                       hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess) {
@@ -783,7 +801,6 @@ kp_status kp_ctx_destroy(kp_ctx* ctx) {
     (void)hipEventDestroy(pr.second);
   }
   if (ctx->status) (void)hipFree(ctx->status);
-  if (ctx->box_dev) (void)hipFree(ctx->box_dev);
   if (ctx->mb) (void)hipHostFree(ctx->mb);
   delete ctx;
   return KP_OK;

@@ -74,15 +74,18 @@ k_minmax(int64_t n, int32_t nv, const int32_t* __restrict__ vals, int32_t* out) 
   }
 }
 
-// Boxes of several exponent arrays in one launch (blockIdx.y = array).
-// Blocks fold into a persistent accumulator with atomics; the last block to
-// finish (counted on `done`) moves the result to the host mailbox, restores
-// the accumulator and the counter (so the next launch starts clean) and
-// then publishes the sequence number.  An empty array reports min 0 and
-// max -1 per variable.
-// One workgroup per array (arrays of up to BOX_ONE_ROWS rows): no
-// cross-block atomics; each workgroup publishes its own array's box and
-// sequence slot.
+// Boxes of several exponent arrays in one launch.  Every workgroup posts its
+// partial box (per variable min and max over its share of the words) to the
+// host mailbox, each word tagged with the low 32 bits of the call's sequence
+// number; the host waits for all the tagged words and combines them.  No
+// device atomics, no last-workgroup step, no fence: each post is one 64-bit
+// store.  One workgroup per array handles arrays of up to BOX_ONE_ROWS rows;
+// longer arrays take up to BOX_PARTS workgroups each (blockIdx.y = array).
+__device__ __forceinline__ void post_box(const BoxArgs& A, int g, int part, int r, int32_t v) {
+  const uint64_t w = ((uint64_t)(uint32_t)A.seq << 32) | (uint32_t)v;
+  __hip_atomic_store(&A.mb->box_part[g][part][r], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 constexpr int BOX_BLOCK = 1024;
 constexpr int64_t BOX_ONE_ROWS = 2048;
 
@@ -145,22 +148,17 @@ __global__ void __launch_bounds__(BOX_BLOCK) k_boxes_one(BoxArgs A) {
   if (threadIdx.x < 2 * KP_MAX_VARS) {
     const int v = threadIdx.x % KP_MAX_VARS;
     const bool is_max = threadIdx.x >= KP_MAX_VARS;
-    int32_t r = is_max ? INT_MIN : INT_MAX;
-    if (v < nv)
+    if (v < nv) {
+      int32_t r = is_max ? INT_MIN : INT_MAX;
       for (int w = 0; w < BOX_BLOCK / 64; ++w) r = is_max ? max(r, smax[v][w]) : min(r, smin[v][w]);
-    A.mb->box[g * 2 * KP_MAX_VARS + threadIdx.x] = n == 0 ? (is_max ? -1 : 0) : r;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence_system();
-    __hip_atomic_store(&A.mb->box_seq[g], A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      post_box(A, g, 0, threadIdx.x, r);
+    }
   }
 }
 
 __global__ void __launch_bounds__(CODEC_BLOCK) k_boxes(BoxArgs A) {
   __shared__ int32_t smin[KP_MAX_VARS][CODEC_BLOCK / 64];
   __shared__ int32_t smax[KP_MAX_VARS][CODEC_BLOCK / 64];
-  __shared__ int s_last;
   const int g = blockIdx.y;
   const int64_t n = A.n[g];
   const int32_t nv = A.nv[g];
@@ -216,37 +214,14 @@ __global__ void __launch_bounds__(CODEC_BLOCK) k_boxes(BoxArgs A) {
     }
   }
   __syncthreads();
-  int32_t* acc = A.acc + g * 2 * KP_MAX_VARS;
-  if (threadIdx.x < nv) {
-    const int v = threadIdx.x;
-    int32_t a = INT_MAX, b = INT_MIN;
-    for (int w = 0; w < CODEC_BLOCK / 64; ++w) {
-      a = min(a, smin[v][w]);
-      b = max(b, smax[v][w]);
+  if (threadIdx.x < 2 * KP_MAX_VARS) {
+    const int v = threadIdx.x % KP_MAX_VARS;
+    const bool is_max = threadIdx.x >= KP_MAX_VARS;
+    if (v < nv) {
+      int32_t r = is_max ? INT_MIN : INT_MAX;
+      for (int w = 0; w < CODEC_BLOCK / 64; ++w) r = is_max ? max(r, smax[v][w]) : min(r, smin[v][w]);
+      post_box(A, g, blockIdx.x, threadIdx.x, r);
     }
-    if (a != INT_MAX) atomicMin(&acc[v], a);
-    if (b != INT_MIN) atomicMax(&acc[KP_MAX_VARS + v], b);
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0)
-    s_last = atomicAdd(A.done, 1u) == gridDim.x * gridDim.y - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int total = A.nseg * 2 * KP_MAX_VARS;
-  for (int k = threadIdx.x; k < total; k += blockDim.x) {
-    const int seg = k / (2 * KP_MAX_VARS), r = k % (2 * KP_MAX_VARS);
-    const bool is_max = r >= KP_MAX_VARS;
-    const int32_t val = atomicExch(&A.acc[k], is_max ? INT_MIN : INT_MAX);
-    A.mb->box[k] = A.n[seg] == 0 ? (is_max ? -1 : 0) : val;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicExch(A.done, 0u);
-    __threadfence_system();
-    for (int k = 0; k < A.nseg; ++k)
-      __hip_atomic_store(&A.mb->box_seq[k], A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -474,18 +449,23 @@ hipError_t launch_degrees(const DevLayout& LA, const DevLayout& LB, const TruncS
   return hipGetLastError();
 }
 
-hipError_t launch_boxes(const BoxArgs& A, hipStream_t s) {
+int box_parts(const BoxArgs& A) {
   int64_t n = 0, words = 0;
   for (int g = 0; g < A.nseg; ++g) {
     n = std::max(n, A.n[g]);
     words = std::max(words, A.n[g] * (int64_t)A.nv[g]);
   }
-  if (n <= BOX_ONE_ROWS) {
+  if (n <= BOX_ONE_ROWS) return 1;
+  return grid_for(words, CODEC_BLOCK * 8, BOX_PARTS);   // one round of 8 words per thread
+}
+
+hipError_t launch_boxes(const BoxArgs& A, hipStream_t s) {
+  int64_t n = 0;
+  for (int g = 0; g < A.nseg; ++g) n = std::max(n, A.n[g]);
+  if (n <= BOX_ONE_ROWS)
     hipLaunchKernelGGL(k_boxes_one, dim3(A.nseg), dim3(BOX_BLOCK), 0, s, A);
-  } else {
-    const int gx = grid_for(words, CODEC_BLOCK * 8, 512);   // one round of 8 words per thread
-    hipLaunchKernelGGL(k_boxes, dim3(gx, A.nseg), dim3(CODEC_BLOCK), 0, s, A);
-  }
+  else
+    hipLaunchKernelGGL(k_boxes, dim3(box_parts(A), A.nseg), dim3(CODEC_BLOCK), 0, s, A);
   return hipGetLastError();
 }
 

@@ -194,13 +194,18 @@ hipError_t launch_minmax(int64_t n, int32_t nv, const int32_t* vals, int32_t* ou
 // hold INT_MAX / INT_MIN and 0 before the first one.
 // Host-coherent pinned block through which kernels hand small results to a
 // host thread that spins on a sequence number (no stream synchronisation).
+// Factor boxes come back as partial boxes, one per workgroup of the box
+// kernel (at most BOX_PARTS per array); every word carries the low 32 bits
+// of the call's sequence number above the value, so the host knows when
+// all have arrived without a fence or a cross-workgroup step on the device.
+constexpr int BOX_PARTS = 64;
 struct Mailbox {
-  int32_t box[4 * 2 * KP_MAX_VARS];   // factor boxes: per array mins, then maxes
+  // per array and box workgroup: KP_MAX_VARS mins, then maxes, tagged
+  uint64_t box_part[4][BOX_PARTS][2 * KP_MAX_VARS];
   int64_t n;                          // a multiply's result count (or -status)
   uint32_t err;                       // the context's latched status bits
   uint32_t pad;
   uint64_t n_seq;                     // written after n and err
-  uint64_t box_seq[4];                // per array, written after its box
 };
 
 struct BoxArgs {
@@ -208,11 +213,11 @@ struct BoxArgs {
   int64_t n[4];
   int32_t nv[4];
   int nseg;
-  int32_t* acc;
-  unsigned* done;
   Mailbox* mb;     // device address of the mailbox
   uint64_t seq;
 };
+// Workgroups (partial boxes) per array of the box kernel for these arrays.
+int box_parts(const BoxArgs& A);
 hipError_t launch_boxes(const BoxArgs& A, hipStream_t s);
 // Posts *out_n and *ctx_err to the mailbox, then seq to n_seq.
 hipError_t launch_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
