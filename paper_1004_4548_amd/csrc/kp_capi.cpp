@@ -102,26 +102,10 @@ unsigned long long* hash_stats_ptr(kp_ctx* ctx) {
 // Words of one array's box as returned by read_boxes: mins, then maxes.
 constexpr int BOX_SET = 2 * KP_MAX_VARS;
 
-// Spins until the kernel side writes `want` to a mailbox sequence slot.
+// Spins until a mailbox word's high half equals `tag` (the low half of the
+// call's sequence number, which the kernel side writes above the payload).
 // Every few hundred polls the stream is queried, so that a stream that
 // failed, or finished without signalling, ends the wait with an error.
-kp_status wait_seq(kp_ctx* ctx, const uint64_t* slot, uint64_t want, hipStream_t s,
-                   const char* what) {
-  for (uint64_t spins = 1;; ++spins) {
-    if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == want) return KP_OK;
-    __builtin_ia32_pause();
-    if ((spins & 255) == 0) {
-      const hipError_t q = hipStreamQuery(s);
-      if (q == hipSuccess) {
-        if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == want) return KP_OK;
-        return fail(ctx, KP_E_DEVICE, "%s: the stream finished without signalling", what);
-      }
-      if (q != hipErrorNotReady) return hip_fail(ctx, q, what);
-    }
-  }
-}
-
-// As wait_seq, for a mailbox word whose high half must equal `tag`.
 kp_status wait_tag(kp_ctx* ctx, const uint64_t* slot, uint64_t tag, hipStream_t s,
                    const char* what) {
   for (uint64_t spins = 1;; ++spins) {
@@ -160,10 +144,15 @@ kp_status wait_count(kp_ctx* ctx, const int64_t* out_n, int64_t* n_host, hipStre
       e = launch_post_count(out_n, &ctx->status->err, ctx->mb_dev, seq, s);
       if (e != hipSuccess) return hip_fail(ctx, e, what);
     }
-    kp_status st = wait_seq(ctx, &ctx->mb->n_seq, seq, s, what);
-    if (st != KP_OK) return st;
-    n = ctx->mb->n;
-    err = ctx->mb->err;
+    const uint64_t tag = (uint64_t)(uint32_t)seq;
+    uint64_t w[3];
+    for (int k = 0; k < 3; ++k) {
+      kp_status st = wait_tag(ctx, &ctx->mb->n_tag[k], tag, s, what);
+      if (st != KP_OK) return st;
+      w[k] = __atomic_load_n(&ctx->mb->n_tag[k], __ATOMIC_ACQUIRE) & 0xffffffffu;
+    }
+    n = (int64_t)(w[0] | (w[1] << 32));
+    err = (uint32_t)w[2];
   }
   if (n < 0 || err) {
     kp_status st = sync_status(ctx, s);

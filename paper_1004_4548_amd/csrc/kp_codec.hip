@@ -228,10 +228,7 @@ __global__ void __launch_bounds__(CODEC_BLOCK) k_boxes(BoxArgs A) {
 __global__ void k_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
                              uint64_t seq) {
   if (threadIdx.x != 0) return;
-  mb->n = *out_n;
-  mb->err = *ctx_err;
-  __threadfence_system();
-  __hip_atomic_store(&mb->n_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  post_count(mb, seq, *out_n, *ctx_err);
 }
 
 __device__ __forceinline__ uint32_t encode_row(const DevLayout& L, int64_t r,

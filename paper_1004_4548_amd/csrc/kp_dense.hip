@@ -1267,12 +1267,8 @@ __global__ void __launch_bounds__(1024) k_dense_scan(ScanArgs A) {
     const int64_t n = e ? -(int64_t)first_error(e) : total;
     if (e) atomicOr(A.ctx_err, e);
     *A.out_n = n;
-    if (A.mb) {   // the waiting host needs only the count; the copy follows in stream order
-      A.mb->n = n;
-      A.mb->err = e;
-      __threadfence_system();
-      __hip_atomic_store(&A.mb->n_seq, A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    // the waiting host needs only the count; the copy follows in stream order
+    if (A.mb) post_count(A.mb, A.seq, n, e);
   }
 }
 
@@ -1331,12 +1327,7 @@ __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
       const int64_t n = e ? -(int64_t)first_error(e) : total;
       if (e) atomicOr(C.ctx_err, e);
       *C.out_n_w = n;
-      if (C.mb) {   // the waiting host needs only the count
-        C.mb->n = n;
-        C.mb->err = e;
-        __threadfence_system();
-        __hip_atomic_store(&C.mb->n_seq, C.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+      if (C.mb) post_count(C.mb, C.seq, n, e);   // the waiting host needs only the count
     }
     if (e) return;
   } else {

@@ -202,11 +202,23 @@ constexpr int BOX_PARTS = 64;
 struct Mailbox {
   // per array and box workgroup: KP_MAX_VARS mins, then maxes, tagged
   uint64_t box_part[4][BOX_PARTS][2 * KP_MAX_VARS];
-  int64_t n;                          // a multiply's result count (or -status)
-  uint32_t err;                       // the context's latched status bits
-  uint32_t pad;
-  uint64_t n_seq;                     // written after n and err
+  // a multiply's result count (or -status), low and high halves, and the
+  // context's latched status bits, tagged the same way
+  uint64_t n_tag[3];
 };
+
+#if defined(__HIPCC__)
+// Posts a result count and status bits to the mailbox: three tagged words,
+// one store each, no fence (the host takes them once all carry the tag).
+__device__ __forceinline__ void post_count(Mailbox* mb, uint64_t seq, int64_t n, uint32_t err) {
+  const uint64_t tag = (uint64_t)(uint32_t)seq << 32;
+  const uint64_t u = (uint64_t)n;
+  __hip_atomic_store(&mb->n_tag[0], tag | (u & 0xffffffffu), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&mb->n_tag[1], tag | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&mb->n_tag[2], tag | err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+#endif
 
 struct BoxArgs {
   const int32_t* vals[4];
@@ -219,7 +231,7 @@ struct BoxArgs {
 // Workgroups (partial boxes) per array of the box kernel for these arrays.
 int box_parts(const BoxArgs& A);
 hipError_t launch_boxes(const BoxArgs& A, hipStream_t s);
-// Posts *out_n and *ctx_err to the mailbox, then seq to n_seq.
+// Posts *out_n and *ctx_err to the mailbox as tagged words (post_count).
 hipError_t launch_post_count(const int64_t* out_n, const uint32_t* ctx_err, Mailbox* mb,
                              uint64_t seq, hipStream_t s);
 hipError_t launch_encode2(const DevLayout& LA, const DevLayout& LB, int64_t na, int64_t nb,
@@ -310,7 +322,7 @@ struct DenseBufs {
   uint32_t* ctx_err;
   hipEvent_t ev0, ev1;   // optional: recorded around the window kernel
   // optional: the output scan also posts the count (or -status) and the
-  // status bits to this mailbox, then seq to its n_seq
+  // status bits to this mailbox, tagged with seq (post_count)
   struct Mailbox* mb;
   uint64_t seq;
   // optional: the output copy writes decoded exponents (int32[n][dec.nx])
