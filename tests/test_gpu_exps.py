@@ -146,7 +146,9 @@ def test_two_call_exponent_outside_the_layout_is_a_range_error():
         assert_exact([r.exps.cpu().numpy()], r.coef.cpu().numpy(), [oe], oc_, f"after, {mode}")
 
 
-def test_box_accumulator_restores_between_launches():
+def test_boxes_fresh_on_every_launch():
+    """Successive plans of random shapes: each sees only its own partial
+    boxes (words left by an earlier, larger launch carry an older tag)."""
     ctx = kp.context()
     rng = np.random.default_rng(10044548)
     for r in range(6):
@@ -214,3 +216,33 @@ def test_two_call_poisson_without_x_variables():
     assert not ox.any()
     gk = [r.y.cpu().numpy(), r.is_sin.cpu().numpy()[:, None]]
     assert_tolerance(gk, r.coef.cpu().numpy(), [oy, ot[:, None]], oc, oab, TOL, "poisson nx=0")
+
+
+def test_factor_boxes_from_partial_posts():
+    """The box kernel posts one partial box per workgroup (tagged mailbox
+    words the host combines): factors of very different lengths in one
+    launch, factors longer than one round of every workgroup, mixed signs,
+    and an empty factor, against numpy's min and max."""
+    import torch
+    rng = np.random.default_rng(2026)
+    ctx = kp.context()
+    for na, nb, nv in ((40000, 5, 4), (3000, 2500, 6), (70000, 70000, 2), (2049, 1, 3)):
+        amp = int(2 ** (58 / nv)) // 8   # product widths below 2^58 in total: codes fit
+        ea = rng.integers(-amp // 2, amp // 2, (na, nv)).astype(np.int32)
+        eb = rng.integers(-amp // 8, amp // 2, (nb, nv)).astype(np.int32)
+        ea[rng.integers(0, na), 0] = -amp        # extremes in one row, anywhere
+        eb[rng.integers(0, nb), nv - 1] = amp
+        pa = kp.Poly(dev(ea), dev(np.ones(na, np.int64)))
+        pb = kp.Poly(dev(eb), dev(np.ones(nb, np.int64)))
+        say("plan boxes", na, "x", nb, "vars", nv)
+        lay = kp.plan_laurent(pa, pb, "hash", ctx)[0]
+        assert list(lay.amin[:nv]) == ea.min(0).tolist() and list(lay.amax[:nv]) == ea.max(0).tolist()
+        assert list(lay.bmin[:nv]) == eb.min(0).tolist() and list(lay.bmax[:nv]) == eb.max(0).tolist()
+    # a long factor and an empty one in the same launch: the empty product
+    a = kp.Poly(dev(rng.integers(-9, 9, (5000, 3)).astype(np.int32)), dev(np.ones(5000, np.int64)))
+    e = kp.Poly(torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
+                torch.zeros(0, dtype=torch.int64, device="cuda"))
+    for x, y in ((a, e), (e, a)):
+        say("long factor times an empty one")
+        r, _ = kp.mul_laurent(x, y, ctx=ctx)
+        assert r.coef.shape[0] == 0
