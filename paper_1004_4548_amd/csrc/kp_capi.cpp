@@ -122,9 +122,16 @@ kp_status wait_tag(kp_ctx* ctx, const uint64_t* slot, uint64_t tag, hipStream_t 
   }
 }
 
+// The next sequence number (the caller holds mb_mu).  Its low half tags the
+// mailbox words and is never 0, the value of a word no kernel has written.
+uint64_t bump_seq(kp_ctx* ctx) {
+  if ((uint32_t)++ctx->seq == 0) ++ctx->seq;
+  return ctx->seq;
+}
+
 uint64_t next_seq(kp_ctx* ctx) {
   std::lock_guard<std::mutex> guard(ctx->mb_mu);
-  return ++ctx->seq;
+  return bump_seq(ctx);
 }
 
 // Blocking end of a from-exponents multiply: the count and the latched
@@ -176,7 +183,7 @@ kp_status read_boxes(kp_ctx* ctx, int nseg, const int32_t* const* vals, const in
     A.nv[g] = nv[g];
   }
   A.mb = ctx->mb_dev;
-  A.seq = ++ctx->seq;
+  A.seq = bump_seq(ctx);
   hipError_t e = launch_boxes(A, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "factor boxes");
   // every partial word of this call carries the sequence number's low half
