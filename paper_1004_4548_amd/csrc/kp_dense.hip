@@ -1320,16 +1320,22 @@ __global__ void __launch_bounds__(256) k_dense_copy(CopyArgs C) {
     __syncthreads();
     off = s_wave[0][0] + s_wave[0][1] + s_wave[0][2] + s_wave[0][3];
     const int64_t total = s_wave[1][0] + s_wave[1][1] + s_wave[1][2] + s_wave[1][3];
-    // the scan kernel's checks, taken by every workgroup on the same inputs
-    uint32_t e = C.meta->err | C.meta->seg_err[0] | C.meta->seg_err[1] | *C.ctx_err;
-    if (total > C.out_cap) e |= ERR_CAPACITY;
+    // The product's own checks, taken by every workgroup on the same inputs
+    // (written by earlier kernels of this stream), decide whether anything
+    // is copied.  The context's latched status may change while the copy
+    // runs (another stream on the same context), so only workgroup 0 reads
+    // it, for the count it posts: a product is then either reported failed
+    // or complete, never short.
+    uint32_t own = C.meta->err | C.meta->seg_err[0] | C.meta->seg_err[1];
+    if (total > C.out_cap) own |= ERR_CAPACITY;
     if (c == 0 && threadIdx.x == 0) {
+      const uint32_t e = own | *C.ctx_err;
       const int64_t n = e ? -(int64_t)first_error(e) : total;
-      if (e) atomicOr(C.ctx_err, e);
+      if (own) atomicOr(C.ctx_err, own);
       *C.out_n_w = n;
       if (C.mb) post_count(C.mb, C.seq, n, e);   // the waiting host needs only the count
     }
-    if (e) return;
+    if (own) return;
   } else {
     if (*C.out_n < 0) return;
     off = C.coff[c];

@@ -246,3 +246,43 @@ def test_factor_boxes_from_partial_posts():
         say("long factor times an empty one")
         r, _ = kp.mul_laurent(x, y, ctx=ctx)
         assert r.coef.shape[0] == 0
+
+
+@pytest.mark.parametrize("path", ["codes", "exps"])
+def test_latched_error_fails_the_next_dense_product_or_leaves_it_complete(path):
+    """An asynchronous call latches an error on the context (an exponent
+    outside the box in kp_encode); a dense product queued after it on the same
+    stream (up to 4096 output chunks, where the copy kernel also scans) must
+    report that status, and a product after the status is cleared must come
+    back complete: a product is never reported whole while short."""
+    import torch
+    ctx = kp.context()
+    a, b = I.config(2, scale=0.1)
+    pa, pb = kp.Poly(dev(a[0]), dev(a[1])), kp.Poly(dev(b[0]), dev(b[1]))
+    lay = kp.laurent_layout(pa, pb, ctx)
+    ka, _ = kp.encode(lay, 0, pa.exps, ctx=ctx)
+    kb, _ = kp.encode(lay, 1, pb.exps, ctx=ctx)
+    oe, oc, _ = O.laurent_mul(a[0], a[1], b[0], b[1])
+    bad = pa.exps.clone()
+    bad[0, 0] = lay.amax[0] + 1
+    say("latched error then dense product,", path)
+    kp.encode(lay, 0, bad, ctx=ctx, flags=kp.KP_FLAG_ASYNC)   # latches KP_E_RANGE
+    if path == "codes":
+        codes, coef, on = kp.mul_laurent_codes(lay, ka, pa.coef, kb, pb.coef, "dense", ctx=ctx,
+                                               flags=kp.KP_FLAG_ASYNC)
+        n = int(on.item())
+        if n >= 0:   # complete, never short
+            ex = kp.decode(lay, codes[:n].contiguous(), ctx=ctx).cpu().numpy()
+            assert_exact([ex], coef[:n].cpu().numpy(), [oe], oc, "after a latched error")
+        else:
+            assert -n == kp.KP_E_RANGE
+        with pytest.raises(kp.KPError) as e:   # read and cleared here
+            ctx.sync_check()
+        assert e.value.status == kp.KP_E_RANGE
+    else:
+        with pytest.raises(kp.KPError) as e:   # read and cleared by the call
+            kp.mul_laurent(pa, pb, mode="dense", ctx=ctx)
+        assert e.value.status == kp.KP_E_RANGE
+    ctx.sync_check()   # nothing left latched
+    r, _ = kp.mul_laurent(pa, pb, mode="dense", ctx=ctx)
+    assert_exact([r.exps.cpu().numpy()], r.coef.cpu().numpy(), [oe], oc, "after clearing")
