@@ -12,7 +12,8 @@ import pytest
 import oracle as O
 import paper_1004_4548_amd as kp
 from paper_1004_4548_amd import inputs as I
-from tests.helpers import assert_exact, assert_tolerance
+from tests.helpers import (P61, assert_exact, assert_tolerance, eval_mod2_64_device,
+                           eval_modp_device, parallel_chunks)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-13
@@ -477,75 +478,138 @@ def test_full_moderately_sparse_10000():
     assert len(gc) > 130000
 
 
-def test_full_highly_sparse_sampled():
-    """The 6-variable sparse product at full size (9e8 pairs), hash mode: keys
-    unique and in the box, every coefficient sum over sign patterns of the
-    variables equal to the product of the factors' (mod 2^64), and sampled
-    terms equal to the oracle's one-by-one coefficients."""
+def _key6(ex, base=161):
+    """One int64 per exponent row (entries in [0, base))."""
+    k = ex[:, 0].to(_torch().int64) if hasattr(ex, "to") else ex[:, 0].astype(np.int64)
+    for v in range(1, ex.shape[1]):
+        col = ex[:, v].to(_torch().int64) if hasattr(ex, "to") else ex[:, v].astype(np.int64)
+        k = k * base + col
+    return k
+
+
+def test_full_highly_sparse_all_terms():
+    """The 6-variable sparse product at full size (9e8 pairs), hash mode, as a
+    whole product from exponents.  Every term is checked: keys unique and in
+    the product box, coefficients nonzero, and the value of the whole result
+    at 3 random points modulo 2^61-1 and 2 random odd points modulo 2^64
+    equals A(r) B(r) (Schwartz-Zippel: a misplaced, missing or wrong term
+    changes the value except with probability about 1e-16 per point).  Then
+    10^4 sampled terms equal the oracle's one-by-one coefficients, and 10^4
+    exponent tuples absent from the result (half uniform in the box, half
+    next to result terms) have oracle coefficient 0."""
     torch = _torch()
     a, b = I.config(3)
-    say("6 vars [0,80], 30000 x 30000 (full)")
+    say("6 vars [0,80], 30000 x 30000 (full, every term)")
     pa = kp.Poly(dev(a[0]), dev(a[1]))
     pb = kp.Poly(dev(b[0]), dev(b[1]))
-    lay = kp.laurent_layout(pa, pb)
-    ka, _ = kp.encode(lay, 0, pa.exps)
-    kb, _ = kp.encode(lay, 1, pb.exps)
-    codes, coef, _ = kp.mul_laurent_codes(lay, ka, pa.coef, kb, pb.coef, "hash")
-    n = codes.shape[0]
+    r, lay = kp.mul_laurent(pa, pb)
+    ex, co = r.exps, r.coef
+    n = co.shape[0]
     assert 8.9e8 < n <= 9e8
-    assert int(torch.unique(codes).shape[0]) == n
-    assert int(codes.min()) >= 0 and int(codes.max()) < lay.nkeys
-    assert bool((coef != 0).all())
-    # sign patterns: sum_t c_t prod_k s_k^e_tk = A(s) B(s)  (mod 2^64), s in {+1,-1}^6
-    par = torch.zeros(n, dtype=torch.int64, device="cuda")
-    q = codes.clone()
-    for v in range(6):
-        w = int(lay.xw[v])
-        e = q % w
-        q = q // w
-        par |= ((e + int(lay.xmin[v])) & 1) << v
-        del e
-    sums = torch.zeros(64, dtype=torch.int64, device="cuda")
-    sums.index_add_(0, par, coef)
-    sums = [int(s) for s in sums.cpu().tolist()]
-    M = 2**64
-    ea, ca, eb, cb = a[0], a[1], b[0], b[1]
-    for s in range(64):
-        sign = np.array([-1 if (s >> v) & 1 else 1 for v in range(6)])
-        pa_ = (ea & 1) @ ((sign < 0).astype(np.int64))
-        pb_ = (eb & 1) @ ((sign < 0).astype(np.int64))
-        va = int(np.where(pa_ % 2 == 1, -ca, ca).sum())
-        vb = int(np.where(pb_ % 2 == 1, -cb, cb).sum())
-        got = sum(sums[m] * (-1 if bin(m & s).count("1") % 2 else 1) for m in range(64))
-        assert got % M == (va * vb) % M, f"sign pattern {s}"
-    # sampled terms against the oracle's one-by-one coefficients
-    rng = np.random.default_rng(77)
-    idx = torch.from_numpy(rng.integers(0, n, 150)).cuda()
-    qe = kp.decode(lay, codes[idx].contiguous()).cpu().numpy()
-    want, _, _ = O.laurent_coeff_at(a[0], a[1], b[0], b[1], qe)
-    np.testing.assert_array_equal(coef[idx].cpu().numpy(), want)
-    # a few codes absent from the result have oracle coefficient 0
-    cand = torch.from_numpy(rng.integers(0, lay.nkeys, 4000)).cuda()
-    absent = cand[~torch.isin(cand, codes)][:20].contiguous()
-    qe = kp.decode(lay, absent).cpu().numpy()
-    want, _, _ = O.laurent_coeff_at(a[0], a[1], b[0], b[1], qe)
-    assert (want == 0).all()
+    assert int(ex.min()) >= 0 and int(ex.max()) <= 160
+    assert bool((co != 0).all())
+    key = _key6(ex)
+    assert int(torch.unique(key).shape[0]) == n
+    rng = np.random.default_rng(2010)
+    for _ in range(3):
+        pt = [int(x) for x in rng.integers(2, P61, 6)]
+        want = O.laurent_eval_modp(a[0], a[1], pt) * O.laurent_eval_modp(b[0], b[1], pt) % P61
+        assert eval_modp_device(ex, co, pt) == want
+    for _ in range(2):
+        pt = [int(x) | 1 for x in rng.integers(3, 2**62, 6)]
+        want = _eval_mod2_64(a[0], a[1], pt) * _eval_mod2_64(b[0], b[1], pt) % 2**64
+        assert eval_mod2_64_device(ex, co, pt) == want
+    # 10^4 sampled terms against the oracle, one by one
+    sel = torch.from_numpy(rng.choice(n, 10000, replace=False)).cuda()
+    qe, qc = ex[sel].cpu().numpy(), co[sel].cpu().numpy()
+    got = parallel_chunks(lambda q: O.laurent_coeff_at(a[0], a[1], b[0], b[1], q)[0], [qe])
+    np.testing.assert_array_equal(np.concatenate(got), qc)
+    # 10^4 absent tuples: uniform in the box, and next to sampled result terms
+    uni = rng.integers(0, 161, (20000, 6)).astype(np.int32)
+    near = qe.copy()
+    near[np.arange(len(near)), rng.integers(0, 6, len(near))] += rng.choice([-1, 1], len(near)).astype(np.int32)
+    near = np.clip(near, 0, 160)
+    absent = []
+    for cand in (uni, near):
+        present = torch.isin(_key6(dev(cand)), key).cpu().numpy()
+        absent.append(cand[~present][:5000])
+    assert len(absent[0]) == 5000 and len(absent[1]) == 5000
+    q = np.concatenate(absent)
+    got = parallel_chunks(lambda q: O.laurent_coeff_at(a[0], a[1], b[0], b[1], q)[0], [q])
+    assert (np.concatenate(got) == 0).all()
 
 
-def test_full_poisson_sampled():
-    """The Poisson product at full size (2.5e7 pairs), hash mode: keys unique
-    and canonical, numeric evaluation at random angles, sampled terms equal to
-    the oracle's one-by-one coefficients within the tolerance."""
-    torch = _torch()
-    a, b = I.config(4)
-    say("Poisson 3+6 vars, 5000 x 5000 (full)")
-    gx, gy, gt, gc, lay = gpu_poisson(a, b)
-    n = len(gc)
-    assert 4.9e7 < n <= 5e7
-    key = np.concatenate([gx.astype(np.int64), gy.astype(np.int64), gt.reshape(-1, 1)], 1)
+def _poisson_keys(x, y, t):
+    """One int64 per Poisson term of the 5000 x 5000 product (x in [-8,8]^3,
+    multipliers in [-16,16]^6)."""
+    k = np.zeros(len(t), dtype=np.int64)
+    for v in range(x.shape[1]):
+        k = k * 17 + (x[:, v].astype(np.int64) + 8)
+    for v in range(y.shape[1]):
+        k = k * 33 + (y[:, v].astype(np.int64) + 16)
+    return k * 2 + t.astype(np.int64)
+
+
+def _canonical(y, t):
+    """Canonical form of multiplier rows: negate a row whose first nonzero
+    entry is negative; the zero row is taken as a cosine."""
+    nz = y != 0
+    first = np.where(nz.any(1), y[np.arange(len(y)), np.argmax(nz, axis=1)], 0)
+    y = np.where((first < 0)[:, None], -y, y)
+    t = np.where(nz.any(1), t, 0).astype(np.uint8)
+    return y, t
+
+
+def _check_poisson_keys(gx, gy, gt):
+    n = len(gt)
+    key = _poisson_keys(gx, gy, gt)
+    assert len(np.unique(key)) == n
     nz = np.argmax(gy != 0, axis=1)
     first = gy[np.arange(n), nz]
     assert ((first > 0) | ((gy == 0).all(1) & (gt == 0))).all()
+    return key
+
+
+def test_full_poisson_every_term_exact():
+    """The Poisson product at full size (2.5e7 pairs, 5e7 pieces) with the
+    configuration's exponents and integer coefficients, so that every half
+    product and every sum is exact in fp64: the value of all result terms
+    over F_{p^2} (p = 2^61-1; cos and sin of j.y mapped through Z_k for
+    exp(i y_k)) equals the product of the factors' values, at 2 random
+    points.  Keys unique and canonical."""
+    a, b = I.config(4)
+    rng = np.random.default_rng(44)
+    ai = (*a[:3], (rng.integers(1, 1000, len(a[3])) * rng.choice([-1, 1], len(a[3]))).astype(np.float64))
+    bi = (*b[:3], (rng.integers(1, 1000, len(b[3])) * rng.choice([-1, 1], len(b[3]))).astype(np.float64))
+    say("Poisson 3+6 vars, 5000 x 5000 (full), integer coefficients, every term")
+    gx, gy, gt, gc, lay = gpu_poisson(ai, bi)
+    n = len(gc)
+    assert 4.9e7 < n <= 5e7
+    _check_poisson_keys(gx, gy, gt)
+    assert (gc * 2 == np.round(gc * 2)).all()
+    for _ in range(2):
+        xp = [int(v) for v in rng.integers(2, P61, 3)]
+        zp = [(int(u), int(v)) for u, v in rng.integers(2, P61, (6, 2))]
+        want = O.fp2_mul(O.poisson_eval_fp2(ai, 3, 6, xp, zp), O.poisson_eval_fp2(bi, 3, 6, xp, zp))
+        parts = parallel_chunks(lambda x, y, t, c: O.poisson_eval_fp2((x, y, t, c), 3, 6, xp, zp),
+                                [gx, gy, gt, gc])
+        got = (sum(p[0] for p in parts) % P61, sum(p[1] for p in parts) % P61)
+        assert got == want
+
+
+def test_full_poisson_sampled_and_absent():
+    """The Poisson product at full size (2.5e7 pairs), N(0,1) 2^-sum|j|
+    coefficients, hash mode: keys unique and canonical, numeric evaluation at
+    random angles, 10^4 sampled terms equal the oracle's one-by-one
+    coefficients within 1e-13 sum|contributions|, and 10^4 canonical keys
+    absent from the result (half next to result terms, half uniform in the
+    product box) have no oracle contribution beyond that tolerance."""
+    a, b = I.config(4)
+    say("Poisson 3+6 vars, 5000 x 5000 (full), sampled and absent keys")
+    gx, gy, gt, gc, lay = gpu_poisson(a, b)
+    n = len(gc)
+    assert 4.9e7 < n <= 5e7
+    key = _check_poisson_keys(gx, gy, gt)
     rng = np.random.default_rng(5)
     for _ in range(2):
         xs = rng.uniform(0.8, 1.2, 3)
@@ -560,10 +624,31 @@ def test_full_poisson_sampled():
         vb, sb = ev(*b)
         vp, sp = ev(gx, gy, gt, gc)
         assert abs(vp - va * vb) <= 1e-11 * sa * sb
-    sel = rng.integers(0, n, 120)
-    want, wab, _ = O.poisson_coeff_at(a, b, 3, 6, gx[sel], gy[sel], gt[sel])
+    sel = rng.choice(n, 10000, replace=False)
+    res = parallel_chunks(lambda x, y, t: O.poisson_coeff_at(a, b, 3, 6, x, y, t)[:2],
+                          [gx[sel], gy[sel], gt[sel]])
+    want = np.concatenate([r[0] for r in res])
+    wab = np.concatenate([r[1] for r in res])
     assert np.all(np.abs(gc[sel] - want) <= TOL * wab)
-    assert len(np.unique(key[sel], axis=0)) == len(np.unique(sel))
+    # absent canonical keys
+    ny_ = gy[sel].copy()
+    ny_[np.arange(len(sel)), rng.integers(0, 6, len(sel))] += rng.choice([-1, 1], len(sel)).astype(np.int32)
+    ny_ = np.clip(ny_, -16, 16)
+    ny_, nt_ = _canonical(ny_, gt[sel])
+    near = (gx[sel], ny_, nt_)
+    ux = rng.integers(-8, 9, (20000, 3)).astype(np.int32)
+    uy, ut = _canonical(rng.integers(-16, 17, (20000, 6)).astype(np.int32),
+                        rng.integers(0, 2, 20000).astype(np.uint8))
+    qs = []
+    for cx, cy, ct in (near, (ux, uy, ut)):
+        keep = ~np.isin(_poisson_keys(cx, cy, ct), key)
+        qs.append((cx[keep][:5000], cy[keep][:5000], ct[keep][:5000]))
+    assert all(len(q[2]) == 5000 for q in qs)
+    qx, qy, qt = (np.concatenate([q[i] for q in qs]) for i in range(3))
+    res = parallel_chunks(lambda x, y, t: O.poisson_coeff_at(a, b, 3, 6, x, y, t)[:2], [qx, qy, qt])
+    want = np.concatenate([r[0] for r in res])
+    wab = np.concatenate([r[1] for r in res])
+    assert np.all(np.abs(want) <= TOL * wab)
 
 
 # ------------------------------------------------------------------ the paper's benchmarks
