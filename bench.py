@@ -1,14 +1,14 @@
 #!/usr/bin/env python3
-"""Benchmark: sparse Laurent-polynomial products on one MI355X.
+"""Benchmark: sparse Laurent-polynomial and Poisson-series products on one MI355X.
 
 A step is one pass of the whole hot path over one product of device-resident
 factors: per-variable min/max of both factors (kernel) and the product layout
-(host), Kronecker encoding of both factors, the multiply (sort, planning,
-dense-window accumulation or hash accumulation, compaction) and decoding of
-the result.  The headline workload is the moderately sparse product: two
-4-variable polynomials of 10,000 terms each drawn from the simplex of total
-degree <= 20, int64 coefficients in [1, 1000] (1e8 term products per step),
-dense accumulation.
+(host), Kronecker encoding of both factors, the multiply (planning, hash or
+dense accumulation, compaction) and decoding of the result.  The headline
+workload is the highly sparse product: two 6-variable polynomials of 30,000
+distinct terms each, exponents uniform in [0, 80], int64 coefficients in
+[-1000, 1000] (9e8 term products per step, about 9e8 result terms), hash
+accumulation.
 
 Prints ONE JSON line.  Term-products/s counts one (i, j) pair of factor
 terms as one term product, the unit of the paper's ccpm figures (Section 5).
@@ -32,17 +32,19 @@ HBM_PEAK_GBS = 8000.0
 LDS_ATOMIC_PEAK = CUS * 16 * CLOCK_HZ          # pair accumulations per second
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_dense_mul_moderately_sparse_10k.md")
+PROFILES = os.path.join(ROOT, "profiles")
+HEADLINE_PROFILE = "k_radix_highly_sparse_30k.md"
+DENSE_PROFILE = "k_dense_mul_moderately_sparse_10k.md"
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dense window kernel from the committed
-    FETCH_SIZE/WRITE_SIZE summary, or None once the kernel source differs
-    from the one the counters were taken on."""
+def measured_traffic(name):
+    """HBM bytes per launch of a profiled kernel sequence from the committed
+    FETCH_SIZE/WRITE_SIZE summary `name` (copy-calibrated), or None once the
+    kernel source differs from the one the counters were taken on."""
     import hashlib
     try:
         kv = {}
-        for line in open(PROFILE):
+        for line in open(os.path.join(PROFILES, name)):
             if " = " in line:
                 k, v = line.strip().split(" = ", 1)
                 kv[k] = v
@@ -54,6 +56,30 @@ def measured_traffic():
         return None
 
 
+def roof_hbm(kernel, alg_bytes, kernel_s, traffic, per_unit):
+    """HBM roofline of a hash accumulation: algorithmic bytes per launch over
+    the accumulation's duration, against 8 TB/s."""
+    achieved = alg_bytes / kernel_s / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": alg_bytes, "per_unit": per_unit,
+            "kernel_ms": kernel_s * 1e3}
+
+
+def roof_lds(kernel, accumulates, kernel_s, traffic):
+    """Roofline of the dense window kernel: one 64-bit LDS accumulate per term
+    product against the LDS atomic peak (256 CUs x 16 eight-byte lanes per
+    clock x 2.4 GHz)."""
+    rate = accumulates / kernel_s
+    return {"bound": "lds", "kernel": kernel, "achieved": rate / 1e12,
+            "peak": LDS_ATOMIC_PEAK / 1e12,
+            "unit": "Tacc/s (one 64-bit LDS accumulate per term product)",
+            "frac": rate / LDS_ATOMIC_PEAK, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel_ms": kernel_s * 1e3, "units_per_launch": accumulates}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,8 +88,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (sparse, Poisson, small)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--requests", type=int, default=300,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=2000,
                     help="requests of the mixed stream for the serving measurement (0: skip)")
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--only", choices=sorted(EXTRA), default=None,
@@ -137,8 +163,14 @@ def measure_laurent(kp, ctx, a, b, mode, steps, warmup, exact=False):
                                        flags=kp.KP_FLAG_ASYNC, exact=exact)
     mul_sec = time_steps(mul, steps, warmup)
     assert int(out[2].item()) == n_out
+    ctx.timing_read()
+    ctx.timing(True)
+    time_steps(mul, steps, 0)
+    kms, ml = ctx.timing_read()
+    ctx.timing(False)
+    del out
     return dict(sec=sec, kernel_s=kernel_s, launches=launches, mul_sec=mul_sec, n_out=n_out,
-                mode=m)
+                mode=m, mul_kernel_s=kms / 1e3 / max(ml, 1))
 
 
 def measure_poisson(kp, ctx, a, b, mode, steps, warmup):
@@ -210,20 +242,42 @@ def run_box(kp, ctx, I, args):
             "mode": r1["mode"]}
 
 
-def run_sparse(kp, ctx, I, args):
+def run_moderate(kp, ctx, I, args):
+    """The 4-variable simplex product (1e8 pairs, dense mode), with the dense
+    window kernel's roofline against the LDS atomic unit."""
+    a, b = I.config(2)
+    r = measure_laurent(kp, ctx, a, b, "auto", max(args.steps, 20), args.warmup)
+    pairs = len(a[1]) * len(b[1])
+    roof = roof_lds("k_dense_mul (LDS window accumulation)", pairs, r["kernel_s"],
+                    measured_traffic(DENSE_PROFILE))
+    rates = [ctx.probe_lds_atomic(p) for p in range(5)]
+    roof["measured_lds_atomic"] = {
+        "u64_consecutive_Tacc_per_s": rates[0] / 1e12, "u64_random_Tacc_per_s": rates[1] / 1e12,
+        "u32_consecutive_Tacc_per_s": rates[2] / 1e12, "u32_random_Tacc_per_s": rates[3] / 1e12,
+        "u128_carry_pair_random_Tacc_per_s": rates[4] / 1e12,
+        "frac_of_u64_consecutive": pairs / r["kernel_s"] / rates[0],
+        "probe": "LDS atomic adds on every CU, 1024-thread workgroups, 128 KiB of counters"}
+    return {"term_products_per_s": pairs / r["sec"], "ms_per_step": r["sec"] * 1e3,
+            "mode": r["mode"], "result_terms": r["n_out"],
+            "multiply_only": {"ms": r["mul_sec"] * 1e3, "term_products_per_s": pairs / r["mul_sec"]},
+            "roofline": roof,
+            "workload": "moderately sparse Laurent product: 4 variables, total degree <= 20, "
+                        "10000 x 10000 terms, int64 coefficients in [1,1000]"}
+
+
+def sparse_layouts(kp, ctx, I, args):
+    """Section 3.2's bucketed table and the global open-addressing table on the
+    highly sparse product (the grouped layout is the headline)."""
     a3, b3 = I.config(3)
-    r3 = measure_laurent(kp, ctx, a3, b3, "auto", 3, 1)
-    alg_bytes = 32 * 9e8 + 16 * r3["n_out"]
-    out = {"term_products_per_s": 9e8 / r3["sec"], "ms_per_step": r3["sec"] * 1e3,
-           "mode": r3["mode"], "result_terms": r3["n_out"],
-           "insert_kernel_ms": r3["kernel_s"] * 1e3,
-           "hbm_frac_of_insert": alg_bytes / r3["kernel_s"] / 1e9 / HBM_PEAK_GBS}
-    if r3["mode"] == "hash":
-        pa = kp.Poly(to_dev(a3[0]), to_dev(a3[1]))
-        pb = kp.Poly(to_dev(b3[0]), to_dev(b3[1]))
-        out["probing"] = hash_probe_stats(
-            kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "auto"))
-    out["hash_layouts"] = compare_layouts(kp, ctx, a3, b3)
+    out = {"hash_layouts": compare_layouts(kp, ctx, a3, b3)}
+    pa = kp.Poly(to_dev(a3[0]), to_dev(a3[1]))
+    pb = kp.Poly(to_dev(b3[0]), to_dev(b3[1]))
+    ctx.set_tune(hash_partitioned=0)
+    try:
+        out["global_table_probing"] = hash_probe_stats(
+            kp, ctx, lambda: laurent_step(kp, ctx, kp.Workspace(), pa, pb, "hash"))
+    finally:
+        ctx.set_tune(hash_partitioned=1)
     return out
 
 
@@ -252,6 +306,8 @@ def run_mp(kp, ctx, I, args):
     out = {"term_products_per_s": pm / rm["sec"], "ms_per_step": rm["sec"] * 1e3,
            "term_products": pm, "mode": rm["mode"], "result_terms": rm["n_out"],
            "insert_kernel_ms": rm["kernel_s"] * 1e3,
+           "roofline": roof_hbm("hash accumulation", 32 * pm + 16 * rm["n_out"], rm["kernel_s"],
+                                None, "32 B per term product + 16 B per result term"),
            "paper_cpu_context": "1.71 s on one Core2 Q6600 core, fp64 (2.2e7 pairs/s)"}
     rx = measure_laurent(kp, ctx, f, g, "auto", 5, 1, exact=True)
     out["exact_128"] = {"term_products_per_s": pm / rx["sec"], "ms_per_step": rx["sec"] * 1e3,
@@ -270,9 +326,14 @@ def run_mp(kp, ctx, I, args):
 def run_poisson(kp, ctx, I, args):
     a4, b4 = I.config(4)
     r4 = measure_poisson(kp, ctx, a4, b4, "auto", 5, 1)
+    alg = 2 * 2.5e7 * 32 + 16 * r4["n_out"]
     return {"term_products_per_s": 2.5e7 / r4["sec"], "ms_per_step": r4["sec"] * 1e3,
             "result_terms": r4["n_out"], "mode": r4["mode"],
-            "accumulation_kernel_ms": r4["kernel_s"] * 1e3}
+            "roofline": roof_hbm("grouped hash accumulation (k_radix_* sequence), Poisson pieces",
+                                 alg, r4["kernel_s"], None,
+                                 "32 B per piece (2 per pair) + 16 B per result term"),
+            "workload": "Poisson series product: 3 polynomial + 6 trigonometric variables, "
+                        "5000 x 5000 terms, fp64 coefficients N(0,1) 2^-sum|j|"}
 
 
 def run_truncated(kp, ctx, I, args):
@@ -295,8 +356,9 @@ def run_truncated(kp, ctx, I, args):
     return out
 
 
-EXTRA = {"box_500x500": run_box, "sparse_30000x30000": run_sparse, "fateman_30": run_fateman,
-         "mp_sparse_12": run_mp, "poisson_5000x5000": run_poisson, "truncated": run_truncated}
+EXTRA = {"moderately_sparse_10000x10000": run_moderate, "box_500x500": run_box,
+         "poisson_5000x5000": run_poisson, "fateman_30": run_fateman, "mp_sparse_12": run_mp,
+         "truncated": run_truncated, "sparse_layouts": sparse_layouts}
 
 
 def measure_serving(kp, n_requests, max_batch):
@@ -329,27 +391,46 @@ def measure_serving(kp, n_requests, max_batch):
         "serving": {"arrival_rate_per_s": rate, "term_products_per_s": pairs / wall,
                     "seconds": wall, **serve.percentiles(lat)},
         "workload": "mixed request stream (types 1-3, 2-6 variables, sizes log-uniform in "
-                    "[50, 20000], int64 or fp64), first requests of the seeded stream",
+                    "[50, 20000], int64 or fp64), the first `requests` requests of the seeded stream",
     }
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(a, b, seconds):
-    """The oracle on a bounded sample: the first R rows of A times all of B."""
+    """The oracle on a bounded sample: the first R rows of A times all of B,
+    R chosen for about `seconds` of work, on the host threads this process
+    may use (at most 16, the CPU share of one GPU); a one-thread run on a
+    smaller prefix is reported beside it."""
     import oracle as O
-    threads = max(1, min(16, O.hardware_threads()))
+    threads = max(1, min(16, O.hardware_threads(), len(os.sched_getaffinity(0))))
     nb = len(b[1])
     t0 = time.perf_counter()
-    O.laurent_mul(a[0], a[1], b[0], b[1], 0, 100, threads)
+    O.laurent_mul(a[0], a[1], b[0], b[1], 0, 20, threads)
     probe = time.perf_counter() - t0
-    rows = int(min(len(a[1]), max(100, 100 * seconds / max(probe, 1e-3))))
+    rows = int(min(len(a[1]), max(20, 20 * seconds / max(probe, 1e-3))))
     t0 = time.perf_counter()
     O.laurent_mul(a[0], a[1], b[0], b[1], 0, rows, threads)
     dt = time.perf_counter() - t0
+    rows1 = max(5, rows // (4 * threads))
+    t0 = time.perf_counter()
+    O.laurent_mul(a[0], a[1], b[0], b[1], 0, rows1, 1)
+    dt1 = time.perf_counter() - t0
     return {"value": rows * nb / dt, "unit": "term-products/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "single_thread_value": rows1 * nb / dt1,
             "sample": f"first {rows} of {len(a[1])} rows of A times all {nb} terms of B "
                       f"({rows * nb:.3g} term products, {dt:.1f} s, std::map oracle, "
-                      f"{threads} threads)"}
+                      f"{threads} threads; one thread: first {rows1} rows, {dt1:.1f} s); "
+                      f"the rate of the whole product is taken as that of the prefix"}
 
 
 def main():
@@ -364,41 +445,35 @@ def main():
     from paper_1004_4548_amd import inputs as I
 
     ctx = kp.context(0)
-    a, b = I.config(2)
+    a, b = I.config(3)
     pairs = len(a[1]) * len(b[1])
     note("headline", len(a[1]), "x", len(b[1]))
     r = measure_laurent(kp, ctx, a, b, "auto", args.steps, args.warmup)
     value = pairs / r["sec"]
-    kernel_rate = pairs / r["kernel_s"]
-    roof = {"bound": "alu", "kernel": "k_dense_mul (LDS window accumulation)",
-            "achieved": kernel_rate / 1e12, "peak": LDS_ATOMIC_PEAK / 1e12,
-            "unit": "Tacc/s (one 64-bit LDS accumulate per term product)",
-            "frac": kernel_rate / LDS_ATOMIC_PEAK, "traffic": measured_traffic(),
-            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel_ms": r["kernel_s"] * 1e3, "units_per_launch": pairs}
+    alg = 32 * pairs + 16 * r["n_out"]
+    roof = roof_hbm("grouped hash accumulation (k_radix_* sequence), whole product", alg,
+                    r["kernel_s"], measured_traffic(HEADLINE_PROFILE),
+                    "32 B per term product (a 16-byte slot read and written) + 16 B per result "
+                    "term (code and coefficient)")
+    roof["multiply_only"] = {"kernel_ms": r["mul_kernel_s"] * 1e3,
+                             "achieved": alg / r["mul_kernel_s"] / 1e9,
+                             "frac": alg / r["mul_kernel_s"] / 1e9 / HBM_PEAK_GBS}
     out = {
         "metric": "term-products/sec", "value": value, "unit": "term-products/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["sec"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": "moderately sparse Laurent product: 4 variables, total degree "
-                               "<= 20, 10000 x 10000 terms, int64 coefficients in [1,1000], "
-                               "dense accumulation",
+        "config": {"workload": "highly sparse Laurent product: 6 variables, exponents uniform in "
+                               "[0,80], 30000 x 30000 distinct terms, int64 coefficients in "
+                               "[-1000,1000], hash accumulation",
                    "term_products_per_step": pairs, "result_terms": r["n_out"],
                    "mode": r["mode"]},
         "multiply_only": {"ms": r["mul_sec"] * 1e3, "term_products_per_s": pairs / r["mul_sec"],
-                          "region": "sort + plan + dense accumulation + compaction, from "
-                                    "encoded codes"},
+                          "region": "from encoded, unsorted codes to compacted (code, coef): "
+                                    "planning + hash accumulation + compaction"},
         "roofline": roof,
     }
-    # measured ceilings of the window kernel's accumulator (context for frac)
-    rates = [ctx.probe_lds_atomic(p) for p in range(5)]
-    roof["measured_lds_atomic"] = {
-        "u64_consecutive_Tacc_per_s": rates[0] / 1e12, "u64_random_Tacc_per_s": rates[1] / 1e12,
-        "u32_consecutive_Tacc_per_s": rates[2] / 1e12, "u32_random_Tacc_per_s": rates[3] / 1e12,
-        "u128_carry_pair_random_Tacc_per_s": rates[4] / 1e12,
-        "frac_of_u64_consecutive": kernel_rate / rates[0],
-        "probe": "LDS atomic adds on every CU, 1024-thread workgroups, 128 KiB of counters"}
+    torch.cuda.empty_cache()
     if args.only:
         out["other_workloads"] = {args.only: EXTRA[args.only](kp, ctx, I, args)}
     elif not args.no_extra:
