@@ -16,8 +16,9 @@
  *  - All functions are extern "C", never throw, and return a kp_status.
  *  - Pointers documented as "device" point to HIP device memory owned by the
  *    caller (for example torch tensors); "host" pointers are ordinary memory.
- *    The library never allocates or frees caller-visible device memory: the
- *    only device allocation it makes is a 256-byte status block per context.
+ *    The library never allocates or frees caller-visible device memory: its
+ *    own device memory is a 256-byte status block per context and the
+ *    scratch array of kp_mul_laurent_noalloc (one per GPU, static).
  *  - Every launch is ordered on the given hipStream_t (0 = null stream).
  *  - Without KP_FLAG_ASYNC a call synchronises its stream once and reports
  *    device-detected errors (range, capacity) in its return value.  With it,
@@ -286,6 +287,30 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
                          const int64_t* b_codes, const void* b_coef, int64_t nb,
                          int64_t* out_codes, void* out_coef, int64_t out_cap, int64_t* out_n,
                          void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Allocation-free kp_mul_laurent, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The same product with the same arguments, except that
+ * the workspace is a scratch array the library keeps in device memory,
+ * KP_SCRATCH_BYTES (64 MiB) per GPU, reserved when the library's code is
+ * loaded on that GPU and held until the process ends; the call allocates no
+ * device memory and creates no events.  KP_E_WORKSPACE (nothing queued) when
+ * the product's workspace (kp_mul_bound) is larger than the scratch array;
+ * KP_E_DEVICE when the array's address could not be found at context
+ * creation.  Every call on one GPU uses that GPU's one array, which keeps the
+ * last call's contents (each call initialises what it needs): calls on one
+ * stream are ordered and safe, calls that overlap on one GPU (different
+ * streams, or asynchronous calls on different streams) race and give
+ * undefined results.
+ */
+#define KP_SCRATCH_BYTES ((size_t)64 << 20)
+kp_status kp_mul_laurent_noalloc(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype,
+                                 kp_mode mode, unsigned flags, const int64_t* a_codes,
+                                 const void* a_coef, int64_t na, const int64_t* b_codes,
+                                 const void* b_coef, int64_t nb, int64_t* out_codes,
+                                 void* out_coef, int64_t out_cap, int64_t* out_n,
+                                 hipStream_t stream);
 
 /*
  * Product of two Poisson series (Section 1, eq. ps_def) in canonical form.

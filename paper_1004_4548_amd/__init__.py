@@ -30,6 +30,7 @@ KP_I64, KP_F64, KP_I128 = 0, 1, 2
 KP_AUTO, KP_DENSE, KP_HASH = 0, 1, 2
 KP_FLAG_ASYNC = 1
 KP_BATCH_GRAPH = 2
+KP_SCRATCH_BYTES = 64 << 20   # the scratch array of kp_mul_laurent_noalloc (include/kp.h)
 KP_KIND_LAURENT, KP_KIND_POISSON = 0, 1
 MODES = {"auto": KP_AUTO, "dense": KP_DENSE, "hash": KP_HASH}
 MODE_NAMES = {v: k for k, v in MODES.items()}
@@ -42,7 +43,8 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_batch_add", "kp_batch_clear", "kp_batch_launch", "kp_batch_status",
             "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic",
             "kp_plan_laurent", "kp_mul_laurent_exps", "kp_plan_poisson", "kp_mul_poisson_exps",
-            "kp_mul_laurent_auto", "kp_ctx_set_truncation", "kp_ctx_clear_truncation"]
+            "kp_mul_laurent_auto", "kp_ctx_set_truncation", "kp_ctx_clear_truncation",
+            "kp_mul_laurent_noalloc"]
 
 
 class KPError(RuntimeError):
@@ -111,6 +113,8 @@ def lib():
                                C.POINTER(i64), C.POINTER(sz)]),
         "kp_mul_laurent": (i32, [p, C.POINTER(Layout), i32, i32, u32, p, p, i64, p, p, i64, p,
                                  p, i64, p, p, sz, p]),
+        "kp_mul_laurent_noalloc": (i32, [p, C.POINTER(Layout), i32, i32, u32, p, p, i64, p, p,
+                                         i64, p, p, i64, p, p]),
         "kp_mul_poisson": (i32, [p, C.POINTER(Layout), i32, u32, p, p, p, p, i64, p, p, p, p,
                                  i64, p, p, i64, p, p, sz, p]),
         "kp_decode": (i32, [p, C.POINTER(Layout), i32, i64, p, p, p, p, u32, p]),
@@ -472,6 +476,25 @@ def mul_laurent_codes(layout, a_codes, a_coef, b_codes, b_coef, mode="auto", ctx
         return oc, ov, on
     n = _count(ctx, on)
     return oc[:n], ov[:n], on
+
+
+def mul_laurent_noalloc(layout, a_codes, a_coef, b_codes, b_coef, out, mode="auto", ctx=None,
+                        flags=0):
+    """kp_mul_laurent_noalloc: kp_mul_laurent with the library's per-GPU
+    scratch array as workspace.  `out` = (codes int64 [cap], coef [cap],
+    count int64 [1]), caller-allocated; nothing is allocated here.  Returns
+    the count (without KP_FLAG_ASYNC; one read) or None."""
+    import torch
+    ctx = ctx or context()
+    dt = _dt(a_coef)
+    for t, nm in ((a_codes, "a_codes"), (b_codes, "b_codes")):
+        _dev_check(t, torch.int64, nm)
+    oc, ov, on = out
+    ctx.check(lib().kp_mul_laurent_noalloc(
+        ctx.h, C.byref(layout), dt, _mode(mode), flags, _ptr(a_codes), _ptr(a_coef),
+        a_codes.shape[0], _ptr(b_codes), _ptr(b_coef), b_codes.shape[0], _ptr(oc), _ptr(ov),
+        oc.shape[0], _ptr(on), _stream()))
+    return None if flags & KP_FLAG_ASYNC else int(on.item())
 
 
 def _count(ctx, on):

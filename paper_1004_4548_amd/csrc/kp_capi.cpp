@@ -31,6 +31,8 @@ struct kp_ctx {
   std::mutex mb_mu;                   // serialises mailbox users
   bool trunc_on = false;              // truncation of Laurent products by weighted degree
   kp::TruncSpec trunc{};
+  void* scratch = nullptr;            // device address of this device's scratch array
+  hipError_t scratch_err = hipSuccess;
 };
 
 namespace kp {
@@ -39,6 +41,34 @@ namespace {
 
 constexpr int64_t CODE_LIMIT = (int64_t)1 << 62;
 constexpr size_t ALIGN = 256;
+
+// Workspace of kp_mul_laurent_noalloc: one array per GPU, reserved when this
+// code object is loaded on the GPU and kept until the process ends.  Host
+// code never uses the name itself (on the host it is only a stand-in for the
+// symbol): the device address of each GPU's copy is looked up once per
+// device, with that device current, and kept in scratch_ptr.
+__device__ __align__(256) unsigned char scratch[KP_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES];
+hipError_t scratch_err[MAX_DEVICES];
+bool scratch_done[MAX_DEVICES];
+
+// Device address of `device`'s scratch array (the device must be current).
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(scratch_mu);
+  if (!scratch_done[device]) {
+    void* ptr = nullptr;
+    scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    scratch_ptr[device] = scratch_err[device] == hipSuccess ? ptr : nullptr;
+    scratch_done[device] = true;
+  }
+  *out = scratch_ptr[device];
+  return scratch_err[device];
+}
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -695,6 +725,9 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
     std::memset(ctx->mb, 0, sizeof(Mailbox));
     e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->mb_dev), ctx->mb, 0);
   }
+  // the allocation-free entry point's workspace (a failure is reported by
+  // that entry point, not here)
+  if (e == hipSuccess) ctx->scratch_err = scratch_address(device, &ctx->scratch);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     kp_ctx_destroy(ctx);
@@ -1249,6 +1282,35 @@ kp_status kp_mul_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, k
                                      workspace_bytes, stream, true);
   if (st != KP_OK) return st;
   return kp::finish(ctx, flags, stream, "kp_mul_laurent");
+}
+
+kp_status kp_mul_laurent_noalloc(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype,
+                                 kp_mode mode, unsigned flags, const int64_t* a_codes,
+                                 const void* a_coef, int64_t na, const int64_t* b_codes,
+                                 const void* b_coef, int64_t nb, int64_t* out_codes,
+                                 void* out_coef, int64_t out_cap, int64_t* out_n,
+                                 hipStream_t stream) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (!ctx->status) return fail(ctx, KP_E_ARG, "host-only context");
+  if (!ctx->scratch)
+    return fail(ctx, KP_E_DEVICE, "kp_mul_laurent_noalloc: no scratch array on device %d (%s)",
+                ctx->device, hipGetErrorString(ctx->scratch_err));
+  Plan p;
+  kp_status st = make_plan(ctx, layout, 0, dtype, mode, na, nb, &p);
+  if (st != KP_OK) return st;
+  if (p.ws > KP_SCRATCH_BYTES)
+    return fail(ctx, KP_E_WORKSPACE,
+                "kp_mul_laurent_noalloc: the product needs %zu bytes of workspace, the scratch "
+                "array holds %zu",
+                p.ws, (size_t)KP_SCRATCH_BYTES);
+  // no timing events (creating them may allocate); the kernels see the
+  // scratch array only through its device address
+  st = kp::enqueue_laurent(ctx, layout, dtype, mode, a_codes, a_coef, na, b_codes, b_coef, nb,
+                           out_codes, out_coef, out_cap, out_n, ctx->scratch, KP_SCRATCH_BYTES,
+                           stream, false);
+  if (st != KP_OK) return st;
+  return kp::finish(ctx, flags, stream, "kp_mul_laurent_noalloc");
 }
 
 kp_status kp_mul_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode, unsigned flags,
