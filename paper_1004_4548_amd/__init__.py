@@ -70,7 +70,8 @@ class Tune(C.Structure):
                 ("dense_max_keys", C.c_int64), ("dense_keys_per_pair", C.c_double),
                 ("hash_rows", C.c_int32), ("hash_partitioned", C.c_int32),
                 ("hash_bucket", C.c_int32), ("hash_order", C.c_int32),
-                ("hash_bin_slots", C.c_int32)]
+                ("hash_bin_slots", C.c_int32), ("hash_grouping", C.c_int32),
+                ("hash_max_bin_bits", C.c_int32)]
 
 
 class MulDesc(C.Structure):

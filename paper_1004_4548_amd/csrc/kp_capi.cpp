@@ -41,6 +41,7 @@ namespace {
 
 constexpr int64_t CODE_LIMIT = (int64_t)1 << 62;
 constexpr size_t ALIGN = 256;
+constexpr uint64_t GOLDEN_ODD = 0x9E3779B97F4A7C15ull;   // 2^64 / golden ratio, odd
 
 // Workspace of kp_mul_laurent_noalloc: one array per GPU, reserved when this
 // code object is loaded on the GPU and kept until the process ends.  Host
@@ -291,6 +292,11 @@ struct Plan {
   int bm = 0;
   int64_t nbuckets = 0, ovcap = 0;
   bool order = false;
+  // grouped by code range: ranges of 2^rw codes, row splits of A, bins, B buckets
+  bool range = false;
+  int rw = 0;
+  int64_t rnr = 0, rnsplit = 1, rrows = 0, rbins = 0, rnbk = 0;
+  int rshift = 0, rtarget = 10;
 };
 
 // Truncation tables: slack of A's terms and degree of B's (input order),
@@ -441,8 +447,16 @@ void carve_poisson_dense(Carver& c, int64_t na, int64_t nb, PoissonDenseBufs* q)
   if (CARVE) *q = PoissonDenseBufs{ak, ac, bk, bc};
 }
 
+struct RangeCarve {
+  int64_t* bk; uint64_t* bc; int32_t* b_tb; int32_t* brank; int32_t* bstart;
+  int64_t* rcount; int32_t* rl2; int64_t* rbin0; int64_t* rtotal; int64_t* rbase;
+  int64_t* rterms; int64_t* rhole; int64_t* rabove; int64_t* cnt;
+  int32_t* bin_range; int64_t* bin_off; int64_t* bin_cnt; void* ent;
+};
+
 struct HashCarve {
   Meta* meta;
+  RangeCarve rg;
   uint64_t* table;
   // bucketed table with its term order: both factors reordered, rank scratch
   int64_t* ord_ak; uint64_t* ord_ac; int64_t* ord_bk; uint64_t* ord_bc;
@@ -473,6 +487,37 @@ void radix_shape(int64_t na, int64_t nb, int64_t nprod, int bin_slots, Plan* p) 
   p->nprod = std::max<int64_t>(nprod, 1);
 }
 
+// Shape of the accumulation grouped by code range: about 2^18 products per
+// range (at least 256 ranges, at most 16384, never more than codes), enough
+// row splits of A for about 2048 counting workgroups, bins of half a table,
+// and B's buckets (about two per term, as for dense mode).
+void range_shape(const kp_layout* L, int64_t na, int64_t nb, int64_t nprod, int bin_slots,
+                 int max_bin_bits, Plan* p) {
+  int K = 0;
+  while (K < 62 && ((int64_t)1 << K) < L->nkeys) ++K;
+  int lr = 8;
+  while (lr < 14 && ((int64_t)1 << (lr + 18)) < nprod) ++lr;
+  lr = std::min(lr, K);
+  p->rw = K - lr;
+  p->rnr = std::max<int64_t>(1, (L->nkeys + ((int64_t)1 << p->rw) - 1) >> p->rw);
+  p->rnsplit = std::max<int64_t>(1, std::min<int64_t>(16, (2048 + p->rnr - 1) / p->rnr));
+  p->rnsplit = std::min<int64_t>(p->rnsplit, std::max<int64_t>(1, na));
+  p->rrows = (na + p->rnsplit - 1) / p->rnsplit;
+  p->blog = bin_slots == 8192 ? 13 : bin_slots == 4096 ? 12 : 11;
+  p->rtarget = p->blog - 1;
+  p->nprod = std::max<int64_t>(nprod, 1);
+  // bins: at most two per 2^rtarget products (bucket granularity adds a few
+  // candidates per row and range) plus one per range
+  const double cand = (double)nprod + 4.0 * (double)na * (double)p->rnr;
+  const int bb = std::max(0, std::min(10, max_bin_bits));
+  p->rbins = std::min<int64_t>(p->rnr << bb,
+                               p->rnr + 2 * (int64_t)std::ceil(cand / (double)((int64_t)1 << p->rtarget)));
+  p->rbins = std::max<int64_t>(p->rbins, p->rnr);
+  const int64_t maxB = factor_maxcode(L, 1);
+  p->rshift = dense_bucket_shift(maxB, nb);
+  p->rnbk = (maxB >> p->rshift) + 1;
+}
+
 void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, HashCarve* h) {
   h->meta = c.take<Meta>(1);
   h->table = nullptr;
@@ -483,7 +528,28 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
   h->ord_ak = h->ord_bk = nullptr;
   h->ord_ac = h->ord_bc = nullptr;
   h->ord_rank = h->ord_sa = h->ord_tb = nullptr;
-  if (p.radix) {
+  h->rg = RangeCarve{};
+  if (p.range) {
+    RangeCarve& g = h->rg;
+    g.bk = c.take<int64_t>(nb);
+    g.bc = c.take<uint64_t>(nb);
+    g.b_tb = p.trunc ? c.take<int32_t>(nb) : nullptr;
+    g.brank = c.take<int32_t>(nb);
+    g.bstart = c.take<int32_t>(p.rnbk + 1);
+    g.rcount = c.take<int64_t>(p.rnr);
+    g.rl2 = c.take<int32_t>(p.rnr);
+    g.rbin0 = c.take<int64_t>(p.rnr + 1);
+    g.rtotal = c.take<int64_t>(p.rnr);
+    g.rbase = c.take<int64_t>(p.rnr);
+    g.rterms = c.take<int64_t>(p.rnr);
+    g.rhole = c.take<int64_t>(p.rnr + 1);
+    g.rabove = c.take<int64_t>(p.rnr + 1);
+    g.cnt = c.take<int64_t>((size_t)(p.rbins * p.rnsplit));
+    g.bin_range = c.take<int32_t>(p.rbins);
+    g.bin_off = c.take<int64_t>(p.rbins);
+    g.bin_cnt = c.take<int64_t>(p.rbins);
+    g.ent = c.take<uint4>((size_t)p.nprod);
+  } else if (p.radix) {
     const int64_t P1 = (int64_t)1 << p.l1, bins = P1 << p.l2;
     h->counts = c.take<uint32_t>((size_t)(P1 * p.nblocks));
     h->pstart = c.take<int64_t>((size_t)P1 + 1);
@@ -618,6 +684,12 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                (ctx->tune.hash_partitioned == 2 ||
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
+    p->range = p->radix && !poisson && dt != KP_I128 && ctx->tune.hash_grouping == 0 &&
+               na < ((int64_t)1 << 31) && nb < ((int64_t)1 << 31);
+    if (p->range) {
+      p->radix = false;
+      range_shape(L, na, nb, contrib, ctx->tune.hash_bin_slots, ctx->tune.hash_max_bin_bits, p);
+    }
     if (p->radix) {
       if (contrib > ((int64_t)1 << 36))
         return fail(ctx, KP_E_CAPACITY, "%lld products exceed the partitioned table",
@@ -702,6 +774,8 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.hash_bucket = 0;
   ctx->tune.hash_order = 1;
   ctx->tune.hash_bin_slots = 4096;
+  ctx->tune.hash_grouping = 0;
+  ctx->tune.hash_max_bin_bits = 10;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
     *out = ctx;
     return KP_OK;
@@ -861,6 +935,10 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "hash_order must be 0 or 1");
   if (t->hash_bin_slots != 2048 && t->hash_bin_slots != 4096 && t->hash_bin_slots != 8192)
     return fail(ctx, KP_E_ARG, "hash_bin_slots must be 2048, 4096 or 8192");
+  if (t->hash_grouping != 0 && t->hash_grouping != 1)
+    return fail(ctx, KP_E_ARG, "hash_grouping must be 0 or 1");
+  if (t->hash_max_bin_bits < 0 || t->hash_max_bin_bits > 10)
+    return fail(ctx, KP_E_ARG, "hash_max_bin_bits must lie in [0, 10]");
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");
@@ -1083,7 +1161,70 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
     H.b_tb = tr.tb;
     if (!empty && timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
     e = launch_meta_init(h.meta, stream);
-    if (!empty && p.radix) {
+    if (!empty && p.range) {
+      const RangeCarve& g = h.rg;
+      RangeArgs R{};
+      R.meta = h.meta;
+      R.ak = a_codes;
+      R.ac = a_coef;
+      R.na = na;
+      R.maxA = factor_maxcode(layout, 0);
+      R.bk_in = b_codes;
+      R.bc_in = b_coef;
+      R.nb = nb;
+      R.maxB = factor_maxcode(layout, 1);
+      R.a_sa = tr.sa;
+      R.b_tb_in = tr.tb;
+      R.bk = g.bk;
+      R.bc = g.bc;
+      R.b_tb = tr.tb ? g.b_tb : nullptr;
+      R.brank = g.brank;
+      R.bstart = g.bstart;
+      R.shiftB = p.rshift;
+      R.nbkB = p.rnbk;
+      R.nkeys = layout->nkeys;
+      R.w = p.rw;
+      R.nr = p.rnr;
+      // an odd multiplier modulo 2^w and its inverse (Newton's iteration
+      // doubles the correct low bits each step: 1, 2, 4, ..., 64)
+      const uint64_t m = GOLDEN_ODD;
+      uint64_t inv = m;
+      for (int k = 0; k < 6; ++k) inv *= 2 - m * inv;
+      const uint64_t mask = p.rw >= 64 ? ~0ull : ((1ull << p.rw) - 1);
+      R.mult = m & mask;
+      R.inv = inv & mask;
+      R.nsplit = p.rnsplit;
+      R.rows = p.rrows;
+      R.target_log = p.rtarget;
+      R.max_l2 = std::max(0, std::min(10, ctx->tune.hash_max_bin_bits));
+      R.nbins_max = p.rbins;
+      R.rcount = g.rcount;
+      R.rl2 = g.rl2;
+      R.rbin0 = g.rbin0;
+      R.rtotal = g.rtotal;
+      R.rbase = g.rbase;
+      R.rterms = g.rterms;
+      R.rhole = g.rhole;
+      R.rabove = g.rabove;
+      R.cnt = g.cnt;
+      R.bin_range = g.bin_range;
+      R.bin_off = g.bin_off;
+      R.bin_cnt = g.bin_cnt;
+      R.ent = g.ent;
+      R.out_k = out_codes;
+      R.out_c = out_coef;
+      R.out_cap = out_cap;
+      if (xo) {
+        R.out_x = xo->exps;
+        R.dec = xo->dec;
+        xo->decoded = true;
+      }
+      R.ev0 = H.ev0;
+      R.ev1 = H.ev1;
+      R.bin_log = p.blog;
+      R.stats = H.stats;
+      if (e == hipSuccess) e = launch_range(R, dtype, stream);
+    } else if (!empty && p.radix) {
       if (e == hipSuccess && dtype == KP_I64)
         e = launch_coef_range((const int64_t*)a_coef, na, (const int64_t*)b_coef, nb, h.meta,
                               stream);

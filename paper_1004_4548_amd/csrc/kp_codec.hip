@@ -378,6 +378,12 @@ __global__ void k_meta_init(Meta* m) {
     m->narrow = 3u;
     m->ntasks = 0;
     m->out_count = 0;
+    m->amax = 0;
+    m->bmax = 0;
+    m->nbins = 0;
+    m->entries = 0;
+    m->pack = 0;
+    m->reserve = 0;
   }
 }
 

@@ -171,6 +171,12 @@ struct Meta {
   uint32_t radix_l2;      // grouped hash: level-2 bits for the products actually made
   int64_t task_rows;      // dense: cost of a task (work items plus window overheads)
   int64_t pad;
+  // hash accumulation grouped by code range
+  unsigned long long amax, bmax;   // largest |coefficient| of A and of B (int64)
+  int64_t nbins;          // bins of all ranges
+  int64_t entries;        // products written (grouped entries)
+  uint32_t pack;          // entries packed in 8 bytes (value above the hash bits)
+  uint32_t reserve;       // each range's terms go to its own entry slots (no shared counter)
 };
 
 // Status block owned by a context (device memory, 256 bytes).
@@ -422,6 +428,49 @@ hipError_t launch_radix(const RadixArgs& R, int kind, hipStream_t s);
 // Threads (terms of B) per count / scatter workgroup; the workspace planner
 // sizes the per-workgroup histograms with it.
 constexpr int RADIX_THREADS = 1024;
+
+// Hash accumulation grouped by output code range (Laurent, int64 or fp64).
+// Range r holds the product codes [r << w, (r + 1) << w) of [0, nkeys).  The
+// products of a range are found from each row of A and an interval of B
+// sorted into buckets of 2^shiftB codes, so nothing is written before they
+// are grouped: each product goes once to a bin of its range, chosen by the
+// top bits of a w-bit hash of its offset in the range, and each bin is
+// accumulated in an LDS table.
+struct RangeArgs {
+  Meta* meta;
+  const int64_t* ak; const void* ac; int64_t na; int64_t maxA;   // A, input order
+  const int64_t* bk_in; const void* bc_in; int64_t nb; int64_t maxB;
+  const int32_t* a_sa; const int32_t* b_tb_in;   // optional truncation: keep b_tb[j] <= a_sa[i]
+  int64_t* bk; uint64_t* bc; int32_t* b_tb;      // B bucket-sorted (b_tb only with truncation)
+  int32_t* brank; int32_t* bstart;               // [nb], [nbkB + 1]
+  int shiftB; int64_t nbkB;
+  int64_t nkeys; int w; int64_t nr;              // ranges of 2^w codes, nr of them
+  uint64_t mult, inv;                            // odd multiplier mod 2^w and its inverse
+  int64_t nsplit, rows;                          // row splits of A, rows per split
+  int target_log;                                // log2 of the products wanted per bin
+  int max_l2;                                    // most bin bits of one range
+  int64_t nbins_max;
+  int64_t* rcount;   // [nr] product bound per range (bucket granularity)
+  int32_t* rl2;      // [nr] bin bits of each range
+  int64_t* rbin0;    // [nr + 1] first bin of each range
+  int64_t* rtotal;   // [nr] entries of each range
+  int64_t* rbase;    // [nr] first entry (and first result slot) of each range
+  int64_t* rterms;   // [nr] result terms written for each range
+  int64_t* rhole;    // [nr + 1] prefix of the empty slots before the result count
+  int64_t* rabove;   // [nr + 1] prefix of the terms past the result count
+  int64_t* cnt;      // [nbins_max * nsplit] entries per (bin, split), then offsets in the range
+  int32_t* bin_range;  // [nbins_max]
+  int64_t* bin_off;    // [nbins_max] first entry of each bin within its range
+  int64_t* bin_cnt;    // [nbins_max]
+  void* ent;         // entries: 8 bytes (packed) or 16 bytes each
+  int64_t* out_k; void* out_c; int64_t out_cap;
+  int32_t* out_x; DevLayout dec;   // optional decoded output instead of codes
+  hipEvent_t ev0, ev1;
+  int bin_log;       // log2 of a bin table's slots (11, 12 or 13)
+  unsigned long long* stats;   // optional: {insertions, extra probe steps}
+};
+hipError_t range_setup();
+hipError_t launch_range(const RangeArgs& R, kp_dtype dt, hipStream_t s);
 
 // diagnostics (kp_diag.hip)
 hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,

@@ -1,0 +1,851 @@
+// kp_range.hip -- hash accumulation of highly sparse Laurent products,
+// grouped by output code range.
+//
+// Section 3.2 accumulates the products of a highly sparse multiplication in a
+// hash table keyed by the product's code.  Here the table is split twice so
+// that every part of it lives in LDS.  The code space [0, nkeys) is cut into
+// ranges of 2^w consecutive codes; since B is sorted by code (into buckets of
+// 2^shiftB codes), the products of row i of A that fall in range r are the
+// terms of one interval of B (Section 3: the schoolbook product of the coded
+// factors, restricted to an output interval, as Section 4 restricts threads
+// to disjoint output intervals).  Nothing is written before grouping: each
+// product is formed from the factors, hashed within its range (an odd
+// multiplier modulo 2^w, a bijection, so the hash identifies the code), and
+// written once to a bin of its range, the bin being the top bits of the
+// hash.  One workgroup then accumulates each bin in an LDS open-addressing
+// table and writes its nonzero terms.
+//
+// HBM traffic per product is one entry written and read (8 bytes when the
+// value fits above the w hash bits, else 16), instead of a 16-byte table slot
+// read and written back per product in a global table.
+//
+// Result slots: the entries of range r occupy [rbase_r, rbase_r + total_r);
+// the range's terms (at most its entries) are written from rbase_r on, in
+// the order in which its bins finish (one counter per range).  The count N
+// of all terms is then known, and the few terms that lie at N or beyond are
+// moved into the empty slots below N, so the result is contiguous without a
+// counter shared by all bins.  When the entries would not fit the caller's
+// capacity, one shared counter places the terms instead.
+//
+// A bin with more distinct codes than its table holds (possible only for
+// adversarial codes, since bins are sized from the product counts) is redone
+// on halves of its hash interval until each part fits: an interval of at most
+// as many hash values as slots always fits, the hash being a bijection.
+#include <climits>
+#include <type_traits>
+
+#include "kp_internal.h"
+
+namespace kp {
+
+namespace {
+
+constexpr uint64_t GOLD = 0x9E3779B97F4A7C15ull;   // 2^64 / golden ratio (Fibonacci hashing)
+constexpr int RG_BLOCK = 1024;    // threads of the counting and scatter workgroups
+constexpr int RG_PER = 8;         // products per thread per staged chunk
+constexpr int RG_STAGE = RG_BLOCK * RG_PER;
+constexpr int RG_MAX_L2 = 10;     // at most 1024 bins per range
+constexpr int SORT_BLOCK = 1024;
+constexpr int SMALL_BLOCK = 256;
+constexpr int BIN_PER = 8;        // entries per thread loaded at once in a bin (slots / threads)
+constexpr int STACK = 72;         // hash intervals of a bin's overflow passes (depth <= 62)
+
+__device__ __forceinline__ uint64_t uabs(int64_t c) {
+  return c < 0 ? 0ull - (uint64_t)c : (uint64_t)c;
+}
+
+__device__ __forceinline__ int64_t mul_value(int64_t a, int64_t b) {
+  return (int64_t)((uint64_t)a * (uint64_t)b);   // wraps modulo 2^64
+}
+__device__ __forceinline__ double mul_value(double a, double b) { return a * b; }
+
+template <typename T>
+__device__ __forceinline__ T from_bits(uint64_t u) {
+  T v;
+  __builtin_memcpy(&v, &u, 8);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ uint64_t to_bits(T v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  return u;
+}
+
+__device__ __forceinline__ uint64_t wmask(int w) {
+  return w >= 64 ? ~0ull : ((1ull << w) - 1);
+}
+
+// Interval [j0, j1) of bucket-sorted B holding every term b with a + b in
+// [lo, hi) (and a few neighbours of the edge buckets); false when empty.
+__device__ __forceinline__ bool row_interval(const RangeArgs& R, int64_t a, int64_t lo,
+                                             int64_t hi, int64_t* j0, int64_t* j1) {
+  int64_t xlo = lo - a, xhi = hi - 1 - a;
+  if (xhi < 0 || xlo > R.maxB) return false;
+  xlo = xlo < 0 ? 0 : xlo;
+  xhi = xhi > R.maxB ? R.maxB : xhi;
+  *j0 = R.bstart[xlo >> R.shiftB];
+  *j1 = R.bstart[(xhi >> R.shiftB) + 1];
+  return *j0 < *j1;
+}
+
+__device__ __forceinline__ uint32_t bin_of(uint64_t h, int w, int l2) {
+  return l2 ? (uint32_t)(h >> (w - l2)) : 0u;
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads.
+template <int NT, typename V>
+__device__ __forceinline__ V block_scan(V v, V* s_ws, V* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  V incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const V y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) s_ws[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V run = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      const V x = s_ws[k];
+      s_ws[k] = run;
+      run += x;
+    }
+    s_ws[NT / 64] = run;
+  }
+  __syncthreads();
+  const V r = s_ws[wave] + incl - v;
+  *total = s_ws[NT / 64];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan, in place, of a[0..n) by one workgroup of NT threads, each
+// taking a contiguous run; returns the total.
+template <int NT, typename V>
+__device__ V block_scan_runs(V* a, int64_t n) {
+  __shared__ V s_ws[NT / 64 + 1];
+  const int64_t per = (n + NT - 1) / NT;
+  const int64_t r0 = min(n, (int64_t)threadIdx.x * per), r1 = min(n, r0 + per);
+  V local = 0;
+  for (int64_t k = r0; k < r1; ++k) local += a[k];
+  V total;
+  V run = block_scan<NT, V>(local, s_ws, &total);
+  for (int64_t k = r0; k < r1; ++k) {
+    const V x = a[k];
+    a[k] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <int NT, typename V, typename Op>
+__device__ V block_reduce(V v, Op op) {
+  __shared__ V s_red[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  V r = s_red[0];
+  for (int k = 1; k < NT / 64; ++k) r = op(r, s_red[k]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ B by buckets
+// One workgroup: bucket histogram of B's codes, each term's rank in its
+// bucket, bucket starts; also clears the per-range counters of this call and
+// finds B's largest |coefficient|.
+template <typename T>
+__global__ void __launch_bounds__(SORT_BLOCK) k_rg_bsort(RangeArgs R) {
+  extern __shared__ int32_t hist[];
+  const int tid = threadIdx.x;
+  for (int64_t k = tid; k < R.nbkB; k += SORT_BLOCK) hist[k] = 0;
+  for (int64_t r = tid; r < R.nr; r += SORT_BLOCK) {
+    R.rcount[r] = 0;
+    R.rterms[r] = 0;
+  }
+  __syncthreads();
+  uint64_t mx = 0;
+  uint32_t err = 0;
+  for (int64_t j = tid; j < R.nb; j += SORT_BLOCK) {
+    int64_t c = R.bk_in[j];
+    if (c < 0 || c > R.maxB) {
+      err |= ERR_RANGE;
+      c = c < 0 ? 0 : R.maxB;
+    }
+    R.brank[j] = atomicAdd(&hist[c >> R.shiftB], 1);
+    if constexpr (std::is_same<T, int64_t>::value)
+      mx = max(mx, uabs(static_cast<const int64_t*>(R.bc_in)[j]));
+  }
+  __syncthreads();
+  const int64_t per = (R.nbkB + SORT_BLOCK - 1) / SORT_BLOCK;
+  const int64_t k0 = min(R.nbkB, (int64_t)tid * per), k1 = min(R.nbkB, k0 + per);
+  int64_t local = 0;
+  for (int64_t k = k0; k < k1; ++k) local += hist[k];
+  __shared__ int64_t s_ws[SORT_BLOCK / 64 + 1];
+  int64_t total;
+  int64_t run = block_scan<SORT_BLOCK, int64_t>(local, s_ws, &total);
+  for (int64_t k = k0; k < k1; ++k) {
+    R.bstart[k] = (int32_t)run;
+    run += hist[k];
+  }
+  if (tid == 0) R.bstart[R.nbkB] = (int32_t)total;
+  mx = block_reduce<SORT_BLOCK>(mx, [](uint64_t x, uint64_t y) { return x > y ? x : y; });
+  err = block_reduce<SORT_BLOCK>(err, [](uint32_t x, uint32_t y) { return x | y; });
+  if (tid == 0) {
+    R.meta->bmax = mx;
+    if (err) atomicOr(&R.meta->err, err);
+  }
+}
+
+__global__ void __launch_bounds__(SMALL_BLOCK) k_rg_bplace(RangeArgs R) {
+  const int64_t j = (int64_t)blockIdx.x * SMALL_BLOCK + threadIdx.x;
+  if (j >= R.nb) return;
+  const int64_t c = R.bk_in[j];
+  const int64_t cc = c < 0 ? 0 : c > R.maxB ? R.maxB : c;
+  const int64_t at = R.bstart[cc >> R.shiftB] + R.brank[j];
+  R.bk[at] = c;
+  R.bc[at] = static_cast<const uint64_t*>(R.bc_in)[j];
+  if (R.b_tb) R.b_tb[at] = R.b_tb_in[j];
+}
+
+// ------------------------------------------------------------ counting
+// Products per range, as an upper bound (whole buckets): one workgroup per
+// (range, row split).  The first range also checks A's codes and finds A's
+// largest |coefficient|.
+template <typename T>
+__global__ void __launch_bounds__(SMALL_BLOCK) k_rg_count0(RangeArgs R) {
+  const int64_t r = blockIdx.x, s = blockIdx.y;
+  const int64_t lo = r << R.w, hi = min(R.nkeys, (r + 1) << R.w);
+  const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
+  int64_t sum = 0;
+  uint64_t mx = 0;
+  uint32_t err = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += SMALL_BLOCK) {
+    const int64_t a = R.ak[i];
+    if (r == 0) {
+      if (a < 0 || a > R.maxA) err |= ERR_RANGE;
+      if constexpr (std::is_same<T, int64_t>::value)
+        mx = max(mx, uabs(static_cast<const int64_t*>(R.ac)[i]));
+    }
+    int64_t j0, j1;
+    if (row_interval(R, a, lo, hi, &j0, &j1)) sum += j1 - j0;
+  }
+  sum = block_reduce<SMALL_BLOCK>(sum, [](int64_t x, int64_t y) { return x + y; });
+  if (threadIdx.x == 0 && sum)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&R.rcount[r]), (unsigned long long)sum);
+  if (r == 0) {
+    mx = block_reduce<SMALL_BLOCK>(mx, [](uint64_t x, uint64_t y) { return x > y ? x : y; });
+    err = block_reduce<SMALL_BLOCK>(err, [](uint32_t x, uint32_t y) { return x | y; });
+    if (threadIdx.x == 0) {
+      atomicMax(&R.meta->amax, mx);
+      if (err) atomicOr(&R.meta->err, err);
+    }
+  }
+}
+
+// One workgroup: bin bits of each range (bins of about 2^target_log
+// products), first bin of each range, the range of each bin, and whether
+// int64 entries fit in 8 bytes (every product below 2^(63 - w) in size).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_rg_plan(RangeArgs R) {
+  __shared__ int s_cut;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_cut = 0;
+  __syncthreads();
+  const int64_t per = (R.nr + 1023) / 1024;
+  const int64_t r0 = min(R.nr, (int64_t)tid * per), r1 = min(R.nr, r0 + per);
+  const int lmax = min(R.max_l2, R.w);
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t c = R.rcount[r];
+    int l2 = 0;
+    while (l2 < lmax && ((int64_t)1 << (R.target_log + l2)) < c) ++l2;
+    R.rl2[r] = l2;
+  }
+  // fewer bits everywhere while the bins would outgrow their arrays
+  int64_t total = 0;
+  __shared__ int64_t s_ws[1024 / 64 + 1];
+  for (int pass = 0; pass <= RG_MAX_L2; ++pass) {
+    int64_t local = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+      int l2 = R.rl2[r] - s_cut;
+      local += (int64_t)1 << (l2 < 0 ? 0 : l2);
+    }
+    int64_t run = block_scan<1024, int64_t>(local, s_ws, &total);
+    if (total <= R.nbins_max) {
+      for (int64_t r = r0; r < r1; ++r) {
+        int l2 = R.rl2[r] - s_cut;
+        l2 = l2 < 0 ? 0 : l2;
+        R.rl2[r] = l2;
+        R.rbin0[r] = run;
+        for (int64_t k = 0; k < ((int64_t)1 << l2); ++k) R.bin_range[run + k] = (int32_t)r;
+        run += (int64_t)1 << l2;
+      }
+      break;
+    }
+    __syncthreads();
+    if (tid == 0) ++s_cut;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    R.rbin0[R.nr] = total;
+    R.meta->nbins = total;
+    uint32_t pack = 0;
+    if constexpr (std::is_same<T, int64_t>::value) {
+      const uint64_t am = R.meta->amax, bm = R.meta->bmax;
+      const uint64_t lim = 1ull << (63 - R.w);
+      pack = (__umul64hi(am, bm) == 0 && am * bm < lim) ? 1u : 0u;
+    }
+    R.meta->pack = pack;
+  }
+}
+
+// The products of (range r, rows of split s) one thread at a time: rows of A
+// with a stride of the workgroup, each against its interval of B.
+template <typename T>
+struct RowWalk {
+  int64_t i, i1, j, j1, a, lo, hi;
+  T ca;
+  int32_t sa;
+  bool done;
+
+  __device__ __forceinline__ void start(const RangeArgs& R, int64_t first, int64_t end,
+                                        int64_t l, int64_t h) {
+    i = first - RG_BLOCK;
+    i1 = end;
+    lo = l;
+    hi = h;
+    j = j1 = 0;
+    done = false;
+  }
+  // Moves to the next row with a nonempty interval (or sets done).
+  __device__ __forceinline__ void next_row(const RangeArgs& R) {
+    for (;;) {
+      i += RG_BLOCK;
+      if (i >= i1) {
+        done = true;
+        return;
+      }
+      a = R.ak[i];
+      if (row_interval(R, a, lo, hi, &j, &j1)) {
+        ca = static_cast<const T*>(R.ac)[i];
+        sa = R.a_sa ? R.a_sa[i] : INT_MAX;
+        return;
+      }
+    }
+  }
+  // The next candidate: false when the walk is over; otherwise *ok tells
+  // whether it is a product of this range (code in range, kept by the
+  // truncation, nonzero), with its hash and value.
+  __device__ __forceinline__ bool next(const RangeArgs& R, int w, uint64_t mult, bool* ok,
+                                       uint64_t* h, T* v) {
+    while (!done && j >= j1) next_row(R);
+    if (done) return false;
+    const int64_t jj = j++;
+    const int64_t c = a + R.bk[jj];
+    *ok = false;
+    if (c < lo || c >= hi) return true;
+    if (R.b_tb && R.b_tb[jj] > sa) return true;
+    *v = mul_value(ca, from_bits<T>(R.bc[jj]));
+    if (*v == T(0)) return true;
+    *h = ((uint64_t)(c - lo) * mult) & wmask(w);
+    *ok = true;
+    return true;
+  }
+};
+
+// Entries per (bin, split) of each range.
+template <typename T>
+__global__ void __launch_bounds__(RG_BLOCK) k_rg_count1(RangeArgs R) {
+  __shared__ uint32_t hist[1 << RG_MAX_L2];
+  const int64_t r = blockIdx.x, s = blockIdx.y;
+  const int l2 = R.rl2[r];
+  const int nbin = 1 << l2;
+  for (int k = threadIdx.x; k < nbin; k += RG_BLOCK) hist[k] = 0;
+  __syncthreads();
+  const int64_t lo = r << R.w, hi = min(R.nkeys, (r + 1) << R.w);
+  const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
+  RowWalk<T> g;
+  g.start(R, i0 + threadIdx.x, i1, lo, hi);
+  bool ok;
+  uint64_t h = 0;
+  T v{};
+  while (g.next(R, R.w, R.mult, &ok, &h, &v))
+    if (ok) atomicAdd(&hist[bin_of(h, R.w, l2)], 1u);
+  __syncthreads();
+  const int64_t b0 = R.rbin0[r];
+  for (int k = threadIdx.x; k < nbin; k += RG_BLOCK)
+    R.cnt[(b0 + k) * R.nsplit + s] = hist[k];
+}
+
+// One workgroup per range: offsets of every (bin, split) within the range,
+// each bin's first entry and size, and the range's entries.
+__global__ void __launch_bounds__(1024) k_rg_scan1(RangeArgs R) {
+  const int64_t r = blockIdx.x;
+  const int64_t b0 = R.rbin0[r], nbin = R.rbin0[r + 1] - b0;
+  int64_t* c = R.cnt + b0 * R.nsplit;
+  const int64_t total = block_scan_runs<1024, int64_t>(c, nbin * R.nsplit);
+  for (int64_t k = threadIdx.x; k < nbin; k += 1024) {
+    const int64_t off = c[k * R.nsplit];
+    const int64_t end = k + 1 < nbin ? c[(k + 1) * R.nsplit] : total;
+    R.bin_off[b0 + k] = off;
+    R.bin_cnt[b0 + k] = end - off;
+  }
+  if (threadIdx.x == 0) R.rtotal[r] = total;
+}
+
+// One workgroup: first entry of each range, the number of entries, and
+// whether each range's terms can take its entry slots in the result.
+__global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
+  const int64_t per = (R.nr + 1023) / 1024;
+  const int64_t r0 = min(R.nr, (int64_t)threadIdx.x * per), r1 = min(R.nr, r0 + per);
+  int64_t local = 0;
+  for (int64_t r = r0; r < r1; ++r) local += R.rtotal[r];
+  __shared__ int64_t s_ws[1024 / 64 + 1];
+  int64_t total;
+  int64_t run = block_scan<1024, int64_t>(local, s_ws, &total);
+  for (int64_t r = r0; r < r1; ++r) {
+    R.rbase[r] = run;
+    run += R.rtotal[r];
+  }
+  if (threadIdx.x == 0) {
+    R.meta->entries = total;
+    R.meta->reserve = total <= R.out_cap ? 1u : 0u;
+  }
+}
+
+// ------------------------------------------------------------ grouping
+// The products of (range r, rows of split s), in chunks of RG_PER per thread:
+// each chunk is counting-sorted by bin through LDS and written as contiguous
+// runs after this workgroup's earlier runs in each bin.
+template <typename T>
+__global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
+  __shared__ uint4 stage[RG_STAGE];
+  __shared__ int64_t base[1 << RG_MAX_L2];
+  __shared__ uint32_t coff[1 << RG_MAX_L2];
+  __shared__ uint32_t s_ws[RG_BLOCK / 64 + 1];
+  const int tid = threadIdx.x;
+  const int64_t r = blockIdx.x, s = blockIdx.y;
+  const int l2 = R.rl2[r];
+  const int nbin = 1 << l2;
+  const int w = R.w;
+  const uint64_t mult = R.mult;
+  const bool pack = R.meta->pack != 0;
+  const int64_t b0 = R.rbin0[r], rb = R.rbase[r];
+  for (int k = tid; k < nbin; k += RG_BLOCK) {
+    base[k] = rb + R.cnt[(b0 + k) * R.nsplit + s];
+    coff[k] = 0;
+  }
+  __syncthreads();
+  const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
+  const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
+  RowWalk<T> g;
+  g.start(R, i0 + tid, i1, lo, hi);
+  uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
+  uint4* ent16 = static_cast<uint4*>(R.ent);
+  for (;;) {
+    uint64_t hh[RG_PER], vb[RG_PER];
+    uint32_t bn[RG_PER], rank[RG_PER];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < RG_PER; ++u) {
+      bool ok = false;
+      uint64_t h = 0;
+      T v{};
+      if (!g.next(R, w, mult, &ok, &h, &v)) break;
+      if (!ok) continue;
+      hh[u] = h;
+      vb[u] = to_bits(v);
+      bn[u] = bin_of(h, w, l2);
+      rank[u] = atomicAdd(&coff[bn[u]], 1u);
+      mask |= 1u << u;
+    }
+    __syncthreads();
+    const uint32_t mine = tid < nbin ? coff[tid] : 0u;
+    uint32_t total;
+    const uint32_t off = block_scan<RG_BLOCK, uint32_t>(mine, s_ws, &total);
+    if (tid < nbin) coff[tid] = off;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RG_PER; ++u)
+      if ((mask >> u) & 1u)
+        stage[coff[bn[u]] + rank[u]] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32),
+                                                  (uint32_t)vb[u], (uint32_t)(vb[u] >> 32));
+    __syncthreads();
+    for (uint32_t t = tid; t < total; t += RG_BLOCK) {
+      const uint4 e = stage[t];
+      const uint64_t h = ((uint64_t)e.y << 32) | e.x;
+      const uint32_t k = bin_of(h, w, l2);
+      const int64_t at = base[k] + (t - coff[k]);
+      if (pack) {
+        const uint64_t v = ((uint64_t)e.w << 32) | e.z;
+        ent8[at] = (v << w) | h;
+      } else {
+        ent16[at] = e;
+      }
+    }
+    __syncthreads();
+    if (tid < nbin) {
+      base[tid] += mine;
+      coff[tid] = 0;
+    }
+    if (!__syncthreads_or(!g.done)) break;
+  }
+}
+
+// ------------------------------------------------------------ bins
+template <typename T>
+__device__ __forceinline__ void entry_at(const RangeArgs& R, bool pack, int w, int64_t k,
+                                         uint64_t* h, T* v) {
+  if (pack) {
+    const uint64_t e = static_cast<const uint64_t*>(R.ent)[k];
+    *h = e & wmask(w);
+    *v = from_bits<T>((uint64_t)((int64_t)e >> w));
+  } else {
+    const uint4 e = static_cast<const uint4*>(R.ent)[k];
+    *h = ((uint64_t)e.y << 32) | e.x;
+    *v = from_bits<T>(((uint64_t)e.w << 32) | e.z);
+  }
+}
+
+__device__ __forceinline__ void lds_add(int64_t* p, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+
+// Workgroups loop over bins (a fixed grid, each taking every gridDim-th bin):
+// a bin's entries go into an LDS table (key = hash + 1, linear probing from a
+// second hash of the key), then its nonzero terms go to the result.
+template <typename T, int LOG>
+__global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
+  constexpr int SLOTS = 1 << LOG, NT = SLOTS / BIN_PER;
+  __shared__ unsigned long long keys[SLOTS];
+  __shared__ uint64_t vwords[SLOTS];
+  T* vals = reinterpret_cast<T*>(vwords);
+  __shared__ int64_t s_wave[NT / 64];
+  __shared__ int64_t s_base;
+  __shared__ int s_over, s_sp;
+  __shared__ unsigned long long s_lo[STACK], s_hi[STACK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = R.w;
+  const bool pack = R.meta->pack != 0;
+  const bool reserve = R.meta->reserve != 0;
+  const int64_t nbins = R.meta->nbins;
+  T* out_c = static_cast<T*>(R.out_c);
+  const int nx = R.dec.nx;
+  const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
+  const uint64_t inv = R.inv, mw = wmask(w);
+  int64_t ins = 0, extra = 0;   // statistics: insertions, slots visited past the first
+  for (int i = tid; i < SLOTS; i += NT) {
+    keys[i] = 0;
+    vals[i] = T(0);
+  }
+  __syncthreads();
+  for (int64_t b = blockIdx.x; b < nbins; b += gridDim.x) {
+    const int64_t n = R.bin_cnt[b];
+    if (n == 0) continue;
+    const int64_t r = R.bin_range[b];
+    const int64_t s = R.rbase[r] + R.bin_off[b], e = s + n;
+    const int64_t lo = r << w;
+    // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over
+    const auto insert = [&](uint64_t h, T v, uint64_t ilo, uint64_t ihi) {
+      if (h < ilo || h > ihi) return;
+      const unsigned long long key = h + 1;
+      uint32_t slot = (uint32_t)((h * GOLD) >> (64 - LOG));
+      for (int q = 0; q < SLOTS; ++q) {
+        unsigned long long c = keys[slot];
+        if (c == 0) {
+          c = atomicCAS(&keys[slot], 0ull, key);
+          if (c == 0) c = key;
+        }
+        if (c == key) {
+          lds_add(&vals[slot], v);
+          ++ins;
+          extra += q;
+          return;
+        }
+        slot = (slot + 1) & (SLOTS - 1);
+      }
+      s_over = 1;
+    };
+    // compacts the table, writes its nonzero terms, and leaves it cleared
+    const auto emit = [&]() {
+      unsigned long long kk[BIN_PER];
+      T vv[BIN_PER];
+      uint64_t ball[BIN_PER];
+      int64_t cnt = 0;
+#pragma unroll
+      for (int u = 0; u < BIN_PER; ++u) {
+        const int i = u * NT + tid;
+        kk[u] = keys[i];
+        vv[u] = vals[i];
+        ball[u] = __ballot(kk[u] != 0 && vv[u] != T(0));
+        cnt += __popcll(ball[u]);
+      }
+      if (lane == 0) s_wave[wave] = cnt;
+      __syncthreads();
+      int64_t tot = 0, pos = 0;
+      for (int k = 0; k < NT / 64; ++k) {
+        if (k == wave) pos = tot;
+        tot += s_wave[k];
+      }
+      if (tid == 0) {
+        unsigned long long* ctr =
+            reserve ? reinterpret_cast<unsigned long long*>(&R.rterms[r])
+                    : reinterpret_cast<unsigned long long*>(&R.meta->out_count);
+        const int64_t off = tot ? (int64_t)atomicAdd(ctr, (unsigned long long)tot) : 0;
+        s_base = reserve ? R.rbase[r] + off : off;
+      }
+      const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+      for (int u = 0; u < BIN_PER; ++u) {
+        if (ball[u] & (1ull << lane)) {
+          const int64_t q = pos + __popcll(ball[u] & lt);
+          keys[q] = kk[u];
+          vals[q] = vv[u];
+        }
+        pos += __popcll(ball[u]);
+      }
+      __syncthreads();
+      const int64_t base = s_base;
+      const int64_t m = min(tot, R.out_cap - base);
+      for (int64_t t = tid; t < m; t += NT) {
+        const int64_t q = base + t;
+        const uint64_t code = (uint64_t)lo + (((keys[t] - 1) * inv) & mw);
+        if (R.out_x) {
+          uint64_t c = code;
+          if (pairs) {
+            int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
+            for (int v = 0; v < nx; v += 2) {
+              const int32_t x0 = decode_step(R.dec, v, c);
+              o[v >> 1] = make_int2(x0, decode_step(R.dec, v + 1, c));
+            }
+          } else {
+            for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
+          }
+        } else {
+          R.out_k[q] = (int64_t)code;
+        }
+        out_c[q] = vals[t];
+      }
+      __syncthreads();
+      for (int i = tid; i < SLOTS; i += NT) {
+        keys[i] = 0;
+        vals[i] = T(0);
+      }
+      __syncthreads();
+    };
+    // the bin's first BIN_PER entries per thread, loaded at once (indices
+    // past the bin repeat its last entry, unused)
+    uint64_t h0[BIN_PER];
+    T v0[BIN_PER];
+#pragma unroll
+    for (int u = 0; u < BIN_PER; ++u)
+      entry_at(R, pack, w, min(s + tid + (int64_t)u * NT, e - 1), &h0[u], &v0[u]);
+    if (tid == 0) s_over = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BIN_PER; ++u)
+      if (s + tid + (int64_t)u * NT < e) insert(h0[u], v0[u], 0, ~0ull);
+    for (int64_t k = s + tid + (int64_t)BIN_PER * NT; k < e; k += NT) {
+      uint64_t h;
+      T v;
+      entry_at(R, pack, w, k, &h, &v);
+      insert(h, v, 0, ~0ull);
+    }
+    __syncthreads();
+    if (!s_over) {
+      emit();
+      continue;
+    }
+    // More distinct codes than slots: the bin again, one hash interval at a
+    // time, halving an interval whose codes overflow the table.
+    for (int i = tid; i < SLOTS; i += NT) {
+      keys[i] = 0;
+      vals[i] = T(0);
+    }
+    uint64_t mn = ~0ull, mx = 0;
+    for (int64_t k = s + tid; k < e; k += NT) {
+      uint64_t h;
+      T v;
+      entry_at(R, pack, w, k, &h, &v);
+      mn = h < mn ? h : mn;
+      mx = h > mx ? h : mx;
+    }
+    mn = block_reduce<NT>(mn, [](uint64_t x, uint64_t y) { return x < y ? x : y; });
+    mx = block_reduce<NT>(mx, [](uint64_t x, uint64_t y) { return x > y ? x : y; });
+    if (tid == 0) {
+      s_lo[0] = mn;
+      s_hi[0] = mx;
+      s_sp = 1;
+    }
+    __syncthreads();
+    while (s_sp > 0) {
+      const uint64_t ilo = s_lo[s_sp - 1], ihi = s_hi[s_sp - 1];
+      __syncthreads();
+      if (tid == 0) {
+        s_over = 0;
+        --s_sp;
+      }
+      __syncthreads();
+      for (int64_t k = s + tid; k < e; k += NT) {
+        uint64_t h;
+        T v;
+        entry_at(R, pack, w, k, &h, &v);
+        insert(h, v, ilo, ihi);
+      }
+      __syncthreads();
+      if (s_over) {
+        // the upper half is pushed first, so the lower half runs next
+        if (tid == 0) {
+          const uint64_t mid = ilo + (ihi - ilo) / 2;
+          s_lo[s_sp] = mid + 1;
+          s_hi[s_sp] = ihi;
+          s_lo[s_sp + 1] = ilo;
+          s_hi[s_sp + 1] = mid;
+          s_sp += 2;
+        }
+        __syncthreads();
+        for (int i = tid; i < SLOTS; i += NT) {
+          keys[i] = 0;
+          vals[i] = T(0);
+        }
+        __syncthreads();
+      } else {
+        emit();
+      }
+    }
+  }
+  if (R.stats) {
+    for (int off = 32; off > 0; off >>= 1) {
+      ins += __shfl_xor(ins, off);
+      extra += __shfl_xor(extra, off);
+    }
+    if (lane == 0) {
+      atomicAdd(&R.stats[0], (unsigned long long)ins);
+      atomicAdd(&R.stats[1], (unsigned long long)extra);
+    }
+  }
+}
+
+// ------------------------------------------------------------ contiguous result
+// One workgroup: the number of result terms N, and for each range the empty
+// slots below N and the terms at N or beyond (prefix sums over ranges).
+__global__ void __launch_bounds__(1024) k_rg_fixscan(RangeArgs R) {
+  if (!R.meta->reserve) return;
+  const int64_t per = (R.nr + 1023) / 1024;
+  const int64_t r0 = min(R.nr, (int64_t)threadIdx.x * per), r1 = min(R.nr, r0 + per);
+  int64_t t = 0;
+  for (int64_t r = r0; r < r1; ++r) t += R.rterms[r];
+  const int64_t N = block_reduce<1024>(t, [](int64_t x, int64_t y) { return x + y; });
+  int64_t hl = 0, al = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t S = R.rbase[r], T_ = R.rterms[r], P = R.rtotal[r];
+    hl += S + T_ < N ? min(S + P, N) - (S + T_) : 0;
+    al += S + T_ > N ? S + T_ - max(S, N) : 0;
+  }
+  __shared__ int64_t s_ws[1024 / 64 + 1];
+  int64_t htot, atot;
+  int64_t hrun = block_scan<1024, int64_t>(hl, s_ws, &htot);
+  int64_t arun = block_scan<1024, int64_t>(al, s_ws, &atot);
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t S = R.rbase[r], T_ = R.rterms[r], P = R.rtotal[r];
+    R.rhole[r] = hrun;
+    R.rabove[r] = arun;
+    hrun += S + T_ < N ? min(S + P, N) - (S + T_) : 0;
+    arun += S + T_ > N ? S + T_ - max(S, N) : 0;
+  }
+  if (threadIdx.x == 0) {
+    R.rhole[R.nr] = htot;
+    R.rabove[R.nr] = atot;
+    R.meta->out_count = N;
+    if (htot != atot) atomicOr(&R.meta->err, 1u);   // cannot happen: reported as a device error
+  }
+}
+
+// The terms at N or beyond move, in range order, into the empty slots below
+// N, in range order.
+template <typename T>
+__global__ void __launch_bounds__(SMALL_BLOCK) k_rg_fixmove(RangeArgs R) {
+  if (!R.meta->reserve) return;
+  const int64_t N = R.meta->out_count;
+  const int nx = R.dec.nx;
+  T* out_c = static_cast<T*>(R.out_c);
+  for (int64_t r = blockIdx.x; r < R.nr; r += gridDim.x) {
+    const int64_t S = R.rbase[r], end = S + R.rterms[r];
+    const int64_t from = max(S, N);
+    if (end <= from) continue;
+    for (int64_t p = from + threadIdx.x; p < end; p += SMALL_BLOCK) {
+      const int64_t k = R.rabove[r] + (p - from);
+      // the range whose empty slots hold rank k: the last r' with rhole[r'] <= k
+      int64_t a = 0, z = R.nr;   // rhole[a] <= k < rhole[z]
+      while (z - a > 1) {
+        const int64_t m = (a + z) / 2;
+        if (R.rhole[m] <= k) a = m;
+        else z = m;
+      }
+      const int64_t q = R.rbase[a] + R.rterms[a] + (k - R.rhole[a]);
+      if (R.out_x) {
+        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = R.out_x[p * nx + v];
+      } else {
+        R.out_k[q] = R.out_k[p];
+      }
+      out_c[q] = out_c[p];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_typed(const RangeArgs& R, hipStream_t s) {
+  const dim3 grid((unsigned)R.nr, (unsigned)R.nsplit);
+  if (R.ev0) (void)hipEventRecord(R.ev0, s);
+  hipLaunchKernelGGL(k_rg_bsort<T>, dim3(1), dim3(SORT_BLOCK), (size_t)R.nbkB * 4, s, R);
+  if (R.nb > 0)
+    hipLaunchKernelGGL(k_rg_bplace, dim3((unsigned)((R.nb + SMALL_BLOCK - 1) / SMALL_BLOCK)),
+                       dim3(SMALL_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_count0<T>, grid, dim3(SMALL_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_plan<T>, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_count1<T>, grid, dim3(RG_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_scan1, dim3((unsigned)R.nr), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_scan2, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_scatter<T>, grid, dim3(RG_BLOCK), 0, s, R);
+  // a fixed grid of bin workgroups: a few per compute unit
+  const dim3 bins((unsigned)std::min<int64_t>(R.nbins_max, 256 * 16));
+  if (R.bin_log >= 13)
+    hipLaunchKernelGGL((k_rg_bins<T, 13>), bins, dim3((1 << 13) / BIN_PER), 0, s, R);
+  else if (R.bin_log == 12)
+    hipLaunchKernelGGL((k_rg_bins<T, 12>), bins, dim3((1 << 12) / BIN_PER), 0, s, R);
+  else
+    hipLaunchKernelGGL((k_rg_bins<T, 11>), bins, dim3((1 << 11) / BIN_PER), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fixscan, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fixmove<T>, dim3((unsigned)std::min<int64_t>(R.nr, 1024)),
+                     dim3(SMALL_BLOCK), 0, s, R);
+  if (R.ev1) (void)hipEventRecord(R.ev1, s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t range_setup() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rg_bsort<int64_t>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(DENSE_MAX_BUCKETS * 4));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rg_bsort<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(DENSE_MAX_BUCKETS * 4));
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+hipError_t launch_range(const RangeArgs& R, kp_dtype dt, hipStream_t s) {
+  if (R.na == 0 || R.nb == 0 || R.nr == 0) return hipSuccess;
+  hipError_t e = range_setup();
+  if (e != hipSuccess) return e;
+  return dt == KP_F64 ? launch_typed<double>(R, s) : launch_typed<int64_t>(R, s);
+}
+
+}  // namespace kp

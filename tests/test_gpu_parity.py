@@ -345,15 +345,11 @@ def test_partitioned_bin_tables(slots):
     check_poisson(pa, pb, f"poisson hash, bins of {slots}", mode="hash")
 
 
-@pytest.mark.parametrize("slots", [2048, 4096, 8192])
-def test_partitioned_full_bin_is_a_capacity_error(slots):
-    """Univariate codes whose multiplicative hash (code times the 64-bit
-    golden-ratio constant) has its top three bits zero all fall in bin 0
-    while the product has at most 4 bins; slots + 1000 of them overflow that
-    bin's table: reported as a capacity error, not hung, and the next product
-    is unaffected."""
-    ctx = kp.context()
-    ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots)
+def _adversarial(slots):
+    """Univariate factors whose product codes, under the two-level hash
+    grouping (code times the 64-bit golden-ratio constant), all have their top
+    three bits zero: slots + 1000 distinct codes in the first of at most 4
+    bins."""
     rng = np.random.default_rng(slots)
     e = np.unique(rng.integers(1, 1 << 31, 1 << 20, dtype=np.int64))
     with np.errstate(over="ignore"):
@@ -362,13 +358,59 @@ def test_partitioned_full_bin_is_a_capacity_error(slots):
     assert len(e) == slots + 999
     a = (np.concatenate([[0], e]).astype(np.int32).reshape(-1, 1), np.ones(slots + 1000, np.int64))
     b = (np.zeros((1, 1), np.int32), np.ones(1, np.int64))
-    say("partitioned capacity error,", slots + 1000, "codes in one bin of", slots, "slots")
+    return a, b
+
+
+@pytest.mark.parametrize("slots", [2048, 4096, 8192])
+def test_two_level_grouping_full_bin_is_a_capacity_error(slots):
+    """With the two-level hash grouping forced, the adversarial codes overflow
+    one bin's table: reported as a capacity error, not hung, and the next
+    product is unaffected."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots, hash_grouping=1)
+    a, b = _adversarial(slots)
+    say("two-level grouping capacity error,", slots + 1000, "codes in one bin of", slots, "slots")
     with pytest.raises(kp.KPError) as err:
         gpu_laurent(a, b, "hash", ctx)
     assert err.value.status == kp.KP_E_CAPACITY
     ctx.sync_check()
     a2, b2 = I.config(3, scale=0.03)
     check_laurent(a2, b2, "hash", f"after the capacity error, bins of {slots}", ctx)
+
+
+@pytest.mark.parametrize("slots", [2048, 4096, 8192])
+def test_range_grouping_recovers_from_full_bins(slots):
+    """Grouped by code range (the default), the same adversarial codes give
+    the oracle's product in auto mode.  With at most one bin per range
+    (hash_max_bin_bits = 0) every bin of the sparse products holds several
+    tables' worth of distinct codes, overflows, and is redone one hash
+    interval at a time: still the oracle's product, int64 and fp64."""
+    ctx = kp.context()
+    ctx.set_tune(hash_bin_slots=slots)
+    a, b = _adversarial(slots)
+    check_laurent(a, b, "auto", f"adversarial codes grouped by range, bins of {slots}", ctx)
+    ctx.set_tune(hash_max_bin_bits=0)
+    a, b = I.config(3, scale=0.1)
+    check_laurent(a, b, "hash", f"one bin per range, bins of {slots}", ctx)
+    check_laurent((a[0], a[1].astype(np.float64) / 4), (b[0], b[1].astype(np.float64)), "hash",
+                  f"one bin per range, fp64, bins of {slots}", ctx)
+
+
+@pytest.mark.parametrize("grouping", [0, 1])
+@pytest.mark.parametrize("cfg,scale,fp", [(3, 0.1, False), (3, 0.05, True), (2, 0.2, False),
+                                          (1, 1.0, True)])
+def test_grouped_hash_matches_oracle(grouping, cfg, scale, fp):
+    """Both groupings of the hash products against the oracle: the highly
+    sparse product (few collisions: each range's terms fill its own slots,
+    the few beyond the count are moved), the simplex forced into hash mode
+    (many products per code: more entries than result slots, so a shared
+    counter places the terms), and the small box."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_grouping=grouping)
+    a, b = I.config(cfg, scale=scale)
+    if fp:
+        a, b = (a[0], a[1].astype(np.float64) * 0.75), (b[0], b[1].astype(np.float64))
+    check_laurent(a, b, "hash", f"grouped {grouping}, config {cfg} x{scale}", ctx)
 
 
 def test_repeat_runs_bit_identical():
@@ -735,10 +777,11 @@ def _trunc_cases():
     return out
 
 
-@pytest.mark.parametrize("mode,part", [("dense", 0), ("hash", 0), ("hash", 2)])
-def test_truncated_products_match_oracle(mode, part):
+@pytest.mark.parametrize("mode,part,grouping", [("dense", 0, 0), ("hash", 0, 0), ("hash", 2, 0),
+                                                ("hash", 2, 1)])
+def test_truncated_products_match_oracle(mode, part, grouping):
     ctx = kp.context()
-    ctx.set_tune(hash_partitioned=part)
+    ctx.set_tune(hash_partitioned=part, hash_grouping=grouping)
     for what, a, b, w, D in _trunc_cases():
         if mode == "dense" and "sparse" in what:
             continue
@@ -753,13 +796,13 @@ def test_truncated_products_match_oracle(mode, part):
             assert_exact([ge], gc, [oe], oc, what)
 
 
-@pytest.mark.parametrize("part", [0, 2])
+@pytest.mark.parametrize("part", [0, 2, 3])
 def test_truncation_keeps_few_or_no_pairs(part):
     """A degree limit below every pair's degree gives the empty product; one a
     little above the smallest keeps a handful of pairs (the grouped layout
     then chooses its fewest level-2 bins).  Against the oracle's filter."""
     ctx = kp.context()
-    ctx.set_tune(hash_partitioned=part)
+    ctx.set_tune(hash_partitioned=min(part, 2), hash_grouping=1 if part == 3 else 0)
     a, b = I.config(3, scale=0.03)
     da, db = a[0].sum(1).min(), b[0].sum(1).min()
     for D, what in ((int(da + db) - 1, "no pair kept"), (int(da + db) + 25, "a few pairs kept")):

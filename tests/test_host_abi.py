@@ -235,7 +235,8 @@ def test_tune_validation():
                 dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1),
                 dict(hash_partitioned=3), dict(hash_partitioned=-1), dict(hash_bucket=-1),
                 dict(hash_bucket=17), dict(hash_order=2), dict(hash_bin_slots=0),
-                dict(hash_bin_slots=3000), dict(hash_bin_slots=16384)):
+                dict(hash_bin_slots=3000), dict(hash_bin_slots=16384), dict(hash_grouping=2),
+                dict(hash_max_bin_bits=11), dict(hash_max_bin_bits=-1)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
     assert t.hash_bucket == 0 and t.hash_order == 1 and t.hash_bin_slots == 4096
@@ -245,15 +246,22 @@ def test_tune_validation():
 
 
 def test_partitioned_hash_workspace():
-    """Partitioned hash mode keeps every product (16 bytes, twice); the
-    global table two 16-byte slots per bounded result term.  Auto takes the
-    partitioned one only when the products are at most 4x the bound."""
+    """Grouped by code range (the default for Laurent int64/fp64), hash mode
+    keeps every product once (at most 16 bytes) plus small per-range and
+    per-bin arrays; grouped by two levels of hash bits, twice (16 bytes each)
+    plus a 2-byte bin id; the global table two 16-byte slots per bounded
+    result term.  Auto takes a grouped layout only when the products are at
+    most 4x the bound."""
     ctx = _host_ctx()
     sparse = kp.layout_product(6, 0, [0] * 6, [80] * 6, [0] * 6, [80] * 6)
     box = kp.layout_product(3, 0, [-5] * 3, [5] * 3, [-5] * 3, [5] * 3)
     na = nb = 3000
     _, mo, ws_auto = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
-    assert mo == na * nb and ws_auto >= 32 * na * nb
+    assert mo == na * nb and 16 * na * nb <= ws_auto < 17 * na * nb
+    ctx.set_tune(hash_grouping=1)
+    _, _, ws_two = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
+    assert ws_two >= 34 * na * nb
+    ctx.set_tune(hash_grouping=0)
     ctx.set_tune(hash_partitioned=0)
     _, _, ws_table = kp.mul_bound(sparse, False, kp.KP_I64, "hash", na, nb, ctx)
     assert 32 * na * nb <= ws_table < 33 * na * nb
@@ -262,7 +270,7 @@ def test_partitioned_hash_workspace():
     assert kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)[2] == ws_box_table
     ctx.set_tune(hash_partitioned=2)
     _, _, ws_box_part = kp.mul_bound(box, False, kp.KP_I64, "hash", 500, 500, ctx)
-    assert mo_box == 21 ** 3 and ws_box_part >= 32 * 500 * 500 > ws_box_table
+    assert mo_box == 21 ** 3 and ws_box_part >= 16 * 500 * 500 > ws_box_table
 
 
 def test_bucketed_hash_workspace():
@@ -316,3 +324,18 @@ def test_to_pyint_round_trip():
                      np.int64)
     assert kp.to_pyint(words) == vals
     assert O.wide_to_int(words) == vals
+
+
+def test_hash_plans_of_empty_and_tiny_products():
+    """Workspace planning of hash products whose key space is empty, a single
+    code or tiny, in both groupings (no launch)."""
+    ctx = _host_ctx()
+    empty = kp.layout_product(2, 0, [0, 0], [-1, -1], [0, 0], [3, 3])
+    one = kp.layout_product(1, 0, [0], [0], [0], [0])
+    small = kp.layout_product(2, 0, [0, 0], [3, 1], [0, 0], [2, 2])
+    for grouping in (0, 1):
+        ctx.set_tune(hash_partitioned=2, hash_grouping=grouping)
+        for lay, na, nb in ((empty, 0, 5), (empty, 5, 0), (one, 1, 1), (one, 7, 3), (small, 1, 1),
+                            (small, 300, 2)):
+            m, mo, ws = kp.mul_bound(lay, False, kp.KP_I64, "hash", na, nb, ctx)
+            assert m == "hash" and 0 <= mo <= max(na * nb, 0) and ws >= 0
