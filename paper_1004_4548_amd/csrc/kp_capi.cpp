@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <climits>
 #include <cstring>
 #include <mutex>
@@ -296,7 +297,8 @@ struct Plan {
   bool range = false;
   int rw = 0;
   int64_t rnr = 0, rnsplit = 1, rrows = 0, rbins = 0, rnbk = 0;
-  int rshift = 0, rtarget = 10;
+  int rshift = 0;
+  int64_t rtarget = 1;
 };
 
 // Truncation tables: slack of A's terms and degree of B's (input order),
@@ -449,9 +451,10 @@ void carve_poisson_dense(Carver& c, int64_t na, int64_t nb, PoissonDenseBufs* q)
 
 struct RangeCarve {
   int64_t* bk; uint64_t* bc; int32_t* b_tb; int32_t* brank; int32_t* bstart;
-  int64_t* rcount; int32_t* rl2; int64_t* rbin0; int64_t* rtotal; int64_t* rbase;
-  int64_t* rterms; int64_t* rhole; int64_t* rabove; int64_t* cnt;
-  int32_t* bin_range; int64_t* bin_off; int64_t* bin_cnt; void* ent;
+  int64_t* rcount; int32_t* rnb; int64_t* rbin0; int64_t* rtotal; int64_t* rbase;
+  int64_t* rhole; int64_t* rabove; int64_t* cnt;
+  int32_t* bin_range; int64_t* bin_start; int64_t* bin_terms; int64_t* bhole; int64_t* babove;
+  void* ent;
 };
 
 struct HashCarve {
@@ -504,14 +507,18 @@ void range_shape(const kp_layout* L, int64_t na, int64_t nb, int64_t nprod, int 
   p->rnsplit = std::min<int64_t>(p->rnsplit, std::max<int64_t>(1, na));
   p->rrows = (na + p->rnsplit - 1) / p->rnsplit;
   p->blog = bin_slots == 8192 ? 13 : bin_slots == 4096 ? 12 : 11;
-  p->rtarget = p->blog - 1;
+  // products per bin: about 0.42 of the table's slots (the bound on products
+  // exceeds them by a few percent), so that linear probing stays short
+  p->rtarget = (int64_t)(0.42 * (double)((int64_t)1 << p->blog));
   p->nprod = std::max<int64_t>(nprod, 1);
   // bins: at most two per 2^rtarget products (bucket granularity adds a few
   // candidates per row and range) plus one per range
-  const double cand = (double)nprod + 4.0 * (double)na * (double)p->rnr;
+  // (a range's bins are its bound on products over rtarget, rounded up; the
+  // bound exceeds the products by a few terms of B per row and range)
+  const double cand = (double)nprod + (double)na * (double)p->rnr;
   const int bb = std::max(0, std::min(10, max_bin_bits));
   p->rbins = std::min<int64_t>(p->rnr << bb,
-                               p->rnr + 2 * (int64_t)std::ceil(cand / (double)((int64_t)1 << p->rtarget)));
+                               p->rnr + (int64_t)std::ceil(cand / (double)p->rtarget));
   p->rbins = std::max<int64_t>(p->rbins, p->rnr);
   const int64_t maxB = factor_maxcode(L, 1);
   p->rshift = dense_bucket_shift(maxB, nb);
@@ -537,17 +544,18 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     g.brank = c.take<int32_t>(nb);
     g.bstart = c.take<int32_t>(p.rnbk + 1);
     g.rcount = c.take<int64_t>(p.rnr);
-    g.rl2 = c.take<int32_t>(p.rnr);
+    g.rnb = c.take<int32_t>(p.rnr);
     g.rbin0 = c.take<int64_t>(p.rnr + 1);
     g.rtotal = c.take<int64_t>(p.rnr);
     g.rbase = c.take<int64_t>(p.rnr);
-    g.rterms = c.take<int64_t>(p.rnr);
     g.rhole = c.take<int64_t>(p.rnr + 1);
     g.rabove = c.take<int64_t>(p.rnr + 1);
     g.cnt = c.take<int64_t>((size_t)(p.rbins * p.rnsplit));
     g.bin_range = c.take<int32_t>(p.rbins);
-    g.bin_off = c.take<int64_t>(p.rbins);
-    g.bin_cnt = c.take<int64_t>(p.rbins);
+    g.bin_start = c.take<int64_t>(p.rbins + 1);
+    g.bin_terms = c.take<int64_t>(p.rbins);
+    g.bhole = c.take<int64_t>(p.rbins);
+    g.babove = c.take<int64_t>(p.rbins);
     g.ent = c.take<uint4>((size_t)p.nprod);
   } else if (p.radix) {
     const int64_t P1 = (int64_t)1 << p.l1, bins = P1 << p.l2;
@@ -684,8 +692,9 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                (ctx->tune.hash_partitioned == 2 ||
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
+    // (a wavefront scans the interval lengths of 64 rows in 32 bits)
     p->range = p->radix && !poisson && dt != KP_I128 && ctx->tune.hash_grouping == 0 &&
-               na < ((int64_t)1 << 31) && nb < ((int64_t)1 << 31);
+               na < ((int64_t)1 << 31) && nb <= ((int64_t)1 << 24);
     if (p->range) {
       p->radix = false;
       range_shape(L, na, nb, contrib, ctx->tune.hash_bin_slots, ctx->tune.hash_max_bin_bits, p);
@@ -722,6 +731,7 @@ DevLayout make_dev_layout(const kp_layout& L, int which) {
     d.xc[v] = L.xc[v];
     d.xmin[v] = L.xmin[v];
     d.dx[v] = make_fastdiv((uint64_t)L.xw[v]);
+    d.dx32[v] = make_fastdiv32((uint64_t)L.xw[v]);
   }
   for (int v = 0; v < L.ny; ++v) {
     d.fh[v] = which ? L.hb[v] : L.ha[v];
@@ -1195,21 +1205,22 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       R.inv = inv & mask;
       R.nsplit = p.rnsplit;
       R.rows = p.rrows;
-      R.target_log = p.rtarget;
+      R.target = p.rtarget;
       R.max_l2 = std::max(0, std::min(10, ctx->tune.hash_max_bin_bits));
       R.nbins_max = p.rbins;
       R.rcount = g.rcount;
-      R.rl2 = g.rl2;
+      R.rnb = g.rnb;
       R.rbin0 = g.rbin0;
       R.rtotal = g.rtotal;
       R.rbase = g.rbase;
-      R.rterms = g.rterms;
       R.rhole = g.rhole;
       R.rabove = g.rabove;
       R.cnt = g.cnt;
       R.bin_range = g.bin_range;
-      R.bin_off = g.bin_off;
-      R.bin_cnt = g.bin_cnt;
+      R.bin_start = g.bin_start;
+      R.bin_terms = g.bin_terms;
+      R.bhole = g.bhole;
+      R.babove = g.babove;
       R.ent = g.ent;
       R.out_k = out_codes;
       R.out_c = out_coef;

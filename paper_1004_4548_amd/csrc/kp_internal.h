@@ -48,7 +48,7 @@ inline FastDiv make_fastdiv(uint64_t d) {
   return f;
 }
 
-__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __umul64hi(a, b);
 #else
@@ -56,8 +56,38 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
 #endif
 }
 
-__host__ __device__ inline uint64_t fdiv(uint64_t n, const FastDiv& f) {
+__host__ __device__ __forceinline__ uint64_t fdiv(uint64_t n, const FastDiv& f) {
   uint64_t t = mulhi64(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// The same method for 32-bit operands (one 32-bit high multiply), for
+// divisors below 2^32.
+struct FastDiv32 {
+  uint32_t m, d;
+  uint32_t s1, s2;
+};
+
+inline FastDiv32 make_fastdiv32(uint64_t d64) {
+  FastDiv32 f{};
+  const uint64_t d = d64 ? d64 : 1;
+  if (d > 0xffffffffull) return f;   // unused: quotients of 32-bit values are then 0
+  f.d = (uint32_t)d;
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  const uint64_t num = ((l == 32 ? (1ull << 32) : (1ull << l)) - d) << 32;
+  f.m = (uint32_t)(num / d + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 0 ? l - 1 : 0;
+  return f;
+}
+
+__host__ __device__ __forceinline__ uint32_t fdiv32(uint32_t n, const FastDiv32& f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t t = __umulhi(f.m, n);
+#else
+  const uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
+#endif
   return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
@@ -76,6 +106,7 @@ struct DevLayout {
   FastDiv dx[KP_MAX_VARS];                       // divide by product width xw_k
   FastDiv dy[KP_MAX_VARS];                       // divide by 2 yh_k + 1
   FastDiv dWx;
+  FastDiv32 dx32[KP_MAX_VARS];                   // the same widths, 32-bit operands
 };
 
 DevLayout make_dev_layout(const kp_layout& L, int which);
@@ -119,11 +150,24 @@ __host__ __device__ inline uint32_t encode_term(const DevLayout& L, const int32_
 // Laurent product code -> exponents.
 // Exponent v of the code whose quotient by the widths of variables < v is q;
 // q becomes the quotient by the widths up to v.
-__host__ __device__ inline int32_t decode_step(const DevLayout& L, int v, uint64_t& q) {
+__host__ __device__ __forceinline__ int32_t decode_step(const DevLayout& L, int v, uint64_t& q) {
   const uint64_t qq = fdiv(q, L.dx[v]);
   const int32_t e = (int32_t)((int64_t)(q - qq * L.dx[v].d) + L.xmin[v]);
   q = qq;
   return e;
+}
+
+// decode_step with a 32-bit division once the quotient fits in 32 bits
+// (widths below 2^32).
+__host__ __device__ __forceinline__ int32_t decode_step_fast(const DevLayout& L, int v, uint64_t& q) {
+  if ((q >> 32) == 0 && L.dx32[v].d != 0) {
+    const uint32_t q32 = (uint32_t)q;
+    const uint32_t qq = fdiv32(q32, L.dx32[v]);
+    const int32_t e = (int32_t)((int64_t)(q32 - qq * L.dx32[v].d) + L.xmin[v]);
+    q = qq;
+    return e;
+  }
+  return decode_step(L, v, q);
 }
 
 __host__ __device__ inline void decode_x(const DevLayout& L, uint64_t q, int32_t* e) {
@@ -447,21 +491,22 @@ struct RangeArgs {
   int64_t nkeys; int w; int64_t nr;              // ranges of 2^w codes, nr of them
   uint64_t mult, inv;                            // odd multiplier mod 2^w and its inverse
   int64_t nsplit, rows;                          // row splits of A, rows per split
-  int target_log;                                // log2 of the products wanted per bin
-  int max_l2;                                    // most bin bits of one range
+  int64_t target;                                // products wanted per bin
+  int max_l2;                                    // at most 2^max_l2 bins per range
   int64_t nbins_max;
   int64_t* rcount;   // [nr] product bound per range (bucket granularity)
-  int32_t* rl2;      // [nr] bin bits of each range
+  int32_t* rnb;      // [nr] bins of each range
   int64_t* rbin0;    // [nr + 1] first bin of each range
   int64_t* rtotal;   // [nr] entries of each range
   int64_t* rbase;    // [nr] first entry (and first result slot) of each range
-  int64_t* rterms;   // [nr] result terms written for each range
-  int64_t* rhole;    // [nr + 1] prefix of the empty slots before the result count
-  int64_t* rabove;   // [nr + 1] prefix of the terms past the result count
+  int64_t* rhole;    // [nr + 1] empty slots below the result count, per range, then prefix
+  int64_t* rabove;   // [nr + 1] terms at the result count or beyond, per range, then prefix
   int64_t* cnt;      // [nbins_max * nsplit] entries per (bin, split), then offsets in the range
   int32_t* bin_range;  // [nbins_max]
-  int64_t* bin_off;    // [nbins_max] first entry of each bin within its range
-  int64_t* bin_cnt;    // [nbins_max]
+  int64_t* bin_start;  // [nbins_max + 1] first entry of each bin (absolute once scattered)
+  int64_t* bin_terms;  // [nbins_max] result terms of each bin
+  int64_t* bhole;      // [nbins_max] prefix of the bins' empty slots below the count, in a range
+  int64_t* babove;     // [nbins_max] prefix of the bins' terms past the count, in a range
   void* ent;         // entries: 8 bytes (packed) or 16 bytes each
   int64_t* out_k; void* out_c; int64_t out_cap;
   int32_t* out_x; DevLayout dec;   // optional decoded output instead of codes

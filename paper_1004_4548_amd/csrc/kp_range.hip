@@ -42,8 +42,6 @@ namespace {
 
 constexpr uint64_t GOLD = 0x9E3779B97F4A7C15ull;   // 2^64 / golden ratio (Fibonacci hashing)
 constexpr int RG_BLOCK = 1024;    // threads of the counting and scatter workgroups
-constexpr int RG_PER = 8;         // products per thread per staged chunk
-constexpr int RG_STAGE = RG_BLOCK * RG_PER;
 constexpr int RG_MAX_L2 = 10;     // at most 1024 bins per range
 constexpr int SORT_BLOCK = 1024;
 constexpr int SMALL_BLOCK = 256;
@@ -89,8 +87,10 @@ __device__ __forceinline__ bool row_interval(const RangeArgs& R, int64_t a, int6
   return *j0 < *j1;
 }
 
-__device__ __forceinline__ uint32_t bin_of(uint64_t h, int w, int l2) {
-  return l2 ? (uint32_t)(h >> (w - l2)) : 0u;
+// Bin of hash h among nb bins of its range: floor(h nb / 2^w), so that every
+// bin of a range covers an equal share of the hash values.
+__device__ __forceinline__ uint32_t bin_of(uint64_t h, int w, uint32_t nb) {
+  return w ? (uint32_t)__umul64hi(h << (64 - w), (uint64_t)nb) : 0u;
 }
 
 // Exclusive scan of one value per thread over a workgroup of NT threads.
@@ -161,10 +161,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_rg_bsort(RangeArgs R) {
   extern __shared__ int32_t hist[];
   const int tid = threadIdx.x;
   for (int64_t k = tid; k < R.nbkB; k += SORT_BLOCK) hist[k] = 0;
-  for (int64_t r = tid; r < R.nr; r += SORT_BLOCK) {
-    R.rcount[r] = 0;
-    R.rterms[r] = 0;
-  }
+  for (int64_t r = tid; r < R.nr; r += SORT_BLOCK) R.rcount[r] = 0;
   __syncthreads();
   uint64_t mx = 0;
   uint32_t err = 0;
@@ -245,9 +242,9 @@ __global__ void __launch_bounds__(SMALL_BLOCK) k_rg_count0(RangeArgs R) {
   }
 }
 
-// One workgroup: bin bits of each range (bins of about 2^target_log
-// products), first bin of each range, the range of each bin, and whether
-// int64 entries fit in 8 bytes (every product below 2^(63 - w) in size).
+// One workgroup: the bins of each range (about `target` products each, from
+// the range's bound on products), first bin of each range, and whether int64
+// entries fit in 8 bytes (every product below 2^(63 - w) in size).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_rg_plan(RangeArgs R) {
   __shared__ int s_cut;
@@ -256,31 +253,25 @@ __global__ void __launch_bounds__(1024) k_rg_plan(RangeArgs R) {
   __syncthreads();
   const int64_t per = (R.nr + 1023) / 1024;
   const int64_t r0 = min(R.nr, (int64_t)tid * per), r1 = min(R.nr, r0 + per);
-  const int lmax = min(R.max_l2, R.w);
+  // at most 2^max_l2 bins, and no more bins than hash values
+  const int64_t most = min((int64_t)1 << R.max_l2, (int64_t)1 << min(R.w, 30));
   for (int64_t r = r0; r < r1; ++r) {
     const int64_t c = R.rcount[r];
-    int l2 = 0;
-    while (l2 < lmax && ((int64_t)1 << (R.target_log + l2)) < c) ++l2;
-    R.rl2[r] = l2;
+    R.rnb[r] = (int32_t)max((int64_t)1, min(most, (c + R.target - 1) / R.target));
   }
-  // fewer bits everywhere while the bins would outgrow their arrays
+  // half as many bins everywhere while the bins would outgrow their arrays
   int64_t total = 0;
   __shared__ int64_t s_ws[1024 / 64 + 1];
   for (int pass = 0; pass <= RG_MAX_L2; ++pass) {
     int64_t local = 0;
-    for (int64_t r = r0; r < r1; ++r) {
-      int l2 = R.rl2[r] - s_cut;
-      local += (int64_t)1 << (l2 < 0 ? 0 : l2);
-    }
+    for (int64_t r = r0; r < r1; ++r) local += max(1, R.rnb[r] >> s_cut);
     int64_t run = block_scan<1024, int64_t>(local, s_ws, &total);
     if (total <= R.nbins_max) {
       for (int64_t r = r0; r < r1; ++r) {
-        int l2 = R.rl2[r] - s_cut;
-        l2 = l2 < 0 ? 0 : l2;
-        R.rl2[r] = l2;
+        const int nb = max(1, R.rnb[r] >> s_cut);
+        R.rnb[r] = nb;
         R.rbin0[r] = run;
-        for (int64_t k = 0; k < ((int64_t)1 << l2); ++k) R.bin_range[run + k] = (int32_t)r;
-        run += (int64_t)1 << l2;
+        run += nb;
       }
       break;
     }
@@ -301,53 +292,117 @@ __global__ void __launch_bounds__(1024) k_rg_plan(RangeArgs R) {
   }
 }
 
-// The products of (range r, rows of split s) one thread at a time: rows of A
-// with a stride of the workgroup, each against its interval of B.
+// ------------------------------------------------------------ expansion
+// A wavefront takes rows of A 64 at a time (lane l holds one row): the rows'
+// intervals of B are found together, their lengths scanned, and the row data
+// staged in LDS.  The candidates of the 64 rows are then taken 64 at a time,
+// lane l holding candidate k = base + l: its row m is the last with
+// pre[m] <= k (a binary search over the staged prefix), its term of B is
+// jb[m] + k.  Every lane has work and the loads of B are coalesced, whatever
+// the rows' interval lengths.
+constexpr int WAVES = RG_BLOCK / 64;
+
+struct WaveRows {
+  int32_t pre[65];    // exclusive prefix of the rows' interval lengths; pre[64] = total
+  int32_t sa[64];     // truncation slack of each row
+  int64_t jb[64];     // first term of B of row m, minus pre[m]
+  int64_t a[64];      // code of row m
+  uint64_t ca[64];    // coefficient bits of row m
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront's walk over its batches of rows in (range, split).
 template <typename T>
-struct RowWalk {
-  int64_t i, i1, j, j1, a, lo, hi;
-  T ca;
-  int32_t sa;
+struct WaveWalk {
+  int64_t row0, row1;   // rows of the split
+  int64_t lo, hi;       // the range's codes
+  int64_t bt;           // current batch (rows row0 + 64 bt ..)
+  int32_t kb, total;    // next candidate and candidates of the batch
   bool done;
 
-  __device__ __forceinline__ void start(const RangeArgs& R, int64_t first, int64_t end,
-                                        int64_t l, int64_t h) {
-    i = first - RG_BLOCK;
-    i1 = end;
+  __device__ __forceinline__ void start(int64_t r0, int64_t r1, int64_t l, int64_t h, int wave) {
+    row0 = r0;
+    row1 = r1;
     lo = l;
     hi = h;
-    j = j1 = 0;
+    bt = wave - WAVES;
+    kb = total = 0;
     done = false;
   }
-  // Moves to the next row with a nonempty interval (or sets done).
-  __device__ __forceinline__ void next_row(const RangeArgs& R) {
+  // Stages the next batch with at least one candidate (or sets done).
+  __device__ __forceinline__ void next_batch(const RangeArgs& R, WaveRows& W) {
+    const int lane = threadIdx.x & 63;
     for (;;) {
-      i += RG_BLOCK;
-      if (i >= i1) {
+      bt += WAVES;
+      const int64_t first = row0 + 64 * bt;
+      if (first >= row1) {
         done = true;
         return;
       }
-      a = R.ak[i];
-      if (row_interval(R, a, lo, hi, &j, &j1)) {
-        ca = static_cast<const T*>(R.ac)[i];
-        sa = R.a_sa ? R.a_sa[i] : INT_MAX;
+      const int64_t i = first + lane;
+      int64_t j0 = 0, j1 = 0, a = 0;
+      uint64_t ca = 0;
+      int32_t sa = INT_MAX;
+      if (i < row1) {
+        a = R.ak[i];
+        if (row_interval(R, a, lo, hi, &j0, &j1)) {
+          ca = static_cast<const uint64_t*>(R.ac)[i];
+          if (R.a_sa) sa = R.a_sa[i];
+        } else {
+          j0 = j1 = 0;
+        }
+      }
+      const int32_t cnt = (int32_t)(j1 - j0);
+      int32_t incl = cnt;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      const int32_t excl = incl - cnt;
+      const int32_t tot = __shfl(incl, 63);
+      wave_sync();
+      W.pre[lane] = excl;
+      if (lane == 63) W.pre[64] = tot;
+      W.jb[lane] = j0 - excl;
+      W.a[lane] = a;
+      W.ca[lane] = ca;
+      W.sa[lane] = sa;
+      wave_sync();
+      if (tot > 0) {
+        kb = 0;
+        total = tot;
         return;
       }
     }
   }
-  // The next candidate: false when the walk is over; otherwise *ok tells
-  // whether it is a product of this range (code in range, kept by the
-  // truncation, nonzero), with its hash and value.
-  __device__ __forceinline__ bool next(const RangeArgs& R, int w, uint64_t mult, bool* ok,
-                                       uint64_t* h, T* v) {
-    while (!done && j >= j1) next_row(R);
+  // The lane's candidate of the next 64: false once the walk is over (for
+  // the whole wavefront); *ok tells whether the lane holds a product of the
+  // range (code in range, kept by the truncation, nonzero value).
+  __device__ __forceinline__ bool step(const RangeArgs& R, WaveRows& W, int w, uint64_t mult,
+                                       bool* ok, uint64_t* h, T* v) {
+    if (!done && kb >= total) next_batch(R, W);
     if (done) return false;
-    const int64_t jj = j++;
-    const int64_t c = a + R.bk[jj];
+    const int32_t k = kb + (threadIdx.x & 63);
+    kb += 64;
     *ok = false;
+    if (k >= total) return true;
+    int m = 0, z = 64;   // pre[m] <= k < pre[z]
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int mid = (m + z) >> 1;
+      if (W.pre[mid] <= k) m = mid;
+      else z = mid;
+    }
+    const int64_t j = W.jb[m] + k;
+    const int64_t c = W.a[m] + R.bk[j];
     if (c < lo || c >= hi) return true;
-    if (R.b_tb && R.b_tb[jj] > sa) return true;
-    *v = mul_value(ca, from_bits<T>(R.bc[jj]));
+    if (R.b_tb && R.b_tb[j] > W.sa[m]) return true;
+    *v = mul_value(from_bits<T>(W.ca[m]), from_bits<T>(R.bc[j]));
     if (*v == T(0)) return true;
     *h = ((uint64_t)(c - lo) * mult) & wmask(w);
     *ok = true;
@@ -359,44 +414,44 @@ struct RowWalk {
 template <typename T>
 __global__ void __launch_bounds__(RG_BLOCK) k_rg_count1(RangeArgs R) {
   __shared__ uint32_t hist[1 << RG_MAX_L2];
+  __shared__ WaveRows rows[WAVES];
   const int64_t r = blockIdx.x, s = blockIdx.y;
-  const int l2 = R.rl2[r];
-  const int nbin = 1 << l2;
-  for (int k = threadIdx.x; k < nbin; k += RG_BLOCK) hist[k] = 0;
+  const uint32_t nbin = (uint32_t)R.rnb[r];
+  for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK) hist[k] = 0;
   __syncthreads();
   const int64_t lo = r << R.w, hi = min(R.nkeys, (r + 1) << R.w);
   const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
-  RowWalk<T> g;
-  g.start(R, i0 + threadIdx.x, i1, lo, hi);
+  const int wave = threadIdx.x >> 6;
+  WaveWalk<T> g;
+  g.start(i0, i1, lo, hi, wave);
   bool ok;
   uint64_t h = 0;
   T v{};
-  while (g.next(R, R.w, R.mult, &ok, &h, &v))
-    if (ok) atomicAdd(&hist[bin_of(h, R.w, l2)], 1u);
+  while (g.step(R, rows[wave], R.w, R.mult, &ok, &h, &v))
+    if (ok) atomicAdd(&hist[bin_of(h, R.w, nbin)], 1u);
   __syncthreads();
   const int64_t b0 = R.rbin0[r];
-  for (int k = threadIdx.x; k < nbin; k += RG_BLOCK)
+  for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK)
     R.cnt[(b0 + k) * R.nsplit + s] = hist[k];
 }
 
 // One workgroup per range: offsets of every (bin, split) within the range,
-// each bin's first entry and size, and the range's entries.
+// each bin's first entry (within the range) and range, and the range's
+// entries.
 __global__ void __launch_bounds__(1024) k_rg_scan1(RangeArgs R) {
   const int64_t r = blockIdx.x;
   const int64_t b0 = R.rbin0[r], nbin = R.rbin0[r + 1] - b0;
   int64_t* c = R.cnt + b0 * R.nsplit;
   const int64_t total = block_scan_runs<1024, int64_t>(c, nbin * R.nsplit);
   for (int64_t k = threadIdx.x; k < nbin; k += 1024) {
-    const int64_t off = c[k * R.nsplit];
-    const int64_t end = k + 1 < nbin ? c[(k + 1) * R.nsplit] : total;
-    R.bin_off[b0 + k] = off;
-    R.bin_cnt[b0 + k] = end - off;
+    R.bin_start[b0 + k] = c[k * R.nsplit];   // within the range; made absolute by the scatter
+    R.bin_range[b0 + k] = (int32_t)r;
   }
   if (threadIdx.x == 0) R.rtotal[r] = total;
 }
 
 // One workgroup: first entry of each range, the number of entries, and
-// whether each range's terms can take its entry slots in the result.
+// whether the result terms can take the entry slots of their bins.
 __global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
   const int64_t per = (R.nr + 1023) / 1024;
   const int64_t r0 = min(R.nr, (int64_t)threadIdx.x * per), r1 = min(R.nr, r0 + per);
@@ -412,23 +467,27 @@ __global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
   if (threadIdx.x == 0) {
     R.meta->entries = total;
     R.meta->reserve = total <= R.out_cap ? 1u : 0u;
+    R.bin_start[R.meta->nbins] = total;
   }
 }
 
 // ------------------------------------------------------------ grouping
-// The products of (range r, rows of split s), in chunks of RG_PER per thread:
-// each chunk is counting-sorted by bin through LDS and written as contiguous
-// runs after this workgroup's earlier runs in each bin.
+// The products of (range r, rows of split s), STEPS candidates per lane per
+// chunk: each chunk is counting-sorted by bin through LDS and written as
+// contiguous runs after this workgroup's earlier runs in each bin.
+constexpr int RG_STEPS = 4;
+constexpr int RG_CHUNK = RG_BLOCK * RG_STEPS;
+
 template <typename T>
 __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
-  __shared__ uint4 stage[RG_STAGE];
+  __shared__ uint4 stage[RG_CHUNK];
+  __shared__ WaveRows rows[WAVES];
   __shared__ int64_t base[1 << RG_MAX_L2];
   __shared__ uint32_t coff[1 << RG_MAX_L2];
   __shared__ uint32_t s_ws[RG_BLOCK / 64 + 1];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
   const int64_t r = blockIdx.x, s = blockIdx.y;
-  const int l2 = R.rl2[r];
-  const int nbin = 1 << l2;
+  const int nbin = R.rnb[r];
   const int w = R.w;
   const uint64_t mult = R.mult;
   const bool pack = R.meta->pack != 0;
@@ -436,28 +495,29 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
   for (int k = tid; k < nbin; k += RG_BLOCK) {
     base[k] = rb + R.cnt[(b0 + k) * R.nsplit + s];
     coff[k] = 0;
+    if (s == 0) R.bin_start[b0 + k] += rb;   // the bins' first entries, absolute
   }
   __syncthreads();
   const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
   const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
-  RowWalk<T> g;
-  g.start(R, i0 + tid, i1, lo, hi);
+  WaveWalk<T> g;
+  g.start(i0, i1, lo, hi, wave);
   uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
   uint4* ent16 = static_cast<uint4*>(R.ent);
   for (;;) {
-    uint64_t hh[RG_PER], vb[RG_PER];
-    uint32_t bn[RG_PER], rank[RG_PER];
+    uint64_t hh[RG_STEPS], vb[RG_STEPS];
+    uint32_t bn[RG_STEPS], rank[RG_STEPS];
     uint32_t mask = 0;
 #pragma unroll
-    for (int u = 0; u < RG_PER; ++u) {
+    for (int u = 0; u < RG_STEPS; ++u) {
       bool ok = false;
       uint64_t h = 0;
       T v{};
-      if (!g.next(R, w, mult, &ok, &h, &v)) break;
+      if (!g.step(R, rows[wave], w, mult, &ok, &h, &v)) break;
       if (!ok) continue;
       hh[u] = h;
       vb[u] = to_bits(v);
-      bn[u] = bin_of(h, w, l2);
+      bn[u] = bin_of(h, w, (uint32_t)nbin);
       rank[u] = atomicAdd(&coff[bn[u]], 1u);
       mask |= 1u << u;
     }
@@ -468,7 +528,7 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
     if (tid < nbin) coff[tid] = off;
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < RG_PER; ++u)
+    for (int u = 0; u < RG_STEPS; ++u)
       if ((mask >> u) & 1u)
         stage[coff[bn[u]] + rank[u]] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32),
                                                   (uint32_t)vb[u], (uint32_t)(vb[u] >> 32));
@@ -476,7 +536,7 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
     for (uint32_t t = tid; t < total; t += RG_BLOCK) {
       const uint4 e = stage[t];
       const uint64_t h = ((uint64_t)e.y << 32) | e.x;
-      const uint32_t k = bin_of(h, w, l2);
+      const uint32_t k = bin_of(h, w, (uint32_t)nbin);
       const int64_t at = base[k] + (t - coff[k]);
       if (pack) {
         const uint64_t v = ((uint64_t)e.w << 32) | e.z;
@@ -495,28 +555,38 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
 }
 
 // ------------------------------------------------------------ bins
-template <typename T>
-__device__ __forceinline__ void entry_at(const RangeArgs& R, bool pack, int w, int64_t k,
-                                         uint64_t* h, T* v) {
-  if (pack) {
-    const uint64_t e = static_cast<const uint64_t*>(R.ent)[k];
-    *h = e & wmask(w);
-    *v = from_bits<T>((uint64_t)((int64_t)e >> w));
-  } else {
-    const uint4 e = static_cast<const uint4*>(R.ent)[k];
-    *h = ((uint64_t)e.y << 32) | e.x;
-    *v = from_bits<T>(((uint64_t)e.w << 32) | e.z);
-  }
-}
-
 __device__ __forceinline__ void lds_add(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
-// Workgroups loop over bins (a fixed grid, each taking every gridDim-th bin):
-// a bin's entries go into an LDS table (key = hash + 1, linear probing from a
-// second hash of the key), then its nonzero terms go to the result.
+// Entry k: its hash and value, from the 8-byte packed form (value above the
+// w hash bits) or the 16-byte one.
+// The load takes 16 bytes at a stride of 8 or 16 whatever the form (no branch
+// around it, so that a thread's loads are all in flight together; the 8
+// bytes past a packed entry lie inside the entry array, which is sized for
+// 16-byte entries).
+template <typename T>
+__device__ __forceinline__ void entry_at(const RangeArgs& R, bool pack, int w, int64_t k,
+                                         uint64_t* h, T* v) {
+  const uint4 e = *reinterpret_cast<const uint4*>(static_cast<const char*>(R.ent) +
+                                                  k * (pack ? 8 : 16));
+  const uint64_t lo64 = ((uint64_t)e.y << 32) | e.x;
+  if (pack) {
+    *h = lo64 & wmask(w);
+    *v = from_bits<T>((uint64_t)((int64_t)lo64 >> w));
+  } else {
+    *h = lo64;
+    *v = from_bits<T>(((uint64_t)e.w << 32) | e.z);
+  }
+}
+
+// One workgroup per bin: the bin's entries go into an LDS table (key = hash
+// + 1, linear probing from a second hash of the key); the table is compacted
+// in LDS and the nonzero terms are written one per thread with every lane
+// busy, from the bin's first entry slot on (the slots of its entries) or,
+// when the entries outnumber the result slots, at an offset taken from the
+// call's counter.
 template <typename T, int LOG>
 __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   constexpr int SLOTS = 1 << LOG, NT = SLOTS / BIN_PER;
@@ -527,138 +597,138 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   __shared__ int64_t s_base;
   __shared__ int s_over, s_sp;
   __shared__ unsigned long long s_lo[STACK], s_hi[STACK];
+  const int64_t b = blockIdx.x;
+  if (b >= R.meta->nbins) return;
+  const int64_t s = R.bin_start[b], e = R.bin_start[b + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (s == e) {
+    if (tid == 0) R.bin_terms[b] = 0;
+    return;
+  }
   const int w = R.w;
   const bool pack = R.meta->pack != 0;
   const bool reserve = R.meta->reserve != 0;
-  const int64_t nbins = R.meta->nbins;
-  T* out_c = static_cast<T*>(R.out_c);
-  const int nx = R.dec.nx;
-  const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
-  const uint64_t inv = R.inv, mw = wmask(w);
-  int64_t ins = 0, extra = 0;   // statistics: insertions, slots visited past the first
+  const int64_t lo = (int64_t)R.bin_range[b] << w;
+  // the bin's first BIN_PER entries per thread, loaded at once (indices past
+  // the bin repeat its last entry, unused: no branch per load)
+  uint64_t h0[BIN_PER];
+  T v0[BIN_PER];
+#pragma unroll
+  for (int u = 0; u < BIN_PER; ++u)
+    entry_at(R, pack, w, min(s + tid + (int64_t)u * NT, e - 1), &h0[u], &v0[u]);
   for (int i = tid; i < SLOTS; i += NT) {
     keys[i] = 0;
     vals[i] = T(0);
   }
+  if (tid == 0) s_over = 0;
   __syncthreads();
-  for (int64_t b = blockIdx.x; b < nbins; b += gridDim.x) {
-    const int64_t n = R.bin_cnt[b];
-    if (n == 0) continue;
-    const int64_t r = R.bin_range[b];
-    const int64_t s = R.rbase[r] + R.bin_off[b], e = s + n;
-    const int64_t lo = r << w;
-    // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over
-    const auto insert = [&](uint64_t h, T v, uint64_t ilo, uint64_t ihi) {
-      if (h < ilo || h > ihi) return;
-      const unsigned long long key = h + 1;
-      uint32_t slot = (uint32_t)((h * GOLD) >> (64 - LOG));
-      for (int q = 0; q < SLOTS; ++q) {
-        unsigned long long c = keys[slot];
-        if (c == 0) {
-          c = atomicCAS(&keys[slot], 0ull, key);
-          if (c == 0) c = key;
-        }
-        if (c == key) {
-          lds_add(&vals[slot], v);
-          ++ins;
-          extra += q;
-          return;
-        }
-        slot = (slot + 1) & (SLOTS - 1);
+  int64_t ins = 0, extra = 0;
+  // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over
+  const auto insert = [&](uint64_t h, T v, uint64_t ilo, uint64_t ihi) {
+    if (h < ilo || h > ihi) return;
+    const unsigned long long key = h + 1;
+    uint32_t slot = (uint32_t)((h * GOLD) >> (64 - LOG));
+    for (int q = 0; q < SLOTS; ++q) {
+      unsigned long long c = keys[slot];
+      if (c == 0) {
+        c = atomicCAS(&keys[slot], 0ull, key);
+        if (c == 0) c = key;
       }
-      s_over = 1;
-    };
-    // compacts the table, writes its nonzero terms, and leaves it cleared
-    const auto emit = [&]() {
-      unsigned long long kk[BIN_PER];
-      T vv[BIN_PER];
-      uint64_t ball[BIN_PER];
-      int64_t cnt = 0;
+      if (c == key) {
+        lds_add(&vals[slot], v);
+        ++ins;
+        extra += q;
+        return;
+      }
+      slot = (slot + 1) & (SLOTS - 1);
+    }
+    s_over = 1;
+  };
+  T* out_c = static_cast<T*>(R.out_c);
+  const int nx = R.dec.nx;
+  const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
+  const uint64_t inv = R.inv, mw = wmask(w);
+  // compacts the table, writes its nonzero terms after the `done` already
+  // written for this bin, leaves the table cleared; returns the count
+  const auto emit = [&](int64_t done) -> int64_t {
+    unsigned long long kk[BIN_PER];
+    T vv[BIN_PER];
+    uint64_t ball[BIN_PER];
+    int64_t cnt = 0;
 #pragma unroll
-      for (int u = 0; u < BIN_PER; ++u) {
-        const int i = u * NT + tid;
-        kk[u] = keys[i];
-        vv[u] = vals[i];
-        ball[u] = __ballot(kk[u] != 0 && vv[u] != T(0));
-        cnt += __popcll(ball[u]);
-      }
-      if (lane == 0) s_wave[wave] = cnt;
-      __syncthreads();
-      int64_t tot = 0, pos = 0;
-      for (int k = 0; k < NT / 64; ++k) {
-        if (k == wave) pos = tot;
-        tot += s_wave[k];
-      }
-      if (tid == 0) {
-        unsigned long long* ctr =
-            reserve ? reinterpret_cast<unsigned long long*>(&R.rterms[r])
-                    : reinterpret_cast<unsigned long long*>(&R.meta->out_count);
-        const int64_t off = tot ? (int64_t)atomicAdd(ctr, (unsigned long long)tot) : 0;
-        s_base = reserve ? R.rbase[r] + off : off;
-      }
-      const uint64_t lt = (1ull << lane) - 1;
+    for (int u = 0; u < BIN_PER; ++u) {
+      const int i = u * NT + tid;
+      kk[u] = keys[i];
+      vv[u] = vals[i];
+      ball[u] = __ballot(kk[u] != 0 && vv[u] != T(0));
+      cnt += __popcll(ball[u]);
+    }
+    if (lane == 0) s_wave[wave] = cnt;
+    __syncthreads();
+    int64_t tot = 0, pos = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+      if (k == wave) pos = tot;
+      tot += s_wave[k];
+    }
+    if (!reserve && tid == 0)
+      s_base = tot ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&R.meta->out_count),
+                                        (unsigned long long)tot)
+                   : 0;
+    const uint64_t lt = (1ull << lane) - 1;
 #pragma unroll
-      for (int u = 0; u < BIN_PER; ++u) {
-        if (ball[u] & (1ull << lane)) {
-          const int64_t q = pos + __popcll(ball[u] & lt);
-          keys[q] = kk[u];
-          vals[q] = vv[u];
-        }
-        pos += __popcll(ball[u]);
+    for (int u = 0; u < BIN_PER; ++u) {
+      if (ball[u] & (1ull << lane)) {
+        const int64_t q = pos + __popcll(ball[u] & lt);
+        keys[q] = kk[u];
+        vals[q] = vv[u];
       }
-      __syncthreads();
-      const int64_t base = s_base;
-      const int64_t m = min(tot, R.out_cap - base);
-      for (int64_t t = tid; t < m; t += NT) {
-        const int64_t q = base + t;
-        const uint64_t code = (uint64_t)lo + (((keys[t] - 1) * inv) & mw);
-        if (R.out_x) {
-          uint64_t c = code;
-          if (pairs) {
-            int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
-            for (int v = 0; v < nx; v += 2) {
-              const int32_t x0 = decode_step(R.dec, v, c);
-              o[v >> 1] = make_int2(x0, decode_step(R.dec, v + 1, c));
-            }
-          } else {
-            for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
+      pos += __popcll(ball[u]);
+    }
+    __syncthreads();
+    const int64_t base = reserve ? s + done : s_base;
+    const int64_t m = min(tot, R.out_cap - base);
+    for (int64_t t = tid; t < m; t += NT) {
+      const int64_t q = base + t;
+      const uint64_t code = (uint64_t)lo + (((keys[t] - 1) * inv) & mw);
+      if (R.out_x) {
+        uint64_t c = code;
+        if (pairs) {
+          int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
+          for (int v = 0; v < nx; v += 2) {
+            const int32_t x0 = decode_step_fast(R.dec, v, c);
+            o[v >> 1] = make_int2(x0, decode_step_fast(R.dec, v + 1, c));
           }
         } else {
-          R.out_k[q] = (int64_t)code;
+          for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step_fast(R.dec, v, c);
         }
-        out_c[q] = vals[t];
+      } else {
+        R.out_k[q] = (int64_t)code;
       }
-      __syncthreads();
-      for (int i = tid; i < SLOTS; i += NT) {
-        keys[i] = 0;
-        vals[i] = T(0);
-      }
-      __syncthreads();
-    };
-    // the bin's first BIN_PER entries per thread, loaded at once (indices
-    // past the bin repeat its last entry, unused)
-    uint64_t h0[BIN_PER];
-    T v0[BIN_PER];
-#pragma unroll
-    for (int u = 0; u < BIN_PER; ++u)
-      entry_at(R, pack, w, min(s + tid + (int64_t)u * NT, e - 1), &h0[u], &v0[u]);
-    if (tid == 0) s_over = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < BIN_PER; ++u)
-      if (s + tid + (int64_t)u * NT < e) insert(h0[u], v0[u], 0, ~0ull);
-    for (int64_t k = s + tid + (int64_t)BIN_PER * NT; k < e; k += NT) {
-      uint64_t h;
-      T v;
-      entry_at(R, pack, w, k, &h, &v);
-      insert(h, v, 0, ~0ull);
+      out_c[q] = vals[t];
     }
     __syncthreads();
-    if (!s_over) {
-      emit();
-      continue;
+    for (int i = tid; i < SLOTS; i += NT) {
+      keys[i] = 0;
+      vals[i] = T(0);
     }
+    __syncthreads();
+    return tot;
+  };
+#pragma unroll
+  for (int u = 0; u < BIN_PER; ++u)
+    if (s + tid + (int64_t)u * NT < e) insert(h0[u], v0[u], 0, ~0ull);
+  // bins of many products per code can hold more entries than slots
+  for (int64_t k = s + tid + (int64_t)BIN_PER * NT; k < e; k += NT) {
+    uint64_t h;
+    T v;
+    entry_at(R, pack, w, k, &h, &v);
+    insert(h, v, 0, ~0ull);
+  }
+  __syncthreads();
+  int64_t terms = 0;
+  if (!s_over) {
+    terms = emit(0);
+  } else {
     // More distinct codes than slots: the bin again, one hash interval at a
     // time, halving an interval whose codes overflow the table.
     for (int i = tid; i < SLOTS; i += NT) {
@@ -713,10 +783,11 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
         }
         __syncthreads();
       } else {
-        emit();
+        terms += emit(terms);
       }
     }
   }
+  if (tid == 0) R.bin_terms[b] = terms;
   if (R.stats) {
     for (int off = 32; off > 0; off >>= 1) {
       ins += __shfl_xor(ins, off);
@@ -730,70 +801,124 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
 }
 
 // ------------------------------------------------------------ contiguous result
-// One workgroup: the number of result terms N, and for each range the empty
-// slots below N and the terms at N or beyond (prefix sums over ranges).
-__global__ void __launch_bounds__(1024) k_rg_fixscan(RangeArgs R) {
+// Each bin's terms fill the first of its entry slots.  With N result terms,
+// the terms at N or beyond move into the empty slots below N: the k-th such
+// term (in bin order) into the k-th empty slot (in bin order).
+// One workgroup per range: the range's result terms (into rhole, as scratch).
+__global__ void __launch_bounds__(SMALL_BLOCK) k_rg_fix0(RangeArgs R) {
   if (!R.meta->reserve) return;
-  const int64_t per = (R.nr + 1023) / 1024;
-  const int64_t r0 = min(R.nr, (int64_t)threadIdx.x * per), r1 = min(R.nr, r0 + per);
+  const int64_t r = blockIdx.x;
   int64_t t = 0;
-  for (int64_t r = r0; r < r1; ++r) t += R.rterms[r];
-  const int64_t N = block_reduce<1024>(t, [](int64_t x, int64_t y) { return x + y; });
+  for (int64_t b = R.rbin0[r] + threadIdx.x; b < R.rbin0[r + 1]; b += SMALL_BLOCK)
+    t += R.bin_terms[b];
+  t = block_reduce<SMALL_BLOCK>(t, [](int64_t x, int64_t y) { return x + y; });
+  if (threadIdx.x == 0) R.rhole[r] = t;
+}
+
+// One workgroup: the number of result terms N.
+__global__ void __launch_bounds__(1024) k_rg_fixn(RangeArgs R) {
+  if (!R.meta->reserve) return;
+  int64_t t = 0;
+  for (int64_t r = threadIdx.x; r < R.nr; r += 1024) t += R.rhole[r];
+  t = block_reduce<1024>(t, [](int64_t x, int64_t y) { return x + y; });
+  if (threadIdx.x == 0) R.meta->out_count = t;
+}
+
+// One workgroup per range: each bin's empty slots below N and terms at N or
+// beyond, as prefix sums within the range, and the range's totals.
+__global__ void __launch_bounds__(SMALL_BLOCK) k_rg_fix1(RangeArgs R) {
+  if (!R.meta->reserve) return;
+  const int64_t r = blockIdx.x;
+  const int64_t N = R.meta->out_count;
+  const int64_t b0 = R.rbin0[r], nbin = R.rbin0[r + 1] - b0;
+  const int64_t per = (nbin + SMALL_BLOCK - 1) / SMALL_BLOCK;
+  const int64_t k0 = min(nbin, (int64_t)threadIdx.x * per), k1 = min(nbin, k0 + per);
+  const auto hole = [&](int64_t b) -> int64_t {
+    const int64_t S = R.bin_start[b], P = R.bin_start[b + 1] - S, T_ = R.bin_terms[b];
+    return S + T_ < N ? min(S + P, N) - (S + T_) : 0;
+  };
+  const auto above = [&](int64_t b) -> int64_t {
+    const int64_t S = R.bin_start[b], T_ = R.bin_terms[b];
+    return S + T_ > N ? S + T_ - max(S, N) : 0;
+  };
   int64_t hl = 0, al = 0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const int64_t S = R.rbase[r], T_ = R.rterms[r], P = R.rtotal[r];
-    hl += S + T_ < N ? min(S + P, N) - (S + T_) : 0;
-    al += S + T_ > N ? S + T_ - max(S, N) : 0;
+  for (int64_t k = k0; k < k1; ++k) {
+    hl += hole(b0 + k);
+    al += above(b0 + k);
   }
-  __shared__ int64_t s_ws[1024 / 64 + 1];
+  __shared__ int64_t s_ws[SMALL_BLOCK / 64 + 1];
   int64_t htot, atot;
-  int64_t hrun = block_scan<1024, int64_t>(hl, s_ws, &htot);
-  int64_t arun = block_scan<1024, int64_t>(al, s_ws, &atot);
-  for (int64_t r = r0; r < r1; ++r) {
-    const int64_t S = R.rbase[r], T_ = R.rterms[r], P = R.rtotal[r];
-    R.rhole[r] = hrun;
-    R.rabove[r] = arun;
-    hrun += S + T_ < N ? min(S + P, N) - (S + T_) : 0;
-    arun += S + T_ > N ? S + T_ - max(S, N) : 0;
+  int64_t hrun = block_scan<SMALL_BLOCK, int64_t>(hl, s_ws, &htot);
+  int64_t arun = block_scan<SMALL_BLOCK, int64_t>(al, s_ws, &atot);
+  for (int64_t k = k0; k < k1; ++k) {
+    R.bhole[b0 + k] = hrun;
+    R.babove[b0 + k] = arun;
+    hrun += hole(b0 + k);
+    arun += above(b0 + k);
   }
   if (threadIdx.x == 0) {
-    R.rhole[R.nr] = htot;
-    R.rabove[R.nr] = atot;
-    R.meta->out_count = N;
-    if (htot != atot) atomicOr(&R.meta->err, 1u);   // cannot happen: reported as a device error
+    R.rhole[r] = htot;
+    R.rabove[r] = atot;
   }
 }
 
-// The terms at N or beyond move, in range order, into the empty slots below
-// N, in range order.
+// One workgroup: prefix sums of the ranges' totals (rhole[nr], rabove[nr]:
+// all of them, which must agree).
+__global__ void __launch_bounds__(1024) k_rg_fix2(RangeArgs R) {
+  if (!R.meta->reserve) return;
+  const int64_t nr = R.nr;
+  const int64_t h = block_scan_runs<1024, int64_t>(R.rhole, nr);
+  const int64_t a = block_scan_runs<1024, int64_t>(R.rabove, nr);
+  if (threadIdx.x == 0) {
+    R.rhole[nr] = h;
+    R.rabove[nr] = a;
+    if (h != a) atomicOr(&R.meta->err, 1u);   // cannot happen: reported as a device error
+  }
+}
+
+// The moves, spread over the whole grid: the source and destination of the
+// k-th move are found by bisection over the ranges, then over the bins of
+// one range.
 template <typename T>
 __global__ void __launch_bounds__(SMALL_BLOCK) k_rg_fixmove(RangeArgs R) {
   if (!R.meta->reserve) return;
   const int64_t N = R.meta->out_count;
+  const int64_t nr = R.nr;
+  const int64_t moves = R.rabove[nr];
   const int nx = R.dec.nx;
   T* out_c = static_cast<T*>(R.out_c);
-  for (int64_t r = blockIdx.x; r < R.nr; r += gridDim.x) {
-    const int64_t S = R.rbase[r], end = S + R.rterms[r];
-    const int64_t from = max(S, N);
-    if (end <= from) continue;
-    for (int64_t p = from + threadIdx.x; p < end; p += SMALL_BLOCK) {
-      const int64_t k = R.rabove[r] + (p - from);
-      // the range whose empty slots hold rank k: the last r' with rhole[r'] <= k
-      int64_t a = 0, z = R.nr;   // rhole[a] <= k < rhole[z]
-      while (z - a > 1) {
-        const int64_t m = (a + z) / 2;
-        if (R.rhole[m] <= k) a = m;
-        else z = m;
-      }
-      const int64_t q = R.rbase[a] + R.rterms[a] + (k - R.rhole[a]);
-      if (R.out_x) {
-        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = R.out_x[p * nx + v];
-      } else {
-        R.out_k[q] = R.out_k[p];
-      }
-      out_c[q] = out_c[p];
+  // the last index g in [a, z) with pre[g] <= k, for pre ascending and pre[a] <= k
+  const auto last_le = [](const int64_t* pre, int64_t a, int64_t z, int64_t k) -> int64_t {
+    while (z - a > 1) {
+      const int64_t m = (a + z) / 2;
+      if (pre[m] <= k) a = m;
+      else z = m;
     }
+    return a;
+  };
+  for (int64_t k = (int64_t)blockIdx.x * SMALL_BLOCK + threadIdx.x; k < moves;
+       k += (int64_t)gridDim.x * SMALL_BLOCK) {
+    const int64_t rs = last_le(R.rabove, 0, nr + 1, k);
+    const int64_t ks = k - R.rabove[rs];
+    const int64_t bsrc = last_le(R.babove, R.rbin0[rs], R.rbin0[rs + 1], ks);
+    const int64_t p = max(R.bin_start[bsrc], N) + (ks - R.babove[bsrc]);
+    const int64_t rd = last_le(R.rhole, 0, nr + 1, k);
+    const int64_t kd = k - R.rhole[rd];
+    const int64_t bdst = last_le(R.bhole, R.rbin0[rd], R.rbin0[rd + 1], kd);
+    const int64_t q = R.bin_start[bdst] + R.bin_terms[bdst] + (kd - R.bhole[bdst]);
+    if (R.out_x) {
+      for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = R.out_x[p * nx + v];
+    } else {
+      R.out_k[q] = R.out_k[p];
+    }
+    out_c[q] = out_c[p];
   }
+}
+
+template <typename T, int LOG>
+void launch_bins(const RangeArgs& R, hipStream_t s) {
+  hipLaunchKernelGGL((k_rg_bins<T, LOG>), dim3((unsigned)R.nbins_max), dim3((1 << LOG) / BIN_PER), 0,
+                     s, R);
 }
 
 template <typename T>
@@ -810,17 +935,14 @@ hipError_t launch_typed(const RangeArgs& R, hipStream_t s) {
   hipLaunchKernelGGL(k_rg_scan1, dim3((unsigned)R.nr), dim3(1024), 0, s, R);
   hipLaunchKernelGGL(k_rg_scan2, dim3(1), dim3(1024), 0, s, R);
   hipLaunchKernelGGL(k_rg_scatter<T>, grid, dim3(RG_BLOCK), 0, s, R);
-  // a fixed grid of bin workgroups: a few per compute unit
-  const dim3 bins((unsigned)std::min<int64_t>(R.nbins_max, 256 * 16));
-  if (R.bin_log >= 13)
-    hipLaunchKernelGGL((k_rg_bins<T, 13>), bins, dim3((1 << 13) / BIN_PER), 0, s, R);
-  else if (R.bin_log == 12)
-    hipLaunchKernelGGL((k_rg_bins<T, 12>), bins, dim3((1 << 12) / BIN_PER), 0, s, R);
-  else
-    hipLaunchKernelGGL((k_rg_bins<T, 11>), bins, dim3((1 << 11) / BIN_PER), 0, s, R);
-  hipLaunchKernelGGL(k_rg_fixscan, dim3(1), dim3(1024), 0, s, R);
-  hipLaunchKernelGGL(k_rg_fixmove<T>, dim3((unsigned)std::min<int64_t>(R.nr, 1024)),
-                     dim3(SMALL_BLOCK), 0, s, R);
+  if (R.bin_log >= 13) launch_bins<T, 13>(R, s);
+  else if (R.bin_log == 12) launch_bins<T, 12>(R, s);
+  else launch_bins<T, 11>(R, s);
+  hipLaunchKernelGGL(k_rg_fix0, dim3((unsigned)R.nr), dim3(SMALL_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fixn, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fix1, dim3((unsigned)R.nr), dim3(SMALL_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fix2, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_rg_fixmove<T>, dim3(1024), dim3(SMALL_BLOCK), 0, s, R);
   if (R.ev1) (void)hipEventRecord(R.ev1, s);
   return hipGetLastError();
 }
