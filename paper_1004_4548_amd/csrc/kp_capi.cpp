@@ -802,6 +802,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->status), sizeof(CtxStatus));
   if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(CtxStatus));
   if (e == hipSuccess) e = dense_setup();
+  if (e == hipSuccess) e = range_setup();
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&ctx->mb), sizeof(Mailbox),
                       hipHostMallocCoherent | hipHostMallocMapped);

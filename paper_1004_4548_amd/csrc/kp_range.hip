@@ -19,13 +19,13 @@
 // value fits above the w hash bits, else 16), instead of a 16-byte table slot
 // read and written back per product in a global table.
 //
-// Result slots: the entries of range r occupy [rbase_r, rbase_r + total_r);
-// the range's terms (at most its entries) are written from rbase_r on, in
-// the order in which its bins finish (one counter per range).  The count N
-// of all terms is then known, and the few terms that lie at N or beyond are
-// moved into the empty slots below N, so the result is contiguous without a
-// counter shared by all bins.  When the entries would not fit the caller's
-// capacity, one shared counter places the terms instead.
+// Result slots: the entries of each bin occupy a run of entry positions, and
+// the bin's terms (at most its entries) are written to the first slots of
+// that run.  The count N of all terms is then known, and the few terms that
+// lie at N or beyond are moved into the empty slots below N, so the result
+// is contiguous without a counter shared by all bins.  When the entries
+// would not fit the caller's capacity, one shared counter places the terms
+// instead.
 //
 // A bin with more distinct codes than its table holds (possible only for
 // adversarial codes, since bins are sized from the product counts) is redone
@@ -382,7 +382,10 @@ struct WaveWalk {
   }
   // The lane's candidate of the next 64: false once the walk is over (for
   // the whole wavefront); *ok tells whether the lane holds a product of the
-  // range (code in range, kept by the truncation, nonzero value).
+  // range (code in range, kept by the truncation).  A product whose value is
+  // zero is kept too, so that counting needs no coefficients (its sum is
+  // dropped with the other zero sums); VAL: form the value.
+  template <bool VAL>
   __device__ __forceinline__ bool step(const RangeArgs& R, WaveRows& W, int w, uint64_t mult,
                                        bool* ok, uint64_t* h, T* v) {
     if (!done && kb >= total) next_batch(R, W);
@@ -402,8 +405,7 @@ struct WaveWalk {
     const int64_t c = W.a[m] + R.bk[j];
     if (c < lo || c >= hi) return true;
     if (R.b_tb && R.b_tb[j] > W.sa[m]) return true;
-    *v = mul_value(from_bits<T>(W.ca[m]), from_bits<T>(R.bc[j]));
-    if (*v == T(0)) return true;
+    if (VAL) *v = mul_value(from_bits<T>(W.ca[m]), from_bits<T>(R.bc[j]));
     *h = ((uint64_t)(c - lo) * mult) & wmask(w);
     *ok = true;
     return true;
@@ -427,7 +429,7 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_count1(RangeArgs R) {
   bool ok;
   uint64_t h = 0;
   T v{};
-  while (g.step(R, rows[wave], R.w, R.mult, &ok, &h, &v))
+  while (g.template step<false>(R, rows[wave], R.w, R.mult, &ok, &h, &v))
     if (ok) atomicAdd(&hist[bin_of(h, R.w, nbin)], 1u);
   __syncthreads();
   const int64_t b0 = R.rbin0[r];
@@ -513,7 +515,7 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
       bool ok = false;
       uint64_t h = 0;
       T v{};
-      if (!g.step(R, rows[wave], w, mult, &ok, &h, &v)) break;
+      if (!g.template step<true>(R, rows[wave], w, mult, &ok, &h, &v)) break;
       if (!ok) continue;
       hh[u] = h;
       vb[u] = to_bits(v);
