@@ -33,7 +33,7 @@ LDS_ATOMIC_PEAK = CUS * 16 * CLOCK_HZ          # pair accumulations per second
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-HEADLINE_PROFILE = "k_radix_highly_sparse_30k.md"
+HEADLINE_PROFILE = "k_rg_highly_sparse_30k.md"
 DENSE_PROFILE = "k_dense_mul_moderately_sparse_10k.md"
 
 
@@ -451,7 +451,7 @@ def main():
     r = measure_laurent(kp, ctx, a, b, "auto", args.steps, args.warmup)
     value = pairs / r["sec"]
     alg = 32 * pairs + 16 * r["n_out"]
-    roof = roof_hbm("grouped hash accumulation (k_radix_* sequence), whole product", alg,
+    roof = roof_hbm("range-grouped hash accumulation (k_rg_* sequence), whole product", alg,
                     r["kernel_s"], measured_traffic(HEADLINE_PROFILE),
                     "32 B per term product (a 16-byte slot read and written) + 16 B per result "
                     "term (code and coefficient)")

@@ -164,6 +164,8 @@ typedef struct kp_tune {
   int32_t hash_max_bin_bits; /* grouped by code range: at most 2^this bins per range (0..10,
                                default 10); fewer bins than the products ask for leave bins
                                that overflow their table and are redone in parts          */
+  int32_t hash_bin_fill;    /* grouped by code range: products planned per bin, in percent
+                               of the bin's table slots (10..90, default 42)              */
 } kp_tune;
 
 typedef struct kp_ctx kp_ctx;

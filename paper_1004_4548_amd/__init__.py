@@ -71,7 +71,7 @@ class Tune(C.Structure):
                 ("hash_rows", C.c_int32), ("hash_partitioned", C.c_int32),
                 ("hash_bucket", C.c_int32), ("hash_order", C.c_int32),
                 ("hash_bin_slots", C.c_int32), ("hash_grouping", C.c_int32),
-                ("hash_max_bin_bits", C.c_int32)]
+                ("hash_max_bin_bits", C.c_int32), ("hash_bin_fill", C.c_int32)]
 
 
 class MulDesc(C.Structure):

@@ -495,7 +495,7 @@ void radix_shape(int64_t na, int64_t nb, int64_t nprod, int bin_slots, Plan* p) 
 // row splits of A for about 2048 counting workgroups, bins of half a table,
 // and B's buckets (about two per term, as for dense mode).
 void range_shape(const kp_layout* L, int64_t na, int64_t nb, int64_t nprod, int bin_slots,
-                 int max_bin_bits, Plan* p) {
+                 int max_bin_bits, int fill, Plan* p) {
   int K = 0;
   while (K < 62 && ((int64_t)1 << K) < L->nkeys) ++K;
   int lr = 8;
@@ -507,9 +507,9 @@ void range_shape(const kp_layout* L, int64_t na, int64_t nb, int64_t nprod, int 
   p->rnsplit = std::min<int64_t>(p->rnsplit, std::max<int64_t>(1, na));
   p->rrows = (na + p->rnsplit - 1) / p->rnsplit;
   p->blog = bin_slots == 8192 ? 13 : bin_slots == 4096 ? 12 : 11;
-  // products per bin: about 0.42 of the table's slots (the bound on products
-  // exceeds them by a few percent), so that linear probing stays short
-  p->rtarget = (int64_t)(0.42 * (double)((int64_t)1 << p->blog));
+  // products per bin: `fill` percent of the table's slots (the bound on
+  // products exceeds them by a few percent), so that linear probing stays short
+  p->rtarget = std::max<int64_t>(1, ((int64_t)fill << p->blog) / 100);
   p->nprod = std::max<int64_t>(nprod, 1);
   // bins: at most two per 2^rtarget products (bucket granularity adds a few
   // candidates per row and range) plus one per range
@@ -697,7 +697,8 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                na < ((int64_t)1 << 31) && nb <= ((int64_t)1 << 24);
     if (p->range) {
       p->radix = false;
-      range_shape(L, na, nb, contrib, ctx->tune.hash_bin_slots, ctx->tune.hash_max_bin_bits, p);
+      range_shape(L, na, nb, contrib, ctx->tune.hash_bin_slots, ctx->tune.hash_max_bin_bits,
+                  ctx->tune.hash_bin_fill, p);
     }
     if (p->radix) {
       if (contrib > ((int64_t)1 << 36))
@@ -786,6 +787,7 @@ kp_status kp_ctx_create(int device, kp_ctx** out) {
   ctx->tune.hash_bin_slots = 4096;
   ctx->tune.hash_grouping = 0;
   ctx->tune.hash_max_bin_bits = 10;
+  ctx->tune.hash_bin_fill = 42;
   if (device < 0) {   // host-only context: planning (kp_mul_bound) and tuning only
     *out = ctx;
     return KP_OK;
@@ -950,6 +952,8 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "hash_grouping must be 0 or 1");
   if (t->hash_max_bin_bits < 0 || t->hash_max_bin_bits > 10)
     return fail(ctx, KP_E_ARG, "hash_max_bin_bits must lie in [0, 10]");
+  if (t->hash_bin_fill < 10 || t->hash_bin_fill > 90)
+    return fail(ctx, KP_E_ARG, "hash_bin_fill must lie in [10, 90]");
   if (t->hash_capacity < 0 || t->dense_max_keys < 0 || t->dense_keys_per_pair < 0 ||
       t->hash_rows < 1)
     return fail(ctx, KP_E_ARG, "negative tuning value");

@@ -236,10 +236,12 @@ def test_tune_validation():
                 dict(hash_partitioned=3), dict(hash_partitioned=-1), dict(hash_bucket=-1),
                 dict(hash_bucket=17), dict(hash_order=2), dict(hash_bin_slots=0),
                 dict(hash_bin_slots=3000), dict(hash_bin_slots=16384), dict(hash_grouping=2),
-                dict(hash_max_bin_bits=11), dict(hash_max_bin_bits=-1)):
+                dict(hash_max_bin_bits=11), dict(hash_max_bin_bits=-1), dict(hash_bin_fill=9),
+                dict(hash_bin_fill=91)):
         with pytest.raises(kp.KPError):
             ctx.set_tune(**bad)
     assert t.hash_bucket == 0 and t.hash_order == 1 and t.hash_bin_slots == 4096
+    assert t.hash_bin_fill == 42
     for slots in (2048, 4096, 8192):
         ctx.set_tune(hash_bin_slots=slots)
         assert ctx.tune.hash_bin_slots == slots
