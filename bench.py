@@ -35,6 +35,7 @@ LDS_ATOMIC_PEAK = CUS * 16 * CLOCK_HZ          # pair accumulations per second
 PROFILES = os.path.join(ROOT, "profiles")
 HEADLINE_PROFILE = "k_rg_highly_sparse_30k.md"
 DENSE_PROFILE = "k_dense_mul_moderately_sparse_10k.md"
+POISSON_PROFILE = "k_radix_poisson_5k.md"
 
 
 def measured_traffic(name):
@@ -330,7 +331,7 @@ def run_poisson(kp, ctx, I, args):
     return {"term_products_per_s": 2.5e7 / r4["sec"], "ms_per_step": r4["sec"] * 1e3,
             "result_terms": r4["n_out"], "mode": r4["mode"],
             "roofline": roof_hbm("grouped hash accumulation (k_radix_* sequence), Poisson pieces",
-                                 alg, r4["kernel_s"], None,
+                                 alg, r4["kernel_s"], measured_traffic(POISSON_PROFILE),
                                  "32 B per piece (2 per pair) + 16 B per result term"),
             "workload": "Poisson series product: 3 polynomial + 6 trigonometric variables, "
                         "5000 x 5000 terms, fp64 coefficients N(0,1) 2^-sum|j|"}
