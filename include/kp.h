@@ -160,7 +160,8 @@ typedef struct kp_tune {
                                output code range (level 1 found from the sorted factors, so
                                each product is written once, to a hash bin of its range);
                                1 = two levels of hash bits through HBM (always used for
-                               Poisson series and 128-bit sums)                            */
+                               Poisson series and 128-bit sums).  Either way a bin whose
+                               distinct codes overflow its table is redone in parts       */
   int32_t hash_max_bin_bits; /* grouped by code range: at most 2^this bins per range (0..10,
                                default 10); fewer bins than the products ask for leave bins
                                that overflow their table and are redone in parts          */

@@ -363,6 +363,7 @@ constexpr int SPLIT_BLOCK = 1024;
 // A bin's LDS table has 2^LOG slots of 8 + 8 bytes (LOG 11, 12 or 13: 32, 64
 // or 128 KiB, four, two or one workgroup per CU) and 2^LOG / 8 threads.
 constexpr int BIN_PER_THREAD = 8;
+constexpr int BIN_STACK = 72;   // code intervals of a bin's overflow passes (depth <= 64)
 
 __device__ __forceinline__ uint64_t code_hash(int64_t code) { return (uint64_t)code * GOLDEN; }
 __device__ __forceinline__ uint32_t part1(uint64_t h, int l1) { return (uint32_t)(h >> (64 - l1)); }
@@ -787,7 +788,8 @@ __device__ __forceinline__ void lds_slot_add(I128* p, I128 v) {
 }
 
 // One workgroup per level-2 bin: accumulate in an LDS table, then write the
-// nonzero terms at an offset taken from the call's output counter.
+// nonzero terms at an offset taken from the call's output counter.  A bin
+// whose distinct codes overflow the table is redone by code interval.
 template <typename T, int LOG>
 __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(RadixArgs R) {
   constexpr int BIN_SLOTS = 1 << LOG, BIN_BLOCK = BIN_SLOTS / BIN_PER_THREAD;
@@ -796,6 +798,8 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   T* vals = reinterpret_cast<T*>(vals_words);
   __shared__ int64_t s_wave[BIN_BLOCK / 64];
   __shared__ int64_t s_base;
+  __shared__ int s_over, s_sp;
+  __shared__ unsigned long long s_lo[BIN_STACK], s_hi[BIN_STACK];
   // the grid covers the planned bins; the bins used are those of the level-2
   // bits chosen for the products actually made
   const int l2 = (int)R.meta->radix_l2;
@@ -817,10 +821,14 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
     keys[i] = 0;
     vals[i] = T(0);
   }
+  if (tid == 0) s_over = 0;
   __syncthreads();
   int64_t ins = 0, extra = 0;
-  const auto insert = [&](const uint4& x) {
+  // inserts the entry when its code lies in [ilo, ihi]; a full table sets
+  // s_over (the bin is then redone in parts)
+  const auto insert = [&](const uint4& x, uint64_t ilo, uint64_t ihi) {
     const int64_t code = (int64_t)(((uint64_t)x.y << 32) | x.x);
+    if ((uint64_t)code < ilo || (uint64_t)code > ihi) return;
     T v;
     if constexpr (std::is_same<T, I128>::value) {   // exact: the entry holds the pair (i, j)
       v = mul_wide(static_cast<const int64_t*>(R.ac)[x.w], static_cast<const int64_t*>(R.bc)[x.z]);
@@ -830,8 +838,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
     }
     const unsigned long long key = (unsigned long long)code + 1;
     uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, l2);
-    int q = 0;
-    for (; q < BIN_SLOTS; ++q) {
+    for (int q = 0; q < BIN_SLOTS; ++q) {
       unsigned long long c = keys[slot];
       if (c == 0) {
         c = atomicCAS(&keys[slot], 0ull, key);
@@ -839,91 +846,157 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
       }
       if (c == key) {
         lds_slot_add(&vals[slot], v);
-        break;
+        ++ins;
+        extra += q;
+        return;
       }
       slot = (slot + 1) & (BIN_SLOTS - 1);
     }
-    if (q == BIN_SLOTS) atomicOr(&R.meta->err, ERR_CAPACITY);
-    ++ins;
-    extra += q;
+    s_over = 1;
   };
-#pragma unroll
-  for (int u = 0; u < BIN_PER_THREAD; ++u)
-    if (s + tid + (int64_t)u * BIN_BLOCK < e) insert(en[u]);
-  // bins of many products per code can hold more entries than slots
-  for (int64_t k = s + tid + (int64_t)BIN_PER_THREAD * BIN_BLOCK; k < e; k += BIN_BLOCK)
-    insert(R.ent2[k]);
-  __syncthreads();
-  // Compaction to the front of the table: thread tid owns slots
-  // tid + r * BIN_BLOCK; every slot is read before any is rewritten.
-  constexpr int PER = BIN_PER_THREAD;
-  unsigned long long kk[PER];
-  T vv[PER];
-  uint64_t ball[PER];
-  int64_t cnt = 0;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int i = r * BIN_BLOCK + tid;
-    kk[r] = keys[i];
-    vv[r] = vals[i];
-    ball[r] = __ballot(kk[r] != 0 && vv[r] != T(0));
-    cnt += __popcll(ball[r]);
-  }
-  if (lane == 0) s_wave[wave] = cnt;
-  __syncthreads();
-  int64_t tot = 0, pos = 0;
-  for (int w = 0; w < BIN_BLOCK / 64; ++w) {
-    if (w == wave) pos = tot;
-    tot += s_wave[w];
-  }
-  if (tid == 0)
-    s_base = tot ? (int64_t)atomicAdd((unsigned long long*)&R.meta->out_count,
-                                      (unsigned long long)tot)
-                 : 0;
-  const uint64_t lt = (1ull << lane) - 1;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    if (ball[r] & (1ull << lane)) {
-      const int64_t q = pos + __popcll(ball[r] & lt);
-      keys[q] = kk[r];
-      vals[q] = vv[r];
-    }
-    pos += __popcll(ball[r]);
-  }
-  __syncthreads();
-  // the bin's terms, one per thread and all lanes busy, at the offset taken
-  // from the call's output counter
-  const int64_t base = s_base;
-  const int64_t n = min(tot, R.out_cap - base);
   T* out_c = static_cast<T*>(R.out_c);
   const int nx = R.dec.nx;
   const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
-  for (int64_t t = tid; t < n; t += BIN_BLOCK) {
-    const int64_t q = base + t;
-    const uint64_t code = (uint64_t)(keys[t] - 1);
-    if (R.out_t) {   // Poisson key: sin flag, then kx + Wx |ky|, decoded
-      uint64_t c = code >> 1;
-      R.out_t[q] = (uint8_t)(code & 1);
-      uint64_t u = fdiv(c, R.dec.dWx);
-      uint64_t kx = c - u * (uint64_t)R.dec.Wx;
-      for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, kx);
-      const int ny = R.dec.ny;
-      for (int v = ny - 1; v >= 0; --v) R.out_y[q * ny + v] = decode_y_step(R.dec, v, u);
-    } else if (R.out_x) {   // decoded exponents, written as they are found
-      uint64_t c = code;
-      if (pairs) {
-        int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
-        for (int v = 0; v < nx; v += 2) {
-          const int32_t lo = decode_step(R.dec, v, c);
-          o[v >> 1] = make_int2(lo, decode_step(R.dec, v + 1, c));
+  // Compacts the table to its front (thread tid owns slots tid + r *
+  // BIN_BLOCK; every slot is read before any is rewritten), writes the
+  // nonzero terms one per thread with all lanes busy at an offset taken from
+  // the call's output counter, and clears the table.
+  const auto emit = [&]() {
+    constexpr int PER = BIN_PER_THREAD;
+    unsigned long long kk[PER];
+    T vv[PER];
+    uint64_t ball[PER];
+    int64_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = r * BIN_BLOCK + tid;
+      kk[r] = keys[i];
+      vv[r] = vals[i];
+      ball[r] = __ballot(kk[r] != 0 && vv[r] != T(0));
+      cnt += __popcll(ball[r]);
+    }
+    if (lane == 0) s_wave[wave] = cnt;
+    __syncthreads();
+    int64_t tot = 0, pos = 0;
+    for (int w = 0; w < BIN_BLOCK / 64; ++w) {
+      if (w == wave) pos = tot;
+      tot += s_wave[w];
+    }
+    if (tid == 0)
+      s_base = tot ? (int64_t)atomicAdd((unsigned long long*)&R.meta->out_count,
+                                        (unsigned long long)tot)
+                   : 0;
+    const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      if (ball[r] & (1ull << lane)) {
+        const int64_t q = pos + __popcll(ball[r] & lt);
+        keys[q] = kk[r];
+        vals[q] = vv[r];
+      }
+      pos += __popcll(ball[r]);
+    }
+    __syncthreads();
+    const int64_t base = s_base;
+    const int64_t n = min(tot, R.out_cap - base);
+    for (int64_t t = tid; t < n; t += BIN_BLOCK) {
+      const int64_t q = base + t;
+      const uint64_t code = (uint64_t)(keys[t] - 1);
+      if (R.out_t) {   // Poisson key: sin flag, then kx + Wx |ky|, decoded
+        uint64_t c = code >> 1;
+        R.out_t[q] = (uint8_t)(code & 1);
+        uint64_t u = fdiv(c, R.dec.dWx);
+        uint64_t kx = c - u * (uint64_t)R.dec.Wx;
+        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, kx);
+        const int ny = R.dec.ny;
+        for (int v = ny - 1; v >= 0; --v) R.out_y[q * ny + v] = decode_y_step(R.dec, v, u);
+      } else if (R.out_x) {   // decoded exponents, written as they are found
+        uint64_t c = code;
+        if (pairs) {
+          int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
+          for (int v = 0; v < nx; v += 2) {
+            const int32_t lo = decode_step(R.dec, v, c);
+            o[v >> 1] = make_int2(lo, decode_step(R.dec, v + 1, c));
+          }
+        } else {
+          for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
         }
       } else {
-        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
+        R.out_k[q] = (int64_t)code;
       }
-    } else {
-      R.out_k[q] = (int64_t)code;
+      out_c[q] = vals[t];
     }
-    out_c[q] = vals[t];
+    __syncthreads();
+    for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
+      keys[i] = 0;
+      vals[i] = T(0);
+    }
+    __syncthreads();
+  };
+#pragma unroll
+  for (int u = 0; u < BIN_PER_THREAD; ++u)
+    if (s + tid + (int64_t)u * BIN_BLOCK < e) insert(en[u], 0, ~0ull);
+  // bins of many products per code can hold more entries than slots
+  for (int64_t k = s + tid + (int64_t)BIN_PER_THREAD * BIN_BLOCK; k < e; k += BIN_BLOCK)
+    insert(R.ent2[k], 0, ~0ull);
+  __syncthreads();
+  if (!s_over) {
+    emit();
+  } else {
+    // More distinct codes than slots (the table is full; Section 3.2 resizes
+    // and rehashes): the bin again, one code interval at a time, halving an
+    // interval whose codes overflow the table.  An interval of at most
+    // BIN_SLOTS codes always fits, so the halving ends.
+    for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
+      keys[i] = 0;
+      vals[i] = T(0);
+    }
+    if (tid == 0) {
+      s_lo[0] = ~0ull;
+      s_hi[0] = 0;
+    }
+    __syncthreads();
+    uint64_t mn = ~0ull, mx = 0;
+    for (int64_t k = s + tid; k < e; k += BIN_BLOCK) {
+      const uint4 x = R.ent2[k];
+      const uint64_t code = ((uint64_t)x.y << 32) | x.x;
+      mn = code < mn ? code : mn;
+      mx = code > mx ? code : mx;
+    }
+    atomicMin(&s_lo[0], (unsigned long long)mn);
+    atomicMax(&s_hi[0], (unsigned long long)mx);
+    if (tid == 0) s_sp = 1;
+    __syncthreads();
+    while (s_sp > 0) {
+      const uint64_t ilo = s_lo[s_sp - 1], ihi = s_hi[s_sp - 1];
+      __syncthreads();
+      if (tid == 0) {
+        s_over = 0;
+        --s_sp;
+      }
+      __syncthreads();
+      for (int64_t k = s + tid; k < e; k += BIN_BLOCK) insert(R.ent2[k], ilo, ihi);
+      __syncthreads();
+      if (s_over) {
+        // the upper half is pushed first, so the lower half runs next
+        if (tid == 0) {
+          const uint64_t mid = ilo + (ihi - ilo) / 2;
+          s_lo[s_sp] = mid + 1;
+          s_hi[s_sp] = ihi;
+          s_lo[s_sp + 1] = ilo;
+          s_hi[s_sp + 1] = mid;
+          s_sp += 2;
+        }
+        __syncthreads();
+        for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
+          keys[i] = 0;
+          vals[i] = T(0);
+        }
+        __syncthreads();
+      } else {
+        emit();
+      }
+    }
   }
   if (R.stats) add_stats(R.stats, ins, extra);
 }

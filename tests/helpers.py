@@ -143,3 +143,21 @@ def parallel_chunks(fn, items, workers=None, parts=64):
         futs = [ex.submit(fn, *[it[b0:b1] for it in items])
                 for b0, b1 in zip(bounds[:-1], bounds[1:]) if b1 > b0]
         return [f.result() for f in futs]
+
+
+def adversarial_codes(slots, coef=None):
+    """Univariate factors whose product codes, under the two-level hash
+    grouping (code times the 64-bit golden-ratio constant), all have their top
+    three bits zero: slots + 1000 distinct codes in the first of at most 4
+    bins.  A is those exponents (and 0) with coefficients `coef` (ones by
+    default), B the constant 1."""
+    rng = np.random.default_rng(slots)
+    e = np.unique(rng.integers(1, 1 << 31, 1 << 20, dtype=np.int64))
+    with np.errstate(over="ignore"):
+        h = e.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    e = e[(h >> np.uint64(61)) == 0][: slots + 999]
+    assert len(e) == slots + 999
+    c = np.ones(slots + 1000, np.int64) if coef is None else np.asarray(coef, np.int64)
+    a = (np.concatenate([[0], e]).astype(np.int32).reshape(-1, 1), c)
+    b = (np.zeros((1, 1), np.int32), np.ones(1, np.int64))
+    return a, b

@@ -12,7 +12,7 @@ import pytest
 import oracle as O
 import paper_1004_4548_amd as kp
 from paper_1004_4548_amd import inputs as I
-from tests.helpers import assert_exact
+from tests.helpers import adversarial_codes, assert_exact
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +103,20 @@ def test_exact_hash_layouts(part):
         for slots in (2048, 4096, 8192):
             ctx.set_tune(hash_bin_slots=slots)
             check_exact(a, b, "hash", f"simplex, bins of {slots} slots", ctx)
+
+
+@pytest.mark.parametrize("slots", [2048, 4096])
+def test_exact_full_bin_recovers(slots):
+    """128-bit sums in the grouped layout: slots + 1000 distinct codes in one
+    bin overflow its table, and the bin is redone by code interval (62-bit
+    coefficients times a 62-bit constant: every product carries into the high
+    word)."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots)
+    rng = np.random.default_rng(77 + slots)
+    a, b = adversarial_codes(slots, _big(rng, slots + 1000))
+    b = (b[0], np.array([3 * 2**60 + 12345], np.int64))
+    check_exact(a, b, "hash", f"{slots + 1000} codes in one bin of {slots}", ctx)
 
 
 def test_exact_split_windows_and_small_windows():

@@ -12,8 +12,8 @@ import pytest
 import oracle as O
 import paper_1004_4548_amd as kp
 from paper_1004_4548_amd import inputs as I
-from tests.helpers import (P61, assert_exact, assert_tolerance, eval_mod2_64_device,
-                           eval_modp_device, parallel_chunks)
+from tests.helpers import (P61, adversarial_codes, assert_exact, assert_tolerance,
+                           eval_mod2_64_device, eval_modp_device, parallel_chunks)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-13
@@ -345,37 +345,20 @@ def test_partitioned_bin_tables(slots):
     check_poisson(pa, pb, f"poisson hash, bins of {slots}", mode="hash")
 
 
-def _adversarial(slots):
-    """Univariate factors whose product codes, under the two-level hash
-    grouping (code times the 64-bit golden-ratio constant), all have their top
-    three bits zero: slots + 1000 distinct codes in the first of at most 4
-    bins."""
-    rng = np.random.default_rng(slots)
-    e = np.unique(rng.integers(1, 1 << 31, 1 << 20, dtype=np.int64))
-    with np.errstate(over="ignore"):
-        h = e.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
-    e = e[(h >> np.uint64(61)) == 0][: slots + 999]
-    assert len(e) == slots + 999
-    a = (np.concatenate([[0], e]).astype(np.int32).reshape(-1, 1), np.ones(slots + 1000, np.int64))
-    b = (np.zeros((1, 1), np.int32), np.ones(1, np.int64))
-    return a, b
-
-
 @pytest.mark.parametrize("slots", [2048, 4096, 8192])
-def test_two_level_grouping_full_bin_is_a_capacity_error(slots):
-    """With the two-level hash grouping forced, the adversarial codes overflow
-    one bin's table: reported as a capacity error, not hung, and the next
-    product is unaffected."""
+def test_two_level_grouping_recovers_from_full_bins(slots):
+    """With the two-level hash grouping forced, the adversarial codes put
+    slots + 1000 distinct codes into one bin: its table overflows, the bin is
+    redone one code interval at a time, and the product is the oracle's
+    (int64 and fp64); the next product is unaffected."""
     ctx = kp.context()
     ctx.set_tune(hash_partitioned=2, hash_bin_slots=slots, hash_grouping=1)
-    a, b = _adversarial(slots)
-    say("two-level grouping capacity error,", slots + 1000, "codes in one bin of", slots, "slots")
-    with pytest.raises(kp.KPError) as err:
-        gpu_laurent(a, b, "hash", ctx)
-    assert err.value.status == kp.KP_E_CAPACITY
-    ctx.sync_check()
+    a, b = adversarial_codes(slots)
+    check_laurent(a, b, "hash", f"two-level grouping, {slots + 1000} codes in one bin of {slots}", ctx)
+    check_laurent((a[0], a[1].astype(np.float64) * 0.5), (b[0], b[1].astype(np.float64)), "hash",
+                  f"two-level grouping, fp64, one bin of {slots}", ctx)
     a2, b2 = I.config(3, scale=0.03)
-    check_laurent(a2, b2, "hash", f"after the capacity error, bins of {slots}", ctx)
+    check_laurent(a2, b2, "hash", f"after the overflowing bin, bins of {slots}", ctx)
 
 
 @pytest.mark.parametrize("slots", [2048, 4096, 8192])
@@ -387,7 +370,7 @@ def test_range_grouping_recovers_from_full_bins(slots):
     interval at a time: still the oracle's product, int64 and fp64."""
     ctx = kp.context()
     ctx.set_tune(hash_bin_slots=slots)
-    a, b = _adversarial(slots)
+    a, b = adversarial_codes(slots)
     check_laurent(a, b, "auto", f"adversarial codes grouped by range, bins of {slots}", ctx)
     ctx.set_tune(hash_max_bin_bits=0)
     a, b = I.config(3, scale=0.1)
