@@ -186,8 +186,7 @@ def measure_poisson(kp, ctx, a, b, mode, steps, warmup):
     time_steps(lambda: poisson_step(kp, ctx, ws, sa, sb, mode), steps, 0)
     kms, launches = ctx.timing_read()
     ctx.timing(False)
-    lay = kp.poisson_layout(sa, sb, ctx)
-    m, _, _ = kp.mul_bound(lay, True, kp.KP_F64, mode, len(a[3]), len(b[3]), ctx)
+    _, m, _, _ = kp.plan_poisson(sa, sb, mode, ctx)
     return dict(sec=sec, kernel_s=kms / 1e3 / max(launches, 1), n_out=n_out, mode=m)
 
 

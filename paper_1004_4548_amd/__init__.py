@@ -662,12 +662,8 @@ def mul_laurent(a: Poly, b: Poly, mode="auto", ctx=None, workspace=None, exact=F
 
 
 def poisson_layout(a: PoissonSeries, b: PoissonSeries, ctx=None) -> Layout:
-    ctx = ctx or context()
-    nx, ny = a.x.shape[1], a.y.shape[1]
-    (amin, amax), (bmin, bmax), ya, yb = _boxes(ctx, a.x, b.x, a.y, b.y)
-    ha = [max(-lo, hi, 0) for lo, hi in zip(*ya)]
-    hb = [max(-lo, hi, 0) for lo, hi in zip(*yb)]
-    return layout_product(nx, ny, amin, amax, bmin, bmax, ha, hb)
+    """The product's layout, as kp_plan_poisson computes it."""
+    return plan_poisson(a, b, "auto", ctx)[0]
 
 
 def plan_poisson(a: PoissonSeries, b: PoissonSeries, mode="auto", ctx=None, stream=None):

@@ -174,7 +174,12 @@ def test_two_call_poisson_matches_oracle_and_layout():
     sa = kp.PoissonSeries(dev(a[0]), dev(a[1]), dev(a[2]), dev(a[3]))
     sb = kp.PoissonSeries(dev(b[0]), dev(b[1]), dev(b[2]), dev(b[3]))
     lay, mode, max_out, ws = kp.plan_poisson(sa, sb, ctx=ctx)
-    assert _fields(lay) == _fields(kp.poisson_layout(sa, sb, ctx))
+    # the layout from the factors' boxes, found here on the host: polynomial
+    # boxes, and trig half-widths max(|lo|, |hi|) (balanced digits)
+    half = lambda y: np.maximum(np.abs(y.min(0)), np.abs(y.max(0))).tolist()
+    ref = kp.layout_product(a[0].shape[1], a[1].shape[1], a[0].min(0), a[0].max(0), b[0].min(0),
+                            b[0].max(0), half(a[1]), half(b[1]))
+    assert _fields(lay) == _fields(ref)
     r, _ = kp.mul_poisson(sa, sb, ctx=ctx)
     nx, ny = a[0].shape[1], a[1].shape[1]
     ox, oy, ot, oc, oab = O.poisson_mul(a, b, nx, ny, threads=4)
