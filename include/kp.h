@@ -156,12 +156,15 @@ typedef struct kp_tune {
                                slots and at most 4096 of them (8192 acts as 4096); their
                                grouped entries carry the pair's 32-bit term indices, so
                                factors of 2^32 terms or more keep the global table        */
-  int32_t hash_grouping;    /* grouped products, Laurent int64/fp64: 0 (default) = grouped by
-                               output code range (level 1 found from the sorted factors, so
-                               each product is written once, to a hash bin of its range);
+  int32_t hash_grouping;    /* grouped products, Laurent int64/fp64: 2 = grouped by output
+                               code range (level 1 found from the sorted factors, so each
+                               product is written once, to a hash bin of its range);
                                1 = two levels of hash bits through HBM (always used for
-                               Poisson series and 128-bit sums).  Either way a bin whose
-                               distinct codes overflow its table is redone in parts       */
+                               Poisson series and 128-bit sums); 0 (default) = by range,
+                               except under a truncation, where the two-level grouping
+                               drops pairs over the limit before forming them.  Either
+                               way a bin whose distinct codes overflow its table is redone
+                               in parts                                                   */
   int32_t hash_max_bin_bits; /* grouped by code range: at most 2^this bins per range (0..10,
                                default 10); fewer bins than the products ask for leave bins
                                that overflow their table and are redone in parts          */

@@ -693,7 +693,12 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
     // (a wavefront scans the interval lengths of 64 rows in 32 bits)
-    p->range = p->radix && !poisson && dt != KP_I128 && ctx->tune.hash_grouping == 0 &&
+    // Under a truncation the two-level grouping is the automatic choice: it
+    // drops a pair over the limit before anything is formed, while the
+    // ranges enumerate every pair of a row's interval of B.
+    const int grouping = ctx->tune.hash_grouping;
+    p->range = p->radix && !poisson && dt != KP_I128 &&
+               (grouping == 2 || (grouping == 0 && !p->trunc)) &&
                na < ((int64_t)1 << 31) && nb <= ((int64_t)1 << 24);
     if (p->range) {
       p->radix = false;
@@ -948,8 +953,8 @@ kp_status kp_ctx_set_tune(kp_ctx* ctx, const kp_tune* t) {
     return fail(ctx, KP_E_ARG, "hash_order must be 0 or 1");
   if (t->hash_bin_slots != 2048 && t->hash_bin_slots != 4096 && t->hash_bin_slots != 8192)
     return fail(ctx, KP_E_ARG, "hash_bin_slots must be 2048, 4096 or 8192");
-  if (t->hash_grouping != 0 && t->hash_grouping != 1)
-    return fail(ctx, KP_E_ARG, "hash_grouping must be 0 or 1");
+  if (t->hash_grouping < 0 || t->hash_grouping > 2)
+    return fail(ctx, KP_E_ARG, "hash_grouping must be 0, 1 or 2");
   if (t->hash_max_bin_bits < 0 || t->hash_max_bin_bits > 10)
     return fail(ctx, KP_E_ARG, "hash_max_bin_bits must lie in [0, 10]");
   if (t->hash_bin_fill < 10 || t->hash_bin_fill > 90)

@@ -847,13 +847,19 @@ struct Coef {
 
 // One instruction of an item: row 4U + g of the item against this lane's term.
 // Window byte offsets are relative to the window's LDS base, which is added
-// last (it folds into the instruction's offset field).
+// last (it folds into the instruction's offset field).  In a truncated
+// product a pair over the degree limit goes to the lane's discard slot, and
+// an instruction whose pairs are all over the limit issues no LDS add (a
+// wavefront-uniform branch: the broadcasts read other lanes, so the
+// execution mask never changes around them).
 template <typename T, int MUL, bool EDGE, bool TRUNC, int U>
 __device__ __forceinline__ void pair_step(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
                                           const Coef<T, MUL>& c, uint32_t sa, int32_t tb) {
+  const bool keep = !TRUNC || (int32_t)bcast16<U>(sa) >= tb;   // within the degree limit
+  if (TRUNC && __builtin_amdgcn_ballot_w64(keep) == 0) return;
   uint32_t rel = bcast16<U>(a8) + off8;
   if (EDGE) rel = min(rel, lim);
-  if (TRUNC && (int32_t)bcast16<U>(sa) < tb) rel = lim;   // over the degree limit: discard
+  if (TRUNC && !keep) rel = lim;
   rel += base;
   T v;
   if constexpr (MUL == 4) {
@@ -891,22 +897,27 @@ template <bool EDGE, bool TRUNC, int U>
 __device__ __forceinline__ void wide_issue(uint32_t a8, uint32_t off8, uint32_t lim, uint32_t base,
                                            uint32_t clo, uint32_t chi, int64_t bw, uint32_t sa,
                                            int32_t tb, uint32_t& addr, uint64_t& plo,
-                                           int64_t& phi, uint64_t& old) {
+                                           int64_t& phi, uint64_t& old, bool& keep) {
+  // wavefront-uniform: false when every pair of the instruction is over the
+  // degree limit (no add issued); lanes over the limit use the discard slot
+  const bool mine = !TRUNC || (int32_t)bcast16<U>(sa) >= tb;
+  keep = !TRUNC || __builtin_amdgcn_ballot_w64(mine) != 0;
   uint32_t rel = bcast16<U>(a8) + off8;
   if (EDGE) rel = min(rel, lim);
-  if (TRUNC && (int32_t)bcast16<U>(sa) < tb) rel = lim;
+  if (TRUNC && !mine) rel = lim;
   addr = rel + base;
   const int64_t x = (int64_t)(((uint64_t)bcast16<U>(chi) << 32) | bcast16<U>(clo));
   plo = (uint64_t)x * (uint64_t)bw;
   phi = __mul64hi(x, bw);
-  old = lds_fetch_add(addr, plo);
+  old = 0;
+  if (keep) old = lds_fetch_add(addr, plo);
 }
 
 // Finish: the carry out of the low-word add goes into the high word.
 __device__ __forceinline__ void wide_finish(uint32_t addr, uint32_t hi8, uint64_t plo,
-                                            int64_t phi, uint64_t old) {
+                                            int64_t phi, uint64_t old, bool keep) {
   const uint64_t carry = old + plo < old ? 1u : 0u;
-  lds_add(addr + hi8, (int64_t)((uint64_t)phi + carry));
+  if (keep) lds_add(addr + hi8, (int64_t)((uint64_t)phi + carry));
 }
 
 // A group of instructions: every low-word add is issued before the first
@@ -920,10 +931,11 @@ __device__ __forceinline__ void wide_group(std::integer_sequence<int, U...>, uin
   uint32_t addr[N];
   uint64_t plo[N], old[N];
   int64_t phi[N];
+  bool keep[N];
   (wide_issue<EDGE, TRUNC, G + U>(a8, off8, lim, base, clo, chi, bw, sa, tb, addr[U], plo[U],
-                                  phi[U], old[U]),
+                                  phi[U], old[U], keep[U]),
    ...);
-  (wide_finish(addr[U], hi8, plo[U], phi[U], old[U]), ...);
+  (wide_finish(addr[U], hi8, plo[U], phi[U], old[U], keep[U]), ...);
 }
 
 // R instructions (4, 8, 12 or 16), in groups of up to eight.
@@ -984,9 +996,25 @@ __device__ __forceinline__ void fetch_item(const MulArgs& M, int64_t d, int lane
   }
 }
 
+// Smallest value of a 16-lane row, in every lane of the row (rotations).
+template <int K>
+__device__ __forceinline__ int32_t row_ror(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xF, 0xF, false);   // row_ror:K
+}
+__device__ __forceinline__ int32_t row_min16(int32_t v) {
+  v = min(v, row_ror<1>(v));
+  v = min(v, row_ror<2>(v));
+  v = min(v, row_ror<4>(v));
+  return min(v, row_ror<8>(v));
+}
+
 template <typename T, int MUL, bool TRUNC>
 __device__ __forceinline__ void run_item(const ItemRegs& x, int64_t L, uint32_t lim, int lane,
                                          int64_t nb, uint32_t base, uint32_t hi8) {
+  // a truncated product skips an item whose every pair is over the degree
+  // limit: no row's slack reaches the tile's smallest degree (every lane
+  // holds a row of the item and every 16-lane row the tile's terms)
+  if (TRUNC && __builtin_amdgcn_ballot_w64(x.sa >= row_min16(x.tb)) == 0) return;
   const bool vb = x.t * DENSE_TILE + (lane & 15) < nb;
   const uint32_t off8 =
       vb ? (uint32_t)(((int32_t)(uint32_t)x.b - (int32_t)L) * 8) : LANE_SENTINEL;
@@ -1156,8 +1184,9 @@ __global__ void __launch_bounds__(BS) k_dense_mul(MulArgs M) {
     } else if constexpr (std::is_same<T, I128>::value) {
       if (trunc) run_items<T, 5, BS, true>(M, pb, pe, L, S8, base, hi8);
       else run_items<T, 5, BS, false>(M, pb, pe, L, S8, base, hi8);
-    } else if (trunc) {   // truncated products: one (int64) coefficient kind
-      run_items<T, 0, BS, true>(M, pb, pe, L, S8, base, hi8);
+    } else if (trunc) {   // truncated products: the narrowest kind, or general int64
+      if (narrow & 4u) run_items<T, 4, BS, true>(M, pb, pe, L, S8, base, hi8);
+      else run_items<T, 0, BS, true>(M, pb, pe, L, S8, base, hi8);
     } else {
       if (narrow & 4u) run_items<T, 4, BS, false>(M, pb, pe, L, S8, base, hi8);
       else if (narrow & 2u) run_items<T, 2, BS, false>(M, pb, pe, L, S8, base, hi8);

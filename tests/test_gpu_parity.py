@@ -761,7 +761,7 @@ def _trunc_cases():
 
 
 @pytest.mark.parametrize("mode,part,grouping", [("dense", 0, 0), ("hash", 0, 0), ("hash", 2, 0),
-                                                ("hash", 2, 1)])
+                                                ("hash", 2, 1), ("hash", 2, 2)])
 def test_truncated_products_match_oracle(mode, part, grouping):
     ctx = kp.context()
     ctx.set_tune(hash_partitioned=part, hash_grouping=grouping)
@@ -783,9 +783,10 @@ def test_truncated_products_match_oracle(mode, part, grouping):
 def test_truncation_keeps_few_or_no_pairs(part):
     """A degree limit below every pair's degree gives the empty product; one a
     little above the smallest keeps a handful of pairs (the grouped layout
-    then chooses its fewest level-2 bins).  Against the oracle's filter."""
+    then chooses its fewest level-2 bins).  Against the oracle's filter.
+    part 3: grouped by code range."""
     ctx = kp.context()
-    ctx.set_tune(hash_partitioned=min(part, 2), hash_grouping=1 if part == 3 else 0)
+    ctx.set_tune(hash_partitioned=min(part, 2), hash_grouping=2 if part == 3 else 0)
     a, b = I.config(3, scale=0.03)
     da, db = a[0].sum(1).min(), b[0].sum(1).min()
     for D, what in ((int(da + db) - 1, "no pair kept"), (int(da + db) + 25, "a few pairs kept")):

@@ -235,7 +235,7 @@ def test_tune_validation():
                 dict(window=1000, block=256), dict(dense_max_keys=(1 << 27) + 1),
                 dict(hash_partitioned=3), dict(hash_partitioned=-1), dict(hash_bucket=-1),
                 dict(hash_bucket=17), dict(hash_order=2), dict(hash_bin_slots=0),
-                dict(hash_bin_slots=3000), dict(hash_bin_slots=16384), dict(hash_grouping=2),
+                dict(hash_bin_slots=3000), dict(hash_bin_slots=16384), dict(hash_grouping=3),
                 dict(hash_max_bin_bits=11), dict(hash_max_bin_bits=-1), dict(hash_bin_fill=9),
                 dict(hash_bin_fill=91)):
         with pytest.raises(kp.KPError):
@@ -335,7 +335,7 @@ def test_hash_plans_of_empty_and_tiny_products():
     empty = kp.layout_product(2, 0, [0, 0], [-1, -1], [0, 0], [3, 3])
     one = kp.layout_product(1, 0, [0], [0], [0], [0])
     small = kp.layout_product(2, 0, [0, 0], [3, 1], [0, 0], [2, 2])
-    for grouping in (0, 1):
+    for grouping in (0, 1, 2):
         ctx.set_tune(hash_partitioned=2, hash_grouping=grouping)
         for lay, na, nb in ((empty, 0, 5), (empty, 5, 0), (one, 1, 1), (one, 7, 3), (small, 1, 1),
                             (small, 300, 2)):
