@@ -482,6 +482,69 @@ kp_status kp_batch_launch(kp_batch* batch, unsigned flags, hipStream_t stream);
 kp_status kp_batch_status(kp_batch* batch, int64_t task_id, int64_t* n_out);
 
 /*
+ * Packed batches: many whole Laurent products of uneven sizes in one fixed
+ * sequence of persistent launches (a systems pattern; each product is the
+ * schoolbook sum of Section 3 over the Kronecker codes of Section 2, the same
+ * set of terms as kp_mul_laurent_exps gives).  The products' descriptions sit
+ * in a device task table; each stage is one launch of a fixed grid whose
+ * workgroups walk the work of every task (encode both factors and clear the
+ * accumulator; form every pair's product and add it at its code; compact the
+ * nonzero sums, decoding them to exponents; post the counts).  Each product
+ * accumulates in device memory of its own: one word per code when the key
+ * space is at most twice the size of the hash table it would otherwise get
+ * (Section 3.1's dense array), else an open-addressing hash table of at least
+ * twice the result bound, compare-and-swap on the key and atomic add on the
+ * coefficient (Section 3.2).  Meant for many small products, whose cost per
+ * call is launches and host waits; large products are better served one call
+ * each.
+ *
+ * kp_pack_create: a pack for up to max_tasks (1..4096) products; it owns a
+ *   device task table and pinned host memory for the boxes and counts.
+ * kp_pack_plan: tasks[0..n) (device arrays: exponents int32 [n][nvars],
+ *   coefficients int64 or double; KP_E_DTYPE otherwise) are copied in; one
+ *   launch takes every factor's box and one host wait brings them back; each
+ *   product's layout (Section 2, KP_E_CODE_OVERFLOW) and result bound
+ *   min(codes, na nb) follow.  out_cap[k] receives task k's bound,
+ *   *arena_bytes the device memory kp_pack_run needs.
+ * kp_pack_run: queues the products on `stream` and returns: task k's terms
+ *   go to out_exps[k] (int32 [out_cap[k]][nvars]) and out_coef[k]
+ *   ([out_cap[k]], the task's type), in unspecified order.  `arena` is
+ *   caller-owned device memory of at least *arena_bytes.  With KP_PACK_GRAPH
+ *   the upload of the table and the four launches are captured into a HIP
+ *   graph at the first such run and replayed by every later one (any
+ *   products: the kernels read them from the table); capture needs a stream
+ *   other than the null stream.
+ * kp_pack_wait: waits for the counts of the last run (one host wait for the
+ *   whole batch); n_out[k] is task k's number of terms, or -(status) after a
+ *   device error (the call then returns that status).  kp_pack_query sets
+ *   *done without waiting.
+ * A pack runs one batch at a time: plan and run refuse while a run has not
+ * been waited for.  The caller keeps the arrays valid until the wait.
+ */
+typedef struct kp_pack kp_pack;
+enum { KP_PACK_GRAPH = 4 };
+
+typedef struct kp_pack_task {
+  int32_t nvars;               /* 1..KP_MAX_VARS                                    */
+  kp_dtype dtype;              /* KP_I64 or KP_F64                                  */
+  const int32_t* a_exps;       /* device [na][nvars]                                */
+  const void* a_coef;          /* device [na]                                       */
+  int64_t na;                  /* < 2^31                                            */
+  const int32_t* b_exps;
+  const void* b_coef;
+  int64_t nb;
+} kp_pack_task;
+
+kp_status kp_pack_create(kp_ctx* ctx, int32_t max_tasks, kp_pack** out);
+kp_status kp_pack_destroy(kp_pack* pack);
+kp_status kp_pack_plan(kp_pack* pack, const kp_pack_task* tasks, int32_t n, int64_t* out_cap,
+                       size_t* arena_bytes, hipStream_t stream);
+kp_status kp_pack_run(kp_pack* pack, int32_t* const* out_exps, void* const* out_coef, void* arena,
+                      size_t arena_bytes, unsigned flags, hipStream_t stream);
+kp_status kp_pack_wait(kp_pack* pack, int64_t* n_out);
+kp_status kp_pack_query(kp_pack* pack, int32_t* done);
+
+/*
  * Host-memory twins of kp_encode / kp_decode, running the same per-term code
  * map on the CPU (for callers without a device and for checking tables).
  * Errors are returned directly.

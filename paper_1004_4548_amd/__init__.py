@@ -30,6 +30,7 @@ KP_I64, KP_F64, KP_I128 = 0, 1, 2
 KP_AUTO, KP_DENSE, KP_HASH = 0, 1, 2
 KP_FLAG_ASYNC = 1
 KP_BATCH_GRAPH = 2
+KP_PACK_GRAPH = 4
 KP_SCRATCH_BYTES = 64 << 20   # the scratch array of kp_mul_laurent_noalloc (include/kp.h)
 KP_KIND_LAURENT, KP_KIND_POISSON = 0, 1
 MODES = {"auto": KP_AUTO, "dense": KP_DENSE, "hash": KP_HASH}
@@ -44,7 +45,14 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_ctx_hash_stats", "kp_ctx_hash_stats_read", "kp_probe_lds_atomic",
             "kp_plan_laurent", "kp_mul_laurent_exps", "kp_plan_poisson", "kp_mul_poisson_exps",
             "kp_mul_laurent_auto", "kp_ctx_set_truncation", "kp_ctx_clear_truncation",
-            "kp_mul_laurent_noalloc"]
+            "kp_mul_laurent_noalloc", "kp_pack_create", "kp_pack_destroy", "kp_pack_plan",
+            "kp_pack_run", "kp_pack_wait", "kp_pack_query"]
+
+
+class PackTask(C.Structure):
+    _fields_ = [("nvars", C.c_int32), ("dtype", C.c_int32), ("a_exps", C.c_void_p),
+                ("a_coef", C.c_void_p), ("na", C.c_int64), ("b_exps", C.c_void_p),
+                ("b_coef", C.c_void_p), ("nb", C.c_int64)]
 
 
 class KPError(RuntimeError):
@@ -137,6 +145,12 @@ def lib():
         "kp_mul_laurent_auto": (i32, [p, i32, i32, i32, u32, p, p, i64, p, p, i64, p, p, i64, p,
                                       C.POINTER(i64), p, sz, C.POINTER(Layout), C.POINTER(i64),
                                       C.POINTER(sz), p]),
+        "kp_pack_create": (i32, [p, i32, C.POINTER(p)]),
+        "kp_pack_destroy": (i32, [p]),
+        "kp_pack_plan": (i32, [p, C.POINTER(PackTask), i32, C.POINTER(i64), C.POINTER(sz), p]),
+        "kp_pack_run": (i32, [p, C.POINTER(p), C.POINTER(p), p, sz, u32, p]),
+        "kp_pack_wait": (i32, [p, C.POINTER(i64)]),
+        "kp_pack_query": (i32, [p, C.POINTER(i32)]),
         "kp_ctx_set_truncation": (i32, [p, i32, C.POINTER(i32), i64]),
         "kp_ctx_clear_truncation": (i32, [p]),
         "kp_plan_poisson": (i32, [p, i32, i32, i32, p, p, i64, p, p, i64, C.POINTER(Layout),
@@ -790,3 +804,89 @@ class Batch:
     def clear(self):
         self.ctx.check(lib().kp_batch_clear(self.h))
         self._keep = []
+
+
+class Pack:
+    """kp_pack: many whole Laurent products in one fixed sequence of
+    persistent launches over a device task table; with graph=True the
+    sequence is a HIP graph captured at the first launch and replayed by
+    every later one.  One batch at a time: launch(), then wait()."""
+
+    def __init__(self, max_tasks, ctx=None):
+        self.ctx = ctx or context()
+        h = C.c_void_p()
+        self.ctx.check(lib().kp_pack_create(self.ctx.h, max_tasks, C.byref(h)))
+        self.h = h
+        self.max_tasks = max_tasks
+        self._run = None
+        self._side = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.kp_pack_destroy(self.h)
+            self.h = None
+
+    def launch(self, products, graph=False, stream=None):
+        """Plans the products [(Poly a, Poly b), ...] (one host wait for every
+        factor's box) and queues them on `stream` (default: the current one)."""
+        import torch
+        n = len(products)
+        tasks = (PackTask * max(n, 1))()
+        for k, (a, b) in enumerate(products):
+            for t, nm in ((a.exps, "a.exps"), (b.exps, "b.exps")):
+                _dev_check(t, torch.int32, nm)
+            if a.coef.dtype != b.coef.dtype or a.coef.dtype not in (torch.int64, torch.float64):
+                raise ValueError("both factors int64 or both float64")
+            if a.nv != b.nv:
+                raise ValueError("factors must have the same number of variables")
+            tasks[k] = PackTask(a.nv, KP_F64 if a.coef.dtype == torch.float64 else KP_I64,
+                                a.exps.data_ptr(), a.coef.data_ptr(), a.coef.shape[0],
+                                b.exps.data_ptr(), b.coef.data_ptr(), b.coef.shape[0])
+        cur = torch.cuda.current_stream() if stream is None else stream
+        run_on = cur
+        if graph and cur.cuda_stream == 0:   # capture needs a stream of its own
+            if self._side is None:
+                self._side = torch.cuda.Stream()
+            self._side.wait_stream(cur)
+            run_on = self._side
+        caps = (C.c_int64 * max(n, 1))()
+        ab = C.c_size_t()
+        self.ctx.check(lib().kp_pack_plan(self.h, tasks, n, caps, C.byref(ab),
+                                          C.c_void_p(run_on.cuda_stream)))
+        caps = [int(caps[k]) for k in range(n)]
+        with torch.cuda.stream(run_on):
+            dev = cur.device
+            nx = sum(c * a.nv for c, (a, _) in zip(caps, products))
+            X = torch.empty(max(nx, 1), dtype=torch.int32, device=dev)
+            V = torch.empty(max(sum(caps), 1), dtype=torch.int64, device=dev)
+            arena = torch.empty(max(ab.value, 256), dtype=torch.uint8, device=dev)
+        ox, oc, views, px, pc = (C.c_void_p * max(n, 1))(), (C.c_void_p * max(n, 1))(), [], 0, 0
+        for k, (a, _) in enumerate(products):
+            x = X[px:px + caps[k] * a.nv].view(caps[k], a.nv)
+            v = V[pc:pc + caps[k]]
+            if a.coef.dtype == torch.float64:
+                v = v.view(torch.float64)
+            ox[k], oc[k] = x.data_ptr(), v.data_ptr()
+            views.append((x, v))
+            px += caps[k] * a.nv
+            pc += caps[k]
+        self.ctx.check(lib().kp_pack_run(self.h, ox, oc, C.c_void_p(arena.data_ptr()), ab.value,
+                                         KP_PACK_GRAPH if graph else 0,
+                                         C.c_void_p(run_on.cuda_stream)))
+        if run_on is not cur:
+            cur.wait_stream(run_on)
+        self._run = (products, views, arena, n)
+
+    def ready(self):
+        """True when the last launch's counts are back (no wait)."""
+        d = C.c_int32()
+        self.ctx.check(lib().kp_pack_query(self.h, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self):
+        """The last launch's products, as Polys (views of two shared buffers)."""
+        _, views, _, n = self._run
+        counts = (C.c_int64 * max(n, 1))()
+        self._run = None
+        self.ctx.check(lib().kp_pack_wait(self.h, counts))
+        return [Poly(x[:counts[k]], v[:counts[k]]) for k, (x, v) in enumerate(views)]

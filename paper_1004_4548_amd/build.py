@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkp.so")
-SOURCES = ["kp_codec.hip", "kp_dense.hip", "kp_hash.hip", "kp_range.hip", "kp_poisson.hip",
+SOURCES = ["kp_codec.hip", "kp_dense.hip", "kp_hash.hip", "kp_range.hip", "kp_pack.hip", "kp_poisson.hip",
            "kp_diag.hip", "kp_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

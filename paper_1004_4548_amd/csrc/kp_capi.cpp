@@ -1808,6 +1808,365 @@ kp_status kp_batch_status(kp_batch* b, int64_t task_id, int64_t* n_out) {
   return *n_out < 0 ? (kp_status)(-*n_out) : KP_OK;
 }
 
+// ------------------------------------------------------------ packed batches
+struct kp_pack {
+  kp_ctx* ctx = nullptr;
+  int max_tasks = 0;
+  size_t table_bytes = 0;
+  void* table_dev = nullptr;        // device task table
+  char* table_host = nullptr;       // pinned staging of the same bytes
+  uint64_t* post = nullptr;         // pinned, mapped: boxes (2 arrays a task), then counts
+  uint64_t* post_dev = nullptr;
+  // box kernel arguments (pinned, mapped): arrays, lengths, variables
+  const int32_t** box_vals = nullptr;
+  int64_t* box_n = nullptr;
+  int32_t* box_nv = nullptr;
+  const int32_t** box_vals_dev = nullptr;
+  int64_t* box_n_dev = nullptr;
+  int32_t* box_nv_dev = nullptr;
+  uint64_t seq = 0;
+  // the planned batch
+  std::vector<kp_pack_task> tasks;
+  std::vector<kp_layout> layouts;
+  std::vector<int64_t> caps, slots, off;
+  std::vector<int32_t> direct;
+  size_t arena = 0;
+  bool running = false;
+  hipStream_t run_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+constexpr int PACK_MAX = 4096;
+
+size_t pack_post_words(int max_tasks) {
+  return (size_t)max_tasks * 2 * 2 * KP_MAX_VARS + 2 * (size_t)max_tasks;
+}
+
+void pack_free(kp_pack* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->table_dev) (void)hipFree(p->table_dev);
+  if (p->table_host) (void)hipHostFree(p->table_host);
+  if (p->post) (void)hipHostFree(p->post);
+  if (p->box_vals) (void)hipHostFree(p->box_vals);
+  delete p;
+}
+
+// Waits until every word of post[0..n) carries `tag` in its high half.
+kp_status pack_wait_words(kp_pack* p, const uint64_t* w, size_t n, uint64_t tag, hipStream_t s,
+                          const char* what) {
+  for (size_t i = 0; i < n; ++i) {
+    kp_status st = kp::wait_tag(p->ctx, w + i, tag, s, what);
+    if (st != KP_OK) return st;
+  }
+  return KP_OK;
+}
+}  // namespace
+
+kp_status kp_pack_create(kp_ctx* ctx, int32_t max_tasks, kp_pack** out) {
+  if (!ctx || !out) return KP_E_ARG;
+  if (!ctx->status) return kp::fail(ctx, KP_E_ARG, "host-only context");
+  if (max_tasks < 1 || max_tasks > PACK_MAX)
+    return kp::fail(ctx, KP_E_ARG, "kp_pack_create: 1..%d tasks", PACK_MAX);
+  kp_pack* p = new (std::nothrow) kp_pack;
+  if (!p) return kp::fail(ctx, KP_E_DEVICE, "out of host memory");
+  p->ctx = ctx;
+  p->max_tasks = max_tasks;
+  p->table_bytes = kp::pack_table_bytes(max_tasks);
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e == hipSuccess) e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&p->table_dev, p->table_bytes);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&p->table_host), p->table_bytes);
+  const size_t pw = pack_post_words(max_tasks);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&p->post), pw * sizeof(uint64_t),
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) {
+    std::memset(p->post, 0, pw * sizeof(uint64_t));
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p->post_dev), p->post, 0);
+  }
+  const size_t segs = 2 * (size_t)max_tasks;
+  const size_t box_bytes = segs * (sizeof(void*) + sizeof(int64_t) + sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&p->box_vals), box_bytes,
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) {
+    p->box_n = reinterpret_cast<int64_t*>(p->box_vals + segs);
+    p->box_nv = reinterpret_cast<int32_t*>(p->box_n + segs);
+    char* dev = nullptr;
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&dev), p->box_vals, 0);
+    if (e == hipSuccess) {
+      p->box_vals_dev = reinterpret_cast<const int32_t**>(dev);
+      p->box_n_dev = reinterpret_cast<int64_t*>(dev + segs * sizeof(void*));
+      p->box_nv_dev = reinterpret_cast<int32_t*>(dev + segs * (sizeof(void*) + sizeof(int64_t)));
+    }
+  }
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    pack_free(p);
+    return kp::hip_fail(ctx, e, "kp_pack_create");
+  }
+  *out = p;
+  return KP_OK;
+}
+
+kp_status kp_pack_destroy(kp_pack* p) {
+  if (!p) return KP_E_ARG;
+  if (p->running && p->run_stream) (void)hipStreamSynchronize(p->run_stream);
+  pack_free(p);
+  return KP_OK;
+}
+
+kp_status kp_pack_plan(kp_pack* p, const kp_pack_task* tasks, int32_t n, int64_t* out_cap,
+                       size_t* arena_bytes, hipStream_t stream) {
+  using namespace kp;
+  if (!p) return KP_E_ARG;
+  kp_ctx* ctx = p->ctx;
+  if (p->running) return fail(ctx, KP_E_ARG, "kp_pack_plan: the last run was not waited for");
+  if (n < 0 || n > p->max_tasks || (n > 0 && (!tasks || !out_cap)) || !arena_bytes)
+    return fail(ctx, KP_E_ARG, "kp_pack_plan: bad arguments (at most %d tasks)", p->max_tasks);
+  for (int32_t k = 0; k < n; ++k) {
+    const kp_pack_task& t = tasks[k];
+    if (t.nvars < 1 || t.nvars > KP_MAX_VARS || t.na < 0 || t.nb < 0 ||
+        t.na >= ((int64_t)1 << 31) || t.nb >= ((int64_t)1 << 31) ||
+        (t.na > 0 && (!t.a_exps || !t.a_coef)) || (t.nb > 0 && (!t.b_exps || !t.b_coef)))
+      return fail(ctx, KP_E_ARG, "kp_pack_plan: task %d has bad sizes or null arrays", (int)k);
+    if (t.dtype != KP_I64 && t.dtype != KP_F64)
+      return fail(ctx, KP_E_DTYPE, "kp_pack_plan: task %d: int64 or fp64 coefficients", (int)k);
+  }
+  p->tasks.assign(tasks, tasks + n);
+  p->layouts.assign((size_t)n, kp_layout{});
+  p->caps.assign((size_t)n, 0);
+  p->slots.assign((size_t)n, 0);
+  p->direct.assign((size_t)n, 0);
+  p->off.assign((size_t)n, 0);
+  p->arena = 0;
+  // every factor's box: one launch, one wait
+  int nseg = 0;
+  for (int32_t k = 0; k < n; ++k)
+    for (int f = 0; f < 2; ++f) {
+      const kp_pack_task& t = tasks[k];
+      p->box_vals[nseg] = f ? t.b_exps : t.a_exps;
+      p->box_n[nseg] = f ? t.nb : t.na;
+      p->box_nv[nseg] = t.nvars;
+      ++nseg;
+    }
+  if (++p->seq == 0 || (uint32_t)p->seq == 0) p->seq += 1;
+  const uint64_t tag = (uint64_t)(uint32_t)p->seq;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  hipError_t e = launch_pack_boxes(p->box_vals_dev, p->box_n_dev, p->box_nv_dev, nseg,
+                                   p->post_dev, p->seq, stream);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_pack_plan boxes");
+  size_t arena = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const kp_pack_task& t = tasks[k];
+    int32_t box[2][2 * KP_MAX_VARS];
+    for (int f = 0; f < 2; ++f) {
+      const int g = 2 * k + f;
+      const uint64_t* w = p->post + (size_t)g * 2 * KP_MAX_VARS;
+      const bool empty = (f ? t.nb : t.na) == 0;
+      for (int v = 0; v < t.nvars; ++v)
+        for (int side = 0; side < 2; ++side) {
+          int32_t x = side ? -1 : 0;   // an empty array: min 0, max -1
+          if (!empty) {
+            const uint64_t* slot = w + side * KP_MAX_VARS + v;
+            kp_status st = wait_tag(ctx, slot, tag, stream, "kp_pack_plan boxes");
+            if (st != KP_OK) return st;
+            x = (int32_t)(uint32_t)__atomic_load_n(slot, __ATOMIC_ACQUIRE);
+          }
+          box[f][side * KP_MAX_VARS + v] = x;
+        }
+    }
+    kp_layout& L = p->layouts[(size_t)k];
+    kp_status st = kp_layout_product(t.nvars, 0, box[0], box[0] + KP_MAX_VARS, box[1],
+                                     box[1] + KP_MAX_VARS, nullptr, nullptr, &L);
+    if (st != KP_OK)
+      return fail(ctx, st, "kp_pack_plan: task %d: the product's codes overflow", (int)k);
+    // bound on result terms; a hash table of at least twice as many slots, or
+    // one word per code when that is no larger
+    const int64_t pairs = t.na * t.nb;
+    const int64_t bound = L.nkeys <= 0 ? 0 : std::min<int64_t>(L.nkeys, pairs);
+    int64_t hs = 64;
+    while (hs < 2 * bound) hs <<= 1;
+    const bool dir = L.nkeys > 0 && L.nkeys <= 2 * hs;
+    p->caps[(size_t)k] = bound;
+    p->slots[(size_t)k] = bound == 0 ? 0 : (dir ? L.nkeys : hs);
+    p->direct[(size_t)k] = dir ? 1 : 0;
+    p->off[(size_t)k] = (int64_t)arena;
+    const int64_t words = p->direct[(size_t)k] ? p->slots[(size_t)k] : 2 * p->slots[(size_t)k];
+    arena += align_up(8 * (size_t)t.na) + align_up(8 * (size_t)t.nb) +
+             align_up(8 * (size_t)std::max<int64_t>(words, 1)) + ALIGN;
+    out_cap[k] = bound;
+  }
+  p->arena = arena;
+  *arena_bytes = arena;
+  return KP_OK;
+}
+
+kp_status kp_pack_run(kp_pack* p, int32_t* const* out_exps, void* const* out_coef, void* arena,
+                      size_t arena_bytes, unsigned flags, hipStream_t stream) {
+  using namespace kp;
+  if (!p) return KP_E_ARG;
+  kp_ctx* ctx = p->ctx;
+  const int n = (int)p->tasks.size();
+  if (p->running) return fail(ctx, KP_E_ARG, "kp_pack_run: the last run was not waited for");
+  if (arena_bytes < p->arena || (p->arena > 0 && !arena) || (n > 0 && (!out_exps || !out_coef)))
+    return fail(ctx, KP_E_WORKSPACE, "kp_pack_run: arena of %zu bytes, %zu needed", arena_bytes,
+                p->arena);
+  for (int k = 0; k < n; ++k)
+    if (p->caps[(size_t)k] > 0 && (!out_exps[k] || !out_coef[k]))
+      return fail(ctx, KP_E_ARG, "kp_pack_run: task %d has no output arrays", k);
+  if ((flags & KP_PACK_GRAPH) && !stream)
+    return fail(ctx, KP_E_ARG, "graph capture needs a stream other than the null stream");
+  // the table: header, unit prefixes, tasks
+  const int m = p->max_tasks;
+  PackHeader* h = reinterpret_cast<PackHeader*>(p->table_host);
+  int64_t* pre = reinterpret_cast<int64_t*>(p->table_host + sizeof(PackHeader));
+  int64_t* pre_prep = pre;
+  int64_t* pre_mul = pre + (m + 1);
+  int64_t* pre_cmp = pre + 2 * (m + 1);
+  PackTask* tt = reinterpret_cast<PackTask*>(pre + 3 * (m + 1));
+  if (++p->seq == 0 || (uint32_t)p->seq == 0) p->seq += 1;
+  h->ntasks = n;
+  h->max_tasks = m;
+  h->err = 0;
+  h->pad = 0;
+  h->seq = p->seq;
+  h->post = p->post_dev + (size_t)m * 2 * 2 * KP_MAX_VARS;
+  pre_prep[0] = pre_mul[0] = pre_cmp[0] = 0;
+  char* base = static_cast<char*>(arena);
+  for (int k = 0; k < n; ++k) {
+    const kp_pack_task& t = p->tasks[(size_t)k];
+    const size_t K = (size_t)k;
+    PackTask& T = tt[k];
+    T.la = make_dev_layout(p->layouts[K], 0);
+    T.lb = make_dev_layout(p->layouts[K], 1);
+    T.ax = t.a_exps;
+    T.bx = t.b_exps;
+    T.ac = t.a_coef;
+    T.bc = t.b_coef;
+    T.na = t.na;
+    T.nb = t.nb;
+    char* q = base + p->off[K];
+    T.ak = reinterpret_cast<int64_t*>(q);
+    q += align_up(8 * (size_t)t.na);
+    T.bk = reinterpret_cast<int64_t*>(q);
+    q += align_up(8 * (size_t)t.nb);
+    T.table = reinterpret_cast<uint64_t*>(q);
+    T.slots = p->slots[K];
+    T.direct = p->direct[K];
+    const int64_t words = T.direct ? T.slots : 2 * T.slots;
+    q += align_up(8 * (size_t)std::max<int64_t>(words, 1));
+    T.count = reinterpret_cast<unsigned long long*>(q);
+    T.f64 = t.dtype == KP_F64 ? 1 : 0;
+    T.out_x = p->caps[K] > 0 ? out_exps[k] : nullptr;
+    T.out_c = p->caps[K] > 0 ? out_coef[k] : nullptr;
+    T.out_cap = p->caps[K];
+    // multiply units: rows of A by blocks of PACK_BLOCK terms of B, about
+    // 2^14 pairs each
+    const int64_t bw = std::min<int64_t>(std::max<int64_t>(t.nb, 1), PACK_BLOCK);
+    T.rows = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(t.na, 1), 16384 / bw));
+    T.bblocks = (t.nb + PACK_BLOCK - 1) / PACK_BLOCK;
+    const int64_t live = p->caps[K] > 0 ? 1 : 0;   // an empty product makes no pairs
+    const int64_t enc = (t.na + PACK_BLOCK - 1) / PACK_BLOCK + (t.nb + PACK_BLOCK - 1) / PACK_BLOCK;
+    const int64_t clr = std::max<int64_t>(1, (words + 4 * PACK_BLOCK - 1) / (4 * PACK_BLOCK));
+    const int64_t mul = live * ((t.na + T.rows - 1) / T.rows) * T.bblocks;
+    const int64_t cmp = (T.slots + 8 * PACK_BLOCK - 1) / (8 * PACK_BLOCK);
+    pre_prep[k + 1] = pre_prep[k] + live * enc + clr;
+    pre_mul[k + 1] = pre_mul[k] + mul;
+    pre_cmp[k + 1] = pre_cmp[k] + cmp;
+    if (!live) {   // nothing to encode: the prep units are the clearing ones
+      T.na = T.nb = 0;
+    }
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  const int grid = std::max(1, ctx->num_cu * 4);
+  hipError_t e = hipSuccess;
+  if (flags & KP_PACK_GRAPH) {
+    if (!p->exec) {
+      // the upload and the four stages, captured once: the kernels read
+      // everything from the table, so every later batch replays them
+      e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        hipError_t e1 = hipMemcpyAsync(p->table_dev, p->table_host, p->table_bytes,
+                                       hipMemcpyHostToDevice, stream);
+        if (e1 == hipSuccess) e1 = launch_pack_run(p->table_dev, grid, stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(stream, &g);
+        if (e1 != hipSuccess) e = e1;
+        if (e == hipSuccess) {
+          p->graph = g;
+          e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        } else if (g) {
+          (void)hipGraphDestroy(g);
+        }
+      }
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(p->exec, stream);
+  } else {
+    e = hipMemcpyAsync(p->table_dev, p->table_host, p->table_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_pack_run(p->table_dev, grid, stream);
+  }
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kp_pack_run");
+  p->running = true;
+  p->run_stream = stream;
+  return KP_OK;
+}
+
+kp_status kp_pack_wait(kp_pack* p, int64_t* n_out) {
+  using namespace kp;
+  if (!p) return KP_E_ARG;
+  const int n = (int)p->tasks.size();
+  if (!p->running) return fail(p->ctx, KP_E_ARG, "kp_pack_wait: nothing is running");
+  if (n > 0 && !n_out) return fail(p->ctx, KP_E_ARG, "kp_pack_wait: null counts");
+  const uint64_t tag = (uint64_t)(uint32_t)p->seq;
+  const uint64_t* w = p->post + (size_t)p->max_tasks * 2 * 2 * KP_MAX_VARS;
+  kp_status st = pack_wait_words(p, w, 2 * (size_t)n, tag, p->run_stream, "kp_pack_wait");
+  p->running = false;
+  if (st != KP_OK) return st;
+  kp_status first = KP_OK;
+  for (int k = 0; k < n; ++k) {
+    const uint64_t lo = __atomic_load_n(w + 2 * k, __ATOMIC_ACQUIRE) & 0xffffffffu;
+    const uint64_t hi = __atomic_load_n(w + 2 * k + 1, __ATOMIC_ACQUIRE) & 0xffffffffu;
+    n_out[k] = (int64_t)((hi << 32) | lo);
+    if (n_out[k] < 0 && first == KP_OK) first = (kp_status)(-n_out[k]);
+  }
+  if (first != KP_OK) return fail(p->ctx, first, "kp_pack_wait: a task reported a device error");
+  return KP_OK;
+}
+
+kp_status kp_pack_query(kp_pack* p, int32_t* done) {
+  if (!p || !done) return KP_E_ARG;
+  if (!p->running) {
+    *done = 1;
+    return KP_OK;
+  }
+  const int n = (int)p->tasks.size();
+  const uint64_t tag = (uint64_t)(uint32_t)p->seq;
+  const uint64_t* w = p->post + (size_t)p->max_tasks * 2 * 2 * KP_MAX_VARS;
+  *done = 1;
+  for (int k = 0; k < 2 * n; ++k)
+    if ((__atomic_load_n(w + k, __ATOMIC_ACQUIRE) >> 32) != tag) {
+      *done = 0;
+      break;
+    }
+  if (!*done) {
+    // a stream that failed or finished without posting ends the wait
+    const hipError_t q = hipStreamQuery(p->run_stream);
+    if (q != hipSuccess && q != hipErrorNotReady) return kp::hip_fail(p->ctx, q, "kp_pack_query");
+  }
+  return KP_OK;
+}
+
 kp_status kp_encode_host(const kp_layout* layout, int which, int64_t n, const int32_t* x_exps,
                          const int32_t* y_mult, const uint8_t* is_sin, int64_t* xcodes,
                          int64_t* ycodes) {

@@ -517,6 +517,42 @@ struct RangeArgs {
 hipError_t range_setup();
 hipError_t launch_range(const RangeArgs& R, kp_dtype dt, hipStream_t s);
 
+// packed batches (kp_pack.hip): many whole Laurent products in one fixed
+// sequence of persistent launches that read a device task table
+constexpr int PACK_BLOCK = 256;
+struct PackTask {
+  DevLayout la, lb;                 // A's and B's code maps; the product's decode
+  const int32_t* ax;                // exponents [na][nx], [nb][nx]
+  const int32_t* bx;
+  const void* ac;                   // coefficients (int64 or double)
+  const void* bc;
+  int64_t na, nb;
+  int64_t* ak;                      // codes (arena)
+  int64_t* bk;
+  uint64_t* table;                  // direct: one word per code; hash: (code + 1, value) pairs
+  int64_t slots;                    // direct: codes; hash: a power of two
+  int64_t rows;                     // rows of A per multiply unit
+  int64_t bblocks;                  // blocks of PACK_BLOCK terms of B
+  int32_t direct, f64;
+  int32_t* out_x;                   // [out_cap][nx]
+  void* out_c;                      // [out_cap]
+  int64_t out_cap;
+  unsigned long long* count;        // arena
+};
+// The table: this header, then three unit prefixes of max_tasks + 1 words
+// (prep, multiply, compaction), then max_tasks tasks.
+struct PackHeader {
+  int32_t ntasks, max_tasks;
+  uint32_t err;
+  uint32_t pad;
+  uint64_t seq;                     // tag of this run's posts
+  uint64_t* post;                   // host-mapped: two tagged words per task
+};
+size_t pack_table_bytes(int max_tasks);
+hipError_t launch_pack_boxes(const int32_t* const* vals, const int64_t* n, const int32_t* nv,
+                             int nseg, uint64_t* post_dev, uint64_t seq, hipStream_t s);
+hipError_t launch_pack_run(void* table_dev, int grid, hipStream_t s);
+
 // diagnostics (kp_diag.hip)
 hipError_t probe_lds_atomic(int pattern, int blocks, int iters, unsigned long long* sink,
                             float* ms, hipStream_t s);

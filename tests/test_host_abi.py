@@ -341,3 +341,18 @@ def test_hash_plans_of_empty_and_tiny_products():
                             (small, 300, 2)):
             m, mo, ws = kp.mul_bound(lay, False, kp.KP_I64, "hash", na, nb, ctx)
             assert m == "hash" and 0 <= mo <= max(na * nb, 0) and ws >= 0
+
+
+def test_pack_needs_a_device_context():
+    """kp_pack_create refuses a host-only context and bad sizes before
+    touching a device; null handles are argument errors."""
+    import ctypes as C
+    ctx = _host_ctx()
+    h = C.c_void_p()
+    L = kp.lib()
+    assert L.kp_pack_create(ctx.h, 4, C.byref(h)) == kp.KP_E_ARG
+    assert L.kp_pack_create(None, 4, C.byref(h)) == kp.KP_E_ARG
+    assert L.kp_pack_destroy(None) == kp.KP_E_ARG
+    assert L.kp_pack_wait(None, None) == kp.KP_E_ARG
+    d = C.c_int32()
+    assert L.kp_pack_query(None, C.byref(d)) == kp.KP_E_ARG
