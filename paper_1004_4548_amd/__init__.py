@@ -382,13 +382,19 @@ def encode(layout, which, x, y=None, t=None, ctx=None, flags=0):
     return kx, ky
 
 
-def decode(layout, codes, poisson=False, ctx=None, flags=0):
-    """kp_decode: product codes (or Poisson keys) back to exponents."""
+def decode(layout, codes, poisson=False, ctx=None, flags=0, out=None):
+    """kp_decode: product codes (or Poisson keys) back to exponents (into
+    `out`, int32 [n, nx], when given: Laurent codes only)."""
     import torch
     ctx = ctx or context()
     _dev_check(codes, torch.int64, "codes")
     n = codes.shape[0]
-    x = torch.empty((n, layout.nx), dtype=torch.int32, device=codes.device)
+    if out is not None:
+        if poisson or tuple(out.shape) != (n, layout.nx) or out.dtype != torch.int32:
+            raise ValueError("out must be int32 [n, nx] for Laurent codes")
+        x = out
+    else:
+        x = torch.empty((n, layout.nx), dtype=torch.int32, device=codes.device)
     y = t = None
     if poisson:
         y = torch.empty((n, layout.ny), dtype=torch.int32, device=codes.device)
@@ -826,9 +832,17 @@ class Pack:
             _lib.kp_pack_destroy(self.h)
             self.h = None
 
-    def launch(self, products, graph=False, stream=None):
+    def launch(self, products, graph=False, stream=None, alloc=None):
         """Plans the products [(Poly a, Poly b), ...] (one host wait for every
-        factor's box) and queues them on `stream` (default: the current one)."""
+        factor's box) and queues them on `stream` (default: the current one).
+        `alloc(numel, dtype)` supplies the device buffers (results and arena)
+        when given, else they are new tensors."""
+        self.plan(products, graph, stream)
+        self.run(alloc)
+
+    def plan(self, products, graph=False, stream=None):
+        """kp_pack_plan: the products' bounds (list) and the device bytes that
+        run() allocates (results and arena), without queueing them."""
         import torch
         n = len(products)
         tasks = (PackTask * max(n, 1))()
@@ -854,12 +868,23 @@ class Pack:
         self.ctx.check(lib().kp_pack_plan(self.h, tasks, n, caps, C.byref(ab),
                                           C.c_void_p(run_on.cuda_stream)))
         caps = [int(caps[k]) for k in range(n)]
+        nx = sum(c * a.nv for c, (a, _) in zip(caps, products))
+        al = lambda x: (x + 255) & ~255
+        need = al(4 * max(nx, 1)) + al(8 * max(sum(caps), 1)) + al(max(ab.value, 256))
+        self._planned = (products, caps, ab.value, nx, graph, cur, run_on)
+        return caps, need
+
+    def run(self, alloc=None):
+        """kp_pack_run of the planned products."""
+        import torch
+        products, caps, ab, nx, graph, cur, run_on = self._planned
+        n = len(products)
         with torch.cuda.stream(run_on):
             dev = cur.device
-            nx = sum(c * a.nv for c, (a, _) in zip(caps, products))
-            X = torch.empty(max(nx, 1), dtype=torch.int32, device=dev)
-            V = torch.empty(max(sum(caps), 1), dtype=torch.int64, device=dev)
-            arena = torch.empty(max(ab.value, 256), dtype=torch.uint8, device=dev)
+            new = alloc or (lambda n_, dt: torch.empty(n_, dtype=dt, device=dev))
+            X = new(max(nx, 1), torch.int32)
+            V = new(max(sum(caps), 1), torch.int64)
+            arena = new(max(ab, 256), torch.uint8)
         ox, oc, views, px, pc = (C.c_void_p * max(n, 1))(), (C.c_void_p * max(n, 1))(), [], 0, 0
         for k, (a, _) in enumerate(products):
             x = X[px:px + caps[k] * a.nv].view(caps[k], a.nv)
@@ -870,11 +895,12 @@ class Pack:
             views.append((x, v))
             px += caps[k] * a.nv
             pc += caps[k]
-        self.ctx.check(lib().kp_pack_run(self.h, ox, oc, C.c_void_p(arena.data_ptr()), ab.value,
+        self.ctx.check(lib().kp_pack_run(self.h, ox, oc, C.c_void_p(arena.data_ptr()), ab,
                                          KP_PACK_GRAPH if graph else 0,
                                          C.c_void_p(run_on.cuda_stream)))
         if run_on is not cur:
             cur.wait_stream(run_on)
+        self._planned = None
         self._run = (products, views, arena, n)
 
     def ready(self):

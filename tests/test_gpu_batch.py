@@ -118,8 +118,10 @@ def test_served_alone_equals_in_a_mix():
     say("stream requests", [(q["type"], q["nv"], len(q["a"][1]), len(q["b"][1])) for q in reqs])
     st = serve.stage(reqs)
     alone, _ = serve.run_per_call(st)
-    mixed = serve.run_batch(st)
+    # one batch: products of at most 50,000 pairs in a pack, the others one by one
+    mixed = serve.run_batch(st, pack_pairs=50_000)
     # continuous batching: batches of 3 on 3 streams, overlapping on the device
+    # (every product in the slots' packs, replayed graphs)
     _, served, _ = serve.serve_stream(st, np.zeros(len(st)), max_batch=3, slots=3)
     for q, x, y in zip(reqs, alone, served):
         ex, cx = x.exps.cpu().numpy(), x.coef.cpu().numpy()
@@ -138,6 +140,61 @@ def test_served_alone_equals_in_a_mix():
         if q["dtype"] == "i64":
             assert np.array_equal(cx[ox], cy[oy]), q["id"]
         _oracle_check(q["a"], q["b"], ey, cy, f"request {q['id']}")
+
+
+def _gpu_keys(e, lo, w):
+    import torch
+    k = torch.zeros(e.shape[0], dtype=torch.int64, device=e.device)
+    m = 1
+    for v in range(e.shape[1]):
+        k += (e[:, v].long() - int(lo[v])) * m
+        m *= int(w[v])
+    return k
+
+
+def test_served_stream_equals_per_call():
+    """The first 300 requests of the bench's stream, less those of more than
+    2e7 pairs (264 requests, 6e8 pairs): served by continuous batching (packs
+    and per-product kernels, 3 slots) against one call each, compared on the
+    device.  int64: the same terms bit for bit.  fp64: the same keys, and each
+    coefficient within 2e-13 of the term's sum of |contributions| (each side is
+    within 1e-13 of the exact sum), that sum taken from the product of the
+    factors' absolute values."""
+    import torch
+    reqs = [q for q in (I.request(r) for r in range(300))
+            if len(q["a"][1]) * len(q["b"][1]) <= 2e7]
+    say("served stream against single calls,", len(reqs), "requests")
+    st = serve.stage(reqs)
+    alone, _ = serve.run_per_call(st)
+    _, served, _ = serve.serve_stream(st, np.zeros(len(st)), max_batch=16, slots=3)
+    for q, s, x, y in zip(reqs, st, alone, served):
+        what = f"request {q['id']} type {q['type']} {q['dtype']}"
+        assert x.exps.shape == y.exps.shape, what
+        if x.exps.shape[0] == 0:
+            continue
+        both = torch.cat([x.exps, y.exps])
+        lo = both.min(0).values.cpu().numpy()
+        w = (both.max(0).values.cpu().numpy() - lo + 1).astype(np.float64)
+        assert np.prod(w) < 2.0**62, what
+        kx, ox = torch.sort(_gpu_keys(x.exps, lo, w))
+        ky, oy = torch.sort(_gpu_keys(y.exps, lo, w))
+        assert torch.equal(kx, ky), what
+        cx, cy = x.coef[ox], y.coef[oy]
+        if q["dtype"] == "i64":
+            assert torch.equal(cx, cy), what
+            continue
+        pa = kp.Poly(s.a.exps, s.a.coef.abs())
+        pb = kp.Poly(s.b.exps, s.b.coef.abs())
+        z, _ = kp.mul_laurent(pa, pb)
+        # the absolute product covers every key of the product (and more)
+        zlo = torch.minimum(z.exps.min(0).values, both.min(0).values).cpu().numpy()
+        zw = (torch.maximum(z.exps.max(0).values, both.max(0).values).cpu().numpy() - zlo + 1)
+        zk, oz = torch.sort(_gpu_keys(z.exps, zlo, zw.astype(np.float64)))
+        kk = _gpu_keys(x.exps[ox], zlo, zw.astype(np.float64))
+        pos = torch.searchsorted(zk, kk)
+        assert torch.equal(zk[pos], kk), what
+        bound = 2e-13 * z.coef[oz][pos]
+        assert bool(((cx - cy).abs() <= bound).all()), what
 
 
 def test_open_loop_serves_every_request():
