@@ -839,11 +839,9 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
     const unsigned long long key = (unsigned long long)code + 1;
     uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, l2);
     for (int q = 0; q < BIN_SLOTS; ++q) {
-      unsigned long long c = keys[slot];
-      if (c == 0) {
-        c = atomicCAS(&keys[slot], 0ull, key);
-        if (c == 0) c = key;
-      }
+      // one compare-and-swap claims an empty slot or returns its key
+      unsigned long long c = atomicCAS(&keys[slot], 0ull, key);
+      if (c == 0) c = key;
       if (c == key) {
         lds_slot_add(&vals[slot], v);
         ++ins;

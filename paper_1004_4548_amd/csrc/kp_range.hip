@@ -591,8 +591,9 @@ __device__ __forceinline__ void entry_at(const RangeArgs& R, bool pack, int w, i
 // call's counter.
 template <typename T, int LOG>
 __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
+  using K = unsigned long long;
   constexpr int SLOTS = 1 << LOG, NT = SLOTS / BIN_PER;
-  __shared__ unsigned long long keys[SLOTS];
+  __shared__ K keys[SLOTS];
   __shared__ uint64_t vwords[SLOTS];
   T* vals = reinterpret_cast<T*>(vwords);
   __shared__ int64_t s_wave[NT / 64];
@@ -628,14 +629,12 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over
   const auto insert = [&](uint64_t h, T v, uint64_t ilo, uint64_t ihi) {
     if (h < ilo || h > ihi) return;
-    const unsigned long long key = h + 1;
+    const K key = (K)(h + 1);
     uint32_t slot = (uint32_t)((h * GOLD) >> (64 - LOG));
     for (int q = 0; q < SLOTS; ++q) {
-      unsigned long long c = keys[slot];
-      if (c == 0) {
-        c = atomicCAS(&keys[slot], 0ull, key);
-        if (c == 0) c = key;
-      }
+      // one compare-and-swap claims an empty slot or returns its key
+      K c = atomicCAS(&keys[slot], (K)0, key);
+      if (c == 0) c = key;
       if (c == key) {
         lds_add(&vals[slot], v);
         ++ins;
@@ -653,7 +652,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   // compacts the table, writes its nonzero terms after the `done` already
   // written for this bin, leaves the table cleared; returns the count
   const auto emit = [&](int64_t done) -> int64_t {
-    unsigned long long kk[BIN_PER];
+    K kk[BIN_PER];
     T vv[BIN_PER];
     uint64_t ball[BIN_PER];
     int64_t cnt = 0;
@@ -691,7 +690,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
     const int64_t m = min(tot, R.out_cap - base);
     for (int64_t t = tid; t < m; t += NT) {
       const int64_t q = base + t;
-      const uint64_t code = (uint64_t)lo + (((keys[t] - 1) * inv) & mw);
+      const uint64_t code = (uint64_t)lo + ((((uint64_t)keys[t] - 1) * inv) & mw);
       if (R.out_x) {
         uint64_t c = code;
         if (pairs) {
@@ -919,8 +918,8 @@ __global__ void __launch_bounds__(SMALL_BLOCK) k_rg_fixmove(RangeArgs R) {
 
 template <typename T, int LOG>
 void launch_bins(const RangeArgs& R, hipStream_t s) {
-  hipLaunchKernelGGL((k_rg_bins<T, LOG>), dim3((unsigned)R.nbins_max), dim3((1 << LOG) / BIN_PER), 0,
-                     s, R);
+  hipLaunchKernelGGL((k_rg_bins<T, LOG>), dim3((unsigned)R.nbins_max), dim3((1 << LOG) / BIN_PER),
+                     0, s, R);
 }
 
 template <typename T>
