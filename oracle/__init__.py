@@ -234,6 +234,20 @@ def poisson_mul(a, b, nx, ny, row_begin=0, row_end=-1, threads=1):
     return x, y, t, co, ab
 
 
+def poisson_mul_truncated(a, b, nx, ny, weights, max_order, threads=1):
+    """Truncated Poisson product by the order of the Fourier harmonics (one of
+    the truncation criteria Section 3 names): the terms of A*B whose weighted
+    harmonic order sum_k weights[k] * |j_k| is at most max_order (weights >= 0;
+    trigonometric variables past len(weights) have weight 0).  Definition
+    applied literally: the full product, then the filter.  Same return layout
+    as ``poisson_mul``."""
+    x, y, t, co, ab = poisson_mul(a, b, nx, ny, threads=threads)
+    w = np.zeros(ny, dtype=np.int64)
+    w[:min(len(weights), ny)] = np.asarray(weights, dtype=np.int64)[:ny]
+    keep = np.abs(y.astype(np.int64)) @ w <= max_order
+    return x[keep], y[keep], t[keep], co[keep], ab[keep]
+
+
 def poisson_coeff_at(a, b, nx, ny, qx, qy, qt):
     """Coefficient of each queried (x, j, is_sin) term of A*B, one by one."""
     lib = _load()

@@ -403,6 +403,93 @@ def test_truncated_limits():
     assert (part[0][:, 1] <= 3).all() and part[0][:, 0].max() > 3
 
 
+# ------------------------------------------------ truncation by harmonic order
+def _cos_sum_squared():
+    # (cos y1 + cos y2)^2 = 1 + 1/2 cos 2y1 + 1/2 cos 2y2 + cos(y1 + y2) + cos(y1 - y2)
+    s = (np.zeros((2, 1), np.int32), np.array([[1, 0], [0, 1]], np.int32),
+         np.zeros(2, np.uint8), np.array([1.0, 1.0]))
+    return s
+
+
+@pytest.mark.parametrize("w,H,want", [
+    ([1, 2], 3, {(0, 0): 1.0, (2, 0): 0.5, (1, 1): 1.0, (1, -1): 1.0}),
+    ([1, 2], 2, {(0, 0): 1.0, (2, 0): 0.5}),
+    ([1, 1], 1, {(0, 0): 1.0}),
+    ([1, 1], 2, {(0, 0): 1.0, (2, 0): 0.5, (0, 2): 0.5, (1, 1): 1.0, (1, -1): 1.0}),
+    ([0, 1], 0, {(0, 0): 1.0, (2, 0): 0.5}),
+])
+def test_harmonic_truncation_closed_form(w, H, want):
+    """(cos y1 + cos y2)^2 cut at weighted harmonic order H: the terms of the
+    closed form whose order sum_k w_k |j_k| is at most H."""
+    s = _cos_sum_squared()
+    x, y, t, c, _ = O.poisson_mul_truncated(s, s, 1, 2, w, H)
+    got = {tuple(int(v) for v in j): float(v) for j, v, tt in zip(y, c, t) if v != 0}
+    assert (t == 0).all()
+    assert got == want
+
+
+def _werner_pieces(ja, ta, jb, tb, c):
+    """The two pieces of one pair (Section 2, with the factor 1/2), each folded
+    to canonical form: [(j, is_sin, coefficient)]."""
+    d = tuple(p - q for p, q in zip(ja, jb))
+    s = tuple(p + q for p, q in zip(ja, jb))
+    h = 0.5 * c
+    if not ta and not tb:
+        raw = [(d, 0, h), (s, 0, h)]
+    elif ta and tb:
+        raw = [(d, 0, h), (s, 0, -h)]
+    elif ta and not tb:
+        raw = [(s, 1, h), (d, 1, h)]
+    else:
+        raw = [(s, 1, h), (d, 1, -h)]
+    out = []
+    for j, t, v in raw:
+        nz = [q for q in j if q != 0]
+        if nz and nz[0] < 0:
+            j = tuple(-q for q in j)
+            if t:
+                v = -v
+        if t and not nz:
+            continue
+        out.append((j, t, v))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_harmonic_truncation_brute_force(seed):
+    """Each piece tested against the order limit before it contributes (in
+    Python, written from the product-to-sum rule), against the oracle's
+    product-then-filter."""
+    nx, ny = 1, 3
+    a = I.poisson_random(nx=nx, ny=ny, n=30, xlo=-2, xhi=2, jmax=3, coef="f64int", cfg=91 + seed,
+                         factor=0)
+    b = I.poisson_random(nx=nx, ny=ny, n=25, xlo=-2, xhi=2, jmax=3, coef="f64int", cfg=91 + seed,
+                         factor=1)
+    w, H = [1, 2, 1], 5 + seed
+    acc = {}
+    for xa, ja, ta, ca in zip(a[0].tolist(), a[1].tolist(), a[2].tolist(), a[3].tolist()):
+        for xb, jb, tb, cb in zip(b[0].tolist(), b[1].tolist(), b[2].tolist(), b[3].tolist()):
+            xs = tuple(p + q for p, q in zip(xa, xb))
+            for j, t, v in _werner_pieces(ja, ta, jb, tb, ca * cb):
+                if sum(wk * abs(q) for wk, q in zip(w, j)) > H:
+                    continue
+                k = (xs, j, t)
+                acc[k] = acc.get(k, 0.0) + v
+    want = {k: v for k, v in acc.items() if v != 0}
+    x, y, t, c, _ = O.poisson_mul_truncated(a, b, nx, ny, w, H)
+    got = {(tuple(xx), tuple(yy), int(tt)): float(cc)
+           for xx, yy, tt, cc in zip(x.tolist(), y.tolist(), t.tolist(), c.tolist()) if cc != 0}
+    assert got == want   # integer-valued halves: exact in fp64
+
+
+def test_harmonic_truncation_limits():
+    a, b = I.config(4, scale=0.01)
+    full = O.poisson_mul(a, b, 3, 6)
+    top = O.poisson_mul_truncated(a, b, 3, 6, [1] * 6, 10**6)
+    assert all(np.array_equal(u, v) for u, v in zip(full, top))
+    assert len(O.poisson_mul_truncated(a, b, 3, 6, [1] * 6, -1)[3]) == 0
+
+
 # ------------------------------------------------------------ exact (128-bit) products
 def _signed128(v):
     v %= 1 << 128
