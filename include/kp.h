@@ -210,6 +210,19 @@ kp_status kp_ctx_timing_read(kp_ctx* ctx, double* total_ms, int64_t* launches);
    plan calls) include the truncation tables while one is set. */
 kp_status kp_ctx_set_truncation(kp_ctx* ctx, int32_t nvars, const int32_t* weights,
                                 int64_t max_degree);
+/* Truncation of Poisson products by the order of the Fourier harmonics
+   (another criterion Section 3 names).  While set, Poisson products computed
+   with this context keep only the terms whose weighted harmonic order
+   sum_k weights[k] * |j_k| is at most max_order (trigonometric variables from
+   ny on have weight 0).  A pair of terms whose orders differ by more than
+   max_order makes no piece (both of its pieces' orders are at least that
+   difference); the other pieces are formed and the terms over the limit are
+   dropped where the sums are compacted.  Such products run in hash mode in
+   the grouped layout (the automatic mode; KP_DENSE is KP_E_MODE).  weights: ny
+   (1..KP_MAX_VARS) values in [0, 2^15].  Laurent products are unaffected.
+   kp_ctx_clear_truncation removes it (and the Laurent one). */
+kp_status kp_ctx_set_harmonic_truncation(kp_ctx* ctx, int32_t ny, const int32_t* weights,
+                                         int64_t max_order);
 kp_status kp_ctx_clear_truncation(kp_ctx* ctx);
 
 /* Hash-table statistics (Section 3.2: open addressing with linear probing).

@@ -46,7 +46,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_ctx_get_tune", "kp_ctx_set_tu
             "kp_plan_laurent", "kp_mul_laurent_exps", "kp_plan_poisson", "kp_mul_poisson_exps",
             "kp_mul_laurent_auto", "kp_ctx_set_truncation", "kp_ctx_clear_truncation",
             "kp_mul_laurent_noalloc", "kp_pack_create", "kp_pack_destroy", "kp_pack_plan",
-            "kp_pack_run", "kp_pack_wait", "kp_pack_query"]
+            "kp_pack_run", "kp_pack_wait", "kp_pack_query", "kp_ctx_set_harmonic_truncation"]
 
 
 class PackTask(C.Structure):
@@ -152,6 +152,7 @@ def lib():
         "kp_pack_wait": (i32, [p, C.POINTER(i64)]),
         "kp_pack_query": (i32, [p, C.POINTER(i32)]),
         "kp_ctx_set_truncation": (i32, [p, i32, C.POINTER(i32), i64]),
+        "kp_ctx_set_harmonic_truncation": (i32, [p, i32, C.POINTER(i32), i64]),
         "kp_ctx_clear_truncation": (i32, [p]),
         "kp_plan_poisson": (i32, [p, i32, i32, i32, p, p, i64, p, p, i64, C.POINTER(Layout),
                                   C.POINTER(i32), C.POINTER(i64), C.POINTER(sz), p]),
@@ -282,6 +283,26 @@ class Context:
         @contextlib.contextmanager
         def scope():
             self.set_truncation(weights, max_degree)
+            try:
+                yield self
+            finally:
+                self.clear_truncation()
+        return scope()
+
+    def set_harmonic_truncation(self, weights, max_order):
+        """Keep only Poisson product terms with sum(w * |j|) <= max_order."""
+        w = [int(x) for x in weights]
+        arr = (C.c_int32 * len(w))(*w)
+        self.check(lib().kp_ctx_set_harmonic_truncation(self.h, len(w), arr, int(max_order)))
+
+    def harmonic_truncation(self, weights, max_order):
+        """Context manager: a harmonic-order truncation for the Poisson
+        products inside the block."""
+        import contextlib
+
+        @contextlib.contextmanager
+        def scope():
+            self.set_harmonic_truncation(weights, max_order)
             try:
                 yield self
             finally:

@@ -32,6 +32,8 @@ struct kp_ctx {
   std::mutex mb_mu;                   // serialises mailbox users
   bool trunc_on = false;              // truncation of Laurent products by weighted degree
   kp::TruncSpec trunc{};
+  bool harm_on = false;               // truncation of Poisson products by harmonic order
+  kp::HarmonicSpec harm{};
   void* scratch = nullptr;            // device address of this device's scratch array
   hipError_t scratch_err = hipSuccess;
 };
@@ -287,6 +289,7 @@ struct Plan {
   int rows = 0, l1 = 1, l2 = 0, blog = 11;   // blog: log2 of a bin's LDS slots
   int64_t nblocks = 0, nprod = 0;
   bool trunc = false;   // truncation tables follow the mode's workspace
+  bool harm = false;    // Poisson truncation by harmonic order (term orders in the workspace)
   int cw = 1;           // 64-bit words per result coefficient (2 for KP_I128)
   // bucketed table: slots per bucket, buckets, overflow slots, term order
   bool bucket = false;
@@ -589,6 +592,10 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     h->pp.bm = c.take<int64_t>(nb);
     h->pp.bkx = c.take<int64_t>(nb);
     h->pp.bt = c.take<uint8_t>(nb);
+    if (p.harm) {
+      h->pp.ao = c.take<int32_t>(na);
+      h->pp.bo = c.take<int32_t>(nb);
+    }
   }
 }
 
@@ -637,9 +644,12 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     d.items_cap = dense_ok ? (int64_t)items : 0;
   }
   kp_mode m = mode;
+  const bool harm = poisson && ctx->harm_on;
+  if (harm && m == KP_DENSE)
+    return fail(ctx, KP_E_MODE, "a Poisson product truncated by harmonic order runs in hash mode");
   if (m == KP_AUTO) {
     double budget = ctx->tune.dense_keys_per_pair * (double)contrib;
-    m = (dense_ok && (double)dn <= budget) ? KP_DENSE : KP_HASH;
+    m = (!harm && dense_ok && (double)dn <= budget) ? KP_DENSE : KP_HASH;
   }
   if (m == KP_DENSE && !dense_ok)
     return fail(ctx, KP_E_MODE,
@@ -648,6 +658,7 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                 (long long)std::min<int64_t>(ctx->tune.dense_max_keys, DENSE_MAX_CODES));
   p->mode = m;
   p->trunc = ctx->trunc_on && !poisson;
+  p->harm = harm;
   Carver c;
   if (m == KP_DENSE) {
     carve_dense<false>(c, *p, na, nbd, nullptr);
@@ -688,8 +699,10 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
     // (128-bit sums: the grouped entries carry 32-bit term indices, and the
     // bins' LDS tables of 24-byte slots hold at most 4096)
     const bool idx32 = na < ((int64_t)1 << 32) && nb < ((int64_t)1 << 32);
+    // (a harmonic truncation always takes the grouped layout, whose bins
+    // drop the terms over the limit)
     p->radix = !p->bucket && (dt != KP_I128 || idx32) &&
-               (ctx->tune.hash_partitioned == 2 ||
+               (harm || ctx->tune.hash_partitioned == 2 ||
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
     // (a wavefront scans the interval lengths of 64 rows in 32 bits)
@@ -872,9 +885,28 @@ kp_status kp_ctx_set_truncation(kp_ctx* ctx, int32_t nvars, const int32_t* weigh
   return KP_OK;
 }
 
+kp_status kp_ctx_set_harmonic_truncation(kp_ctx* ctx, int32_t ny, const int32_t* weights,
+                                         int64_t max_order) {
+  using namespace kp;
+  if (!ctx) return KP_E_ARG;
+  if (ny < 1 || ny > KP_MAX_VARS || !weights)
+    return fail(ctx, KP_E_ARG, "kp_ctx_set_harmonic_truncation: 1..%d weights", KP_MAX_VARS);
+  HarmonicSpec h{};
+  for (int v = 0; v < ny; ++v) {
+    if (weights[v] < 0 || weights[v] > (1 << 15))
+      return fail(ctx, KP_E_ARG, "kp_ctx_set_harmonic_truncation: weights must lie in [0, 2^15]");
+    h.w[v] = weights[v];
+  }
+  h.max_order = max_order;
+  ctx->harm = h;
+  ctx->harm_on = true;
+  return KP_OK;
+}
+
 kp_status kp_ctx_clear_truncation(kp_ctx* ctx) {
   if (!ctx) return KP_E_ARG;
   ctx->trunc_on = false;
+  ctx->harm_on = false;
   return KP_OK;
 }
 
@@ -1390,13 +1422,20 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
   hipError_t e = launch_meta_init(h.meta, stream);
   if (na > 0 && nb > 0 && layout->nkeys > 0 && p.radix) {
     if (timed) std::tie(H.ev0, H.ev1) = timing_pair(ctx);
+    const DevLayout dec = make_dev_layout(*layout, 0);
     if (e == hipSuccess)
-      e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream);
+      e = launch_poisson_prep(layout->Wx, a_x, a_y, a_sin, na, b_x, b_y, b_sin, nb, h.pp, stream,
+                              p.harm ? &dec : nullptr, p.harm ? &ctx->harm : nullptr);
     RadixArgs R{nullptr, a_coef, na, nullptr, b_coef, nb, layout->Wx, h.pp, p.rows, p.l1,
                 p.l2, 0, h.counts, h.pstart, h.bstart, h.ent1, h.ent2, h.meta, out_keys,
                 out_coef, out_cap, H.stats, H.ev0, H.ev1};
     R.bin_log = p.blog;
     R.bin1 = h.bin1;
+    R.dec = dec;
+    if (p.harm) {
+      R.harm_on = 1;
+      R.harm = ctx->harm;
+    }
     if (po) {
       R.out_x = po->x;
       R.out_y = po->y;

@@ -201,23 +201,40 @@ k_hash_laurent(uint64_t* __restrict__ table, uint64_t cap, int64_t max_probe, Me
   if (stats) add_stats(stats, ins, extra);
 }
 
+// Harmonic order of a factor's term, saturated to int32.
+__device__ __forceinline__ int32_t term_order(const DevLayout& L, const HarmonicSpec& H,
+                                              int64_t ky) {
+  const int64_t o = harmonic_order(L, (uint64_t)(ky < 0 ? -ky : ky), H);
+  return (int32_t)min(o, (int64_t)INT_MAX);
+}
+
 __global__ void __launch_bounds__(HASH_BLOCK)
 k_poisson_prep(int64_t Wx, const int64_t* __restrict__ ax, const int64_t* __restrict__ ay,
                const uint8_t* __restrict__ as, int64_t na, const int64_t* __restrict__ bx,
                const int64_t* __restrict__ by, const uint8_t* __restrict__ bs, int64_t nb,
-               PoissonPrep P) {
+               PoissonPrep P, DevLayout L, HarmonicSpec H, int harm_on) {
   const int64_t g = (int64_t)blockIdx.x * HASH_BLOCK + threadIdx.x;
   if (g < na) {
     P.ap[g] = ax[g] + Wx * ay[g];
     P.akx[g] = ax[g];
     P.at[g] = as[g];
+    if (harm_on) P.ao[g] = term_order(L, H, ay[g]);
   } else if (g < na + nb) {
     const int64_t j = g - na;
     P.bp[j] = bx[j] + Wx * by[j];
     P.bm[j] = bx[j] - Wx * by[j];
     P.bkx[j] = bx[j];
     P.bt[j] = bs[j];
+    if (harm_on) P.bo[j] = term_order(L, H, by[j]);
   }
+}
+
+// A truncated pair makes no piece when its factors' orders differ by more
+// than the limit: both pieces' orders are at least that difference.
+__device__ __forceinline__ bool pair_over(const RadixArgs& R, int64_t i, int64_t j) {
+  if (!R.harm_on) return false;
+  const int64_t d = (int64_t)R.P.ao[i] - (int64_t)R.P.bo[j];
+  return (d < 0 ? -d : d) > R.harm.max_order;
 }
 
 // Key and signed value of one piece; false when the piece vanishes.
@@ -390,6 +407,7 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
     const int tb = R.P.bt[j];
     const double cb = static_cast<const double*>(R.bc)[j];
     for (int64_t i = i0; i < i1; ++i) {
+      if (pair_over(R, i, j)) continue;
       const int ta = R.P.at[i];
       const double h = 0.5 * (ac[i] * cb);
       if (h == 0.0) continue;
@@ -455,6 +473,7 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
         }
       }
       if (r0 + u >= r1) break;
+      if (pair_over(R, r0 + u, j)) continue;
       const int ta = at[u & 1];
       const double h = 0.5 * (ca[u & 1] * cb);
       if (h == 0.0) continue;
@@ -870,7 +889,13 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
       const int i = r * BIN_BLOCK + tid;
       kk[r] = keys[i];
       vv[r] = vals[i];
-      ball[r] = __ballot(kk[r] != 0 && vv[r] != T(0));
+      bool keep = kk[r] != 0 && vv[r] != T(0);
+      // a truncated Poisson product drops the terms over the order limit
+      // (key: 2 (kx + Wx |ky|) + is_sin)
+      if (R.harm_on && keep)
+        keep = harmonic_order(R.dec, fdiv((uint64_t)(kk[r] - 1) >> 1, R.dec.dWx), R.harm) <=
+               R.harm.max_order;
+      ball[r] = __ballot(keep);
       cnt += __popcll(ball[r]);
     }
     if (lane == 0) s_wave[wave] = cnt;
@@ -1172,11 +1197,14 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
 
 hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay, const uint8_t* as,
                                int64_t na, const int64_t* bx, const int64_t* by,
-                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s) {
+                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s,
+                               const DevLayout* L, const HarmonicSpec* H) {
   const int64_t n = na + nb;
   if (n == 0) return hipSuccess;
+  const int harm_on = L && H && P.ao && P.bo ? 1 : 0;
   hipLaunchKernelGGL(k_poisson_prep, dim3((unsigned)((n + HASH_BLOCK - 1) / HASH_BLOCK)),
-                     dim3(HASH_BLOCK), 0, s, Wx, ax, ay, as, na, bx, by, bs, nb, P);
+                     dim3(HASH_BLOCK), 0, s, Wx, ax, ay, as, na, bx, by, bs, nb, P,
+                     harm_on ? *L : DevLayout{}, harm_on ? *H : HarmonicSpec{}, harm_on);
   return hipGetLastError();
 }
 

@@ -191,6 +191,24 @@ __host__ __device__ inline void decode_y(const DevLayout& L, uint64_t u, int32_t
   for (int v = L.ny - 1; v >= 0; --v) j[v] = decode_y_step(L, v, u);
 }
 
+// Truncation of Poisson products by weighted harmonic order
+// sum_k w_k |j_k| <= max_order (weights >= 0).
+struct HarmonicSpec {
+  int32_t w[KP_MAX_VARS];
+  int64_t max_order;
+};
+// Order of the trigonometric part whose code is +-u (u = |ky|), saturated
+// to int32 range.
+__host__ __device__ inline int64_t harmonic_order(const DevLayout& L, uint64_t u,
+                                                  const HarmonicSpec& H) {
+  int64_t o = 0;
+  for (int v = L.ny - 1; v >= 0; --v) {
+    const int32_t d = decode_y_step(L, v, u);
+    o += (int64_t)H.w[v] * (d < 0 ? -(int64_t)d : (int64_t)d);
+  }
+  return o;
+}
+
 // ------------------------------------------------------------ wave helpers
 #if defined(__HIPCC__)
 __device__ inline uint32_t wave_or(uint32_t v) {
@@ -405,10 +423,13 @@ hipError_t launch_hash_laurent(const HashBufs& H, kp_dtype dt, const int64_t* ak
 struct PoissonPrep {
   int64_t* ap; int64_t* akx; uint8_t* at;     // A: kx + Wx ky, kx, is_sin
   int64_t* bp; int64_t* bm; int64_t* bkx; uint8_t* bt;  // B: kx + Wx ky, kx - Wx ky, kx, is_sin
+  int32_t* ao; int32_t* bo;   // harmonic orders of A's and B's terms (truncated products)
 };
+// H: optional harmonic truncation (the orders are then written, from L).
 hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay, const uint8_t* as,
                                int64_t na, const int64_t* bx, const int64_t* by,
-                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s);
+                               const uint8_t* bs, int64_t nb, const PoissonPrep& P, hipStream_t s,
+                               const DevLayout* L = nullptr, const HarmonicSpec* H = nullptr);
 hipError_t launch_hash_poisson(const HashBufs& H, int64_t Wx, const PoissonPrep& P,
                                const double* ac, int64_t na, const double* bc, int64_t nb,
                                int rows, hipStream_t s);
@@ -464,6 +485,11 @@ struct RadixArgs {
   uint16_t* bin1 = nullptr;   // [products] level-2 bin of each entry of ent1
   int32_t* out_y = nullptr;   // optional (Poisson, with out_x and out_t): decoded
   uint8_t* out_t = nullptr;   // trigonometric exponents and sin flags instead of keys
+  // optional (Poisson): truncation by harmonic order; a pair whose factors'
+  // orders (P.ao, P.bo) differ by more than the limit makes no piece, and the
+  // bins drop the terms over it (dec decodes the keys)
+  int32_t harm_on = 0;
+  HarmonicSpec harm{};
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64), 3 Laurent int64
 // factors with exact 128-bit sums (entries carry the pair's indices, the bins

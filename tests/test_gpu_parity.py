@@ -422,6 +422,52 @@ def check_poisson(a, b, what, nx=3, ny=6, mode="auto"):
     return gx, gy, gt, gc
 
 
+@pytest.mark.parametrize("w,H", [([1] * 6, 6), ([1] * 6, 12), ([1, 2, 1, 0, 3, 1], 10),
+                                 ([1] * 6, 0), ([1] * 6, -1), ([1] * 6, 10**6)])
+def test_poisson_harmonic_truncation_matches_oracle(w, H):
+    """Truncation by weighted harmonic order: the whole-product path and the
+    codes path (grouped hash, automatic mode) against the oracle's full
+    product filtered; the limit 0 keeps the terms without harmonics, -1 none,
+    a huge one all."""
+    ctx = kp.context()
+    a, b = I.config(4, scale=0.06)
+    say("poisson truncated by harmonic order", w, H, len(a[3]), "x", len(b[3]))
+    ox, oy, ot, oc, oab = O.poisson_mul_truncated(a, b, 3, 6, w, H, threads=4)
+    with ctx.harmonic_truncation(w, H):
+        gx, gy, gt, gc, lay = gpu_poisson(a, b, "auto", ctx)
+        assert_tolerance(_pkeys(gx, gy, gt), gc, _pkeys(ox, oy, ot), oc, oab, TOL,
+                         f"harmonic {w} <= {H}")
+        # the codes path: the same terms as keys
+        dts = (np.int32, np.int32, np.uint8, np.float64)
+        sa = [dev(np.asarray(a[k], dts[k])) for k in range(4)]
+        sb = [dev(np.asarray(b[k], dts[k])) for k in range(4)]
+        ka = kp.encode(lay, 0, sa[0], sa[1], sa[2], ctx=ctx)
+        kb = kp.encode(lay, 1, sb[0], sb[1], sb[2], ctx=ctx)
+        keys, coef, n = kp.mul_poisson_codes(lay, (ka[0], ka[1], sa[2], sa[3]),
+                                             (kb[0], kb[1], sb[2], sb[3]), "auto", ctx)
+        assert int(n) == len(gc)
+        if H >= 0:
+            x, y, t = kp.decode(lay, keys, poisson=True, ctx=ctx)
+            assert_tolerance(_pkeys(x.cpu().numpy(), y.cpu().numpy(), t.cpu().numpy()),
+                             coef.cpu().numpy(), _pkeys(ox, oy, ot), oc, oab, TOL,
+                             f"harmonic codes path {w} <= {H}")
+
+
+def test_poisson_harmonic_truncation_modes_and_clear():
+    """Dense mode is refused under a harmonic truncation; clearing it gives the
+    whole product back; a Laurent product is unaffected by it."""
+    ctx = kp.context()
+    a, b = I.config(4, scale=0.02)
+    with ctx.harmonic_truncation([1] * 6, 4):
+        say("harmonic truncation, forced dense mode")
+        with pytest.raises(kp.KPError) as err:
+            gpu_poisson(a, b, "dense", ctx)
+        assert err.value.status == kp.KP_E_MODE
+        la, lb = I.config(1, scale=0.2)
+        check_laurent(la, lb, "auto", "a Laurent product under a harmonic truncation", ctx)
+    check_poisson(a, b, "after clearing the harmonic truncation")
+
+
 def test_poisson_identities_on_device():
     one = lambda x, j, t, c: (np.array([[x]], np.int32), np.array([j], np.int32),
                               np.array([t], np.uint8), np.array([c], np.float64))
