@@ -160,9 +160,11 @@ typedef struct kp_tune {
                                code range (level 1 found from the sorted factors, so each
                                product is written once, to a hash bin of its range);
                                1 = two levels of hash bits through HBM (always used for
-                               Poisson series and 128-bit sums); 0 (default) = by range,
-                               except under a truncation, where the two-level grouping
-                               drops pairs over the limit before forming them.  Either
+                               Poisson series and 128-bit sums); 0 (default) = by range
+                               for products spread thinly over the code space (at most one
+                               per 64 codes), else, and under a truncation (the two-level
+                               grouping drops pairs over the limit before forming them),
+                               two levels.  Either
                                way a bin whose distinct codes overflow its table is redone
                                in parts                                                   */
   int32_t hash_max_bin_bits; /* grouped by code range: at most 2^this bins per range (0..10,

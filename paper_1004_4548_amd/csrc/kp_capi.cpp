@@ -299,7 +299,7 @@ struct Plan {
   // grouped by code range: ranges of 2^rw codes, row splits of A, bins, B buckets
   bool range = false;
   int rw = 0;
-  int64_t rnr = 0, rnsplit = 1, rrows = 0, rbins = 0, rnbk = 0;
+  int64_t rnr = 0, rnsplit = 1, rrows = 0, rbins = 0, rnbk = 0, rsplit_cap = 1;
   int rshift = 0;
   int64_t rtarget = 1;
 };
@@ -455,7 +455,8 @@ void carve_poisson_dense(Carver& c, int64_t na, int64_t nb, PoissonDenseBufs* q)
 struct RangeCarve {
   int64_t* bk; uint64_t* bc; int32_t* b_tb; int32_t* brank; int32_t* bstart;
   int64_t* rcount; int32_t* rnb; int64_t* rbin0; int64_t* rtotal; int64_t* rbase;
-  int64_t* rhole; int64_t* rabove; int64_t* cnt;
+  int64_t* rhole; int64_t* rabove; int64_t* cnt; int32_t* rns; int64_t* rupre; int64_t* rcbase;
+  int32_t* umap;
   int32_t* bin_range; int64_t* bin_start; int64_t* bin_terms; int64_t* bhole; int64_t* babove;
   void* ent;
 };
@@ -509,6 +510,9 @@ void range_shape(const kp_layout* L, int64_t na, int64_t nb, int64_t nprod, int 
   p->rnsplit = std::max<int64_t>(1, std::min<int64_t>(16, (2048 + p->rnr - 1) / p->rnr));
   p->rnsplit = std::min<int64_t>(p->rnsplit, std::max<int64_t>(1, na));
   p->rrows = (na + p->rnsplit - 1) / p->rnsplit;
+  // a range may take up to four times the even share of splits (the device
+  // gives each range splits in proportion to its products)
+  p->rsplit_cap = std::max<int64_t>(1, std::min<int64_t>({64, 4 * p->rnsplit, na}));
   p->blog = bin_slots == 8192 ? 13 : bin_slots == 4096 ? 12 : 11;
   // products per bin: `fill` percent of the table's slots (the bound on
   // products exceeds them by a few percent), so that linear probing stays short
@@ -553,7 +557,11 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     g.rbase = c.take<int64_t>(p.rnr);
     g.rhole = c.take<int64_t>(p.rnr + 1);
     g.rabove = c.take<int64_t>(p.rnr + 1);
-    g.cnt = c.take<int64_t>((size_t)(p.rbins * p.rnsplit));
+    g.cnt = c.take<int64_t>((size_t)(p.rbins * p.rsplit_cap));
+    g.rns = c.take<int32_t>(p.rnr);
+    g.rupre = c.take<int64_t>(p.rnr + 1);
+    g.rcbase = c.take<int64_t>(p.rnr + 1);
+    g.umap = c.take<int32_t>((size_t)(p.rnr * p.rsplit_cap));
     g.bin_range = c.take<int32_t>(p.rbins);
     g.bin_start = c.take<int64_t>(p.rbins + 1);
     g.bin_terms = c.take<int64_t>(p.rbins);
@@ -706,12 +714,15 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
                 (ctx->tune.hash_partitioned == 1 &&
                  (double)contrib <= 4.0 * (double)std::max<int64_t>(p->max_out, 1)));
     // (a wavefront scans the interval lengths of 64 rows in 32 bits)
-    // Under a truncation the two-level grouping is the automatic choice: it
-    // drops a pair over the limit before anything is formed, while the
-    // ranges enumerate every pair of a row's interval of B.
+    // Automatic grouping: by ranges for products spread thinly over the code
+    // space (at most one product per 64 codes: most are distinct terms, and
+    // each is written once), else two levels of hash bits, which also take a
+    // truncated product (they drop a pair over the limit before forming it,
+    // while the ranges enumerate every pair of a row's interval of B).
     const int grouping = ctx->tune.hash_grouping;
+    const bool thin = (double)contrib * 64.0 <= (double)L->nkeys;
     p->range = p->radix && !poisson && dt != KP_I128 &&
-               (grouping == 2 || (grouping == 0 && !p->trunc)) &&
+               (grouping == 2 || (grouping == 0 && !p->trunc && thin)) &&
                na < ((int64_t)1 << 31) && nb <= ((int64_t)1 << 24);
     if (p->range) {
       p->radix = false;
@@ -1247,6 +1258,11 @@ kp_status enqueue_laurent(kp_ctx* ctx, const kp_layout* layout, kp_dtype dtype, 
       R.inv = inv & mask;
       R.nsplit = p.rnsplit;
       R.rows = p.rrows;
+      R.split_cap = p.rsplit_cap;
+      R.rns = g.rns;
+      R.rupre = g.rupre;
+      R.rcbase = g.rcbase;
+      R.umap = g.umap;
       R.target = p.rtarget;
       R.max_l2 = std::max(0, std::min(10, ctx->tune.hash_max_bin_bits));
       R.nbins_max = p.rbins;

@@ -516,7 +516,8 @@ struct RangeArgs {
   int shiftB; int64_t nbkB;
   int64_t nkeys; int w; int64_t nr;              // ranges of 2^w codes, nr of them
   uint64_t mult, inv;                            // odd multiplier mod 2^w and its inverse
-  int64_t nsplit, rows;                          // row splits of A, rows per split
+  int64_t nsplit, rows;                          // row splits of A, rows per split (bounds)
+  int64_t split_cap;                             // at most this many splits of one range
   int64_t target;                                // products wanted per bin
   int max_l2;                                    // at most 2^max_l2 bins per range
   int64_t nbins_max;
@@ -527,7 +528,11 @@ struct RangeArgs {
   int64_t* rbase;    // [nr] first entry (and first result slot) of each range
   int64_t* rhole;    // [nr + 1] empty slots below the result count, per range, then prefix
   int64_t* rabove;   // [nr + 1] terms at the result count or beyond, per range, then prefix
-  int64_t* cnt;      // [nbins_max * nsplit] entries per (bin, split), then offsets in the range
+  int32_t* rns;      // [nr] row splits of each range (its share of the products)
+  int64_t* rupre;    // [nr + 1] first (range, split) unit of each range
+  int64_t* rcbase;   // [nr + 1] first count of each range: its bins times its splits
+  int32_t* umap;     // [nr * split_cap] range of each (range, split) unit
+  int64_t* cnt;      // [nbins_max * split_cap] entries per (bin, split), then offsets in the range
   int32_t* bin_range;  // [nbins_max]
   int64_t* bin_start;  // [nbins_max + 1] first entry of each bin (absolute once scattered)
   int64_t* bin_terms;  // [nbins_max] result terms of each bin

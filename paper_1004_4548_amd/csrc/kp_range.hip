@@ -279,7 +279,39 @@ __global__ void __launch_bounds__(1024) k_rg_plan(RangeArgs R) {
     if (tid == 0) ++s_cut;
     __syncthreads();
   }
+  // row splits per range in proportion to its products, so that the
+  // counting and grouping workgroups get about equal shares (products
+  // concentrate in part of the code space for dense-like factors)
+  __syncthreads();
+  int64_t local = 0;
+  for (int64_t r = r0; r < r1; ++r) local += R.rcount[r];
+  int64_t all = 0;
+  (void)block_scan<1024, int64_t>(local, s_ws, &all);
+  const int64_t units = R.nr * R.nsplit;
+  const int64_t share = max((int64_t)1, (all + units - 1) / units);
+  const int64_t cap = min(R.split_cap, max((int64_t)1, R.na));
+  int64_t lu = 0, lc = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    // (a range is split once it holds eight times its even share: mild
+    // unevenness costs less than the extra walks over the rows)
+    const int64_t ns = max((int64_t)1, min(cap, R.rcount[r] / (4 * share)));
+    R.rns[r] = (int32_t)ns;
+    lu += ns;
+    lc += ns * R.rnb[r];
+  }
+  int64_t tu = 0, tc = 0;
+  int64_t ru = block_scan<1024, int64_t>(lu, s_ws, &tu);
+  int64_t rc = block_scan<1024, int64_t>(lc, s_ws, &tc);
+  for (int64_t r = r0; r < r1; ++r) {
+    R.rupre[r] = ru;
+    R.rcbase[r] = rc;
+    for (int32_t k = 0; k < R.rns[r]; ++k) R.umap[ru + k] = (int32_t)r;
+    ru += R.rns[r];
+    rc += (int64_t)R.rns[r] * R.rnb[r];
+  }
   if (tid == 0) {
+    R.rupre[R.nr] = tu;
+    R.rcbase[R.nr] = tc;
     R.rbin0[R.nr] = total;
     R.meta->nbins = total;
     uint32_t pack = 0;
@@ -412,29 +444,50 @@ struct WaveWalk {
   }
 };
 
+// The (range, split) unit of workgroup g: false past the last unit.  Split s
+// of range r takes rows [s ceil(na / ns), ...) of A, ns its range's splits.
+struct Unit {
+  int64_t r, s, ns, i0, i1;
+};
+__device__ __forceinline__ bool unit_of(const RangeArgs& R, int64_t g, Unit* u) {
+  if (g >= R.rupre[R.nr]) return false;
+  const int64_t a = R.umap[g];
+  u->r = a;
+  u->s = g - R.rupre[a];
+  u->ns = R.rns[a];
+  const int64_t rows = (R.na + u->ns - 1) / u->ns;
+  u->i0 = u->s * rows;
+  u->i1 = min(R.na, u->i0 + rows);
+  return true;
+}
+
 // Entries per (bin, split) of each range.
 template <typename T>
-__global__ void __launch_bounds__(RG_BLOCK) k_rg_count1(RangeArgs R) {
+__global__ void __launch_bounds__(RG_BLOCK, 8) k_rg_count1(RangeArgs R) {   // two per CU
   __shared__ uint32_t hist[1 << RG_MAX_L2];
   __shared__ WaveRows rows[WAVES];
-  const int64_t r = blockIdx.x, s = blockIdx.y;
-  const uint32_t nbin = (uint32_t)R.rnb[r];
-  for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK) hist[k] = 0;
-  __syncthreads();
-  const int64_t lo = r << R.w, hi = min(R.nkeys, (r + 1) << R.w);
-  const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
-  const int wave = threadIdx.x >> 6;
-  WaveWalk<T> g;
-  g.start(i0, i1, lo, hi, wave);
-  bool ok;
-  uint64_t h = 0;
-  T v{};
-  while (g.template step<false>(R, rows[wave], R.w, R.mult, &ok, &h, &v))
-    if (ok) atomicAdd(&hist[bin_of(h, R.w, nbin)], 1u);
-  __syncthreads();
-  const int64_t b0 = R.rbin0[r];
-  for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK)
-    R.cnt[(b0 + k) * R.nsplit + s] = hist[k];
+  // the grid walks the (range, split) units
+  for (int64_t gu = blockIdx.x;; gu += gridDim.x) {
+    Unit U;
+    if (!unit_of(R, gu, &U)) return;
+    const int64_t r = U.r, s = U.s;
+    const uint32_t nbin = (uint32_t)R.rnb[r];
+    for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK) hist[k] = 0;
+    __syncthreads();
+    const int64_t lo = r << R.w, hi = min(R.nkeys, (r + 1) << R.w);
+    const int wave = threadIdx.x >> 6;
+    WaveWalk<T> g;
+    g.start(U.i0, U.i1, lo, hi, wave);
+    bool ok;
+    uint64_t h = 0;
+    T v{};
+    while (g.template step<false>(R, rows[wave], R.w, R.mult, &ok, &h, &v))
+      if (ok) atomicAdd(&hist[bin_of(h, R.w, nbin)], 1u);
+    __syncthreads();
+    int64_t* c = R.cnt + R.rcbase[r];
+    for (int k = threadIdx.x; k < (int)nbin; k += RG_BLOCK) c[k * U.ns + s] = hist[k];
+    __syncthreads();   // the next unit clears hist
+  }
 }
 
 // One workgroup per range: offsets of every (bin, split) within the range,
@@ -443,10 +496,11 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_count1(RangeArgs R) {
 __global__ void __launch_bounds__(1024) k_rg_scan1(RangeArgs R) {
   const int64_t r = blockIdx.x;
   const int64_t b0 = R.rbin0[r], nbin = R.rbin0[r + 1] - b0;
-  int64_t* c = R.cnt + b0 * R.nsplit;
-  const int64_t total = block_scan_runs<1024, int64_t>(c, nbin * R.nsplit);
+  const int64_t ns = R.rns[r];
+  int64_t* c = R.cnt + R.rcbase[r];
+  const int64_t total = block_scan_runs<1024, int64_t>(c, nbin * ns);
   for (int64_t k = threadIdx.x; k < nbin; k += 1024) {
-    R.bin_start[b0 + k] = c[k * R.nsplit];   // within the range; made absolute by the scatter
+    R.bin_start[b0 + k] = c[k * ns];   // within the range; made absolute by the scatter
     R.bin_range[b0 + k] = (int32_t)r;
   }
   if (threadIdx.x == 0) R.rtotal[r] = total;
@@ -488,71 +542,77 @@ __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
   __shared__ uint32_t coff[1 << RG_MAX_L2];
   __shared__ uint32_t s_ws[RG_BLOCK / 64 + 1];
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int64_t r = blockIdx.x, s = blockIdx.y;
-  const int nbin = R.rnb[r];
-  const int w = R.w;
-  const uint64_t mult = R.mult;
-  const bool pack = R.meta->pack != 0;
-  const int64_t b0 = R.rbin0[r], rb = R.rbase[r];
-  for (int k = tid; k < nbin; k += RG_BLOCK) {
-    base[k] = rb + R.cnt[(b0 + k) * R.nsplit + s];
-    coff[k] = 0;
-    if (s == 0) R.bin_start[b0 + k] += rb;   // the bins' first entries, absolute
-  }
-  __syncthreads();
-  const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
-  const int64_t i0 = s * R.rows, i1 = min(R.na, i0 + R.rows);
-  WaveWalk<T> g;
-  g.start(i0, i1, lo, hi, wave);
-  uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
-  uint4* ent16 = static_cast<uint4*>(R.ent);
-  for (;;) {
-    uint64_t hh[RG_STEPS], vb[RG_STEPS];
-    uint32_t bn[RG_STEPS], rank[RG_STEPS];
-    uint32_t mask = 0;
-#pragma unroll
-    for (int u = 0; u < RG_STEPS; ++u) {
-      bool ok = false;
-      uint64_t h = 0;
-      T v{};
-      if (!g.template step<true>(R, rows[wave], w, mult, &ok, &h, &v)) break;
-      if (!ok) continue;
-      hh[u] = h;
-      vb[u] = to_bits(v);
-      bn[u] = bin_of(h, w, (uint32_t)nbin);
-      rank[u] = atomicAdd(&coff[bn[u]], 1u);
-      mask |= 1u << u;
+  // the grid walks the (range, split) units
+  for (int64_t gu = blockIdx.x;; gu += gridDim.x) {
+    Unit U;
+    if (!unit_of(R, gu, &U)) return;
+    const int64_t r = U.r, s = U.s;
+    const int nbin = R.rnb[r];
+    const int w = R.w;
+    const uint64_t mult = R.mult;
+    const bool pack = R.meta->pack != 0;
+    const int64_t b0 = R.rbin0[r], rb = R.rbase[r];
+    for (int k = tid; k < nbin; k += RG_BLOCK) {
+      base[k] = rb + R.cnt[R.rcbase[r] + k * U.ns + s];
+      coff[k] = 0;
+      if (s == 0) R.bin_start[b0 + k] += rb;   // the bins' first entries, absolute
     }
     __syncthreads();
-    const uint32_t mine = tid < nbin ? coff[tid] : 0u;
-    uint32_t total;
-    const uint32_t off = block_scan<RG_BLOCK, uint32_t>(mine, s_ws, &total);
-    if (tid < nbin) coff[tid] = off;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RG_STEPS; ++u)
-      if ((mask >> u) & 1u)
-        stage[coff[bn[u]] + rank[u]] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32),
-                                                  (uint32_t)vb[u], (uint32_t)(vb[u] >> 32));
-    __syncthreads();
-    for (uint32_t t = tid; t < total; t += RG_BLOCK) {
-      const uint4 e = stage[t];
-      const uint64_t h = ((uint64_t)e.y << 32) | e.x;
-      const uint32_t k = bin_of(h, w, (uint32_t)nbin);
-      const int64_t at = base[k] + (t - coff[k]);
-      if (pack) {
-        const uint64_t v = ((uint64_t)e.w << 32) | e.z;
-        ent8[at] = (v << w) | h;
-      } else {
-        ent16[at] = e;
+    const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
+    const int64_t i0 = U.i0, i1 = U.i1;
+    WaveWalk<T> g;
+    g.start(i0, i1, lo, hi, wave);
+    uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
+    uint4* ent16 = static_cast<uint4*>(R.ent);
+    for (;;) {
+      uint64_t hh[RG_STEPS], vb[RG_STEPS];
+      uint32_t bn[RG_STEPS], rank[RG_STEPS];
+      uint32_t mask = 0;
+  #pragma unroll
+      for (int u = 0; u < RG_STEPS; ++u) {
+        bool ok = false;
+        uint64_t h = 0;
+        T v{};
+        if (!g.template step<true>(R, rows[wave], w, mult, &ok, &h, &v)) break;
+        if (!ok) continue;
+        hh[u] = h;
+        vb[u] = to_bits(v);
+        bn[u] = bin_of(h, w, (uint32_t)nbin);
+        rank[u] = atomicAdd(&coff[bn[u]], 1u);
+        mask |= 1u << u;
       }
+      __syncthreads();
+      const uint32_t mine = tid < nbin ? coff[tid] : 0u;
+      uint32_t total;
+      const uint32_t off = block_scan<RG_BLOCK, uint32_t>(mine, s_ws, &total);
+      if (tid < nbin) coff[tid] = off;
+      __syncthreads();
+  #pragma unroll
+      for (int u = 0; u < RG_STEPS; ++u)
+        if ((mask >> u) & 1u)
+          stage[coff[bn[u]] + rank[u]] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32),
+                                                    (uint32_t)vb[u], (uint32_t)(vb[u] >> 32));
+      __syncthreads();
+      for (uint32_t t = tid; t < total; t += RG_BLOCK) {
+        const uint4 e = stage[t];
+        const uint64_t h = ((uint64_t)e.y << 32) | e.x;
+        const uint32_t k = bin_of(h, w, (uint32_t)nbin);
+        const int64_t at = base[k] + (t - coff[k]);
+        if (pack) {
+          const uint64_t v = ((uint64_t)e.w << 32) | e.z;
+          ent8[at] = (v << w) | h;
+        } else {
+          ent16[at] = e;
+        }
+      }
+      __syncthreads();
+      if (tid < nbin) {
+        base[tid] += mine;
+        coff[tid] = 0;
+      }
+      if (!__syncthreads_or(!g.done)) break;
     }
-    __syncthreads();
-    if (tid < nbin) {
-      base[tid] += mine;
-      coff[tid] = 0;
-    }
-    if (!__syncthreads_or(!g.done)) break;
+    __syncthreads();   // the next unit resets base and coff
   }
 }
 
@@ -932,10 +992,11 @@ hipError_t launch_typed(const RangeArgs& R, hipStream_t s) {
                        dim3(SMALL_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_rg_count0<T>, grid, dim3(SMALL_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_rg_plan<T>, dim3(1), dim3(1024), 0, s, R);
-  hipLaunchKernelGGL(k_rg_count1<T>, grid, dim3(RG_BLOCK), 0, s, R);
+  const dim3 units((unsigned)(R.nr * R.nsplit));   // walking every (range, split) unit
+  hipLaunchKernelGGL(k_rg_count1<T>, units, dim3(RG_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_rg_scan1, dim3((unsigned)R.nr), dim3(1024), 0, s, R);
   hipLaunchKernelGGL(k_rg_scan2, dim3(1), dim3(1024), 0, s, R);
-  hipLaunchKernelGGL(k_rg_scatter<T>, grid, dim3(RG_BLOCK), 0, s, R);
+  hipLaunchKernelGGL(k_rg_scatter<T>, units, dim3(RG_BLOCK), 0, s, R);
   if (R.bin_log >= 13) launch_bins<T, 13>(R, s);
   else if (R.bin_log == 12) launch_bins<T, 12>(R, s);
   else launch_bins<T, 11>(R, s);

@@ -379,15 +379,15 @@ def test_range_grouping_recovers_from_full_bins(slots):
                   f"one bin per range, fp64, bins of {slots}", ctx)
 
 
-@pytest.mark.parametrize("grouping", [0, 1])
+@pytest.mark.parametrize("grouping", [0, 1, 2])
 @pytest.mark.parametrize("cfg,scale,fp", [(3, 0.1, False), (3, 0.05, True), (2, 0.2, False),
                                           (1, 1.0, True)])
 def test_grouped_hash_matches_oracle(grouping, cfg, scale, fp):
-    """Both groupings of the hash products against the oracle: the highly
-    sparse product (few collisions: each range's terms fill its own slots,
-    the few beyond the count are moved), the simplex forced into hash mode
-    (many products per code: more entries than result slots, so a shared
-    counter places the terms), and the small box."""
+    """Every grouping of the hash products against the oracle (0 automatic,
+    1 two levels, 2 ranges): the highly sparse product (few collisions: each
+    range's terms fill its own slots, the few beyond the count are moved), the
+    simplex forced into hash mode (many products per code: more entries than
+    result slots, so a shared counter places the terms), and the small box."""
     ctx = kp.context()
     ctx.set_tune(hash_partitioned=2, hash_grouping=grouping)
     a, b = I.config(cfg, scale=scale)
