@@ -1,13 +1,19 @@
 """Autotuner for the knobs the paper leaves open (Sections 3.1, 3.2): the
 dense window size, workgroup size and tasks per compute unit, the global
-hash table's load factor and rows per thread, the size of the LDS tables of
-grouped products, and the density threshold of the dense/hash choice.  None
-of them changes a result; each is picked by timing the library's own
-multiplies on seeded products of the benchmark shapes.
+hash table's load factor and rows per thread, the size and fill of the LDS
+tables of grouped products, and the density threshold of the dense/hash
+choice (Section 3 leaves it to "an analysis of the densities").  None of them
+changes a result; each is picked by timing the library's own multiplies on
+seeded products of the benchmark shapes.  Results persist in a JSON cache
+keyed by the GPU and the library build, so a process on the same machine
+applies them without timing again.
 """
 from __future__ import annotations
 
+import hashlib
 import itertools
+import json
+import os
 import time
 
 import numpy as np
@@ -20,7 +26,10 @@ DENSE_GRID = [dict(window=w, block=b, tasks_per_cu=t)
               for w, b, t in itertools.product((8192, 16384, 18432), (512, 1024), (1, 2))]
 HASH_GRID = [dict(hash_load=l, hash_rows=r)
              for l, r in itertools.product((0.35, 0.5, 0.7), (32, 64, 128))]
-BIN_GRID = [dict(hash_bin_slots=s) for s in (2048, 4096, 8192)]
+BIN_GRID = [dict(hash_bin_slots=s, hash_bin_fill=f)
+            for s, f in ((2048, 42), (4096, 42), (4096, 55), (8192, 42))]
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1004_4548_amd",
+                             "tune.json")
 
 
 def _dev(x):
@@ -110,38 +119,92 @@ def tune_bins(ctx, scale=0.5, reps=3):
                    fixed=dict(hash_partitioned=2))
 
 
-def tune_threshold(ctx, n=2000, reps=3):
-    """The dense/hash switch: products of n x n terms in 3-variable boxes of
-    growing width; the threshold on codes per term product lies between the
-    sparsest box where dense mode still wins and the densest where hash wins."""
-    rows = []
-    for h in (5, 7, 9, 12, 16, 22, 30, 40, 55, 70, 90):
-        if (2 * h + 1) ** 3 < n:
-            continue
-        a = I.laurent_box(n=n, cfg=7, factor=0, lo=-h, hi=h)
-        b = I.laurent_box(n=n, cfg=7, factor=1, lo=-h, hi=h)
-        prod = _Product(ctx, a, b)
-        if not (prod.feasible("dense") and prod.feasible("hash")):
-            continue
-        td, th = prod.seconds("dense", reps), prod.seconds("hash", reps)
-        rows.append((prod.lay.nkeys / prod.pairs, td, th))
+def _crossover(rows, fallback):
+    """Threshold on codes per term product between the sparsest product where
+    dense mode still wins and the densest sparser one where hash wins."""
     dense_wins = [r for r, td, th in rows if td <= th]
     hash_wins = [r for r, td, th in rows if td > th]
     lo = max(dense_wins) if dense_wins else None
     hi = min([r for r in hash_wins if lo is None or r > lo], default=None)
     if lo is None:
-        thr = 0.0
-    elif hi is None:
-        thr = max(ctx.tune.dense_keys_per_pair, lo)
-    else:
-        thr = float(np.sqrt(lo * hi))
+        return 0.0
+    if hi is None:
+        return max(fallback, lo)
+    return float(np.sqrt(lo * hi))
+
+
+def tune_threshold(ctx, n=2000, reps=3, nvars=(2, 3, 4)):
+    """The dense/hash switch: products of n x n terms in boxes of growing
+    width, for each number of variables in `nvars`; each shape class gives a
+    crossover, and the threshold is their median (the library keeps one).
+    Returns the threshold and the rows (codes per pair, dense s, hash s, nv)."""
+    rows, per_nv = [], {}
+    widths = {2: (30, 45, 70, 100, 150, 220, 330, 500, 750, 1100),
+              3: (5, 7, 9, 12, 16, 22, 30, 40, 55, 70, 90),
+              4: (4, 5, 7, 9, 12, 16, 22, 30)}
+    for nv in nvars:
+        mine = []
+        for h in widths.get(nv, widths[3]):
+            if (2 * h + 1) ** nv < n:
+                continue
+            a = I.laurent_box(nv=nv, n=n, cfg=7, factor=0, lo=-h, hi=h)
+            b = I.laurent_box(nv=nv, n=n, cfg=7, factor=1, lo=-h, hi=h)
+            prod = _Product(ctx, a, b)
+            if not (prod.feasible("dense") and prod.feasible("hash")):
+                continue
+            td, th = prod.seconds("dense", reps), prod.seconds("hash", reps)
+            mine.append((prod.lay.nkeys / prod.pairs, td, th))
+        per_nv[nv] = _crossover(mine, ctx.tune.dense_keys_per_pair)
+        rows += [(r, td, th, nv) for r, td, th in mine]
+    thr = float(np.median(list(per_nv.values()))) if per_nv else ctx.tune.dense_keys_per_pair
     return thr, rows
 
 
-def autotune(ctx=None, apply=True, quick=True):
+def cache_key(device_name, library_path, quick):
+    """Key of a tuning result: the GPU, the library build (its SHA-256) and
+    the tuning depth."""
+    h = hashlib.sha256()
+    with open(library_path, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return f"{device_name}|{h.hexdigest()[:16]}|{'quick' if quick else 'full'}"
+
+
+def load_cache(path):
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path, key, result):
+    d = load_cache(path)
+    d[key] = result
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(ctx=None, apply=True, quick=True, cache=DEFAULT_CACHE):
     """Tunes every knob and (when `apply`) sets the context to the result.
-    Returns the chosen settings and the timing tables."""
+    With a `cache` path, a result for this GPU and library build is applied
+    from it without timing, and a new result is stored there.  Returns the
+    chosen settings and the timing tables."""
+    import torch
+    from . import LIB_PATH
     ctx = ctx or context()
+    key = None
+    if cache:
+        key = cache_key(torch.cuda.get_device_name(ctx.device), LIB_PATH, quick)
+        hit = load_cache(cache).get(key)
+        if hit and "chosen" in hit:
+            if apply:
+                ctx.set_tune(**hit["chosen"])
+            return {**hit, "cached": True, "cache_key": key}
     dense, dt = tune_dense(ctx, scale=0.5 if quick else 1.0)
     hashed, ht = tune_hash(ctx, scale=0.1 if quick else 0.3)
     bins, bt = tune_bins(ctx, scale=0.5 if quick else 1.0)
@@ -149,9 +212,12 @@ def autotune(ctx=None, apply=True, quick=True):
     chosen = {**dense, **hashed, **bins, "dense_keys_per_pair": thr}
     if apply:
         ctx.set_tune(**chosen)
-    return {"chosen": chosen,
-            "dense_ms": [(round(t * 1e3, 4), c) for t, c in dt],
-            "hash_ms": [(round(t * 1e3, 4), c) for t, c in ht],
-            "bins_ms": [(round(t * 1e3, 4), c) for t, c in bt],
-            "threshold_rows": [(round(r, 3), round(a * 1e3, 4), round(b * 1e3, 4))
-                               for r, a, b in rows]}
+    out = {"chosen": chosen,
+           "dense_ms": [(round(t * 1e3, 4), c) for t, c in dt],
+           "hash_ms": [(round(t * 1e3, 4), c) for t, c in ht],
+           "bins_ms": [(round(t * 1e3, 4), c) for t, c in bt],
+           "threshold_rows": [(round(r, 3), round(a * 1e3, 4), round(b * 1e3, 4), nv)
+                              for r, a, b, nv in rows]}
+    if cache:
+        save_cache(cache, key, out)
+    return {**out, "cached": False, "cache_key": key}

@@ -356,3 +356,27 @@ def test_pack_needs_a_device_context():
     assert L.kp_pack_wait(None, None) == kp.KP_E_ARG
     d = C.c_int32()
     assert L.kp_pack_query(None, C.byref(d)) == kp.KP_E_ARG
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The autotuner's JSON cache: a stored result comes back under the same
+    key; the key changes with the library build and the tuning depth; a
+    damaged file reads as empty."""
+    from paper_1004_4548_amd import tune
+    lib = tmp_path / "lib.so"
+    lib.write_bytes(b"build one")
+    k1 = tune.cache_key("MI355X", str(lib), True)
+    assert k1 != tune.cache_key("MI355X", str(lib), False)
+    path = str(tmp_path / "sub" / "tune.json")
+    assert tune.load_cache(path) == {}
+    res = {"chosen": {"window": 16384, "dense_keys_per_pair": 8.0}}
+    tune.save_cache(path, k1, res)
+    assert tune.load_cache(path)[k1] == res
+    lib.write_bytes(b"build two")
+    k2 = tune.cache_key("MI355X", str(lib), True)
+    assert k2 != k1 and k2 not in tune.load_cache(path)
+    tune.save_cache(path, k2, res)
+    assert set(tune.load_cache(path)) == {k1, k2}
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert tune.load_cache(path) == {}
