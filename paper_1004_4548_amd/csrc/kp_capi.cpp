@@ -290,6 +290,7 @@ struct Plan {
   int64_t nblocks = 0, nprod = 0;
   bool trunc = false;   // truncation tables follow the mode's workspace
   bool harm = false;    // Poisson truncation by harmonic order (term orders in the workspace)
+  bool harm_exact = false;   // ... from the factors' multipliers, packed as bytes
   int cw = 1;           // 64-bit words per result coefficient (2 for KP_I128)
   // bucketed table: slots per bucket, buckets, overflow slots, term order
   bool bucket = false;
@@ -600,7 +601,10 @@ void carve_hash(Carver& c, const Plan& p, int poisson, int64_t na, int64_t nb, H
     h->pp.bm = c.take<int64_t>(nb);
     h->pp.bkx = c.take<int64_t>(nb);
     h->pp.bt = c.take<uint8_t>(nb);
-    if (p.harm) {
+    if (p.harm_exact) {
+      h->pp.ad = c.take<uint4>(na);
+      h->pp.bd = c.take<uint4>(nb);
+    } else if (p.harm) {
       h->pp.ao = c.take<int32_t>(na);
       h->pp.bo = c.take<int32_t>(nb);
     }
@@ -667,6 +671,11 @@ kp_status make_plan(kp_ctx* ctx, const kp_layout* L, int poisson, kp_dtype dt, k
   p->mode = m;
   p->trunc = ctx->trunc_on && !poisson;
   p->harm = harm;
+  if (harm) {   // every factor multiplier fits a signed byte: exact orders per piece
+    bool small = true;
+    for (int v = 0; v < L->ny; ++v) small = small && L->ha[v] <= 127 && L->hb[v] <= 127;
+    p->harm_exact = small;
+  }
   Carver c;
   if (m == KP_DENSE) {
     carve_dense<false>(c, *p, na, nbd, nullptr);
@@ -1451,6 +1460,7 @@ kp_status enqueue_poisson(kp_ctx* ctx, const kp_layout* layout, kp_mode mode,
     if (p.harm) {
       R.harm_on = 1;
       R.harm = ctx->harm;
+      R.harm_exact = p.harm_exact ? 1 : 0;
     }
     if (po) {
       R.out_x = po->x;

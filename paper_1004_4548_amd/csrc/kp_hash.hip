@@ -208,6 +208,18 @@ __device__ __forceinline__ int32_t term_order(const DevLayout& L, const Harmonic
   return (int32_t)min(o, (int64_t)INT_MAX);
 }
 
+// A factor term's multipliers (balanced digits of its canonical code ky >= 0)
+// as signed bytes, variable k in byte k.
+__device__ __forceinline__ uint4 pack_multipliers(const DevLayout& L, int64_t ky) {
+  uint32_t w[4] = {0, 0, 0, 0};
+  uint64_t u = (uint64_t)(ky < 0 ? -ky : ky);
+  for (int v = L.ny - 1; v >= 0; --v) {
+    const int32_t d = decode_y_step(L, v, u);
+    w[v >> 2] |= ((uint32_t)d & 0xFFu) << (8 * (v & 3));
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 __global__ void __launch_bounds__(HASH_BLOCK)
 k_poisson_prep(int64_t Wx, const int64_t* __restrict__ ax, const int64_t* __restrict__ ay,
                const uint8_t* __restrict__ as, int64_t na, const int64_t* __restrict__ bx,
@@ -218,21 +230,48 @@ k_poisson_prep(int64_t Wx, const int64_t* __restrict__ ax, const int64_t* __rest
     P.ap[g] = ax[g] + Wx * ay[g];
     P.akx[g] = ax[g];
     P.at[g] = as[g];
-    if (harm_on) P.ao[g] = term_order(L, H, ay[g]);
+    if (harm_on && P.ad) P.ad[g] = pack_multipliers(L, ay[g]);
+    else if (harm_on) P.ao[g] = term_order(L, H, ay[g]);
   } else if (g < na + nb) {
     const int64_t j = g - na;
     P.bp[j] = bx[j] + Wx * by[j];
     P.bm[j] = bx[j] - Wx * by[j];
     P.bkx[j] = bx[j];
     P.bt[j] = bs[j];
-    if (harm_on) P.bo[j] = term_order(L, H, by[j]);
+    if (harm_on && P.bd) P.bd[j] = pack_multipliers(L, by[j]);
+    else if (harm_on) P.bo[j] = term_order(L, H, by[j]);
   }
+}
+
+// The orders of a pair's difference and sum pieces, sum_k w_k |a_k -+ b_k|,
+// from the factors' packed multipliers.
+__device__ __forceinline__ void piece_orders(const uint4& a, const uint4& b, const RadixArgs& R,
+                                             int64_t* om, int64_t* op) {
+  int64_t m = 0, p = 0;
+  const int ny = R.dec.ny;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t x = q == 0 ? a.x : q == 1 ? a.y : q == 2 ? a.z : a.w;
+    const uint32_t y = q == 0 ? b.x : q == 1 ? b.y : q == 2 ? b.z : b.w;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < ny) {
+        const int32_t da = (int32_t)(int8_t)(x >> (8 * r));
+        const int32_t db = (int32_t)(int8_t)(y >> (8 * r));
+        m += (int64_t)R.harm.w[k] * abs(da - db);
+        p += (int64_t)R.harm.w[k] * abs(da + db);
+      }
+    }
+  }
+  *om = m;
+  *op = p;
 }
 
 // A truncated pair makes no piece when its factors' orders differ by more
 // than the limit: both pieces' orders are at least that difference.
 __device__ __forceinline__ bool pair_over(const RadixArgs& R, int64_t i, int64_t j) {
-  if (!R.harm_on) return false;
+  if (!R.harm_on || R.harm_exact) return false;
   const int64_t d = (int64_t)R.P.ao[i] - (int64_t)R.P.bo[j];
   return (d < 0 ? -d : d) > R.harm.max_order;
 }
@@ -406,8 +445,17 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
     const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
     const int tb = R.P.bt[j];
     const double cb = static_cast<const double*>(R.bc)[j];
+    const uint4 bd = R.harm_exact ? R.P.bd[j] : uint4{};
     for (int64_t i = i0; i < i1; ++i) {
       if (pair_over(R, i, j)) continue;
+      bool km = true, kp = true;   // the pieces within the order limit
+      if (R.harm_exact) {
+        int64_t om, op;
+        piece_orders(R.P.ad[i], bd, R, &om, &op);
+        km = om <= R.harm.max_order;
+        kp = op <= R.harm.max_order;
+        if (!km && !kp) continue;
+      }
       const int ta = R.P.at[i];
       const double h = 0.5 * (ac[i] * cb);
       if (h == 0.0) continue;
@@ -417,8 +465,10 @@ __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow
       const double sp = (ta && tb) ? -h : h;    // sin a sin b: -1/2 cos(a + b)
       int64_t key;
       double v;
-      if (poisson_piece(R.Wx, R.P.ap[i] + Bm, kx, t, sm, &key, &v)) f(key, __double_as_longlong(v));
-      if (poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &key, &v)) f(key, __double_as_longlong(v));
+      if (km && poisson_piece(R.Wx, R.P.ap[i] + Bm, kx, t, sm, &key, &v))
+        f(key, __double_as_longlong(v));
+      if (kp && poisson_piece(R.Wx, R.P.ap[i] + Bp, kx, t, sp, &key, &v))
+        f(key, __double_as_longlong(v));
     }
   } else {
     using T = typename std::conditional<KIND == 1, double, int64_t>::type;
@@ -474,6 +524,14 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
       }
       if (r0 + u >= r1) break;
       if (pair_over(R, r0 + u, j)) continue;
+      bool km = true, kp = true;   // the pieces within the order limit
+      if (R.harm_exact) {
+        int64_t om, op;
+        piece_orders(R.P.ad[r0 + u], R.P.bd[j], R, &om, &op);
+        km = om <= R.harm.max_order;
+        kp = op <= R.harm.max_order;
+        if (!km && !kp) continue;
+      }
       const int ta = at[u & 1];
       const double h = 0.5 * (ca[u & 1] * cb);
       if (h == 0.0) continue;
@@ -482,11 +540,11 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
       const double sm = (!ta && tb) ? -h : h;
       const double sp = (ta && tb) ? -h : h;
       double v;
-      if (poisson_piece(R.Wx, ap[u & 1] + Bm, kx, t, sm, &code[2 * u], &v)) {
+      if (km && poisson_piece(R.Wx, ap[u & 1] + Bm, kx, t, sm, &code[2 * u], &v)) {
         bits[2 * u] = __double_as_longlong(v);
         mask |= 1u << (2 * u);
       }
-      if (poisson_piece(R.Wx, ap[u & 1] + Bp, kx, t, sp, &code[2 * u + 1], &v)) {
+      if (kp && poisson_piece(R.Wx, ap[u & 1] + Bp, kx, t, sp, &code[2 * u + 1], &v)) {
         bits[2 * u + 1] = __double_as_longlong(v);
         mask |= 1u << (2 * u + 1);
       }
@@ -892,7 +950,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
       bool keep = kk[r] != 0 && vv[r] != T(0);
       // a truncated Poisson product drops the terms over the order limit
       // (key: 2 (kx + Wx |ky|) + is_sin)
-      if (R.harm_on && keep)
+      if (R.harm_on && !R.harm_exact && keep)
         keep = harmonic_order(R.dec, fdiv((uint64_t)(kk[r] - 1) >> 1, R.dec.dWx), R.harm) <=
                R.harm.max_order;
       ball[r] = __ballot(keep);
@@ -1201,7 +1259,7 @@ hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay,
                                const DevLayout* L, const HarmonicSpec* H) {
   const int64_t n = na + nb;
   if (n == 0) return hipSuccess;
-  const int harm_on = L && H && P.ao && P.bo ? 1 : 0;
+  const int harm_on = L && H && ((P.ao && P.bo) || (P.ad && P.bd)) ? 1 : 0;
   hipLaunchKernelGGL(k_poisson_prep, dim3((unsigned)((n + HASH_BLOCK - 1) / HASH_BLOCK)),
                      dim3(HASH_BLOCK), 0, s, Wx, ax, ay, as, na, bx, by, bs, nb, P,
                      harm_on ? *L : DevLayout{}, harm_on ? *H : HarmonicSpec{}, harm_on);

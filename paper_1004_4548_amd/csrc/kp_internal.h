@@ -424,6 +424,7 @@ struct PoissonPrep {
   int64_t* ap; int64_t* akx; uint8_t* at;     // A: kx + Wx ky, kx, is_sin
   int64_t* bp; int64_t* bm; int64_t* bkx; uint8_t* bt;  // B: kx + Wx ky, kx - Wx ky, kx, is_sin
   int32_t* ao; int32_t* bo;   // harmonic orders of A's and B's terms (truncated products)
+  uint4* ad; uint4* bd;       // or their multipliers as 16 signed bytes (all within +-127)
 };
 // H: optional harmonic truncation (the orders are then written, from L).
 hipError_t launch_poisson_prep(int64_t Wx, const int64_t* ax, const int64_t* ay, const uint8_t* as,
@@ -490,6 +491,9 @@ struct RadixArgs {
   // bins drop the terms over it (dec decodes the keys)
   int32_t harm_on = 0;
   HarmonicSpec harm{};
+  // with P.ad / P.bd: each piece's order is computed from the factors'
+  // multipliers and a piece over the limit is never formed
+  int32_t harm_exact = 0;
 };
 // kind: 0 Laurent int64, 1 Laurent fp64, 2 Poisson (fp64), 3 Laurent int64
 // factors with exact 128-bit sums (entries carry the pair's indices, the bins

@@ -453,6 +453,35 @@ def test_poisson_harmonic_truncation_matches_oracle(w, H):
                              f"harmonic codes path {w} <= {H}")
 
 
+def test_poisson_harmonic_truncation_large_multipliers():
+    """Multipliers past a signed byte (up to 200): the orders come from each
+    factor term's order, pairs whose orders differ by more than the limit make
+    no piece, and the bins drop the terms over it; against the oracle."""
+    ctx = kp.context()
+    rng = np.random.default_rng(12)
+    n = 300
+    def series(seed):
+        r = np.random.default_rng(seed)
+        y = r.integers(-200, 201, (n, 2)).astype(np.int32)
+        first = np.where(y[:, 0] != 0, y[:, 0], y[:, 1])
+        y[first < 0] *= -1                       # canonical: first nonzero positive
+        t = r.integers(0, 2, n).astype(np.uint8)
+        t[(y == 0).all(1)] = 0                   # no sin of the zero vector
+        x = r.integers(-2, 3, (n, 1)).astype(np.int32)
+        key = np.concatenate([x, y, t[:, None].astype(np.int32)], 1)
+        _, keep = np.unique(key, axis=0, return_index=True)
+        keep = np.sort(keep)
+        return x[keep], y[keep], t[keep], r.standard_normal(len(keep))
+    a, b = series(1), series(2)
+    for w, H in (([1, 1], 150), ([1, 2], 300), ([0, 1], 40)):
+        say("poisson, multipliers up to 200, harmonic", w, H)
+        ox, oy, ot, oc, oab = O.poisson_mul_truncated(a, b, 1, 2, w, H, threads=4)
+        with ctx.harmonic_truncation(w, H):
+            gx, gy, gt, gc, _ = gpu_poisson(a, b, "auto", ctx)
+        assert_tolerance(_pkeys(gx, gy, gt), gc, _pkeys(ox, oy, ot), oc, oab, TOL,
+                         f"large multipliers {w} <= {H}")
+
+
 def test_poisson_harmonic_truncation_modes_and_clear():
     """Dense mode is refused under a harmonic truncation; clearing it gives the
     whole product back; a Laurent product is unaffected by it."""
