@@ -433,23 +433,25 @@ __device__ __forceinline__ uint32_t bin_slot(uint64_t h, int l1, int l2) {
 
 // Every nonzero product of this thread: its term j of B against rows
 // [i0, i1) of A.  KIND 0: Laurent int64, 1: Laurent fp64, 2: Poisson (two
-// pieces per pair).  f(code, value bits).
+// pieces per pair), 3: Laurent exact 128-bit sums, 4: Poisson cut by
+// harmonic order.  f(code, value bits).
 template <int KIND, typename F>
 __device__ __forceinline__ void each_product(const RadixArgs& R, uint32_t narrow, F&& f) {
   const int64_t j = (int64_t)blockIdx.x * RADIX_BLOCK + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * R.rows;
   const int64_t i1 = min(i0 + R.rows, R.na);
   if (j >= R.nb) return;
-  if constexpr (KIND == 2) {
+  if constexpr (KIND == 2 || KIND == 4) {
+    constexpr bool CUT = KIND == 4;
     const double* ac = static_cast<const double*>(R.ac);
     const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
     const int tb = R.P.bt[j];
     const double cb = static_cast<const double*>(R.bc)[j];
-    const uint4 bd = R.harm_exact ? R.P.bd[j] : uint4{};
+    const uint4 bd = CUT && R.harm_exact ? R.P.bd[j] : uint4{};
     for (int64_t i = i0; i < i1; ++i) {
-      if (pair_over(R, i, j)) continue;
+      if (CUT && pair_over(R, i, j)) continue;
       bool km = true, kp = true;   // the pieces within the order limit
-      if (R.harm_exact) {
+      if (CUT && R.harm_exact) {
         int64_t om, op;
         piece_orders(R.P.ad[i], bd, R, &om, &op);
         km = om <= R.harm.max_order;
@@ -501,7 +503,8 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
                                                    int64_t (&bits)[8]) {
   uint32_t mask = 0;
   if (j >= R.nb) return 0;
-  if constexpr (KIND == 2) {
+  if constexpr (KIND == 2 || KIND == 4) {
+    constexpr bool CUT = KIND == 4;
     const double* ac = static_cast<const double*>(R.ac);
     const int64_t Bp = R.P.bp[j], Bm = R.P.bm[j], kxb = R.P.bkx[j];
     const int tb = R.P.bt[j];
@@ -523,9 +526,9 @@ __device__ __forceinline__ uint32_t chunk_products(const RadixArgs& R, uint32_t 
         }
       }
       if (r0 + u >= r1) break;
-      if (pair_over(R, r0 + u, j)) continue;
+      if (CUT && pair_over(R, r0 + u, j)) continue;
       bool km = true, kp = true;   // the pieces within the order limit
-      if (R.harm_exact) {
+      if (CUT && R.harm_exact) {
         int64_t om, op;
         piece_orders(R.P.ad[r0 + u], R.P.bd[j], R, &om, &op);
         km = om <= R.harm.max_order;
@@ -710,7 +713,7 @@ __global__ void __launch_bounds__(RADIX_BLOCK) k_radix_scatter(RadixArgs R) {
   __shared__ uint32_t coff[1 << RADIX_MAX_L];
   __shared__ uint32_t done[1 << RADIX_MAX_L];
   __shared__ uint32_t s_ws[RADIX_BLOCK / 64 + 1];
-  constexpr int CR = KIND == 2 ? 4 : 8;
+  constexpr int CR = KIND == 2 || KIND == 4 ? 4 : 8;
   const int tid = threadIdx.x;
   const int P1 = 1 << R.l1;
   const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -1299,12 +1302,15 @@ hipError_t launch_hash_compact(const HashBufs& H, kp_dtype dt, hipStream_t s) {
 hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
   RadixArgs R = R0;
   if (R.na == 0 || R.nb == 0) return hipSuccess;
+  if (kind == 2 && R.harm_on) kind = 4;   // Poisson products cut by harmonic order
   const dim3 grid((unsigned)((R.nb + RADIX_BLOCK - 1) / RADIX_BLOCK),
                   (unsigned)((R.na + R.rows - 1) / R.rows));
   R.nblocks = (int64_t)grid.x * grid.y;
   const unsigned P1 = 1u << R.l1;
   if (R.ev0) (void)hipEventRecord(R.ev0, s);
-  if (kind == 3)
+  if (kind == 4)
+    hipLaunchKernelGGL(k_radix_count<4>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 3)
     hipLaunchKernelGGL(k_radix_count<3>, grid, dim3(RADIX_BLOCK), 0, s, R);
   else if (kind == 2)
     hipLaunchKernelGGL(k_radix_count<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
@@ -1314,7 +1320,9 @@ hipError_t launch_radix(const RadixArgs& R0, int kind, hipStream_t s) {
     hipLaunchKernelGGL(k_radix_count<0>, grid, dim3(RADIX_BLOCK), 0, s, R);
   hipLaunchKernelGGL(k_radix_scan_parts, dim3(P1), dim3(256), 0, s, R);
   hipLaunchKernelGGL(k_radix_scan_totals, dim3(1), dim3(1024), 0, s, R);
-  if (kind == 3)
+  if (kind == 4)
+    hipLaunchKernelGGL(k_radix_scatter<4>, grid, dim3(RADIX_BLOCK), 0, s, R);
+  else if (kind == 3)
     hipLaunchKernelGGL(k_radix_scatter<3>, grid, dim3(RADIX_BLOCK), 0, s, R);
   else if (kind == 2)
     hipLaunchKernelGGL(k_radix_scatter<2>, grid, dim3(RADIX_BLOCK), 0, s, R);
