@@ -530,89 +530,116 @@ __global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
 // ------------------------------------------------------------ grouping
 // The products of (range r, rows of split s), STEPS candidates per lane per
 // chunk: each chunk is counting-sorted by bin through LDS and written as
-// contiguous runs after this workgroup's earlier runs in each bin.
-constexpr int RG_STEPS = 4;
-constexpr int RG_CHUNK = RG_BLOCK * RG_STEPS;
+// contiguous runs after this workgroup's earlier runs in each bin.  The
+// 8-byte entry form is staged as it is written, eight candidates per lane
+// per chunk; the 16-byte form four, in the same 64 KiB of LDS.
+constexpr int RG_STAGE_BYTES = RG_BLOCK * 64;
+
+struct ScatterLds {
+  uint4 stage[RG_STAGE_BYTES / 16];
+  WaveRows rows[WAVES];
+  int64_t base[1 << RG_MAX_L2];
+  uint32_t coff[1 << RG_MAX_L2];
+  uint32_t s_ws[RG_BLOCK / 64 + 1];
+};
+
+template <typename T, bool PACK>
+__device__ __forceinline__ void scatter_unit(const RangeArgs& R, const Unit& U, ScatterLds& L) {
+  constexpr int STEPS = PACK ? 8 : 4;
+  static_assert(RG_BLOCK * STEPS * (PACK ? 8 : 16) == RG_STAGE_BYTES, "stage size");
+  uint64_t* stage8 = reinterpret_cast<uint64_t*>(L.stage);
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int64_t r = U.r, s = U.s;
+  const int nbin = R.rnb[r];
+  const int w = R.w;
+  const uint64_t mult = R.mult, mw = wmask(w);
+  const int64_t b0 = R.rbin0[r], rb = R.rbase[r];
+  for (int k = tid; k < nbin; k += RG_BLOCK) {
+    L.base[k] = rb + R.cnt[R.rcbase[r] + k * U.ns + s];
+    L.coff[k] = 0;
+    if (s == 0) R.bin_start[b0 + k] += rb;   // the bins' first entries, absolute
+  }
+  __syncthreads();
+  const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
+  WaveWalk<T> g;
+  g.start(U.i0, U.i1, lo, hi, wave);
+  uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
+  uint4* ent16 = static_cast<uint4*>(R.ent);
+  for (;;) {
+    uint64_t hh[STEPS], vb[STEPS];   // PACK: hh holds the packed entry
+    uint32_t bn[STEPS], rank[STEPS];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < STEPS; ++u) {
+      bool ok = false;
+      uint64_t h = 0;
+      T v{};
+      if (!g.template step<true>(R, L.rows[wave], w, mult, &ok, &h, &v)) break;
+      if (!ok) continue;
+      if (PACK) {
+        hh[u] = (to_bits(v) << w) | h;
+      } else {
+        hh[u] = h;
+        vb[u] = to_bits(v);
+      }
+      bn[u] = bin_of(h, w, (uint32_t)nbin);
+      rank[u] = atomicAdd(&L.coff[bn[u]], 1u);
+      mask |= 1u << u;
+    }
+    __syncthreads();
+    const uint32_t mine = tid < nbin ? L.coff[tid] : 0u;
+    uint32_t total;
+    const uint32_t off = block_scan<RG_BLOCK, uint32_t>(mine, L.s_ws, &total);
+    if (tid < nbin) L.coff[tid] = off;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < STEPS; ++u)
+      if ((mask >> u) & 1u) {
+        const uint32_t at = L.coff[bn[u]] + rank[u];
+        if (PACK)
+          stage8[at] = hh[u];
+        else
+          L.stage[at] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32), (uint32_t)vb[u],
+                                   (uint32_t)(vb[u] >> 32));
+      }
+    __syncthreads();
+    for (uint32_t t = tid; t < total; t += RG_BLOCK) {
+      if (PACK) {
+        const uint64_t e = stage8[t];
+        const uint32_t k = bin_of(e & mw, w, (uint32_t)nbin);
+        ent8[L.base[k] + (t - L.coff[k])] = e;
+      } else {
+        const uint4 e = L.stage[t];
+        const uint32_t k = bin_of(((uint64_t)e.y << 32) | e.x, w, (uint32_t)nbin);
+        ent16[L.base[k] + (t - L.coff[k])] = e;
+      }
+    }
+    __syncthreads();
+    if (tid < nbin) {
+      L.base[tid] += mine;
+      L.coff[tid] = 0;
+    }
+    if (!__syncthreads_or(!g.done)) break;
+  }
+  __syncthreads();   // the next unit resets base and coff
+}
 
 template <typename T>
 __global__ void __launch_bounds__(RG_BLOCK) k_rg_scatter(RangeArgs R) {
-  __shared__ uint4 stage[RG_CHUNK];
-  __shared__ WaveRows rows[WAVES];
-  __shared__ int64_t base[1 << RG_MAX_L2];
-  __shared__ uint32_t coff[1 << RG_MAX_L2];
-  __shared__ uint32_t s_ws[RG_BLOCK / 64 + 1];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  __shared__ ScatterLds L;
+  const bool pack = R.meta->pack != 0;
   // the grid walks the (range, split) units
   for (int64_t gu = blockIdx.x;; gu += gridDim.x) {
     Unit U;
     if (!unit_of(R, gu, &U)) return;
-    const int64_t r = U.r, s = U.s;
-    const int nbin = R.rnb[r];
-    const int w = R.w;
-    const uint64_t mult = R.mult;
-    const bool pack = R.meta->pack != 0;
-    const int64_t b0 = R.rbin0[r], rb = R.rbase[r];
-    for (int k = tid; k < nbin; k += RG_BLOCK) {
-      base[k] = rb + R.cnt[R.rcbase[r] + k * U.ns + s];
-      coff[k] = 0;
-      if (s == 0) R.bin_start[b0 + k] += rb;   // the bins' first entries, absolute
+    if constexpr (std::is_same<T, int64_t>::value) {   // only int64 entries are packed
+      if (pack)
+        scatter_unit<T, true>(R, U, L);
+      else
+        scatter_unit<T, false>(R, U, L);
+    } else {
+      scatter_unit<T, false>(R, U, L);
     }
-    __syncthreads();
-    const int64_t lo = r << w, hi = min(R.nkeys, (r + 1) << w);
-    const int64_t i0 = U.i0, i1 = U.i1;
-    WaveWalk<T> g;
-    g.start(i0, i1, lo, hi, wave);
-    uint64_t* ent8 = static_cast<uint64_t*>(R.ent);
-    uint4* ent16 = static_cast<uint4*>(R.ent);
-    for (;;) {
-      uint64_t hh[RG_STEPS], vb[RG_STEPS];
-      uint32_t bn[RG_STEPS], rank[RG_STEPS];
-      uint32_t mask = 0;
-  #pragma unroll
-      for (int u = 0; u < RG_STEPS; ++u) {
-        bool ok = false;
-        uint64_t h = 0;
-        T v{};
-        if (!g.template step<true>(R, rows[wave], w, mult, &ok, &h, &v)) break;
-        if (!ok) continue;
-        hh[u] = h;
-        vb[u] = to_bits(v);
-        bn[u] = bin_of(h, w, (uint32_t)nbin);
-        rank[u] = atomicAdd(&coff[bn[u]], 1u);
-        mask |= 1u << u;
-      }
-      __syncthreads();
-      const uint32_t mine = tid < nbin ? coff[tid] : 0u;
-      uint32_t total;
-      const uint32_t off = block_scan<RG_BLOCK, uint32_t>(mine, s_ws, &total);
-      if (tid < nbin) coff[tid] = off;
-      __syncthreads();
-  #pragma unroll
-      for (int u = 0; u < RG_STEPS; ++u)
-        if ((mask >> u) & 1u)
-          stage[coff[bn[u]] + rank[u]] = make_uint4((uint32_t)hh[u], (uint32_t)(hh[u] >> 32),
-                                                    (uint32_t)vb[u], (uint32_t)(vb[u] >> 32));
-      __syncthreads();
-      for (uint32_t t = tid; t < total; t += RG_BLOCK) {
-        const uint4 e = stage[t];
-        const uint64_t h = ((uint64_t)e.y << 32) | e.x;
-        const uint32_t k = bin_of(h, w, (uint32_t)nbin);
-        const int64_t at = base[k] + (t - coff[k]);
-        if (pack) {
-          const uint64_t v = ((uint64_t)e.w << 32) | e.z;
-          ent8[at] = (v << w) | h;
-        } else {
-          ent16[at] = e;
-        }
-      }
-      __syncthreads();
-      if (tid < nbin) {
-        base[tid] += mine;
-        coff[tid] = 0;
-      }
-      if (!__syncthreads_or(!g.done)) break;
-    }
-    __syncthreads();   // the next unit resets base and coff
   }
 }
 
