@@ -904,6 +904,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   if (tid == 0) s_over = 0;
   __syncthreads();
   int64_t ins = 0, extra = 0;
+  const bool stats = R.stats != nullptr;
   // inserts the entry when its code lies in [ilo, ihi]; a full table sets
   // s_over (the bin is then redone in parts)
   const auto insert = [&](const uint4& x, uint64_t ilo, uint64_t ihi) {
@@ -918,19 +919,25 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
     }
     const unsigned long long key = (unsigned long long)code + 1;
     uint32_t slot = bin_slot<LOG>(code_hash(code), R.l1, l2);
-    for (int q = 0; q < BIN_SLOTS; ++q) {
-      // one compare-and-swap claims an empty slot or returns its key
-      unsigned long long c = atomicCAS(&keys[slot], 0ull, key);
-      if (c == 0) c = key;
-      if (c == key) {
-        lds_slot_add(&vals[slot], v);
-        ++ins;
-        extra += q;
-        return;
-      }
+    // one compare-and-swap claims an empty slot or returns its key; the
+    // probe loop has one exit test and the value is added after it
+    unsigned long long c = atomicCAS(&keys[slot], 0ull, key);
+    int q = 0;
+#pragma nounroll
+    while (c != 0 && c != key && q < BIN_SLOTS - 1) {
+      ++q;
       slot = (slot + 1) & (BIN_SLOTS - 1);
+      c = atomicCAS(&keys[slot], 0ull, key);
     }
-    s_over = 1;
+    if (c != 0 && c != key) {   // every slot holds another code
+      s_over = 1;
+      return;
+    }
+    lds_slot_add(&vals[slot], v);
+    if (stats) {
+      ++ins;
+      extra += q;
+    }
   };
   T* out_c = static_cast<T*>(R.out_c);
   const int nx = R.dec.nx;
@@ -938,8 +945,9 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
   // Compacts the table to its front (thread tid owns slots tid + r *
   // BIN_BLOCK; every slot is read before any is rewritten), writes the
   // nonzero terms one per thread with all lanes busy at an offset taken from
-  // the call's output counter, and clears the table.
-  const auto emit = [&]() {
+  // the call's output counter, and clears the table when asked (another code
+  // interval of the bin follows).
+  const auto emit = [&](bool clear) {
     constexpr int PER = BIN_PER_THREAD;
     unsigned long long kk[PER];
     T vv[PER];
@@ -991,7 +999,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
         R.out_t[q] = (uint8_t)(code & 1);
         uint64_t u = fdiv(c, R.dec.dWx);
         uint64_t kx = c - u * (uint64_t)R.dec.Wx;
-        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, kx);
+        for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step_fast(R.dec, v, kx);
         const int ny = R.dec.ny;
         for (int v = ny - 1; v >= 0; --v) R.out_y[q * ny + v] = decode_y_step(R.dec, v, u);
       } else if (R.out_x) {   // decoded exponents, written as they are found
@@ -999,23 +1007,25 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
         if (pairs) {
           int2* o = reinterpret_cast<int2*>(R.out_x + q * nx);
           for (int v = 0; v < nx; v += 2) {
-            const int32_t lo = decode_step(R.dec, v, c);
-            o[v >> 1] = make_int2(lo, decode_step(R.dec, v + 1, c));
+            const int32_t lo = decode_step_fast(R.dec, v, c);
+            o[v >> 1] = make_int2(lo, decode_step_fast(R.dec, v + 1, c));
           }
         } else {
-          for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step(R.dec, v, c);
+          for (int v = 0; v < nx; ++v) R.out_x[q * nx + v] = decode_step_fast(R.dec, v, c);
         }
       } else {
         R.out_k[q] = (int64_t)code;
       }
       out_c[q] = vals[t];
     }
-    __syncthreads();
-    for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
-      keys[i] = 0;
-      vals[i] = T(0);
+    if (clear) {
+      __syncthreads();
+      for (int i = tid; i < BIN_SLOTS; i += BIN_BLOCK) {
+        keys[i] = 0;
+        vals[i] = T(0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   };
 #pragma unroll
   for (int u = 0; u < BIN_PER_THREAD; ++u)
@@ -1025,7 +1035,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
     insert(R.ent2[k], 0, ~0ull);
   __syncthreads();
   if (!s_over) {
-    emit();
+    emit(false);
   } else {
     // More distinct codes than slots (the table is full; Section 3.2 resizes
     // and rehashes): the bin again, one code interval at a time, halving an
@@ -1078,7 +1088,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER_THREAD) k_radix_bins(Radi
         }
         __syncthreads();
       } else {
-        emit();
+        emit(true);
       }
     }
   }

@@ -713,32 +713,41 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   if (tid == 0) s_over = 0;
   __syncthreads();
   int64_t ins = 0, extra = 0;
-  // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over
+  const bool stats = R.stats != nullptr;
+  // inserts (h, v) when h lies in [ilo, ihi]; a full table sets s_over.  The
+  // probe loop has one exit test, and the value is added once the slot is
+  // found, so a wavefront's lanes leave the loop with little mask handling.
   const auto insert = [&](uint64_t h, T v, uint64_t ilo, uint64_t ihi) {
     if (h < ilo || h > ihi) return;
     const K key = (K)(h + 1);
     uint32_t slot = (uint32_t)((h * GOLD) >> (64 - LOG));
-    for (int q = 0; q < SLOTS; ++q) {
-      // one compare-and-swap claims an empty slot or returns its key
-      K c = atomicCAS(&keys[slot], (K)0, key);
-      if (c == 0) c = key;
-      if (c == key) {
-        lds_add(&vals[slot], v);
-        ++ins;
-        extra += q;
-        return;
-      }
+    // one compare-and-swap claims an empty slot or returns its key
+    K c = atomicCAS(&keys[slot], (K)0, key);
+    int q = 0;
+#pragma nounroll
+    while (c != 0 && c != key && q < SLOTS - 1) {
+      ++q;
       slot = (slot + 1) & (SLOTS - 1);
+      c = atomicCAS(&keys[slot], (K)0, key);
     }
-    s_over = 1;
+    if (c != 0 && c != key) {   // every slot holds another code
+      s_over = 1;
+      return;
+    }
+    lds_add(&vals[slot], v);
+    if (stats) {
+      ++ins;
+      extra += q;
+    }
   };
   T* out_c = static_cast<T*>(R.out_c);
   const int nx = R.dec.nx;
   const bool pairs = (nx & 1) == 0 && ((uintptr_t)R.out_x & 7) == 0;
   const uint64_t inv = R.inv, mw = wmask(w);
   // compacts the table, writes its nonzero terms after the `done` already
-  // written for this bin, leaves the table cleared; returns the count
-  const auto emit = [&](int64_t done) -> int64_t {
+  // written for this bin, leaves the table cleared when asked (another hash
+  // interval of the bin follows); returns the count
+  const auto emit = [&](int64_t done, bool clear) -> int64_t {
     K kk[BIN_PER];
     T vv[BIN_PER];
     uint64_t ball[BIN_PER];
@@ -794,12 +803,14 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
       }
       out_c[q] = vals[t];
     }
-    __syncthreads();
-    for (int i = tid; i < SLOTS; i += NT) {
-      keys[i] = 0;
-      vals[i] = T(0);
+    if (clear) {
+      __syncthreads();
+      for (int i = tid; i < SLOTS; i += NT) {
+        keys[i] = 0;
+        vals[i] = T(0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     return tot;
   };
 #pragma unroll
@@ -815,7 +826,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   __syncthreads();
   int64_t terms = 0;
   if (!s_over) {
-    terms = emit(0);
+    terms = emit(0, false);
   } else {
     // More distinct codes than slots: the bin again, one hash interval at a
     // time, halving an interval whose codes overflow the table.
@@ -871,7 +882,7 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
         }
         __syncthreads();
       } else {
-        terms += emit(terms);
+        terms += emit(terms, true);
       }
     }
   }
