@@ -699,13 +699,33 @@ __global__ void __launch_bounds__((1 << LOG) / BIN_PER) k_rg_bins(RangeArgs R) {
   const bool pack = R.meta->pack != 0;
   const bool reserve = R.meta->reserve != 0;
   const int64_t lo = (int64_t)R.bin_range[b] << w;
-  // the bin's first BIN_PER entries per thread, loaded at once (indices past
-  // the bin repeat its last entry, unused: no branch per load)
+  // the bin's first BIN_PER entries per thread, loaded at once: the rounds
+  // that reach into the bin (a branch on the bin's size, the same for every
+  // thread), indices past the bin repeating its last entry, unused; packed
+  // entries are read as their 8 bytes
   uint64_t h0[BIN_PER];
   T v0[BIN_PER];
+  bool packed_load = false;
+  if constexpr (std::is_same<T, int64_t>::value) {
+    if (pack) {
+      packed_load = true;
+      const uint64_t* ent8 = static_cast<const uint64_t*>(R.ent);
+      const uint64_t mw0 = wmask(w);
 #pragma unroll
-  for (int u = 0; u < BIN_PER; ++u)
-    entry_at(R, pack, w, min(s + tid + (int64_t)u * NT, e - 1), &h0[u], &v0[u]);
+      for (int u = 0; u < BIN_PER; ++u)
+        if (s + (int64_t)u * NT < e) {
+          const uint64_t x = ent8[min(s + tid + (int64_t)u * NT, e - 1)];
+          h0[u] = x & mw0;
+          v0[u] = (int64_t)x >> w;
+        }
+    }
+  }
+  if (!packed_load) {
+#pragma unroll
+    for (int u = 0; u < BIN_PER; ++u)
+      if (s + (int64_t)u * NT < e)
+        entry_at(R, pack, w, min(s + tid + (int64_t)u * NT, e - 1), &h0[u], &v0[u]);
+  }
   for (int i = tid; i < SLOTS; i += NT) {
     keys[i] = 0;
     vals[i] = T(0);

@@ -396,6 +396,22 @@ def test_grouped_hash_matches_oracle(grouping, cfg, scale, fp):
     check_laurent(a, b, "hash", f"grouped {grouping}, config {cfg} x{scale}", ctx)
 
 
+def test_range_grouping_wide_int64_entries():
+    """int64 products too wide to sit above the hash bits of an 8-byte entry
+    take 16-byte entries (and the grouping kernel's shorter chunks): the
+    ranges against the oracle, then a factor holding every term of B twice
+    with opposite signs, whose product is zero term by term."""
+    ctx = kp.context()
+    ctx.set_tune(hash_partitioned=2, hash_grouping=2)
+    a, b = I.config(3, scale=0.1)
+    a = (a[0], np.asarray(a[1], np.int64) << 24)
+    check_laurent(a, b, "hash", "ranges, int64 products past the packed width", ctx)
+    bb = np.asarray(b[1], np.int64)
+    both = (np.concatenate([b[0], b[0]]), np.concatenate([bb, -bb]))
+    ge, gc, _ = check_laurent(a, both, "hash", "ranges, every sum cancels", ctx)
+    assert len(gc) == 0
+
+
 def test_repeat_runs_bit_identical():
     a, b = I.config(2, scale=0.2)
     r1 = gpu_laurent(a, b, "hash")
