@@ -82,14 +82,16 @@ class _Product:
 
 def _search(ctx, prod, mode, grid, reps, fixed=None):
     """Times every candidate (with `fixed` settings held while timing, not
-    part of the result) and returns the fastest and the table."""
+    part of the result) and returns the fastest and the table.  `prod` is a
+    product or a list of them, a candidate's time being their sum."""
+    prods = prod if isinstance(prod, (list, tuple)) else [prod]
     saved = ctx.tune
     base = {f: getattr(saved, f) for f, _ in type(saved)._fields_}
     table = []
     try:
         for cand in grid:
             ctx.set_tune(**{**base, **(fixed or {}), **cand})
-            table.append((prod.seconds(mode, reps), cand))
+            table.append((sum(p.seconds(mode, reps) for p in prods), cand))
     finally:
         ctx.set_tune(**base)
     table.sort(key=lambda x: x[0])
@@ -111,12 +113,16 @@ def tune_hash(ctx, scale=0.2, reps=3):
 
 
 def tune_bins(ctx, scale=0.5, reps=3):
-    """Slots of the grouped products' LDS tables (the grouped layout forced
-    while timing) on the 6-variable sparse product; the bins are sized from
-    the product count, so the product should be of the size it is tuned for."""
+    """Slots and fill of the grouped products' LDS tables (the grouped layout
+    forced while timing), one setting for both groupings: timed on the
+    6-variable sparse product (grouped by range; the bins are sized from the
+    product count, so the product should be of the size it is tuned for) plus
+    the Monagan-Pearce product (many products per term: two-level grouping,
+    where small tables lose most)."""
     a, b = I.config(3, scale=scale)
-    return _search(ctx, _Product(ctx, a, b), "hash", BIN_GRID, reps,
-                   fixed=dict(hash_partitioned=2))
+    f, g = I.mp_sparse(12, "f"), I.mp_sparse(12, "g")
+    prods = [_Product(ctx, a, b), _Product(ctx, f, g)]
+    return _search(ctx, prods, "hash", BIN_GRID, reps, fixed=dict(hash_partitioned=2))
 
 
 def _crossover(rows, fallback):
