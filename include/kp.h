@@ -216,10 +216,13 @@ kp_status kp_ctx_set_truncation(kp_ctx* ctx, int32_t nvars, const int32_t* weigh
    (another criterion Section 3 names).  While set, Poisson products computed
    with this context keep only the terms whose weighted harmonic order
    sum_k weights[k] * |j_k| is at most max_order (trigonometric variables from
-   ny on have weight 0).  A pair of terms whose orders differ by more than
-   max_order makes no piece (both of its pieces' orders are at least that
-   difference); the other pieces are formed and the terms over the limit are
-   dropped where the sums are compacted.  Such products run in hash mode in
+   ny on have weight 0).  When every factor multiplier lies in [-127, 127],
+   each pair's two pieces have their orders computed from the factors'
+   multipliers and a piece over the limit is never formed.  Otherwise a pair
+   whose factor orders differ by more than max_order makes no piece (both of
+   its pieces' orders are at least that difference), the other pieces are
+   formed, and the terms over the limit are dropped where the sums are
+   compacted.  Either way the result is the same.  Such products run in hash mode in
    the grouped layout (the automatic mode; KP_DENSE is KP_E_MODE).  weights: ny
    (1..KP_MAX_VARS) values in [0, 2^15].  Laurent products are unaffected.
    kp_ctx_clear_truncation removes it (and the Laurent one). */
