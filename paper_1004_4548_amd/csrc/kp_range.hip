@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
 // contiguous runs after this workgroup's earlier runs in each bin.  The
 // 8-byte entry form is staged as it is written, eight candidates per lane
 // per chunk; the 16-byte form four, in the same 64 KiB of LDS.
-constexpr int RG_STAGE_BYTES = RG_BLOCK * 64;
+constexpr int RG_STAGE_BYTES = RG_BLOCK * 96;
 
 struct ScatterLds {
   uint4 stage[RG_STAGE_BYTES / 16];
@@ -545,7 +545,7 @@ struct ScatterLds {
 
 template <typename T, bool PACK>
 __device__ __forceinline__ void scatter_unit(const RangeArgs& R, const Unit& U, ScatterLds& L) {
-  constexpr int STEPS = PACK ? 8 : 4;
+  constexpr int STEPS = PACK ? 12 : 6;
   static_assert(RG_BLOCK * STEPS * (PACK ? 8 : 16) == RG_STAGE_BYTES, "stage size");
   uint64_t* stage8 = reinterpret_cast<uint64_t*>(L.stage);
   const int tid = threadIdx.x, wave = tid >> 6;
