@@ -380,3 +380,49 @@ def test_tune_cache_round_trip(tmp_path):
     with open(path, "w") as f:
         f.write("{not json")
     assert tune.load_cache(path) == {}
+
+
+def test_tune_search_sums_products_and_restores_knobs():
+    """The autotuner's search: a candidate's time is the sum over the products
+    it is timed on, the fastest sum wins (a setting that only ties on one
+    product does not beat one that wins on the other), and the knobs held
+    while timing are put back."""
+    from paper_1004_4548_amd import tune
+    import ctypes as C
+
+    class Knobs(C.Structure):
+        _fields_ = [("slots", C.c_int32), ("fill", C.c_int32), ("grouping", C.c_int32)]
+
+    class Ctx:
+        def __init__(self):
+            self.k = Knobs(4096, 42, 0)
+            self.seen = []
+
+        @property
+        def tune(self):
+            return Knobs(self.k.slots, self.k.fill, self.k.grouping)
+
+        def set_tune(self, **kw):
+            for f, v in kw.items():
+                setattr(self.k, f, v)
+
+    ctx = Ctx()
+
+    class Prod:
+        def __init__(self, times):
+            self.times = times
+
+        def seconds(self, mode, reps):
+            ctx.seen.append((ctx.k.slots, ctx.k.grouping))
+            return self.times[ctx.k.slots]
+
+    ranges = Prod({2048: 5.49, 4096: 5.54, 8192: 6.1})   # 2048 ties on this one
+    levels = Prod({2048: 1.52, 4096: 1.12, 8192: 1.2})   # and loses on this one
+    grid = [dict(slots=s) for s in (2048, 4096, 8192)]
+    best, table = tune._search(ctx, [ranges, levels], "hash", grid, 1, fixed=dict(grouping=2))
+    assert best == dict(slots=4096)
+    assert [round(t, 2) for t, _ in table] == [6.66, 7.01, 7.3]
+    assert all(g == 2 for _, g in ctx.seen) and len(ctx.seen) == 6
+    assert (ctx.k.slots, ctx.k.fill, ctx.k.grouping) == (4096, 42, 0)
+    alone, _ = tune._search(ctx, ranges, "hash", grid, 1)   # one product, not a list
+    assert alone == dict(slots=2048)
