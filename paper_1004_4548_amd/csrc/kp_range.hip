@@ -531,8 +531,8 @@ __global__ void __launch_bounds__(1024) k_rg_scan2(RangeArgs R) {
 // The products of (range r, rows of split s), STEPS candidates per lane per
 // chunk: each chunk is counting-sorted by bin through LDS and written as
 // contiguous runs after this workgroup's earlier runs in each bin.  The
-// 8-byte entry form is staged as it is written, eight candidates per lane
-// per chunk; the 16-byte form four, in the same 64 KiB of LDS.
+// 8-byte entry form is staged as it is written, twelve candidates per lane
+// per chunk; the 16-byte form six, in the same 96 KiB of LDS.
 constexpr int RG_STAGE_BYTES = RG_BLOCK * 96;
 
 struct ScatterLds {
