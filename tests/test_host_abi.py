@@ -426,3 +426,18 @@ def test_tune_search_sums_products_and_restores_knobs():
     assert (ctx.k.slots, ctx.k.fill, ctx.k.grouping) == (4096, 42, 0)
     alone, _ = tune._search(ctx, ranges, "hash", grid, 1)   # one product, not a list
     assert alone == dict(slots=2048)
+
+
+def test_tune_crossover():
+    """The dense/hash switch from timed rows (codes per pair, dense s, hash
+    s): the geometric mean of the sparsest shape where dense still wins and
+    the densest sparser one where hash wins; 0 when hash always wins; the
+    larger of the fallback and the last dense win when dense always wins."""
+    from paper_1004_4548_amd import tune
+    rows = [(1.0, 1, 2), (4.0, 1, 2), (9.0, 3, 2), (16.0, 5, 2), (2.0, 1, 3)]
+    assert tune._crossover(rows, 32.0) == pytest.approx(6.0)   # sqrt(4 * 9)
+    assert tune._crossover([(r, 2, 1) for r in (1.0, 5.0)], 32.0) == 0.0
+    assert tune._crossover([(r, 1, 2) for r in (1.0, 5.0)], 32.0) == 32.0
+    assert tune._crossover([(r, 1, 2) for r in (1.0, 50.0)], 32.0) == 50.0
+    # a hash win below the last dense win does not set the upper end
+    assert tune._crossover([(1.0, 2, 1), (4.0, 1, 2), (9.0, 2, 1)], 32.0) == pytest.approx(6.0)
